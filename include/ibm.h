@@ -1,0 +1,199 @@
+/*
+ * ibm.h - C ABI of the MI355X (gfx950) topology-free immersed boundary time step.
+ *
+ * The method (Onishi & Tsubokura, arXiv:2002.06206): an incompressible LES step on
+ * a uniform Cartesian grid, fractional step with a pressure Poisson solve
+ * (Sec. 2.1, eqs. (crank-nicolson), (correction), (poisson)), driven directly by
+ * an arbitrary, possibly non-watertight ("dirty") triangle soup (Sec. 2.3).  No
+ * inside/outside decision is ever made: every grid-line segment between two cell
+ * centres that meets a triangle makes the neighbour behind the crossing a ghost
+ * cell for that cell only (Sec. 2.3.1), and the ghost value comes from the
+ * axis-projected formula eq. (q_axis) (Sec. 2.3.2).
+ *
+ * Conventions shared by every entry point
+ *  - Cells: c = i + nx*(j + ny*k), x fastest.  Cell centre = origin + (i + 0.5)*dx.
+ *  - Directions: 0..5 = -x,+x,-y,+y,-z,+z; blocked masks use bit d for direction d.
+ *  - Face velocities U[k] (k = x,y,z) hold the normal velocity on the +k face of
+ *    every cell; the -k face of the first layer comes from the boundary kind.
+ *  - All field pointers are caller-owned, contiguous DEVICE memory on the current
+ *    HIP device.  Cell fields (u, H, nu_t) are double under IBM_FP64 and float
+ *    under IBM_MIXED; U, p, b and wall velocities are always double.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Every call is enqueued on
+ *    it and returns without waiting, except where a host output is requested
+ *    (n_cut_out, stats, forces), which synchronises that stream.
+ *  - Return codes: IBM_OK (0); IBM_NOT_CONVERGED (+1, tolerance not met within
+ *    max_iter, results still written); negative codes are errors and leave the
+ *    outputs unspecified: IBM_ERR_ARG (bad argument / shape / state),
+ *    IBM_ERR_HIP (HIP runtime error), IBM_ERR_OOM (device allocation failed),
+ *    IBM_ERR_NAN (non-finite residual).  ibm_last_error() gives a message
+ *    (thread-local).  No C++ exception crosses this boundary.
+ *  - Determinism: identical inputs on the same GPU give bit-identical outputs
+ *    (all reductions use a fixed order; tagging uses order-independent atomics).
+ *  - Calls on one context must not overlap (one stream at a time per context).
+ */
+#ifndef IBM_H
+#define IBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { IBM_BC_PERIODIC = 0, IBM_BC_INFLOW = 1, IBM_BC_OUTFLOW = 2, IBM_BC_SLIP = 3 };
+enum { IBM_FP64 = 0, IBM_MIXED = 1 };
+enum {
+    IBM_SOLVER_PCG_JACOBI = 0, /* FP64 Jacobi-preconditioned CG                          */
+    IBM_SOLVER_FCG_CNN = 1,    /* FP64 refinement around FP32 flexible CG, CNN precond.   */
+    IBM_SOLVER_FCG_JACOBI = 2  /* FP64 refinement around FP32 flexible CG, Jacobi precond.*/
+};
+enum { IBM_OK = 0, IBM_NOT_CONVERGED = 1, IBM_ERR_ARG = -1, IBM_ERR_HIP = -2, IBM_ERR_OOM = -3,
+       IBM_ERR_NAN = -4 };
+
+/* Uniform Cartesian grid (the one-level case of the paper's cube grid, Sec. 2.2). */
+typedef struct {
+    int32_t n[3];      /* cells per axis, each >= 3                              */
+    double dx;         /* cell size (> 0)                                         */
+    double origin[3];  /* low corner of the domain                                */
+} ibm_grid;
+
+/* Outer boundary kinds, order -x,+x,-y,+y,-z,+z (the paper omits them, Sec. 2.1):
+ * PERIODIC must be set on both faces of an axis; INFLOW = Dirichlet u_in with
+ * zero-gradient pressure; OUTFLOW (only on a + face) = zero-gradient velocity with
+ * p = 0 on the face; SLIP = zero normal velocity, zero-gradient tangential velocity
+ * and pressure. */
+typedef struct {
+    int32_t face[6];
+    double u_in[3];
+} ibm_bc;
+
+/* Pressure solver options.  tol is the relative residual ||b - L p||_2 / ||b||_2
+ * (equivalently ||div U^{n+1}||_2 / (dt ||b||_2)). */
+typedef struct {
+    double tol;
+    int32_t max_iter;        /* cap on (inner) iterations per solve                */
+    int32_t kind;            /* IBM_SOLVER_*                                        */
+    double inner_tol;        /* FCG kinds: relative reduction per refinement sweep  */
+    int32_t inner_max_iter;  /* FCG kinds: cap per refinement sweep                 */
+    double stall_factor;     /* FCG kinds: fall back to FP64 PCG when one sweep     */
+                             /* reduces the FP64 residual by less than this factor  */
+    int32_t check_every;     /* iterations enqueued between host convergence polls  */
+    int32_t force_stall;     /* test hook: 1 = treat the first sweep as stalled      */
+} ibm_solver_opts;
+
+/* One time step: AB2 momentum predictor (forward Euler when step == 0), coherent
+ * structure model (Sec. 2.3) when csm_on, body force, Poisson, projection. */
+typedef struct {
+    double dt;
+    double nu;              /* molecular kinematic viscosity (1/Re in flow units)   */
+    double c1;              /* CSM constant C1, 1/20 in the paper                   */
+    int32_t csm_on;
+    int32_t step;           /* 0 = first step (forward Euler), else AB2              */
+    double body_force[3];
+    ibm_solver_opts poisson;
+} ibm_step_params;
+
+typedef struct {
+    int32_t iters_inner;     /* CG / FCG iterations                                  */
+    int32_t iters_outer;     /* FP64 refinement sweeps (0 for plain PCG)             */
+    int32_t fallback_used;   /* 1 when the FP64 PCG fallback ran                     */
+    int32_t status;          /* return code of the solve                             */
+    double rel_residual;     /* FP64 ||b - L p|| / ||b|| after the solve             */
+    double div_l2;           /* ||div U^{n+1}||_2 over all cells (ibm_step only)     */
+    double div_linf;         /* max |div U^{n+1}|                                    */
+} ibm_stats;
+
+typedef struct ibm_ctx ibm_ctx;
+
+/* Creates a context on the current HIP device and allocates the per-step
+ * workspace once (no allocation happens later inside ibm_step or
+ * ibm_poisson_solve).  precision = IBM_FP64 or IBM_MIXED. */
+int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ctx** out);
+int ibm_destroy(ibm_ctx* ctx);
+const char* ibm_last_error(void);
+
+/* Tagging (Sec. 2.3.1): tri_dev = ntri x 3 vertices x xyz doubles (device).  For every
+ * segment between face-adjacent cell centres inside the domain, decides exactly
+ * whether the closed segment meets a closed triangle (edges and vertices inclusive;
+ * triangles parallel to the segment never block), sets bit d of blocked_dev[c]
+ * and bit d^1 of the neighbour, and stores theta = distance from the cell centre to
+ * its nearest crossing / dx in [0,1] at theta_dev[6*c + d] (2.0 where open).
+ * theta uses one fixed double formula: the crossing coordinate is the barycentric
+ * combination of the vertex coordinates weighted by the double 2-D sub-areas.
+ * Domain and periodic-wrap faces are never tagged.  Coordinates must be finite
+ * with magnitude 0 or within [2^-200, 2^200] (IBM_ERR_ARG otherwise).
+ * blocked_dev: N bytes.  theta_dev: N*6 doubles, or NULL (the context keeps its own
+ * copy either way, for ibm_build_stencils). */
+int ibm_tag_geometry(ibm_ctx* ctx, const double* tri_dev, int64_t ntri, uint8_t* blocked_dev,
+                     double* theta_dev, void* stream);
+
+/* Stencil build (Sec. 2.3.1-2.3.2): from blocked bits and theta (theta_dev NULL = the
+ * context's copy from the last ibm_tag_geometry), applies the dead-end filter of
+ * eq. (deadend_filter) when deadend != 0 (a cell closed in >= 5 directions is closed
+ * in all six and frozen at the wall velocity; its open neighbours see a wall at its
+ * centre, theta = 1), builds the cut list (one entry per blocked (cell, dir),
+ * ordered by cell then dir) with the coefficients of eq. (q_axis), the classes of
+ * eq. (dummy_cell_region), and the connected components of the pressure problem.
+ * flags_dev (N uint16, or NULL): bits 0-5 effective blocked bits, bits 6-7 class
+ * (0 fluid, 1 wall-including, 2 wall-adjacent), bits 8-13 theta < 0.5 per blocked
+ * dir, bit 14 dead end, bit 15 enclosed (component without an outlet face).
+ * label_dev (N int32, or NULL): smallest cell index of the cell's component over
+ * open faces.  n_cut_out (host, or NULL): number of cuts. */
+int ibm_build_stencils(ibm_ctx* ctx, const uint8_t* blocked_dev, const double* theta_dev,
+                       int32_t deadend, uint16_t* flags_dev, int32_t* label_dev,
+                       int64_t* n_cut_out, void* stream);
+
+/* Crossing point X of every cut (n_cut x 3 doubles, device): the cell centre moved
+ * by theta*dx along the cut direction.  Callers evaluate wall velocities u_IB(X). */
+int ibm_cut_points(ibm_ctx* ctx, double* xyz_dev, void* stream);
+
+/* Initial state: u = u0 in every cell, U = u0 on open and periodic faces, the mean
+ * wall normal velocity of the two cuts on blocked faces, boundary values on domain
+ * faces; p = 0; h = 0.  wall_dev: n_cut x 3 doubles or NULL (stationary walls). */
+int ibm_init_state(ibm_ctx* ctx, void* u_dev[3], double* U_dev[3], double* p_dev, void* h_dev[3],
+                   const double u0[3], const double* wall_dev, void* stream);
+
+/* One fractional step (Sec. 2.1): coherent-structure eddy viscosity (Sec. 2.3), AB2
+ * predictor in flux form with the axis-projected ghost values of eq. (q_axis)
+ * across blocked faces, face velocity U* (Rhie-Chow style compact face velocity),
+ * b = div U* / dt made compatible on enclosed components, pressure solve warm
+ * started from p, projection of U and u, FP64 divergence check.
+ * u_dev, h_dev: in u^n, H^{n-1}; out u^{n+1}, H^n.  U_dev: in U^n, out U^{n+1}.
+ * p_dev: in guess, out p^{n+1} (zero mean on enclosed components).
+ * wall_dev: n_cut x 3 wall velocities u_IB at the crossing points, or NULL.
+ * stats (host, or NULL): filled and the stream synchronised when non-NULL. */
+int ibm_step(ibm_ctx* ctx, void* u_dev[3], double* U_dev[3], double* p_dev, void* h_dev[3],
+             const double* wall_dev, const ibm_step_params* prm, ibm_stats* stats, void* stream);
+
+/* Pressure Poisson solve (eq. (poisson)) on the context's stencil: L x = b where
+ * L p = (1/dx^2)[sum over open faces (p_nb - p_c) - 2 p_c per outlet face];
+ * blocked, inflow and slip faces are Neumann (ghost p = p_c, eq. (Mittal) with
+ * zeta = 1, eta = 0).  b is made compatible (mean removed) on enclosed components
+ * in a private copy; x (in: guess, out: solution) gets zero mean there.
+ * Always synchronises the stream (the solver polls convergence). */
+int ibm_poisson_solve(ibm_ctx* ctx, const double* b_dev, double* x_dev, const ibm_solver_opts* opts,
+                      ibm_stats* stats, void* stream);
+
+/* y = L x (the operator above), for tests. */
+int ibm_apply_laplacian(ibm_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
+
+/* Copies of quantities from the last ibm_step: eddy viscosity (cell type) and the
+ * compatible Poisson right-hand side b (double). */
+int ibm_get_nut(ibm_ctx* ctx, void* out_dev, void* stream);
+int ibm_get_rhs(ibm_ctx* ctx, double* out_dev, void* stream);
+
+/* Force on the immersed surface as the momentum flux through every blocked face
+ * (cut-face form of the near-field force): for each cut of cell c with direction
+ * s*e_k, F_p += dx^2 s p_c e_k and F_v -= dx^2 (nu + nu_t,c)(q_GC - q_c)/dx, with
+ * q_GC the eq. (q_axis) ghost of each velocity component.  nut_dev NULL = the
+ * context's eddy viscosity from the last step (zero before any step).
+ * out_host[6] = F_p xyz, F_v xyz.  Synchronises the stream.  Drag coefficients
+ * follow eqs. (cd_sphere) / (cd_flat_plate) on the caller's side. */
+int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const void* nut_dev, double nu,
+               const double* wall_dev, double out_host[6], void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBM_H */

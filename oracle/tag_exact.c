@@ -241,6 +241,14 @@ static double centre(const double *origin, double dx, int ax, int64_t i)
     return origin[ax] + ((double)i + 0.5) * dx;
 }
 
+/* a line index, clamped in double before the integer cast */
+static int64_t clampi(double v, int64_t lo, int64_t hi)
+{
+    if (v < (double)lo) v = (double)lo;
+    if (v > (double)hi) v = (double)hi;
+    return (int64_t)v;
+}
+
 static void put_theta(double *theta, int64_t c, int dir, double th)
 {
     if (th < theta[6 * c + dir]) theta[6 * c + dir] = th;
@@ -266,18 +274,13 @@ int oracle_tag(const double *tri, int64_t ntri, const int32_t *n, double dx, con
             double vmin = fmin(A[v], fmin(B[v], C[v])), vmax = fmax(A[v], fmax(B[v], C[v]));
             double kmin = fmin(A[k], fmin(B[k], C[k])), kmax = fmax(A[k], fmax(B[k], C[k]));
             /* candidate grid lines: generous bounding box, the exact test decides */
-            int64_t j0 = (int64_t)floor((umin - origin[u]) / dx - 0.5) - 1;
-            int64_t j1 = (int64_t)ceil((umax - origin[u]) / dx - 0.5) + 1;
-            int64_t l0 = (int64_t)floor((vmin - origin[v]) / dx - 0.5) - 1;
-            int64_t l1 = (int64_t)ceil((vmax - origin[v]) / dx - 0.5) + 1;
-            int64_t i0 = (int64_t)floor((kmin - origin[k]) / dx - 0.5) - 1;
-            int64_t i1 = (int64_t)ceil((kmax - origin[k]) / dx - 0.5) + 1;
-            if (j0 < 0) j0 = 0;
-            if (l0 < 0) l0 = 0;
-            if (i0 < 0) i0 = 0;
-            if (j1 > nn[u] - 1) j1 = nn[u] - 1;
-            if (l1 > nn[v] - 1) l1 = nn[v] - 1;
-            if (i1 > nn[k] - 2) i1 = nn[k] - 2; /* segments (i, i+1) inside the domain */
+            int64_t j0 = clampi(floor((umin - origin[u]) / dx - 0.5) - 1.0, 0, nn[u]);
+            int64_t j1 = clampi(ceil((umax - origin[u]) / dx - 0.5) + 1.0, -1, nn[u] - 1);
+            int64_t l0 = clampi(floor((vmin - origin[v]) / dx - 0.5) - 1.0, 0, nn[v]);
+            int64_t l1 = clampi(ceil((vmax - origin[v]) / dx - 0.5) + 1.0, -1, nn[v] - 1);
+            int64_t i0 = clampi(floor((kmin - origin[k]) / dx - 0.5) - 1.0, 0, nn[k]);
+            /* segments (i, i+1) inside the domain */
+            int64_t i1 = clampi(ceil((kmax - origin[k]) / dx - 0.5) + 1.0, -1, nn[k] - 2);
             for (int64_t j = j0; j <= j1; ++j) {
                 for (int64_t l = l0; l <= l1; ++l) {
                     const double pu = centre(origin, dx, u, j), pv = centre(origin, dx, v, l);

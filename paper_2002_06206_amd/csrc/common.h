@@ -1,0 +1,229 @@
+// Internal declarations shared by the gfx950 kernels and the C ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ibm.h"
+
+namespace ibm {
+
+constexpr int TX = 64;          // tile width in x (one wavefront)
+constexpr int TY = 4;           // tile height in y
+constexpr int NT = TX * TY;     // threads per block for cell kernels
+constexpr int MAX_BLOCKS = 8192;  // cap for grid-stride kernels with reductions
+constexpr int NXCD = 8;         // gfx950: 8 XCDs, each with its own L2
+
+// Per-launch geometry of the grid and the boundary kinds, passed by value.
+struct Geo {
+    int nx, ny, nz;
+    int ntx, nty;               // tiles per axis
+    long long ntiles;
+    double dx;
+    double ox, oy, oz;
+    int bc[6];
+    double uin[3];
+    int nblocks;                // launched blocks (grid-stride over tiles)
+};
+
+struct Solver {                 // device-resident scalars of the Krylov loops
+    double fnorm2;              // ||f||^2 of the current solve
+    double tol2;                // tol^2 * fnorm2
+    double rz, rz_new, rr, dq, alpha, beta;
+    double rr_prev_fcg;         // unused slot kept for layout stability
+    int converged;
+    int iters;
+    int nan_seen;
+    int pad;
+};
+
+}  // namespace ibm
+
+struct ibm_ctx {
+    int device;
+    int precision;
+    ibm::Geo geo;
+    long long N;
+    // tagging output kept for the stencil build
+    uint32_t* tagmask;      // padded 4-byte words, one byte per cell
+    double* theta;          // N*6
+    bool tagged;
+    // stencil
+    uint8_t* mask;          // effective blocked bits
+    uint16_t* flags;
+    int32_t* label;
+    uint32_t* cut_off;      // exclusive prefix of popcount(mask)
+    long long ncut;
+    long long ncut_cap;
+    int32_t* cut_cell;
+    uint8_t* cut_dir;
+    double* cut_theta;
+    double* a_ib;
+    double* a_c;
+    double* a_o;
+    int32_t* cut_opp;
+    int ncomp;              // enclosed components
+    long long nenc;         // cells in enclosed components
+    int32_t* enc_cells;     // sorted by (component, cell)
+    long long* comp_start;  // ncomp + 1
+    long long enc_cap;
+    int comp_cap;
+    int has_dead;
+    bool stencil_ready;
+    // per-step workspace
+    void* ustar[3];
+    void* nut;
+    double* b;
+    double* bwork;
+    double* r;
+    double* d;
+    double* q;
+    double* x64;            // FP64 scratch (refinement / fallback)
+    float* r32;             // mixed: inner FCG vectors
+    float* z32;
+    float* d32;
+    float* q32;
+    float* e32;
+    float* zprev32;
+    double* partials;       // 8 * MAX_BLOCKS (up to 8 reduction slots)
+    unsigned int* counter;  // last-block tickets
+    ibm::Solver* solver;    // device scalars
+    ibm::Solver* h_solver;  // pinned host mirror
+    double* h_red;          // pinned host scalars
+    double* red;            // device reduction outputs (8 doubles)
+    void* cnn;              // preconditioner network (IBM_SOLVER_FCG_CNN), not owned
+    int last_iters;         // iterations of the previous solve (batch sizing)
+    bool nut_valid;
+};
+
+namespace ibm {
+
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define IBM_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t _e = (call);                                        \
+        if (_e != hipSuccess) return ibm::hip_fail(_e, #call);         \
+    } while (0)
+
+inline int grid_blocks(const Geo& g) {
+    long long t = g.ntiles;
+    return (int)(t < MAX_BLOCKS ? t : MAX_BLOCKS);
+}
+
+// ---------------------------------------------------------------- device helpers
+
+// Logical chunk of block b so that the blocks resident on one XCD (b % 8) walk one
+// contiguous range of tiles: neighbouring planes stay in that XCD's L2.
+__device__ inline int xcd_chunk(int b, int nb) {
+    int per = nb / NXCD;
+    int full = per * NXCD;
+    if (b >= full) return b;
+    return (b % NXCD) * per + b / NXCD;
+}
+
+// Tile range [t0, t1) of this block.
+__device__ inline void tile_range(const Geo& g, long long& t0, long long& t1) {
+    int nb = gridDim.x;
+    int ch = xcd_chunk(blockIdx.x, nb);
+    t0 = g.ntiles * ch / nb;
+    t1 = g.ntiles * (ch + 1) / nb;
+}
+
+__device__ inline bool tile_cell(const Geo& g, long long t, int& i, int& j, int& k) {
+    int tx = (int)(t % g.ntx);
+    long long r = t / g.ntx;
+    int ty = (int)(r % g.nty);
+    k = (int)(r / g.nty);
+    i = tx * TX + (threadIdx.x % TX);
+    j = ty * TY + (threadIdx.x / TX);
+    return i < g.nx && j < g.ny;
+}
+
+__device__ inline long long cidx(const Geo& g, int i, int j, int k) {
+    return (long long)i + (long long)g.nx * ((long long)j + (long long)g.ny * k);
+}
+
+// Neighbour index across direction d (wrapping), and whether the face is a
+// non-periodic domain face.
+__device__ inline long long nb_index(const Geo& g, int i, int j, int k, int d, bool& boundary) {
+    int ax = d >> 1;
+    int s = (d & 1) ? 1 : -1;
+    int n = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
+    int co = ax == 0 ? i : (ax == 1 ? j : k);
+    int cn = co + s;
+    boundary = false;
+    if (cn < 0 || cn >= n) {
+        if (g.bc[d] != IBM_BC_PERIODIC) boundary = true;
+        cn = (cn + n) % n;
+    }
+    int ii = i, jj = j, kk = k;
+    if (ax == 0) ii = cn; else if (ax == 1) jj = cn; else kk = cn;
+    return cidx(g, ii, jj, kk);
+}
+
+// Deterministic block reduction of NV doubles (fixed tree order).
+template <int NV>
+__device__ inline void block_reduce(double (&v)[NV], double* sh /* NT*NV */) {
+    for (int a = 0; a < NV; ++a) sh[a * NT + threadIdx.x] = v[a];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int a = 0; a < NV; ++a) sh[a * NT + threadIdx.x] += sh[a * NT + threadIdx.x + s];
+        __syncthreads();
+    }
+    for (int a = 0; a < NV; ++a) v[a] = sh[a * NT];
+    __syncthreads();
+}
+
+// Writes the block partials and returns true in the last block to finish, after
+// which `tot` holds the totals summed over blocks in block order.
+template <int NV>
+__device__ inline bool grid_reduce(double (&v)[NV], double* partials, unsigned int* counter, double* sh,
+                                   double (&tot)[NV]) {
+    block_reduce<NV>(v, sh);
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < NV; ++a) partials[a * MAX_BLOCKS + blockIdx.x] = v[a];
+        __threadfence();
+        unsigned int t = atomicAdd(counter, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double acc[NV];
+    for (int a = 0; a < NV; ++a) acc[a] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += NT)
+        for (int a = 0; a < NV; ++a) acc[a] += partials[a * MAX_BLOCKS + b];
+    block_reduce<NV>(acc, sh);
+    for (int a = 0; a < NV; ++a) tot[a] = acc[a];
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+}  // namespace ibm
+
+// Host-side launchers implemented in the .hip files.
+namespace ibm {
+int tag_run(ibm_ctx* c, const double* tri, long long ntri, hipStream_t s);
+int stencil_run(ibm_ctx* c, const uint8_t* blocked, const double* theta, int deadend, hipStream_t s);
+int cut_points_run(ibm_ctx* c, double* xyz, hipStream_t s);
+int remove_means(ibm_ctx* c, double* a, hipStream_t s);
+int laplacian_run(ibm_ctx* c, const double* x, double* y, hipStream_t s);
+int init_state_run(ibm_ctx* c, void** u, double** U, double* p, void** h, const double* u0,
+                   const double* wall, hipStream_t s);
+int step_predict(ibm_ctx* c, void** u, double** U, void** h, const double* wall, const ibm_step_params* prm,
+                 hipStream_t s);
+int step_rhs(ibm_ctx* c, double** U, const double* wall, double dt, hipStream_t s);
+int step_project(ibm_ctx* c, void** u, double** U, const double* p, double dt, hipStream_t s);
+int divergence_norms(ibm_ctx* c, double** U, double* l2, double* linf, hipStream_t s);
+int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st,
+                hipStream_t s);
+int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hipStream_t s);
+int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
+               double* out, hipStream_t s);
+}  // namespace ibm

@@ -1,0 +1,621 @@
+// Per-step kernels of the fractional step (Sec. 2.1), templated on the cell-field
+// type T (double for the plain path, float for the mixed path); face velocities U,
+// pressure and the Poisson right-hand side are always double.
+//
+// Every kernel walks 64x4 tiles of one z-plane, one cell per thread, with the
+// XCD-aware tile order of common.h.  Face neighbours are read straight from global
+// memory: within a wavefront the x-neighbours are the same cache lines, the y- and
+// z-neighbours were just touched by the tiles before on the same XCD, so each value
+// comes from HBM about once.  Cells with a blocked face take the one branch that
+// looks up the cut list (the paper's single 'if' into the dummy-cell data, Sec. 2.3.1).
+
+#include "common.h"
+
+namespace ibm {
+
+struct Sten {
+    const uint8_t* mask;
+    const uint32_t* cut_off;
+    const double* a_ib;
+    const double* a_c;
+    const double* a_o;
+    const int32_t* opp;
+    const uint16_t* flags;
+    int has_dead;
+};
+
+template <class T>
+struct V3 {
+    T* p[3];
+};
+template <class T>
+struct C3 {
+    const T* p[3];
+};
+
+namespace {
+
+inline Sten sten_of(const ibm_ctx* c) {
+    return Sten{c->mask, c->cut_off, c->a_ib, c->a_c, c->a_o, c->cut_opp, c->flags, c->has_dead};
+}
+
+__device__ inline uint32_t cut_id(const Sten& st, long long c, uint8_t msk, int d) {
+    return st.cut_off[c] + (uint32_t)__builtin_popcount((unsigned)msk & ((1u << d) - 1u));
+}
+
+// eq. (q_axis) ghost of component m behind blocked face d of cell c
+template <class T>
+__device__ inline double ghost(const Sten& st, const T* q, long long c, uint8_t msk, int d, int m,
+                               const double* wall, double qc) {
+    uint32_t id = cut_id(st, c, msk, d);
+    double w = wall ? wall[3 * (long long)id + m] : 0.0;
+    double v = st.a_ib[id] * w + st.a_c[id] * qc;
+    int32_t o = st.opp[id];
+    if (o >= 0) v += st.a_o[id] * (double)q[o];
+    return v;
+}
+
+// velocity ghost behind a domain face: inflow Dirichlet u_in, slip (odd normal,
+// even tangential), outflow zero gradient
+__device__ inline double bc_ghost(const Geo& g, int d, int m, double qc) {
+    int kind = g.bc[d];
+    if (kind == IBM_BC_INFLOW) return 2.0 * g.uin[m] - qc;
+    if (kind == IBM_BC_SLIP && m == (d >> 1)) return -qc;
+    return qc;
+}
+
+template <class T, class A>
+__device__ inline void nbvals(const Geo& g, const Sten& st, const T* q, int m, int i, int j, int k, long long c,
+                              uint8_t msk, const double* wall, A qc, A (&nb)[6]) {
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        bool bnd;
+        long long n = nb_index(g, i, j, k, d, bnd);
+        if ((msk >> d) & 1) nb[d] = (A)ghost(st, q, c, msk, d, m, wall, (double)qc);
+        else if (bnd) nb[d] = (A)bc_ghost(g, d, m, (double)qc);
+        else nb[d] = (A)q[n];
+    }
+}
+
+// Coherent structure model (Sec. 2.3): G_ij by central differences, S, W, Q, E,
+// F_CS = Q/E, C = C1 |F_CS|^(3/2), nu_t = C dx^2 sqrt(S_ij S_ij).
+template <class T>
+__global__ void __launch_bounds__(NT) k_csm(Geo g, Sten st, C3<T> u, const double* wall, T* nut, double c1) {
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        long long c = cidx(g, i, j, k);
+        uint8_t msk = st.mask[c];
+        T G[3][3];
+        const T inv2dx = (T)(1.0 / (2.0 * g.dx));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            T nb[6];
+            T qc = u.p[a][c];
+            nbvals<T, T>(g, st, u.p[a], a, i, j, k, c, msk, wall, qc, nb);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) G[a][b] = (nb[2 * b + 1] - nb[2 * b]) * inv2dx;
+        }
+        T SS = 0, WW = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                T s = (T)0.5 * (G[a][b] + G[b][a]);
+                T w = (T)0.5 * (G[a][b] - G[b][a]);
+                SS += s * s;
+                WW += w * w;
+            }
+        T Q = (T)0.5 * (WW - SS);
+        T E = (T)0.5 * (WW + SS);
+        T F = E > (T)0 ? Q / E : (T)0;
+        T aF = F < (T)0 ? -F : F;
+        T C = (T)c1 * aF * sqrt(aF);
+        nut[c] = C * (T)(g.dx * g.dx) * sqrt(SS);
+    }
+}
+
+// Momentum predictor (Sec. 2.1, explicit Adams-Bashforth form):
+// H = -(1/dx) sum_f s U_f (q_c + q_nb)/2 + (1/dx^2) sum_f (nu + nu_t,f)(q_nb - q_c) + g,
+// u* = u + dt (3/2 H - 1/2 H_prev), forward Euler on the first step.  q_nb is the
+// eq. (q_axis) ghost behind blocked faces, which realises the direct forcing of
+// eq. (forcing_term).  Dead-end cells are frozen at their mean wall velocity.
+template <class T>
+__global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<double> U, const T* nut, V3<T> hio,
+                                                V3<T> us, const double* wall, double dt, double nu, double bx,
+                                                double by, double bz, int first) {
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    const double body[3] = {bx, by, bz};
+    const T idx = (T)(1.0 / g.dx);
+    const T idx2 = (T)(1.0 / (g.dx * g.dx));
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        long long c = cidx(g, i, j, k);
+        uint8_t msk = st.mask[c];
+        T nut_c = nut[c];
+        T visc[6];
+        T Uf[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            bool bnd;
+            long long n = nb_index(g, i, j, k, d, bnd);
+            bool closed = bnd || ((msk >> d) & 1);
+            visc[d] = (T)nu + (closed ? nut_c : (T)0.5 * (nut_c + nut[n]));
+            int ax = d >> 1;
+            if (d & 1) {
+                Uf[d] = (T)U.p[ax][c];
+            } else if (bnd) {
+                Uf[d] = g.bc[d] == IBM_BC_INFLOW ? (T)g.uin[ax] : (T)0;
+            } else {
+                Uf[d] = (T)U.p[ax][n];
+            }
+        }
+        const int nbits = __builtin_popcount((unsigned)msk);
+        bool dead = st.has_dead && nbits >= 5 && ((st.flags[c] >> 14) & 1);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            T qc = u.p[m][c];
+            T nb[6];
+            nbvals<T, T>(g, st, u.p[m], m, i, j, k, c, msk, wall, qc, nb);
+            T h = (T)body[m];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                T s = (d & 1) ? (T)1 : (T)-1;
+                T qf = (T)0.5 * (qc + nb[d]);
+                h = h - s * Uf[d] * qf * idx + visc[d] * (nb[d] - qc) * idx2;
+            }
+            T v;
+            if (first) v = qc + (T)dt * h;
+            else v = qc + (T)dt * ((T)1.5 * h - (T)0.5 * hio.p[m][c]);
+            if (dead) {
+                uint32_t id0 = st.cut_off[c];
+                double acc = 0.0;
+                for (int q = 0; q < nbits; ++q) acc += wall ? wall[3 * (long long)(id0 + q) + m] : 0.0;
+                v = (T)(acc / (double)nbits);
+                h = (T)0;
+            }
+            us.p[m][c] = v;
+            hio.p[m][c] = h;
+        }
+    }
+}
+
+// normal wall velocity on the +k face of cell c (blocked): mean of the two cuts
+// that see the face, one from each side
+template <class T>
+__device__ inline double wall_face(const Sten& st, long long c, uint8_t msk, long long nb, int k,
+                                   const double* wall) {
+    if (!wall) return 0.0;
+    uint32_t a = cut_id(st, c, msk, 2 * k + 1);
+    uint8_t mn = st.mask[nb];
+    uint32_t b = cut_id(st, nb, mn, 2 * k);
+    return 0.5 * (wall[3 * (long long)a + k] + wall[3 * (long long)b + k]);
+}
+
+// Face velocity U* and b = div(U*)/dt (eq. poisson).  U* is the mean of the two
+// predicted cell velocities on open faces, the wall normal velocity on blocked faces
+// and the boundary value on domain faces.  Each thread also evaluates its -faces, so
+// the kernel needs no second pass.
+template <class T>
+__global__ void __launch_bounds__(NT) k_rhs(Geo g, Sten st, C3<T> us, V3<double> U, double* b,
+                                            const double* wall, double dt) {
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    const double idx = 1.0 / g.dx;
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        long long c = cidx(g, i, j, k);
+        uint8_t msk = st.mask[c];
+        double div = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double qc = (double)us.p[a][c];
+            int dp = 2 * a + 1, dm = 2 * a;
+            bool bp, bm;
+            long long np = nb_index(g, i, j, k, dp, bp);
+            long long nm = nb_index(g, i, j, k, dm, bm);
+            double Up, Um;
+            if ((msk >> dp) & 1) Up = wall_face<T>(st, c, msk, np, a, wall);
+            else if (bp) Up = g.bc[dp] == IBM_BC_INFLOW ? g.uin[a] : (g.bc[dp] == IBM_BC_OUTFLOW ? qc : 0.0);
+            else Up = 0.5 * (qc + (double)us.p[a][np]);
+            if ((msk >> dm) & 1) Um = wall_face<T>(st, nm, st.mask[nm], c, a, wall);
+            else if (bm) Um = g.bc[dm] == IBM_BC_INFLOW ? g.uin[a] : 0.0;
+            else Um = 0.5 * ((double)us.p[a][nm] + qc);
+            U.p[a][c] = Up;
+            div += (Up - Um) * idx;
+        }
+        b[c] = div / dt;
+    }
+}
+
+// Correction (eq. correction): U = U* - dt (p_nb - p_c)/dx on open faces, U* + 2 dt p_c/dx
+// on outlet faces (p = 0 on the face), unchanged on blocked/inflow/slip faces;
+// u = u* - dt (p_E - p_W)/(2 dx) with the Neumann ghost p_c behind blocked, inflow and
+// slip faces and the Dirichlet ghost -p_c behind outlet faces.
+template <class T>
+__global__ void __launch_bounds__(NT) k_project(Geo g, Sten st, C3<T> us, V3<double> U, const double* p, V3<T> u,
+                                                double dt) {
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    const double idx = 1.0 / g.dx;
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        long long c = cidx(g, i, j, k);
+        uint8_t msk = st.mask[c];
+        double pc = p[c];
+        bool dead = st.has_dead && __builtin_popcount((unsigned)msk) >= 5 && ((st.flags[c] >> 14) & 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int dp = 2 * a + 1, dm = 2 * a;
+            bool bp, bm;
+            long long np = nb_index(g, i, j, k, dp, bp);
+            long long nm = nb_index(g, i, j, k, dm, bm);
+            bool openp = !bp && !((msk >> dp) & 1);
+            bool openm = !bm && !((msk >> dm) & 1);
+            bool outp = bp && g.bc[dp] == IBM_BC_OUTFLOW;
+            bool outm = bm && g.bc[dm] == IBM_BC_OUTFLOW;
+            double pE = openp ? p[np] : (outp ? -pc : pc);
+            double pW = openm ? p[nm] : (outm ? -pc : pc);
+            double Uc = U.p[a][c];
+            if (openp) Uc = Uc - dt * (pE - pc) * idx;
+            else if (outp) Uc = Uc + 2.0 * dt * pc * idx;
+            U.p[a][c] = Uc;
+            double usc = (double)us.p[a][c];
+            double v = dead ? usc : usc - dt * (pE - pW) / (2.0 * g.dx);
+            u.p[a][c] = (T)v;
+        }
+    }
+}
+
+// ||div U||_2^2 and max |div U| (FP64 divergence check); per-block sums and maxima,
+// combined by the last block in block order
+__global__ void __launch_bounds__(NT) k_div(Geo g, C3<double> U, double* partials, unsigned int* counter,
+                                            double* out) {
+    __shared__ double sh[NT];
+    __shared__ double shm[NT];
+    __shared__ bool last;
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    double v0 = 0.0, v1 = 0.0;
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        long long c = cidx(g, i, j, k);
+        double div = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            bool bm;
+            long long nm = nb_index(g, i, j, k, 2 * a, bm);
+            double Um = bm ? (g.bc[2 * a] == IBM_BC_INFLOW ? g.uin[a] : 0.0) : U.p[a][nm];
+            div += (U.p[a][c] - Um) / g.dx;
+        }
+        v0 += div * div;
+        v1 = fmax(v1, fabs(div));
+    }
+    sh[threadIdx.x] = v0;
+    shm[threadIdx.x] = v1;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[threadIdx.x] += sh[threadIdx.x + s];
+            shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = sh[0];
+        partials[MAX_BLOCKS + blockIdx.x] = shm[0];
+        __threadfence();
+        unsigned int tk = atomicAdd(counter, 1u);
+        last = (tk == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double acc = 0.0, mx = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += NT) {
+        acc += partials[b];
+        mx = fmax(mx, partials[MAX_BLOCKS + b]);
+    }
+    sh[threadIdx.x] = acc;
+    shm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[threadIdx.x] += sh[threadIdx.x + s];
+            shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sh[0];
+        out[1] = shm[0];
+        *counter = 0u;
+    }
+}
+
+// Initial state: u = u0; U = u0 on open/periodic/outflow faces, mean wall normal
+// velocity on blocked faces, boundary value on inflow/slip faces; p = 0; H = 0.
+template <class T>
+__global__ void __launch_bounds__(NT) k_init(Geo g, Sten st, V3<T> u, V3<double> U, double* p, V3<T> h,
+                                             double u0x, double u0y, double u0z, const double* wall) {
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    const double u0[3] = {u0x, u0y, u0z};
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        long long c = cidx(g, i, j, k);
+        uint8_t msk = st.mask[c];
+        for (int a = 0; a < 3; ++a) {
+            u.p[a][c] = (T)u0[a];
+            h.p[a][c] = (T)0;
+            int dp = 2 * a + 1;
+            bool bp;
+            long long np = nb_index(g, i, j, k, dp, bp);
+            double v = u0[a];
+            if (bp && g.bc[dp] == IBM_BC_INFLOW) v = g.uin[a];
+            else if (bp && g.bc[dp] == IBM_BC_SLIP) v = 0.0;
+            if ((msk >> dp) & 1) v = wall_face<T>(st, c, msk, np, a, wall);
+            U.p[a][c] = v;
+        }
+        p[c] = 0.0;
+    }
+}
+
+// y = L x: (1/dx^2) [sum over open faces (x_nb - x_c) - 2 x_c per outlet face]
+__global__ void __launch_bounds__(NT) k_lap(Geo g, const uint8_t* mask, const double* x, double* y) {
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        long long c = cidx(g, i, j, k);
+        uint8_t msk = mask[c];
+        double xc = x[c];
+        double acc = 0.0;
+        for (int d = 0; d < 6; ++d) {
+            bool bnd;
+            long long n = nb_index(g, i, j, k, d, bnd);
+            if (bnd) {
+                if (g.bc[d] == IBM_BC_OUTFLOW) acc += -2.0 * xc;
+            } else if (!((msk >> d) & 1)) {
+                acc += x[n] - xc;
+            }
+        }
+        y[c] = acc * idx2;
+    }
+}
+
+__global__ void k_cut_points(Geo g, long long ncut, const int32_t* cell, const uint8_t* dir, const double* theta,
+                             double* X) {
+    for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < ncut;
+         id += (long long)gridDim.x * blockDim.x) {
+        long long c = cell[id];
+        int i = (int)(c % g.nx);
+        int j = (int)((c / g.nx) % g.ny);
+        int k = (int)(c / ((long long)g.nx * g.ny));
+        double x = g.ox + ((double)i + 0.5) * g.dx;
+        double y = g.oy + ((double)j + 0.5) * g.dx;
+        double z = g.oz + ((double)k + 0.5) * g.dx;
+        int d = dir[id];
+        double s = (d & 1) ? 1.0 : -1.0;
+        double off = s * theta[id] * g.dx;
+        int ax = d >> 1;
+        if (ax == 0) x += off; else if (ax == 1) y += off; else z += off;
+        X[3 * id] = x;
+        X[3 * id + 1] = y;
+        X[3 * id + 2] = z;
+    }
+}
+
+// Force on the surface: F_p += dx^2 s p_c e_k, F_v -= dx^2 (nu + nu_t,c)(q_GC - q_c)/dx,
+// summed over the cut list in a fixed order.
+template <class T>
+__global__ void __launch_bounds__(NT) k_forces(long long ncut, const int32_t* cell, const uint8_t* dir,
+                                               const double* a_ib, const double* a_c, const double* a_o,
+                                               const int32_t* opp, C3<T> u, const double* p, const T* nut,
+                                               double nu, double dx, const double* wall, double* partials,
+                                               unsigned int* counter, double* out) {
+    __shared__ double sh[6 * NT];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    const double A = dx * dx;
+    long long per = (ncut + gridDim.x - 1) / gridDim.x;
+    long long b0 = per * blockIdx.x, b1 = b0 + per < ncut ? b0 + per : ncut;
+    for (long long id = b0 + threadIdx.x; id < b1; id += NT) {
+        long long c = cell[id];
+        int d = dir[id];
+        int ax = d >> 1;
+        double s = (d & 1) ? 1.0 : -1.0;
+        v[ax] += s * p[c] * A;
+        double vis = nu + (nut ? (double)nut[c] : 0.0);
+        int32_t o = opp[id];
+        for (int m = 0; m < 3; ++m) {
+            double qc = (double)u.p[m][c];
+            double w = wall ? wall[3 * id + m] : 0.0;
+            double gh = a_ib[id] * w + a_c[id] * qc;
+            if (o >= 0) gh += a_o[id] * (double)u.p[m][o];
+            v[3 + m] -= vis * (gh - qc) / dx * A;
+        }
+    }
+    double tot[6];
+    if (grid_reduce<6>(v, partials, counter, sh, tot)) {
+        if (threadIdx.x == 0)
+            for (int a = 0; a < 6; ++a) out[a] = tot[a];
+    }
+}
+
+// Mean removal on every enclosed component: one block per component, fixed order.
+__global__ void __launch_bounds__(NT) k_remove_means(const int32_t* cells, const long long* start, double* a) {
+    __shared__ double sh[NT];
+    long long s0 = start[blockIdx.x], s1 = start[blockIdx.x + 1];
+    double v[1] = {0.0};
+    for (long long q = s0 + threadIdx.x; q < s1; q += NT) v[0] += a[cells[q]];
+    block_reduce<1>(v, sh);
+    double mean = v[0] / (double)(s1 - s0);
+    for (long long q = s0 + threadIdx.x; q < s1; q += NT) a[cells[q]] -= mean;
+}
+
+template <class T>
+__global__ void k_copy(const T* a, T* b, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+template <class T>
+__global__ void k_zero(T* a, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = (T)0;
+}
+
+template <class T>
+int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, const ibm_step_params* prm,
+              hipStream_t s) {
+    const Geo& g = c->geo;
+    Sten st = sten_of(c);
+    int nb = grid_blocks(g);
+    C3<T> uu{{(const T*)u[0], (const T*)u[1], (const T*)u[2]}};
+    T* nut = (T*)c->nut;
+    if (prm->csm_on) {
+        k_csm<T><<<nb, NT, 0, s>>>(g, st, uu, wall, nut, prm->c1);
+    } else {
+        k_zero<T><<<2048, 256, 0, s>>>(nut, c->N);
+    }
+    c->nut_valid = true;
+    C3<double> UU{{U[0], U[1], U[2]}};
+    V3<T> hh{{(T*)h[0], (T*)h[1], (T*)h[2]}};
+    V3<T> us{{(T*)c->ustar[0], (T*)c->ustar[1], (T*)c->ustar[2]}};
+    k_predict<T><<<nb, NT, 0, s>>>(g, st, uu, UU, nut, hh, us, wall, prm->dt, prm->nu, prm->body_force[0],
+                                   prm->body_force[1], prm->body_force[2], prm->step == 0 ? 1 : 0);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+template <class T>
+int rhs_t(ibm_ctx* c, double** U, const double* wall, double dt, hipStream_t s) {
+    const Geo& g = c->geo;
+    C3<T> us{{(const T*)c->ustar[0], (const T*)c->ustar[1], (const T*)c->ustar[2]}};
+    V3<double> UU{{U[0], U[1], U[2]}};
+    k_rhs<T><<<grid_blocks(g), NT, 0, s>>>(g, sten_of(c), us, UU, c->b, wall, dt);
+    IBM_HIP(hipGetLastError());
+    return remove_means(c, c->b, s);
+}
+
+template <class T>
+int project_t(ibm_ctx* c, void** u, double** U, const double* p, double dt, hipStream_t s) {
+    const Geo& g = c->geo;
+    C3<T> us{{(const T*)c->ustar[0], (const T*)c->ustar[1], (const T*)c->ustar[2]}};
+    V3<double> UU{{U[0], U[1], U[2]}};
+    V3<T> uu{{(T*)u[0], (T*)u[1], (T*)u[2]}};
+    k_project<T><<<grid_blocks(g), NT, 0, s>>>(g, sten_of(c), us, UU, p, uu, dt);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+template <class T>
+int init_t(ibm_ctx* c, void** u, double** U, double* p, void** h, const double* u0, const double* wall,
+           hipStream_t s) {
+    const Geo& g = c->geo;
+    V3<T> uu{{(T*)u[0], (T*)u[1], (T*)u[2]}};
+    V3<T> hh{{(T*)h[0], (T*)h[1], (T*)h[2]}};
+    V3<double> UU{{U[0], U[1], U[2]}};
+    k_init<T><<<grid_blocks(g), NT, 0, s>>>(g, sten_of(c), uu, UU, p, hh, u0[0], u0[1], u0[2], wall);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+template <class T>
+int forces_t(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
+             double* out, hipStream_t s) {
+    C3<T> uu{{(const T*)u[0], (const T*)u[1], (const T*)u[2]}};
+    const T* nt = nut ? (const T*)nut : (c->nut_valid ? (const T*)c->nut : nullptr);
+    if (c->ncut == 0) {
+        for (int a = 0; a < 6; ++a) out[a] = 0.0;
+        return IBM_OK;
+    }
+    long long nbk = (c->ncut + NT - 1) / NT;
+    int nb = (int)(nbk < 1024 ? nbk : 1024);
+    k_forces<T><<<nb, NT, 0, s>>>(c->ncut, c->cut_cell, c->cut_dir, c->a_ib, c->a_c, c->a_o, c->cut_opp, uu, p, nt,
+                                  nu, c->geo.dx, wall, c->partials, c->counter, c->red);
+    IBM_HIP(hipGetLastError());
+    IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    for (int a = 0; a < 6; ++a) out[a] = c->h_red[a];
+    return IBM_OK;
+}
+
+}  // namespace
+
+int remove_means(ibm_ctx* c, double* a, hipStream_t s) {
+    if (c->ncomp <= 0) return IBM_OK;
+    k_remove_means<<<c->ncomp, NT, 0, s>>>(c->enc_cells, c->comp_start, a);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int laplacian_run(ibm_ctx* c, const double* x, double* y, hipStream_t s) {
+    k_lap<<<grid_blocks(c->geo), NT, 0, s>>>(c->geo, c->mask, x, y);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int cut_points_run(ibm_ctx* c, double* xyz, hipStream_t s) {
+    if (c->ncut == 0) return IBM_OK;
+    long long nbk = (c->ncut + 255) / 256;
+    int nb = (int)(nbk < 4096 ? nbk : 4096);
+    k_cut_points<<<nb, 256, 0, s>>>(c->geo, c->ncut, c->cut_cell, c->cut_dir, c->cut_theta, xyz);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int init_state_run(ibm_ctx* c, void** u, double** U, double* p, void** h, const double* u0, const double* wall,
+                   hipStream_t s) {
+    return c->precision == IBM_FP64 ? init_t<double>(c, u, U, p, h, u0, wall, s)
+                                    : init_t<float>(c, u, U, p, h, u0, wall, s);
+}
+
+int step_predict(ibm_ctx* c, void** u, double** U, void** h, const double* wall, const ibm_step_params* prm,
+                 hipStream_t s) {
+    return c->precision == IBM_FP64 ? predict_t<double>(c, u, U, h, wall, prm, s)
+                                    : predict_t<float>(c, u, U, h, wall, prm, s);
+}
+
+int step_rhs(ibm_ctx* c, double** U, const double* wall, double dt, hipStream_t s) {
+    return c->precision == IBM_FP64 ? rhs_t<double>(c, U, wall, dt, s) : rhs_t<float>(c, U, wall, dt, s);
+}
+
+int step_project(ibm_ctx* c, void** u, double** U, const double* p, double dt, hipStream_t s) {
+    return c->precision == IBM_FP64 ? project_t<double>(c, u, U, p, dt, s) : project_t<float>(c, u, U, p, dt, s);
+}
+
+int divergence_norms(ibm_ctx* c, double** U, double* l2, double* linf, hipStream_t s) {
+    C3<double> UU{{U[0], U[1], U[2]}};
+    k_div<<<grid_blocks(c->geo), NT, 0, s>>>(c->geo, UU, c->partials, c->counter, c->red);
+    IBM_HIP(hipGetLastError());
+    IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    *l2 = sqrt(c->h_red[0]);
+    *linf = c->h_red[1];
+    return IBM_OK;
+}
+
+int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
+               double* out, hipStream_t s) {
+    return c->precision == IBM_FP64 ? forces_t<double>(c, u, p, nut, nu, wall, out, s)
+                                    : forces_t<float>(c, u, p, nut, nu, wall, out, s);
+}
+
+int copy_cells(ibm_ctx* c, const void* src, void* dst, bool is_double, hipStream_t s) {
+    if (is_double) k_copy<double><<<2048, 256, 0, s>>>((const double*)src, (double*)dst, c->N);
+    else k_copy<float><<<2048, 256, 0, s>>>((const float*)src, (float*)dst, c->N);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+}  // namespace ibm

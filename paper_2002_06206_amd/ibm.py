@@ -1,0 +1,271 @@
+"""Python binding of the C ABI in include/ibm.h (ctypes; argument marshalling only).
+
+Every function named ``ibm_*`` here calls the C entry point of the same name in
+libibm.so with device pointers taken from torch tensors and the current torch
+stream; torch is used for device memory and streams only.  All arithmetic of the
+step runs in the library's gfx950 kernels.  If libibm.so is missing or cannot be
+loaded this module raises at import: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibm.so")
+
+PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+SOLVER_PCG_JACOBI, SOLVER_FCG_CNN, SOLVER_FCG_JACOBI = 0, 1, 2
+OK, NOT_CONVERGED = 0, 1
+
+
+class IBMError(RuntimeError):
+    pass
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double), ("origin", ctypes.c_double * 3)]
+
+
+class BC(ctypes.Structure):
+    _fields_ = [("face", ctypes.c_int32 * 6), ("u_in", ctypes.c_double * 3)]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32),
+                ("stall_factor", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("force_stall", ctypes.c_int32)]
+
+
+class StepParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("nu", ctypes.c_double), ("c1", ctypes.c_double),
+                ("csm_on", ctypes.c_int32), ("step", ctypes.c_int32), ("body_force", ctypes.c_double * 3),
+                ("poisson", SolverOpts)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters_inner", ctypes.c_int32), ("iters_outer", ctypes.c_int32),
+                ("fallback_used", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("div_l2", ctypes.c_double), ("div_linf", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libibm.so is not built (run: python -m paper_2002_06206_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    P3 = vp * 3
+    sig = {
+        "ibm_create": ([ctypes.POINTER(Grid), ctypes.POINTER(BC), ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int),
+        "ibm_destroy": ([vp], ctypes.c_int),
+        "ibm_last_error": ([], ctypes.c_char_p),
+        "ibm_tag_geometry": ([vp, vp, ctypes.c_int64, vp, vp, vp], ctypes.c_int),
+        "ibm_build_stencils": ([vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.POINTER(ctypes.c_int64), vp],
+                               ctypes.c_int),
+        "ibm_cut_points": ([vp, vp, vp], ctypes.c_int),
+        "ibm_init_state": ([vp, P3, P3, vp, P3, ctypes.POINTER(ctypes.c_double), vp, vp], ctypes.c_int),
+        "ibm_step": ([vp, P3, P3, vp, P3, vp, ctypes.POINTER(StepParams), ctypes.POINTER(Stats), vp],
+                     ctypes.c_int),
+        "ibm_poisson_solve": ([vp, vp, vp, ctypes.POINTER(SolverOpts), ctypes.POINTER(Stats), vp], ctypes.c_int),
+        "ibm_apply_laplacian": ([vp, vp, vp, vp], ctypes.c_int),
+        "ibm_get_nut": ([vp, vp, vp], ctypes.c_int),
+        "ibm_get_rhs": ([vp, vp, vp], ctypes.c_int),
+        "ibm_forces": ([vp, P3, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "ibm_build_stencils",
+            "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
+            "ibm_get_nut", "ibm_get_rhs", "ibm_forces")
+
+
+def lib():
+    return _lib
+
+
+def _check(rc, what):
+    if rc < 0:
+        msg = _lib.ibm_last_error()
+        raise IBMError("%s failed (%d): %s" % (what, rc, msg.decode() if msg else ""))
+    return rc
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise IBMError("fields must be contiguous CUDA (HIP) tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _p3(ts):
+    return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
+
+
+# ------------------------------------------------------------ C ABI, same names
+
+def ibm_create(n, dx, origin, bc, u_in=(0.0, 0.0, 0.0), precision=FP64):
+    g = Grid((ctypes.c_int32 * 3)(*n), float(dx), (ctypes.c_double * 3)(*origin))
+    b = BC((ctypes.c_int32 * 6)(*bc), (ctypes.c_double * 3)(*u_in))
+    out = ctypes.c_void_p()
+    _check(_lib.ibm_create(ctypes.byref(g), ctypes.byref(b), int(precision), ctypes.byref(out)), "ibm_create")
+    return out
+
+
+def ibm_destroy(ctx):
+    return _check(_lib.ibm_destroy(ctx), "ibm_destroy")
+
+
+def ibm_tag_geometry(ctx, tri, blocked, theta=None):
+    assert tri.dtype == torch.float64 and blocked.dtype == torch.uint8
+    return _check(_lib.ibm_tag_geometry(ctx, _ptr(tri), tri.shape[0] if tri.numel() else 0, _ptr(blocked),
+                                        _ptr(theta), _stream()), "ibm_tag_geometry")
+
+
+def ibm_build_stencils(ctx, blocked, theta=None, deadend=False, flags=None, label=None):
+    ncut = ctypes.c_int64(0)
+    _check(_lib.ibm_build_stencils(ctx, _ptr(blocked), _ptr(theta), int(bool(deadend)), _ptr(flags), _ptr(label),
+                                   ctypes.byref(ncut), _stream()), "ibm_build_stencils")
+    return int(ncut.value)
+
+
+def ibm_cut_points(ctx, xyz):
+    return _check(_lib.ibm_cut_points(ctx, _ptr(xyz), _stream()), "ibm_cut_points")
+
+
+def ibm_init_state(ctx, u, U, p, h, u0, wall=None):
+    return _check(_lib.ibm_init_state(ctx, _p3(u), _p3(U), _ptr(p), _p3(h), (ctypes.c_double * 3)(*u0),
+                                      _ptr(wall), _stream()), "ibm_init_state")
+
+
+def ibm_step(ctx, u, U, p, h, params: StepParams, wall=None, want_stats=True):
+    st = Stats()
+    rc = _check(_lib.ibm_step(ctx, _p3(u), _p3(U), _ptr(p), _p3(h), _ptr(wall), ctypes.byref(params),
+                              ctypes.byref(st) if want_stats else None, _stream()), "ibm_step")
+    return rc, (st.as_dict() if want_stats else None)
+
+
+def ibm_poisson_solve(ctx, b, x, opts: SolverOpts):
+    st = Stats()
+    rc = _check(_lib.ibm_poisson_solve(ctx, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(st), _stream()),
+                "ibm_poisson_solve")
+    return rc, st.as_dict()
+
+
+def ibm_apply_laplacian(ctx, x, y):
+    return _check(_lib.ibm_apply_laplacian(ctx, _ptr(x), _ptr(y), _stream()), "ibm_apply_laplacian")
+
+
+def ibm_get_nut(ctx, out):
+    return _check(_lib.ibm_get_nut(ctx, _ptr(out), _stream()), "ibm_get_nut")
+
+
+def ibm_get_rhs(ctx, out):
+    return _check(_lib.ibm_get_rhs(ctx, _ptr(out), _stream()), "ibm_get_rhs")
+
+
+def ibm_forces(ctx, u, p, nu, nut=None, wall=None):
+    out = (ctypes.c_double * 6)()
+    _check(_lib.ibm_forces(ctx, _p3(u), _ptr(p), _ptr(nut), float(nu), _ptr(wall), out, _stream()), "ibm_forces")
+    return list(out[:3]), list(out[3:])
+
+
+# ------------------------------------------------------------- convenience
+
+def solver_opts(tol=1e-10, max_iter=20000, kind=SOLVER_PCG_JACOBI, inner_tol=1e-2, inner_max_iter=200,
+                stall_factor=2.0, check_every=16, force_stall=0):
+    return SolverOpts(tol, max_iter, kind, inner_tol, inner_max_iter, stall_factor, check_every, force_stall)
+
+
+def step_params(dt, nu, c1=1.0 / 20.0, csm=True, step=0, body=(0.0, 0.0, 0.0), **solver):
+    return StepParams(dt, nu, c1, int(bool(csm)), int(step), (ctypes.c_double * 3)(*body), solver_opts(**solver))
+
+
+class Solver:
+    """Owns one context and the flow state on the current HIP device."""
+
+    def __init__(self, n, dx, origin, bc, u_in=(0.0, 0.0, 0.0), precision=FP64, device=None):
+        self.n = tuple(int(v) for v in n)
+        self.shape = (self.n[2], self.n[1], self.n[0])
+        self.dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.precision = precision
+        self.ftype = torch.float64 if precision == FP64 else torch.float32
+        self.ctx = ibm_create(self.n, dx, origin, bc, u_in, precision)
+        self.ncut = 0
+
+    def close(self):
+        if self.ctx is not None:
+            ibm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tag(self, tri):
+        tri_t = torch.as_tensor(tri, dtype=torch.float64).to(self.dev).contiguous()
+        blocked = torch.zeros(self.shape, dtype=torch.uint8, device=self.dev)
+        theta = torch.empty(self.shape + (6,), dtype=torch.float64, device=self.dev)
+        ibm_tag_geometry(self.ctx, tri_t.reshape(-1, 3, 3), blocked, theta)
+        return blocked, theta
+
+    def build(self, blocked, theta=None, deadend=False):
+        flags = torch.empty(self.shape, dtype=torch.int16, device=self.dev)
+        label = torch.empty(self.shape, dtype=torch.int32, device=self.dev)
+        self.ncut = ibm_build_stencils(self.ctx, blocked, theta, deadend, flags, label)
+        return flags, label
+
+    def cut_points(self):
+        X = torch.empty((max(self.ncut, 1), 3), dtype=torch.float64, device=self.dev)
+        ibm_cut_points(self.ctx, X)
+        return X[: self.ncut]
+
+    def new_state(self, u0, wall=None):
+        z = lambda dt: torch.empty(self.shape, dtype=dt, device=self.dev)  # noqa: E731
+        st = {"u": [z(self.ftype) for _ in range(3)], "U": [z(torch.float64) for _ in range(3)],
+              "p": z(torch.float64), "h": [z(self.ftype) for _ in range(3)]}
+        ibm_init_state(self.ctx, st["u"], st["U"], st["p"], st["h"], u0, wall)
+        return st
+
+    def step(self, st, params, wall=None, want_stats=True):
+        return ibm_step(self.ctx, st["u"], st["U"], st["p"], st["h"], params, wall, want_stats)
+
+    def poisson(self, b, x, **opts):
+        return ibm_poisson_solve(self.ctx, b, x, solver_opts(**opts))
+
+    def laplacian(self, x):
+        y = torch.empty_like(x)
+        ibm_apply_laplacian(self.ctx, x, y)
+        return y
+
+    def nut(self):
+        out = torch.empty(self.shape, dtype=self.ftype, device=self.dev)
+        ibm_get_nut(self.ctx, out)
+        return out
+
+    def rhs(self):
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.dev)
+        ibm_get_rhs(self.ctx, out)
+        return out
+
+    def forces(self, st, nu, wall=None):
+        return ibm_forces(self.ctx, st["u"], st["p"], nu, None, wall)
