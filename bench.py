@@ -1,0 +1,236 @@
+"""Benchmark: cell-steps/s of the immersed-boundary time step at Poisson
+(divergence) residual 1e-6 on one MI355X.
+
+Workload (default): 256^3 uniform cells, 40 seeded overlapping ellipsoids
+(semi-axes 4-20 cells, ~2k triangles each, 3% gaps) plus 5 thin plates, inflow
+U = 1, Re = 1e4 on the mean ellipsoid diameter, CSM on, CFL 0.3.  A step is one
+pass of the whole hot path on this input: eddy viscosity, predictor, face
+velocity and right-hand side, pressure solve to relative residual 1e-6,
+projection, FP64 divergence check and surface force.  Tagging and the stencil
+build happen once per geometry before the timed region (reported as setup).
+
+Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-steps/s at div residual 1e-6: mixed+learned vs plain FP64, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell of the two fused conjugate-gradient passes (FP64
+# vectors, 1-byte pressure code): A reads z, d, x, code and writes x, d; B reads d, r,
+# code and writes r, z
+SWEEP_BYTES = {"pcg_a": 41, "pcg_b": 33, "unused": 0}
+SWEEP_NAMES = ("pcg_a", "pcg_b", "unused")
+# kernel names of the double2 passes (grids with an even cell count in x; the scalar
+# passes k_pcg_a / k_pcg_b serve odd nx)
+KERNEL_SYMBOL = {"pcg_a": "k_pcg_a_v", "pcg_b": "k_pcg_b_v", "unused": ""}
+
+
+def workload(name):
+    from paper_2002_06206_amd import inputs
+    if name == "ellipsoids256":
+        return inputs.case_ellipsoids256(0)
+    if name == "dirty_sphere128":
+        return inputs.case_dirty_sphere128(0)
+    if name == "sphere32":
+        return inputs.case_sphere32(0)
+    if name == "plate256":
+        return inputs.case_plate256(0)
+    raise SystemExit("unknown workload %s" % name)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("poisson.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2002_06206_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel, wl):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, when it was
+    taken on the current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, wl))
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("{"):
+            try:
+                d = json.loads(line)
+            except ValueError:
+                return None
+            if d.get("source_sha256") == kernel_source_hash():
+                return d.get("hbm_bytes_per_launch")
+    return None
+
+
+def cpu_baseline(case, gpu_iters_per_step, n_pcg=3):
+    """The FP64 oracle on a bounded sample of the same workload: one time step with
+    eddy viscosity, predictor, face velocity + right-hand side and projection timed
+    in full, and `n_pcg` conjugate-gradient iterations timed and scaled to the
+    iterations per step the GPU solve needed (same algorithm)."""
+    import numpy as np
+
+    from oracle import flow, tagging
+    g = flow.Grid(case.n, case.dx, case.origin, case.bc, case.u_in)
+    b, th = tagging.tag(case.tri, case.n, case.dx, case.origin)
+    st = flow.build_stencils(g, b, th, case.deadend)
+    u, U, p, h = flow.init_state(st, case.u_in)
+    t0 = time.perf_counter()
+    nut = flow.csm_nut(st, u) if case.csm else np.zeros(g.shape)
+    us, H = flow.predictor(st, u, U, h, nut, case.nu, case.dt, (0.0, 0.0, 0.0), 0, None)
+    Us = flow.face_predicted(st, us, None)
+    rhs = flow.poisson_rhs(st, Us, case.dt)
+    t1 = time.perf_counter()
+    x, it = flow.pcg(st, rhs, p, 1e-30, n_pcg)
+    t2 = time.perf_counter()
+    flow.project(st, us, Us, x, case.dt)
+    t3 = time.perf_counter()
+    t_fixed = (t1 - t0) + (t3 - t2)
+    t_iter = (t2 - t1) / max(it, 1)
+    t_step = t_fixed + gpu_iters_per_step * t_iter
+    return {
+        "value": float(g.ncell / t_step),
+        "unit": "cell-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": ("one FP64 oracle step on the same %dx%dx%d workload: eddy viscosity, predictor, face "
+                   "velocity/RHS and projection timed in full (%.1f s); %d PCG iterations timed (%.2f s each) "
+                   "and scaled to the %.1f iterations per step of the GPU solve (numpy, single thread)"
+                   % (case.n[0], case.n[1], case.n[2], t_fixed, it, t_iter, gpu_iters_per_step)),
+        "seconds_measured": round(t3 - t0, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ellipsoids256")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (collectives and sharding are not part of it); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2002_06206_amd import ibm
+    torch.cuda.set_device(0)
+    case = workload(args.workload)
+    N = case.n[0] * case.n[1] * case.n[2]
+
+    t0 = time.perf_counter()
+    s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
+    blocked, theta = s.tag(case.tri)
+    s.build(blocked, None, case.deadend)
+    del theta
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    st = s.new_state(case.u_in)
+
+    # time step: CFL 0.3 on the largest face velocity of the previous step, capped at
+    # the configured dt (= CFL 0.3 on the inflow velocity); variable-step AB2
+    ctl = {"dt_prev": 0.0, "umax": max(abs(v) for v in case.u_in)}
+
+    def params(step):
+        dt = min(case.dt, 0.3 * case.dx / max(ctl["umax"], 1e-30))
+        p = ibm.step_params(dt, case.nu, csm=case.csm, step=step, dt_prev=ctl["dt_prev"], tol=args.tol,
+                            max_iter=20000, check_every=16)
+        ctl["dt_prev"] = dt
+        return p
+
+    step = 0
+    for _ in range(args.warmup):
+        rc, stats = s.step(st, params(step))
+        ctl["umax"] = stats["umax"]
+        step += 1
+    ibm.ibm_timing_enable(s.ctx, True)
+    ibm.ibm_timing_read(s.ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    worst_res = 0.0
+    worst_div = 0.0
+    forces = None
+    for _ in range(args.steps):
+        rc, stats = s.step(st, params(step))
+        ctl["umax"] = stats["umax"]
+        forces = s.forces(st, case.nu)
+        step += 1
+        iters.append(stats["iters_inner"])
+        worst_res = max(worst_res, stats["rel_residual"])
+        worst_div = max(worst_div, stats["div_linf"])
+        if rc != 0:
+            raise SystemExit("step %d did not converge (rc=%d)" % (step, rc))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = ibm.ibm_timing_read(s.ctx, reset=True)
+    ibm.ibm_timing_enable(s.ctx, False)
+    elapsed = t1 - t0
+    value = N * args.steps / elapsed
+
+    # dominant kernel: the sweep with the largest accumulated time
+    k_dom = max(range(3), key=lambda k: tim["ms"][k])
+    name = SWEEP_NAMES[k_dom]
+    real = tim["real_iters"]
+    avg_s = tim["ms"][k_dom] / 1e3 / max(real, 1)
+    achieved = SWEEP_BYTES[name] * N / avg_s / 1e9
+    traffic = committed_traffic(name, args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_SYMBOL[name],
+                "algorithmic_bytes_per_launch": SWEEP_BYTES[name] * N,
+                "avg_launch_us": round(avg_s * 1e6, 2), "launches": tim["launches"][k_dom],
+                "launches_with_work": real,
+                "sweeps_ms": {SWEEP_NAMES[k]: round(tim["ms"][k], 2) for k in range(3)}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(case, sum(iters) / len(iters))
+
+    Fp, Fv = forces
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "cells": list(case.n), "triangles": int(len(case.tri)),
+                   "cuts": s.ncut, "solver": "pcg_jacobi_fp64", "tol": args.tol, "re_nu": case.nu,
+                   "dt_max": case.dt, "cfl": 0.3, "dt_last": ctl["dt_prev"], "csm": case.csm},
+        "plain_fp64_value": value,
+        "pcg_iters_per_step": sum(iters) / len(iters),
+        "max_rel_residual": worst_res,
+        "max_div_linf": worst_div,
+        "setup_s": round(t_setup, 3),
+        "force_last_step": [a + b for a, b in zip(Fp, Fv)],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

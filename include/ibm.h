@@ -82,9 +82,12 @@ typedef struct {
 } ibm_solver_opts;
 
 /* One time step: AB2 momentum predictor (forward Euler when step == 0), coherent
- * structure model (Sec. 2.3) when csm_on, body force, Poisson, projection. */
+ * structure model (Sec. 2.3) when csm_on, body force, Poisson, projection.
+ * Variable-step AB2: u* = u + dt [(1 + r/2) H^n - (r/2) H^{n-1}], r = dt/dt_prev
+ * (dt_prev <= 0 means dt_prev = dt, the constant-step 3/2, -1/2 weights). */
 typedef struct {
     double dt;
+    double dt_prev;         /* previous step's dt (<= 0: same as dt)                 */
     double nu;              /* molecular kinematic viscosity (1/Re in flow units)   */
     double c1;              /* CSM constant C1, 1/20 in the paper                   */
     int32_t csm_on;
@@ -101,6 +104,7 @@ typedef struct {
     double rel_residual;     /* FP64 ||b - L p|| / ||b|| after the solve             */
     double div_l2;           /* ||div U^{n+1}||_2 over all cells (ibm_step only)     */
     double div_linf;         /* max |div U^{n+1}|                                    */
+    double umax;             /* max |U| over all faces after the step (CFL control)  */
 } ibm_stats;
 
 typedef struct ibm_ctx ibm_ctx;
@@ -191,6 +195,18 @@ int ibm_get_rhs(ibm_ctx* ctx, double* out_dev, void* stream);
  * follow eqs. (cd_sphere) / (cd_flat_plate) on the caller's side. */
 int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const void* nut_dev, double nu,
                const double* wall_dev, double out_host[6], void* stream);
+
+/* Measurement support (not part of the method).  When enabled, every launch of
+ * the three conjugate-gradient sweeps (0: SpMV + <d,q>, 1: x/r update + <r,r> +
+ * <r,z>, 2: direction update) is bracketed by HIP events on its own stream; the
+ * elapsed times are collected at the end of each solve.  ibm_timing_read fills
+ * out[0..2] = accumulated milliseconds per sweep, out[3..5] = launches per sweep,
+ * out[6] = iterations that did work (launches after convergence exit at once),
+ * out[7] = cells, out[8] = cuts, out[9] = precision; reset != 0 zeroes the
+ * accumulators.  Enabling creates the events once (host objects, no device
+ * memory). */
+int ibm_timing_enable(ibm_ctx* ctx, int32_t on);
+int ibm_timing_read(ibm_ctx* ctx, double out[10], int32_t reset);
 
 #ifdef __cplusplus
 }

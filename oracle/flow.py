@@ -419,16 +419,18 @@ def dead_velocity(st: Stencil, wall) -> list:
     return out
 
 
-def predictor(st, u, U, hprev, nut, nu, dt, body, step, wall):
-    """u* = u^n + dt (3/2 H^n - 1/2 H^{n-1}) (Adams-Bashforth 2), forward Euler at step 0."""
+def predictor(st, u, U, hprev, nut, nu, dt, body, step, wall, dt_prev=0.0):
+    """u* = u^n + dt ((1 + r/2) H^n - (r/2) H^{n-1}), r = dt/dt_prev: second-order
+    Adams-Bashforth with a variable step (r = 1 gives 3/2, -1/2); forward Euler at step 0."""
     H = momentum_rhs(st, u, U, nut, nu, body, wall)
     us = []
     dv = dead_velocity(st, wall) if st.deadend.any() else None
+    r = dt / dt_prev if dt_prev > 0 else 1.0
     for m in range(3):
         if step == 0:
             v = u[m] + dt * H[m]
         else:
-            v = u[m] + dt * (1.5 * H[m] - 0.5 * hprev[m])
+            v = u[m] + dt * ((1.0 + 0.5 * r) * H[m] - (0.5 * r) * hprev[m])
         if dv is not None:
             v = np.where(st.deadend, dv[m], v)
             H[m] = np.where(st.deadend, 0.0, H[m])
@@ -586,6 +588,7 @@ class StepParams:
     body: tuple = (0.0, 0.0, 0.0)
     tol: float = 1e-10
     max_iter: int = 10000
+    dt_prev: float = 0.0
 
 
 def step(st: Stencil, u, U, p, hprev, prm: StepParams, step_index: int, wall=None):
@@ -593,7 +596,7 @@ def step(st: Stencil, u, U, p, hprev, prm: StepParams, step_index: int, wall=Non
     PCG -> gauge -> projection.  Returns (u, U, p, H, stats)."""
     g = st.grid
     nut = csm_nut(st, u, prm.c1, wall) if prm.csm else np.zeros(g.shape)
-    us, H = predictor(st, u, U, hprev, nut, prm.nu, prm.dt, prm.body, step_index, wall)
+    us, H = predictor(st, u, U, hprev, nut, prm.nu, prm.dt, prm.body, step_index, wall, prm.dt_prev)
     Us = face_predicted(st, us, wall)
     b = poisson_rhs(st, Us, prm.dt)
     pn, iters = pcg(st, b, p, prm.tol, prm.max_iter)
@@ -604,6 +607,7 @@ def step(st: Stencil, u, U, p, hprev, prm: StepParams, step_index: int, wall=Non
     div = divergence(g, Un)
     stats = dict(iters=iters, rel_residual=float(np.sqrt(np.sum(res * res)) / bn) if bn > 0 else 0.0,
                  div_l2=float(np.sqrt(np.sum(div * div))), div_linf=float(np.max(np.abs(div))),
+                 umax=float(max(np.max(np.abs(face_velocity(g, Un, d))) for d in range(6))),
                  nut=nut, b=b)
     return un, Un, pn, H, stats
 

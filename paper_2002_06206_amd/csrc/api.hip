@@ -112,6 +112,7 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
     const size_t padN = (size_t)((N + 3) / 4) * 4 + 64;
     int rc = IBM_OK;
     if (!rc) rc = dalloc(&c->mask, padN);
+    if (!rc) rc = dalloc(&c->pcode, padN);
     if (!rc) rc = dalloc(&c->flags, sizeof(uint16_t) * N);
     if (!rc) rc = dalloc(&c->label, sizeof(int32_t) * N);
     if (!rc) rc = dalloc(&c->cut_off, sizeof(uint32_t) * N);
@@ -122,7 +123,8 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
     if (!rc) rc = dalloc(&c->r, sizeof(double) * N);
     if (!rc) rc = dalloc(&c->d, sizeof(double) * N);
     if (!rc) rc = dalloc(&c->q, sizeof(double) * N);
-    if (!rc) rc = dalloc(&c->partials, sizeof(double) * 8 * MAX_BLOCKS);
+    if (!rc) rc = dalloc(&c->zbuf, sizeof(double) * N);
+    if (!rc) rc = dalloc(&c->partials, sizeof(double) * 16 * MAX_BLOCKS);
     if (!rc) rc = dalloc(&c->counter, sizeof(unsigned int) * 16);
     if (!rc) rc = dalloc(&c->solver, sizeof(Solver));
     if (!rc) rc = dalloc(&c->red, sizeof(double) * 8);
@@ -145,12 +147,23 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
     return IBM_OK;
 }
 
+static void free_events(ibm_ctx* c) {
+    for (int k = 0; k < 4; ++k) {
+        if (!c->ev[k]) continue;
+        for (int e = 0; e < 2 * c->ev_cap; ++e) (void)hipEventDestroy(c->ev[k][e]);
+        delete[] c->ev[k];
+        c->ev[k] = nullptr;
+    }
+    c->ev_cap = 0;
+}
+
 int ibm_destroy(ibm_ctx* c) {
     if (!c) return IBM_OK;
     (void)hipDeviceSynchronize();
-    void* ps[] = {c->tagmask, c->theta, c->mask, c->flags, c->label, c->cut_off, c->cut_cell, c->cut_dir,
+    free_events(c);
+    void* ps[] = {c->tagmask, c->theta, c->mask, c->pcode, c->flags, c->label, c->cut_off, c->cut_cell, c->cut_dir,
                   c->cut_theta, c->a_ib, c->a_c, c->a_o, c->cut_opp, c->enc_cells, c->comp_start,
-                  c->ustar[0], c->ustar[1], c->ustar[2], c->nut, c->b, c->bwork, c->r, c->d, c->q, c->x64,
+                  c->ustar[0], c->ustar[1], c->ustar[2], c->nut, c->b, c->bwork, c->r, c->d, c->q, c->zbuf, c->x64,
                   c->r32, c->z32, c->d32, c->q32, c->e32, c->zprev32, c->partials, c->counter, c->solver, c->red};
     for (void* p : ps) dfree(p);
     if (c->h_solver) (void)hipHostFree(c->h_solver);
@@ -236,7 +249,7 @@ int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const 
     if (rc) return rc;
     if (st) {
         *st = local;
-        rc = divergence_norms(c, U, &st->div_l2, &st->div_linf, s);
+        rc = divergence_norms(c, U, &st->div_l2, &st->div_linf, &st->umax, s);
         if (rc) return rc;
     }
     return prc;
@@ -285,6 +298,43 @@ int ibm_forces(ibm_ctx* c, void* const u[3], const double* p, const void* nut, d
     for (int a = 0; a < 3; ++a)
         if (!u[a]) return bad("ibm_forces: null velocity pointer");
     return forces_run(c, u, p, nut, nu, wall, out, (hipStream_t)stream);
+}
+
+int ibm_timing_enable(ibm_ctx* c, int32_t on) {
+    if (!c) return bad("null context");
+    if (int rc = check_device(c)) return rc;
+    if (on && c->ev_cap == 0) {
+        const int cap = 8192;
+        for (int k = 0; k < 4; ++k) {
+            c->ev[k] = new (std::nothrow) hipEvent_t[2 * cap];
+            if (!c->ev[k]) return bad("ibm_timing_enable: host allocation failed");
+            for (int e = 0; e < 2 * cap; ++e) IBM_HIP(hipEventCreate(&c->ev[k][e]));
+        }
+        c->ev_cap = cap;
+    }
+    c->timing_on = on ? 1 : 0;
+    for (int k = 0; k < 4; ++k) c->ev_used[k] = 0;
+    return IBM_OK;
+}
+
+int ibm_timing_read(ibm_ctx* c, double out[10], int32_t reset) {
+    if (!c || !out) return bad("ibm_timing_read: null argument");
+    for (int k = 0; k < 3; ++k) {
+        out[k] = c->t_ms[k];
+        out[3 + k] = (double)c->t_launches[k];
+    }
+    out[6] = (double)c->t_real_iters;
+    out[7] = (double)c->N;
+    out[8] = (double)c->ncut;
+    out[9] = (double)c->precision;
+    if (reset) {
+        for (int k = 0; k < 4; ++k) {
+            c->t_ms[k] = 0.0;
+            c->t_launches[k] = 0;
+        }
+        c->t_real_iters = 0;
+    }
+    return IBM_OK;
 }
 
 }  // extern "C"

@@ -52,6 +52,7 @@ struct ibm_ctx {
     bool tagged;
     // stencil
     uint8_t* mask;          // effective blocked bits
+    uint8_t* pcode;         // pressure operator code: bits 0-5 open faces, bits 6-7 outlet faces
     uint16_t* flags;
     int32_t* label;
     uint32_t* cut_off;      // exclusive prefix of popcount(mask)
@@ -80,6 +81,7 @@ struct ibm_ctx {
     double* r;
     double* d;
     double* q;
+    double* zbuf;           // M^-1 r of the conjugate-gradient loop
     double* x64;            // FP64 scratch (refinement / fallback)
     float* r32;             // mixed: inner FCG vectors
     float* z32;
@@ -87,7 +89,7 @@ struct ibm_ctx {
     float* q32;
     float* e32;
     float* zprev32;
-    double* partials;       // 8 * MAX_BLOCKS (up to 8 reduction slots)
+    double* partials;       // 16 * MAX_BLOCKS (16 reduction slots)
     unsigned int* counter;  // last-block tickets
     ibm::Solver* solver;    // device scalars
     ibm::Solver* h_solver;  // pinned host mirror
@@ -96,6 +98,14 @@ struct ibm_ctx {
     void* cnn;              // preconditioner network (IBM_SOLVER_FCG_CNN), not owned
     int last_iters;         // iterations of the previous solve (batch sizing)
     bool nut_valid;
+    // optional per-kernel event timing of the Krylov sweeps (ibm_timing_enable)
+    int timing_on;
+    int ev_cap;             // event pairs per timed kernel
+    int ev_used[4];
+    hipEvent_t* ev[4];      // 2 * ev_cap events per timed kernel
+    double t_ms[4];         // accumulated kernel time
+    long long t_launches[4];
+    long long t_real_iters; // iterations that did work (the rest exit at once)
 };
 
 namespace ibm {
@@ -179,32 +189,6 @@ __device__ inline void block_reduce(double (&v)[NV], double* sh /* NT*NV */) {
     __syncthreads();
 }
 
-// Writes the block partials and returns true in the last block to finish, after
-// which `tot` holds the totals summed over blocks in block order.
-template <int NV>
-__device__ inline bool grid_reduce(double (&v)[NV], double* partials, unsigned int* counter, double* sh,
-                                   double (&tot)[NV]) {
-    block_reduce<NV>(v, sh);
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
-        for (int a = 0; a < NV; ++a) partials[a * MAX_BLOCKS + blockIdx.x] = v[a];
-        __threadfence();
-        unsigned int t = atomicAdd(counter, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double acc[NV];
-    for (int a = 0; a < NV; ++a) acc[a] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += NT)
-        for (int a = 0; a < NV; ++a) acc[a] += partials[a * MAX_BLOCKS + b];
-    block_reduce<NV>(acc, sh);
-    for (int a = 0; a < NV; ++a) tot[a] = acc[a];
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
-}
-
 }  // namespace ibm
 
 // Host-side launchers implemented in the .hip files.
@@ -214,16 +198,22 @@ int stencil_run(ibm_ctx* c, const uint8_t* blocked, const double* theta, int dea
 int cut_points_run(ibm_ctx* c, double* xyz, hipStream_t s);
 int remove_means(ibm_ctx* c, double* a, hipStream_t s);
 int laplacian_run(ibm_ctx* c, const double* x, double* y, hipStream_t s);
+int march_blocks(const Geo& g);
 int init_state_run(ibm_ctx* c, void** u, double** U, double* p, void** h, const double* u0,
                    const double* wall, hipStream_t s);
 int step_predict(ibm_ctx* c, void** u, double** U, void** h, const double* wall, const ibm_step_params* prm,
                  hipStream_t s);
 int step_rhs(ibm_ctx* c, double** U, const double* wall, double dt, hipStream_t s);
 int step_project(ibm_ctx* c, void** u, double** U, const double* p, double dt, hipStream_t s);
-int divergence_norms(ibm_ctx* c, double** U, double* l2, double* linf, hipStream_t s);
+int divergence_norms(ibm_ctx* c, double** U, double* l2, double* linf, double* umax, hipStream_t s);
 int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st,
                 hipStream_t s);
 int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hipStream_t s);
+// timing helpers (poisson.hip)
+enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3 };
+void timing_begin(ibm_ctx* c, int k, hipStream_t s);
+void timing_end(ibm_ctx* c, int k, hipStream_t s);
+void timing_collect(ibm_ctx* c);
 int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
                double* out, hipStream_t s);
 }  // namespace ibm

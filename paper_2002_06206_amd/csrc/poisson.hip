@@ -1,205 +1,669 @@
 // Pressure Poisson solve (eq. poisson) on the immersed-boundary stencil.
 //
 // A = -L, L p = (1/dx^2)[sum over open faces (p_nb - p_c) - 2 p_c per outlet face],
-// is symmetric positive semi-definite (the face blocking is symmetric), so the plain
-// solver is Jacobi-preconditioned conjugate gradients in FP64, warm started.
-// Each iteration is three fused sweeps (SpMV + <d,q>; x/r update + <r,r> + <r,z>;
-// direction update); the scalars alpha and beta are formed on the device by the last
-// block of each reduction, so the host only enqueues work.  Convergence is decided
-// on the device after every update and turns the remaining enqueued sweeps into
-// no-ops; the host polls between batches of iterations.
+// is symmetric positive semi-definite (blocking is per face, seen from both sides),
+// so the plain solver is Jacobi-preconditioned conjugate gradients in FP64, warm
+// started.
+//
+// MI355X design:
+//  * one byte per cell ("pressure code": bits 0-5 open faces incl. periodic wraps,
+//    bits 6-7 number of outlet faces) carries the whole operator: the diagonal is
+//    popcount(open) + 2 * outlets, every open face couples with weight 1;
+//  * the SpMV marches each 64x4 column tile through a slab of z-planes keeping the
+//    planes z-1, z, z+1 in registers; the slabs are laid out so each XCD owns a
+//    contiguous range of z and its L2 serves the x/y neighbours;
+//  * no grid-wide fences: a reduction kernel only writes one partial per block, and
+//    every block of the consumer kernel sums those partials itself in a fixed order
+//    (identical in every block, so the scalars alpha, beta and the convergence test
+//    agree everywhere and the result is deterministic);
+//  * the two <r,*> reductions ping-pong between two partial sets by iteration
+//    parity so that rz of the previous iteration is still available.
+// Convergence is decided on the device after every update; later sweeps of the
+// batch exit at once.  The host polls between batches.
 
 #include "common.h"
 
 namespace ibm {
 namespace {
 
-// diagonal of A times dx^2: open faces + 2 per outlet face
-__device__ inline double diag_count(const Geo& g, int i, int j, int k, uint8_t msk) {
-    int cnt = 0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        int ax = d >> 1;
-        int n = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
-        int co = ax == 0 ? i : (ax == 1 ? j : k);
-        bool bnd = (d & 1) ? (co == n - 1) : (co == 0);
-        if (bnd && g.bc[d] != IBM_BC_PERIODIC) {
-            if (g.bc[d] == IBM_BC_OUTFLOW) cnt += 2;
-        } else if (!((msk >> d) & 1)) {
-            cnt += 1;
-        }
-    }
-    return (double)cnt;
+__device__ inline double jacobi_count(uint8_t pc) {
+    return (double)(__builtin_popcount((unsigned)(pc & 0x3F)) + 2 * (pc >> 6));
 }
 
-// (L x)_c
-__device__ inline double lap_at(const Geo& g, const uint8_t msk, const double* x, int i, int j, int k, long long c) {
-    double xc = x[c];
-    double acc = 0.0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        bool bnd;
-        long long n = nb_index(g, i, j, k, d, bnd);
-        if (bnd) {
-            if (g.bc[d] == IBM_BC_OUTFLOW) acc += -2.0 * xc;
-        } else if (!((msk >> d) & 1)) {
-            acc += x[n] - xc;
-        }
-    }
-    return acc / (g.dx * g.dx);
+// Work item = (column tile, z slab).  Items are ordered slab-major; the XCD chunk
+// remap hands every XCD a contiguous run of slabs.
+struct Slabs {
+    int nzc;         // slabs
+    long long items; // tiles_xy * nzc
+};
+
+__host__ __device__ inline int slab_count(int nz) {
+    int want = (nz + 31) / 32;               // about 32 planes per slab
+    want = ((want + 7) / 8) * 8;             // multiple of the XCD count
+    if (want > nz) want = nz;
+    return want < 1 ? 1 : want;
 }
 
-__global__ void __launch_bounds__(NT) k_pcg_init(Geo g, const uint8_t* mask, const double* b, const double* x,
-                                                 double* r, double* d, double* partials, unsigned int* counter,
-                                                 Solver* sv, double tol) {
+// (L x)_c from the pressure code and the three planes of the column
+__device__ inline double lap_code(uint8_t pc, double xc, double xw, double xe, double xs, double xn, double xb,
+                                  double xt, double idx2) {
+    double acc = -jacobi_count(pc) * xc;
+    if (pc & 1) acc += xw;
+    if (pc & 2) acc += xe;
+    if (pc & 4) acc += xs;
+    if (pc & 8) acc += xn;
+    if (pc & 16) acc += xb;
+    if (pc & 32) acc += xt;
+    return acc * idx2;
+}
+
+// Generic z-marching sweep over (tile, slab) items.  For each cell it hands the
+// functor the code byte and the 7 values of x needed by L.
+template <class F>
+__device__ inline void march(const Geo& g, const uint8_t* __restrict__ pcode, const double* __restrict__ x, F&& f) {
+    const int nzc = slab_count(g.nz);
+    const long long tiles = (long long)g.ntx * g.nty;
+    const long long items = tiles * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
+    for (long long w = w0; w < w1; ++w) {
+        const int zc = (int)(w / tiles);
+        const long long t = w % tiles;
+        const int i = (int)(t % g.ntx) * TX + (threadIdx.x % TX);
+        const int j = (int)(t / g.ntx) * TY + (threadIdx.x / TX);
+        const int z0 = (int)((long long)g.nz * zc / nzc), z1 = (int)((long long)g.nz * (zc + 1) / nzc);
+        if (i >= g.nx || j >= g.ny) continue;
+        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i == g.nx - 1 ? 0 : i + 1;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+        const long long col = (long long)i + (long long)g.nx * j;
+        const long long ow = (long long)iw + (long long)g.nx * j - col;
+        const long long oe = (long long)ie + (long long)g.nx * j - col;
+        const long long os = (long long)i + (long long)g.nx * js - col;
+        const long long on = (long long)i + (long long)g.nx * jn - col;
+        int zb = z0 == 0 ? g.nz - 1 : z0 - 1;
+        double xb = x[col + plane * zb];
+        double xc = x[col + plane * z0];
+#pragma unroll 4
+        for (int k = z0; k < z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = col + plane * k;
+            const double xt = x[col + plane * zt];
+            f(c, pcode[c], xc, x[c + ow], x[c + oe], x[c + os], x[c + on], xb, xt);
+            xb = xc;
+            xc = xt;
+        }
+    }
+}
+
+// --------------------------------------------------------------- kernels
+//
+// Conjugate gradients fused into two stencil passes per iteration i:
+//   pass A_i: x_i = x_{i-1} + alpha_{i-1} d_{i-1};  d_i = M^-1 r_i + beta_{i-1} d_{i-1}
+//             (formed on the fly for the cell and its six neighbours);
+//             q = A d_i (not stored);  partial <d_i, q>;  writes x, d_i
+//   pass B_i: q = A d_i again from the cached halo;  r_{i+1} = r_i - alpha_i q;
+//             z_{i+1} = M^-1 r_{i+1}; partials <r_{i+1}, r_{i+1}>, <r_{i+1}, z_{i+1}>;
+//             writes r, z
+// with alpha_i = rz_i / <d_i, A d_i> and beta_{i-1} = rz_i / rz_{i-1}.  The test
+// ||r_i|| <= tol ||b|| is made at the start of A_i, which then only applies the last
+// x update.  d ping-pongs between two buffers (neighbours read d_{i-1} while d_i is
+// written); partial slots ping-pong by iteration parity.
+// Algorithmic traffic per cell and iteration: A reads z, d, x, code and writes x, d
+// (41 B); B reads d, r, code and writes r, z (33 B).  Storing z = M^-1 r lets pass A
+// form each neighbour's new direction from two plain loads.
+
+// slots: <r,r> and <r,z> of r_i live in RR[i & 1], RZ[i & 1]; <d_i, A d_i> in DQ[i & 1]
+__device__ inline int slot_rr(int i) { return (i & 1) ? 1 : 0; }
+__device__ inline int slot_rz(int i) { return (i & 1) ? 3 : 2; }
+__device__ inline int slot_dq(int i) { return (i & 1) ? 5 : 4; }
+constexpr int SLOT_FF = 6;
+constexpr int SLOT_RES0 = 8, SLOT_RES1 = 9;
+
+// dx^2 / (Jacobi count) for every code, 0 for cells without open faces
+__device__ inline void fill_inv(double* inv, double dx2) {
+    if (threadIdx.x < 16) inv[threadIdx.x] = threadIdx.x ? dx2 / (double)threadIdx.x : 0.0;
+    __syncthreads();
+}
+
+__device__ inline int jcount(uint8_t pc) { return __builtin_popcount((unsigned)(pc & 0x3F)) + 2 * (pc >> 6); }
+
+// sum of one partial slot over nparts blocks, in block order, by the whole block
+__device__ inline double sum_slot(const double* partials, int slot, int nparts, double* sh) {
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nparts; b += NT) v[0] += partials[slot * MAX_BLOCKS + b];
+    block_reduce<1>(v, sh);
+    return v[0];
+}
+
+// r_0 = -b + L x_0; partials <b,b>, <r_0,r_0>, <r_0, M^-1 r_0>
+__global__ void __launch_bounds__(NT) k_pcg_init(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ b, const double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ zz, double* __restrict__ partials) {
     __shared__ double sh[3 * NT];
-    long long t0, t1;
-    tile_range(g, t0, t1);
+    __shared__ double inv[16];
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    fill_inv(inv, g.dx * g.dx);
     double v[3] = {0.0, 0.0, 0.0};
-    const double dx2 = g.dx * g.dx;
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        uint8_t msk = mask[c];
-        double rc = -b[c] + lap_at(g, msk, x, i, j, k, c);
-        double cnt = diag_count(g, i, j, k, msk);
-        double z = cnt > 0.0 ? rc * dx2 / cnt : 0.0;
+    march(g, pcode, x, [&](long long c, uint8_t pc, double xc, double xw, double xe, double xs, double xn,
+                           double xb, double xt) {
+        double bc = b[c];
+        double rc = -bc + lap_code(pc, xc, xw, xe, xs, xn, xb, xt, idx2);
+        double z = inv[jcount(pc)] * rc;
         r[c] = rc;
-        d[c] = z;
-        v[0] += b[c] * b[c];
+        zz[c] = z;
+        v[0] += bc * bc;
         v[1] += rc * rc;
         v[2] += rc * z;
+    });
+    block_reduce<3>(v, sh);
+    if (threadIdx.x == 0) {
+        partials[SLOT_FF * MAX_BLOCKS + blockIdx.x] = v[0];
+        partials[0 * MAX_BLOCKS + blockIdx.x] = v[1];   // RR[0]
+        partials[2 * MAX_BLOCKS + blockIdx.x] = v[2];   // RZ[0]
     }
-    double tot[3];
-    if (grid_reduce<3>(v, partials, counter, sh, tot) && threadIdx.x == 0) {
-        sv->fnorm2 = tot[0];
-        sv->tol2 = tol * tol * tot[0];
-        sv->rr = tot[1];
-        sv->rz = tot[2];
+}
+
+// one block: totals of the init partials -> solver state
+__global__ void __launch_bounds__(NT) k_pcg_start(const double* partials, int nparts, Solver* sv, double tol) {
+    __shared__ double sh[3 * NT];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += NT) {
+        v[0] += partials[SLOT_FF * MAX_BLOCKS + b];
+        v[1] += partials[0 * MAX_BLOCKS + b];
+        v[2] += partials[2 * MAX_BLOCKS + b];
+    }
+    block_reduce<3>(v, sh);
+    if (threadIdx.x == 0) {
+        sv->fnorm2 = v[0];
+        sv->tol2 = tol * tol * v[0];
+        sv->rr = v[1];
+        sv->rz = v[2];
         sv->iters = 0;
         sv->nan_seen = 0;
-        if (!(tot[1] == tot[1]) || !(tot[0] == tot[0])) {
+        if (!(v[1] == v[1]) || !(v[0] == v[0])) {
             sv->nan_seen = 1;
             sv->converged = 3;
-        } else if (tot[0] == 0.0) {
+        } else if (v[0] == 0.0) {
             sv->converged = 2;
         } else {
-            sv->converged = tot[1] <= sv->tol2 ? 1 : 0;
+            sv->converged = v[1] <= sv->tol2 ? 1 : 0;
         }
     }
 }
 
-__global__ void k_zero_if_trivial(Geo g, double* x, const Solver* sv) {
+__global__ void k_zero_if_trivial(long long n, double* x, const Solver* sv) {
     if (sv->converged != 2) return;
-    long long n = (long long)g.nx * g.ny * g.nz;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         x[i] = 0.0;
 }
 
-__global__ void __launch_bounds__(NT) k_pcg_spmv(Geo g, const uint8_t* mask, const double* d, double* q,
-                                                 double* partials, unsigned int* counter, Solver* sv) {
+// Pass A of iteration it (see above); z = M^-1 r_it is stored by the previous pass.
+// final_only: apply the last x update only (used when the iteration cap is reached).
+__global__ void __launch_bounds__(NT) k_pcg_a(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ zz, const double* __restrict__ dold,
+                                              double* __restrict__ dnew, double* __restrict__ x, double* __restrict__ partials, int nparts, int it,
+                                              int final_only, Solver* sv) {
     if (sv->converged) return;
     __shared__ double sh[NT];
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    double v[1] = {0.0};
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        double qc = -lap_at(g, mask[c], d, i, j, k, c);
-        q[c] = qc;
-        v[0] += d[c] * qc;
-    }
-    double tot[1];
-    if (grid_reduce<1>(v, partials, counter, sh, tot) && threadIdx.x == 0) {
-        sv->dq = tot[0];
-        sv->alpha = sv->rz / tot[0];
-    }
-}
-
-__global__ void __launch_bounds__(NT) k_pcg_update(Geo g, const uint8_t* mask, double* x, const double* d,
-                                                   const double* q, double* r, double* partials,
-                                                   unsigned int* counter, Solver* sv) {
-    if (sv->converged) return;
-    __shared__ double sh[2 * NT];
-    const double alpha = sv->alpha;
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    double v[2] = {0.0, 0.0};
-    const double dx2 = g.dx * g.dx;
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        x[c] = x[c] + alpha * d[c];
-        double rc = r[c] - alpha * q[c];
-        r[c] = rc;
-        double cnt = diag_count(g, i, j, k, mask[c]);
-        double z = cnt > 0.0 ? rc * dx2 / cnt : 0.0;
-        v[0] += rc * rc;
-        v[1] += rc * z;
-    }
-    double tot[2];
-    if (grid_reduce<2>(v, partials, counter, sh, tot) && threadIdx.x == 0) {
-        sv->iters += 1;
-        sv->rr = tot[0];
-        if (!(tot[0] == tot[0])) {
-            sv->nan_seen = 1;
-            sv->converged = 3;
-        } else if (tot[0] <= sv->tol2) {
-            sv->converged = 1;
-        } else {
-            sv->beta = tot[1] / sv->rz;
-            sv->rz = tot[1];
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    double alpha = 0.0, beta = 0.0;
+    bool stop = final_only != 0;
+    if (it > 0) {
+        const double rr = sum_slot(partials, slot_rr(it), nparts, sh);
+        const double rz = sum_slot(partials, slot_rz(it), nparts, sh);
+        const double rzp = sum_slot(partials, slot_rz(it - 1), nparts, sh);
+        const double dq = sum_slot(partials, slot_dq(it - 1), nparts, sh);
+        alpha = rzp / dq;
+        beta = rz / rzp;
+        if (!(rr == rr)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sv->nan_seen = 1;
+                sv->converged = 3;
+                sv->iters = it;
+            }
+            return;
+        }
+        if (rr <= sv->tol2) stop = true;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sv->rr = rr;
+            sv->iters = it;
+            if (stop && !final_only) sv->converged = 1;
         }
     }
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    if (stop) {
+        // last x update only: x_it = x_{it-1} + alpha_{it-1} d_{it-1}
+        for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+             c += (long long)gridDim.x * blockDim.x)
+            x[c] = x[c] + alpha * dold[c];
+        return;
+    }
+    const bool first = it == 0;
+    double v[1] = {0.0};
+    const int nzc = slab_count(g.nz);
+    const long long tiles = (long long)g.ntx * g.nty;
+    const long long items = tiles * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
+    for (long long w = w0; w < w1; ++w) {
+        const int zc = (int)(w / tiles);
+        const long long t = w % tiles;
+        const int i = (int)(t % g.ntx) * TX + (threadIdx.x % TX);
+        const int j = (int)(t / g.ntx) * TY + (threadIdx.x / TX);
+        const int z0 = (int)((long long)g.nz * zc / nzc), z1 = (int)((long long)g.nz * (zc + 1) / nzc);
+        if (i >= g.nx || j >= g.ny) continue;
+        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i == g.nx - 1 ? 0 : i + 1;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+        const long long col = (long long)i + (long long)g.nx * j;
+        const long long ow = (long long)iw + (long long)g.nx * j - col;
+        const long long oe = (long long)ie + (long long)g.nx * j - col;
+        const long long os = (long long)i + (long long)g.nx * js - col;
+        const long long on = (long long)i + (long long)g.nx * jn - col;
+        const int zb = z0 == 0 ? g.nz - 1 : z0 - 1;
+        if (first) {
+            // d_0 = z_0
+            double db = zz[col + plane * zb];
+            double dc = zz[col + plane * z0];
+#pragma unroll 4
+            for (int k = z0; k < z1; ++k) {
+                const int zt = k == g.nz - 1 ? 0 : k + 1;
+                const long long c = col + plane * k;
+                const double dt = zz[col + plane * zt];
+                const double q = -lap_code(pcode[c], dc, zz[c + ow], zz[c + oe], zz[c + os], zz[c + on], db, dt, idx2);
+                dnew[c] = dc;
+                v[0] += dc * q;
+                db = dc;
+                dc = dt;
+            }
+            continue;
+        }
+        const long long cb0 = col + plane * zb, cc0 = col + plane * z0;
+        double db = zz[cb0] + beta * dold[cb0];
+        double oc = dold[cc0];
+        double dc = zz[cc0] + beta * oc;
+#pragma unroll 2
+        for (int k = z0; k < z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = col + plane * k;
+            const long long ct = col + plane * zt;
+            const double ot = dold[ct];
+            const double dt = zz[ct] + beta * ot;
+            const double dw = zz[c + ow] + beta * dold[c + ow];
+            const double de = zz[c + oe] + beta * dold[c + oe];
+            const double ds = zz[c + os] + beta * dold[c + os];
+            const double dn = zz[c + on] + beta * dold[c + on];
+            const double q = -lap_code(pcode[c], dc, dw, de, ds, dn, db, dt, idx2);
+            x[c] = x[c] + alpha * oc;
+            dnew[c] = dc;
+            v[0] += dc * q;
+            db = dc;
+            dc = dt;
+            oc = ot;
+        }
+    }
+    block_reduce<1>(v, sh);
+    if (threadIdx.x == 0) partials[slot_dq(it) * MAX_BLOCKS + blockIdx.x] = v[0];
 }
 
-__global__ void __launch_bounds__(NT) k_pcg_dir(Geo g, const uint8_t* mask, const double* r, double* d,
-                                                const Solver* sv) {
+// Pass B of iteration it: r_{it+1} = r_it - alpha_it A d_it; partials for r_{it+1}
+__global__ void __launch_bounds__(NT) k_pcg_b(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ d, double* __restrict__ r,
+                                              double* __restrict__ zz, double* __restrict__ partials, int nparts, int it, const Solver* sv) {
     if (sv->converged) return;
-    const double beta = sv->beta;
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    const double dx2 = g.dx * g.dx;
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        double cnt = diag_count(g, i, j, k, mask[c]);
-        double z = cnt > 0.0 ? r[c] * dx2 / cnt : 0.0;
-        d[c] = z + beta * d[c];
+    __shared__ double sh[2 * NT];
+    __shared__ double inv[16];
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    fill_inv(inv, g.dx * g.dx);
+    const double rz = sum_slot(partials, slot_rz(it), nparts, sh);
+    const double dq = sum_slot(partials, slot_dq(it), nparts, sh);
+    const double alpha = rz / dq;
+    double v[2] = {0.0, 0.0};
+    march(g, pcode, d, [&](long long c, uint8_t pc, double xc, double xw, double xe, double xs, double xn,
+                           double xb, double xt) {
+        const double q = -lap_code(pc, xc, xw, xe, xs, xn, xb, xt, idx2);
+        const double rn = r[c] - alpha * q;
+        const double z = inv[jcount(pc)] * rn;
+        r[c] = rn;
+        zz[c] = z;
+        v[0] += rn * rn;
+        v[1] += rn * z;
+    });
+    block_reduce<2>(v, sh);
+    if (threadIdx.x == 0) {
+        partials[slot_rr(it + 1) * MAX_BLOCKS + blockIdx.x] = v[0];
+        partials[slot_rz(it + 1) * MAX_BLOCKS + blockIdx.x] = v[1];
     }
 }
 
-// ||b - L x||^2 and ||b||^2
-__global__ void __launch_bounds__(NT) k_resid(Geo g, const uint8_t* mask, const double* b, const double* x,
-                                              double* partials, unsigned int* counter, double* out) {
+
+// ----------------------------------------------------- vector (double2) passes
+//
+// On grids with an even number of cells in x every thread owns an aligned pair of
+// cells; a block owns a 128x4 column tile.  Pass A shares the new direction of the
+// current plane through a double-buffered LDS tile with a one-cell halo (one
+// barrier per plane).  Every result is written with non-temporal stores (measured
+// faster than regular stores for all four vectors on the full-size solve).
+
+constexpr int VTX = 128;               // cells of a tile row (64 lanes x 2)
+constexpr int VW = VTX + 2;            // LDS row with halo
+
+__host__ __device__ inline int vslab_count(int nz) {
+    int want = (nz + 15) / 16;               // about 16 planes per slab
+    want = ((want + 7) / 8) * 8;             // multiple of the XCD count
+    if (want > nz) want = nz;
+    return want < 1 ? 1 : want;
+}
+
+struct VItem {
+    int i, j, z0, z1;     // first cell of this thread's pair, row, slab
+    int i0, j0;           // tile origin
+    bool valid;
+};
+
+__device__ inline VItem vitem(const Geo& g, long long w, int ntx2, int nzc) {
+    const long long tiles = (long long)ntx2 * g.nty;
+    VItem v;
+    const int zc = (int)(w / tiles);
+    const long long t = w % tiles;
+    v.i0 = (int)(t % ntx2) * VTX;
+    v.j0 = (int)(t / ntx2) * TY;
+    v.i = v.i0 + 2 * (threadIdx.x % 64);
+    v.j = v.j0 + (int)(threadIdx.x / 64);
+    v.z0 = (int)((long long)g.nz * zc / nzc);
+    v.z1 = (int)((long long)g.nz * (zc + 1) / nzc);
+    v.valid = v.i < g.nx && v.j < g.ny;
+    return v;
+}
+
+__device__ inline double2 ld2(const double* __restrict__ p, long long c) {
+    return *reinterpret_cast<const double2*>(p + c);
+}
+
+__device__ inline void st2nt(double* __restrict__ p, long long c, double a, double b) {
+    __builtin_nontemporal_store(a, p + c);
+    __builtin_nontemporal_store(b, p + c + 1);
+}
+
+// Pass A, vector form (see the scalar k_pcg_a for the mathematics).
+template <bool FIRST>
+__global__ void __launch_bounds__(NT) k_pcg_a_v(Geo g, const uint8_t* __restrict__ pcode,
+                                                const double* __restrict__ zz, const double* __restrict__ dold,
+                                                double* __restrict__ dnew, double* __restrict__ x,
+                                                double* __restrict__ partials, int nparts, int it, Solver* sv) {
+    if (sv->converged) return;
+    __shared__ double sh[NT];
+    __shared__ double pln[2][(TY + 2) * VW];
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    double alpha = 0.0, beta = 0.0;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    if (!FIRST) {
+        const double rr = sum_slot(partials, slot_rr(it), nparts, sh);
+        const double rz = sum_slot(partials, slot_rz(it), nparts, sh);
+        const double rzp = sum_slot(partials, slot_rz(it - 1), nparts, sh);
+        const double dq = sum_slot(partials, slot_dq(it - 1), nparts, sh);
+        alpha = rzp / dq;
+        beta = rz / rzp;
+        if (!(rr == rr)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sv->nan_seen = 1;
+                sv->converged = 3;
+                sv->iters = it;
+            }
+            return;
+        }
+        const bool stop = rr <= sv->tol2;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sv->rr = rr;
+            sv->iters = it;
+            if (stop) sv->converged = 1;
+        }
+        if (stop) {
+            for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+                 c += (long long)gridDim.x * blockDim.x)
+                x[c] = x[c] + alpha * dold[c];
+            return;
+        }
+    }
+    auto dn1 = [&](long long c) -> double { return FIRST ? zz[c] : zz[c] + beta * dold[c]; };
+    auto dn2 = [&](long long c) -> double2 {
+        double2 a = ld2(zz, c);
+        if (FIRST) return a;
+        double2 o = ld2(dold, c);
+        return make_double2(a.x + beta * o.x, a.y + beta * o.y);
+    };
+    const int ntx2 = (g.nx + VTX - 1) / VTX;
+    const int nzc = vslab_count(g.nz);
+    const long long items = (long long)ntx2 * g.nty * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
+    const int lane = threadIdx.x % 64, lj = threadIdx.x / 64;
+    const int li = 2 * lane;
+    double v = 0.0;
+    int buf = 0;
+    for (long long w = w0; w < w1; ++w) {
+        const VItem it_ = vitem(g, w, ntx2, nzc);
+        const int i = it_.i, j = it_.j;
+        // last valid pair and row of the tile own the east / north halo
+        const int lane_max = min(63, (g.nx - it_.i0) / 2 - 1);
+        const int row_max = min(TY - 1, g.ny - it_.j0 - 1);
+        const int iw = it_.i0 == 0 ? g.nx - 1 : it_.i0 - 1;
+        const int ie = i + 2 >= g.nx ? 0 : i + 2;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j >= g.ny - 1 ? 0 : j + 1;
+        const long long col = it_.valid ? (long long)i + (long long)g.nx * j : 0;
+        const int zb = it_.z0 == 0 ? g.nz - 1 : it_.z0 - 1;
+        double2 db = make_double2(0.0, 0.0), dc = db, oc = db;
+        if (it_.valid) {
+            db = dn2(col + plane * zb);
+            const double2 zc2 = ld2(zz, col + plane * it_.z0);
+            if (!FIRST) oc = ld2(dold, col + plane * it_.z0);
+            dc = FIRST ? zc2 : make_double2(zc2.x + beta * oc.x, zc2.y + beta * oc.y);
+        }
+        for (int k = it_.z0; k < it_.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            double* P = pln[buf];
+            double2 dt = make_double2(0.0, 0.0), ot = dt;
+            if (it_.valid) {
+                const long long ct = col + plane * zt;
+                const double2 zt2 = ld2(zz, ct);
+                if (!FIRST) ot = ld2(dold, ct);
+                dt = FIRST ? zt2 : make_double2(zt2.x + beta * ot.x, zt2.y + beta * ot.y);
+                P[(lj + 1) * VW + li + 1] = dc.x;
+                P[(lj + 1) * VW + li + 2] = dc.y;
+                const long long pk = plane * k;
+                if (lane == 0) P[(lj + 1) * VW] = dn1((long long)iw + (long long)g.nx * j + pk);
+                if (lane == lane_max) P[(lj + 1) * VW + li + 3] = dn1((long long)ie + (long long)g.nx * j + pk);
+                if (lj == 0) {
+                    const double2 s2 = dn2((long long)i + (long long)g.nx * js + pk);
+                    P[li + 1] = s2.x;
+                    P[li + 2] = s2.y;
+                }
+                if (lj == row_max) {
+                    const double2 n2 = dn2((long long)i + (long long)g.nx * jn + pk);
+                    P[(lj + 2) * VW + li + 1] = n2.x;
+                    P[(lj + 2) * VW + li + 2] = n2.y;
+                }
+            }
+            __syncthreads();
+            if (it_.valid) {
+                const long long c = col + plane * k;
+                const double w_ = P[(lj + 1) * VW + li], e_ = P[(lj + 1) * VW + li + 3];
+                const double s0 = P[lj * VW + li + 1], s1 = P[lj * VW + li + 2];
+                const double n0 = P[(lj + 2) * VW + li + 1], n1 = P[(lj + 2) * VW + li + 2];
+                const uint8_t pc0 = pcode[c], pc1 = pcode[c + 1];
+                const double q0 = -lap_code(pc0, dc.x, w_, dc.y, s0, n0, db.x, dt.x, idx2);
+                const double q1 = -lap_code(pc1, dc.y, dc.x, e_, s1, n1, db.y, dt.y, idx2);
+                if (!FIRST) {
+                    const double2 xx = ld2(x, c);
+                    st2nt(x, c, xx.x + alpha * oc.x, xx.y + alpha * oc.y);
+                }
+                st2nt(dnew, c, dc.x, dc.y);
+                v += dc.x * q0 + dc.y * q1;
+            }
+            db = dc;
+            dc = dt;
+            oc = ot;
+            buf ^= 1;
+        }
+    }
+    double vv[1] = {v};
+    block_reduce<1>(vv, sh);
+    if (threadIdx.x == 0) partials[slot_dq(it) * MAX_BLOCKS + blockIdx.x] = vv[0];
+}
+
+// Pass B, vector form: r_{it+1} = r_it - alpha A d_it, z = M^-1 r; partials.
+__global__ void __launch_bounds__(NT) k_pcg_b_v(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ d,
+                                                double* __restrict__ r, double* __restrict__ zz,
+                                                double* __restrict__ partials, int nparts, int it, const Solver* sv) {
+    if (sv->converged) return;
     __shared__ double sh[2 * NT];
-    long long t0, t1;
-    tile_range(g, t0, t1);
+    __shared__ double inv[16];
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    fill_inv(inv, g.dx * g.dx);
+    const double rz = sum_slot(partials, slot_rz(it), nparts, sh);
+    const double dq = sum_slot(partials, slot_dq(it), nparts, sh);
+    const double alpha = rz / dq;
+    const int ntx2 = (g.nx + VTX - 1) / VTX;
+    const int nzc = vslab_count(g.nz);
+    const long long items = (long long)ntx2 * g.nty * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
     double v[2] = {0.0, 0.0};
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        double res = b[c] - lap_at(g, mask[c], x, i, j, k, c);
+    for (long long w = w0; w < w1; ++w) {
+        const VItem it_ = vitem(g, w, ntx2, nzc);
+        if (!it_.valid) continue;
+        const int i = it_.i, j = it_.j;
+        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i + 2 >= g.nx ? 0 : i + 2;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+        const long long col = (long long)i + (long long)g.nx * j;
+        const long long ow = (long long)iw + (long long)g.nx * j - col;
+        const long long oe = (long long)ie + (long long)g.nx * j - col;
+        const long long os = (long long)i + (long long)g.nx * js - col;
+        const long long on = (long long)i + (long long)g.nx * jn - col;
+        const int zb = it_.z0 == 0 ? g.nz - 1 : it_.z0 - 1;
+        double2 xb = ld2(d, col + plane * zb);
+        double2 xc = ld2(d, col + plane * it_.z0);
+        for (int k = it_.z0; k < it_.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = col + plane * k;
+            const double2 xt = ld2(d, col + plane * zt);
+            const double2 xs = ld2(d, c + os), xn = ld2(d, c + on);
+            const double xw = d[c + ow], xe = d[c + oe];
+            const uint8_t pc0 = pcode[c], pc1 = pcode[c + 1];
+            const double q0 = -lap_code(pc0, xc.x, xw, xc.y, xs.x, xn.x, xb.x, xt.x, idx2);
+            const double q1 = -lap_code(pc1, xc.y, xc.x, xe, xs.y, xn.y, xb.y, xt.y, idx2);
+            const double2 rr = ld2(r, c);
+            const double rn0 = rr.x - alpha * q0, rn1 = rr.y - alpha * q1;
+            const double z0 = inv[jcount(pc0)] * rn0, z1 = inv[jcount(pc1)] * rn1;
+            st2nt(r, c, rn0, rn1);
+            st2nt(zz, c, z0, z1);
+            v[0] += rn0 * rn0 + rn1 * rn1;
+            v[1] += rn0 * z0 + rn1 * z1;
+            xb = xc;
+            xc = xt;
+        }
+    }
+    block_reduce<2>(v, sh);
+    if (threadIdx.x == 0) {
+        partials[slot_rr(it + 1) * MAX_BLOCKS + blockIdx.x] = v[0];
+        partials[slot_rz(it + 1) * MAX_BLOCKS + blockIdx.x] = v[1];
+    }
+}
+
+// partials of ||b - L x||^2 and ||b||^2
+__global__ void __launch_bounds__(NT) k_resid(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ b, const double* __restrict__ x,
+                                              double* __restrict__ partials) {
+    __shared__ double sh[2 * NT];
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    double v[2] = {0.0, 0.0};
+    march(g, pcode, x, [&](long long c, uint8_t pc, double xc, double xw, double xe, double xs, double xn,
+                           double xb, double xt) {
+        double res = b[c] - lap_code(pc, xc, xw, xe, xs, xn, xb, xt, idx2);
         v[0] += res * res;
         v[1] += b[c] * b[c];
+    });
+    block_reduce<2>(v, sh);
+    if (threadIdx.x == 0) {
+        partials[SLOT_RES0 * MAX_BLOCKS + blockIdx.x] = v[0];
+        partials[SLOT_RES1 * MAX_BLOCKS + blockIdx.x] = v[1];
     }
-    double tot[2];
-    if (grid_reduce<2>(v, partials, counter, sh, tot) && threadIdx.x == 0) {
-        out[0] = tot[0];
-        out[1] = tot[1];
+}
+
+__global__ void __launch_bounds__(NT) k_sum2(const double* partials, int nparts, int s0, int s1, double* out) {
+    __shared__ double sh[2 * NT];
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += NT) {
+        v[0] += partials[s0 * MAX_BLOCKS + b];
+        v[1] += partials[s1 * MAX_BLOCKS + b];
     }
+    block_reduce<2>(v, sh);
+    if (threadIdx.x == 0) {
+        out[0] = v[0];
+        out[1] = v[1];
+    }
+}
+
+// y = L x
+__global__ void __launch_bounds__(NT) k_lap(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ x, double* __restrict__ y) {
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    march(g, pcode, x, [&](long long c, uint8_t pc, double xc, double xw, double xe, double xs, double xn,
+                           double xb, double xt) { y[c] = lap_code(pc, xc, xw, xe, xs, xn, xb, xt, idx2); });
 }
 
 }  // namespace
 
+// blocks of the z-marching sweeps: one per (tile, slab) item up to the partial capacity
+int march_blocks(const Geo& g) {
+    long long items = (long long)g.ntx * g.nty * slab_count(g.nz);
+    return (int)(items < MAX_BLOCKS ? items : MAX_BLOCKS);
+}
+
+static int vmarch_blocks(const Geo& g) {
+    long long items = (long long)((g.nx + VTX - 1) / VTX) * g.nty * vslab_count(g.nz);
+    return (int)(items < MAX_BLOCKS ? items : MAX_BLOCKS);
+}
+
+// Event pairs around the timed sweeps, recorded on the launch stream; collected
+// after the solve's final host synchronisation.
+void timing_begin(ibm_ctx* c, int k, hipStream_t s) {
+    if (!c->timing_on || c->ev_used[k] >= c->ev_cap) return;
+    (void)hipEventRecord(c->ev[k][2 * c->ev_used[k]], s);
+}
+
+void timing_end(ibm_ctx* c, int k, hipStream_t s) {
+    if (!c->timing_on || c->ev_used[k] >= c->ev_cap) return;
+    (void)hipEventRecord(c->ev[k][2 * c->ev_used[k] + 1], s);
+    c->ev_used[k] += 1;
+}
+
+void timing_collect(ibm_ctx* c) {
+    if (!c->timing_on) return;
+    for (int k = 0; k < 4; ++k) {
+        for (int e = 0; e < c->ev_used[k]; ++e) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev[k][2 * e], c->ev[k][2 * e + 1]) == hipSuccess) {
+                c->t_ms[k] += ms;
+                c->t_launches[k] += 1;
+            }
+        }
+        c->ev_used[k] = 0;
+    }
+}
+
+int laplacian_run(ibm_ctx* c, const double* x, double* y, hipStream_t s) {
+    k_lap<<<march_blocks(c->geo), NT, 0, s>>>(c->geo, c->pcode, x, y);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
 int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hipStream_t s) {
-    k_resid<<<grid_blocks(c->geo), NT, 0, s>>>(c->geo, c->mask, b, x, c->partials, c->counter, c->red);
+    const int nb = march_blocks(c->geo);
+    k_resid<<<nb, NT, 0, s>>>(c->geo, c->pcode, b, x, c->partials);
+    k_sum2<<<1, NT, 0, s>>>(c->partials, nb, SLOT_RES0, SLOT_RES1, c->red);
     IBM_HIP(hipGetLastError());
     IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     IBM_HIP(hipStreamSynchronize(s));
@@ -211,23 +675,62 @@ int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hip
 int pcg64(ibm_ctx* c, const double* b, double* x, double tol, int max_iter, int check_every, int* iters,
           hipStream_t s) {
     const Geo& g = c->geo;
-    const int nb = grid_blocks(g);
-    k_pcg_init<<<nb, NT, 0, s>>>(g, c->mask, b, x, c->r, c->d, c->partials, c->counter, c->solver, tol);
-    k_zero_if_trivial<<<1024, 256, 0, s>>>(g, x, c->solver);
+    const long long N = c->N;
+    // even nx: the double2 passes; every reduction of the solve is then written by nv
+    // blocks (the init sweep runs with the same count), so all partial sums agree
+    const bool vec = (g.nx % 2) == 0 && ((uintptr_t)x % 16) == 0;
+    const int nred = vec ? vmarch_blocks(g) : march_blocks(g);
+    double* dbuf[2] = {c->d, c->q};
+    k_pcg_init<<<nred, NT, 0, s>>>(g, c->pcode, b, x, c->r, c->zbuf, c->partials);
+    k_pcg_start<<<1, NT, 0, s>>>(c->partials, nred, c->solver, tol);
+    k_zero_if_trivial<<<1024, 256, 0, s>>>(N, x, c->solver);
     IBM_HIP(hipGetLastError());
+    auto pass_a = [&](int it) {
+        double* dnew = dbuf[it & 1];
+        double* dold = dbuf[(it + 1) & 1];
+        if (vec) {
+            if (it == 0)
+                k_pcg_a_v<true><<<nred, NT, 0, s>>>(g, c->pcode, c->zbuf, dold, dnew, x, c->partials, nred, it,
+                                                    c->solver);
+            else
+                k_pcg_a_v<false><<<nred, NT, 0, s>>>(g, c->pcode, c->zbuf, dold, dnew, x, c->partials, nred, it,
+                                                     c->solver);
+        } else {
+            k_pcg_a<<<nred, NT, 0, s>>>(g, c->pcode, c->zbuf, dold, dnew, x, c->partials, nred, it, 0, c->solver);
+        }
+    };
+    auto pass_b = [&](int it) {
+        double* dnew = dbuf[it & 1];
+        if (vec)
+            k_pcg_b_v<<<nred, NT, 0, s>>>(g, c->pcode, dnew, c->r, c->zbuf, c->partials, nred, it, c->solver);
+        else
+            k_pcg_b<<<nred, NT, 0, s>>>(g, c->pcode, dnew, c->r, c->zbuf, c->partials, nred, it, c->solver);
+    };
     if (check_every <= 0) check_every = 16;
     int batch = c->last_iters > 0 ? c->last_iters + 2 : check_every;
     int total = 0;
     while (true) {
         int n = batch;
         if (n > max_iter - total) n = max_iter - total;
-        for (int it = 0; it < n; ++it) {
-            k_pcg_spmv<<<nb, NT, 0, s>>>(g, c->mask, c->d, c->q, c->partials, c->counter, c->solver);
-            k_pcg_update<<<nb, NT, 0, s>>>(g, c->mask, x, c->d, c->q, c->r, c->partials, c->counter, c->solver);
-            k_pcg_dir<<<nb, NT, 0, s>>>(g, c->mask, c->r, c->d, c->solver);
+        for (int k = 0; k < n; ++k) {
+            const int it = total + k;
+            timing_begin(c, TK_SPMV, s);
+            pass_a(it);
+            timing_end(c, TK_SPMV, s);
+            timing_begin(c, TK_UPDATE, s);
+            pass_b(it);
+            timing_end(c, TK_UPDATE, s);
         }
         IBM_HIP(hipGetLastError());
         total += n;
+        if (total >= max_iter) {
+            // at the cap, one more pass A tests r_total and applies the last x update
+            // (when not converged it also starts a direction that is never used)
+            pass_a(total);
+            IBM_HIP(hipGetLastError());
+        }
+        // otherwise a residual that converged in the last pass B is detected by the
+        // first pass A of the next batch, which then only applies the last x update
         IBM_HIP(hipMemcpyAsync(c->h_solver, c->solver, sizeof(Solver), hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
         if (c->h_solver->converged || total >= max_iter) break;
@@ -235,6 +738,8 @@ int pcg64(ibm_ctx* c, const double* b, double* x, double tol, int max_iter, int 
     }
     *iters = c->h_solver->iters;
     c->last_iters = c->h_solver->iters;
+    timing_collect(c);
+    if (c->timing_on) c->t_real_iters += c->h_solver->iters;
     if (c->h_solver->converged == 3) {
         set_error("pressure solve: non-finite residual");
         return IBM_ERR_NAN;

@@ -185,6 +185,30 @@ __global__ void k_class_adj(Geo g, uint16_t* flags) {
     }
 }
 
+// pressure operator code: open faces (not blocked, not a non-periodic domain face;
+// periodic wraps are open) and the number of outlet faces (Dirichlet p = 0)
+__global__ void k_pcode(Geo g, const uint8_t* eff, uint8_t* pcode) {
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        long long c = cidx(g, i, j, k);
+        uint8_t m = eff[c];
+        unsigned code = 0, outl = 0;
+        for (int d = 0; d < 6; ++d) {
+            bool bnd;
+            (void)nb_index(g, i, j, k, d, bnd);
+            if (bnd) {
+                if (g.bc[d] == IBM_BC_OUTFLOW) outl += 1;
+            } else if (!((m >> d) & 1)) {
+                code |= 1u << d;
+            }
+        }
+        pcode[c] = (uint8_t)(code | (outl << 6));
+    }
+}
+
 __global__ void k_label_init(Geo g, int32_t* label) {
     long long t0, t1;
     tile_range(g, t0, t1);
@@ -360,6 +384,7 @@ int stencil_run(ibm_ctx* c, const uint8_t* blocked, const double* theta, int dea
     k_fill_cuts<<<nb, NT, 0, s>>>(g, blocked, c->mask, c->flags, c->cut_off, theta, o);
     k_class_inc<<<nb, NT, 0, s>>>(g, blocked, c->mask, theta, c->flags);
     k_class_adj<<<nb, NT, 0, s>>>(g, c->flags);
+    k_pcode<<<nb, NT, 0, s>>>(g, c->mask, c->pcode);
     IBM_HIP(hipGetLastError());
 
     // connected components over open faces

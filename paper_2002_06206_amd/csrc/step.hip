@@ -124,8 +124,9 @@ __global__ void __launch_bounds__(NT) k_csm(Geo g, Sten st, C3<T> u, const doubl
 // eq. (forcing_term).  Dead-end cells are frozen at their mean wall velocity.
 template <class T>
 __global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<double> U, const T* nut, V3<T> hio,
-                                                V3<T> us, const double* wall, double dt, double nu, double bx,
-                                                double by, double bz, int first) {
+                                                V3<T> us, const double* wall, double dt, double w_now,
+                                                double w_prev, double nu, double bx, double by, double bz,
+                                                int first) {
     long long t0, t1;
     tile_range(g, t0, t1);
     const double body[3] = {bx, by, bz};
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<doub
             }
             T v;
             if (first) v = qc + (T)dt * h;
-            else v = qc + (T)dt * ((T)1.5 * h - (T)0.5 * hio.p[m][c]);
+            else v = qc + (T)dt * ((T)w_now * h - (T)w_prev * hio.p[m][c]);
             if (dead) {
                 uint32_t id0 = st.cut_off[c];
                 double acc = 0.0;
@@ -275,14 +276,13 @@ __global__ void __launch_bounds__(NT) k_project(Geo g, Sten st, C3<T> us, V3<dou
 
 // ||div U||_2^2 and max |div U| (FP64 divergence check); per-block sums and maxima,
 // combined by the last block in block order
-__global__ void __launch_bounds__(NT) k_div(Geo g, C3<double> U, double* partials, unsigned int* counter,
-                                            double* out) {
+__global__ void __launch_bounds__(NT) k_div(Geo g, C3<double> U, double* partials) {
     __shared__ double sh[NT];
     __shared__ double shm[NT];
-    __shared__ bool last;
     long long t0, t1;
     tile_range(g, t0, t1);
-    double v0 = 0.0, v1 = 0.0;
+    __shared__ double shu[NT];
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
     for (long long t = t0; t < t1; ++t) {
         int i, j, k;
         if (!tile_cell(g, t, i, j, k)) continue;
@@ -292,50 +292,59 @@ __global__ void __launch_bounds__(NT) k_div(Geo g, C3<double> U, double* partial
             bool bm;
             long long nm = nb_index(g, i, j, k, 2 * a, bm);
             double Um = bm ? (g.bc[2 * a] == IBM_BC_INFLOW ? g.uin[a] : 0.0) : U.p[a][nm];
-            div += (U.p[a][c] - Um) / g.dx;
+            double Uc = U.p[a][c];
+            div += (Uc - Um) / g.dx;
+            v2 = fmax(v2, fmax(fabs(Uc), fabs(Um)));
         }
         v0 += div * div;
         v1 = fmax(v1, fabs(div));
     }
     sh[threadIdx.x] = v0;
     shm[threadIdx.x] = v1;
+    shu[threadIdx.x] = v2;
     __syncthreads();
     for (int s = NT / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             sh[threadIdx.x] += sh[threadIdx.x + s];
             shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + s]);
+            shu[threadIdx.x] = fmax(shu[threadIdx.x], shu[threadIdx.x + s]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         partials[blockIdx.x] = sh[0];
         partials[MAX_BLOCKS + blockIdx.x] = shm[0];
-        __threadfence();
-        unsigned int tk = atomicAdd(counter, 1u);
-        last = (tk == gridDim.x - 1);
+        partials[2 * MAX_BLOCKS + blockIdx.x] = shu[0];
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double acc = 0.0, mx = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += NT) {
+}
+
+// one block: sum of the squared divergence, max |div|, max |U| over the block partials
+__global__ void __launch_bounds__(NT) k_div_final(const double* partials, int nparts, double* out) {
+    __shared__ double sh[NT];
+    __shared__ double shm[NT];
+    __shared__ double shu[NT];
+    double acc = 0.0, mx = 0.0, mu = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += NT) {
         acc += partials[b];
         mx = fmax(mx, partials[MAX_BLOCKS + b]);
+        mu = fmax(mu, partials[2 * MAX_BLOCKS + b]);
     }
     sh[threadIdx.x] = acc;
     shm[threadIdx.x] = mx;
+    shu[threadIdx.x] = mu;
     __syncthreads();
     for (int s = NT / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             sh[threadIdx.x] += sh[threadIdx.x + s];
             shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + s]);
+            shu[threadIdx.x] = fmax(shu[threadIdx.x], shu[threadIdx.x + s]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         out[0] = sh[0];
         out[1] = shm[0];
-        *counter = 0u;
+        out[2] = shu[0];
     }
 }
 
@@ -368,31 +377,6 @@ __global__ void __launch_bounds__(NT) k_init(Geo g, Sten st, V3<T> u, V3<double>
     }
 }
 
-// y = L x: (1/dx^2) [sum over open faces (x_nb - x_c) - 2 x_c per outlet face]
-__global__ void __launch_bounds__(NT) k_lap(Geo g, const uint8_t* mask, const double* x, double* y) {
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    const double idx2 = 1.0 / (g.dx * g.dx);
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        uint8_t msk = mask[c];
-        double xc = x[c];
-        double acc = 0.0;
-        for (int d = 0; d < 6; ++d) {
-            bool bnd;
-            long long n = nb_index(g, i, j, k, d, bnd);
-            if (bnd) {
-                if (g.bc[d] == IBM_BC_OUTFLOW) acc += -2.0 * xc;
-            } else if (!((msk >> d) & 1)) {
-                acc += x[n] - xc;
-            }
-        }
-        y[c] = acc * idx2;
-    }
-}
-
 __global__ void k_cut_points(Geo g, long long ncut, const int32_t* cell, const uint8_t* dir, const double* theta,
                              double* X) {
     for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < ncut;
@@ -421,8 +405,7 @@ template <class T>
 __global__ void __launch_bounds__(NT) k_forces(long long ncut, const int32_t* cell, const uint8_t* dir,
                                                const double* a_ib, const double* a_c, const double* a_o,
                                                const int32_t* opp, C3<T> u, const double* p, const T* nut,
-                                               double nu, double dx, const double* wall, double* partials,
-                                               unsigned int* counter, double* out) {
+                                               double nu, double dx, const double* wall, double* partials) {
     __shared__ double sh[6 * NT];
     double v[6] = {0, 0, 0, 0, 0, 0};
     const double A = dx * dx;
@@ -444,11 +427,19 @@ __global__ void __launch_bounds__(NT) k_forces(long long ncut, const int32_t* ce
             v[3 + m] -= vis * (gh - qc) / dx * A;
         }
     }
-    double tot[6];
-    if (grid_reduce<6>(v, partials, counter, sh, tot)) {
-        if (threadIdx.x == 0)
-            for (int a = 0; a < 6; ++a) out[a] = tot[a];
-    }
+    block_reduce<6>(v, sh);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) partials[a * MAX_BLOCKS + blockIdx.x] = v[a];
+}
+
+__global__ void __launch_bounds__(NT) k_sum6(const double* partials, int nparts, double* out) {
+    __shared__ double sh[6 * NT];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nparts; b += NT)
+        for (int a = 0; a < 6; ++a) v[a] += partials[a * MAX_BLOCKS + b];
+    block_reduce<6>(v, sh);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) out[a] = v[a];
 }
 
 // Mean removal on every enclosed component: one block per component, fixed order.
@@ -491,8 +482,11 @@ int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, co
     C3<double> UU{{U[0], U[1], U[2]}};
     V3<T> hh{{(T*)h[0], (T*)h[1], (T*)h[2]}};
     V3<T> us{{(T*)c->ustar[0], (T*)c->ustar[1], (T*)c->ustar[2]}};
-    k_predict<T><<<nb, NT, 0, s>>>(g, st, uu, UU, nut, hh, us, wall, prm->dt, prm->nu, prm->body_force[0],
-                                   prm->body_force[1], prm->body_force[2], prm->step == 0 ? 1 : 0);
+    // variable-step Adams-Bashforth weights, r = dt / dt_prev
+    const double r = prm->dt_prev > 0.0 ? prm->dt / prm->dt_prev : 1.0;
+    k_predict<T><<<nb, NT, 0, s>>>(g, st, uu, UU, nut, hh, us, wall, prm->dt, 1.0 + 0.5 * r, 0.5 * r, prm->nu,
+                                   prm->body_force[0], prm->body_force[1], prm->body_force[2],
+                                   prm->step == 0 ? 1 : 0);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -542,7 +536,8 @@ int forces_t(ibm_ctx* c, void* const* u, const double* p, const void* nut, doubl
     long long nbk = (c->ncut + NT - 1) / NT;
     int nb = (int)(nbk < 1024 ? nbk : 1024);
     k_forces<T><<<nb, NT, 0, s>>>(c->ncut, c->cut_cell, c->cut_dir, c->a_ib, c->a_c, c->a_o, c->cut_opp, uu, p, nt,
-                                  nu, c->geo.dx, wall, c->partials, c->counter, c->red);
+                                  nu, c->geo.dx, wall, c->partials);
+    k_sum6<<<1, NT, 0, s>>>(c->partials, nb, c->red);
     IBM_HIP(hipGetLastError());
     IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
     IBM_HIP(hipStreamSynchronize(s));
@@ -555,12 +550,6 @@ int forces_t(ibm_ctx* c, void* const* u, const double* p, const void* nut, doubl
 int remove_means(ibm_ctx* c, double* a, hipStream_t s) {
     if (c->ncomp <= 0) return IBM_OK;
     k_remove_means<<<c->ncomp, NT, 0, s>>>(c->enc_cells, c->comp_start, a);
-    IBM_HIP(hipGetLastError());
-    return IBM_OK;
-}
-
-int laplacian_run(ibm_ctx* c, const double* x, double* y, hipStream_t s) {
-    k_lap<<<grid_blocks(c->geo), NT, 0, s>>>(c->geo, c->mask, x, y);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -594,14 +583,17 @@ int step_project(ibm_ctx* c, void** u, double** U, const double* p, double dt, h
     return c->precision == IBM_FP64 ? project_t<double>(c, u, U, p, dt, s) : project_t<float>(c, u, U, p, dt, s);
 }
 
-int divergence_norms(ibm_ctx* c, double** U, double* l2, double* linf, hipStream_t s) {
+int divergence_norms(ibm_ctx* c, double** U, double* l2, double* linf, double* umax, hipStream_t s) {
     C3<double> UU{{U[0], U[1], U[2]}};
-    k_div<<<grid_blocks(c->geo), NT, 0, s>>>(c->geo, UU, c->partials, c->counter, c->red);
+    const int nb = grid_blocks(c->geo);
+    k_div<<<nb, NT, 0, s>>>(c->geo, UU, c->partials);
+    k_div_final<<<1, NT, 0, s>>>(c->partials, nb, c->red);
     IBM_HIP(hipGetLastError());
-    IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     IBM_HIP(hipStreamSynchronize(s));
     *l2 = sqrt(c->h_red[0]);
     *linf = c->h_red[1];
+    *umax = c->h_red[2];
     return IBM_OK;
 }
 

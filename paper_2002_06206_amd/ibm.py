@@ -42,7 +42,8 @@ class SolverOpts(ctypes.Structure):
 
 
 class StepParams(ctypes.Structure):
-    _fields_ = [("dt", ctypes.c_double), ("nu", ctypes.c_double), ("c1", ctypes.c_double),
+    _fields_ = [("dt", ctypes.c_double), ("dt_prev", ctypes.c_double), ("nu", ctypes.c_double),
+                ("c1", ctypes.c_double),
                 ("csm_on", ctypes.c_int32), ("step", ctypes.c_int32), ("body_force", ctypes.c_double * 3),
                 ("poisson", SolverOpts)]
 
@@ -50,7 +51,8 @@ class StepParams(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iters_inner", ctypes.c_int32), ("iters_outer", ctypes.c_int32),
                 ("fallback_used", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double), ("div_l2", ctypes.c_double), ("div_linf", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("div_l2", ctypes.c_double), ("div_linf", ctypes.c_double),
+                ("umax", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -78,6 +80,8 @@ def _load():
         "ibm_get_nut": ([vp, vp, vp], ctypes.c_int),
         "ibm_get_rhs": ([vp, vp, vp], ctypes.c_int),
         "ibm_forces": ([vp, P3, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
+        "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
+        "ibm_timing_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -89,7 +93,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "ibm_build_stencils",
             "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
-            "ibm_get_nut", "ibm_get_rhs", "ibm_forces")
+            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_timing_enable", "ibm_timing_read")
 
 
 def lib():
@@ -187,6 +191,18 @@ def ibm_forces(ctx, u, p, nu, nut=None, wall=None):
     return list(out[:3]), list(out[3:])
 
 
+def ibm_timing_enable(ctx, on=True):
+    return _check(_lib.ibm_timing_enable(ctx, int(bool(on))), "ibm_timing_enable")
+
+
+def ibm_timing_read(ctx, reset=False):
+    out = (ctypes.c_double * 10)()
+    _check(_lib.ibm_timing_read(ctx, out, int(bool(reset))), "ibm_timing_read")
+    v = list(out)
+    return {"ms": v[0:3], "launches": [int(x) for x in v[3:6]], "real_iters": int(v[6]), "cells": int(v[7]),
+            "cuts": int(v[8]), "precision": int(v[9])}
+
+
 # ------------------------------------------------------------- convenience
 
 def solver_opts(tol=1e-10, max_iter=20000, kind=SOLVER_PCG_JACOBI, inner_tol=1e-2, inner_max_iter=200,
@@ -194,8 +210,9 @@ def solver_opts(tol=1e-10, max_iter=20000, kind=SOLVER_PCG_JACOBI, inner_tol=1e-
     return SolverOpts(tol, max_iter, kind, inner_tol, inner_max_iter, stall_factor, check_every, force_stall)
 
 
-def step_params(dt, nu, c1=1.0 / 20.0, csm=True, step=0, body=(0.0, 0.0, 0.0), **solver):
-    return StepParams(dt, nu, c1, int(bool(csm)), int(step), (ctypes.c_double * 3)(*body), solver_opts(**solver))
+def step_params(dt, nu, c1=1.0 / 20.0, csm=True, step=0, body=(0.0, 0.0, 0.0), dt_prev=0.0, **solver):
+    return StepParams(dt, dt_prev, nu, c1, int(bool(csm)), int(step), (ctypes.c_double * 3)(*body),
+                      solver_opts(**solver))
 
 
 class Solver:

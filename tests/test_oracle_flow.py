@@ -431,3 +431,25 @@ def test_deadend_filter_closes_pocket():
     assert st.deadend.sum() == 1
     # the pocket is an isolated enclosed cell
     assert st.flags[c] & (1 << 15)
+
+
+def test_variable_step_ab2_integrates_linear_forcing_exactly():
+    """Second-order Adams-Bashforth with r = dt/dt_prev integrates a right-hand side
+    that is linear in time exactly: with a uniform periodic flow and body force
+    g(t) = a + b t, every increment after the Euler start equals the integral of g."""
+    g = flow.Grid((4, 4, 4), 1.0, (0.0, 0.0, 0.0), (P,) * 6)
+    st = flow.build_stencils(g, *empty(g))
+    u, U, p, h = flow.init_state(st, (0.3, 0.0, 0.0))
+    a, b = 0.7, -0.45
+    t = 0.0
+    dts = [0.1, 0.13, 0.07, 0.2, 0.05, 0.11]
+    dt_prev = 0.0
+    for n, dt in enumerate(dts):
+        u0 = u[0][0, 0, 0]
+        prm = flow.StepParams(dt=dt, nu=0.01, csm=False, body=(a + b * t, 0.0, 0.0), tol=1e-12, dt_prev=dt_prev)
+        u, U, p, h, _ = flow.step(st, u, U, p, h, prm, n)
+        if n > 0:
+            exact = a * dt + b * ((t + dt) ** 2 - t ** 2) / 2
+            assert abs((u[0][0, 0, 0] - u0) - exact) < 1e-14
+        t += dt
+        dt_prev = dt
