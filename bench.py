@@ -34,6 +34,9 @@ SWEEP_BYTES = {"pcg_a": 41, "pcg_b": 33, "unused": 0}
 SWEEP_NAMES = ("pcg_a", "pcg_b", "unused")
 # kernel names of the double2 passes (grids with an even cell count in x; the scalar
 # passes k_pcg_a / k_pcg_b serve odd nx)
+# FP32 vectors of the mixed correction solve: A reads z, d, x (4 B), code; writes x, d.
+# B reads d, r, code; writes r, z
+SWEEP_BYTES_F32 = {"pcg_a": 21, "pcg_b": 17, "unused": 0}
 KERNEL_SYMBOL = {"pcg_a": "k_pcg_a_v", "pcg_b": "k_pcg_b_v", "unused": ""}
 
 
@@ -114,6 +117,83 @@ def cpu_baseline(case, gpu_iters_per_step, n_pcg=3):
     }
 
 
+def run_solver(case, solver, args, ibm, torch):
+    """Set-up, warm-up and timed steps of one solver configuration.  Returns a dict."""
+    N = case.n[0] * case.n[1] * case.n[2]
+    precision = ibm.FP64 if solver == "pcg_fp64" else ibm.MIXED
+    kind = {"pcg_fp64": ibm.SOLVER_PCG_JACOBI, "mixed": ibm.SOLVER_FCG_JACOBI,
+            "mixed_learned": ibm.SOLVER_FCG_CNN}[solver]
+    t0 = time.perf_counter()
+    s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, precision)
+    blocked, theta = s.tag(case.tri)
+    s.build(blocked, None, case.deadend)
+    del theta
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    st = s.new_state(case.u_in)
+    # time step: CFL 0.3 on the largest face velocity of the previous step, capped at
+    # the configured dt (= CFL 0.3 on the inflow velocity); variable-step AB2
+    ctl = {"dt_prev": 0.0, "umax": max(abs(v) for v in case.u_in)}
+
+    def params(step):
+        dt = min(case.dt, 0.3 * case.dx / max(ctl["umax"], 1e-30))
+        p = ibm.step_params(dt, case.nu, csm=case.csm, step=step, dt_prev=ctl["dt_prev"], tol=args.tol,
+                            max_iter=20000, check_every=16, kind=kind, inner_tol=args.inner_tol,
+                            inner_max_iter=2000)
+        ctl["dt_prev"] = dt
+        return p
+
+    step = 0
+    for _ in range(args.warmup):
+        rc, stats = s.step(st, params(step))
+        ctl["umax"] = stats["umax"]
+        step += 1
+    ibm.ibm_timing_enable(s.ctx, True)
+    ibm.ibm_timing_read(s.ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, outers, fallbacks = [], [], 0
+    worst_res = 0.0
+    worst_div = 0.0
+    forces = None
+    for _ in range(args.steps):
+        rc, stats = s.step(st, params(step))
+        ctl["umax"] = stats["umax"]
+        forces = s.forces(st, case.nu)
+        step += 1
+        iters.append(stats["iters_inner"])
+        outers.append(stats["iters_outer"])
+        fallbacks += stats["fallback_used"]
+        worst_res = max(worst_res, stats["rel_residual"])
+        worst_div = max(worst_div, stats["div_linf"])
+        if rc != 0:
+            raise SystemExit("%s: step %d did not converge (rc=%d)" % (solver, step, rc))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = ibm.ibm_timing_read(s.ctx, reset=True)
+    ibm.ibm_timing_enable(s.ctx, False)
+    elapsed = t1 - t0
+    bytes_tab = SWEEP_BYTES if precision == ibm.FP64 else SWEEP_BYTES_F32
+    k_dom = max(range(3), key=lambda k: tim["ms"][k])
+    name = SWEEP_NAMES[k_dom]
+    real = tim["real_iters"]
+    avg_s = tim["ms"][k_dom] / 1e3 / max(real, 1)
+    achieved = bytes_tab[name] * N / avg_s / 1e9
+    Fp, Fv = forces
+    out = {"solver": solver, "value": N * args.steps / elapsed, "ms_per_step": elapsed / args.steps * 1e3,
+           "iters_per_step": sum(iters) / len(iters), "refinement_sweeps_per_step": sum(outers) / len(outers),
+           "fallbacks": fallbacks, "max_rel_residual": worst_res, "max_div_linf": worst_div,
+           "setup_s": round(t_setup, 3), "cuts": s.ncut, "dt_last": ctl["dt_prev"],
+           "force_last_step": [a + b for a, b in zip(Fp, Fv)],
+           "dominant": {"name": name, "kernel": KERNEL_SYMBOL[name] + ("" if precision == ibm.FP64 else "<float>"),
+                        "bytes_per_cell": bytes_tab[name], "avg_s": avg_s, "achieved_gbs": achieved,
+                        "launches": tim["launches"][k_dom], "launches_with_work": real,
+                        "sweeps_ms": {SWEEP_NAMES[k]: round(tim["ms"][k], 2) for k in range(3)}}}
+    s.close()
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +201,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ellipsoids256")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--solver", default="mixed", choices=["mixed", "mixed_learned", "pcg_fp64"],
+                    help="headline solver; the plain FP64 solver is always run beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -135,97 +218,38 @@ def main():
     case = workload(args.workload)
     N = case.n[0] * case.n[1] * case.n[2]
 
-    t0 = time.perf_counter()
-    s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
-    blocked, theta = s.tag(case.tri)
-    s.build(blocked, None, case.deadend)
-    del theta
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    st = s.new_state(case.u_in)
-
-    # time step: CFL 0.3 on the largest face velocity of the previous step, capped at
-    # the configured dt (= CFL 0.3 on the inflow velocity); variable-step AB2
-    ctl = {"dt_prev": 0.0, "umax": max(abs(v) for v in case.u_in)}
-
-    def params(step):
-        dt = min(case.dt, 0.3 * case.dx / max(ctl["umax"], 1e-30))
-        p = ibm.step_params(dt, case.nu, csm=case.csm, step=step, dt_prev=ctl["dt_prev"], tol=args.tol,
-                            max_iter=20000, check_every=16)
-        ctl["dt_prev"] = dt
-        return p
-
-    step = 0
-    for _ in range(args.warmup):
-        rc, stats = s.step(st, params(step))
-        ctl["umax"] = stats["umax"]
-        step += 1
-    ibm.ibm_timing_enable(s.ctx, True)
-    ibm.ibm_timing_read(s.ctx, reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = []
-    worst_res = 0.0
-    worst_div = 0.0
-    forces = None
-    for _ in range(args.steps):
-        rc, stats = s.step(st, params(step))
-        ctl["umax"] = stats["umax"]
-        forces = s.forces(st, case.nu)
-        step += 1
-        iters.append(stats["iters_inner"])
-        worst_res = max(worst_res, stats["rel_residual"])
-        worst_div = max(worst_div, stats["div_linf"])
-        if rc != 0:
-            raise SystemExit("step %d did not converge (rc=%d)" % (step, rc))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tim = ibm.ibm_timing_read(s.ctx, reset=True)
-    ibm.ibm_timing_enable(s.ctx, False)
-    elapsed = t1 - t0
-    value = N * args.steps / elapsed
-
-    # dominant kernel: the sweep with the largest accumulated time
-    k_dom = max(range(3), key=lambda k: tim["ms"][k])
-    name = SWEEP_NAMES[k_dom]
-    real = tim["real_iters"]
-    avg_s = tim["ms"][k_dom] / 1e3 / max(real, 1)
-    achieved = SWEEP_BYTES[name] * N / avg_s / 1e9
-    traffic = committed_traffic(name, args.workload)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_SYMBOL[name],
-                "algorithmic_bytes_per_launch": SWEEP_BYTES[name] * N,
-                "avg_launch_us": round(avg_s * 1e6, 2), "launches": tim["launches"][k_dom],
-                "launches_with_work": real,
-                "sweeps_ms": {SWEEP_NAMES[k]: round(tim["ms"][k], 2) for k in range(3)}}
-
+    plain = run_solver(case, "pcg_fp64", args, ibm, torch)
+    head = plain if args.solver == "pcg_fp64" else run_solver(case, args.solver, args, ibm, torch)
+    dom = head["dominant"]
+    traffic = committed_traffic(dom["name"], args.workload) if args.solver == "pcg_fp64" else None
+    roofline = {"bound": "hbm", "achieved": round(dom["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["kernel"],
+                "algorithmic_bytes_per_launch": dom["bytes_per_cell"] * N,
+                "avg_launch_us": round(dom["avg_s"] * 1e6, 2), "launches": dom["launches"],
+                "launches_with_work": dom["launches_with_work"], "sweeps_ms": dom["sweeps_ms"]}
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(case, sum(iters) / len(iters))
-
-    Fp, Fv = forces
+        cpu = cpu_baseline(case, plain["iters_per_step"])
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "cell-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.solver == "pcg_fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": case.name, "cells": list(case.n), "triangles": int(len(case.tri)),
-                   "cuts": s.ncut, "solver": "pcg_jacobi_fp64", "tol": args.tol, "re_nu": case.nu,
-                   "dt_max": case.dt, "cfl": 0.3, "dt_last": ctl["dt_prev"], "csm": case.csm},
-        "plain_fp64_value": value,
-        "pcg_iters_per_step": sum(iters) / len(iters),
-        "max_rel_residual": worst_res,
-        "max_div_linf": worst_div,
-        "setup_s": round(t_setup, 3),
-        "force_last_step": [a + b for a, b in zip(Fp, Fv)],
+                   "cuts": head["cuts"], "solver": head["solver"], "tol": args.tol, "inner_tol": args.inner_tol,
+                   "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm},
+        "plain_fp64_value": plain["value"],
+        "speedup_vs_plain_fp64": head["value"] / plain["value"],
+        "headline": {k: v for k, v in head.items() if k != "dominant"},
+        "plain_fp64": {k: v for k, v in plain.items() if k != "dominant"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

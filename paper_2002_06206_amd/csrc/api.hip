@@ -124,6 +124,12 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
     if (!rc) rc = dalloc(&c->d, sizeof(double) * N);
     if (!rc) rc = dalloc(&c->q, sizeof(double) * N);
     if (!rc) rc = dalloc(&c->zbuf, sizeof(double) * N);
+    // FP32 vectors of the mixed-precision correction solve
+    if (!rc) rc = dalloc(&c->r32, sizeof(float) * N);
+    if (!rc) rc = dalloc(&c->z32, sizeof(float) * N);
+    if (!rc) rc = dalloc(&c->d32, sizeof(float) * N);
+    if (!rc) rc = dalloc(&c->q32, sizeof(float) * N);
+    if (!rc) rc = dalloc(&c->e32, sizeof(float) * N);
     if (!rc) rc = dalloc(&c->partials, sizeof(double) * 16 * MAX_BLOCKS);
     if (!rc) rc = dalloc(&c->counter, sizeof(unsigned int) * 16);
     if (!rc) rc = dalloc(&c->solver, sizeof(Solver));

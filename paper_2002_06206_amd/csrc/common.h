@@ -32,7 +32,8 @@ struct Solver {                 // device-resident scalars of the Krylov loops
     double fnorm2;              // ||f||^2 of the current solve
     double tol2;                // tol^2 * fnorm2
     double rz, rz_new, rr, dq, alpha, beta;
-    double rr_prev_fcg;         // unused slot kept for layout stability
+    double bnorm2;              // <b,b> of the current solve
+    double r64norm2;            // <r,r> of the FP64 residual at the last init sweep
     int converged;
     int iters;
     int nan_seen;
@@ -96,7 +97,8 @@ struct ibm_ctx {
     double* h_red;          // pinned host scalars
     double* red;            // device reduction outputs (8 doubles)
     void* cnn;              // preconditioner network (IBM_SOLVER_FCG_CNN), not owned
-    int last_iters;         // iterations of the previous solve (batch sizing)
+    int last_iters;         // iterations of the previous FP64 solve (batch sizing)
+    int last_iters_inner;   // iterations of the previous FP32 correction solve
     bool nut_valid;
     // optional per-kernel event timing of the Krylov sweeps (ibm_timing_enable)
     int timing_on;
@@ -209,6 +211,9 @@ int divergence_norms(ibm_ctx* c, double** U, double* l2, double* linf, double* u
 int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st,
                 hipStream_t s);
 int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hipStream_t s);
+int pcg64(ibm_ctx* c, const double* b, double* x, double tol, int max_iter, int check_every, int* iters,
+          hipStream_t s);
+int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s);
 // timing helpers (poisson.hip)
 enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3 };
 void timing_begin(ibm_ctx* c, int k, hipStream_t s);

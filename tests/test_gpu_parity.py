@@ -295,3 +295,69 @@ def test_determinism_bitwise():
             s.step(gs, ibm.step_params(case.dt, case.nu, step=n, tol=1e-10))
         outs.append(torch.cat([gs["u"][0].flatten(), gs["p"].flatten(), gs["U"][2].flatten()]).cpu().numpy())
     assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+
+
+# ------------------------------------------------------------ mixed precision
+
+def _manufactured(seed=7, n=(32, 24, 20), bc=(1, 2, 3, 3, 0, 0)):
+    rng = np.random.default_rng(seed)
+    g = _grid(n, bc=bc)
+    tri = inputs.dirty_sphere(24, 6.0, seed=2, level=3) + np.array([3.0, 0.0, -2.0])
+    s, st, _, _ = _stencil_both(g, np.ascontiguousarray(tri))
+    p_true = flow.remove_component_means(st, rng.standard_normal(g.shape))
+    b = flow.laplacian(st, p_true)
+    return g, s, st, p_true, b
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-12])
+def test_mixed_refinement_reaches_fp64_accuracy(tol):
+    """FP32 CG corrections inside FP64 iterative refinement: the FP64 residual judge
+    drives the solution below what FP32 alone can represent."""
+    g, s, st, p_true, b = _manufactured()
+    print("case mixed refinement tol", tol, flush=True)
+    x = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    rc, stats = s.poisson(torch.from_numpy(b).cuda(), x, tol=tol, max_iter=20000,
+                          kind=ibm.SOLVER_FCG_JACOBI, inner_tol=1e-3)
+    assert rc == 0
+    assert stats["rel_residual"] <= tol * 1.0001
+    assert stats["iters_outer"] >= 2 and stats["fallback_used"] == 0
+    if tol <= 1e-12:
+        assert rel_l2(x.cpu().numpy(), p_true) < 1e-9
+
+
+def test_mixed_forced_stall_falls_back_to_fp64():
+    g, s, st, p_true, b = _manufactured(9)
+    print("case forced stall", flush=True)
+    x = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    rc, stats = s.poisson(torch.from_numpy(b).cuda(), x, tol=1e-10, max_iter=20000,
+                          kind=ibm.SOLVER_FCG_JACOBI, inner_tol=1e-2, force_stall=1)
+    assert rc == 0 and stats["fallback_used"] == 1
+    assert stats["rel_residual"] <= 1e-10 * 1.0001
+
+
+def test_mixed_precision_step_error_stated():
+    """FP32 cell fields + mixed pressure solve against the FP64 oracle on the 32^3
+    sphere: relative L2 errors of u, p and drag are printed; bounds are loose (the
+    mixed path is not meant to be bit-close)."""
+    case = inputs.case_sphere32()
+    g = _grid(case.n, case.dx, case.origin, case.bc, case.u_in)
+    ob, ot = tagging.tag(case.tri, g.n, g.dx, g.origin)
+    st = flow.build_stencils(g, ob, ot)
+    s = _solver(g, ibm.MIXED)
+    s.build(torch.from_numpy(ob).cuda(), torch.from_numpy(ot).cuda())
+    u, U, p, h = flow.init_state(st, (1.0, 0.0, 0.0))
+    gs = s.new_state((1.0, 0.0, 0.0))
+    oprm = flow.StepParams(dt=case.dt, nu=case.nu, tol=1e-10)
+    print("case mixed step sphere32", flush=True)
+    for n in range(10):
+        u, U, p, h, ostats = flow.step(st, u, U, p, h, oprm, n)
+        rc, gstats = s.step(gs, ibm.step_params(case.dt, case.nu, step=n, tol=1e-10, kind=ibm.SOLVER_FCG_JACOBI,
+                                                inner_tol=1e-3))
+        assert rc == 0 and gstats["rel_residual"] <= 1e-10 * 1.0001
+    eu = rel_l2(_vec(gs["u"]), _vec(u))
+    ep = rel_l2(gs["p"].cpu().numpy(), p)
+    Fp, Fv = s.forces(gs, case.nu)
+    oFp, oFv = flow.forces(st, u, p, ostats["nut"], case.nu)
+    ed = abs((Fp[0] + Fv[0]) - (oFp[0] + oFv[0])) / abs(oFp[0] + oFv[0])
+    print("mixed vs FP64 oracle after 10 steps: rel L2 u %.2e, p %.2e, drag %.2e" % (eu, ep, ed), flush=True)
+    assert eu < 1e-4 and ep < 1e-3 and ed < 1e-3
