@@ -1,0 +1,265 @@
+"""CNN preconditioner oracle: FP64 numpy reference of the learned part of the
+pressure solve (test infrastructure only; the product path never imports it).
+
+What is computed:
+
+* A 3-D convolutional network of four 3x3x3 layers, 2 -> 16 -> 16 -> 16 -> 1
+  channels, ReLU after the first three, zero padding at the domain faces, no
+  biases.  Input channels: the residual scaled by its RMS, and the fraction of
+  the six pressure faces of the cell that are open (geometry).
+* The preconditioner  z = D^-1 r + s * net([r / s, g]),  s = RMS(r), D the
+  diagonal of the pressure operator A = -L.  With all weights zero it is Jacobi.
+* Training loss for one (b, p) pair of the pressure equation L p = b, i.e.
+  A p = f with f = -b:  the A-norm distance of p from the best multiple of the
+  preconditioned right-hand side p_hat = M(f),
+      loss = min_a |p - a p_hat|_A^2 / |p|_A^2 = 1 - (f.p_hat)^2 / ((f.p)(p_hat.A p_hat)),
+  which is invariant to the scale of p_hat, as is the Krylov method it serves.
+* Adam (Kingma and Ba, 2015) and flexible conjugate gradients FCG(1) (Notay,
+  2000: the Polak-Ribiere form of beta), the Krylov method that tolerates a
+  preconditioner that changes from one iteration to the next.
+
+The paper itself runs plain CG-type pressure solves on CPU clusters; this part is
+the learned extension layered on its pressure solve (sec. on the fractional step:
+the pressure Poisson equation).  Rounding points that the GPU path takes in BF16
+(activations, input, output gradient) are reproduced by `bf16_round` when
+`bf16=True`; with `bf16=False` everything is FP64.
+
+Weight layout (also the flat FP32 layout the C ABI takes): per layer, an array
+w[t, ci, co], tap t = (dz+1)*9 + (dy+1)*3 + (dx+1) for offsets dx, dy, dz in
+{-1, 0, 1}; layers concatenated in order.  Fields are numpy arrays shaped
+(nz, ny, nx, C), x fastest in memory.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import flow
+
+LAYERS = ((2, 16), (16, 16), (16, 16), (16, 1))
+TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def n_weights() -> int:
+    return sum(27 * ci * co for ci, co in LAYERS)
+
+
+def split_weights(flat: np.ndarray) -> list:
+    out, o = [], 0
+    for ci, co in LAYERS:
+        n = 27 * ci * co
+        out.append(np.asarray(flat[o:o + n], dtype=np.float64).reshape(27, ci, co))
+        o += n
+    return out
+
+
+def join_weights(ws: list) -> np.ndarray:
+    return np.concatenate([np.asarray(w, dtype=np.float64).reshape(-1) for w in ws])
+
+
+# ------------------------------------------------------------------ bf16
+
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round to the nearest bfloat16 (8-bit significand), ties to even, returned as
+    float64.  bfloat16 is the upper half of an IEEE binary32: round the value to
+    binary32 first, then drop the low 16 bits with round-half-even on them.
+    NaN stays NaN; overflow goes to infinity."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    low = u & 0xFFFF
+    keep = u >> 16
+    up = (low > 0x8000) | ((low == 0x8000) & ((keep & 1) == 1))
+    keep = keep + up.astype(np.uint64)
+    nan = np.isnan(f)
+    r = (keep << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(nan, np.nan, r)
+
+
+# ------------------------------------------------------------------ convolution
+
+def shift0(a: np.ndarray, dz: int, dy: int, dx: int) -> np.ndarray:
+    """Value of `a` at (z+dz, y+dy, x+dx) for every cell (z, y, x), zero where that
+    neighbour lies outside the grid.  `a` is shaped (nz, ny, nx, C)."""
+    out = np.zeros_like(a)
+    nz, ny, nx = a.shape[:3]
+
+    def rng(n, d):
+        lo, hi = max(0, -d), n - max(0, d)
+        return slice(lo, hi), slice(lo + d, hi + d)
+
+    (zo, zi), (yo, yi), (xo, xi) = rng(nz, dz), rng(ny, dy), rng(nx, dx)
+    out[zo, yo, xo] = a[zi, yi, xi]
+    return out
+
+
+def conv_forward(x: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """y[c, co] = sum over taps t and input channels ci of x[c + off_t, ci] w[t, ci, co],
+    zero padding (a cross-correlation, the convention of CNN layers)."""
+    y = np.zeros(x.shape[:3] + (w.shape[2],))
+    for t, (dz, dy, dx) in enumerate(TAPS):
+        y += shift0(x, dz, dy, dx) @ w[t]
+    return y
+
+
+def conv_backward_data(dy: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Adjoint of conv_forward in x: dx[c, ci] = sum_t sum_co w[t, ci, co] dy[c - off_t, co]."""
+    dx = np.zeros(dy.shape[:3] + (w.shape[1],))
+    for t, (dz, dyy, dxx) in enumerate(TAPS):
+        dx += shift0(dy, -dz, -dyy, -dxx) @ w[t].T
+    return dx
+
+
+def conv_backward_weight(x: np.ndarray, dy: np.ndarray) -> np.ndarray:
+    """Gradient in w: dw[t, ci, co] = sum_c x[c + off_t, ci] dy[c, co]."""
+    ci, co = x.shape[3], dy.shape[3]
+    dw = np.zeros((27, ci, co))
+    dyf = dy.reshape(-1, co)
+    for t, (dz, dyy, dxx) in enumerate(TAPS):
+        dw[t] = shift0(x, dz, dyy, dxx).reshape(-1, ci).T @ dyf
+    return dw
+
+
+# ------------------------------------------------------------------ network
+
+def forward(x0: np.ndarray, ws: list, bf16: bool = False):
+    """Network output y (nz, ny, nx) and the saved activations [x0, a1, a2, a3].
+    With bf16=True the input and each hidden activation are rounded to bfloat16 and
+    the weights are taken as their bfloat16 values; sums are FP64 (exact products)."""
+    rnd = bf16_round if bf16 else (lambda v: v)
+    a = rnd(x0)
+    acts = [a]
+    for l, w in enumerate(ws):
+        z = conv_forward(a, rnd(w))
+        if l < len(ws) - 1:
+            a = rnd(np.maximum(z, 0.0))
+            acts.append(a)
+        else:
+            return z[..., 0], acts
+    raise AssertionError
+
+
+def backward(acts: list, ws: list, dy: np.ndarray, bf16: bool = False):
+    """Gradients of a scalar whose gradient in the output y is dy (nz, ny, nx):
+    returns (dws, dx0).  With bf16=True the incoming gradient of every layer is
+    rounded to bfloat16 before it meets the weights or activations, as on the GPU."""
+    rnd = bf16_round if bf16 else (lambda v: v)
+    g = rnd(dy[..., None])
+    dws = [None] * len(ws)
+    dx0 = None
+    for l in range(len(ws) - 1, -1, -1):
+        w = rnd(ws[l])
+        dws[l] = conv_backward_weight(acts[l], g)
+        da = conv_backward_data(g, w)
+        if l == 0:
+            dx0 = da
+        else:
+            g = rnd(np.where(acts[l] > 0.0, da, 0.0))
+    return dws, dx0
+
+
+# ------------------------------------------------------------------ preconditioner
+
+def geometry_channel(st: flow.Stencil) -> np.ndarray:
+    """Fraction of the six faces of each cell that are open pressure faces."""
+    n = np.zeros(st.grid.shape)
+    for d in range(6):
+        n += flow.open_face(st, d)
+    return n / 6.0
+
+
+def jacobi_inverse(st: flow.Stencil) -> np.ndarray:
+    dg = flow.jacobi_diag(st)
+    return np.divide(1.0, dg, out=np.zeros_like(dg), where=dg > 0)
+
+
+def rms(r: np.ndarray) -> float:
+    return float(np.sqrt(np.sum(r * r) / r.size))
+
+
+def network_input(st: flow.Stencil, r: np.ndarray, s: float) -> np.ndarray:
+    return np.stack([r / s, geometry_channel(st)], axis=-1)
+
+
+def precondition(st: flow.Stencil, r: np.ndarray, ws: list, bf16: bool = False) -> np.ndarray:
+    """z = D^-1 r + s net([r/s, g]), s = RMS(r); z = 0 for r = 0."""
+    s = rms(r)
+    if s == 0.0:
+        return np.zeros_like(r)
+    y, _ = forward(network_input(st, r, s), ws, bf16)
+    return jacobi_inverse(st) * r + s * y
+
+
+def apply_A(st: flow.Stencil, v: np.ndarray) -> np.ndarray:
+    """The symmetric positive (semi-)definite pressure operator A = -L."""
+    return -flow.laplacian(st, v)
+
+
+def loss_and_grad(st: flow.Stencil, b: np.ndarray, p: np.ndarray, ws: list, bf16: bool = False):
+    """Scale-invariant A-norm loss of the preconditioned right-hand side for the pair
+    (b, p), L p = b, and its gradient in the weights.  Returns (loss, dws)."""
+    f = -b
+    s = rms(f)
+    y, acts = forward(network_input(st, f, s), ws, bf16)
+    ph = jacobi_inverse(st) * f + s * y
+    q = apply_A(st, ph)
+    c = float(np.sum(f * ph))
+    Q = float(np.sum(ph * q))
+    B = float(np.sum(f * p))
+    loss = 1.0 - c * c / (B * Q)
+    # d loss / d p_hat = (2c/(BQ)) ((c/Q) A p_hat - f), chained through p_hat = ... + s y
+    gph = (2.0 * c / (B * Q)) * ((c / Q) * q - f)
+    dws, _ = backward(acts, ws, s * gph, bf16)
+    return loss, dws
+
+
+def loss_only(st, b, p, ws, bf16=False) -> float:
+    f = -b
+    ph = precondition(st, f, ws, bf16)
+    c = float(np.sum(f * ph))
+    Q = float(np.sum(ph * apply_A(st, ph)))
+    return 1.0 - c * c / (float(np.sum(f * p)) * Q)
+
+
+def adam(w: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int, lr: float,
+         b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (step count t starting at 1) of the flat arrays; returns (w, m, v)."""
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return w - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ------------------------------------------------------------------ flexible CG
+
+def fcg(st: flow.Stencil, b: np.ndarray, x0: np.ndarray, precond, tol: float, max_iter: int):
+    """Flexible conjugate gradients FCG(1) on A x = -b (A = -L), warm start x0.
+
+    Iteration: z = M(r); beta = <z, r - r_prev> / <z_prev, r_prev> (zero on the first
+    iteration); d = z + beta d; alpha = <z, r> / <d, A d>; x += alpha d; r -= alpha A d.
+    Stops at |r|_2 <= tol |b|_2 on the recursive residual.  Returns (x, iters)."""
+    f = -b
+    fn = np.sqrt(np.sum(f * f))
+    if fn == 0.0:
+        return np.zeros_like(x0), 0
+    x = x0.copy()
+    r = f - apply_A(st, x)
+    it = 0
+    d = None
+    zr_prev = r_prev = None
+    while np.sqrt(np.sum(r * r)) > tol * fn and it < max_iter:
+        z = precond(r)
+        zr = float(np.sum(z * r))
+        if d is None:
+            d = z.copy()
+        else:
+            beta = float(np.sum(z * (r - r_prev))) / zr_prev
+            d = z + beta * d
+        q = apply_A(st, d)
+        alpha = zr / float(np.sum(d * q))
+        x = x + alpha * d
+        r_prev = r
+        r = r - alpha * q
+        zr_prev = zr
+        it += 1
+    return x, it
+

@@ -6,7 +6,7 @@
 #include <cstdint>
 #include <string>
 
-#include "../../include/ibm.h"
+#include "ibm.h"
 
 namespace ibm {
 
@@ -177,17 +177,27 @@ __device__ inline long long nb_index(const Geo& g, int i, int j, int k, int d, b
     return cidx(g, ii, jj, kk);
 }
 
-// Deterministic block reduction of NV doubles (fixed tree order).
+// Deterministic block reduction of NV doubles over NT threads: butterfly within each
+// wavefront, then the wavefront totals in wavefront order; every thread gets the result.
 template <int NV>
-__device__ inline void block_reduce(double (&v)[NV], double* sh /* NT*NV */) {
-    for (int a = 0; a < NV; ++a) sh[a * NT + threadIdx.x] = v[a];
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int a = 0; a < NV; ++a) sh[a * NT + threadIdx.x] += sh[a * NT + threadIdx.x + s];
-        __syncthreads();
+__device__ inline void block_reduce(double (&v)[NV], double* sh /* at least 4 * NV */) {
+    constexpr int NW = NT / 64;
+    const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+        double x = v[a];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) sh[a * NW + wid] = x;
     }
-    for (int a = 0; a < NV; ++a) v[a] = sh[a * NT];
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += sh[a * NW + w];
+        v[a] = t;
+    }
     __syncthreads();
 }
 

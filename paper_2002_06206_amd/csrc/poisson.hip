@@ -21,6 +21,8 @@
 // Convergence is decided on the device after every update; later sweeps of the
 // batch exit at once.  The host polls between batches.
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace ibm {
@@ -142,14 +144,29 @@ __device__ inline double sum_slot(const double* partials, int slot, int nparts, 
     return v[0];
 }
 
+// sums of K partial slots over nparts blocks in one pass (same order as sum_slot)
+template <int K>
+__device__ inline void sum_slots(const double* partials, const int (&slot)[K], int nparts, double* sh,
+                                 double (&out)[K]) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) out[q] = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += NT) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) out[q] += partials[slot[q] * MAX_BLOCKS + b];
+    }
+    block_reduce<K>(out, sh);
+}
+
 // r_0 = -b + L x_0 (double), stored as T together with z_0 = M^-1 r_0; partials
-// <b,b>, <r_0,r_0> (double), and <r_0,r_0>, <r_0,z_0> of the stored T values.  For the
+// <b,b>, <r_0,r_0> (double), and <r_0,r_0>, <r_0,z_0> of the stored T values (in the
+// RR/RZ slots of iteration parity par).  For the
 // FP64 solve this starts CG on A x = -b; for iterative refinement the stored vector is
 // the right-hand side -(b - L x) of the FP32 correction solve A e = -(b - L x).
 template <class T>
 __global__ void __launch_bounds__(NT) k_pcg_init(Geo g, const uint8_t* __restrict__ pcode,
                                                  const double* __restrict__ b, const double* __restrict__ x,
-                                                 T* __restrict__ r, T* __restrict__ zz, double* __restrict__ partials) {
+                                                 T* __restrict__ r, T* __restrict__ zz, double* __restrict__ partials,
+                                                 int par) {
     __shared__ double sh[4 * NT];
     __shared__ double inv[16];
     const double idx2 = 1.0 / (g.dx * g.dx);
@@ -172,8 +189,8 @@ __global__ void __launch_bounds__(NT) k_pcg_init(Geo g, const uint8_t* __restric
     if (threadIdx.x == 0) {
         partials[SLOT_B2 * MAX_BLOCKS + blockIdx.x] = v[0];
         partials[SLOT_R2D * MAX_BLOCKS + blockIdx.x] = v[1];
-        partials[0 * MAX_BLOCKS + blockIdx.x] = v[2];   // RR[0]
-        partials[2 * MAX_BLOCKS + blockIdx.x] = v[3];   // RZ[0]
+        partials[slot_rr(par) * MAX_BLOCKS + blockIdx.x] = v[2];
+        partials[slot_rz(par) * MAX_BLOCKS + blockIdx.x] = v[3];
     }
 }
 
@@ -224,18 +241,18 @@ template <class T>
 __global__ void __launch_bounds__(NT) k_pcg_a(Geo g, const uint8_t* __restrict__ pcode, const T* __restrict__ zz,
                                               const T* __restrict__ dold, T* __restrict__ dnew, T* __restrict__ x,
                                               double* __restrict__ partials, int nparts, int it, int final_only,
-                                              Solver* sv) {
+                                              int skip_x, Solver* sv) {
     if (sv->converged) return;
     __shared__ double sh[NT];
     const double idx2 = 1.0 / (g.dx * g.dx);
     double alpha = 0.0, beta = 0.0;
     bool stop = final_only != 0;
     if (it > 0) {
-        const double rr = sum_slot(partials, slot_rr(it), nparts, sh);
-        const double rz = sum_slot(partials, slot_rz(it), nparts, sh);
-        const double rzp = sum_slot(partials, slot_rz(it - 1), nparts, sh);
-        const double dq = sum_slot(partials, slot_dq(it - 1), nparts, sh);
-        alpha = rzp / dq;
+        const int sl[4] = {slot_rr(it), slot_rz(it), slot_rz(it - 1), slot_dq(it - 1)};
+        double tot[4];
+        sum_slots<4>(partials, sl, nparts, sh, tot);
+        const double rr = tot[0], rz = tot[1], rzp = tot[2], dq = tot[3];
+        alpha = skip_x ? 0.0 : rzp / dq;
         beta = rz / rzp;
         if (!(rr == rr)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -339,8 +356,10 @@ __global__ void __launch_bounds__(NT) k_pcg_b(Geo g, const uint8_t* __restrict__
     __shared__ double inv[16];
     const double idx2 = 1.0 / (g.dx * g.dx);
     fill_inv(inv, g.dx * g.dx);
-    const double rz = sum_slot(partials, slot_rz(it), nparts, sh);
-    const double dq = sum_slot(partials, slot_dq(it), nparts, sh);
+    const int sl[2] = {slot_rz(it), slot_dq(it)};
+    double tot[2];
+    sum_slots<2>(partials, sl, nparts, sh, tot);
+    const double rz = tot[0], dq = tot[1];
     const double alpha = rz / dq;
     double v[2] = {0.0, 0.0};
     march(g, pcode, d, [&](long long c, uint8_t pc, double xc, double xw, double xe, double xs, double xn,
@@ -420,7 +439,8 @@ template <class T, bool FIRST>
 __global__ void __launch_bounds__(NT) k_pcg_a_v(Geo g, const uint8_t* __restrict__ pcode,
                                                 const T* __restrict__ zz, const T* __restrict__ dold,
                                                 T* __restrict__ dnew, T* __restrict__ x,
-                                                double* __restrict__ partials, int nparts, int it, Solver* sv) {
+                                                double* __restrict__ partials, int nparts, int it, int skip_x,
+                                                Solver* sv) {
     if (sv->converged) return;
     __shared__ double sh[NT];
     __shared__ double pln[2][(TY + 2) * VW];
@@ -428,11 +448,11 @@ __global__ void __launch_bounds__(NT) k_pcg_a_v(Geo g, const uint8_t* __restrict
     double alpha = 0.0, beta = 0.0;
     const long long N = (long long)g.nx * g.ny * g.nz;
     if (!FIRST) {
-        const double rr = sum_slot(partials, slot_rr(it), nparts, sh);
-        const double rz = sum_slot(partials, slot_rz(it), nparts, sh);
-        const double rzp = sum_slot(partials, slot_rz(it - 1), nparts, sh);
-        const double dq = sum_slot(partials, slot_dq(it - 1), nparts, sh);
-        alpha = rzp / dq;
+        const int sl[4] = {slot_rr(it), slot_rz(it), slot_rz(it - 1), slot_dq(it - 1)};
+        double tot[4];
+        sum_slots<4>(partials, sl, nparts, sh, tot);
+        const double rr = tot[0], rz = tot[1], rzp = tot[2], dq = tot[3];
+        alpha = skip_x ? 0.0 : rzp / dq;
         beta = rz / rzp;
         if (!(rr == rr)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -555,8 +575,10 @@ __global__ void __launch_bounds__(NT) k_pcg_b_v(Geo g, const uint8_t* __restrict
     __shared__ double inv[16];
     const double idx2 = 1.0 / (g.dx * g.dx);
     fill_inv(inv, g.dx * g.dx);
-    const double rz = sum_slot(partials, slot_rz(it), nparts, sh);
-    const double dq = sum_slot(partials, slot_dq(it), nparts, sh);
+    const int sl[2] = {slot_rz(it), slot_dq(it)};
+    double tot[2];
+    sum_slots<2>(partials, sl, nparts, sh, tot);
+    const double rz = tot[0], dq = tot[1];
     const double alpha = rz / dq;
     const int ntx2 = (g.nx + VTX - 1) / VTX;
     const int nzc = vslab_count(g.nz);
@@ -607,6 +629,306 @@ __global__ void __launch_bounds__(NT) k_pcg_b_v(Geo g, const uint8_t* __restrict
     }
 }
 
+// ------------------------------------------------------------- FP32 sweeps
+//
+// The correction solve of the mixed path stores and computes in FP32.  Four cells per
+// lane (16-byte loads and stores): a block owns a 256x4 column tile and marches a slab
+// of about 16 planes; pass A shares the new direction of the plane through a
+// double-buffered LDS tile of floats.  Dot products are accumulated in double.
+// Requires nx % 4 == 0 and 16-byte aligned vectors.
+
+constexpr int FTX = 256;               // cells of a tile row (64 lanes x 4)
+constexpr int FW = FTX + 8;            // LDS row: west halo at 3, cells from 4, east halo at FTX + 4
+
+__host__ __device__ inline int fslab_count(int nz) {
+    int want = (nz + 15) / 16;               // about 16 planes per slab
+    want = ((want + 7) / 8) * 8;             // multiple of the XCD count
+    if (want > nz) want = nz;
+    return want < 1 ? 1 : want;
+}
+
+__device__ inline VItem fitem(const Geo& g, long long w, int ntx4, int nzc) {
+    const long long tiles = (long long)ntx4 * g.nty;
+    VItem v;
+    const int zc = (int)(w / tiles);
+    const long long t = w % tiles;
+    v.i0 = (int)(t % ntx4) * FTX;
+    v.j0 = (int)(t / ntx4) * TY;
+    v.i = v.i0 + 4 * (threadIdx.x % 64);
+    v.j = v.j0 + (int)(threadIdx.x / 64);
+    v.z0 = (int)((long long)g.nz * zc / nzc);
+    v.z1 = (int)((long long)g.nz * (zc + 1) / nzc);
+    v.valid = v.i < g.nx && v.j < g.ny;
+    return v;
+}
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 ld4(const float* __restrict__ p, long long c) { return *reinterpret_cast<const f4*>(p + c); }
+__device__ inline void st4nt(float* __restrict__ p, long long c, f4 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p + c));
+}
+// a * x + y per component, one rounding each
+__device__ inline f4 fma4(float a, f4 x, f4 y) {
+    f4 r;
+    r.x = fmaf(a, x.x, y.x);
+    r.y = fmaf(a, x.y, y.y);
+    r.z = fmaf(a, x.z, y.z);
+    r.w = fmaf(a, x.w, y.w);
+    return r;
+}
+__device__ inline float dot4(f4 a, f4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
+
+// (A x)_c = -(L x)_c in float from the code byte
+__device__ inline float aq(unsigned pc, float xc, float xw, float xe, float xs, float xn, float xb, float xt,
+                           float idx2) {
+    float acc = (float)(__builtin_popcount(pc & 0x3Fu) + 2 * (pc >> 6)) * xc;
+    acc -= (pc & 1) ? xw : 0.0f;
+    acc -= (pc & 2) ? xe : 0.0f;
+    acc -= (pc & 4) ? xs : 0.0f;
+    acc -= (pc & 8) ? xn : 0.0f;
+    acc -= (pc & 16) ? xb : 0.0f;
+    acc -= (pc & 32) ? xt : 0.0f;
+    return acc * idx2;
+}
+
+__device__ inline f4 aq4(unsigned pc4, f4 c, float w, float e, f4 s, f4 n, f4 b, f4 t, float idx2) {
+    f4 q;
+    q.x = aq(pc4 & 0xFFu, c.x, w, c.y, s.x, n.x, b.x, t.x, idx2);
+    q.y = aq((pc4 >> 8) & 0xFFu, c.y, c.x, c.z, s.y, n.y, b.y, t.y, idx2);
+    q.z = aq((pc4 >> 16) & 0xFFu, c.z, c.y, c.w, s.z, n.z, b.z, t.z, idx2);
+    q.w = aq(pc4 >> 24, c.w, c.z, e, s.w, n.w, b.w, t.w, idx2);
+    return q;
+}
+
+// Pass A in FP32 (see k_pcg_a for the mathematics).  skip_x: the x update of this pass
+// was already folded into the FP64 solution by a residual replacement.
+template <bool FIRST>
+__global__ void __launch_bounds__(NT) k_pcg_a_f4(Geo g, const uint8_t* __restrict__ pcode,
+                                                 const float* __restrict__ zz, const float* __restrict__ dold,
+                                                 float* __restrict__ dnew, float* __restrict__ x,
+                                                 double* __restrict__ partials, int nparts, int it, int skip_x,
+                                                 Solver* sv) {
+    if (sv->converged) return;
+    __shared__ double sh[NT];
+    __shared__ __attribute__((aligned(16))) float pln[2][(TY + 2) * FW];
+    const float idx2 = (float)(1.0 / (g.dx * g.dx));
+    double alpha = 0.0, beta = 0.0;
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    if (!FIRST) {
+        const int sl[4] = {slot_rr(it), slot_rz(it), slot_rz(it - 1), slot_dq(it - 1)};
+        double tot[4];
+        sum_slots<4>(partials, sl, nparts, sh, tot);
+        const double rr = tot[0], rz = tot[1], rzp = tot[2], dq = tot[3];
+        alpha = skip_x ? 0.0 : rzp / dq;
+        beta = rz / rzp;
+        if (!(rr == rr)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sv->nan_seen = 1;
+                sv->converged = 3;
+                sv->iters = it;
+            }
+            return;
+        }
+        const bool stop = rr <= sv->tol2;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sv->rr = rr;
+            sv->iters = it;
+            if (stop) sv->converged = 1;
+        }
+        if (stop) {
+            if (!skip_x) {
+                const float af = (float)alpha;
+                for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+                     c += (long long)gridDim.x * blockDim.x)
+                    x[c] = fmaf(af, dold[c], x[c]);
+            }
+            return;
+        }
+    }
+    const float af = (float)alpha, bf = (float)beta;
+    const bool upd_x = !FIRST && !skip_x;
+    auto dn1 = [&](long long c) -> float { return FIRST ? zz[c] : fmaf(bf, dold[c], zz[c]); };
+    auto dn4 = [&](long long c) -> f4 { return FIRST ? ld4(zz, c) : fma4(bf, ld4(dold, c), ld4(zz, c)); };
+    const int ntx4 = (g.nx + FTX - 1) / FTX;
+    const int nzc = fslab_count(g.nz);
+    const long long items = (long long)ntx4 * g.nty * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
+    const int lane = threadIdx.x % 64, lj = threadIdx.x / 64;
+    const int li = 4 * lane;
+    double v = 0.0;
+    int buf = 0;
+    const f4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (long long w = w0; w < w1; ++w) {
+        const VItem it_ = fitem(g, w, ntx4, nzc);
+        const int i = it_.i, j = it_.j;
+        // last valid lane and row of the tile own the east / north halo
+        const int lane_max = min(63, (g.nx - it_.i0) / 4 - 1);
+        const int row_max = min(TY - 1, g.ny - it_.j0 - 1);
+        const int iw = it_.i0 == 0 ? g.nx - 1 : it_.i0 - 1;
+        const int ie = i + 4 >= g.nx ? 0 : i + 4;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j >= g.ny - 1 ? 0 : j + 1;
+        const long long col = it_.valid ? (long long)i + (long long)g.nx * j : 0;
+        const int zb = it_.z0 == 0 ? g.nz - 1 : it_.z0 - 1;
+        f4 db = zero4, dc = zero4, oc = zero4;
+        if (it_.valid) {
+            db = dn4(col + plane * zb);
+            const f4 zc4 = ld4(zz, col + plane * it_.z0);
+            if (!FIRST) oc = ld4(dold, col + plane * it_.z0);
+            dc = FIRST ? zc4 : fma4(bf, oc, zc4);
+        }
+        for (int k = it_.z0; k < it_.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            float* P = pln[buf];
+            f4 dt = zero4, ot = zero4;
+            if (it_.valid) {
+                const long long ct = col + plane * zt;
+                const f4 zt4 = ld4(zz, ct);
+                if (!FIRST) ot = ld4(dold, ct);
+                dt = FIRST ? zt4 : fma4(bf, ot, zt4);
+                *reinterpret_cast<f4*>(&P[(lj + 1) * FW + 4 + li]) = dc;
+                const long long pk = plane * k;
+                if (lane == 0) P[(lj + 1) * FW + 3] = dn1((long long)iw + (long long)g.nx * j + pk);
+                if (lane == lane_max) P[(lj + 1) * FW + 8 + li] = dn1((long long)ie + (long long)g.nx * j + pk);
+                if (lj == 0) *reinterpret_cast<f4*>(&P[4 + li]) = dn4((long long)i + (long long)g.nx * js + pk);
+                if (lj == row_max)
+                    *reinterpret_cast<f4*>(&P[(lj + 2) * FW + 4 + li]) =
+                        dn4((long long)i + (long long)g.nx * jn + pk);
+            }
+            __syncthreads();
+            if (it_.valid) {
+                const long long c = col + plane * k;
+                const float w_ = P[(lj + 1) * FW + 3 + li], e_ = P[(lj + 1) * FW + 8 + li];
+                const f4 s4 = *reinterpret_cast<const f4*>(&P[lj * FW + 4 + li]);
+                const f4 n4 = *reinterpret_cast<const f4*>(&P[(lj + 2) * FW + 4 + li]);
+                const unsigned pc4 = *reinterpret_cast<const unsigned*>(pcode + c);
+                const f4 q = aq4(pc4, dc, w_, e_, s4, n4, db, dt, idx2);
+                if (upd_x) st4nt(x, c, fma4(af, oc, ld4(x, c)));
+                st4nt(dnew, c, dc);
+                v += (double)dot4(dc, q);
+            }
+            db = dc;
+            dc = dt;
+            oc = ot;
+            buf ^= 1;
+        }
+    }
+    double vv[1] = {v};
+    block_reduce<1>(vv, sh);
+    if (threadIdx.x == 0) partials[slot_dq(it) * MAX_BLOCKS + blockIdx.x] = vv[0];
+}
+
+// Pass B in FP32: r_{it+1} = r_it - alpha A d_it, z = M^-1 r; partials.
+__global__ void __launch_bounds__(NT) k_pcg_b_f4(Geo g, const uint8_t* __restrict__ pcode,
+                                                 const float* __restrict__ d, float* __restrict__ r,
+                                                 float* __restrict__ zz, double* __restrict__ partials, int nparts,
+                                                 int it, const Solver* sv) {
+    if (sv->converged) return;
+    __shared__ double sh[2 * NT];
+    __shared__ float invf[16];
+    const double dx2 = g.dx * g.dx;
+    const float idx2 = (float)(1.0 / dx2);
+    if (threadIdx.x < 16) invf[threadIdx.x] = threadIdx.x ? (float)(dx2 / (double)threadIdx.x) : 0.0f;
+    __syncthreads();
+    const int sl[2] = {slot_rz(it), slot_dq(it)};
+    double tot[2];
+    sum_slots<2>(partials, sl, nparts, sh, tot);
+    const double rz = tot[0], dq = tot[1];
+    const float af = (float)(rz / dq);
+    const int ntx4 = (g.nx + FTX - 1) / FTX;
+    const int nzc = fslab_count(g.nz);
+    const long long items = (long long)ntx4 * g.nty * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
+    double v[2] = {0.0, 0.0};
+    for (long long w = w0; w < w1; ++w) {
+        const VItem it_ = fitem(g, w, ntx4, nzc);
+        if (!it_.valid) continue;
+        const int i = it_.i, j = it_.j;
+        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i + 4 >= g.nx ? 0 : i + 4;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+        const long long col = (long long)i + (long long)g.nx * j;
+        const long long ow = (long long)iw + (long long)g.nx * j - col;
+        const long long oe = (long long)ie + (long long)g.nx * j - col;
+        const long long os = (long long)i + (long long)g.nx * js - col;
+        const long long on = (long long)i + (long long)g.nx * jn - col;
+        const int zb = it_.z0 == 0 ? g.nz - 1 : it_.z0 - 1;
+        f4 xb = ld4(d, col + plane * zb);
+        f4 xc = ld4(d, col + plane * it_.z0);
+        for (int k = it_.z0; k < it_.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = col + plane * k;
+            const f4 xt = ld4(d, col + plane * zt);
+            const f4 xs = ld4(d, c + os), xn = ld4(d, c + on);
+            const float xw = d[c + ow], xe = d[c + oe];
+            const unsigned pc4 = *reinterpret_cast<const unsigned*>(pcode + c);
+            const f4 q = aq4(pc4, xc, xw, xe, xs, xn, xb, xt, idx2);
+            const f4 rn = fma4(-af, q, ld4(r, c));
+            f4 z;
+            z.x = invf[jcount((uint8_t)(pc4 & 0xFFu))] * rn.x;
+            z.y = invf[jcount((uint8_t)((pc4 >> 8) & 0xFFu))] * rn.y;
+            z.z = invf[jcount((uint8_t)((pc4 >> 16) & 0xFFu))] * rn.z;
+            z.w = invf[jcount((uint8_t)(pc4 >> 24))] * rn.w;
+            st4nt(r, c, rn);
+            st4nt(zz, c, z);
+            v[0] += (double)dot4(rn, rn);
+            v[1] += (double)dot4(rn, z);
+            xb = xc;
+            xc = xt;
+        }
+    }
+    block_reduce<2>(v, sh);
+    if (threadIdx.x == 0) {
+        partials[slot_rr(it + 1) * MAX_BLOCKS + blockIdx.x] = v[0];
+        partials[slot_rz(it + 1) * MAX_BLOCKS + blockIdx.x] = v[1];
+    }
+}
+
+// One block: totals after a residual replacement (an init sweep with parity it) ->
+// solver state of the next FP32 segment, which stops once its recursive <r,r> falls
+// below max(delta^2 <r,r>, (eta_tol)^2 <b,b>).  The host judges the FP64 residual.
+__global__ void __launch_bounds__(NT) k_seg_start(const double* partials, int nparts, Solver* sv, int it,
+                                                  double delta, double eta_tol) {
+    __shared__ double sh[4 * NT];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += NT) {
+        v[0] += partials[SLOT_B2 * MAX_BLOCKS + b];
+        v[1] += partials[SLOT_R2D * MAX_BLOCKS + b];
+        v[2] += partials[slot_rr(it) * MAX_BLOCKS + b];
+        v[3] += partials[slot_rz(it) * MAX_BLOCKS + b];
+    }
+    block_reduce<4>(v, sh);
+    if (threadIdx.x == 0) {
+        sv->bnorm2 = v[0];
+        sv->r64norm2 = v[1];
+        sv->fnorm2 = v[1];
+        sv->rr = v[2];
+        sv->rz = v[3];
+        sv->iters = it;
+        sv->nan_seen = 0;
+        sv->tol2 = fmax(delta * delta * v[2], eta_tol * eta_tol * v[0]);
+        if (!(v[0] == v[0]) || !(v[1] == v[1]) || !(v[2] == v[2]) || !(v[3] == v[3])) {
+            sv->nan_seen = 1;
+            sv->converged = 3;
+        } else {
+            sv->converged = v[0] == 0.0 ? 2 : 0;
+        }
+    }
+}
+
+// x += e (FP64 += FP32), e = 0
+__global__ void k_accum_zero(long long n, double* __restrict__ x, float* __restrict__ e) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        x[i] = x[i] + (double)e[i];
+        e[i] = 0.0f;
+    }
+}
+
 // partials of ||b - L x||^2 and ||b||^2
 __global__ void __launch_bounds__(NT) k_resid(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ b, const double* __restrict__ x,
                                               double* __restrict__ partials) {
@@ -652,6 +974,11 @@ __global__ void __launch_bounds__(NT) k_lap(Geo g, const uint8_t* __restrict__ p
 // blocks of the z-marching sweeps: one per (tile, slab) item up to the partial capacity
 int march_blocks(const Geo& g) {
     long long items = (long long)g.ntx * g.nty * slab_count(g.nz);
+    return (int)(items < MAX_BLOCKS ? items : MAX_BLOCKS);
+}
+
+static int fmarch_blocks(const Geo& g) {
+    long long items = (long long)((g.nx + FTX - 1) / FTX) * g.nty * fslab_count(g.nz);
     return (int)(items < MAX_BLOCKS ? items : MAX_BLOCKS);
 }
 
@@ -704,30 +1031,52 @@ int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hip
     return IBM_OK;
 }
 
-// Conjugate-gradient iterations after an init + start pair; vectors of type T.
-// Returns the device flag (0 not converged at the cap, 1 converged, 2 trivial, 3 NaN).
+// Conjugate-gradient iterations from iteration start_it (0: after an init + start
+// pair; otherwise after a residual replacement, whose first pass A skips the x update);
+// vectors of type T.  path: 0 scalar sweeps, 1 pairs of cells per lane, 2 (float
+// only) four cells per lane.  Sets *done to the iterations made.  Returns the device
+// flag (0 not converged at the cap, 1 converged, 2 trivial, 3 NaN).
 template <class T>
-static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, bool vec, int nred, int max_iter, int check_every,
-                   int* last_iters, int* iters, hipStream_t s) {
+static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nred, int start_it, int max_iter,
+                   int check_every, int* last_iters, int* done, hipStream_t s) {
     const Geo& g = c->geo;
     T* dbuf[2] = {d0, d1};
     auto pass_a = [&](int it) {
         T* dnew = dbuf[it & 1];
         T* dold = dbuf[(it + 1) & 1];
-        if (vec) {
+        const int skip = (start_it > 0 && it == start_it) ? 1 : 0;
+        if constexpr (std::is_same<T, float>::value) {
+            if (path == 2) {
+                if (it == 0)
+                    k_pcg_a_f4<true><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, 0,
+                                                         c->solver);
+                else
+                    k_pcg_a_f4<false><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it,
+                                                          skip, c->solver);
+                return;
+            }
+        }
+        if (path == 1) {
             if (it == 0)
-                k_pcg_a_v<T, true><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it,
+                k_pcg_a_v<T, true><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, 0,
                                                        c->solver);
             else
-                k_pcg_a_v<T, false><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it,
+                k_pcg_a_v<T, false><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, skip,
                                                         c->solver);
         } else {
-            k_pcg_a<T><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, 0, c->solver);
+            k_pcg_a<T><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, 0, skip,
+                                           c->solver);
         }
     };
     auto pass_b = [&](int it) {
         T* dnew = dbuf[it & 1];
-        if (vec)
+        if constexpr (std::is_same<T, float>::value) {
+            if (path == 2) {
+                k_pcg_b_f4<<<nred, NT, 0, s>>>(g, c->pcode, dnew, r, z, c->partials, nred, it, c->solver);
+                return;
+            }
+        }
+        if (path == 1)
             k_pcg_b_v<T><<<nred, NT, 0, s>>>(g, c->pcode, dnew, r, z, c->partials, nred, it, c->solver);
         else
             k_pcg_b<T><<<nred, NT, 0, s>>>(g, c->pcode, dnew, r, z, c->partials, nred, it, c->solver);
@@ -740,7 +1089,7 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, bool vec, int nre
         int n = batch;
         if (n > max_iter - total) n = max_iter - total;
         for (int k = 0; k < n; ++k) {
-            const int it = total + k;
+            const int it = start_it + total + k;
             timing_begin(c, TK_SPMV, s);
             pass_a(it);
             timing_end(c, TK_SPMV, s);
@@ -751,9 +1100,9 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, bool vec, int nre
         IBM_HIP(hipGetLastError());
         total += n;
         if (total >= max_iter) {
-            // at the cap, one more pass A tests r_total and applies the last x update
-            // (when not converged it also starts a direction that is never used)
-            pass_a(total);
+            // at the cap, one more pass A tests r and applies the last x update (when not
+            // converged it also starts a direction that a later segment recomputes)
+            pass_a(start_it + total);
             IBM_HIP(hipGetLastError());
         }
         // otherwise a residual that converged in the last pass B is detected by the
@@ -763,10 +1112,12 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, bool vec, int nre
         if (c->h_solver->converged || total >= max_iter) break;
         batch = check_every;
     }
-    *iters = c->h_solver->iters;
-    *last_iters = c->h_solver->iters;
+    int made = c->h_solver->iters - start_it;
+    if (made < 0) made = 0;
+    *done = made;
+    *last_iters = made;
     timing_collect(c);
-    if (c->timing_on) c->t_real_iters += c->h_solver->iters;
+    if (c->timing_on) c->t_real_iters += made;
     return c->h_solver->converged;
 }
 
@@ -782,12 +1133,12 @@ int pcg64(ibm_ctx* c, const double* b, double* x, double tol, int max_iter, int 
     // blocks (the init sweep runs with the same count), so all partial sums agree
     const bool vec = vec_ok(g, x, 16);
     const int nred = vec ? vmarch_blocks(g) : march_blocks(g);
-    k_pcg_init<double><<<nred, NT, 0, s>>>(g, c->pcode, b, x, c->r, c->zbuf, c->partials);
+    k_pcg_init<double><<<nred, NT, 0, s>>>(g, c->pcode, b, x, c->r, c->zbuf, c->partials, 0);
     k_pcg_start<<<1, NT, 0, s>>>(c->partials, nred, c->solver, tol, SLOT_B2);
     k_zero_if_trivial<<<1024, 256, 0, s>>>(c->N, x, c->solver);
     IBM_HIP(hipGetLastError());
-    int flag = cg_loop<double>(c, x, c->r, c->zbuf, c->d, c->q, vec, nred, max_iter, check_every, &c->last_iters,
-                               iters, s);
+    int flag = cg_loop<double>(c, x, c->r, c->zbuf, c->d, c->q, vec ? 1 : 0, nred, 0, max_iter, check_every,
+                               &c->last_iters, iters, s);
     if (flag < 0) return flag;
     if (flag == 3) {
         set_error("pressure solve: non-finite residual");
@@ -806,38 +1157,42 @@ __global__ void k_zero_f64(long long n, double* __restrict__ x) {
         x[i] = 0.0;
 }
 
-__global__ void k_accumulate(long long n, double* __restrict__ x, const float* __restrict__ e) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        x[i] = x[i] + (double)e[i];
-}
-
-// Mixed precision: FP64 iterative refinement around an FP32 Jacobi-CG correction solve.
-// Each sweep: r64 = b - L x in FP64 (the judge), stored as the FP32 right-hand side of
-// A e = -r64; FP32 CG to inner_tol relative to ||r64||; x += e in FP64.  Stops when
-// ||r64|| <= tol ||b||.  A sweep that shrinks ||r64|| by less than stall_factor, a
-// non-finite value, too many sweeps, or the force_stall hook hand the solve to FP64
-// PCG from the current x.
+// Mixed precision: FP32 Jacobi-CG on the correction equation, wrapped in FP64
+// iterative refinement with residual replacement.  The FP64 residual r64 = b - L x (the
+// judge) is rounded to FP32 and CG runs on A e = -r64 until its recursive residual has
+// fallen by inner_tol (or below eta tol ||b||); then x += e in FP64, e = 0, and r64 is
+// recomputed and replaces the FP32 residual.  CG continues with its search direction
+// instead of restarting, so the Krylov information of earlier segments is kept.  Stops
+// when ||r64|| <= tol ||b||.  A segment that shrinks ||r64|| by less than stall_factor,
+// a non-finite value, too many segments, or the force_stall hook hand the solve to
+// FP64 PCG from the current x.
 int mixed_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {
     const Geo& g = c->geo;
     const long long N = c->N;
-    const bool vec = vec_ok(g, c->r32, 8);
-    const int nred = vec ? vmarch_blocks(g) : march_blocks(g);
-    const double inner_tol = o->inner_tol > 0.0 ? o->inner_tol : 1e-3;
+    const bool quad = (g.nx % 4) == 0 && ((uintptr_t)c->r32 % 16) == 0 && ((uintptr_t)c->z32 % 16) == 0 &&
+                      ((uintptr_t)c->e32 % 16) == 0 && ((uintptr_t)c->d32 % 16) == 0 &&
+                      ((uintptr_t)c->q32 % 16) == 0;
+    const bool pair = vec_ok(g, c->r32, 8);
+    const int path = quad ? 2 : (pair ? 1 : 0);
+    const int nred = quad ? fmarch_blocks(g) : (pair ? vmarch_blocks(g) : march_blocks(g));
+    const double delta = (o->inner_tol > 0.0 && o->inner_tol < 1.0) ? o->inner_tol : 0.1;
     const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : 1000;
     const double stall = o->stall_factor > 1.0 ? o->stall_factor : 2.0;
-    int total_inner = 0, sweeps = 0;
+    const double eta_tol = 0.25 * o->tol;   // last segment aims below tol, leaving room for FP32 drift
+    const int max_sweeps = 200;
+    int total_inner = 0, sweeps = 0, it = 0;
     double prev_rel = -1.0;
     bool fallback = false;
     int rc = IBM_OK;
-    const int max_sweeps = 60;
+    k_zero_f32<<<2048, 256, 0, s>>>(N, c->e32);
+    k_pcg_init<float><<<nred, NT, 0, s>>>(g, c->pcode, b, x, c->r32, c->z32, c->partials, 0);
+    k_seg_start<<<1, NT, 0, s>>>(c->partials, nred, c->solver, 0, delta, eta_tol);
+    IBM_HIP(hipGetLastError());
     while (true) {
-        k_pcg_init<float><<<nred, NT, 0, s>>>(g, c->pcode, b, x, c->r32, c->z32, c->partials);
-        k_pcg_start<<<1, NT, 0, s>>>(c->partials, nred, c->solver, inner_tol, SLOT_R2D);
-        IBM_HIP(hipGetLastError());
         IBM_HIP(hipMemcpyAsync(c->h_solver, c->solver, sizeof(Solver), hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
         const double bn2 = c->h_solver->bnorm2, rn2 = c->h_solver->r64norm2;
-        if (bn2 == 0.0) {
+        if (bn2 == 0.0 && c->h_solver->converged != 3) {
             k_zero_f64<<<2048, 256, 0, s>>>(N, x);   // b = 0: x = 0 (zero mean on enclosed components)
             IBM_HIP(hipGetLastError());
             break;
@@ -857,18 +1212,20 @@ int mixed_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
             break;
         }
         prev_rel = rel;
-        k_zero_f32<<<2048, 256, 0, s>>>(N, c->e32);
-        int it = 0;
-        int flag = cg_loop<float>(c, c->e32, c->r32, c->z32, c->d32, c->q32, vec, nred, inner_max, o->check_every,
-                                  &c->last_iters_inner, &it, s);
+        int made = 0;
+        int flag = cg_loop<float>(c, c->e32, c->r32, c->z32, c->d32, c->q32, path, nred, it, inner_max,
+                                  o->check_every, &c->last_iters_inner, &made, s);
         if (flag < 0) return flag;
-        total_inner += it;
+        total_inner += made;
+        it += made;
         sweeps += 1;
         if (flag == 3) {
             fallback = true;
             break;
         }
-        k_accumulate<<<2048, 256, 0, s>>>(N, x, c->e32);
+        k_accum_zero<<<2048, 256, 0, s>>>(N, x, c->e32);
+        k_pcg_init<float><<<nred, NT, 0, s>>>(g, c->pcode, b, x, c->r32, c->z32, c->partials, it);
+        k_seg_start<<<1, NT, 0, s>>>(c->partials, nred, c->solver, it, delta, eta_tol);
         IBM_HIP(hipGetLastError());
     }
     int fb_iters = 0;

@@ -356,3 +356,23 @@ def channel_planes(y_lo: float, y_hi: float, lo: float, hi: float) -> np.ndarray
 def random_field(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.ascontiguousarray(rng.standard_normal(shape) * scale)
+
+
+# ------------------------------------------------------------------ learned preconditioner
+
+CNN_LAYERS = ((2, 16), (16, 16), (16, 16), (16, 1))
+
+
+def cnn_init_weights(seed: int, last_scale: float = 0.1) -> np.ndarray:
+    """Seeded He-normal initial weights (std sqrt(2 / fan_in), fan_in = 27 ci) of the
+    four 3x3x3 layers, flat float32 in the layout w[t, ci, co] per layer, layers in
+    order.  The last layer is scaled down so that the untrained network is a small
+    perturbation."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l, (ci, co) in enumerate(CNN_LAYERS):
+        w = rng.standard_normal((27, ci, co)) * math.sqrt(2.0 / (27 * ci))
+        if l == len(CNN_LAYERS) - 1:
+            w *= last_scale
+        parts.append(w.reshape(-1))
+    return np.ascontiguousarray(np.concatenate(parts).astype(np.float32))
