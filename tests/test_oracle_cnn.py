@@ -1,0 +1,265 @@
+"""Pins for the CNN-preconditioner oracle (oracle/cnn.py) against library routines
+(scipy's n-d correlation, torch's bfloat16 conversion, scipy's scalar minimiser, a
+dense solve), brute-force loops, adjoint identities, finite differences and the
+closed forms of Adam and conjugate gradients.
+"""
+import numpy as np
+import pytest
+import scipy.ndimage
+import scipy.optimize
+import torch
+
+from oracle import cnn, flow, tagging
+from paper_2002_06206_amd import inputs
+
+P, I, O, S = flow.PERIODIC, flow.INFLOW, flow.OUTFLOW, flow.SLIP
+
+
+# ------------------------------------------------------------------ bf16
+
+def test_bf16_round_matches_torch_including_ties():
+    rng = np.random.default_rng(0)
+    a = (rng.standard_normal(20000) * np.exp(rng.uniform(-30, 30, 20000))).astype(np.float32)
+    # exact ties: low 16 bits = 0x8000, both parities of the kept part
+    u = rng.integers(0x00800000, 0x7F000000, 4000, dtype=np.uint32)
+    ties = ((u & 0xFFFF0000) | 0x8000).view(np.float32)
+    a = np.concatenate([a, ties, -ties, np.float32([0.0, -0.0, 1.0, 3.0e38])])
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(cnn.bf16_round(a), ref)
+
+
+def test_bf16_round_closed_forms():
+    # bfloat16 keeps 7 fraction bits: the spacing at 1 is 2^-7
+    assert cnn.bf16_round(np.array([1.0 + 2.0 ** -8]))[0] == 1.0                    # tie -> even
+    assert cnn.bf16_round(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6    # tie -> even (up)
+    assert cnn.bf16_round(np.array([1.0 + 2.0 ** -8 + 2.0 ** -12]))[0] == 1.0 + 2.0 ** -7
+    assert np.isnan(cnn.bf16_round(np.array([np.nan]))[0])
+
+
+# ------------------------------------------------------------------ convolution
+
+def test_conv_forward_matches_scipy_correlate():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((5, 6, 7, 3))
+    w = rng.standard_normal((27, 3, 2))
+    y = cnn.conv_forward(x, w)
+    for co in range(2):
+        ref = np.zeros(x.shape[:3])
+        for ci in range(3):
+            k = w[:, ci, co].reshape(3, 3, 3)     # [dz+1, dy+1, dx+1]
+            ref += scipy.ndimage.correlate(x[..., ci], k, mode="constant", cval=0.0)
+        np.testing.assert_allclose(y[..., co], ref, rtol=0, atol=1e-12)
+
+
+def test_conv_forward_brute_force_loops():
+    rng = np.random.default_rng(2)
+    nz, ny, nx = 3, 4, 5
+    x = rng.standard_normal((nz, ny, nx, 2))
+    w = rng.standard_normal((27, 2, 3))
+    y = cnn.conv_forward(x, w)
+    for z in range(nz):
+        for yy in range(ny):
+            for xx in range(nx):
+                for co in range(3):
+                    acc = 0.0
+                    for dz in (-1, 0, 1):
+                        for dy in (-1, 0, 1):
+                            for dx in (-1, 0, 1):
+                                zz, y2, x2 = z + dz, yy + dy, xx + dx
+                                if 0 <= zz < nz and 0 <= y2 < ny and 0 <= x2 < nx:
+                                    t = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
+                                    for ci in range(2):
+                                        acc += x[zz, y2, x2, ci] * w[t, ci, co]
+                    assert abs(y[z, yy, xx, co] - acc) < 1e-12
+
+
+def test_conv_backward_adjoint_identities():
+    """conv_forward is bilinear in (x, w); its two backward maps are the adjoints:
+    <conv(x, w), g> = <x, bwd_data(g, w)> = <w, bwd_weight(x, g)>."""
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((4, 5, 6, 16))
+    w = rng.standard_normal((27, 16, 4))
+    g = rng.standard_normal((4, 5, 6, 4))
+    lhs = np.sum(cnn.conv_forward(x, w) * g)
+    assert abs(lhs - np.sum(x * cnn.conv_backward_data(g, w))) < 1e-9 * abs(lhs)
+    assert abs(lhs - np.sum(w * cnn.conv_backward_weight(x, g))) < 1e-9 * abs(lhs)
+
+
+def test_network_backward_matches_finite_differences():
+    rng = np.random.default_rng(4)
+    x0 = rng.standard_normal((4, 5, 6, 2))
+    ws = cnn.split_weights(inputs.cnn_init_weights(7, last_scale=1.0).astype(np.float64))
+    R = rng.standard_normal((4, 5, 6))
+
+    def J(ws_, x_):
+        y, _ = cnn.forward(x_, ws_)
+        return float(np.sum(y * R))
+
+    y, acts = cnn.forward(x0, ws)
+    dws, dx0 = cnn.backward(acts, ws, R)
+    h = 1e-6
+    for l in range(4):
+        for _ in range(6):
+            idx = tuple(rng.integers(0, s) for s in ws[l].shape)
+            wp = [w.copy() for w in ws]
+            wm = [w.copy() for w in ws]
+            wp[l][idx] += h
+            wm[l][idx] -= h
+            fd = (J(wp, x0) - J(wm, x0)) / (2 * h)
+            assert abs(fd - dws[l][idx]) < 1e-6 * max(1.0, abs(fd)), (l, idx, fd, dws[l][idx])
+    for _ in range(6):
+        idx = tuple(rng.integers(0, s) for s in x0.shape)
+        xp, xm = x0.copy(), x0.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (J(ws, xp) - J(ws, xm)) / (2 * h)
+        assert abs(fd - dx0[idx]) < 1e-6 * max(1.0, abs(fd))
+
+
+def test_network_is_positively_homogeneous_without_geometry():
+    """No biases and ReLU: net(c x) = c net(x) for c > 0."""
+    rng = np.random.default_rng(5)
+    x0 = rng.standard_normal((3, 4, 5, 2))
+    ws = cnn.split_weights(inputs.cnn_init_weights(1).astype(np.float64))
+    y1, _ = cnn.forward(x0, ws)
+    y2, _ = cnn.forward(3.5 * x0, ws)
+    np.testing.assert_allclose(y2, 3.5 * y1, rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------------------------------ preconditioner and loss
+
+def _plate_stencil(n=(10, 8, 6), seed=0):
+    """Open geometry (a plate) with an outlet: A is nonsingular."""
+    g = flow.Grid(n, 1.0, (0.0, 0.0, 0.0), (I, O, S, S, S, S))
+    tri = inputs.rectangle((4.4, 3.7, 2.9), (0, 4.0, 0.7), (0.5, 0, 3.0))
+    b, th = tagging.tag(tri, g.n, g.dx, g.origin)
+    return g, flow.build_stencils(g, b, th)
+
+
+def _dense_A(st):
+    g = st.grid
+    N = g.ncell
+    A = np.zeros((N, N))
+    e = np.zeros(N)
+    for j in range(N):
+        e[j] = 1.0
+        A[:, j] = cnn.apply_A(st, e.reshape(g.shape)).ravel()
+        e[j] = 0.0
+    return A
+
+
+def test_geometry_channel_closed_form():
+    g = flow.Grid((4, 5, 6), 1.0, (0.0, 0.0, 0.0), (P,) * 6)
+    st = flow.build_stencils(g, *(np.zeros(g.shape, np.uint8), np.full(g.shape + (6,), 2.0)))
+    assert np.all(cnn.geometry_channel(st) == 1.0)
+    g = flow.Grid((4, 5, 6), 1.0, (0.0, 0.0, 0.0), (S,) * 6)
+    st = flow.build_stencils(g, *(np.zeros(g.shape, np.uint8), np.full(g.shape + (6,), 2.0)))
+    gc = cnn.geometry_channel(st)
+    assert gc[0, 0, 0] == 3.0 / 6.0 and gc[2, 2, 1] == 1.0 and gc[0, 2, 2] == 5.0 / 6.0
+
+
+def test_zero_weights_give_jacobi():
+    g, st = _plate_stencil()
+    r = np.random.default_rng(6).standard_normal(g.shape)
+    ws = [np.zeros((27, ci, co)) for ci, co in cnn.LAYERS]
+    z = cnn.precondition(st, r, ws)
+    np.testing.assert_allclose(z, r / flow.jacobi_diag(st), rtol=1e-15)
+
+
+def test_loss_is_the_minimum_energy_distance():
+    """loss = min_a |p - a p_hat|_A^2 / |p|_A^2, checked with a dense solve for p and a
+    scalar minimiser for a."""
+    g, st = _plate_stencil()
+    A = _dense_A(st)
+    assert np.allclose(A, A.T)
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(g.shape)
+    p = np.linalg.solve(A, -b.ravel()).reshape(g.shape)        # L p = b  <=>  A p = -b
+    ws = cnn.split_weights(inputs.cnn_init_weights(3, last_scale=0.5).astype(np.float64))
+    ph = cnn.precondition(st, -b, ws)
+    pA = p.ravel() @ A @ p.ravel()
+
+    def E(a):
+        e = p.ravel() - a * ph.ravel()
+        return e @ A @ e / pA
+
+    res = scipy.optimize.minimize_scalar(E, bracket=(0.0, 1.0), tol=1e-12)
+    loss = cnn.loss_only(st, b, p, ws)
+    assert 0.0 < loss < 1.0
+    assert abs(loss - res.fun) < 1e-10
+
+
+def test_loss_scale_invariance():
+    g, st = _plate_stencil()
+    A = _dense_A(st)
+    rng = np.random.default_rng(9)
+    b = rng.standard_normal(g.shape)
+    p = np.linalg.solve(A, -b.ravel()).reshape(g.shape)
+    ws = cnn.split_weights(inputs.cnn_init_weights(4).astype(np.float64))
+    l1 = cnn.loss_only(st, b, p, ws)
+    l2 = cnn.loss_only(st, 1e-3 * b, 1e-3 * p, ws)
+    assert abs(l1 - l2) < 1e-12
+
+
+def test_loss_gradient_matches_finite_differences():
+    g, st = _plate_stencil()
+    A = _dense_A(st)
+    rng = np.random.default_rng(10)
+    b = rng.standard_normal(g.shape)
+    p = np.linalg.solve(A, -b.ravel()).reshape(g.shape)
+    ws = cnn.split_weights(inputs.cnn_init_weights(5, last_scale=1.0).astype(np.float64))
+    loss, dws = cnn.loss_and_grad(st, b, p, ws)
+    assert abs(loss - cnn.loss_only(st, b, p, ws)) < 1e-14
+    h = 1e-6
+    for l in range(4):
+        for _ in range(5):
+            idx = tuple(rng.integers(0, s) for s in ws[l].shape)
+            wp = [w.copy() for w in ws]
+            wm = [w.copy() for w in ws]
+            wp[l][idx] += h
+            wm[l][idx] -= h
+            fd = (cnn.loss_only(st, b, p, wp) - cnn.loss_only(st, b, p, wm)) / (2 * h)
+            assert abs(fd - dws[l][idx]) < 1e-6 * max(1e-3, abs(fd)), (l, idx, fd, dws[l][idx])
+
+
+def test_adam_first_steps_closed_form():
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    w0 = np.array([1.0, 2.0, 3.0, 4.0])
+    m = np.zeros(4)
+    v = np.zeros(4)
+    w1, m, v = cnn.adam(w0, g, m, v, 1, 0.01)
+    # first step: m_hat = g, v_hat = g^2, so the step is lr g / (|g| + eps)
+    np.testing.assert_allclose(w1, w0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-14)
+    # second step with the same gradient: bias corrections make m_hat = g, v_hat = g^2 again
+    w2, m, v = cnn.adam(w1, g, m, v, 2, 0.01)
+    np.testing.assert_allclose(w2, w1 - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# ------------------------------------------------------------------ flexible CG
+
+def test_fcg_with_jacobi_equals_pcg():
+    """With a fixed symmetric positive definite preconditioner the Polak-Ribiere beta
+    equals the Fletcher-Reeves one (r_k is orthogonal to z_{k-1} = M^-1 r_{k-1}), so
+    FCG(1) reproduces Jacobi-PCG."""
+    g, st = _plate_stencil()
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(g.shape)
+    minv = cnn.jacobi_inverse(st)
+    x1, it1 = cnn.fcg(st, b, np.zeros(g.shape), lambda r: minv * r, 1e-10, 500)
+    x2, it2 = flow.pcg(st, b, np.zeros(g.shape), 1e-10, 500)
+    assert abs(it1 - it2) <= 1
+    assert np.max(np.abs(x1 - x2)) < 1e-7 * np.max(np.abs(x2))
+
+
+def test_fcg_with_nonlinear_preconditioner_solves():
+    g, st = _plate_stencil()
+    A = _dense_A(st)
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal(g.shape)
+    p = np.linalg.solve(A, -b.ravel()).reshape(g.shape)
+    # a perturbation of Jacobi, as the trained network is: FCG(1) converges for
+    # preconditioners close to a fixed symmetric positive definite one
+    ws = cnn.split_weights(inputs.cnn_init_weights(6, last_scale=0.02).astype(np.float64))
+    x, it = cnn.fcg(st, b, np.zeros(g.shape), lambda r: cnn.precondition(st, r, ws), 1e-10, 500)
+    assert it > 3
+    assert np.max(np.abs(x - p)) < 1e-7 * np.max(np.abs(p))
