@@ -40,6 +40,9 @@ SWEEP_BYTES_F32 = {"pcg_a": 21, "pcg_b": 17, "unused": 0}
 KERNEL_SYMBOL = {"pcg_a": "k_pcg_a_v<double, false>", "pcg_b": "k_pcg_b_v<double>", "unused": ""}
 # the FP32 correction sweeps of the mixed solve (nx divisible by 4)
 KERNEL_SYMBOL_F32 = {"pcg_a": "k_pcg_a_f4<false>", "pcg_b": "k_pcg_b_f4", "unused": ""}
+# algorithmic FLOPs of one network application per cell: 2 * 27 * (2*16 + 16*16 + 16*16 + 16*1)
+CNN_FLOP_PER_CELL = 30240
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def workload(name):
@@ -119,8 +122,9 @@ def cpu_baseline(case, gpu_iters_per_step, n_pcg=3):
     }
 
 
-def run_solver(case, solver, args, ibm, torch):
-    """Set-up, warm-up and timed steps of one solver configuration.  Returns a dict."""
+def run_solver(case, solver, args, ibm, torch, weights=None):
+    """Set-up, warm-up and timed steps of one solver configuration.  Returns a dict.
+    weights: trained preconditioner weights for the learned solver."""
     N = case.n[0] * case.n[1] * case.n[2]
     precision = ibm.FP64 if solver == "pcg_fp64" else ibm.MIXED
     kind = {"pcg_fp64": ibm.SOLVER_PCG_JACOBI, "mixed": ibm.SOLVER_FCG_JACOBI,
@@ -130,6 +134,10 @@ def run_solver(case, solver, args, ibm, torch):
     blocked, theta = s.tag(case.tri)
     s.build(blocked, None, case.deadend)
     del theta
+    net = None
+    if solver == "mixed_learned":
+        net = ibm.Network(N, weights)
+        net.attach(s)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     st = s.new_state(case.u_in)
@@ -191,9 +199,40 @@ def run_solver(case, solver, args, ibm, torch):
                         "bytes_per_cell": bytes_tab[name], "avg_s": avg_s, "achieved_gbs": achieved,
                         "launches": tim["launches"][k_dom], "launches_with_work": real,
                         "sweeps_ms": {SWEEP_NAMES[k]: round(tim["ms"][k], 2) for k in range(3)}}}
+    if solver == "mixed_learned":
+        # preconditioner applications: input + four BF16 MFMA convolutions + combine
+        apply_s = tim["ms"][0] / 1e3 / max(real, 1)
+        out["cnn"] = {"flop_per_cell": CNN_FLOP_PER_CELL, "avg_apply_us": round(apply_s * 1e6, 2),
+                      "tflops": round(CNN_FLOP_PER_CELL * N / apply_s / 1e12, 2),
+                      "fcg_update_ms": round(tim["ms"][1], 2)}
+        net.close()
     s.close()
     torch.cuda.synchronize()
     return out
+
+
+def train_network(args, ibm, torch):
+    """Trains the learned preconditioner on the GPU (library forward/backward kernels,
+    Adam) on (b, p) pairs of the plain FP64 solver from seeded 64^3 windows of the
+    ellipsoid field, disjoint from the benchmark geometry (seed 0).  Untimed set-up."""
+    from paper_2002_06206_amd import inputs, train
+    t0 = time.perf_counter()
+    data = train.build_dataset(train.TRAIN_SEEDS, 64)
+    held = train.build_dataset(train.EVAL_SEEDS, 64)
+    t1 = time.perf_counter()
+    net = ibm.Network(64 ** 3, inputs.cnn_init_weights(0, last_scale=0.01))
+    before = train.mean_loss(net, held)
+    train.train(net, data, args.train_iters, args.train_lr)
+    after = train.mean_loss(net, held)
+    w = net.weights
+    net.close()
+    for s_, _ in data + held:
+        s_.close()
+    torch.cuda.synchronize()
+    info = {"pairs": sum(len(p) for _, p in data), "data_s": round(t1 - t0, 2),
+            "train_s": round(time.perf_counter() - t1, 2), "iters": args.train_iters,
+            "heldout_loss_before": round(before, 4), "heldout_loss_after": round(after, 4)}
+    return w, info
 
 
 def main():
@@ -206,7 +245,10 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-1,
                     help="mixed solve: residual reduction of each FP32 segment between FP64 replacements")
     ap.add_argument("--solver", default="mixed", choices=["mixed", "mixed_learned", "pcg_fp64"],
-                    help="headline solver; the plain FP64 solver is always run beside it")
+                    help="headline solver; plain FP64 and mixed always run beside it")
+    ap.add_argument("--no-learned", action="store_true", help="skip training and the learned solver")
+    ap.add_argument("--train-iters", type=int, default=1500)
+    ap.add_argument("--train-lr", type=float, default=2e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -222,9 +264,14 @@ def main():
     N = case.n[0] * case.n[1] * case.n[2]
 
     plain = run_solver(case, "pcg_fp64", args, ibm, torch)
-    head = plain if args.solver == "pcg_fp64" else run_solver(case, args.solver, args, ibm, torch)
+    runs = {"pcg_fp64": plain, "mixed": run_solver(case, "mixed", args, ibm, torch)}
+    train_info = None
+    if not args.no_learned or args.solver == "mixed_learned":
+        w, train_info = train_network(args, ibm, torch)
+        runs["mixed_learned"] = run_solver(case, "mixed_learned", args, ibm, torch, w)
+    head = runs[args.solver]
     dom = head["dominant"]
-    traffic = committed_traffic(dom["name"], args.workload) if args.solver == "pcg_fp64" else None
+    traffic = committed_traffic(dom["name"] + ("" if args.solver == "pcg_fp64" else "_f32"), args.workload)
     roofline = {"bound": "hbm", "achieved": round(dom["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom["kernel"],
                 "algorithmic_bytes_per_launch": dom["bytes_per_cell"] * N,
@@ -244,15 +291,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.solver == "pcg_fp64" else "f32+f64",
+        "dtype": {"pcg_fp64": "f64", "mixed": "f32+f64", "mixed_learned": "bf16+f32+f64"}[args.solver],
         "data": "synthetic",
         "config": {"workload": case.name, "cells": list(case.n), "triangles": int(len(case.tri)),
                    "cuts": head["cuts"], "solver": head["solver"], "tol": args.tol, "inner_tol": args.inner_tol,
                    "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm},
         "plain_fp64_value": plain["value"],
         "speedup_vs_plain_fp64": head["value"] / plain["value"],
-        "headline": {k: v for k, v in head.items() if k != "dominant"},
-        "plain_fp64": {k: v for k, v in plain.items() if k != "dominant"},
+        "solvers": {k: {kk: vv for kk, vv in v.items() if kk != "dominant"} for k, v in runs.items()},
+        "speedups_vs_plain_fp64": {k: round(v["value"] / plain["value"], 4) for k, v in runs.items()},
+        "training": train_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

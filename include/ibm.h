@@ -73,9 +73,11 @@ typedef struct {
     double tol;
     int32_t max_iter;        /* cap on (inner) iterations per solve                */
     int32_t kind;            /* IBM_SOLVER_*                                        */
-    double inner_tol;        /* FCG kinds: relative reduction per refinement sweep  */
-    int32_t inner_max_iter;  /* FCG kinds: cap per refinement sweep                 */
-    double stall_factor;     /* FCG kinds: fall back to FP64 PCG when one sweep     */
+    double inner_tol;        /* mixed kinds: reduction of the FP32 recursive        */
+                             /* residual per segment before the FP64 residual      */
+                             /* replaces it (default 0.1)                           */
+    int32_t inner_max_iter;  /* mixed kinds: iteration cap per segment              */
+    double stall_factor;     /* mixed kinds: fall back to FP64 PCG when a segment   */
                              /* reduces the FP64 residual by less than this factor  */
     int32_t check_every;     /* iterations enqueued between host convergence polls  */
     int32_t force_stall;     /* test hook: 1 = treat the first sweep as stalled      */
@@ -98,7 +100,8 @@ typedef struct {
 
 typedef struct {
     int32_t iters_inner;     /* CG / FCG iterations                                  */
-    int32_t iters_outer;     /* FP64 refinement sweeps (0 for plain PCG)             */
+    int32_t iters_outer;     /* FP32 segments between FP64 residual replacements     */
+                             /* (0 for plain PCG)                                    */
     int32_t fallback_used;   /* 1 when the FP64 PCG fallback ran                     */
     int32_t status;          /* return code of the solve                             */
     double rel_residual;     /* FP64 ||b - L p|| / ||b|| after the solve             */
@@ -195,6 +198,57 @@ int ibm_get_rhs(ibm_ctx* ctx, double* out_dev, void* stream);
  * follow eqs. (cd_sphere) / (cd_flat_plate) on the caller's side. */
 int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const void* nut_dev, double nu,
                const double* wall_dev, double out_host[6], void* stream);
+
+/* ---- Learned preconditioner (an extension layered on the pressure solve of
+ * eq. (poisson); the paper itself uses plain Krylov solves).
+ *
+ * Network: four 3x3x3 convolutions, 2 -> 16 -> 16 -> 16 -> 1 channels, ReLU after the
+ * first three, zero padding at the grid faces, no biases.  As the preconditioner of
+ * IBM_SOLVER_FCG_CNN it maps a residual r to
+ *     z = D^-1 r + s * net([r / s, g]),   s = RMS of r over the cells,
+ * D the diagonal of A = -L and g the open-face fraction of the cell (open pressure
+ * faces / 6).  All weights zero gives Jacobi.
+ * Weights: IBM_CNN_NWEIGHTS floats, per layer w[t][ci][co] (row-major) with tap
+ * t = (dz+1)*9 + (dy+1)*3 + (dx+1) for offsets in {-1,0,1}; layers in order at
+ * offsets 0, 864, 7776, 14688.  The FP32 master copy lives on the device.
+ * Arithmetic: BF16 operands on the matrix cores with FP32 accumulation; hidden
+ * activations and backward signals are stored in BF16 (channels-last).
+ * Field buffers are device memory, x fastest (cell c = i + nx*(j + ny*k)). */
+#define IBM_CNN_NWEIGHTS 15120
+typedef struct ibm_cnn ibm_cnn;
+
+/* Creates a network on the current HIP device with all weights zero and workspace for
+ * grids of up to max_cells cells (about 200 bytes per cell). */
+int ibm_cnn_create(int64_t max_cells, ibm_cnn** out);
+int ibm_cnn_destroy(ibm_cnn* net);
+/* Host FP32 weights in, n = IBM_CNN_NWEIGHTS; resets the Adam state.  Synchronous. */
+int ibm_cnn_set_weights(ibm_cnn* net, const float* w_host, int64_t n);
+int ibm_cnn_get_weights(ibm_cnn* net, float* w_host, int64_t n);
+/* Network output y (cells floats) for the input x (cells x 2 BF16 bit patterns,
+ * channels-last) on an nx x ny x nz grid.  Keeps the activations for
+ * ibm_cnn_backward. */
+int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t nx, int32_t ny, int32_t nz,
+                    void* stream);
+/* Backward pass of the last forward for a scalar J with dJ/dy = dy (cells floats,
+ * rounded to BF16): dJ/dw into dw_dev (IBM_CNN_NWEIGHTS floats, weight layout) and,
+ * when dx_dev != NULL, dJ/dx (cells x 2 floats). */
+int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx_dev, void* stream);
+/* Training loss of one pair (b, p) with L p = b on the context's stencil: with
+ * f = -b and h = the preconditioned f,  loss = 1 - (f.h)^2 / ((f.p)(h.A h)), the
+ * A-norm distance of p from the best multiple of h relative to |p|_A^2 (in [0,1],
+ * invariant to the scale of h).  loss_out (host) and, when dw_dev != NULL, the
+ * gradient in the weights.  Synchronises the stream. */
+int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, double* loss_out,
+                 float* dw_dev, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, FP32 moments) on that loss; loss_out
+ * gets the loss before the update.  Synchronises the stream. */
+int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, float lr,
+                       double* loss_out, void* stream);
+/* z = D^-1 r + s net([r/s, g]) on the context's grid (r, z: cells floats). */
+int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, void* stream);
+/* Preconditioner used by IBM_SOLVER_FCG_CNN on this context (NULL detaches); the network
+ * must cover the grid and outlive its use. */
+int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net);
 
 /* Measurement support (not part of the method).  When enabled, every launch of
  * the three conjugate-gradient sweeps (0: SpMV + <d,q>, 1: x/r update + <r,r> +

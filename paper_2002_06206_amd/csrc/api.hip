@@ -130,6 +130,7 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
     if (!rc) rc = dalloc(&c->d32, sizeof(float) * N);
     if (!rc) rc = dalloc(&c->q32, sizeof(float) * N);
     if (!rc) rc = dalloc(&c->e32, sizeof(float) * N);
+    if (!rc) rc = dalloc(&c->zprev32, sizeof(float) * N);   // FCG: previous residual
     if (!rc) rc = dalloc(&c->partials, sizeof(double) * 16 * MAX_BLOCKS);
     if (!rc) rc = dalloc(&c->counter, sizeof(unsigned int) * 16);
     if (!rc) rc = dalloc(&c->solver, sizeof(Solver));

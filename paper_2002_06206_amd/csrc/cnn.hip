@@ -1,16 +1,921 @@
-// Learned preconditioner: 3-D convolutional network inside flexible CG.
+// Learned preconditioner for the pressure solve (eq. (poisson)): a small 3-D
+// convolutional network inside flexible CG.  The network, its training and the
+// preconditioner application live here; the Krylov loop is in poisson.hip.
+//
+// Network: four 3x3x3 convolutions, 2 -> 16 -> 16 -> 16 -> 1 channels, ReLU after the
+// first three, zero padding at the grid faces, no biases.  Input channels: the residual
+// divided by its RMS s, and the open-face fraction of the cell.  Preconditioner:
+// z = D^-1 r + s * net([r/s, g]), D the diagonal of A = -L.
+//
+// MI355X design:
+//  * activations channels-last in BF16: 16 channels = 32 bytes per cell, one 16-byte
+//    load per lane feeds an MFMA operand;
+//  * every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16 with FP32
+//    accumulation: M = 16 output channels, N = 16 cells along x, K = 32 = (two taps x
+//    16 input channels), 14 k-steps per 3x3x3 stencil.  The weights of a layer sit in
+//    registers for the whole block (A operand, 56 VGPRs); the input tile with its halo
+//    (34 x 10 x 6 cells) is staged once in LDS as two 16-byte half-cell planes so that
+//    the B-operand reads of 16 lanes are contiguous;
+//  * the output D tile gives each lane 4 consecutive channels of one cell: one 8-byte
+//    store per lane, 512 contiguous bytes per 16-cell tile;
+//  * the backward data pass is the same kernel with flipped taps and transposed
+//    weights, the ReLU mask fused into its epilogue;
+//  * the weight gradient is an implicit GEMM over cells (K = cells of the tile): both
+//    operands are staged channel-major in LDS, each block writes one partial 27x16x16
+//    gradient and a second kernel sums the partials in block order (deterministic);
+//  * blocks walk the tiles z-slowest through the XCD chunk map, so neighbouring tiles
+//    (shared halos) run on one XCD and its L2.
+
+#include <cmath>
+#include <cstring>
+
 #include "common.h"
 
 namespace ibm {
+namespace {
 
-int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {
-    (void)b; (void)x; (void)o; (void)st; (void)s;
-    if (!c->cnn) {
-        set_error("IBM_SOLVER_FCG_CNN: no network attached to the context");
-        return IBM_ERR_ARG;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NWTS = IBM_CNN_NWEIGHTS;
+
+// output tile of one convolution block and its halo
+constexpr int CTX = 32, CTY = 8, CTZ = 4;
+constexpr int HX = CTX + 2, HY = CTY + 2, HZ = CTZ + 2;
+constexpr int HCELLS = HX * HY * HZ;      // 2040
+constexpr int OCELLS = CTX * CTY * CTZ;   // 1024
+constexpr int MTILES = OCELLS / 16;       // 16-cell MFMA column tiles per block
+constexpr int WG_MAX_BLOCKS = 1024;       // weight-gradient partials
+
+enum { EPI_RELU = 0, EPI_MASK = 1, EPI_F32 = 2 };
+
+__host__ __device__ constexpr int ksteps(int cin) { return cin == 16 ? 14 : (27 * cin + 31) / 32; }
+
+// (tap, input channel) held by element e of lane group g in k-step s; tap = -1 for
+// padding.  Used by the weight packing and by the B-operand gather, so the two MFMA
+// operands agree on k.
+template <int CIN>
+__host__ __device__ inline void kmap(int s, int g, int e, int& tap, int& ci) {
+    if (CIN == 16) {
+        tap = 2 * s + (g >> 1);
+        ci = 8 * (g & 1) + e;
+    } else {
+        const int k = 32 * s + 8 * g + e;
+        tap = k / CIN;
+        ci = k % CIN;
     }
-    set_error("IBM_SOLVER_FCG_CNN: not available");
-    return IBM_ERR_ARG;
+    if (tap > 26) tap = -1;
 }
 
+// float -> bfloat16 bits, round to nearest, ties to even; NaN stays NaN
+__device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x0040u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline int jcnt(uint8_t pc) { return __builtin_popcount((unsigned)(pc & 0x3F)) + 2 * (pc >> 6); }
+
+// ------------------------------------------------------------------ weight packing
+
+}  // namespace
+
+struct PackDesc {
+    int loff, lcin, lcout;   // layer: offset in the flat weights, its channels
+    int bwd;                 // 0 forward conv, 1 backward-data conv (flipped, transposed)
+    int cin, cout;           // channels of the conv as launched
+    int ks, off;             // k-steps, offset in the packed array (elements)
+};
+
+namespace {
+
+// Packed A operand: for k-step s and lane l, 8 BF16 values W[row = l % 16][k(s, l / 16, e)].
+__global__ void k_pack(const float* __restrict__ w, uint16_t* __restrict__ wp, PackDesc d) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= d.ks * 512) return;
+    const int e = idx & 7, lane = (idx >> 3) & 63, s = idx >> 9;
+    const int g = lane >> 4, row = lane & 15;
+    int tap, ci;
+    if (d.cin == 16)
+        kmap<16>(s, g, e, tap, ci);
+    else if (d.cin == 2)
+        kmap<2>(s, g, e, tap, ci);
+    else
+        kmap<1>(s, g, e, tap, ci);
+    float val = 0.0f;
+    if (tap >= 0 && row < d.cout && ci < d.cin) {
+        const float* wl = w + d.loff;
+        if (!d.bwd)
+            val = wl[(tap * d.lcin + ci) * d.lcout + row];
+        else   // backward conv: input channel = layer output channel, output = layer input
+            val = wl[((26 - tap) * d.lcin + row) * d.lcout + ci];
+    }
+    wp[d.off + idx] = f2bf(val);
+}
+
+// ------------------------------------------------------------------ convolution
+
+__device__ inline void tile_of(int b, int nb, int ntx, int nty, int& tx, int& ty, int& tz) {
+    const int t = xcd_chunk(b, nb);
+    tx = t % ntx;
+    ty = (t / ntx) % nty;
+    tz = t / (ntx * nty);
+}
+
+// One 3x3x3 convolution layer over an nx x ny x nz grid (zero padding).
+//   in:  cells x CIN BF16 (channels-last);  wp: packed weights of the layer;
+//   EPI_RELU: out = BF16(relu(acc)), cells x 16;  EPI_MASK: out = BF16(mask > 0 ? acc : 0)
+//   with mask = cells x 16 BF16 activations;  EPI_F32: out = acc as float, cells x COUT.
+// sv (may be null): the solve's state; the kernel does nothing once it has converged.
+template <int CIN, int COUT, int EPI>
+__global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const uint16_t* __restrict__ in,
+                                                 const uint16_t* __restrict__ wp, void* __restrict__ out,
+                                                 const uint16_t* __restrict__ mask, const Solver* sv) {
+    if (sv && sv->converged) return;
+    constexpr int KS = ksteps(CIN);
+    constexpr int LDS_ELEMS = CIN == 16 ? 2 * HCELLS * 8 : HCELLS * CIN;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[LDS_ELEMS];
+    const int ntx = (nx + CTX - 1) / CTX, nty = (ny + CTY - 1) / CTY;
+    int tx, ty, tz;
+    tile_of(blockIdx.x, gridDim.x, ntx, nty, tx, ty, tz);
+    const int hx0 = tx * CTX - 1, hy0 = ty * CTY - 1, hz0 = tz * CTZ - 1;
+    // stage the input tile with its halo (zero outside the grid)
+    if (CIN == 16) {
+        for (int q = threadIdx.x; q < 2 * HCELLS; q += 256) {
+            const int cell = q >> 1, h = q & 1;
+            const int hx = cell % HX, hy = (cell / HX) % HY, hz = cell / (HX * HY);
+            const int gx = hx0 + hx, gy = hy0 + hy, gz = hz0 + hz;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
+                const long long c = (long long)gx + (long long)nx * ((long long)gy + (long long)ny * gz);
+                v = *reinterpret_cast<const uint4*>(in + c * 16 + h * 8);
+            }
+            *reinterpret_cast<uint4*>(&lds[(h * HCELLS + cell) * 8]) = v;
+        }
+    } else {
+        for (int cell = threadIdx.x; cell < HCELLS; cell += 256) {
+            const int hx = cell % HX, hy = (cell / HX) % HY, hz = cell / (HX * HY);
+            const int gx = hx0 + hx, gy = hy0 + hy, gz = hz0 + hz;
+            const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+            const long long c = ok ? (long long)gx + (long long)nx * ((long long)gy + (long long)ny * gz) : 0;
+#pragma unroll
+            for (int ci = 0; ci < CIN; ++ci) lds[cell * CIN + ci] = ok ? in[c * CIN + ci] : (uint16_t)0;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    bf16x8 wa[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) wa[s] = *reinterpret_cast<const bf16x8*>(wp + ((long long)s * 64 + lane) * 8);
+    __syncthreads();
+    for (int m = wv; m < MTILES; m += 4) {
+        const int xg = m & 1, oy = (m >> 1) & (CTY - 1), oz = m >> 4;
+        const int ox = xg * 16 + j;
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            bf16x8 bv;
+            if (CIN == 16) {
+                int tap = 2 * s + (g >> 1);
+                if (tap > 26) tap = 26;   // padding slot: its weights are zero
+                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                const int hc = (ox + 1 + dx) + HX * ((oy + 1 + dy) + HY * (oz + 1 + dz));
+                bv = *reinterpret_cast<const bf16x8*>(&lds[((g & 1) * HCELLS + hc) * 8]);
+            } else {
+                uint16_t tmp[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    int tap, ci;
+                    kmap<CIN>(s, g, e, tap, ci);
+                    uint16_t v = 0;
+                    if (tap >= 0) {
+                        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                        const int hc = (ox + 1 + dx) + HX * ((oy + 1 + dy) + HY * (oz + 1 + dz));
+                        v = lds[hc * CIN + ci];
+                    }
+                    tmp[e] = v;
+                }
+                __builtin_memcpy(&bv, tmp, 16);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc, 0, 0, 0);
+        }
+        // lane holds output channels 4g .. 4g+3 of cell (ox, oy, oz)
+        const int gx = tx * CTX + ox, gy = ty * CTY + oy, gz = tz * CTZ + oz;
+        if (gx < nx && gy < ny && gz < nz) {
+            const long long c = (long long)gx + (long long)nx * ((long long)gy + (long long)ny * gz);
+            if (EPI == EPI_RELU || EPI == EPI_MASK) {
+                float v[4] = {acc[0], acc[1], acc[2], acc[3]};
+                if (EPI == EPI_RELU) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = v[r] > 0.0f ? v[r] : 0.0f;
+                } else {
+                    const uint2 mk = *reinterpret_cast<const uint2*>(mask + c * 16 + 4 * g);
+                    const uint16_t mh[4] = {(uint16_t)(mk.x & 0xFFFFu), (uint16_t)(mk.x >> 16),
+                                            (uint16_t)(mk.y & 0xFFFFu), (uint16_t)(mk.y >> 16)};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = bf2f(mh[r]) > 0.0f ? v[r] : 0.0f;
+                }
+                uint2 o;
+                o.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+                o.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+                *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + c * 16 + 4 * g) = o;
+            } else {
+                if (g == 0) {
+                    float* of = static_cast<float*>(out);
+#pragma unroll
+                    for (int r = 0; r < COUT; ++r) of[c * COUT + r] = acc[r];
+                }
+            }
+        }
+    }
+}
+
+// Weight gradient of one layer: dW[t][ci][co] = sum over cells c of X[c + off_t][ci] dY[c][co].
+// MFMA with M = co, N = ci, K = 32 cells of the tile.  Each block loops over tiles and
+// writes its partial 27 x 16 x 16 sum (layout t*256 + ci*16 + co).
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256, 1) k_wgrad(int nx, int ny, int nz, const uint16_t* __restrict__ x,
+                                                  const uint16_t* __restrict__ dy, float* __restrict__ part,
+                                                  int ntiles) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs[CIN * HCELLS];
+    __shared__ __attribute__((aligned(16))) uint16_t ds[COUT * OCELLS];
+    const int ntx = (nx + CTX - 1) / CTX, nty = (ny + CTY - 1) / CTY;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    f32x4 acc[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) acc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        int tx, ty, tz;
+        tile_of(t, ntiles, ntx, nty, tx, ty, tz);
+        const int hx0 = tx * CTX - 1, hy0 = ty * CTY - 1, hz0 = tz * CTZ - 1;
+        __syncthreads();   // previous tile's reads are done
+        for (int cell = threadIdx.x; cell < HCELLS; cell += 256) {
+            const int hx = cell % HX, hy = (cell / HX) % HY, hz = cell / (HX * HY);
+            const int gx = hx0 + hx, gy = hy0 + hy, gz = hz0 + hz;
+            const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+            const long long c = ok ? (long long)gx + (long long)nx * ((long long)gy + (long long)ny * gz) : 0;
+#pragma unroll
+            for (int ci = 0; ci < CIN; ++ci) xs[ci * HCELLS + cell] = ok ? x[c * CIN + ci] : (uint16_t)0;
+        }
+        for (int cell = threadIdx.x; cell < OCELLS; cell += 256) {
+            const int ox = cell % CTX, oy = (cell / CTX) % CTY, oz = cell / (CTX * CTY);
+            const int gx = hx0 + 1 + ox, gy = hy0 + 1 + oy, gz = hz0 + 1 + oz;
+            const bool ok = gx < nx && gy < ny && gz < nz;
+            const long long c = ok ? (long long)gx + (long long)nx * ((long long)gy + (long long)ny * gz) : 0;
+#pragma unroll
+            for (int co = 0; co < COUT; ++co) ds[co * OCELLS + cell] = ok ? dy[c * COUT + co] : (uint16_t)0;
+        }
+        __syncthreads();
+        for (int kb = 0; kb < OCELLS; kb += 32) {
+            // A operand: dY of channel j for the 8 cells kb + 8g .. kb + 8g + 7
+            bf16x8 av;
+            if (j < COUT) {
+                av = *reinterpret_cast<const bf16x8*>(&ds[j * OCELLS + kb + 8 * g]);
+            } else {
+                const uint16_t z8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                __builtin_memcpy(&av, z8, 16);
+            }
+            const int k0 = kb + 8 * g;   // first of 8 cells, all in one tile row
+            const int ox0 = k0 % CTX, oy = (k0 / CTX) % CTY, oz = k0 / (CTX * CTY);
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                const int tap = wv + 4 * q;
+                if (tap > 26) break;
+                const int dz = tap / 9 - 1, dyy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                uint16_t tmp[8];
+                const int hc0 = (ox0 + 1 + dx) + HX * ((oy + 1 + dyy) + HY * (oz + 1 + dz));
+#pragma unroll
+                for (int e = 0; e < 8; ++e) tmp[e] = j < CIN ? xs[j * HCELLS + hc0 + e] : (uint16_t)0;
+                bf16x8 bv;
+                __builtin_memcpy(&bv, tmp, 16);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds D[co = 4g + r][ci = j] of each of its taps
+    float* pb = part + (long long)blockIdx.x * (27 * 256);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+        const int tap = wv + 4 * q;
+        if (tap > 26) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pb[tap * 256 + j * 16 + 4 * g + r] = acc[q][r];
+    }
+}
+
+// dW (layer layout [27][CIN][COUT]) = sum of the block partials in block order
+__global__ void k_wsum(const float* __restrict__ part, int nblocks, int cin, int cout, float* __restrict__ dw) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 27 * cin * cout) return;
+    const int co = idx % cout, ci = (idx / cout) % cin, t = idx / (cout * cin);
+    const int o = t * 256 + ci * 16 + co;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += part[(long long)b * (27 * 256) + o];
+    dw[idx] = s;
+}
+
+// ------------------------------------------------------------------ input, loss, Adam
+
+// partial sums of f^2 (one per block)
+template <class T>
+__global__ void __launch_bounds__(NT) k_sumsq(long long n, const T* __restrict__ f, double* __restrict__ part) {
+    __shared__ double sh[4];
+    double v[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+        const double a = (double)f[i];
+        v[0] += a * a;
+    }
+    block_reduce<1>(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Network input x0 = [BF16(f / s), BF16(open faces / 6)] with s^2 = (sum of the partials
+// of <f,f> in slot) / n.  With a solver state: stops the solve (sets converged) when
+// <f,f> <= tol2, and stores s for the combining step.
+template <class T>
+__global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__ f, const uint8_t* __restrict__ pcode,
+                                              const double* __restrict__ part, int nparts, uint16_t* __restrict__ x0,
+                                              double* __restrict__ s_out, Solver* sv, int it) {
+    if (sv && sv->converged) return;
+    __shared__ double sh[4];
+    double v[1] = {0.0};
+    for (int b = threadIdx.x; b < nparts; b += NT) v[0] += part[b];
+    block_reduce<1>(v, sh);
+    const double ff = v[0];
+    if (sv) {
+        if (!(ff == ff)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sv->nan_seen = 1;
+                sv->converged = 3;
+                sv->iters = it;
+            }
+            return;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sv->rr = ff;
+            sv->iters = it;
+        }
+        if (ff <= sv->tol2) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) sv->converged = 1;
+            return;
+        }
+    }
+    const double s = sqrt(ff / (double)n);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *s_out = s;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+        const double a = s > 0.0 ? (double)f[i] / s : 0.0;
+        const uint8_t pc = pcode[i];
+        const float gfr = (float)((double)__builtin_popcount((unsigned)(pc & 0x3F)) / 6.0);
+        const uint32_t w = (uint32_t)f2bf((float)a) | ((uint32_t)f2bf(gfr) << 16);
+        reinterpret_cast<uint32_t*>(x0)[i] = w;
+    }
+}
+
+// h = D^-1 f + s y (double)
+__global__ void k_phat(long long n, double dx2, const double* __restrict__ f, const uint8_t* __restrict__ pcode,
+                       const float* __restrict__ y, const double* __restrict__ s_in, double* __restrict__ h) {
+    const double s = *s_in;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int cnt = jcnt(pcode[i]);
+        const double dinv = cnt ? dx2 / (double)cnt : 0.0;
+        h[i] = dinv * f[i] + s * (double)y[i];
+    }
+}
+
+// q = A h = -L h; partials <f,h>, <h,q>, <f,p> (slots 0, 1, 2 of part, MAX_BLOCKS apart)
+__global__ void __launch_bounds__(NT) k_loss_dots(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ f,
+                                                  const double* __restrict__ p, const double* __restrict__ h,
+                                                  double* __restrict__ q, double* __restrict__ part) {
+    __shared__ double sh[12];
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += (long long)gridDim.x * NT) {
+        const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / ((long long)g.nx * g.ny));
+        const uint8_t pc = pcode[c];
+        const double hc = h[c];
+        double acc = (double)jcnt(pc) * hc;
+        for (int d = 0; d < 6; ++d) {
+            if (pc & (1 << d)) {
+                bool bnd;
+                acc -= h[nb_index(g, i, j, k, d, bnd)];
+            }
+        }
+        const double qc = acc * idx2;
+        q[c] = qc;
+        v[0] += f[c] * hc;
+        v[1] += hc * qc;
+        v[2] += f[c] * p[c];
+    }
+    block_reduce<3>(v, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        part[MAX_BLOCKS + blockIdx.x] = v[1];
+        part[2 * MAX_BLOCKS + blockIdx.x] = v[2];
+    }
+}
+
+// loss = 1 - c^2 / (B Q); scal[1] = s 2c/(BQ), scal[2] = c/Q (gradient coefficients)
+__global__ void __launch_bounds__(NT) k_loss_final(const double* __restrict__ part, int nparts, double* __restrict__ scal) {
+    __shared__ double sh[12];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += NT) {
+        v[0] += part[b];
+        v[1] += part[MAX_BLOCKS + b];
+        v[2] += part[2 * MAX_BLOCKS + b];
+    }
+    block_reduce<3>(v, sh);
+    if (threadIdx.x == 0) {
+        const double c = v[0], Q = v[1], B = v[2];
+        const double s = scal[0];
+        scal[3] = 1.0 - c * c / (B * Q);
+        scal[1] = s * 2.0 * c / (B * Q);
+        scal[2] = c / Q;
+    }
+}
+
+// d loss / d y = s (2c/(BQ)) ((c/Q) q - f), rounded to BF16 for the backward pass
+__global__ void k_dy(long long n, const double* __restrict__ q, const double* __restrict__ f,
+                     const double* __restrict__ scal, uint16_t* __restrict__ dy) {
+    const double k1 = scal[1], k2 = scal[2];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dy[i] = f2bf((float)(k1 * (k2 * q[i] - f[i])));
+}
+
+__global__ void k_neg(long long n, const double* __restrict__ a, double* __restrict__ b) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = -a[i];
+}
+
+__global__ void k_f32_to_bf16(long long n, const float* __restrict__ a, uint16_t* __restrict__ b) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = f2bf(a[i]);
+}
+
+// Adam (Kingma & Ba): step t >= 1, beta1 0.9, beta2 0.999, eps 1e-8
+__global__ void k_adam(int n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int t, float lr) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / (1.0f - powf(b1, (float)t));
+    const float vh = vi / (1.0f - powf(b2, (float)t));
+    w[i] = w[i] - lr * mh / (sqrtf(vh) + 1e-8f);
+}
+
+// Solver step: z = D^-1 r + s y (float); partials <z,r> -> slot zr, <z,rp> -> slot zrp
+__global__ void __launch_bounds__(NT) k_combine(long long n, double dx2, const float* __restrict__ r,
+                                                const float* __restrict__ rp, const uint8_t* __restrict__ pcode,
+                                                const float* __restrict__ y, const double* __restrict__ s_in,
+                                                float* __restrict__ z, double* __restrict__ partials, int zr_slot,
+                                                int zrp_slot, const Solver* sv) {
+    if (sv && sv->converged) return;
+    __shared__ double sh[8];
+    __shared__ float invf[16];
+    if (threadIdx.x < 16) invf[threadIdx.x] = threadIdx.x ? (float)(dx2 / (double)threadIdx.x) : 0.0f;
+    __syncthreads();
+    const float s = (float)*s_in;
+    double v[2] = {0.0, 0.0};
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+        const float ri = r[i];
+        const float zi = invf[jcnt(pcode[i])] * ri + s * y[i];
+        z[i] = zi;
+        v[0] += (double)zi * (double)ri;
+        if (rp) v[1] += (double)zi * (double)rp[i];
+    }
+    block_reduce<2>(v, sh);
+    if (threadIdx.x == 0) {
+        partials[zr_slot * MAX_BLOCKS + blockIdx.x] = v[0];
+        if (zrp_slot >= 0) partials[zrp_slot * MAX_BLOCKS + blockIdx.x] = v[1];
+    }
+}
+
+}  // namespace
+
 }  // namespace ibm
+
+// ------------------------------------------------------------------ network object
+
+struct ibm_cnn {
+    int device;
+    long long cap;
+    float* w;        // FP32 master weights (flat, ABI layout)
+    float* m;        // Adam moments
+    float* v;
+    float* dw;       // last gradient
+    int adam_t;
+    uint16_t* wp;    // packed BF16 A operands of the eight convolutions
+    ibm::PackDesc pd[8];
+    uint16_t* x0;    // cap x 2
+    uint16_t* act[3];// cap x 16
+    uint16_t* sig[2];// cap x 16 backward signals
+    uint16_t* dy4;   // cap
+    float* y;        // cap
+    float* wpart;    // WG_MAX_BLOCKS x 27 x 256
+    double* h;       // cap (loss)
+    double* q;       // cap
+    double* f;       // cap (loss: -b)
+    double* part;    // 3 x MAX_BLOCKS
+    double* scal;    // 8: s, k1, k2, loss
+    double* h_scal;  // pinned host copy
+    int nx, ny, nz;  // dims of the last forward
+    bool have_fwd;
+};
+
+namespace ibm {
+namespace {
+
+enum { PV_F1 = 0, PV_F2, PV_F3, PV_F4, PV_B4, PV_B3, PV_B2, PV_B1, PV_N };
+
+void fill_pack_desc(ibm_cnn* n) {
+    const int loff[4] = {0, 864, 7776, 14688};
+    const int lcin[4] = {2, 16, 16, 16}, lcout[4] = {16, 16, 16, 1};
+    int off = 0;
+    for (int v = 0; v < PV_N; ++v) {
+        PackDesc d;
+        int l;
+        if (v <= PV_F4) {
+            l = v;
+            d.bwd = 0;
+            d.cin = lcin[l];
+            d.cout = lcout[l];
+        } else {
+            l = 3 - (v - PV_B4);   // B4 -> layer 3, B1 -> layer 0
+            d.bwd = 1;
+            d.cin = lcout[l];
+            d.cout = lcin[l];
+        }
+        d.loff = loff[l];
+        d.lcin = lcin[l];
+        d.lcout = lcout[l];
+        d.ks = ksteps(d.cin);
+        d.off = off;
+        off += d.ks * 512;
+        n->pd[v] = d;
+    }
+}
+
+int packed_elems(const ibm_cnn* n) { return n->pd[PV_N - 1].off + n->pd[PV_N - 1].ks * 512; }
+
+int repack(ibm_cnn* n, hipStream_t s) {
+    for (int v = 0; v < PV_N; ++v) {
+        const int tot = n->pd[v].ks * 512;
+        k_pack<<<(tot + 255) / 256, 256, 0, s>>>(n->w, n->wp, n->pd[v]);
+    }
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int conv_blocks(int nx, int ny, int nz) {
+    return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY) * ((nz + CTZ - 1) / CTZ);
+}
+
+const uint16_t* pw(const ibm_cnn* n, int v) { return n->wp + n->pd[v].off; }
+
+// x0 -> act[0..2] -> y
+int net_forward(ibm_cnn* n, int nx, int ny, int nz, const Solver* sv, hipStream_t s) {
+    const int nb = conv_blocks(nx, ny, nz);
+    k_conv<2, 16, EPI_RELU><<<nb, 256, 0, s>>>(nx, ny, nz, n->x0, pw(n, PV_F1), n->act[0], nullptr, sv);
+    k_conv<16, 16, EPI_RELU><<<nb, 256, 0, s>>>(nx, ny, nz, n->act[0], pw(n, PV_F2), n->act[1], nullptr, sv);
+    k_conv<16, 16, EPI_RELU><<<nb, 256, 0, s>>>(nx, ny, nz, n->act[1], pw(n, PV_F3), n->act[2], nullptr, sv);
+    k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->act[2], pw(n, PV_F4), n->y, nullptr, sv);
+    IBM_HIP(hipGetLastError());
+    n->nx = nx;
+    n->ny = ny;
+    n->nz = nz;
+    n->have_fwd = true;
+    return IBM_OK;
+}
+
+template <int CIN, int COUT>
+int wgrad(ibm_cnn* n, const uint16_t* x, const uint16_t* dy, int layer, hipStream_t s) {
+    const int nx = n->nx, ny = n->ny, nz = n->nz;
+    const int ntiles = conv_blocks(nx, ny, nz);
+    const int nb = ntiles < WG_MAX_BLOCKS ? ntiles : WG_MAX_BLOCKS;
+    k_wgrad<CIN, COUT><<<nb, 256, 0, s>>>(nx, ny, nz, x, dy, n->wpart, ntiles);
+    const int loff[4] = {0, 864, 7776, 14688};
+    const int nw = 27 * CIN * COUT;
+    k_wsum<<<(nw + 255) / 256, 256, 0, s>>>(n->wpart, nb, CIN, COUT, n->dw + loff[layer]);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+// dy4 -> dw (and dx, cells x 2 floats, when non-null), using the saved activations
+int net_backward(ibm_cnn* n, float* dx, hipStream_t s) {
+    const int nx = n->nx, ny = n->ny, nz = n->nz;
+    const int nb = conv_blocks(nx, ny, nz);
+    int rc;
+    if ((rc = wgrad<16, 1>(n, n->act[2], n->dy4, 3, s))) return rc;
+    k_conv<1, 16, EPI_MASK><<<nb, 256, 0, s>>>(nx, ny, nz, n->dy4, pw(n, PV_B4), n->sig[0], n->act[2], nullptr);
+    if ((rc = wgrad<16, 16>(n, n->act[1], n->sig[0], 2, s))) return rc;
+    k_conv<16, 16, EPI_MASK><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_B3), n->sig[1], n->act[1], nullptr);
+    if ((rc = wgrad<16, 16>(n, n->act[0], n->sig[1], 1, s))) return rc;
+    k_conv<16, 16, EPI_MASK><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[1], pw(n, PV_B2), n->sig[0], n->act[0], nullptr);
+    if ((rc = wgrad<2, 16>(n, n->x0, n->sig[0], 0, s))) return rc;
+    if (dx) k_conv<16, 2, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_B1), dx, nullptr, nullptr);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int check_grid(const ibm_cnn* n, long long cells) {
+    if (cells <= 0 || cells > n->cap) {
+        set_error("cnn: grid has more cells than the network was created for");
+        return IBM_ERR_ARG;
+    }
+    return IBM_OK;
+}
+
+// Loss of one pair (b, p), L p = b, on the context's stencil, and the gradient signal
+// d loss / d y in dy4 (BF16): f = -b, s = RMS(f), x0 = [f/s, g], h = D^-1 f + s y,
+// loss = 1 - (f.h)^2 / ((f.p)(h.A h)).  scal[3] = loss.
+int loss_forward(ibm_cnn* n, ibm_ctx* c, const double* b, const double* p, hipStream_t s) {
+    const Geo& g = c->geo;
+    const long long N = c->N;
+    const int nred = 1024;
+    k_neg<<<2048, 256, 0, s>>>(N, b, n->f);
+    k_sumsq<double><<<nred, NT, 0, s>>>(N, n->f, n->part);
+    k_input<double><<<nred, NT, 0, s>>>(N, n->f, c->pcode, n->part, nred, n->x0, n->scal, nullptr, 0);
+    IBM_HIP(hipGetLastError());
+    int rc = net_forward(n, g.nx, g.ny, g.nz, nullptr, s);
+    if (rc) return rc;
+    k_phat<<<2048, 256, 0, s>>>(N, g.dx * g.dx, n->f, c->pcode, n->y, n->scal, n->h);
+    k_loss_dots<<<nred, NT, 0, s>>>(g, c->pcode, n->f, p, n->h, n->q, n->part);
+    k_loss_final<<<1, NT, 0, s>>>(n->part, nred, n->scal);
+    k_dy<<<2048, 256, 0, s>>>(N, n->q, n->f, n->scal, n->dy4);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+}  // namespace
+
+// z = D^-1 r + s net([r/s, g]) inside the FCG solve (see poisson.hip): s^2 = <r,r>/N from
+// the partials in rr_slot; <z,r> -> zr_slot, <z,rp> -> zrp_slot (-1: none).  Stops the
+// solve (sv->converged = 1) when <r,r> <= sv->tol2.
+int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
+                            int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, hipStream_t s) {
+    ibm_cnn* n = static_cast<ibm_cnn*>(net);
+    const Geo& g = c->geo;
+    k_input<float><<<nparts, NT, 0, s>>>(c->N, r, c->pcode, partials + (long long)rr_slot * MAX_BLOCKS, nparts, n->x0,
+                                         n->scal, sv, it);
+    int rc = net_forward(n, g.nx, g.ny, g.nz, sv, s);
+    if (rc) return rc;
+    k_combine<<<nparts, NT, 0, s>>>(c->N, g.dx * g.dx, r, rp, c->pcode, n->y, n->scal, z, partials, zr_slot, zrp_slot,
+                                     sv);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+bool cnn_covers(const void* net, long long cells) { return net && static_cast<const ibm_cnn*>(net)->cap >= cells; }
+
+}  // namespace ibm
+
+// ------------------------------------------------------------------ C ABI
+
+using namespace ibm;
+
+namespace {
+
+void net_free(ibm_cnn* n) {
+    if (!n) return;
+    void* bufs[] = {n->w, n->m, n->v, n->dw, n->wp, n->x0, n->act[0], n->act[1], n->act[2], n->sig[0], n->sig[1],
+                    n->dy4, n->y, n->wpart, n->h, n->q, n->f, n->part, n->scal};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    if (n->h_scal) (void)hipHostFree(n->h_scal);
+    delete n;
+}
+
+int net_check(const ibm_cnn* n) {
+    if (!n) {
+        set_error("cnn: null network");
+        return IBM_ERR_ARG;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != n->device) {
+        set_error("cnn: call on a device other than the one the network was created on");
+        return IBM_ERR_ARG;
+    }
+    return IBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibm_cnn_create(int64_t max_cells, ibm_cnn** out) {
+    if (!out || max_cells <= 0) {
+        set_error("ibm_cnn_create: bad arguments");
+        return IBM_ERR_ARG;
+    }
+    *out = nullptr;
+    ibm_cnn* n = new (std::nothrow) ibm_cnn();
+    if (!n) {
+        set_error("ibm_cnn_create: host allocation failed");
+        return IBM_ERR_OOM;
+    }
+    std::memset(n, 0, sizeof(*n));
+    if (hipGetDevice(&n->device) != hipSuccess) {
+        delete n;
+        set_error("ibm_cnn_create: no HIP device");
+        return IBM_ERR_HIP;
+    }
+    n->cap = max_cells;
+    fill_pack_desc(n);
+    const size_t cap = (size_t)max_cells;
+    bool ok = true;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
+    };
+    alloc((void**)&n->w, NWTS * sizeof(float));
+    alloc((void**)&n->m, NWTS * sizeof(float));
+    alloc((void**)&n->v, NWTS * sizeof(float));
+    alloc((void**)&n->dw, NWTS * sizeof(float));
+    alloc((void**)&n->wp, (size_t)packed_elems(n) * sizeof(uint16_t));
+    alloc((void**)&n->x0, cap * 2 * sizeof(uint16_t));
+    for (int k = 0; k < 3; ++k) alloc((void**)&n->act[k], cap * 16 * sizeof(uint16_t));
+    for (int k = 0; k < 2; ++k) alloc((void**)&n->sig[k], cap * 16 * sizeof(uint16_t));
+    alloc((void**)&n->dy4, cap * sizeof(uint16_t));
+    alloc((void**)&n->y, cap * sizeof(float));
+    alloc((void**)&n->wpart, (size_t)WG_MAX_BLOCKS * 27 * 256 * sizeof(float));
+    alloc((void**)&n->h, cap * sizeof(double));
+    alloc((void**)&n->q, cap * sizeof(double));
+    alloc((void**)&n->f, cap * sizeof(double));
+    alloc((void**)&n->part, 3 * MAX_BLOCKS * sizeof(double));
+    alloc((void**)&n->scal, 8 * sizeof(double));
+    if (ok && hipHostMalloc((void**)&n->h_scal, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) ok = false;
+    if (!ok) {
+        net_free(n);
+        set_error("ibm_cnn_create: device allocation failed");
+        return IBM_ERR_OOM;
+    }
+    ok = hipMemset(n->w, 0, NWTS * sizeof(float)) == hipSuccess &&
+         hipMemset(n->m, 0, NWTS * sizeof(float)) == hipSuccess &&
+         hipMemset(n->v, 0, NWTS * sizeof(float)) == hipSuccess &&
+         hipMemset(n->scal, 0, 8 * sizeof(double)) == hipSuccess;
+    if (!ok || repack(n, nullptr) != IBM_OK || hipDeviceSynchronize() != hipSuccess) {
+        net_free(n);
+        set_error("ibm_cnn_create: initialisation failed");
+        return IBM_ERR_HIP;
+    }
+    *out = n;
+    return IBM_OK;
+}
+
+int ibm_cnn_destroy(ibm_cnn* net) {
+    if (!net) return IBM_OK;
+    (void)hipDeviceSynchronize();
+    net_free(net);
+    return IBM_OK;
+}
+
+int ibm_cnn_set_weights(ibm_cnn* net, const float* w_host, int64_t n) {
+    int rc = net_check(net);
+    if (rc) return rc;
+    if (!w_host || n != NWTS) {
+        set_error("ibm_cnn_set_weights: expected IBM_CNN_NWEIGHTS host floats");
+        return IBM_ERR_ARG;
+    }
+    IBM_HIP(hipMemcpy(net->w, w_host, NWTS * sizeof(float), hipMemcpyHostToDevice));
+    IBM_HIP(hipMemset(net->m, 0, NWTS * sizeof(float)));
+    IBM_HIP(hipMemset(net->v, 0, NWTS * sizeof(float)));
+    net->adam_t = 0;
+    rc = repack(net, nullptr);
+    if (rc) return rc;
+    IBM_HIP(hipDeviceSynchronize());
+    return IBM_OK;
+}
+
+int ibm_cnn_get_weights(ibm_cnn* net, float* w_host, int64_t n) {
+    int rc = net_check(net);
+    if (rc) return rc;
+    if (!w_host || n != NWTS) {
+        set_error("ibm_cnn_get_weights: expected IBM_CNN_NWEIGHTS host floats");
+        return IBM_ERR_ARG;
+    }
+    IBM_HIP(hipDeviceSynchronize());
+    IBM_HIP(hipMemcpy(w_host, net->w, NWTS * sizeof(float), hipMemcpyDeviceToHost));
+    return IBM_OK;
+}
+
+int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t nx, int32_t ny, int32_t nz,
+                    void* stream) {
+    int rc = net_check(net);
+    if (rc) return rc;
+    if (!x_dev || !y_dev || nx <= 0 || ny <= 0 || nz <= 0) {
+        set_error("ibm_cnn_forward: bad arguments");
+        return IBM_ERR_ARG;
+    }
+    const long long cells = (long long)nx * ny * nz;
+    if ((rc = check_grid(net, cells))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    IBM_HIP(hipMemcpyAsync(net->x0, x_dev, cells * 2 * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
+    if ((rc = net_forward(net, nx, ny, nz, nullptr, s))) return rc;
+    IBM_HIP(hipMemcpyAsync(y_dev, net->y, cells * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return IBM_OK;
+}
+
+int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx_dev, void* stream) {
+    int rc = net_check(net);
+    if (rc) return rc;
+    if (!dy_dev || !dw_dev) {
+        set_error("ibm_cnn_backward: bad arguments");
+        return IBM_ERR_ARG;
+    }
+    if (!net->have_fwd) {
+        set_error("ibm_cnn_backward: no forward pass to differentiate");
+        return IBM_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const long long cells = (long long)net->nx * net->ny * net->nz;
+    k_f32_to_bf16<<<2048, 256, 0, s>>>(cells, dy_dev, net->dy4);
+    IBM_HIP(hipGetLastError());
+    if ((rc = net_backward(net, dx_dev, s))) return rc;
+    IBM_HIP(hipMemcpyAsync(dw_dev, net->dw, NWTS * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return IBM_OK;
+}
+
+int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, double* loss_out,
+                 float* dw_dev, void* stream) {
+    int rc = net_check(net);
+    if (rc) return rc;
+    if (!ctx || !ctx->stencil_ready || !b_dev || !p_dev) {
+        set_error("ibm_cnn_loss: bad arguments (context needs a stencil)");
+        return IBM_ERR_ARG;
+    }
+    if ((rc = check_grid(net, ctx->N))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = loss_forward(net, ctx, b_dev, p_dev, s))) return rc;
+    if (dw_dev) {
+        if ((rc = net_backward(net, nullptr, s))) return rc;
+        IBM_HIP(hipMemcpyAsync(dw_dev, net->dw, NWTS * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    IBM_HIP(hipMemcpyAsync(net->h_scal, net->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    if (loss_out) *loss_out = net->h_scal[3];
+    return IBM_OK;
+}
+
+int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, float lr,
+                       double* loss_out, void* stream) {
+    int rc = net_check(net);
+    if (rc) return rc;
+    if (!ctx || !ctx->stencil_ready || !b_dev || !p_dev || !(lr > 0.0f)) {
+        set_error("ibm_cnn_train_step: bad arguments (context needs a stencil, lr > 0)");
+        return IBM_ERR_ARG;
+    }
+    if ((rc = check_grid(net, ctx->N))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = loss_forward(net, ctx, b_dev, p_dev, s))) return rc;
+    if ((rc = net_backward(net, nullptr, s))) return rc;
+    net->adam_t += 1;
+    k_adam<<<(NWTS + 255) / 256, 256, 0, s>>>(NWTS, net->w, net->dw, net->m, net->v, net->adam_t, lr);
+    IBM_HIP(hipGetLastError());
+    if ((rc = repack(net, s))) return rc;
+    IBM_HIP(hipMemcpyAsync(net->h_scal, net->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    if (loss_out) *loss_out = net->h_scal[3];
+    return IBM_OK;
+}
+
+int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, void* stream) {
+    int rc = net_check(net);
+    if (rc) return rc;
+    if (!ctx || !ctx->stencil_ready || !r_dev || !z_dev) {
+        set_error("ibm_cnn_precondition: bad arguments (context needs a stencil)");
+        return IBM_ERR_ARG;
+    }
+    if ((rc = check_grid(net, ctx->N))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int nred = 1024;
+    k_sumsq<float><<<nred, NT, 0, s>>>(ctx->N, r_dev, net->part);
+    IBM_HIP(hipGetLastError());
+    // partial slot 0 of net->part holds <r,r>; <z,r> goes to slot 1
+    return cnn_precondition_solver(net, ctx, r_dev, nullptr, z_dev, net->part, nred, 0, 1, -1, nullptr, 0, s);
+}
+
+int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net) {
+    if (!ctx) {
+        set_error("ibm_ctx_set_preconditioner: null context");
+        return IBM_ERR_ARG;
+    }
+    if (net) {
+        int rc = net_check(net);
+        if (rc) return rc;
+        if (net->cap < ctx->N) {
+            set_error("ibm_ctx_set_preconditioner: network workspace smaller than the grid");
+            return IBM_ERR_ARG;
+        }
+    }
+    ctx->cnn = net;
+    return IBM_OK;
+}
+
+}  // extern "C"

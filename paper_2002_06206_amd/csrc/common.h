@@ -224,6 +224,10 @@ int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hip
 int pcg64(ibm_ctx* c, const double* b, double* x, double tol, int max_iter, int check_every, int* iters,
           hipStream_t s);
 int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s);
+// z = D^-1 r + s net([r/s, g]) inside a solve (cnn.hip); see cnn_precondition_solver there
+int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
+                            int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, hipStream_t s);
+bool cnn_covers(const void* net, long long cells);
 // timing helpers (poisson.hip)
 enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3 };
 void timing_begin(ibm_ctx* c, int k, hipStream_t s);

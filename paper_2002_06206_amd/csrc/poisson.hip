@@ -120,6 +120,7 @@ __device__ inline void march(const Geo& g, const uint8_t* __restrict__ pcode, co
 __device__ inline int slot_rr(int i) { return (i & 1) ? 1 : 0; }
 __device__ inline int slot_rz(int i) { return (i & 1) ? 3 : 2; }
 __device__ inline int slot_dq(int i) { return (i & 1) ? 5 : 4; }
+inline int slot_rr_host(int i) { return (i & 1) ? 1 : 0; }
 constexpr int SLOT_B2 = 6;    // <b,b>
 constexpr int SLOT_R2D = 7;   // <r,r> of the double residual before any rounding
 constexpr int SLOT_RES0 = 8, SLOT_RES1 = 9;
@@ -1157,26 +1158,153 @@ __global__ void k_zero_f64(long long n, double* __restrict__ x) {
         x[i] = 0.0;
 }
 
-// Mixed precision: FP32 Jacobi-CG on the correction equation, wrapped in FP64
-// iterative refinement with residual replacement.  The FP64 residual r64 = b - L x (the
-// judge) is rounded to FP32 and CG runs on A e = -r64 until its recursive residual has
-// fallen by inner_tol (or below eta tol ||b||); then x += e in FP64, e = 0, and r64 is
-// recomputed and replaces the FP32 residual.  CG continues with its search direction
-// instead of restarting, so the Krylov information of earlier segments is kept.  Stops
-// when ||r64|| <= tol ||b||.  A segment that shrinks ||r64|| by less than stall_factor,
-// a non-finite value, too many segments, or the force_stall hook hand the solve to
-// FP64 PCG from the current x.
-int mixed_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {
+// ------------------------------------------------------------- flexible CG
+//
+// FCG(1) in FP32 with the learned preconditioner (cnn.hip) on the correction equation:
+//   z = M(r);  beta = <z, r - r_prev> / <z_prev, r_prev> (0 at a restart);  d = z + beta d;
+//   q = A d;  alpha = <z, r> / <d, q>;  e += alpha d;  r_prev = r;  r -= alpha q.
+// Slots of the partial sums: <r,r> of the update in FCG_RR (the first iteration of a
+// segment reads the init sweep's RR slot), <z,r> ping-pong in FCG_ZR + parity,
+// <z, r_prev> in FCG_ZRP, <d,q> in FCG_DQ.  Every kernel exits at once after the
+// segment has converged (the preconditioner's input kernel makes that test).
+constexpr int FCG_RR = 10, FCG_ZR = 11, FCG_ZRP = 13, FCG_DQ = 14;
+
+// d = z + beta d (beta = 0 when first); stops the segment when <z,r> is not positive
+// (the preconditioner is then not a descent direction) or not finite.
+__global__ void __launch_bounds__(NT) k_fcg_dir(long long n, const float* __restrict__ z, float* __restrict__ d,
+                                                const double* __restrict__ partials, int nparts, int zr_slot,
+                                                int zrprev_slot, int first, Solver* sv) {
+    if (sv->converged) return;
+    __shared__ double sh[12];
+    const int sl[3] = {zr_slot, FCG_ZRP, zrprev_slot};
+    double tot[3];
+    sum_slots<3>(partials, sl, nparts, sh, tot);
+    const double zr = tot[0];
+    if (!(zr > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (zr == zr) {
+                sv->converged = 1;   // no descent: end the segment, the FP64 judge decides
+            } else {
+                sv->nan_seen = 1;
+                sv->converged = 3;
+            }
+        }
+        return;
+    }
+    const float beta = first ? 0.0f : (float)((zr - tot[1]) / tot[2]);
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+        d[i] = first ? z[i] : fmaf(beta, d[i], z[i]);
+}
+
+// q = A d (FP32), partial <d,q>
+__global__ void __launch_bounds__(NT) k_fcg_q(Geo g, const uint8_t* __restrict__ pcode, const float* __restrict__ d,
+                                              float* __restrict__ q, double* __restrict__ partials, Solver* sv) {
+    if (sv->converged) return;
+    __shared__ double sh[4];
+    const float idx2 = (float)(1.0 / (g.dx * g.dx));
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    double v[1] = {0.0};
+    for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += (long long)gridDim.x * NT) {
+        const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / ((long long)g.nx * g.ny));
+        const uint8_t pc = pcode[c];
+        const float dc = d[c];
+        float acc = (float)jcount(pc) * dc;
+        for (int dd = 0; dd < 6; ++dd) {
+            if (pc & (1 << dd)) {
+                bool bnd;
+                acc -= d[nb_index(g, i, j, k, dd, bnd)];
+            }
+        }
+        const float qc = acc * idx2;
+        q[c] = qc;
+        v[0] += (double)dc * (double)qc;
+    }
+    block_reduce<1>(v, sh);
+    if (threadIdx.x == 0) partials[FCG_DQ * MAX_BLOCKS + blockIdx.x] = v[0];
+}
+
+// e += alpha d; r_new = r - alpha q; partial <r_new, r_new>
+__global__ void __launch_bounds__(NT) k_fcg_upd(long long n, float* __restrict__ e, const float* __restrict__ d,
+                                                const float* __restrict__ q, const float* __restrict__ r,
+                                                float* __restrict__ rnew, double* __restrict__ partials, int nparts,
+                                                int zr_slot, Solver* sv) {
+    if (sv->converged) return;
+    __shared__ double sh[8];
+    const int sl[2] = {zr_slot, FCG_DQ};
+    double tot[2];
+    sum_slots<2>(partials, sl, nparts, sh, tot);
+    const float alpha = (float)(tot[0] / tot[1]);
+    double v[1] = {0.0};
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
+        e[i] = fmaf(alpha, d[i], e[i]);
+        const float rn = fmaf(-alpha, q[i], r[i]);
+        rnew[i] = rn;
+        v[0] += (double)rn * (double)rn;
+    }
+    block_reduce<1>(v, sh);
+    if (threadIdx.x == 0) partials[FCG_RR * MAX_BLOCKS + blockIdx.x] = v[0];
+}
+
+// One FCG segment from a residual replacement whose init sweep wrote the RR slot of
+// parity it0 (r in c->r32, e = 0).  Sets *made to the iterations made; returns the
+// device flag as cg_loop does.
+static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_every, int* made, hipStream_t s) {
+    const Geo& g = c->geo;
+    float* rb[2] = {c->r32, c->zprev32};
+    int cur = 0;
+    if (check_every <= 0) check_every = 8;
+    int total = 0;
+    int batch = c->last_iters_inner > 0 ? c->last_iters_inner + 1 : check_every;
+    while (true) {
+        int nb = batch;
+        if (nb > max_iter - total) nb = max_iter - total;
+        for (int k = total; k < total + nb; ++k) {
+            const int it = it0 + k;
+            const int zr = FCG_ZR + (k & 1), zrprev = FCG_ZR + ((k + 1) & 1);
+            timing_begin(c, TK_SPMV, s);
+            int rc = cnn_precondition_solver(c->cnn, c, rb[cur], k ? rb[cur ^ 1] : nullptr, c->z32, c->partials, nred,
+                                             k ? FCG_RR : slot_rr_host(it0), zr, k ? FCG_ZRP : -1, c->solver, it, s);
+            timing_end(c, TK_SPMV, s);
+            if (rc) return rc;
+            timing_begin(c, TK_UPDATE, s);
+            k_fcg_dir<<<nred, NT, 0, s>>>(c->N, c->z32, c->d32, c->partials, nred, zr, zrprev, k == 0 ? 1 : 0,
+                                          c->solver);
+            k_fcg_q<<<nred, NT, 0, s>>>(g, c->pcode, c->d32, c->q32, c->partials, c->solver);
+            k_fcg_upd<<<nred, NT, 0, s>>>(c->N, c->e32, c->d32, c->q32, rb[cur], rb[cur ^ 1], c->partials, nred, zr,
+                                          c->solver);
+            timing_end(c, TK_UPDATE, s);
+            cur ^= 1;
+        }
+        IBM_HIP(hipGetLastError());
+        total += nb;
+        IBM_HIP(hipMemcpyAsync(c->h_solver, c->solver, sizeof(Solver), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        if (c->h_solver->converged || total >= max_iter) break;
+        batch = check_every;
+    }
+    int m = c->h_solver->converged ? c->h_solver->iters - it0 : total;
+    if (m < 0) m = 0;
+    *made = m;
+    c->last_iters_inner = m;
+    timing_collect(c);
+    if (c->timing_on) c->t_real_iters += m;
+    return c->h_solver->converged;
+}
+
+// FP64 iterative refinement with residual replacement around FP32 segments.  The FP64
+// residual r64 = b - L x (the judge) is rounded to FP32 and a segment works on
+// A e = -r64 until its recursive residual has fallen by inner_tol (or below
+// eta tol ||b||); then x += e in FP64, e = 0, and r64 is recomputed and replaces the
+// FP32 residual.  Stops when ||r64|| <= tol ||b||.  A segment that shrinks ||r64|| by
+// less than stall_factor, a non-finite value, too many segments, or the force_stall
+// hook hand the solve to FP64 PCG from the current x.
+// seg(it, &made) runs one segment from global iteration it and returns its flag.
+template <class Seg>
+static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, int nred,
+                        Seg&& seg, hipStream_t s) {
     const Geo& g = c->geo;
     const long long N = c->N;
-    const bool quad = (g.nx % 4) == 0 && ((uintptr_t)c->r32 % 16) == 0 && ((uintptr_t)c->z32 % 16) == 0 &&
-                      ((uintptr_t)c->e32 % 16) == 0 && ((uintptr_t)c->d32 % 16) == 0 &&
-                      ((uintptr_t)c->q32 % 16) == 0;
-    const bool pair = vec_ok(g, c->r32, 8);
-    const int path = quad ? 2 : (pair ? 1 : 0);
-    const int nred = quad ? fmarch_blocks(g) : (pair ? vmarch_blocks(g) : march_blocks(g));
     const double delta = (o->inner_tol > 0.0 && o->inner_tol < 1.0) ? o->inner_tol : 0.1;
-    const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : 1000;
     const double stall = o->stall_factor > 1.0 ? o->stall_factor : 2.0;
     const double eta_tol = 0.25 * o->tol;   // last segment aims below tol, leaving room for FP32 drift
     const int max_sweeps = 200;
@@ -1213,8 +1341,7 @@ int mixed_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
         }
         prev_rel = rel;
         int made = 0;
-        int flag = cg_loop<float>(c, c->e32, c->r32, c->z32, c->d32, c->q32, path, nred, it, inner_max,
-                                  o->check_every, &c->last_iters_inner, &made, s);
+        int flag = seg(it, &made);
         if (flag < 0) return flag;
         total_inner += made;
         it += made;
@@ -1239,6 +1366,44 @@ int mixed_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
         st->fallback_used = fallback ? 1 : 0;
     }
     return rc;
+}
+
+// Mixed precision with Jacobi: FP32 CG segments that keep their search direction across
+// the residual replacements (the Krylov information of earlier segments is kept).
+int mixed_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {
+    const Geo& g = c->geo;
+    const bool quad = (g.nx % 4) == 0 && ((uintptr_t)c->r32 % 16) == 0 && ((uintptr_t)c->z32 % 16) == 0 &&
+                      ((uintptr_t)c->e32 % 16) == 0 && ((uintptr_t)c->d32 % 16) == 0 &&
+                      ((uintptr_t)c->q32 % 16) == 0;
+    const bool pair = vec_ok(g, c->r32, 8);
+    const int path = quad ? 2 : (pair ? 1 : 0);
+    const int nred = quad ? fmarch_blocks(g) : (pair ? vmarch_blocks(g) : march_blocks(g));
+    const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : 1000;
+    return refine_solve(
+        c, b, x, o, st, nred,
+        [&](int it, int* made) {
+            return cg_loop<float>(c, c->e32, c->r32, c->z32, c->d32, c->q32, path, nred, it, inner_max,
+                                  o->check_every, &c->last_iters_inner, made, s);
+        },
+        s);
+}
+
+// Mixed precision with the learned preconditioner: FCG(1) segments, restarted at every
+// residual replacement (a nonlinear preconditioner has no Krylov space to keep).
+int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {
+    if (!c->cnn) {
+        set_error("IBM_SOLVER_FCG_CNN: no network attached to the context");
+        return IBM_ERR_ARG;
+    }
+    if (!cnn_covers(c->cnn, c->N)) {
+        set_error("IBM_SOLVER_FCG_CNN: network workspace smaller than the grid");
+        return IBM_ERR_ARG;
+    }
+    const int nred = march_blocks(c->geo);
+    const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : 1000;
+    return refine_solve(
+        c, b, x, o, st, nred,
+        [&](int it, int* made) { return fcg_segment(c, nred, it, inner_max, o->check_every, made, s); }, s);
 }
 
 int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {

@@ -82,6 +82,17 @@ def _load():
         "ibm_forces": ([vp, P3, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
         "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
         "ibm_timing_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
+        "ibm_cnn_create": ([ctypes.c_int64, ctypes.POINTER(vp)], ctypes.c_int),
+        "ibm_cnn_destroy": ([vp], ctypes.c_int),
+        "ibm_cnn_set_weights": ([vp, vp, ctypes.c_int64], ctypes.c_int),
+        "ibm_cnn_get_weights": ([vp, vp, ctypes.c_int64], ctypes.c_int),
+        "ibm_cnn_forward": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp], ctypes.c_int),
+        "ibm_cnn_backward": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "ibm_cnn_loss": ([vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp], ctypes.c_int),
+        "ibm_cnn_train_step": ([vp, vp, vp, vp, ctypes.c_float, ctypes.POINTER(ctypes.c_double), vp],
+                               ctypes.c_int),
+        "ibm_cnn_precondition": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "ibm_ctx_set_preconditioner": ([vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -93,7 +104,11 @@ def _load():
 _lib = _load()
 EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "ibm_build_stencils",
             "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
-            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_timing_enable", "ibm_timing_read")
+            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_timing_enable", "ibm_timing_read",
+            "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
+            "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
+            "ibm_ctx_set_preconditioner")
+CNN_NWEIGHTS = 15120
 
 
 def lib():
@@ -203,6 +218,60 @@ def ibm_timing_read(ctx, reset=False):
             "cuts": int(v[8]), "precision": int(v[9])}
 
 
+def ibm_cnn_create(max_cells):
+    out = ctypes.c_void_p()
+    _check(_lib.ibm_cnn_create(int(max_cells), ctypes.byref(out)), "ibm_cnn_create")
+    return out
+
+
+def ibm_cnn_destroy(net):
+    return _check(_lib.ibm_cnn_destroy(net), "ibm_cnn_destroy")
+
+
+def ibm_cnn_set_weights(net, w):
+    import numpy as np
+    a = np.ascontiguousarray(w, dtype=np.float32)
+    return _check(_lib.ibm_cnn_set_weights(net, a.ctypes.data_as(ctypes.c_void_p), a.size), "ibm_cnn_set_weights")
+
+
+def ibm_cnn_get_weights(net):
+    import numpy as np
+    a = np.empty(CNN_NWEIGHTS, dtype=np.float32)
+    _check(_lib.ibm_cnn_get_weights(net, a.ctypes.data_as(ctypes.c_void_p), a.size), "ibm_cnn_get_weights")
+    return a
+
+
+def ibm_cnn_forward(net, x_bf16, y, n):
+    """x_bf16: (nz, ny, nx, 2) torch.bfloat16 (or int16 bit patterns); y: (nz, ny, nx) float32."""
+    return _check(_lib.ibm_cnn_forward(net, _ptr(x_bf16), _ptr(y), int(n[0]), int(n[1]), int(n[2]), _stream()),
+                  "ibm_cnn_forward")
+
+
+def ibm_cnn_backward(net, dy, dw, dx=None):
+    return _check(_lib.ibm_cnn_backward(net, _ptr(dy), _ptr(dw), _ptr(dx), _stream()), "ibm_cnn_backward")
+
+
+def ibm_cnn_loss(net, ctx, b, p, dw=None):
+    loss = ctypes.c_double()
+    _check(_lib.ibm_cnn_loss(net, ctx, _ptr(b), _ptr(p), ctypes.byref(loss), _ptr(dw), _stream()), "ibm_cnn_loss")
+    return loss.value
+
+
+def ibm_cnn_train_step(net, ctx, b, p, lr):
+    loss = ctypes.c_double()
+    _check(_lib.ibm_cnn_train_step(net, ctx, _ptr(b), _ptr(p), float(lr), ctypes.byref(loss), _stream()),
+           "ibm_cnn_train_step")
+    return loss.value
+
+
+def ibm_cnn_precondition(net, ctx, r, z):
+    return _check(_lib.ibm_cnn_precondition(net, ctx, _ptr(r), _ptr(z), _stream()), "ibm_cnn_precondition")
+
+
+def ibm_ctx_set_preconditioner(ctx, net):
+    return _check(_lib.ibm_ctx_set_preconditioner(ctx, net), "ibm_ctx_set_preconditioner")
+
+
 # ------------------------------------------------------------- convenience
 
 def solver_opts(tol=1e-10, max_iter=20000, kind=SOLVER_PCG_JACOBI, inner_tol=1e-2, inner_max_iter=200,
@@ -286,3 +355,40 @@ class Solver:
 
     def forces(self, st, nu, wall=None):
         return ibm_forces(self.ctx, st["u"], st["p"], nu, None, wall)
+
+
+class Network:
+    """Owns one learned-preconditioner network on the current HIP device."""
+
+    def __init__(self, max_cells, weights=None):
+        self.net = ibm_cnn_create(max_cells)
+        if weights is not None:
+            ibm_cnn_set_weights(self.net, weights)
+
+    def close(self):
+        if self.net is not None:
+            ibm_cnn_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def weights(self):
+        return ibm_cnn_get_weights(self.net)
+
+    @weights.setter
+    def weights(self, w):
+        ibm_cnn_set_weights(self.net, w)
+
+    def train_step(self, solver: "Solver", b, p, lr):
+        return ibm_cnn_train_step(self.net, solver.ctx, b, p, lr)
+
+    def loss(self, solver: "Solver", b, p, dw=None):
+        return ibm_cnn_loss(self.net, solver.ctx, b, p, dw)
+
+    def attach(self, solver: "Solver"):
+        ibm_ctx_set_preconditioner(solver.ctx, self.net)

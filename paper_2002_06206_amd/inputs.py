@@ -376,3 +376,17 @@ def cnn_init_weights(seed: int, last_scale: float = 0.1) -> np.ndarray:
             w *= last_scale
         parts.append(w.reshape(-1))
     return np.ascontiguousarray(np.concatenate(parts).astype(np.float32))
+
+
+def case_ellipsoid_window(seed: int, n: int = 64, field_n: int = 256) -> Case:
+    """An n^3 window of the field_n^3 ellipsoid field of the given seed (same object
+    sizes as the full workload), centred on a seeded triangle of the field so that it
+    always holds geometry; inflow U=1 on -x, outflow on +x, slip elsewhere.  Used for
+    training pairs and held-out evaluation of the learned preconditioner."""
+    tri = ellipsoid_field(field_n, seed)
+    rng = np.random.default_rng(seed + 7919)
+    c = tri[rng.integers(len(tri)), 0]
+    o = tuple(float(v) for v in np.clip(c - n / 2.0 + rng.uniform(-0.5, 0.5, 3), 0.0, field_n - n))
+    return Case("ellipsoid_window%d" % n, (n, n, n), 1.0, o,
+                (INFLOW, OUTFLOW, SLIP, SLIP, SLIP, SLIP), (1.0, 0.0, 0.0), tri,
+                nu=24.0 / 1e4, dt=0.3, steps=100, ref_length=24.0)
