@@ -40,8 +40,8 @@ SWEEP_BYTES_F32 = {"pcg_a": 21, "pcg_b": 17, "unused": 0}
 KERNEL_SYMBOL = {"pcg_a": "k_pcg_a_v<double, false>", "pcg_b": "k_pcg_b_v<double>", "unused": ""}
 # the FP32 correction sweeps of the mixed solve (nx divisible by 4)
 KERNEL_SYMBOL_F32 = {"pcg_a": "k_pcg_a_f4<false>", "pcg_b": "k_pcg_b_f4", "unused": ""}
-# algorithmic FLOPs of one network application per cell: 2 * 27 * (2*16 + 16*16 + 16*16 + 16*1)
-CNN_FLOP_PER_CELL = 30240
+# algorithmic FLOPs of one network application per cell: 2 * 27 * (16 + 256 + 256 + 16)
+CNN_FLOP_PER_CELL = 29376
 BF16_PEAK_TFLOPS = 2500.0
 
 
@@ -220,7 +220,7 @@ def train_network(args, ibm, torch):
     data = train.build_dataset(train.TRAIN_SEEDS, 64)
     held = train.build_dataset(train.EVAL_SEEDS, 64)
     t1 = time.perf_counter()
-    net = ibm.Network(64 ** 3, inputs.cnn_init_weights(0, last_scale=0.01))
+    net = ibm.Network(64 ** 3, inputs.cnn_init_weights(0))
     before = train.mean_loss(net, held)
     train.train(net, data, args.train_iters, args.train_lr)
     after = train.mean_loss(net, held)

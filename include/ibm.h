@@ -202,36 +202,40 @@ int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const vo
 /* ---- Learned preconditioner (an extension layered on the pressure solve of
  * eq. (poisson); the paper itself uses plain Krylov solves).
  *
- * Network: four 3x3x3 convolutions, 2 -> 16 -> 16 -> 16 -> 1 channels, ReLU after the
- * first three, zero padding at the grid faces, no biases.  As the preconditioner of
- * IBM_SOLVER_FCG_CNN it maps a residual r to
- *     z = D^-1 r + s * net([r / s, g]),   s = RMS of r over the cells,
- * D the diagonal of A = -L and g the open-face fraction of the cell (open pressure
- * faces / 6).  All weights zero gives Jacobi.
- * Weights: IBM_CNN_NWEIGHTS floats, per layer w[t][ci][co] (row-major) with tap
- * t = (dz+1)*9 + (dy+1)*3 + (dx+1) for offsets in {-1,0,1}; layers in order at
- * offsets 0, 864, 7776, 14688.  The FP32 master copy lives on the device.
- * Arithmetic: BF16 operands on the matrix cores with FP32 accumulation; hidden
- * activations and backward signals are stored in BF16 (channels-last).
+ * Operator: a linear, symmetric positive semi-definite convolutional network of four
+ * 3x3x3 convolutions with 16 channels and a geometry gate,
+ *     G = sigmoid(Wg * g),  K x = W2 * ((W1 * x) . G),  net(x) = K^T K x,
+ * with g the open-face fraction of the cell (open pressure faces / 6), "*" a
+ * zero-padded 3x3x3 cross-correlation (taps at the grid faces are zero), K^T the
+ * adjoint (flipped, transposed convolutions) and "." the per-channel product.  As the
+ * preconditioner of IBM_SOLVER_FCG_CNN it maps a residual r to
+ *     z = D^-1 r + s * net(r / s),   s = RMS of r over the cells,
+ * D the diagonal of A = -L (symmetric positive definite; Jacobi for zero weights).
+ * Weights: IBM_CNN_NWEIGHTS floats: W1[t][0][co] (432 at offset 0), W2[t][ci][co]
+ * (6912 at 432), Wg[t][0][co] (432 at 7344), row-major, tap
+ * t = (dz+1)*9 + (dy+1)*3 + (dx+1) for offsets in {-1,0,1}.  The FP32 master copy
+ * lives on the device.
+ * Arithmetic: BF16 operands on the matrix cores with FP32 accumulation; activations
+ * and backward signals are stored in BF16 (channels-last).
  * Field buffers are device memory, x fastest (cell c = i + nx*(j + ny*k)). */
-#define IBM_CNN_NWEIGHTS 15120
+#define IBM_CNN_NWEIGHTS 7776
 typedef struct ibm_cnn ibm_cnn;
 
 /* Creates a network on the current HIP device with all weights zero and workspace for
- * grids of up to max_cells cells (about 200 bytes per cell). */
+ * grids of up to max_cells cells (about 380 bytes per cell). */
 int ibm_cnn_create(int64_t max_cells, ibm_cnn** out);
 int ibm_cnn_destroy(ibm_cnn* net);
 /* Host FP32 weights in, n = IBM_CNN_NWEIGHTS; resets the Adam state.  Synchronous. */
 int ibm_cnn_set_weights(ibm_cnn* net, const float* w_host, int64_t n);
 int ibm_cnn_get_weights(ibm_cnn* net, float* w_host, int64_t n);
-/* Network output y (cells floats) for the input x (cells x 2 BF16 bit patterns,
- * channels-last) on an nx x ny x nz grid.  Keeps the activations for
- * ibm_cnn_backward. */
+/* Network output y = net(x) (cells floats) for the input x_dev = cells x 2 BF16 bit
+ * patterns (channel 0 = x, channel 1 = g) on an nx x ny x nz grid.  Keeps the
+ * activations for ibm_cnn_backward. */
 int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t nx, int32_t ny, int32_t nz,
                     void* stream);
 /* Backward pass of the last forward for a scalar J with dJ/dy = dy (cells floats,
  * rounded to BF16): dJ/dw into dw_dev (IBM_CNN_NWEIGHTS floats, weight layout) and,
- * when dx_dev != NULL, dJ/dx (cells x 2 floats). */
+ * when dx_dev != NULL, dJ/dx and dJ/dg interleaved (cells x 2 floats). */
 int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx_dev, void* stream);
 /* Training loss of one pair (b, p) with L p = b on the context's stencil: with
  * f = -b and h = the preconditioned f,  loss = 1 - (f.h)^2 / ((f.p)(h.A h)), the
@@ -244,7 +248,7 @@ int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* 
  * gets the loss before the update.  Synchronises the stream. */
 int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, float lr,
                        double* loss_out, void* stream);
-/* z = D^-1 r + s net([r/s, g]) on the context's grid (r, z: cells floats). */
+/* z = D^-1 r + s net(r/s) on the context's grid and geometry (r, z: cells floats). */
 int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, void* stream);
 /* Preconditioner used by IBM_SOLVER_FCG_CNN on this context (NULL detaches); the network
  * must cover the grid and outlive its use. */

@@ -3,31 +3,39 @@ pressure solve (test infrastructure only; the product path never imports it).
 
 What is computed:
 
-* A 3-D convolutional network of four 3x3x3 layers, 2 -> 16 -> 16 -> 16 -> 1
-  channels, ReLU after the first three, zero padding at the domain faces, no
-  biases.  Input channels: the residual scaled by its RMS, and the fraction of
-  the six pressure faces of the cell that are open (geometry).
-* The preconditioner  z = D^-1 r + s * net([r / s, g]),  s = RMS(r), D the
-  diagonal of the pressure operator A = -L.  With all weights zero it is Jacobi.
+* A linear, symmetric positive semi-definite convolutional operator built from
+  four 3x3x3 convolutions with 16 channels and a geometry gate:
+      G      = sigmoid(Wg * g)                      (16 channels, per geometry)
+      K x    = W2 * ((W1 * x) . G)                  (1 -> 16 channels)
+      K^T y  = W1^T * ((W2^T * y) . G)              (16 -> 1, adjoint convolutions)
+      net(x) = K^T K x
+  with g the fraction of the six faces of a cell that are open pressure faces, "*"
+  a zero-padded 3x3x3 cross-correlation, "^T *" its adjoint and "." the
+  per-channel product.  The operator is linear in x, so a Krylov method sees a
+  fixed preconditioner; x^T net(x) = |K x|^2 >= 0.
+* The preconditioner  z = D^-1 r + s * net(r / s),  s = RMS(r), D the diagonal of
+  the pressure operator A = -L: symmetric positive definite, Jacobi when the
+  weights are zero.  (Dividing by s only keeps BF16 activations near unit size;
+  in exact arithmetic s * net(r/s) = net(r).)
 * Training loss for one (b, p) pair of the pressure equation L p = b, i.e.
   A p = f with f = -b:  the A-norm distance of p from the best multiple of the
   preconditioned right-hand side p_hat = M(f),
       loss = min_a |p - a p_hat|_A^2 / |p|_A^2 = 1 - (f.p_hat)^2 / ((f.p)(p_hat.A p_hat)),
   which is invariant to the scale of p_hat, as is the Krylov method it serves.
 * Adam (Kingma and Ba, 2015) and flexible conjugate gradients FCG(1) (Notay,
-  2000: the Polak-Ribiere form of beta), the Krylov method that tolerates a
-  preconditioner that changes from one iteration to the next.
+  2000: the Polak-Ribiere form of beta), which tolerates the small asymmetry that
+  BF16 rounding leaves in the preconditioner.
 
-The paper itself runs plain CG-type pressure solves on CPU clusters; this part is
-the learned extension layered on its pressure solve (sec. on the fractional step:
-the pressure Poisson equation).  Rounding points that the GPU path takes in BF16
-(activations, input, output gradient) are reproduced by `bf16_round` when
+The paper itself runs plain Krylov pressure solves on CPU clusters; this part is
+the learned extension layered on its pressure solve (eq. (poisson)).  Rounding
+points that the GPU path takes in BF16 (network input, gate, every stored
+activation and backward signal, weights) are reproduced by `bf16_round` when
 `bf16=True`; with `bf16=False` everything is FP64.
 
-Weight layout (also the flat FP32 layout the C ABI takes): per layer, an array
-w[t, ci, co], tap t = (dz+1)*9 + (dy+1)*3 + (dx+1) for offsets dx, dy, dz in
-{-1, 0, 1}; layers concatenated in order.  Fields are numpy arrays shaped
-(nz, ny, nx, C), x fastest in memory.
+Weight layout (also the flat FP32 layout the C ABI takes): W1[t, 0, co] (432),
+W2[t, ci, co] (6912), Wg[t, 0, co] (432), in that order, tap
+t = (dz+1)*9 + (dy+1)*3 + (dx+1) for offsets dx, dy, dz in {-1, 0, 1}.  Fields are
+numpy arrays shaped (nz, ny, nx[, C]), x fastest in memory.
 """
 from __future__ import annotations
 
@@ -35,17 +43,18 @@ import numpy as np
 
 from . import flow
 
-LAYERS = ((2, 16), (16, 16), (16, 16), (16, 1))
+# (name, input channels, output channels) of the three weight tensors
+LAYERS = (("W1", 1, 16), ("W2", 16, 16), ("Wg", 1, 16))
 TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 
 
 def n_weights() -> int:
-    return sum(27 * ci * co for ci, co in LAYERS)
+    return sum(27 * ci * co for _, ci, co in LAYERS)
 
 
 def split_weights(flat: np.ndarray) -> list:
     out, o = [], 0
-    for ci, co in LAYERS:
+    for _, ci, co in LAYERS:
         n = 27 * ci * co
         out.append(np.asarray(flat[o:o + n], dtype=np.float64).reshape(27, ci, co))
         o += n
@@ -120,40 +129,62 @@ def conv_backward_weight(x: np.ndarray, dy: np.ndarray) -> np.ndarray:
 
 # ------------------------------------------------------------------ network
 
-def forward(x0: np.ndarray, ws: list, bf16: bool = False):
-    """Network output y (nz, ny, nx) and the saved activations [x0, a1, a2, a3].
-    With bf16=True the input and each hidden activation are rounded to bfloat16 and
-    the weights are taken as their bfloat16 values; sums are FP64 (exact products)."""
-    rnd = bf16_round if bf16 else (lambda v: v)
-    a = rnd(x0)
-    acts = [a]
-    for l, w in enumerate(ws):
-        z = conv_forward(a, rnd(w))
-        if l < len(ws) - 1:
-            a = rnd(np.maximum(z, 0.0))
-            acts.append(a)
-        else:
-            return z[..., 0], acts
-    raise AssertionError
+def sigmoid(v):
+    return 1.0 / (1.0 + np.exp(-v))
 
 
-def backward(acts: list, ws: list, dy: np.ndarray, bf16: bool = False):
-    """Gradients of a scalar whose gradient in the output y is dy (nz, ny, nx):
-    returns (dws, dx0).  With bf16=True the incoming gradient of every layer is
-    rounded to bfloat16 before it meets the weights or activations, as on the GPU."""
+def forward(x: np.ndarray, g: np.ndarray, ws: list, bf16: bool = False):
+    """net(x) = K^T K x (x, g: (nz, ny, nx)).  Returns (y, saved) with saved the
+    activations the backward pass needs.  With bf16=True the input, the gate and
+    every stored activation are rounded to bfloat16 and the weights taken as their
+    bfloat16 values; sums are FP64 (exact products)."""
     rnd = bf16_round if bf16 else (lambda v: v)
-    g = rnd(dy[..., None])
-    dws = [None] * len(ws)
-    dx0 = None
-    for l in range(len(ws) - 1, -1, -1):
-        w = rnd(ws[l])
-        dws[l] = conv_backward_weight(acts[l], g)
-        da = conv_backward_data(g, w)
-        if l == 0:
-            dx0 = da
-        else:
-            g = rnd(np.where(acts[l] > 0.0, da, 0.0))
-    return dws, dx0
+    W1, W2, Wg = (rnd(w) for w in ws)
+    x1 = rnd(x)[..., None]
+    g1 = rnd(g)[..., None]
+    G = rnd(sigmoid(conv_forward(g1, Wg)))
+    u1 = conv_forward(x1, W1)
+    a1 = rnd(u1 * G)
+    y = rnd(conv_forward(a1, W2))
+    v = conv_backward_data(y, W2)
+    b = rnd(v * G)
+    out = conv_backward_data(b, W1)[..., 0]
+    saved = {"x": x1, "g": g1, "G": G, "u1": rnd(u1), "a1": a1, "y": y, "v": rnd(v), "b": b}
+    return out, saved
+
+
+def backward(saved: dict, ws: list, dy: np.ndarray, bf16: bool = False):
+    """Gradients of a scalar J with dJ/d(net output) = dy (nz, ny, nx): returns
+    (dws, dx, dg) with dws = [dW1, dW2, dWg] and dx, dg the gradients in the two
+    inputs.  With bf16=True every backward signal is rounded to bfloat16 before it
+    meets weights or activations, as on the GPU."""
+    rnd = bf16_round if bf16 else (lambda v: v)
+    W1, W2, Wg = (rnd(w) for w in ws)
+    G = saved["G"]
+    go = rnd(dy[..., None])
+    # out = W1^T * b
+    dW1 = conv_backward_weight(go, saved["b"])
+    db = conv_forward(go, W1)
+    # b = v . G
+    dv = rnd(db * G)
+    dG = db * saved["v"]
+    # v = W2^T * y
+    dW2 = conv_backward_weight(dv, saved["y"])
+    dyy = rnd(conv_forward(dv, W2))
+    # y = W2 * a1
+    dW2 = dW2 + conv_backward_weight(saved["a1"], dyy)
+    da1 = conv_backward_data(dyy, W2)
+    # a1 = u1 . G
+    du1 = rnd(da1 * G)
+    dG = dG + da1 * saved["u1"]
+    # u1 = W1 * x
+    dW1 = dW1 + conv_backward_weight(saved["x"], du1)
+    dx = conv_backward_data(du1, W1)[..., 0]
+    # G = sigmoid(Wg * g)
+    dpre = rnd(dG * G * (1.0 - G))
+    dWg = conv_backward_weight(saved["g"], dpre)
+    dg = conv_backward_data(dpre, Wg)[..., 0]
+    return [dW1, dW2, dWg], dx, dg
 
 
 # ------------------------------------------------------------------ preconditioner
@@ -175,16 +206,12 @@ def rms(r: np.ndarray) -> float:
     return float(np.sqrt(np.sum(r * r) / r.size))
 
 
-def network_input(st: flow.Stencil, r: np.ndarray, s: float) -> np.ndarray:
-    return np.stack([r / s, geometry_channel(st)], axis=-1)
-
-
 def precondition(st: flow.Stencil, r: np.ndarray, ws: list, bf16: bool = False) -> np.ndarray:
-    """z = D^-1 r + s net([r/s, g]), s = RMS(r); z = 0 for r = 0."""
+    """z = D^-1 r + s net(r/s), s = RMS(r); z = 0 for r = 0."""
     s = rms(r)
     if s == 0.0:
         return np.zeros_like(r)
-    y, _ = forward(network_input(st, r, s), ws, bf16)
+    y, _ = forward(r / s, geometry_channel(st), ws, bf16)
     return jacobi_inverse(st) * r + s * y
 
 
@@ -198,7 +225,7 @@ def loss_and_grad(st: flow.Stencil, b: np.ndarray, p: np.ndarray, ws: list, bf16
     (b, p), L p = b, and its gradient in the weights.  Returns (loss, dws)."""
     f = -b
     s = rms(f)
-    y, acts = forward(network_input(st, f, s), ws, bf16)
+    y, saved = forward(f / s, geometry_channel(st), ws, bf16)
     ph = jacobi_inverse(st) * f + s * y
     q = apply_A(st, ph)
     c = float(np.sum(f * ph))
@@ -207,7 +234,7 @@ def loss_and_grad(st: flow.Stencil, b: np.ndarray, p: np.ndarray, ws: list, bf16
     loss = 1.0 - c * c / (B * Q)
     # d loss / d p_hat = (2c/(BQ)) ((c/Q) A p_hat - f), chained through p_hat = ... + s y
     gph = (2.0 * c / (B * Q)) * ((c / Q) * q - f)
-    dws, _ = backward(acts, ws, s * gph, bf16)
+    dws, _, _ = backward(saved, ws, s * gph, bf16)
     return loss, dws
 
 

@@ -2,24 +2,29 @@
 // convolutional network inside flexible CG.  The network, its training and the
 // preconditioner application live here; the Krylov loop is in poisson.hip.
 //
-// Network: four 3x3x3 convolutions, 2 -> 16 -> 16 -> 16 -> 1 channels, ReLU after the
-// first three, zero padding at the grid faces, no biases.  Input channels: the residual
-// divided by its RMS s, and the open-face fraction of the cell.  Preconditioner:
-// z = D^-1 r + s * net([r/s, g]), D the diagonal of A = -L.
+// Operator (linear and symmetric in the residual, so that a Krylov method sees a fixed
+// symmetric positive definite preconditioner):
+//   G = sigmoid(Wg * g)                  geometry gate, 16 channels, once per geometry
+//   K x = W2 * ((W1 * x) . G)            conv 1 -> 16, gate, conv 16 -> 16
+//   K^T y = W1^T * ((W2^T * y) . G)      the adjoint convolutions
+//   z = D^-1 r + s K^T K (r / s),        s = RMS(r), D the diagonal of A = -L,
+// "*" a zero-padded 3x3x3 cross-correlation, "^T *" its adjoint (flipped taps,
+// transposed channels) and "." the per-channel product; g is the open-face fraction of
+// the cell.  Four 3x3x3 convolutions with 16 channels per application.
 //
 // MI355X design:
 //  * activations channels-last in BF16: 16 channels = 32 bytes per cell, one 16-byte
 //    load per lane feeds an MFMA operand;
 //  * every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16 with FP32
 //    accumulation: M = 16 output channels, N = 16 cells along x, K = 32 = (two taps x
-//    16 input channels), 14 k-steps per 3x3x3 stencil.  The weights of a layer sit in
-//    registers for the whole block (A operand, 56 VGPRs); the input tile with its halo
-//    (34 x 10 x 6 cells) is staged once in LDS as two 16-byte half-cell planes so that
-//    the B-operand reads of 16 lanes are contiguous;
+//    16 input channels), 14 k-steps per 3x3x3 stencil (2 for one input channel).  The
+//    weights sit in registers for the whole block (A operand, 56 VGPRs); the input
+//    tile with its halo (34 x 10 x 6 cells) is staged once in LDS as two 16-byte
+//    half-cell planes so that the B-operand reads of 16 lanes are contiguous;
 //  * the output D tile gives each lane 4 consecutive channels of one cell: one 8-byte
-//    store per lane, 512 contiguous bytes per 16-cell tile;
-//  * the backward data pass is the same kernel with flipped taps and transposed
-//    weights, the ReLU mask fused into its epilogue;
+//    store per lane, 512 contiguous bytes per 16-cell tile; gating, the sigmoid and the
+//    gradient of the gate are fused into that epilogue;
+//  * an adjoint convolution is the same kernel with flipped, transposed packed weights;
 //  * the weight gradient is an implicit GEMM over cells (K = cells of the tile): both
 //    operands are staged channel-major in LDS, each block writes one partial 27x16x16
 //    gradient and a second kernel sums the partials in block order (deterministic);
@@ -47,7 +52,24 @@ constexpr int OCELLS = CTX * CTY * CTZ;   // 1024
 constexpr int MTILES = OCELLS / 16;       // 16-cell MFMA column tiles per block
 constexpr int WG_MAX_BLOCKS = 1024;       // weight-gradient partials
 
-enum { EPI_RELU = 0, EPI_MASK = 1, EPI_F32 = 2 };
+// epilogues of k_conv (acc = the FP32 convolution of the lane's 4 channels)
+enum {
+    EPI_BF16 = 0,     // out = bf16(acc)
+    EPI_GATE = 1,     // out = bf16(acc . G); aux (optional) = bf16(acc)
+    EPI_SIGMOID = 2,  // out = bf16(sigmoid(acc))
+    EPI_BGATE = 3,    // out = bf16(acc . G); dG (float) = [dG +] acc . P
+    EPI_F32 = 4       // out = acc (float, COUT channels, stride ostride)
+};
+
+// optional operands of the epilogues
+struct ConvIO {
+    const uint16_t* gate;   // G, cells x 16 BF16
+    uint16_t* aux;          // EPI_GATE: pre-gate copy, or null
+    const uint16_t* pre;    // EPI_BGATE: stored pre-gate activation P
+    float* dg;              // EPI_BGATE: gate gradient accumulator, cells x 16
+    int accum;              // EPI_BGATE: add to dg instead of overwriting
+    int ostride;            // EPI_F32: floats per cell of out
+};
 
 __host__ __device__ constexpr int ksteps(int cin) { return cin == 16 ? 14 : (27 * cin + 31) / 32; }
 
@@ -124,15 +146,26 @@ __device__ inline void tile_of(int b, int nb, int ntx, int nty, int& tx, int& ty
     tz = t / (ntx * nty);
 }
 
-// One 3x3x3 convolution layer over an nx x ny x nz grid (zero padding).
-//   in:  cells x CIN BF16 (channels-last);  wp: packed weights of the layer;
-//   EPI_RELU: out = BF16(relu(acc)), cells x 16;  EPI_MASK: out = BF16(mask > 0 ? acc : 0)
-//   with mask = cells x 16 BF16 activations;  EPI_F32: out = acc as float, cells x COUT.
+__device__ inline void unpack4(uint2 w, float (&f)[4]) {
+    f[0] = bf2f((uint16_t)(w.x & 0xFFFFu));
+    f[1] = bf2f((uint16_t)(w.x >> 16));
+    f[2] = bf2f((uint16_t)(w.y & 0xFFFFu));
+    f[3] = bf2f((uint16_t)(w.y >> 16));
+}
+__device__ inline uint2 pack4(const float (&f)[4]) {
+    uint2 o;
+    o.x = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
+    o.y = (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+    return o;
+}
+
+// One 3x3x3 convolution over an nx x ny x nz grid (zero padding): in = cells x CIN
+// BF16 (channels-last), wp = packed weights, out per the epilogue (see EPI_*).
 // sv (may be null): the solve's state; the kernel does nothing once it has converged.
 template <int CIN, int COUT, int EPI>
 __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const uint16_t* __restrict__ in,
                                                  const uint16_t* __restrict__ wp, void* __restrict__ out,
-                                                 const uint16_t* __restrict__ mask, const Solver* sv) {
+                                                 ConvIO io, const Solver* sv) {
     if (sv && sv->converged) return;
     constexpr int KS = ksteps(CIN);
     constexpr int LDS_ELEMS = CIN == 16 ? 2 * HCELLS * 8 : HCELLS * CIN;
@@ -205,28 +238,36 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
         const int gx = tx * CTX + ox, gy = ty * CTY + oy, gz = tz * CTZ + oz;
         if (gx < nx && gy < ny && gz < nz) {
             const long long c = (long long)gx + (long long)nx * ((long long)gy + (long long)ny * gz);
-            if (EPI == EPI_RELU || EPI == EPI_MASK) {
-                float v[4] = {acc[0], acc[1], acc[2], acc[3]};
-                if (EPI == EPI_RELU) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = v[r] > 0.0f ? v[r] : 0.0f;
-                } else {
-                    const uint2 mk = *reinterpret_cast<const uint2*>(mask + c * 16 + 4 * g);
-                    const uint16_t mh[4] = {(uint16_t)(mk.x & 0xFFFFu), (uint16_t)(mk.x >> 16),
-                                            (uint16_t)(mk.y & 0xFFFFu), (uint16_t)(mk.y >> 16)};
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = bf2f(mh[r]) > 0.0f ? v[r] : 0.0f;
-                }
-                uint2 o;
-                o.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
-                o.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
-                *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + c * 16 + 4 * g) = o;
-            } else {
+            if (EPI == EPI_F32) {
                 if (g == 0) {
                     float* of = static_cast<float*>(out);
 #pragma unroll
-                    for (int r = 0; r < COUT; ++r) of[c * COUT + r] = acc[r];
+                    for (int r = 0; r < COUT; ++r) of[c * io.ostride + r] = acc[r];
                 }
+            } else {
+                float v[4] = {acc[0], acc[1], acc[2], acc[3]};
+                const long long o16 = c * 16 + 4 * g;
+                if (EPI == EPI_SIGMOID) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = 1.0f / (1.0f + __expf(-v[r]));
+                } else if (EPI == EPI_GATE || EPI == EPI_BGATE) {
+                    float gt[4];
+                    unpack4(*reinterpret_cast<const uint2*>(io.gate + o16), gt);
+                    if (EPI == EPI_GATE && io.aux) *reinterpret_cast<uint2*>(io.aux + o16) = pack4(v);
+                    if (EPI == EPI_BGATE) {
+                        float pr[4];
+                        unpack4(*reinterpret_cast<const uint2*>(io.pre + o16), pr);
+                        float4 d = io.accum ? *reinterpret_cast<const float4*>(io.dg + o16) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        d.x += v[0] * pr[0];
+                        d.y += v[1] * pr[1];
+                        d.z += v[2] * pr[2];
+                        d.w += v[3] * pr[3];
+                        *reinterpret_cast<float4*>(io.dg + o16) = d;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] *= gt[r];
+                }
+                *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + o16) = pack4(v);
             }
         }
     }
@@ -306,15 +347,16 @@ __global__ void __launch_bounds__(256, 1) k_wgrad(int nx, int ny, int nz, const 
     }
 }
 
-// dW (layer layout [27][CIN][COUT]) = sum of the block partials in block order
-__global__ void k_wsum(const float* __restrict__ part, int nblocks, int cin, int cout, float* __restrict__ dw) {
+// dW (layer layout [27][CIN][COUT]) = (accum ? dW : 0) + the block partials in block order
+__global__ void k_wsum(const float* __restrict__ part, int nblocks, int cin, int cout, float* __restrict__ dw,
+                       int accum) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= 27 * cin * cout) return;
     const int co = idx % cout, ci = (idx / cout) % cin, t = idx / (cout * cin);
     const int o = t * 256 + ci * 16 + co;
     float s = 0.0f;
     for (int b = 0; b < nblocks; ++b) s += part[(long long)b * (27 * 256) + o];
-    dw[idx] = s;
+    dw[idx] = accum ? dw[idx] + s : s;
 }
 
 // ------------------------------------------------------------------ input, loss, Adam
@@ -332,13 +374,13 @@ __global__ void __launch_bounds__(NT) k_sumsq(long long n, const T* __restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-// Network input x0 = [BF16(f / s), BF16(open faces / 6)] with s^2 = (sum of the partials
-// of <f,f> in slot) / n.  With a solver state: stops the solve (sets converged) when
-// <f,f> <= tol2, and stores s for the combining step.
+// Network input x = BF16(f / s) with s^2 = (sum of the partials of <f,f>) / n.  With a
+// solver state: stops the solve (sets converged) when <f,f> <= tol2; s is stored for
+// the combining step.
 template <class T>
-__global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__ f, const uint8_t* __restrict__ pcode,
-                                              const double* __restrict__ part, int nparts, uint16_t* __restrict__ x0,
-                                              double* __restrict__ s_out, Solver* sv, int it) {
+__global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__ f, const double* __restrict__ part,
+                                              int nparts, uint16_t* __restrict__ x, double* __restrict__ s_out,
+                                              Solver* sv, int it) {
     if (sv && sv->converged) return;
     __shared__ double sh[4];
     double v[1] = {0.0};
@@ -365,12 +407,31 @@ __global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__
     }
     const double s = sqrt(ff / (double)n);
     if (blockIdx.x == 0 && threadIdx.x == 0) *s_out = s;
-    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
-        const double a = s > 0.0 ? (double)f[i] / s : 0.0;
-        const uint8_t pc = pcode[i];
-        const float gfr = (float)((double)__builtin_popcount((unsigned)(pc & 0x3F)) / 6.0);
-        const uint32_t w = (uint32_t)f2bf((float)a) | ((uint32_t)f2bf(gfr) << 16);
-        reinterpret_cast<uint32_t*>(x0)[i] = w;
+    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
+        x[i] = f2bf((float)(s > 0.0 ? (double)f[i] / s : 0.0));
+}
+
+// geometry input: BF16(open pressure faces / 6)
+__global__ void k_geom(long long n, const uint8_t* __restrict__ pcode, uint16_t* __restrict__ xg) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        xg[i] = f2bf((float)((double)__builtin_popcount((unsigned)(pcode[i] & 0x3F)) / 6.0));
+}
+
+// cells x 2 BF16 -> two single-channel planes
+__global__ void k_split(long long n, const uint16_t* __restrict__ x2, uint16_t* __restrict__ a,
+                        uint16_t* __restrict__ b) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        a[i] = x2[2 * i];
+        b[i] = x2[2 * i + 1];
+    }
+}
+
+// gradient at the gate's pre-activation: BF16(dG . G (1 - G))
+__global__ void k_dpre(long long n16, const float* __restrict__ dg, const uint16_t* __restrict__ gt,
+                       uint16_t* __restrict__ out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (long long)gridDim.x * blockDim.x) {
+        const float gv = bf2f(gt[i]);
+        out[i] = f2bf(dg[i] * gv * (1.0f - gv));
     }
 }
 
@@ -512,13 +573,20 @@ struct ibm_cnn {
     float* v;
     float* dw;       // last gradient
     int adam_t;
-    uint16_t* wp;    // packed BF16 A operands of the eight convolutions
-    ibm::PackDesc pd[8];
-    uint16_t* x0;    // cap x 2
-    uint16_t* act[3];// cap x 16
-    uint16_t* sig[2];// cap x 16 backward signals
-    uint16_t* dy4;   // cap
-    float* y;        // cap
+    uint16_t* wp;    // packed BF16 A operands of the six convolutions
+    ibm::PackDesc pd[6];
+    uint16_t* xr;    // network input (residual / s), cells
+    uint16_t* xg;    // geometry input, cells
+    uint16_t* G;     // gate, cells x 16
+    uint16_t* u1;    // W1 * x before the gate (training), cells x 16
+    uint16_t* a1;    // (W1 * x) . G
+    uint16_t* y;     // W2 * a1
+    uint16_t* vv;    // W2^T * y before the gate (training)
+    uint16_t* bb;    // (W2^T * y) . G
+    uint16_t* sig[2];// backward signals, cells x 16
+    uint16_t* dy1;   // BF16 output gradient, cells
+    float* dG;       // gate gradient, cells x 16
+    float* out;      // K^T K x, cells
     float* wpart;    // WG_MAX_BLOCKS x 27 x 256
     double* h;       // cap (loss)
     double* q;       // cap
@@ -533,29 +601,22 @@ struct ibm_cnn {
 namespace ibm {
 namespace {
 
-enum { PV_F1 = 0, PV_F2, PV_F3, PV_F4, PV_B4, PV_B3, PV_B2, PV_B1, PV_N };
+enum { PV_W1 = 0, PV_W2, PV_W2T, PV_W1T, PV_WG, PV_WGT, PV_N };
+constexpr int OFF_W1 = 0, OFF_W2 = 432, OFF_WG = 7344;
 
 void fill_pack_desc(ibm_cnn* n) {
-    const int loff[4] = {0, 864, 7776, 14688};
-    const int lcin[4] = {2, 16, 16, 16}, lcout[4] = {16, 16, 16, 1};
+    // (layer offset, layer cin, layer cout, adjoint)
+    const int spec[PV_N][4] = {{OFF_W1, 1, 16, 0}, {OFF_W2, 16, 16, 0}, {OFF_W2, 16, 16, 1},
+                               {OFF_W1, 1, 16, 1}, {OFF_WG, 1, 16, 0}, {OFF_WG, 1, 16, 1}};
     int off = 0;
     for (int v = 0; v < PV_N; ++v) {
         PackDesc d;
-        int l;
-        if (v <= PV_F4) {
-            l = v;
-            d.bwd = 0;
-            d.cin = lcin[l];
-            d.cout = lcout[l];
-        } else {
-            l = 3 - (v - PV_B4);   // B4 -> layer 3, B1 -> layer 0
-            d.bwd = 1;
-            d.cin = lcout[l];
-            d.cout = lcin[l];
-        }
-        d.loff = loff[l];
-        d.lcin = lcin[l];
-        d.lcout = lcout[l];
+        d.loff = spec[v][0];
+        d.lcin = spec[v][1];
+        d.lcout = spec[v][2];
+        d.bwd = spec[v][3];
+        d.cin = d.bwd ? d.lcout : d.lcin;
+        d.cout = d.bwd ? d.lcin : d.lcout;
         d.ks = ksteps(d.cin);
         d.off = off;
         off += d.ks * 512;
@@ -580,47 +641,80 @@ int conv_blocks(int nx, int ny, int nz) {
 
 const uint16_t* pw(const ibm_cnn* n, int v) { return n->wp + n->pd[v].off; }
 
-// x0 -> act[0..2] -> y
-int net_forward(ibm_cnn* n, int nx, int ny, int nz, const Solver* sv, hipStream_t s) {
+ConvIO io_none(int ostride = 1) { return ConvIO{nullptr, nullptr, nullptr, nullptr, 0, ostride}; }
+ConvIO io_gate(const uint16_t* G, uint16_t* aux) { return ConvIO{G, aux, nullptr, nullptr, 0, 1}; }
+ConvIO io_bgate(const uint16_t* G, const uint16_t* pre, float* dg, int accum) {
+    return ConvIO{G, nullptr, pre, dg, accum, 1};
+}
+
+// G = sigmoid(Wg * xg)
+int net_gate(ibm_cnn* n, int nx, int ny, int nz, hipStream_t s) {
+    k_conv<1, 16, EPI_SIGMOID><<<conv_blocks(nx, ny, nz), 256, 0, s>>>(nx, ny, nz, n->xg, pw(n, PV_WG), n->G,
+                                                                        io_none(), nullptr);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+// out = K^T K xr with the current gate; `keep` stores the pre-gate activations for
+// the backward pass
+int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv, hipStream_t s) {
     const int nb = conv_blocks(nx, ny, nz);
-    k_conv<2, 16, EPI_RELU><<<nb, 256, 0, s>>>(nx, ny, nz, n->x0, pw(n, PV_F1), n->act[0], nullptr, sv);
-    k_conv<16, 16, EPI_RELU><<<nb, 256, 0, s>>>(nx, ny, nz, n->act[0], pw(n, PV_F2), n->act[1], nullptr, sv);
-    k_conv<16, 16, EPI_RELU><<<nb, 256, 0, s>>>(nx, ny, nz, n->act[1], pw(n, PV_F3), n->act[2], nullptr, sv);
-    k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->act[2], pw(n, PV_F4), n->y, nullptr, sv);
+    k_conv<1, 16, EPI_GATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->xr, pw(n, PV_W1), n->a1,
+                                               io_gate(n->G, keep ? n->u1 : nullptr), sv);
+    k_conv<16, 16, EPI_BF16><<<nb, 256, 0, s>>>(nx, ny, nz, n->a1, pw(n, PV_W2), n->y, io_none(), sv);
+    k_conv<16, 16, EPI_GATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->y, pw(n, PV_W2T), n->bb,
+                                                io_gate(n->G, keep ? n->vv : nullptr), sv);
+    k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->bb, pw(n, PV_W1T), n->out, io_none(1), sv);
     IBM_HIP(hipGetLastError());
     n->nx = nx;
     n->ny = ny;
     n->nz = nz;
-    n->have_fwd = true;
+    n->have_fwd = keep;
     return IBM_OK;
 }
 
 template <int CIN, int COUT>
-int wgrad(ibm_cnn* n, const uint16_t* x, const uint16_t* dy, int layer, hipStream_t s) {
+int wgrad(ibm_cnn* n, const uint16_t* x, const uint16_t* dy, int off, int accum, hipStream_t s) {
     const int nx = n->nx, ny = n->ny, nz = n->nz;
     const int ntiles = conv_blocks(nx, ny, nz);
     const int nb = ntiles < WG_MAX_BLOCKS ? ntiles : WG_MAX_BLOCKS;
     k_wgrad<CIN, COUT><<<nb, 256, 0, s>>>(nx, ny, nz, x, dy, n->wpart, ntiles);
-    const int loff[4] = {0, 864, 7776, 14688};
     const int nw = 27 * CIN * COUT;
-    k_wsum<<<(nw + 255) / 256, 256, 0, s>>>(n->wpart, nb, CIN, COUT, n->dw + loff[layer]);
+    k_wsum<<<(nw + 255) / 256, 256, 0, s>>>(n->wpart, nb, CIN, COUT, n->dw + off, accum);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
 
-// dy4 -> dw (and dx, cells x 2 floats, when non-null), using the saved activations
+// Backward pass of the kept forward for d J / d out = dy1 (BF16): dW into n->dw; when
+// dx is non-null, dJ/dxr and dJ/dxg into dx (cells x 2 floats).
 int net_backward(ibm_cnn* n, float* dx, hipStream_t s) {
     const int nx = n->nx, ny = n->ny, nz = n->nz;
     const int nb = conv_blocks(nx, ny, nz);
+    const long long cells = (long long)nx * ny * nz;
     int rc;
-    if ((rc = wgrad<16, 1>(n, n->act[2], n->dy4, 3, s))) return rc;
-    k_conv<1, 16, EPI_MASK><<<nb, 256, 0, s>>>(nx, ny, nz, n->dy4, pw(n, PV_B4), n->sig[0], n->act[2], nullptr);
-    if ((rc = wgrad<16, 16>(n, n->act[1], n->sig[0], 2, s))) return rc;
-    k_conv<16, 16, EPI_MASK><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_B3), n->sig[1], n->act[1], nullptr);
-    if ((rc = wgrad<16, 16>(n, n->act[0], n->sig[1], 1, s))) return rc;
-    k_conv<16, 16, EPI_MASK><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[1], pw(n, PV_B2), n->sig[0], n->act[0], nullptr);
-    if ((rc = wgrad<2, 16>(n, n->x0, n->sig[0], 0, s))) return rc;
-    if (dx) k_conv<16, 2, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_B1), dx, nullptr, nullptr);
+    // out = W1^T * bb
+    if ((rc = wgrad<1, 16>(n, n->dy1, n->bb, OFF_W1, 0, s))) return rc;
+    // d bb = W1 * dy1;  d vv = d bb . G;  dG = d bb . vv
+    k_conv<1, 16, EPI_BGATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->dy1, pw(n, PV_W1), n->sig[0],
+                                                io_bgate(n->G, n->vv, n->dG, 0), nullptr);
+    // vv = W2^T * y
+    if ((rc = wgrad<16, 16>(n, n->sig[0], n->y, OFF_W2, 0, s))) return rc;
+    // d y = W2 * d vv
+    k_conv<16, 16, EPI_BF16><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_W2), n->sig[1], io_none(), nullptr);
+    // y = W2 * a1
+    if ((rc = wgrad<16, 16>(n, n->a1, n->sig[1], OFF_W2, 1, s))) return rc;
+    // d a1 = W2^T * d y;  d u1 = d a1 . G;  dG += d a1 . u1
+    k_conv<16, 16, EPI_BGATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[1], pw(n, PV_W2T), n->sig[0],
+                                                 io_bgate(n->G, n->u1, n->dG, 1), nullptr);
+    // u1 = W1 * xr
+    if ((rc = wgrad<1, 16>(n, n->xr, n->sig[0], OFF_W1, 1, s))) return rc;
+    if (dx)
+        k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_W1T), dx, io_none(2), nullptr);
+    // G = sigmoid(Wg * xg)
+    k_dpre<<<2048, 256, 0, s>>>(cells * 16, n->dG, n->G, n->sig[1]);
+    if ((rc = wgrad<1, 16>(n, n->xg, n->sig[1], OFF_WG, 0, s))) return rc;
+    if (dx)
+        k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[1], pw(n, PV_WGT), dx + 1, io_none(2), nullptr);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -633,42 +727,55 @@ int check_grid(const ibm_cnn* n, long long cells) {
     return IBM_OK;
 }
 
+// gate of the context's geometry
+int prepare_geometry(ibm_cnn* n, ibm_ctx* c, hipStream_t s) {
+    k_geom<<<2048, 256, 0, s>>>(c->N, c->pcode, n->xg);
+    IBM_HIP(hipGetLastError());
+    return net_gate(n, c->geo.nx, c->geo.ny, c->geo.nz, s);
+}
+
 // Loss of one pair (b, p), L p = b, on the context's stencil, and the gradient signal
-// d loss / d y in dy4 (BF16): f = -b, s = RMS(f), x0 = [f/s, g], h = D^-1 f + s y,
+// d loss / d out in dy1 (BF16): f = -b, s = RMS(f), h = D^-1 f + s K^T K (f/s),
 // loss = 1 - (f.h)^2 / ((f.p)(h.A h)).  scal[3] = loss.
 int loss_forward(ibm_cnn* n, ibm_ctx* c, const double* b, const double* p, hipStream_t s) {
     const Geo& g = c->geo;
     const long long N = c->N;
     const int nred = 1024;
+    int rc = prepare_geometry(n, c, s);
+    if (rc) return rc;
     k_neg<<<2048, 256, 0, s>>>(N, b, n->f);
     k_sumsq<double><<<nred, NT, 0, s>>>(N, n->f, n->part);
-    k_input<double><<<nred, NT, 0, s>>>(N, n->f, c->pcode, n->part, nred, n->x0, n->scal, nullptr, 0);
+    k_input<double><<<nred, NT, 0, s>>>(N, n->f, n->part, nred, n->xr, n->scal, nullptr, 0);
     IBM_HIP(hipGetLastError());
-    int rc = net_forward(n, g.nx, g.ny, g.nz, nullptr, s);
-    if (rc) return rc;
-    k_phat<<<2048, 256, 0, s>>>(N, g.dx * g.dx, n->f, c->pcode, n->y, n->scal, n->h);
+    if ((rc = net_forward(n, g.nx, g.ny, g.nz, true, nullptr, s))) return rc;
+    k_phat<<<2048, 256, 0, s>>>(N, g.dx * g.dx, n->f, c->pcode, n->out, n->scal, n->h);
     k_loss_dots<<<nred, NT, 0, s>>>(g, c->pcode, n->f, p, n->h, n->q, n->part);
     k_loss_final<<<1, NT, 0, s>>>(n->part, nred, n->scal);
-    k_dy<<<2048, 256, 0, s>>>(N, n->q, n->f, n->scal, n->dy4);
+    k_dy<<<2048, 256, 0, s>>>(N, n->q, n->f, n->scal, n->dy1);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
 
 }  // namespace
 
-// z = D^-1 r + s net([r/s, g]) inside the FCG solve (see poisson.hip): s^2 = <r,r>/N from
+// Gate of the context's geometry; called once per solve before the FCG segments.
+int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s) {
+    return prepare_geometry(static_cast<ibm_cnn*>(net), c, s);
+}
+
+// z = D^-1 r + s K^T K (r/s) inside the FCG solve (see poisson.hip): s^2 = <r,r>/N from
 // the partials in rr_slot; <z,r> -> zr_slot, <z,rp> -> zrp_slot (-1: none).  Stops the
-// solve (sv->converged = 1) when <r,r> <= sv->tol2.
+// solve (sv->converged = 1) when <r,r> <= sv->tol2.  The gate must be prepared.
 int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
                             int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, hipStream_t s) {
     ibm_cnn* n = static_cast<ibm_cnn*>(net);
     const Geo& g = c->geo;
-    k_input<float><<<nparts, NT, 0, s>>>(c->N, r, c->pcode, partials + (long long)rr_slot * MAX_BLOCKS, nparts, n->x0,
+    k_input<float><<<nparts, NT, 0, s>>>(c->N, r, partials + (long long)rr_slot * MAX_BLOCKS, nparts, n->xr,
                                          n->scal, sv, it);
-    int rc = net_forward(n, g.nx, g.ny, g.nz, sv, s);
+    int rc = net_forward(n, g.nx, g.ny, g.nz, false, sv, s);
     if (rc) return rc;
-    k_combine<<<nparts, NT, 0, s>>>(c->N, g.dx * g.dx, r, rp, c->pcode, n->y, n->scal, z, partials, zr_slot, zrp_slot,
-                                     sv);
+    k_combine<<<nparts, NT, 0, s>>>(c->N, g.dx * g.dx, r, rp, c->pcode, n->out, n->scal, z, partials, zr_slot,
+                                     zrp_slot, sv);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -685,8 +792,9 @@ namespace {
 
 void net_free(ibm_cnn* n) {
     if (!n) return;
-    void* bufs[] = {n->w, n->m, n->v, n->dw, n->wp, n->x0, n->act[0], n->act[1], n->act[2], n->sig[0], n->sig[1],
-                    n->dy4, n->y, n->wpart, n->h, n->q, n->f, n->part, n->scal};
+    void* bufs[] = {n->w,  n->m,  n->v,      n->dw,     n->wp,  n->xr,    n->xg,  n->G, n->u1, n->a1, n->y,
+                    n->vv, n->bb, n->sig[0], n->sig[1], n->dy1, n->dG,    n->out, n->wpart, n->h, n->q,  n->f,
+                    n->part, n->scal};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (n->h_scal) (void)hipHostFree(n->h_scal);
@@ -739,11 +847,13 @@ int ibm_cnn_create(int64_t max_cells, ibm_cnn** out) {
     alloc((void**)&n->v, NWTS * sizeof(float));
     alloc((void**)&n->dw, NWTS * sizeof(float));
     alloc((void**)&n->wp, (size_t)packed_elems(n) * sizeof(uint16_t));
-    alloc((void**)&n->x0, cap * 2 * sizeof(uint16_t));
-    for (int k = 0; k < 3; ++k) alloc((void**)&n->act[k], cap * 16 * sizeof(uint16_t));
-    for (int k = 0; k < 2; ++k) alloc((void**)&n->sig[k], cap * 16 * sizeof(uint16_t));
-    alloc((void**)&n->dy4, cap * sizeof(uint16_t));
-    alloc((void**)&n->y, cap * sizeof(float));
+    alloc((void**)&n->xr, cap * sizeof(uint16_t));
+    alloc((void**)&n->xg, cap * sizeof(uint16_t));
+    uint16_t** c16[] = {&n->G, &n->u1, &n->a1, &n->y, &n->vv, &n->bb, &n->sig[0], &n->sig[1]};
+    for (uint16_t** pp : c16) alloc((void**)pp, cap * 16 * sizeof(uint16_t));
+    alloc((void**)&n->dy1, cap * sizeof(uint16_t));
+    alloc((void**)&n->dG, cap * 16 * sizeof(float));
+    alloc((void**)&n->out, cap * sizeof(float));
     alloc((void**)&n->wpart, (size_t)WG_MAX_BLOCKS * 27 * 256 * sizeof(float));
     alloc((void**)&n->h, cap * sizeof(double));
     alloc((void**)&n->q, cap * sizeof(double));
@@ -816,9 +926,11 @@ int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t n
     const long long cells = (long long)nx * ny * nz;
     if ((rc = check_grid(net, cells))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    IBM_HIP(hipMemcpyAsync(net->x0, x_dev, cells * 2 * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
-    if ((rc = net_forward(net, nx, ny, nz, nullptr, s))) return rc;
-    IBM_HIP(hipMemcpyAsync(y_dev, net->y, cells * sizeof(float), hipMemcpyDeviceToDevice, s));
+    k_split<<<2048, 256, 0, s>>>(cells, x_dev, net->xr, net->xg);
+    IBM_HIP(hipGetLastError());
+    if ((rc = net_gate(net, nx, ny, nz, s))) return rc;
+    if ((rc = net_forward(net, nx, ny, nz, true, nullptr, s))) return rc;
+    IBM_HIP(hipMemcpyAsync(y_dev, net->out, cells * sizeof(float), hipMemcpyDeviceToDevice, s));
     return IBM_OK;
 }
 
@@ -830,12 +942,12 @@ int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx
         return IBM_ERR_ARG;
     }
     if (!net->have_fwd) {
-        set_error("ibm_cnn_backward: no forward pass to differentiate");
+        set_error("ibm_cnn_backward: no kept forward pass to differentiate");
         return IBM_ERR_ARG;
     }
     hipStream_t s = (hipStream_t)stream;
     const long long cells = (long long)net->nx * net->ny * net->nz;
-    k_f32_to_bf16<<<2048, 256, 0, s>>>(cells, dy_dev, net->dy4);
+    k_f32_to_bf16<<<2048, 256, 0, s>>>(cells, dy_dev, net->dy1);
     IBM_HIP(hipGetLastError());
     if ((rc = net_backward(net, dx_dev, s))) return rc;
     IBM_HIP(hipMemcpyAsync(dw_dev, net->dw, NWTS * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -895,6 +1007,7 @@ int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* 
     if ((rc = check_grid(net, ctx->N))) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int nred = 1024;
+    if ((rc = prepare_geometry(net, ctx, s))) return rc;
     k_sumsq<float><<<nred, NT, 0, s>>>(ctx->N, r_dev, net->part);
     IBM_HIP(hipGetLastError());
     // partial slot 0 of net->part holds <r,r>; <z,r> goes to slot 1

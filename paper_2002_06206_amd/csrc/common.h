@@ -228,6 +228,7 @@ int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts*
 int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
                             int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, hipStream_t s);
 bool cnn_covers(const void* net, long long cells);
+int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s);
 // timing helpers (poisson.hip)
 enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3 };
 void timing_begin(ibm_ctx* c, int k, hipStream_t s);

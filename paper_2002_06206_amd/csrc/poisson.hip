@@ -1389,7 +1389,8 @@ int mixed_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
 }
 
 // Mixed precision with the learned preconditioner: FCG(1) segments, restarted at every
-// residual replacement (a nonlinear preconditioner has no Krylov space to keep).
+// residual replacement (the BF16 preconditioner is only nearly symmetric, so the
+// flexible beta is used and no Krylov space is carried across replacements).
 int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {
     if (!c->cnn) {
         set_error("IBM_SOLVER_FCG_CNN: no network attached to the context");
@@ -1401,6 +1402,8 @@ int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts*
     }
     const int nred = march_blocks(c->geo);
     const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : 1000;
+    int rc = cnn_prepare_geometry(c->cnn, c, s);
+    if (rc) return rc;
     return refine_solve(
         c, b, x, o, st, nred,
         [&](int it, int* made) { return fcg_segment(c, nred, it, inner_max, o->check_every, made, s); }, s);

@@ -108,7 +108,7 @@ EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
             "ibm_ctx_set_preconditioner")
-CNN_NWEIGHTS = 15120
+CNN_NWEIGHTS = 7776
 
 
 def lib():

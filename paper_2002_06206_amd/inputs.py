@@ -360,21 +360,17 @@ def random_field(shape, seed: int, scale: float = 1.0) -> np.ndarray:
 
 # ------------------------------------------------------------------ learned preconditioner
 
-CNN_LAYERS = ((2, 16), (16, 16), (16, 16), (16, 1))
+CNN_LAYERS = (("W1", 1, 16), ("W2", 16, 16), ("Wg", 1, 16))
 
 
-def cnn_init_weights(seed: int, last_scale: float = 0.1) -> np.ndarray:
-    """Seeded He-normal initial weights (std sqrt(2 / fan_in), fan_in = 27 ci) of the
-    four 3x3x3 layers, flat float32 in the layout w[t, ci, co] per layer, layers in
-    order.  The last layer is scaled down so that the untrained network is a small
-    perturbation."""
+def cnn_init_weights(seed: int, scale: float = 1.0) -> np.ndarray:
+    """Seeded normal initial weights of the learned preconditioner, flat float32 in the
+    layout W1[t, 0, co], W2[t, ci, co], Wg[t, 0, co] (t = 27 taps).  Standard
+    deviations 0.05 (W1), 0.3 / sqrt(27 * 16) (W2) and 0.1 (Wg) keep the untrained
+    operator a small addition to Jacobi; `scale` multiplies W1 and W2."""
     rng = np.random.default_rng(seed)
-    parts = []
-    for l, (ci, co) in enumerate(CNN_LAYERS):
-        w = rng.standard_normal((27, ci, co)) * math.sqrt(2.0 / (27 * ci))
-        if l == len(CNN_LAYERS) - 1:
-            w *= last_scale
-        parts.append(w.reshape(-1))
+    std = {"W1": 0.05 * scale, "W2": 0.3 / math.sqrt(27 * 16) * scale, "Wg": 0.1}
+    parts = [rng.standard_normal(27 * ci * co) * std[name] for name, ci, co in CNN_LAYERS]
     return np.ascontiguousarray(np.concatenate(parts).astype(np.float32))
 
 

@@ -104,7 +104,7 @@ def main():
     held = build_dataset(EVAL_SEEDS, args.n)
     print("pairs: train %d, held-out %d (%.1fs)" % (sum(len(p) for _, p in data), sum(len(p) for _, p in held),
                                                    time.time() - t0), flush=True)
-    net = ibm.Network(args.n ** 3, inputs.cnn_init_weights(args.init_seed, last_scale=0.01))
+    net = ibm.Network(args.n ** 3, inputs.cnn_init_weights(args.init_seed))
     print("held-out loss before %.4f" % mean_loss(net, held), flush=True)
     train(net, data, args.iters, args.lr, log_every=100)
     print("held-out loss after %.4f (%.1fs)" % (mean_loss(net, held), time.time() - t0), flush=True)
