@@ -1,0 +1,186 @@
+"""Parity at the full sizes of the workloads, in the launch configuration bench.py times.
+
+* Tagging, blocked bits, theta bits, flags, labels, cut counts and cut points of the
+  128^3 dirty sphere, the 256^3 ellipsoid field and the 256^3 plate: bit-exact
+  against the oracle over the whole grid.
+* The benchmark workload (256^3 ellipsoids, plain FP64): one full step from a
+  developed state, each piece checked against the oracle functions evaluated on the
+  GPU's own input state: eddy viscosity, Poisson right-hand side, H, and the
+  projected u and U from the GPU's pressure (relative L2 1e-10); the pressure itself
+  by the FP64 residual of the oracle's operator (<= tol).
+* Mixed and learned solves at that size: the FP64 judge residual recomputed by the
+  oracle's operator, and the discrete divergence identity div U^{n+1} =
+  dt (b - L p) cell by cell (a property at any size).
+* The precision configuration (256^3 plate): relative L2 error of u, p and drag of the
+  mixed path against the plain FP64 path after the same steps, stated.
+"""
+import numpy as np
+import pytest
+
+from oracle import flow, tagging
+from paper_2002_06206_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2002_06206_amd import ibm
+else:  # collected on CPU machines, skipped by the marker filter
+    ibm = None
+
+CASES = {"dirty_sphere128": lambda: inputs.case_dirty_sphere128(0),
+         "ellipsoids256": lambda: inputs.case_ellipsoids256(0),
+         "plate256": lambda: inputs.case_plate256(0)}
+_ORACLE = {}
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.sqrt(np.sum(b * b))
+    return np.sqrt(np.sum((a - b) ** 2)) / den if den > 0 else np.sqrt(np.sum(a * a))
+
+
+def _vec(ts):
+    return np.concatenate([np.asarray(t.cpu().numpy() if hasattr(t, "cpu") else t, np.float64).ravel() for t in ts])
+
+
+def _oracle(name):
+    """Oracle tagging and stencils of a workload (cached for the module)."""
+    if name not in _ORACLE:
+        case = CASES[name]()
+        g = flow.Grid(case.n, case.dx, case.origin, case.bc, case.u_in)
+        ob, ot = tagging.tag(case.tri, g.n, g.dx, g.origin)
+        st = flow.build_stencils(g, ob, ot, case.deadend)
+        _ORACLE[name] = (case, g, ob, ot, st)
+    return _ORACLE[name]
+
+
+def _gpu(case, precision):
+    s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, precision)
+    gb, gt = s.tag(case.tri)
+    flags, label = s.build(gb, None, case.deadend)
+    return s, gb, gt, flags, label
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_size_tagging_and_stencils_bit_exact(name):
+    print("case full-size tagging/stencil", name, flush=True)
+    case, g, ob, ot, st = _oracle(name)
+    s, gb, gt, flags, label = _gpu(case, ibm.FP64)
+    assert np.array_equal(gb.cpu().numpy(), ob)
+    assert np.array_equal(gt.cpu().numpy().view(np.uint64), ot.view(np.uint64))
+    assert s.ncut == st.ncut and st.ncut > 1000
+    assert np.array_equal(flags.cpu().numpy().view(np.uint16), st.flags)
+    assert np.array_equal(label.cpu().numpy(), st.label)
+    X = s.cut_points().cpu().numpy()
+    assert np.array_equal(X.view(np.uint64), flow.cut_points(st).view(np.uint64))
+    s.close()
+
+
+def _cfl_steps(s, gs, case, n, kind, tol, ctl, dts=None):
+    """n steps with the benchmark's CFL-0.3 time step control (or the given dt
+    sequence); appends the dts used to ctl["dts"]; returns the last stats."""
+    stats = None
+    for k in range(n):
+        dt = dts[k] if dts is not None else min(case.dt, 0.3 * case.dx / max(ctl["umax"], 1e-30))
+        ctl.setdefault("dts", []).append(dt)
+        rc, stats = s.step(gs, ibm.step_params(dt, case.nu, csm=case.csm, step=ctl["step"], dt_prev=ctl["dt_prev"],
+                                               tol=tol, max_iter=20000, check_every=16, kind=kind,
+                                               inner_tol=0.1, inner_max_iter=2000))
+        assert rc == 0
+        ctl.update(umax=stats["umax"], dt_prev=dt, step=ctl["step"] + 1, dt=dt)
+    return stats
+
+
+def _host(gs):
+    return ([t.cpu().numpy().astype(np.float64) for t in gs["u"]], [t.cpu().numpy() for t in gs["U"]],
+            gs["p"].cpu().numpy(), [t.cpu().numpy().astype(np.float64) for t in gs["h"]])
+
+
+def test_benchmark_workload_step_pieces_match_oracle():
+    case, g, ob, ot, st = _oracle("ellipsoids256")
+    s, *_ = _gpu(case, ibm.FP64)
+    gs = s.new_state(case.u_in)
+    ctl = {"umax": 1.0, "dt_prev": 0.0, "step": 0, "dt": case.dt}
+    print("case full-size step pieces ellipsoids256", flush=True)
+    _cfl_steps(s, gs, case, 3, ibm.SOLVER_PCG_JACOBI, 1e-6, ctl)
+    u0, U0, p0, h0 = _host(gs)
+    dt_prev, n = ctl["dt_prev"], ctl["step"]
+    _cfl_steps(s, gs, case, 1, ibm.SOLVER_PCG_JACOBI, 1e-6, ctl)
+    dt = ctl["dt"]
+    u1, U1, p1, h1 = _host(gs)
+    nut = flow.csm_nut(st, u0)
+    e_nut = rel_l2(s.nut().cpu().numpy(), nut)
+    us, H = flow.predictor(st, u0, U0, h0, nut, case.nu, dt, (0.0, 0.0, 0.0), n, None, dt_prev)
+    Us = flow.face_predicted(st, us, None)
+    b = flow.poisson_rhs(st, Us, dt)
+    e_b = rel_l2(s.rhs().cpu().numpy(), b)
+    e_h = rel_l2(_vec(h1), _vec(H))
+    res = rel_l2(flow.laplacian(st, p1), b)          # ||b - L p|| / ||b||
+    uo, Uo = flow.project(st, us, Us, p1, dt)
+    e_u = rel_l2(_vec(u1), _vec(uo))
+    e_U = rel_l2(_vec(U1), _vec(Uo))
+    print("256^3 step %d: rel L2 nut %.1e b %.1e H %.1e u %.1e U %.1e; FP64 residual %.3e" %
+          (n, e_nut, e_b, e_h, e_u, e_U, res), flush=True)
+    assert max(e_nut, e_b, e_h, e_u, e_U) < 1e-10
+    assert res <= 1e-6 * 1.0001
+    s.close()
+
+
+@pytest.mark.parametrize("kind", ["mixed", "learned"])
+def test_benchmark_workload_judge_and_divergence_identity(kind):
+    """Mixed (FP32 fields, FP32 CG in FP64 refinement) and learned (FCG with the network,
+    untrained weights: the properties hold for any weights) at 256^3."""
+    case, g, ob, ot, st = _oracle("ellipsoids256")
+    s, *_ = _gpu(case, ibm.MIXED)
+    net = None
+    if kind == "learned":
+        net = ibm.Network(g.ncell, inputs.cnn_init_weights(0))
+        net.attach(s)
+    solver = ibm.SOLVER_FCG_CNN if kind == "learned" else ibm.SOLVER_FCG_JACOBI
+    gs = s.new_state(case.u_in)
+    ctl = {"umax": 1.0, "dt_prev": 0.0, "step": 0, "dt": case.dt}
+    print("case full-size judge", kind, flush=True)
+    stats = _cfl_steps(s, gs, case, 3, solver, 1e-6, ctl)
+    dt = ctl["dt"]
+    b = s.rhs().cpu().numpy()
+    p = gs["p"].cpu().numpy()
+    U = [t.cpu().numpy() for t in gs["U"]]
+    res = rel_l2(flow.laplacian(st, p), b)
+    div = flow.divergence(g, U)
+    ident = dt * (b - flow.laplacian(st, p))
+    err = np.max(np.abs(div - ident)) / (dt * np.max(np.abs(b)))
+    print("%s: FP64 residual %.3e (solver %.3e), fallback %d, identity error %.1e" %
+          (kind, res, stats["rel_residual"], stats["fallback_used"], err), flush=True)
+    assert res <= 1e-6 * 1.0001 and stats["fallback_used"] == 0
+    assert err < 1e-10
+    if net is not None:
+        net.close()
+    s.close()
+
+
+def test_precision_configuration_errors_stated():
+    """256^3 plate at 30 deg incidence, Re = 1e5: the mixed path (FP32 stencils and
+    fields, FP32 CG with FP64 refinement) against the plain FP64 path after the same
+    10 steps (same dt sequence), both to Poisson tolerance 1e-6."""
+    case = CASES["plate256"]()
+    runs = {}
+    dts = None
+    for prec, solver in ((ibm.FP64, ibm.SOLVER_PCG_JACOBI), (ibm.MIXED, ibm.SOLVER_FCG_JACOBI)):
+        s, *_ = _gpu(case, prec)
+        gs = s.new_state(case.u_in)
+        ctl = {"umax": 1.0, "dt_prev": 0.0, "step": 0, "dt": case.dt}
+        print("case precision plate256 precision", prec, flush=True)
+        _cfl_steps(s, gs, case, 10, solver, 1e-6, ctl, dts)
+        dts = ctl["dts"]
+        Fp, Fv = s.forces(gs, case.nu)
+        runs[prec] = (_host(gs), Fp[0] + Fv[0], ctl["dt"])
+        s.close()
+    (u64, _, p64, _), d64, dt64 = runs[ibm.FP64]
+    (u32, _, p32, _), d32, dt32 = runs[ibm.MIXED]
+    eu, ep = rel_l2(_vec(u32), _vec(u64)), rel_l2(p32, p64)
+    ed = abs(d32 - d64) / abs(d64)
+    print("plate256 mixed vs FP64 after 10 steps: rel L2 u %.2e, p %.2e, drag %.2e (dt %.4g / %.4g)" %
+          (eu, ep, ed, dt32, dt64), flush=True)
+    assert eu < 1e-3 and ep < 1e-2 and ed < 1e-2
