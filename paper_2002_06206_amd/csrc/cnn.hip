@@ -273,6 +273,216 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
     }
 }
 
+// Marching form of a convolution for the solver's preconditioner applications.
+// A block owns a 32 x 8 output tile in x-y and walks a slab of mz planes in z.  The
+// input planes z-1, z, z+1 (34 x 10 cells with halo) sit in a ring of four LDS planes
+// (two 16-byte half-cell planes each for CIN = 16); plane z+2 is loaded into registers
+// while plane z is computed and written to the free ring slot afterwards (one barrier
+// per plane).  Each wave owns two output rows = four 16-cell MFMA tiles and keeps four
+// independent accumulator chains.  EPI_BF16 and EPI_F32 (COUT channels) as in k_conv;
+// EPI_GATE computes the gate sigmoid(Wg * g) of its output cells on the fly (one more
+// MFMA per tile from a ring of geometry planes) instead of reading a stored gate.
+constexpr int PX = CTX + 2, PY = CTY + 2;    // 34 x 10 halo plane
+constexpr int PCELLS = PX * PY;              // 340
+constexpr int PCHUNK = (2 * PCELLS + 255) / 256;   // 16-byte chunks per thread per plane (CIN = 16)
+constexpr int PSCAL = (PCELLS + 255) / 256;        // cells per thread per plane (1-channel planes)
+
+template <int CIN, int COUT, int EPI>
+__global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz, const uint16_t* __restrict__ in,
+                                                  const uint16_t* __restrict__ wp, void* __restrict__ out,
+                                                  const uint16_t* __restrict__ gsrc, const uint16_t* __restrict__ wgp,
+                                                  const Solver* sv) {
+    if (sv && sv->converged) return;
+    constexpr int KS = ksteps(CIN);
+    constexpr int PLANE = CIN == 16 ? 2 * PCELLS * 8 : PCELLS * CIN;   // uint16 per ring plane
+    __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
+    __shared__ uint16_t gring[EPI == EPI_GATE ? 4 * PCELLS : 1];
+    const int ntx = (nx + CTX - 1) / CTX, nty = (ny + CTY - 1) / CTY;
+    const int nslab = (nz + mz - 1) / mz;
+    const int t = xcd_chunk(blockIdx.x, gridDim.x);
+    const int tx = t % ntx, ty = (t / ntx) % nty, tzs = t / (ntx * nty);
+    if (tzs >= nslab) return;
+    const int x0 = tx * CTX - 1, y0 = ty * CTY - 1;
+    const int z0 = tzs * mz, z1 = min(nz, z0 + mz);
+    const long long plane = (long long)nx * ny;
+    // loader: plane pz of the halo region into registers (zero outside the grid)
+    uint4 pre[CIN == 16 ? PCHUNK : 1];
+    uint16_t pre1[CIN == 16 ? 1 : PSCAL * CIN];
+    uint16_t preg[EPI == EPI_GATE ? PSCAL : 1];
+    auto load_plane = [&](int pz) {
+        if (EPI == EPI_GATE) {
+#pragma unroll
+            for (int k = 0; k < PSCAL; ++k) {
+                const int cell = threadIdx.x + 256 * k;
+                uint16_t v = 0;
+                if (cell < PCELLS && pz >= 0 && pz < nz) {
+                    const int gx = x0 + cell % PX, gy = y0 + cell / PX;
+                    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = gsrc[(long long)gx + (long long)nx * gy + plane * pz];
+                }
+                preg[k] = v;
+            }
+        }
+        if (CIN == 16) {
+#pragma unroll
+            for (int k = 0; k < PCHUNK; ++k) {
+                const int q = threadIdx.x + 256 * k;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (q < 2 * PCELLS && pz >= 0 && pz < nz) {
+                    const int cell = q >> 1, h = q & 1;
+                    const int gx = x0 + cell % PX, gy = y0 + cell / PX;
+                    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                        v = *reinterpret_cast<const uint4*>(in + ((long long)gx + (long long)nx * gy + plane * pz) * 16 +
+                                                            h * 8);
+                }
+                pre[k] = v;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < PSCAL; ++k) {
+                const int cell = threadIdx.x + 256 * k;
+#pragma unroll
+                for (int ci = 0; ci < CIN; ++ci) {
+                    uint16_t v = 0;
+                    if (cell < PCELLS && pz >= 0 && pz < nz) {
+                        const int gx = x0 + cell % PX, gy = y0 + cell / PX;
+                        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                            v = in[((long long)gx + (long long)nx * gy + plane * pz) * CIN + ci];
+                    }
+                    pre1[k * CIN + ci] = v;
+                }
+            }
+        }
+    };
+    auto store_plane = [&](int slot) {
+        if (EPI == EPI_GATE) {
+#pragma unroll
+            for (int k = 0; k < PSCAL; ++k) {
+                const int cell = threadIdx.x + 256 * k;
+                if (cell < PCELLS) gring[slot * PCELLS + cell] = preg[k];
+            }
+        }
+        uint16_t* P = ring + slot * PLANE;
+        if (CIN == 16) {
+#pragma unroll
+            for (int k = 0; k < PCHUNK; ++k) {
+                const int q = threadIdx.x + 256 * k;
+                if (q < 2 * PCELLS) {
+                    const int cell = q >> 1, h = q & 1;
+                    *reinterpret_cast<uint4*>(&P[(h * PCELLS + cell) * 8]) = pre[k];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < PSCAL; ++k) {
+                const int cell = threadIdx.x + 256 * k;
+                if (cell < PCELLS) {
+#pragma unroll
+                    for (int ci = 0; ci < CIN; ++ci) P[cell * CIN + ci] = pre1[k * CIN + ci];
+                }
+            }
+        }
+    };
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    bf16x8 wa[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) wa[s] = *reinterpret_cast<const bf16x8*>(wp + ((long long)s * 64 + lane) * 8);
+    bf16x8 wg;
+    if (EPI == EPI_GATE) wg = *reinterpret_cast<const bf16x8*>(wgp + (long long)lane * 8);
+    // prologue: planes z0-1, z0, z0+1 into ring slots (z & 3)
+    for (int pz = z0 - 1; pz <= z0 + 1; ++pz) {
+        load_plane(pz);
+        store_plane(pz & 3);
+    }
+    __syncthreads();
+    for (int z = z0; z < z1; ++z) {
+        load_plane(z + 2);                      // in flight during the compute of plane z
+        const int gy0 = ty * CTY + 2 * wv;
+        f32x4 acc[4];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                const int ox = (tt & 1) * 16 + j, oy = 2 * wv + (tt >> 1);
+                bf16x8 bv;
+                if (CIN == 16) {
+                    int tap = 2 * s + (g >> 1);
+                    if (tap > 26) tap = 26;   // padding slot: its weights are zero
+                    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                    const uint16_t* P = ring + ((z + dz) & 3) * PLANE;
+                    const int hc = (ox + 1 + dx) + PX * (oy + 1 + dy);
+                    bv = *reinterpret_cast<const bf16x8*>(&P[((g & 1) * PCELLS + hc) * 8]);
+                } else {
+                    uint16_t tmp[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        int tap, ci;
+                        kmap<CIN>(s, g, e, tap, ci);
+                        uint16_t v = 0;
+                        if (tap >= 0) {
+                            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                            const uint16_t* P = ring + ((z + dz) & 3) * PLANE;
+                            v = P[((ox + 1 + dx) + PX * (oy + 1 + dy)) * CIN + ci];
+                        }
+                        tmp[e] = v;
+                    }
+                    __builtin_memcpy(&bv, tmp, 16);
+                }
+                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc[tt], 0, 0, 0);
+            }
+        }
+        // gate of the output cells, BF16(sigmoid(Wg * g)) as the stored gate; computed for
+        // every tile (out-of-grid cells read zeros) so that no MFMA sits in a branch
+        float gate4[4][4];
+        if (EPI == EPI_GATE) {
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                const int ox = (tt & 1) * 16 + j, oy = 2 * wv + (tt >> 1);
+                uint16_t tmp[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    int tap, ci;
+                    kmap<1>(0, g, e, tap, ci);
+                    uint16_t gv = 0;
+                    if (tap >= 0) {
+                        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                        gv = gring[((z + dz) & 3) * PCELLS + (ox + 1 + dx) + PX * (oy + 1 + dy)];
+                    }
+                    tmp[e] = gv;
+                }
+                bf16x8 bg;
+                __builtin_memcpy(&bg, tmp, 16);
+                const f32x4 ga = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, bg, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) gate4[tt][r] = bf2f(f2bf(1.0f / (1.0f + __expf(-ga[r]))));
+            }
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const int gx = tx * CTX + (tt & 1) * 16 + j, gy = gy0 + (tt >> 1);
+            if (gx >= nx || gy >= ny) continue;
+            const long long c = (long long)gx + (long long)nx * gy + plane * z;
+            if (EPI == EPI_F32) {
+                if (g == 0) {
+#pragma unroll
+                    for (int r = 0; r < COUT; ++r) static_cast<float*>(out)[c * COUT + r] = acc[tt][r];
+                }
+            } else {
+                float v[4] = {acc[tt][0], acc[tt][1], acc[tt][2], acc[tt][3]};
+                if (EPI == EPI_GATE) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] *= gate4[tt][r];
+                }
+                *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + c * 16 + 4 * g) = pack4(v);
+            }
+        }
+        store_plane((z + 2) & 3);               // slot of plane z-2, last read for plane z-1
+        __syncthreads();
+    }
+}
+
 // Weight gradient of one layer: dW[t][ci][co] = sum over cells c of X[c + off_t][ci] dY[c][co].
 // MFMA with M = co, N = ci, K = 32 cells of the tile.  Each block loops over tiles and
 // writes its partial 27 x 16 x 16 sum (layout t*256 + ci*16 + co).
@@ -375,19 +585,20 @@ __global__ void __launch_bounds__(NT) k_sumsq(long long n, const T* __restrict__
 }
 
 // Network input x = BF16(f / s) with s^2 = (sum of the partials of <f,f>) / n.  With a
-// solver state: stops the solve (sets converged) when <f,f> <= tol2; s is stored for
-// the combining step.
+// solver state the kernel does nothing once the solve has converged, and with `check`
+// it stops the solve itself (sets converged) when <f,f> <= tol2; s is stored for the
+// combining step.
 template <class T>
 __global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__ f, const double* __restrict__ part,
                                               int nparts, uint16_t* __restrict__ x, double* __restrict__ s_out,
-                                              Solver* sv, int it) {
+                                              Solver* sv, int it, int check) {
     if (sv && sv->converged) return;
     __shared__ double sh[4];
     double v[1] = {0.0};
     for (int b = threadIdx.x; b < nparts; b += NT) v[0] += part[b];
     block_reduce<1>(v, sh);
     const double ff = v[0];
-    if (sv) {
+    if (sv && check) {
         if (!(ff == ff)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 sv->nan_seen = 1;
@@ -657,7 +868,36 @@ int net_gate(ibm_cnn* n, int nx, int ny, int nz, hipStream_t s) {
 
 // out = K^T K xr with the current gate; `keep` stores the pre-gate activations for
 // the backward pass
+// planes per slab: up to 32, fewer when the grid would give less than ~2048 blocks
+int mconv_planes(int nx, int ny, int nz) {
+    const int txy = ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY);
+    const int want_slabs = (2048 + txy - 1) / txy;
+    int mz = (nz + want_slabs - 1) / want_slabs;
+    return mz < 2 ? 2 : (mz > 32 ? 32 : mz);
+}
+
+int mconv_blocks(int nx, int ny, int nz, int mz) {
+    return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY) * ((nz + mz - 1) / mz);
+}
+
 int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv, hipStream_t s) {
+    if (!keep) {
+        // solver path: marching kernels, no activations kept
+        const int mz = mconv_planes(nx, ny, nz);
+        const int mb = mconv_blocks(nx, ny, nz, mz);
+        const uint16_t* wg = pw(n, PV_WG);
+        k_mconv<1, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, pw(n, PV_W1), n->a1, n->xg, wg, sv);
+        k_mconv<16, 16, EPI_BF16><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W2), n->y, nullptr, nullptr, sv);
+        k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->bb, n->xg, wg, sv);
+        k_mconv<16, 1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->bb, pw(n, PV_W1T), n->out, nullptr, nullptr,
+                                                   sv);
+        IBM_HIP(hipGetLastError());
+        n->nx = nx;
+        n->ny = ny;
+        n->nz = nz;
+        n->have_fwd = false;
+        return IBM_OK;
+    }
     const int nb = conv_blocks(nx, ny, nz);
     k_conv<1, 16, EPI_GATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->xr, pw(n, PV_W1), n->a1,
                                                io_gate(n->G, keep ? n->u1 : nullptr), sv);
@@ -745,7 +985,7 @@ int loss_forward(ibm_cnn* n, ibm_ctx* c, const double* b, const double* p, hipSt
     if (rc) return rc;
     k_neg<<<2048, 256, 0, s>>>(N, b, n->f);
     k_sumsq<double><<<nred, NT, 0, s>>>(N, n->f, n->part);
-    k_input<double><<<nred, NT, 0, s>>>(N, n->f, n->part, nred, n->xr, n->scal, nullptr, 0);
+    k_input<double><<<nred, NT, 0, s>>>(N, n->f, n->part, nred, n->xr, n->scal, nullptr, 0, 0);
     IBM_HIP(hipGetLastError());
     if ((rc = net_forward(n, g.nx, g.ny, g.nz, true, nullptr, s))) return rc;
     k_phat<<<2048, 256, 0, s>>>(N, g.dx * g.dx, n->f, c->pcode, n->out, n->scal, n->h);
@@ -764,14 +1004,16 @@ int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s) {
 }
 
 // z = D^-1 r + s K^T K (r/s) inside the FCG solve (see poisson.hip): s^2 = <r,r>/N from
-// the partials in rr_slot; <z,r> -> zr_slot, <z,rp> -> zrp_slot (-1: none).  Stops the
-// solve (sv->converged = 1) when <r,r> <= sv->tol2.  The gate must be prepared.
+// the partials in rr_slot; <z,r> -> zr_slot, <z,rp> -> zrp_slot (-1: none).  With check,
+// stops the solve (sv->converged = 1) when <r,r> <= sv->tol2.  The gate must be
+// prepared.
 int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
-                            int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, hipStream_t s) {
+                            int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, int check,
+                            hipStream_t s) {
     ibm_cnn* n = static_cast<ibm_cnn*>(net);
     const Geo& g = c->geo;
     k_input<float><<<nparts, NT, 0, s>>>(c->N, r, partials + (long long)rr_slot * MAX_BLOCKS, nparts, n->xr,
-                                         n->scal, sv, it);
+                                         n->scal, sv, it, check);
     int rc = net_forward(n, g.nx, g.ny, g.nz, false, sv, s);
     if (rc) return rc;
     k_combine<<<nparts, NT, 0, s>>>(c->N, g.dx * g.dx, r, rp, c->pcode, n->out, n->scal, z, partials, zr_slot,
@@ -1011,7 +1253,7 @@ int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* 
     k_sumsq<float><<<nred, NT, 0, s>>>(ctx->N, r_dev, net->part);
     IBM_HIP(hipGetLastError());
     // partial slot 0 of net->part holds <r,r>; <z,r> goes to slot 1
-    return cnn_precondition_solver(net, ctx, r_dev, nullptr, z_dev, net->part, nred, 0, 1, -1, nullptr, 0, s);
+    return cnn_precondition_solver(net, ctx, r_dev, nullptr, z_dev, net->part, nred, 0, 1, -1, nullptr, 0, 0, s);
 }
 
 int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net) {

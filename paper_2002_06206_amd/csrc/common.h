@@ -226,7 +226,8 @@ int pcg64(ibm_ctx* c, const double* b, double* x, double tol, int max_iter, int 
 int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s);
 // z = D^-1 r + s net([r/s, g]) inside a solve (cnn.hip); see cnn_precondition_solver there
 int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
-                            int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, hipStream_t s);
+                            int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, int check,
+                            hipStream_t s);
 bool cnn_covers(const void* net, long long cells);
 int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s);
 // timing helpers (poisson.hip)

@@ -121,6 +121,9 @@ __device__ inline int slot_rr(int i) { return (i & 1) ? 1 : 0; }
 __device__ inline int slot_rz(int i) { return (i & 1) ? 3 : 2; }
 __device__ inline int slot_dq(int i) { return (i & 1) ? 5 : 4; }
 inline int slot_rr_host(int i) { return (i & 1) ? 1 : 0; }
+inline int slot_rz_host(int i) { return (i & 1) ? 3 : 2; }
+// flexible CG: <r,r> of the generic update kernel, <z,r> ping-pong, <z, r_prev>, <d,q>
+constexpr int FCG_RR = 10, FCG_ZR = 11, FCG_ZRP = 13, FCG_DQ = 14;
 constexpr int SLOT_B2 = 6;    // <b,b>
 constexpr int SLOT_R2D = 7;   // <r,r> of the double residual before any rounding
 constexpr int SLOT_RES0 = 8, SLOT_RES1 = 9;
@@ -703,8 +706,9 @@ __device__ inline f4 aq4(unsigned pc4, f4 c, float w, float e, f4 s, f4 n, f4 b,
 }
 
 // Pass A in FP32 (see k_pcg_a for the mathematics).  skip_x: the x update of this pass
-// was already folded into the FP64 solution by a residual replacement.
-template <bool FIRST>
+// was already folded into the FP64 solution by a residual replacement.  FLEX: flexible
+// CG, beta = (<z,r> - <z,r_prev>) / <z_prev,r_prev> with <z,r_prev> in slot FCG_ZRP.
+template <bool FIRST, bool FLEX = false>
 __global__ void __launch_bounds__(NT) k_pcg_a_f4(Geo g, const uint8_t* __restrict__ pcode,
                                                  const float* __restrict__ zz, const float* __restrict__ dold,
                                                  float* __restrict__ dnew, float* __restrict__ x,
@@ -717,12 +721,19 @@ __global__ void __launch_bounds__(NT) k_pcg_a_f4(Geo g, const uint8_t* __restric
     double alpha = 0.0, beta = 0.0;
     const long long N = (long long)g.nx * g.ny * g.nz;
     if (!FIRST) {
-        const int sl[4] = {slot_rr(it), slot_rz(it), slot_rz(it - 1), slot_dq(it - 1)};
-        double tot[4];
-        sum_slots<4>(partials, sl, nparts, sh, tot);
+        double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (FLEX) {
+            const int sl[5] = {slot_rr(it), slot_rz(it), slot_rz(it - 1), slot_dq(it - 1), FCG_ZRP};
+            sum_slots<5>(partials, sl, nparts, sh, tot);
+        } else {
+            const int sl[4] = {slot_rr(it), slot_rz(it), slot_rz(it - 1), slot_dq(it - 1)};
+            double t4[4];
+            sum_slots<4>(partials, sl, nparts, sh, t4);
+            for (int q = 0; q < 4; ++q) tot[q] = t4[q];
+        }
         const double rr = tot[0], rz = tot[1], rzp = tot[2], dq = tot[3];
         alpha = skip_x ? 0.0 : rzp / dq;
-        beta = rz / rzp;
+        beta = FLEX ? (rz - tot[4]) / rzp : rz / rzp;
         if (!(rr == rr)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 sv->nan_seen = 1;
@@ -822,9 +833,12 @@ __global__ void __launch_bounds__(NT) k_pcg_a_f4(Geo g, const uint8_t* __restric
     if (threadIdx.x == 0) partials[slot_dq(it) * MAX_BLOCKS + blockIdx.x] = vv[0];
 }
 
-// Pass B in FP32: r_{it+1} = r_it - alpha A d_it, z = M^-1 r; partials.
+// Pass B in FP32: r_{it+1} = r_it - alpha A d_it into rout (may be r), and with JZ the
+// Jacobi z = M^-1 r; partials <r,r> (and <r,z>).  Without JZ the preconditioner is
+// applied by a separate step (the learned one) and <r,z> comes from there.
+template <bool JZ = true>
 __global__ void __launch_bounds__(NT) k_pcg_b_f4(Geo g, const uint8_t* __restrict__ pcode,
-                                                 const float* __restrict__ d, float* __restrict__ r,
+                                                 const float* __restrict__ d, const float* r, float* rout,
                                                  float* __restrict__ zz, double* __restrict__ partials, int nparts,
                                                  int it, const Solver* sv) {
     if (sv->converged) return;
@@ -870,15 +884,17 @@ __global__ void __launch_bounds__(NT) k_pcg_b_f4(Geo g, const uint8_t* __restric
             const unsigned pc4 = *reinterpret_cast<const unsigned*>(pcode + c);
             const f4 q = aq4(pc4, xc, xw, xe, xs, xn, xb, xt, idx2);
             const f4 rn = fma4(-af, q, ld4(r, c));
-            f4 z;
-            z.x = invf[jcount((uint8_t)(pc4 & 0xFFu))] * rn.x;
-            z.y = invf[jcount((uint8_t)((pc4 >> 8) & 0xFFu))] * rn.y;
-            z.z = invf[jcount((uint8_t)((pc4 >> 16) & 0xFFu))] * rn.z;
-            z.w = invf[jcount((uint8_t)(pc4 >> 24))] * rn.w;
-            st4nt(r, c, rn);
-            st4nt(zz, c, z);
+            st4nt(rout, c, rn);
             v[0] += (double)dot4(rn, rn);
-            v[1] += (double)dot4(rn, z);
+            if (JZ) {
+                f4 z;
+                z.x = invf[jcount((uint8_t)(pc4 & 0xFFu))] * rn.x;
+                z.y = invf[jcount((uint8_t)((pc4 >> 8) & 0xFFu))] * rn.y;
+                z.z = invf[jcount((uint8_t)((pc4 >> 16) & 0xFFu))] * rn.z;
+                z.w = invf[jcount((uint8_t)(pc4 >> 24))] * rn.w;
+                st4nt(zz, c, z);
+                v[1] += (double)dot4(rn, z);
+            }
             xb = xc;
             xc = xt;
         }
@@ -886,7 +902,7 @@ __global__ void __launch_bounds__(NT) k_pcg_b_f4(Geo g, const uint8_t* __restric
     block_reduce<2>(v, sh);
     if (threadIdx.x == 0) {
         partials[slot_rr(it + 1) * MAX_BLOCKS + blockIdx.x] = v[0];
-        partials[slot_rz(it + 1) * MAX_BLOCKS + blockIdx.x] = v[1];
+        if (JZ) partials[slot_rz(it + 1) * MAX_BLOCKS + blockIdx.x] = v[1];
     }
 }
 
@@ -1073,7 +1089,7 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nre
         T* dnew = dbuf[it & 1];
         if constexpr (std::is_same<T, float>::value) {
             if (path == 2) {
-                k_pcg_b_f4<<<nred, NT, 0, s>>>(g, c->pcode, dnew, r, z, c->partials, nred, it, c->solver);
+                k_pcg_b_f4<true><<<nred, NT, 0, s>>>(g, c->pcode, dnew, r, r, z, c->partials, nred, it, c->solver);
                 return;
             }
         }
@@ -1167,8 +1183,6 @@ __global__ void k_zero_f64(long long n, double* __restrict__ x) {
 // segment reads the init sweep's RR slot), <z,r> ping-pong in FCG_ZR + parity,
 // <z, r_prev> in FCG_ZRP, <d,q> in FCG_DQ.  Every kernel exits at once after the
 // segment has converged (the preconditioner's input kernel makes that test).
-constexpr int FCG_RR = 10, FCG_ZR = 11, FCG_ZRP = 13, FCG_DQ = 14;
-
 // d = z + beta d (beta = 0 when first); stops the segment when <z,r> is not positive
 // (the preconditioner is then not a descent direction) or not finite.
 __global__ void __launch_bounds__(NT) k_fcg_dir(long long n, const float* __restrict__ z, float* __restrict__ d,
@@ -1245,6 +1259,69 @@ __global__ void __launch_bounds__(NT) k_fcg_upd(long long n, float* __restrict__
     if (threadIdx.x == 0) partials[FCG_RR * MAX_BLOCKS + blockIdx.x] = v[0];
 }
 
+// One FCG segment on the fused FP32 passes (nx % 4 == 0), from a residual replacement
+// whose init sweep wrote the RR slot of parity it0 (r in c->r32, e = 0).  Iteration it:
+// the network gives z_it = M(r_it) with <z,r> in RZ(it) and <z, r_{it-1}> in FCG_ZRP;
+// pass A (flexible beta) applies the lagging x update, forms d_it and <d, A d>; pass B
+// writes r_{it+1} into the other residual buffer with <r,r>.  Convergence is tested by
+// pass A, as in cg_loop.  Sets *made; returns the device flag.
+static int fcg_segment_fused(ibm_ctx* c, int nred, int it0, int max_iter, int check_every, int* made,
+                             hipStream_t s) {
+    const Geo& g = c->geo;
+    float* rb[2] = {c->r32, c->zprev32};
+    float* dbuf[2] = {c->d32, c->q32};
+    int cur = 0;
+    if (check_every <= 0) check_every = 8;
+    int total = 0;
+    int batch = c->last_iters_inner > 0 ? c->last_iters_inner + 1 : check_every;
+    auto pass_a = [&](int it, int k) {
+        float* dnew = dbuf[it & 1];
+        float* dold = dbuf[(it + 1) & 1];
+        if (k == 0)
+            k_pcg_a_f4<true><<<nred, NT, 0, s>>>(g, c->pcode, c->z32, dold, dnew, c->e32, c->partials, nred, it, 0,
+                                                 c->solver);
+        else
+            k_pcg_a_f4<false, true><<<nred, NT, 0, s>>>(g, c->pcode, c->z32, dold, dnew, c->e32, c->partials, nred,
+                                                        it, 0, c->solver);
+    };
+    while (true) {
+        int nb = batch;
+        if (nb > max_iter - total) nb = max_iter - total;
+        for (int k = total; k < total + nb; ++k) {
+            const int it = it0 + k;
+            timing_begin(c, TK_SPMV, s);
+            int rc = cnn_precondition_solver(c->cnn, c, rb[cur], k ? rb[cur ^ 1] : nullptr, c->z32, c->partials, nred,
+                                             slot_rr_host(it), slot_rz_host(it), k ? FCG_ZRP : -1, c->solver, it, 0,
+                                             s);
+            timing_end(c, TK_SPMV, s);
+            if (rc) return rc;
+            timing_begin(c, TK_UPDATE, s);
+            pass_a(it, k);
+            k_pcg_b_f4<false><<<nred, NT, 0, s>>>(g, c->pcode, dbuf[it & 1], rb[cur], rb[cur ^ 1], nullptr, c->partials,
+                                                  nred, it, c->solver);
+            timing_end(c, TK_UPDATE, s);
+            cur ^= 1;
+        }
+        IBM_HIP(hipGetLastError());
+        total += nb;
+        if (total >= max_iter) {
+            pass_a(it0 + total, total);   // tests r and applies the last x update
+            IBM_HIP(hipGetLastError());
+        }
+        IBM_HIP(hipMemcpyAsync(c->h_solver, c->solver, sizeof(Solver), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        if (c->h_solver->converged || total >= max_iter) break;
+        batch = check_every;
+    }
+    int m = c->h_solver->iters - it0;
+    if (m < 0) m = 0;
+    *made = m;
+    c->last_iters_inner = m;
+    timing_collect(c);
+    if (c->timing_on) c->t_real_iters += m;
+    return c->h_solver->converged;
+}
+
 // One FCG segment from a residual replacement whose init sweep wrote the RR slot of
 // parity it0 (r in c->r32, e = 0).  Sets *made to the iterations made; returns the
 // device flag as cg_loop does.
@@ -1263,7 +1340,7 @@ static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_ev
             const int zr = FCG_ZR + (k & 1), zrprev = FCG_ZR + ((k + 1) & 1);
             timing_begin(c, TK_SPMV, s);
             int rc = cnn_precondition_solver(c->cnn, c, rb[cur], k ? rb[cur ^ 1] : nullptr, c->z32, c->partials, nred,
-                                             k ? FCG_RR : slot_rr_host(it0), zr, k ? FCG_ZRP : -1, c->solver, it, s);
+                                             k ? FCG_RR : slot_rr_host(it0), zr, k ? FCG_ZRP : -1, c->solver, it, 1, s);
             timing_end(c, TK_SPMV, s);
             if (rc) return rc;
             timing_begin(c, TK_UPDATE, s);
@@ -1400,13 +1477,21 @@ int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts*
         set_error("IBM_SOLVER_FCG_CNN: network workspace smaller than the grid");
         return IBM_ERR_ARG;
     }
-    const int nred = march_blocks(c->geo);
+    const Geo& g = c->geo;
+    const bool quad = (g.nx % 4) == 0 && ((uintptr_t)c->r32 % 16) == 0 && ((uintptr_t)c->zprev32 % 16) == 0 &&
+                      ((uintptr_t)c->z32 % 16) == 0 && ((uintptr_t)c->e32 % 16) == 0 &&
+                      ((uintptr_t)c->d32 % 16) == 0 && ((uintptr_t)c->q32 % 16) == 0;
+    const int nred = quad ? fmarch_blocks(g) : march_blocks(g);
     const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : 1000;
     int rc = cnn_prepare_geometry(c->cnn, c, s);
     if (rc) return rc;
     return refine_solve(
         c, b, x, o, st, nred,
-        [&](int it, int* made) { return fcg_segment(c, nred, it, inner_max, o->check_every, made, s); }, s);
+        [&](int it, int* made) {
+            return quad ? fcg_segment_fused(c, nred, it, inner_max, o->check_every, made, s)
+                        : fcg_segment(c, nred, it, inner_max, o->check_every, made, s);
+        },
+        s);
 }
 
 int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {
