@@ -254,15 +254,16 @@ int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* 
  * must cover the grid and outlive its use. */
 int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net);
 
-/* Measurement support (not part of the method).  When enabled, every launch of
- * the three conjugate-gradient sweeps (0: SpMV + <d,q>, 1: x/r update + <r,r> +
- * <r,z>, 2: direction update) is bracketed by HIP events on its own stream; the
- * elapsed times are collected at the end of each solve.  ibm_timing_read fills
- * out[0..2] = accumulated milliseconds per sweep, out[3..5] = launches per sweep,
- * out[6] = iterations that did work (launches after convergence exit at once),
- * out[7] = cells, out[8] = cuts, out[9] = precision; reset != 0 zeroes the
- * accumulators.  Enabling creates the events once (host objects, no device
- * memory). */
+/* Measurement support (not part of the method).  When enabled, launches of the
+ * pressure solve are bracketed by HIP events on its stream and the elapsed times are
+ * collected at the end of each solve.  Slots: 0 = CG pass A (SpMV, <d,q>; for the
+ * learned solve: the whole preconditioner application), 1 = CG pass B (update, <r,r>,
+ * <r,z>; for the learned solve: passes A and B), 2 = the dominant convolution of the
+ * learned preconditioner (gated 16 -> 16 adjoint).  ibm_timing_read fills out[0..2] =
+ * accumulated milliseconds per slot, out[3..5] = launches per slot, out[6] =
+ * iterations that did work (launches after convergence exit at once), out[7] =
+ * cells, out[8] = cuts, out[9] = precision; reset != 0 zeroes the accumulators.
+ * Enabling creates the events once (host objects, no device memory). */
 int ibm_timing_enable(ibm_ctx* ctx, int32_t on);
 int ibm_timing_read(ibm_ctx* ctx, double out[10], int32_t reset);
 

@@ -880,7 +880,8 @@ int mconv_blocks(int nx, int ny, int nz, int mz) {
     return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY) * ((nz + mz - 1) / mz);
 }
 
-int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv, hipStream_t s) {
+int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv, hipStream_t s,
+                ibm_ctx* timed = nullptr) {
     if (!keep) {
         // solver path: marching kernels, no activations kept
         const int mz = mconv_planes(nx, ny, nz);
@@ -888,7 +889,9 @@ int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv,
         const uint16_t* wg = pw(n, PV_WG);
         k_mconv<1, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, pw(n, PV_W1), n->a1, n->xg, wg, sv);
         k_mconv<16, 16, EPI_BF16><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W2), n->y, nullptr, nullptr, sv);
+        if (timed) timing_begin(timed, TK_DIR, s);
         k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->bb, n->xg, wg, sv);
+        if (timed) timing_end(timed, TK_DIR, s);
         k_mconv<16, 1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->bb, pw(n, PV_W1T), n->out, nullptr, nullptr,
                                                    sv);
         IBM_HIP(hipGetLastError());
@@ -1014,7 +1017,7 @@ int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* 
     const Geo& g = c->geo;
     k_input<float><<<nparts, NT, 0, s>>>(c->N, r, partials + (long long)rr_slot * MAX_BLOCKS, nparts, n->xr,
                                          n->scal, sv, it, check);
-    int rc = net_forward(n, g.nx, g.ny, g.nz, false, sv, s);
+    int rc = net_forward(n, g.nx, g.ny, g.nz, false, sv, s, sv ? c : nullptr);
     if (rc) return rc;
     k_combine<<<nparts, NT, 0, s>>>(c->N, g.dx * g.dx, r, rp, c->pcode, n->out, n->scal, z, partials, zr_slot,
                                      zrp_slot, sv);

@@ -231,6 +231,8 @@ int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* 
 bool cnn_covers(const void* net, long long cells);
 int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s);
 // timing helpers (poisson.hip)
+// timed kernel slots: the two CG passes (or the preconditioner and the passes of the
+// learned solve), the dominant convolution of the learned preconditioner, spare
 enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3 };
 void timing_begin(ibm_ctx* c, int k, hipStream_t s);
 void timing_end(ibm_ctx* c, int k, hipStream_t s);

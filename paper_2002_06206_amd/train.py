@@ -17,14 +17,15 @@ import torch
 
 from . import ibm, inputs
 
-TRAIN_SEEDS = (101, 102, 103, 104, 105, 106)
+TRAIN_SEEDS = tuple(range(101, 121))   # 20 windows
 EVAL_SEEDS = (201, 202)
 
 
-def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: float = 1e-8):
+def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: float = 1e-8, first: int = 2):
     """Runs the plain FP64 solver for `steps` CFL-0.3 steps and keeps (b, p) of every
-    `every`-th step (b = the compatible Poisson right-hand side, p = its solution).
-    Returns the solver (it owns the stencil the pairs belong to) and the pairs."""
+    `every`-th step from step `first` on (b = the compatible Poisson right-hand side,
+    p = its solution).  Returns the solver (it owns the stencil the pairs belong to)
+    and the pairs."""
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
     blocked, theta = s.tag(case.tri)
     s.build(blocked, None, case.deadend)
@@ -38,7 +39,7 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
         if rc < 0 or not np.isfinite(stats["umax"]):
             break
         umax, dt_prev = stats["umax"], dt
-        if k % every == every - 1:
+        if k >= first and (k - first) % every == 0:
             b = s.rhs()
             if float(torch.linalg.vector_norm(b)) > 0.0:
                 pairs.append((b, st["p"].clone()))
@@ -48,7 +49,7 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
 def build_dataset(seeds, n: int = 64, steps: int = 24, every: int = 3):
     data = []
     for seed in seeds:
-        s, pairs = generate_pairs(inputs.case_ellipsoid_window(seed, n), steps, every)
+        s, pairs = generate_pairs(inputs.case_ellipsoid_window(seed, n), steps, every, first=min(2, steps - 1))
         if pairs:
             data.append((s, pairs))
     return data
