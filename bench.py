@@ -61,6 +61,10 @@ def workload(name):
         return inputs.case_sphere32(0)
     if name == "plate256":
         return inputs.case_plate256(0)
+    if name == "vehicle1024":
+        # 1024^3 cells, ~1M-triangle vehicle-like assembly, dead-end filter on; run as
+        #   python bench.py --workload vehicle1024 --steps 2 --warmup 1 --no-cpu-baseline
+        return inputs.case_vehicle(1024, 0)
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -137,12 +141,11 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
             "mixed_learned": ibm.SOLVER_FCG_CNN}[solver]
     t0 = time.perf_counter()
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, precision)
-    blocked, theta = s.tag(case.tri)
+    blocked, _ = s.tag(case.tri, want_theta=False)
     s.build(blocked, None, case.deadend)
-    del theta
     net = None
     if solver == "mixed_learned":
-        net = ibm.Network(N, weights)
+        net = ibm.Network(N, weights, inference_only=True)
         net.attach(s)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -151,19 +154,29 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     # the configured dt (= CFL 0.3 on the inflow velocity); variable-step AB2
     ctl = {"dt_prev": 0.0, "umax": max(abs(v) for v in case.u_in)}
 
-    def params(step):
+    def params(step, tol=None):
         dt = min(case.dt, 0.3 * case.dx / max(ctl["umax"], 1e-30))
-        p = ibm.step_params(dt, case.nu, csm=case.csm, step=step, dt_prev=ctl["dt_prev"], tol=args.tol,
+        p = ibm.step_params(dt, case.nu, csm=case.csm, step=step, dt_prev=ctl["dt_prev"],
+                            tol=args.tol if tol is None else tol,
                             max_iter=20000, check_every=16, kind=kind, inner_tol=args.inner_tol,
                             inner_max_iter=2000)
         ctl["dt_prev"] = dt
         return p
 
+    # progress lines on stderr for workloads whose steps take many seconds
+    verbose = N >= 512 ** 3
+
+    def progress(msg):
+        if verbose:
+            print("[bench] %s: %s (%.0f s)" % (solver, msg, time.perf_counter() - t0), file=sys.stderr, flush=True)
+
+    progress("set-up done")
     step = 0
     for _ in range(args.warmup):
-        rc, stats = s.step(st, params(step))
+        rc, stats = s.step(st, params(step, args.warmup_tol))
         ctl["umax"] = stats["umax"]
         step += 1
+        progress("warm-up step %d: %d iterations" % (step, stats["iters_inner"]))
     ibm.ibm_timing_enable(s.ctx, True)
     ibm.ibm_timing_read(s.ctx, reset=True)
     torch.cuda.synchronize()
@@ -182,6 +195,7 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
         fallbacks += stats["fallback_used"]
         worst_res = max(worst_res, stats["rel_residual"])
         worst_div = max(worst_div, stats["div_linf"])
+        progress("timed step %d: %d iterations" % (step, stats["iters_inner"]))
         if rc != 0:
             raise SystemExit("%s: step %d did not converge (rc=%d)" % (solver, step, rc))
     torch.cuda.synchronize()
@@ -258,6 +272,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ellipsoids256")
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--warmup-tol", type=float, default=None,
+                    help="Poisson tolerance of the untimed warm-up steps (default: --tol)")
     ap.add_argument("--inner-tol", type=float, default=1e-1,
                     help="mixed solve: residual reduction of each FP32 segment between FP64 replacements")
     ap.add_argument("--solver", default="mixed_learned", choices=["mixed", "mixed_learned", "pcg_fp64"],
@@ -280,8 +296,11 @@ def main():
     case = workload(args.workload)
     N = case.n[0] * case.n[1] * case.n[2]
 
-    plain = run_solver(case, "pcg_fp64", args, ibm, torch)
-    runs = {"pcg_fp64": plain, "mixed": run_solver(case, "mixed", args, ibm, torch)}
+    # the plain FP64 context and state (~330 B per cell) do not fit one GPU at 1024^3
+    plain = run_solver(case, "pcg_fp64", args, ibm, torch) if N <= 512 ** 3 else None
+    runs = {"mixed": run_solver(case, "mixed", args, ibm, torch)}
+    if plain is not None:
+        runs["pcg_fp64"] = plain
     train_info = None
     if not args.no_learned or args.solver == "mixed_learned":
         w, train_info = train_network(args, ibm, torch)
@@ -312,7 +331,7 @@ def main():
                     "avg_launch_us": round(dom["avg_s"] * 1e6, 2), "launches": dom["launches"],
                     "launches_with_work": dom["launches_with_work"], "sweeps_ms": dom["sweeps_ms"]}
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and plain is not None:
         cpu = cpu_baseline(case, plain["iters_per_step"])
     out = {
         "metric": METRIC,
@@ -330,10 +349,10 @@ def main():
         "config": {"workload": case.name, "cells": list(case.n), "triangles": int(len(case.tri)),
                    "cuts": head["cuts"], "solver": head["solver"], "tol": args.tol, "inner_tol": args.inner_tol,
                    "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm},
-        "plain_fp64_value": plain["value"],
-        "speedup_vs_plain_fp64": head["value"] / plain["value"],
+        "plain_fp64_value": plain["value"] if plain else None,
+        "speedup_vs_plain_fp64": head["value"] / plain["value"] if plain else None,
         "solvers": {k: {kk: vv for kk, vv in v.items() if kk != "dominant"} for k, v in runs.items()},
-        "speedups_vs_plain_fp64": {k: round(v["value"] / plain["value"], 4) for k, v in runs.items()},
+        "speedups_vs_plain_fp64": {k: round(v["value"] / plain["value"], 4) for k, v in runs.items()} if plain else None,
         "training": train_info,
         "roofline": roofline,
         "roofline_sweeps": roofline_sweeps,

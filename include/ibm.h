@@ -135,7 +135,8 @@ int ibm_tag_geometry(ibm_ctx* ctx, const double* tri_dev, int64_t ntri, uint8_t*
                      double* theta_dev, void* stream);
 
 /* Stencil build (Sec. 2.3.1-2.3.2): from blocked bits and theta (theta_dev NULL = the
- * context's copy from the last ibm_tag_geometry), applies the dead-end filter of
+ * context's copy from the last ibm_tag_geometry, which the build then releases: 48 B per
+ * cell; building again from it needs a new ibm_tag_geometry), applies the dead-end filter of
  * eq. (deadend_filter) when deadend != 0 (a cell closed in >= 5 directions is closed
  * in all six and frozen at the wall velocity; its open neighbours see a wall at its
  * centre, theta = 1), builds the cut list (one entry per blocked (cell, dir),
@@ -222,8 +223,12 @@ int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const vo
 typedef struct ibm_cnn ibm_cnn;
 
 /* Creates a network on the current HIP device with all weights zero and workspace for
- * grids of up to max_cells cells (about 380 bytes per cell). */
-int ibm_cnn_create(int64_t max_cells, ibm_cnn** out);
+ * grids of up to max_cells cells: about 380 bytes per cell, or 72 with
+ * IBM_CNN_INFERENCE_ONLY in flags (then only ibm_cnn_set/get_weights,
+ * ibm_cnn_forward, ibm_cnn_precondition and the solver use it; training and backward
+ * calls return IBM_ERR_ARG). */
+#define IBM_CNN_INFERENCE_ONLY 1
+int ibm_cnn_create(int64_t max_cells, int32_t flags, ibm_cnn** out);
 int ibm_cnn_destroy(ibm_cnn* net);
 /* Host FP32 weights in, n = IBM_CNN_NWEIGHTS; resets the Adam state.  Synchronous. */
 int ibm_cnn_set_weights(ibm_cnn* net, const float* w_host, int64_t n);

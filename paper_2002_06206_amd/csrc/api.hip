@@ -205,18 +205,31 @@ int ibm_build_stencils(ibm_ctx* c, const uint8_t* blocked, const double* theta, 
     if (int rc = check_device(c)) return rc;
     if (!blocked) return bad("ibm_build_stencils: null blocked");
     if (!theta) {
-        if (!c->tagged) return bad("ibm_build_stencils: theta is NULL and no tagging has run on this context");
+        if (!c->tagged)
+            return bad("ibm_build_stencils: theta is NULL and the context holds no tagging (none ran, or a "
+                       "previous build consumed it)");
         theta = c->theta;
     }
     hipStream_t s = (hipStream_t)stream;
     c->stencil_ready = false;
     c->last_iters = 0;
     c->nut_valid = false;
+    const bool own_theta = theta == c->theta;
     int rc = stencil_run(c, blocked, theta, deadend ? 1 : 0, s);
     if (rc) return rc;
     if (flags) IBM_HIP(hipMemcpyAsync(flags, c->flags, sizeof(uint16_t) * c->N, hipMemcpyDeviceToDevice, s));
     if (label) IBM_HIP(hipMemcpyAsync(label, c->label, sizeof(int32_t) * c->N, hipMemcpyDeviceToDevice, s));
     if (n_cut_out) *n_cut_out = c->ncut;
+    if (own_theta) {
+        // the compact cut list now holds what the step needs: release the dense copy
+        // (48 B per cell) and the tagging mask
+        IBM_HIP(hipStreamSynchronize(s));
+        IBM_HIP(hipFree(c->theta));
+        IBM_HIP(hipFree(c->tagmask));
+        c->theta = nullptr;
+        c->tagmask = nullptr;
+        c->tagged = false;
+    }
     return IBM_OK;
 }
 

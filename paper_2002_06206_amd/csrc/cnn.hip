@@ -807,6 +807,7 @@ struct ibm_cnn {
     double* h_scal;  // pinned host copy
     int nx, ny, nz;  // dims of the last forward
     bool have_fwd;
+    bool train_ok;   // training buffers allocated (not IBM_CNN_INFERENCE_ONLY)
 };
 
 namespace ibm {
@@ -889,10 +890,11 @@ int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv,
         const uint16_t* wg = pw(n, PV_WG);
         k_mconv<1, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, pw(n, PV_W1), n->a1, n->xg, wg, sv);
         k_mconv<16, 16, EPI_BF16><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W2), n->y, nullptr, nullptr, sv);
+        // the gated adjoint output reuses a1's buffer (a1 is dead once y exists)
         if (timed) timing_begin(timed, TK_DIR, s);
-        k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->bb, n->xg, wg, sv);
+        k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv);
         if (timed) timing_end(timed, TK_DIR, s);
-        k_mconv<16, 1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->bb, pw(n, PV_W1T), n->out, nullptr, nullptr,
+        k_mconv<16, 1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1T), n->out, nullptr, nullptr,
                                                    sv);
         IBM_HIP(hipGetLastError());
         n->nx = nx;
@@ -970,11 +972,20 @@ int check_grid(const ibm_cnn* n, long long cells) {
     return IBM_OK;
 }
 
-// gate of the context's geometry
+// geometry input of the context (and, for training networks, the stored gate the
+// training kernels use; the solver path computes the gate on the fly)
 int prepare_geometry(ibm_cnn* n, ibm_ctx* c, hipStream_t s) {
     k_geom<<<2048, 256, 0, s>>>(c->N, c->pcode, n->xg);
     IBM_HIP(hipGetLastError());
-    return net_gate(n, c->geo.nx, c->geo.ny, c->geo.nz, s);
+    return n->train_ok ? net_gate(n, c->geo.nx, c->geo.ny, c->geo.nz, s) : IBM_OK;
+}
+
+int need_training(const ibm_cnn* n, const char* what) {
+    if (!n->train_ok) {
+        set_error(std::string(what) + ": network was created inference-only");
+        return IBM_ERR_ARG;
+    }
+    return IBM_OK;
 }
 
 // Loss of one pair (b, p), L p = b, on the context's stencil, and the gradient signal
@@ -1063,8 +1074,8 @@ int net_check(const ibm_cnn* n) {
 
 extern "C" {
 
-int ibm_cnn_create(int64_t max_cells, ibm_cnn** out) {
-    if (!out || max_cells <= 0) {
+int ibm_cnn_create(int64_t max_cells, int32_t flags, ibm_cnn** out) {
+    if (!out || max_cells <= 0 || (flags & ~IBM_CNN_INFERENCE_ONLY)) {
         set_error("ibm_cnn_create: bad arguments");
         return IBM_ERR_ARG;
     }
@@ -1081,6 +1092,7 @@ int ibm_cnn_create(int64_t max_cells, ibm_cnn** out) {
         return IBM_ERR_HIP;
     }
     n->cap = max_cells;
+    n->train_ok = !(flags & IBM_CNN_INFERENCE_ONLY);
     fill_pack_desc(n);
     const size_t cap = (size_t)max_cells;
     bool ok = true;
@@ -1094,17 +1106,21 @@ int ibm_cnn_create(int64_t max_cells, ibm_cnn** out) {
     alloc((void**)&n->wp, (size_t)packed_elems(n) * sizeof(uint16_t));
     alloc((void**)&n->xr, cap * sizeof(uint16_t));
     alloc((void**)&n->xg, cap * sizeof(uint16_t));
-    uint16_t** c16[] = {&n->G, &n->u1, &n->a1, &n->y, &n->vv, &n->bb, &n->sig[0], &n->sig[1]};
-    for (uint16_t** pp : c16) alloc((void**)pp, cap * 16 * sizeof(uint16_t));
-    alloc((void**)&n->dy1, cap * sizeof(uint16_t));
-    alloc((void**)&n->dG, cap * 16 * sizeof(float));
+    alloc((void**)&n->a1, cap * 16 * sizeof(uint16_t));
+    alloc((void**)&n->y, cap * 16 * sizeof(uint16_t));
     alloc((void**)&n->out, cap * sizeof(float));
-    alloc((void**)&n->wpart, (size_t)WG_MAX_BLOCKS * 27 * 256 * sizeof(float));
-    alloc((void**)&n->h, cap * sizeof(double));
-    alloc((void**)&n->q, cap * sizeof(double));
-    alloc((void**)&n->f, cap * sizeof(double));
     alloc((void**)&n->part, 3 * MAX_BLOCKS * sizeof(double));
     alloc((void**)&n->scal, 8 * sizeof(double));
+    if (n->train_ok) {
+        uint16_t** c16[] = {&n->G, &n->u1, &n->vv, &n->bb, &n->sig[0], &n->sig[1]};
+        for (uint16_t** pp : c16) alloc((void**)pp, cap * 16 * sizeof(uint16_t));
+        alloc((void**)&n->dy1, cap * sizeof(uint16_t));
+        alloc((void**)&n->dG, cap * 16 * sizeof(float));
+        alloc((void**)&n->wpart, (size_t)WG_MAX_BLOCKS * 27 * 256 * sizeof(float));
+        alloc((void**)&n->h, cap * sizeof(double));
+        alloc((void**)&n->q, cap * sizeof(double));
+        alloc((void**)&n->f, cap * sizeof(double));
+    }
     if (ok && hipHostMalloc((void**)&n->h_scal, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) ok = false;
     if (!ok) {
         net_free(n);
@@ -1173,8 +1189,12 @@ int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t n
     hipStream_t s = (hipStream_t)stream;
     k_split<<<2048, 256, 0, s>>>(cells, x_dev, net->xr, net->xg);
     IBM_HIP(hipGetLastError());
-    if ((rc = net_gate(net, nx, ny, nz, s))) return rc;
-    if ((rc = net_forward(net, nx, ny, nz, true, nullptr, s))) return rc;
+    if (net->train_ok) {
+        if ((rc = net_gate(net, nx, ny, nz, s))) return rc;
+        if ((rc = net_forward(net, nx, ny, nz, true, nullptr, s))) return rc;
+    } else if ((rc = net_forward(net, nx, ny, nz, false, nullptr, s))) {
+        return rc;
+    }
     IBM_HIP(hipMemcpyAsync(y_dev, net->out, cells * sizeof(float), hipMemcpyDeviceToDevice, s));
     return IBM_OK;
 }
@@ -1182,6 +1202,7 @@ int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t n
 int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx_dev, void* stream) {
     int rc = net_check(net);
     if (rc) return rc;
+    if ((rc = need_training(net, "ibm_cnn_backward"))) return rc;
     if (!dy_dev || !dw_dev) {
         set_error("ibm_cnn_backward: bad arguments");
         return IBM_ERR_ARG;
@@ -1203,6 +1224,7 @@ int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* 
                  float* dw_dev, void* stream) {
     int rc = net_check(net);
     if (rc) return rc;
+    if ((rc = need_training(net, "ibm_cnn_loss"))) return rc;
     if (!ctx || !ctx->stencil_ready || !b_dev || !p_dev) {
         set_error("ibm_cnn_loss: bad arguments (context needs a stencil)");
         return IBM_ERR_ARG;
@@ -1224,6 +1246,7 @@ int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const do
                        double* loss_out, void* stream) {
     int rc = net_check(net);
     if (rc) return rc;
+    if ((rc = need_training(net, "ibm_cnn_train_step"))) return rc;
     if (!ctx || !ctx->stencil_ready || !b_dev || !p_dev || !(lr > 0.0f)) {
         set_error("ibm_cnn_train_step: bad arguments (context needs a stencil, lr > 0)");
         return IBM_ERR_ARG;

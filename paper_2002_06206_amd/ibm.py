@@ -82,7 +82,7 @@ def _load():
         "ibm_forces": ([vp, P3, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
         "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
         "ibm_timing_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
-        "ibm_cnn_create": ([ctypes.c_int64, ctypes.POINTER(vp)], ctypes.c_int),
+        "ibm_cnn_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int),
         "ibm_cnn_destroy": ([vp], ctypes.c_int),
         "ibm_cnn_set_weights": ([vp, vp, ctypes.c_int64], ctypes.c_int),
         "ibm_cnn_get_weights": ([vp, vp, ctypes.c_int64], ctypes.c_int),
@@ -218,9 +218,12 @@ def ibm_timing_read(ctx, reset=False):
             "cuts": int(v[8]), "precision": int(v[9])}
 
 
-def ibm_cnn_create(max_cells):
+CNN_INFERENCE_ONLY = 1
+
+
+def ibm_cnn_create(max_cells, flags=0):
     out = ctypes.c_void_p()
-    _check(_lib.ibm_cnn_create(int(max_cells), ctypes.byref(out)), "ibm_cnn_create")
+    _check(_lib.ibm_cnn_create(int(max_cells), int(flags), ctypes.byref(out)), "ibm_cnn_create")
     return out
 
 
@@ -307,11 +310,14 @@ class Solver:
         except Exception:
             pass
 
-    def tag(self, tri):
+    def tag(self, tri, want_theta=True):
+        """Blocked bits and (when want_theta) a copy of theta; the context keeps its own
+        theta for the next build either way."""
         tri_t = torch.as_tensor(tri, dtype=torch.float64).to(self.dev).contiguous()
         blocked = torch.zeros(self.shape, dtype=torch.uint8, device=self.dev)
-        theta = torch.empty(self.shape + (6,), dtype=torch.float64, device=self.dev)
+        theta = torch.empty(self.shape + (6,), dtype=torch.float64, device=self.dev) if want_theta else None
         ibm_tag_geometry(self.ctx, tri_t.reshape(-1, 3, 3), blocked, theta)
+        del tri_t
         return blocked, theta
 
     def build(self, blocked, theta=None, deadend=False):
@@ -360,8 +366,8 @@ class Solver:
 class Network:
     """Owns one learned-preconditioner network on the current HIP device."""
 
-    def __init__(self, max_cells, weights=None):
-        self.net = ibm_cnn_create(max_cells)
+    def __init__(self, max_cells, weights=None, inference_only=False):
+        self.net = ibm_cnn_create(max_cells, CNN_INFERENCE_ONLY if inference_only else 0)
         if weights is not None:
             ibm_cnn_set_weights(self.net, weights)
 

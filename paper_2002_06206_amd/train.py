@@ -27,9 +27,8 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
     p = its solution).  Returns the solver (it owns the stencil the pairs belong to)
     and the pairs."""
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
-    blocked, theta = s.tag(case.tri)
+    blocked, _ = s.tag(case.tri, want_theta=False)
     s.build(blocked, None, case.deadend)
-    del theta
     st = s.new_state(case.u_in)
     pairs = []
     umax, dt_prev = max(abs(v) for v in case.u_in), 0.0
