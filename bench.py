@@ -171,6 +171,15 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
             print("[bench] %s: %s (%.0f s)" % (solver, msg, time.perf_counter() - t0), file=sys.stderr, flush=True)
 
     progress("set-up done")
+    cb = None
+    if verbose:
+        last = [time.perf_counter()]
+
+        def on_poll(iters, rr):
+            if time.perf_counter() - last[0] > 20.0:
+                last[0] = time.perf_counter()
+                progress("solving, %d iterations" % iters)
+        cb = ibm.ibm_set_progress(s.ctx, on_poll)
     step = 0
     for _ in range(args.warmup):
         rc, stats = s.step(st, params(step, args.warmup_tol))
@@ -202,6 +211,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     t1 = time.perf_counter()
     tim = ibm.ibm_timing_read(s.ctx, reset=True)
     ibm.ibm_timing_enable(s.ctx, False)
+    if cb is not None:
+        ibm.ibm_set_progress(s.ctx, None)
     elapsed = t1 - t0
     bytes_tab = SWEEP_BYTES if precision == ibm.FP64 else SWEEP_BYTES_F32
     k_dom = max(range(3), key=lambda k: tim["ms"][k])

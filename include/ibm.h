@@ -270,6 +270,11 @@ int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net);
  * cells, out[8] = cuts, out[9] = precision; reset != 0 zeroes the accumulators.
  * Enabling creates the events once (host objects, no device memory). */
 int ibm_timing_enable(ibm_ctx* ctx, int32_t on);
+/* Progress hook (measurement support): when set, the pressure solve calls
+ * fn(user, iterations so far in this solve, current <r,r> of the recursive residual)
+ * from the calling thread at each of its host convergence polls.  NULL removes it. */
+typedef void (*ibm_progress_fn)(void* user, int64_t iterations, double rr);
+int ibm_set_progress(ibm_ctx* ctx, ibm_progress_fn fn, void* user);
 int ibm_timing_read(ibm_ctx* ctx, double out[10], int32_t reset);
 
 #ifdef __cplusplus

@@ -337,6 +337,13 @@ int ibm_timing_enable(ibm_ctx* c, int32_t on) {
     return IBM_OK;
 }
 
+int ibm_set_progress(ibm_ctx* c, ibm_progress_fn fn, void* user) {
+    if (!c) return bad("null context");
+    c->progress = fn;
+    c->progress_user = user;
+    return IBM_OK;
+}
+
 int ibm_timing_read(ibm_ctx* c, double out[10], int32_t reset) {
     if (!c || !out) return bad("ibm_timing_read: null argument");
     for (int k = 0; k < 3; ++k) {

@@ -108,6 +108,10 @@ struct ibm_ctx {
     double t_ms[4];         // accumulated kernel time
     long long t_launches[4];
     long long t_real_iters; // iterations that did work (the rest exit at once)
+    // optional progress hook, called at the solver's host convergence polls
+    ibm_progress_fn progress;
+    void* progress_user;
+    long long progress_iters; // iterations made by the current solve before this segment
 };
 
 namespace ibm {

@@ -1126,6 +1126,7 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nre
         // first pass A of the next batch, which then only applies the last x update
         IBM_HIP(hipMemcpyAsync(c->h_solver, c->solver, sizeof(Solver), hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
+        if (c->progress) c->progress(c->progress_user, c->progress_iters + total, c->h_solver->rr);
         if (c->h_solver->converged || total >= max_iter) break;
         batch = check_every;
     }
@@ -1310,6 +1311,7 @@ static int fcg_segment_fused(ibm_ctx* c, int nred, int it0, int max_iter, int ch
         }
         IBM_HIP(hipMemcpyAsync(c->h_solver, c->solver, sizeof(Solver), hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
+        if (c->progress) c->progress(c->progress_user, c->progress_iters + total, c->h_solver->rr);
         if (c->h_solver->converged || total >= max_iter) break;
         batch = check_every;
     }
@@ -1356,6 +1358,7 @@ static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_ev
         total += nb;
         IBM_HIP(hipMemcpyAsync(c->h_solver, c->solver, sizeof(Solver), hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
+        if (c->progress) c->progress(c->progress_user, c->progress_iters + total, c->h_solver->rr);
         if (c->h_solver->converged || total >= max_iter) break;
         batch = check_every;
     }
@@ -1389,6 +1392,7 @@ static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver
     double prev_rel = -1.0;
     bool fallback = false;
     int rc = IBM_OK;
+    c->progress_iters = 0;
     k_zero_f32<<<2048, 256, 0, s>>>(N, c->e32);
     k_pcg_init<float><<<nred, NT, 0, s>>>(g, c->pcode, b, x, c->r32, c->z32, c->partials, 0);
     k_seg_start<<<1, NT, 0, s>>>(c->partials, nred, c->solver, 0, delta, eta_tol);
@@ -1418,6 +1422,7 @@ static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver
         }
         prev_rel = rel;
         int made = 0;
+        c->progress_iters = total_inner;
         int flag = seg(it, &made);
         if (flag < 0) return flag;
         total_inner += made;
@@ -1434,6 +1439,7 @@ static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver
     }
     int fb_iters = 0;
     if (fallback) {
+        c->progress_iters = total_inner;
         rc = pcg64(c, b, x, o->tol, o->max_iter, o->check_every, &fb_iters, s);
         if (rc < 0) return rc;
     }
@@ -1502,6 +1508,7 @@ int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
         rc = mixed_solve(c, b, x, o, &local, s);
         iters = local.iters_inner;
     } else if (o->kind == IBM_SOLVER_PCG_JACOBI) {
+        c->progress_iters = 0;
         rc = pcg64(c, b, x, o->tol, o->max_iter, o->check_every, &iters, s);
         local.iters_outer = 0;
         local.fallback_used = 0;

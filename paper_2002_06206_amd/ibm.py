@@ -58,6 +58,9 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libibm.so is not built (run: python -m paper_2002_06206_amd.build)")
@@ -82,6 +85,7 @@ def _load():
         "ibm_forces": ([vp, P3, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
         "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
         "ibm_timing_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
+        "ibm_set_progress": ([vp, PROGRESS_FN, vp], ctypes.c_int),
         "ibm_cnn_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int),
         "ibm_cnn_destroy": ([vp], ctypes.c_int),
         "ibm_cnn_set_weights": ([vp, vp, ctypes.c_int64], ctypes.c_int),
@@ -104,7 +108,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "ibm_build_stencils",
             "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
-            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_timing_enable", "ibm_timing_read",
+            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_timing_enable", "ibm_timing_read", "ibm_set_progress",
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
             "ibm_ctx_set_preconditioner")
@@ -208,6 +212,13 @@ def ibm_forces(ctx, u, p, nu, nut=None, wall=None):
 
 def ibm_timing_enable(ctx, on=True):
     return _check(_lib.ibm_timing_enable(ctx, int(bool(on))), "ibm_timing_enable")
+
+
+def ibm_set_progress(ctx, fn):
+    """fn(iterations, rr) or None; returns the ctypes callback, which the caller keeps alive."""
+    cb = PROGRESS_FN(lambda user, it, rr: fn(int(it), float(rr))) if fn is not None else PROGRESS_FN()
+    _check(_lib.ibm_set_progress(ctx, cb, None), "ibm_set_progress")
+    return cb
 
 
 def ibm_timing_read(ctx, reset=False):
