@@ -891,9 +891,11 @@ int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv,
         k_mconv<1, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, pw(n, PV_W1), n->a1, n->xg, wg, sv);
         k_mconv<16, 16, EPI_BF16><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W2), n->y, nullptr, nullptr, sv);
         // the gated adjoint output reuses a1's buffer (a1 is dead once y exists)
-        if (timed) timing_begin(timed, TK_DIR, s);
-        k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv);
-        if (timed) timing_end(timed, TK_DIR, s);
+        if (timed)
+            launch_timed(timed, TK_DIR, k_mconv<16, 16, EPI_GATE>, mb, s, nx, ny, nz, mz, (const uint16_t*)n->y,
+                         pw(n, PV_W2T), (void*)n->a1, (const uint16_t*)n->xg, wg, sv);
+        else
+            k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv);
         k_mconv<16, 1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1T), n->out, nullptr, nullptr,
                                                    sv);
         IBM_HIP(hipGetLastError());

@@ -1,6 +1,7 @@
 // Internal declarations shared by the gfx950 kernels and the C ABI host code.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -238,6 +239,18 @@ int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s);
 // timed kernel slots: the two CG passes (or the preconditioner and the passes of the
 // learned solve), the dominant convolution of the learned preconditioner, spare
 enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3 };
+// Launches kern<<<grid, NT, 0, s>>>(args...).  When timing slot k is on, the launch
+// carries HIP's dispatch-level start/stop events (hipExtLaunchKernelGGL), so the time
+// collected is the kernel's own, without the gaps between dispatches.
+template <class F, class... Args>
+inline void launch_timed(ibm_ctx* c, int k, F kern, int grid, hipStream_t s, Args... args) {
+    if (c->timing_on && c->ev_used[k] < c->ev_cap) {
+        const int e = c->ev_used[k]++;
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, s, c->ev[k][2 * e], c->ev[k][2 * e + 1], 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, s, args...);
+    }
+}
 void timing_begin(ibm_ctx* c, int k, hipStream_t s);
 void timing_end(ibm_ctx* c, int k, hipStream_t s);
 void timing_collect(ibm_ctx* c);

@@ -1062,41 +1062,46 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nre
         T* dnew = dbuf[it & 1];
         T* dold = dbuf[(it + 1) & 1];
         const int skip = (start_it > 0 && it == start_it) ? 1 : 0;
+        const int K = TK_SPMV;
         if constexpr (std::is_same<T, float>::value) {
             if (path == 2) {
                 if (it == 0)
-                    k_pcg_a_f4<true><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, 0,
-                                                         c->solver);
+                    launch_timed(c, K, k_pcg_a_f4<true>, nred, s, g, (const uint8_t*)c->pcode, (const float*)z,
+                                 (const float*)dold, dnew, x, c->partials, nred, it, 0, c->solver);
                 else
-                    k_pcg_a_f4<false><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it,
-                                                          skip, c->solver);
+                    launch_timed(c, K, k_pcg_a_f4<false>, nred, s, g, (const uint8_t*)c->pcode, (const float*)z,
+                                 (const float*)dold, dnew, x, c->partials, nred, it, skip, c->solver);
                 return;
             }
         }
         if (path == 1) {
             if (it == 0)
-                k_pcg_a_v<T, true><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, 0,
-                                                       c->solver);
+                launch_timed(c, K, k_pcg_a_v<T, true>, nred, s, g, (const uint8_t*)c->pcode, (const T*)z,
+                             (const T*)dold, dnew, x, c->partials, nred, it, 0, c->solver);
             else
-                k_pcg_a_v<T, false><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, skip,
-                                                        c->solver);
+                launch_timed(c, K, k_pcg_a_v<T, false>, nred, s, g, (const uint8_t*)c->pcode, (const T*)z,
+                             (const T*)dold, dnew, x, c->partials, nred, it, skip, c->solver);
         } else {
-            k_pcg_a<T><<<nred, NT, 0, s>>>(g, c->pcode, z, dold, dnew, x, c->partials, nred, it, 0, skip,
-                                           c->solver);
+            launch_timed(c, K, k_pcg_a<T>, nred, s, g, (const uint8_t*)c->pcode, (const T*)z, (const T*)dold, dnew, x,
+                         c->partials, nred, it, 0, skip, c->solver);
         }
     };
     auto pass_b = [&](int it) {
         T* dnew = dbuf[it & 1];
+        const int K = TK_UPDATE;
         if constexpr (std::is_same<T, float>::value) {
             if (path == 2) {
-                k_pcg_b_f4<true><<<nred, NT, 0, s>>>(g, c->pcode, dnew, r, r, z, c->partials, nred, it, c->solver);
+                launch_timed(c, K, k_pcg_b_f4<true>, nred, s, g, (const uint8_t*)c->pcode, (const float*)dnew,
+                             (const float*)r, r, z, c->partials, nred, it, (const Solver*)c->solver);
                 return;
             }
         }
         if (path == 1)
-            k_pcg_b_v<T><<<nred, NT, 0, s>>>(g, c->pcode, dnew, r, z, c->partials, nred, it, c->solver);
+            launch_timed(c, K, k_pcg_b_v<T>, nred, s, g, (const uint8_t*)c->pcode, (const T*)dnew, r, z, c->partials,
+                         nred, it, (const Solver*)c->solver);
         else
-            k_pcg_b<T><<<nred, NT, 0, s>>>(g, c->pcode, dnew, r, z, c->partials, nred, it, c->solver);
+            launch_timed(c, K, k_pcg_b<T>, nred, s, g, (const uint8_t*)c->pcode, (const T*)dnew, r, z, c->partials,
+                         nred, it, (const Solver*)c->solver);
     };
     if (check_every <= 0) check_every = 16;
     int batch = *last_iters > 0 ? *last_iters + 2 : check_every;
@@ -1107,12 +1112,8 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nre
         if (n > max_iter - total) n = max_iter - total;
         for (int k = 0; k < n; ++k) {
             const int it = start_it + total + k;
-            timing_begin(c, TK_SPMV, s);
             pass_a(it);
-            timing_end(c, TK_SPMV, s);
-            timing_begin(c, TK_UPDATE, s);
             pass_b(it);
-            timing_end(c, TK_UPDATE, s);
         }
         IBM_HIP(hipGetLastError());
         total += n;
