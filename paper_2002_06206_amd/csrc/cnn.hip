@@ -73,14 +73,32 @@ struct ConvIO {
 
 __host__ __device__ constexpr int ksteps(int cin) { return cin == 16 ? 14 : (27 * cin + 31) / 32; }
 
+// Tap order of the 16-channel k-steps.  Lane groups g = 0, 1 (h = 0) hold the first of
+// the step's two taps, g = 2, 3 (h = 1) the second, and the pairs are chosen so that,
+// within each run of steps, the second tap lies a fixed distance from the first in the
+// halo planes: steps 0..8 pair plane dz = -1 with dz = +1 at the same (dy, dx), steps
+// 9..11 pair row dy = -1 with row dy = +1 of plane dz = 0, step 12 pairs dx = -1 with
+// dx = +1 and step 13 holds the centre tap and a padding slot.  A lane's B-operand
+// addresses are then three per-plane base registers plus compile-time offsets.
+// Taps are numbered 9 (dz + 1) + 3 (dy + 1) + (dx + 1).
+__host__ __device__ constexpr int tap16(int s, int h) {
+    return s < 9 ? (h ? 18 + s : s) : s < 12 ? (h ? s + 6 : s) : s == 12 ? (h ? 14 : 12) : (h ? -1 : 13);
+}
+
 // (tap, input channel) held by element e of lane group g in k-step s; tap = -1 for
-// padding.  Used by the weight packing and by the B-operand gather, so the two MFMA
-// operands agree on k.
+// padding.  Used by the weight packing and by the B-operand gathers, so the two MFMA
+// operands agree on k.  One input channel (a single k-step): group g < 3 holds taps
+// q = 0..7 of plane dz = g - 1 (q = 3 (dy + 1) + (dx + 1)), group 3 holds q = 8 of
+// the planes dz = -1, 0, +1 in its elements 0..2; again a lane's eight addresses are
+// few base registers plus compile-time offsets.
 template <int CIN>
 __host__ __device__ inline void kmap(int s, int g, int e, int& tap, int& ci) {
     if (CIN == 16) {
-        tap = 2 * s + (g >> 1);
+        tap = tap16(s, g >> 1);
         ci = 8 * (g & 1) + e;
+    } else if (CIN == 1) {
+        tap = g < 3 ? 9 * g + e : (e < 3 ? 9 * e + 8 : -1);
+        ci = 0;
     } else {
         const int k = 32 * s + 8 * g + e;
         tap = k / CIN;
@@ -89,12 +107,12 @@ __host__ __device__ inline void kmap(int s, int g, int e, int& tap, int& ci) {
     if (tap > 26) tap = -1;
 }
 
-// float -> bfloat16 bits, round to nearest, ties to even; NaN stays NaN
+// float -> bfloat16 bits, round to nearest, ties to even (the hardware conversion)
 __device__ inline uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x0040u);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const __bf16 h = (__bf16)f;
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -153,11 +171,15 @@ __device__ inline void unpack4(uint2 w, float (&f)[4]) {
     f[3] = bf2f((uint16_t)(w.y >> 16));
 }
 __device__ inline uint2 pack4(const float (&f)[4]) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    const bf16x4 h = {(__bf16)f[0], (__bf16)f[1], (__bf16)f[2], (__bf16)f[3]};
     uint2 o;
-    o.x = (uint32_t)f2bf(f[0]) | ((uint32_t)f2bf(f[1]) << 16);
-    o.y = (uint32_t)f2bf(f[2]) | ((uint32_t)f2bf(f[3]) << 16);
+    __builtin_memcpy(&o, &h, 8);
     return o;
 }
+// logistic function; exp and the hardware reciprocal (about 1 ulp each, far below the
+// BF16 rounding every use of it takes)
+__device__ inline float sigmoid(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
 
 // One 3x3x3 convolution over an nx x ny x nz grid (zero padding): in = cells x CIN
 // BF16 (channels-last), wp = packed weights, out per the epilogue (see EPI_*).
@@ -211,8 +233,8 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
         for (int s = 0; s < KS; ++s) {
             bf16x8 bv;
             if (CIN == 16) {
-                int tap = 2 * s + (g >> 1);
-                if (tap > 26) tap = 26;   // padding slot: its weights are zero
+                int tap = tap16(s, g >> 1);
+                if (tap < 0) tap = 13;   // padding slot: its weights are zero
                 const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
                 const int hc = (ox + 1 + dx) + HX * ((oy + 1 + dy) + HY * (oz + 1 + dz));
                 bv = *reinterpret_cast<const bf16x8*>(&lds[((g & 1) * HCELLS + hc) * 8]);
@@ -249,7 +271,7 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
                 const long long o16 = c * 16 + 4 * g;
                 if (EPI == EPI_SIGMOID) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = 1.0f / (1.0f + __expf(-v[r]));
+                    for (int r = 0; r < 4; ++r) v[r] = sigmoid(v[r]);
                 } else if (EPI == EPI_GATE || EPI == EPI_BGATE) {
                     float gt[4];
                     unpack4(*reinterpret_cast<const uint2*>(io.gate + o16), gt);
@@ -287,14 +309,23 @@ constexpr int PCELLS = PX * PY;              // 340
 constexpr int PCHUNK = (2 * PCELLS + 255) / 256;   // 16-byte chunks per thread per plane (CIN = 16)
 constexpr int PSCAL = (PCELLS + 255) / 256;        // cells per thread per plane (1-channel planes)
 
+// halo-plane cell of in-plane tap q = 3 (dy + 1) + (dx + 1), relative to the cell at
+// (dx, dy) = (-1, -1) of the output cell
+__host__ __device__ constexpr int qcell(int q) { return q % 3 + PX * (q / 3); }
+// halo-plane cell offset of a wave's output tile tt (two 16-cell halves of two rows)
+__host__ __device__ constexpr int tcell(int tt) { return (tt & 1) * 16 + PX * (tt >> 1); }
+
 template <int CIN, int COUT, int EPI>
 __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz, const uint16_t* __restrict__ in,
                                                   const uint16_t* __restrict__ wp, void* __restrict__ out,
                                                   const uint16_t* __restrict__ gsrc, const uint16_t* __restrict__ wgp,
                                                   const Solver* sv) {
+    static_assert(CIN == 1 || CIN == 16, "marching convolution: 1 or 16 input channels");
     if (sv && sv->converged) return;
     constexpr int KS = ksteps(CIN);
-    constexpr int PLANE = CIN == 16 ? 2 * PCELLS * 8 : PCELLS * CIN;   // uint16 per ring plane
+    constexpr int PLANE = CIN == 16 ? 2 * PCELLS * 8 : PCELLS;   // uint16 per ring plane
+    constexpr int NLD = CIN == 16 ? PCHUNK : PSCAL;             // input loads per thread per plane
+    constexpr bool ONE = CIN == 1 || EPI == EPI_GATE;           // some 1-channel ring is gathered
     __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
     __shared__ uint16_t gring[EPI == EPI_GATE ? 4 * PCELLS : 1];
     const int ntx = (nx + CTX - 1) / CTX, nty = (ny + CTY - 1) / CTY;
@@ -305,52 +336,64 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
     const int x0 = tx * CTX - 1, y0 = ty * CTY - 1;
     const int z0 = tzs * mz, z1 = min(nz, z0 + mz);
     const long long plane = (long long)nx * ny;
+    // The thread's loads are the same in every plane: in-plane byte offsets of its
+    // chunks (CIN = 16: half cells of 8 channels) and cells (1-channel planes).  Plane
+    // loads go through buffer resources sized to the plane, so that a load at an offset
+    // past its end returns zero: halo cells outside the grid (and threads without a
+    // chunk) take offset OOB, and planes outside the grid get an empty resource.  The
+    // host keeps nx * ny * 32 below 2^31.
+    constexpr int OOB = 0x7FFFFFF0;
+    constexpr int RSRC3 = 0x00020000;   // word 3 of a raw buffer resource on this target
+    int o16[CIN == 16 ? PCHUNK : 1], o1[PSCAL];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int q = threadIdx.x + 256 * k;
+        const int cell = CIN == 16 ? q >> 1 : q;
+        int o = OOB;
+        if (cell < PCELLS) {
+            const int gx = x0 + cell % PX, gy = y0 + cell / PX;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+                o = ((gx + nx * gy) * CIN + (CIN == 16 ? (q & 1) * 8 : 0)) * 2;
+        }
+        if (CIN == 16) o16[k] = o; else o1[k] = o;
+    }
+    if (CIN == 16 && EPI == EPI_GATE) {
+#pragma unroll
+        for (int k = 0; k < PSCAL; ++k) {
+            const int cell = threadIdx.x + 256 * k;
+            int o = OOB;
+            if (cell < PCELLS) {
+                const int gx = x0 + cell % PX, gy = y0 + cell / PX;
+                if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) o = (gx + nx * gy) * 2;
+            }
+            o1[k] = o;
+        }
+    }
     // loader: plane pz of the halo region into registers (zero outside the grid)
     uint4 pre[CIN == 16 ? PCHUNK : 1];
-    uint16_t pre1[CIN == 16 ? 1 : PSCAL * CIN];
+    uint16_t pre1[CIN == 16 ? 1 : PSCAL];
     uint16_t preg[EPI == EPI_GATE ? PSCAL : 1];
     auto load_plane = [&](int pz) {
+        const bool zin = pz >= 0 && pz < nz;
+        const long long pb = zin ? (long long)pz * plane : 0;
+        const int bytes = zin ? (int)(plane * 2) : 0;   // of one channel
         if (EPI == EPI_GATE) {
+            const __amdgpu_buffer_rsrc_t rg =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(gsrc + pb), 0, bytes, RSRC3);
 #pragma unroll
-            for (int k = 0; k < PSCAL; ++k) {
-                const int cell = threadIdx.x + 256 * k;
-                uint16_t v = 0;
-                if (cell < PCELLS && pz >= 0 && pz < nz) {
-                    const int gx = x0 + cell % PX, gy = y0 + cell / PX;
-                    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = gsrc[(long long)gx + (long long)nx * gy + plane * pz];
-                }
-                preg[k] = v;
-            }
+            for (int k = 0; k < PSCAL; ++k) preg[k] = __builtin_amdgcn_raw_buffer_load_b16(rg, o1[k], 0, 0);
         }
+        const __amdgpu_buffer_rsrc_t ri =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(in + pb * CIN), 0, bytes * CIN, RSRC3);
         if (CIN == 16) {
 #pragma unroll
             for (int k = 0; k < PCHUNK; ++k) {
-                const int q = threadIdx.x + 256 * k;
-                uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                if (q < 2 * PCELLS && pz >= 0 && pz < nz) {
-                    const int cell = q >> 1, h = q & 1;
-                    const int gx = x0 + cell % PX, gy = y0 + cell / PX;
-                    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-                        v = *reinterpret_cast<const uint4*>(in + ((long long)gx + (long long)nx * gy + plane * pz) * 16 +
-                                                            h * 8);
-                }
-                pre[k] = v;
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ri, o16[k], 0, 0);
+                pre[k] = make_uint4(v[0], v[1], v[2], v[3]);
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < PSCAL; ++k) {
-                const int cell = threadIdx.x + 256 * k;
-#pragma unroll
-                for (int ci = 0; ci < CIN; ++ci) {
-                    uint16_t v = 0;
-                    if (cell < PCELLS && pz >= 0 && pz < nz) {
-                        const int gx = x0 + cell % PX, gy = y0 + cell / PX;
-                        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-                            v = in[((long long)gx + (long long)nx * gy + plane * pz) * CIN + ci];
-                    }
-                    pre1[k * CIN + ci] = v;
-                }
-            }
+            for (int k = 0; k < PSCAL; ++k) pre1[k] = __builtin_amdgcn_raw_buffer_load_b16(ri, o1[k], 0, 0);
         }
     };
     auto store_plane = [&](int slot) {
@@ -366,29 +409,26 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
 #pragma unroll
             for (int k = 0; k < PCHUNK; ++k) {
                 const int q = threadIdx.x + 256 * k;
-                if (q < 2 * PCELLS) {
-                    const int cell = q >> 1, h = q & 1;
-                    *reinterpret_cast<uint4*>(&P[(h * PCELLS + cell) * 8]) = pre[k];
-                }
+                if (q < 2 * PCELLS)
+                    *reinterpret_cast<uint4*>(&P[((q & 1) * PCELLS + (q >> 1)) * 8]) = pre[k];
             }
         } else {
 #pragma unroll
             for (int k = 0; k < PSCAL; ++k) {
                 const int cell = threadIdx.x + 256 * k;
-                if (cell < PCELLS) {
-#pragma unroll
-                    for (int ci = 0; ci < CIN; ++ci) P[cell * CIN + ci] = pre1[k * CIN + ci];
-                }
+                if (cell < PCELLS) P[cell] = pre1[k];
             }
         }
     };
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int j = lane & 15, g = lane >> 4;
+    const int j = lane & 15, g = lane >> 4, h = g >> 1;
     bf16x8 wa[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) wa[s] = *reinterpret_cast<const bf16x8*>(wp + ((long long)s * 64 + lane) * 8);
     bf16x8 wg;
     if (EPI == EPI_GATE) wg = *reinterpret_cast<const bf16x8*>(wgp + (long long)lane * 8);
+    // halo-plane cell of the lane's output cell in tile 0, shifted to its (-1, -1) neighbour
+    const int cb = j + PX * 2 * wv;
     // prologue: planes z0-1, z0, z0+1 into ring slots (z & 3)
     for (int pz = z0 - 1; pz <= z0 + 1; ++pz) {
         load_plane(pz);
@@ -397,6 +437,25 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
     __syncthreads();
     for (int z = z0; z < z1; ++z) {
         load_plane(z + 2);                      // in flight during the compute of plane z
+        // ring slots of the planes z - 1, z, z + 1
+        const int sl0 = (z + 3) & 3, sl1 = z & 3, sl2 = (z + 1) & 3;
+        // 1-channel gathers (kmap<1>): element e of the lane reads cell
+        // a1[e] + qcell(e) + tcell(tt) of a 1-channel ring
+        int a1[8];
+        if (ONE) {
+            const int base = cb + ((z + (g < 3 ? g : 2) + 3) & 3) * PCELLS;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a1[e] = base;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const int sl = e == 0 ? sl0 : (e == 1 ? sl1 : sl2);
+                if (g == 3) a1[e] = cb + sl * PCELLS + qcell(8) - qcell(e);
+            }
+        }
+        // 16-channel gathers (tap16): bases of the three runs of k-steps
+        const uint16_t* b0 = ring + (CIN == 16 ? ((g & 1) * PCELLS + cb) * 8 + (h ? sl2 : sl0) * PLANE : 0);
+        const uint16_t* b1 = ring + (CIN == 16 ? ((g & 1) * PCELLS + cb + h * 2 * PX) * 8 + sl1 * PLANE : 0);
+        const uint16_t* b2 = ring + (CIN == 16 ? ((g & 1) * PCELLS + cb + h * 2) * 8 + sl1 * PLANE : 0);
         const int gy0 = ty * CTY + 2 * wv;
         f32x4 acc[4];
 #pragma unroll
@@ -405,29 +464,15 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
         for (int s = 0; s < KS; ++s) {
 #pragma unroll
             for (int tt = 0; tt < 4; ++tt) {
-                const int ox = (tt & 1) * 16 + j, oy = 2 * wv + (tt >> 1);
                 bf16x8 bv;
                 if (CIN == 16) {
-                    int tap = 2 * s + (g >> 1);
-                    if (tap > 26) tap = 26;   // padding slot: its weights are zero
-                    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-                    const uint16_t* P = ring + ((z + dz) & 3) * PLANE;
-                    const int hc = (ox + 1 + dx) + PX * (oy + 1 + dy);
-                    bv = *reinterpret_cast<const bf16x8*>(&P[((g & 1) * PCELLS + hc) * 8]);
+                    const uint16_t* P = s < 9 ? b0 : (s < 12 ? b1 : b2);
+                    const int o = s < 9 ? qcell(s) : (s < 12 ? s - 9 : (s == 12 ? PX : PX + 1));
+                    bv = *reinterpret_cast<const bf16x8*>(P + (o + tcell(tt)) * 8);
                 } else {
                     uint16_t tmp[8];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        int tap, ci;
-                        kmap<CIN>(s, g, e, tap, ci);
-                        uint16_t v = 0;
-                        if (tap >= 0) {
-                            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-                            const uint16_t* P = ring + ((z + dz) & 3) * PLANE;
-                            v = P[((ox + 1 + dx) + PX * (oy + 1 + dy)) * CIN + ci];
-                        }
-                        tmp[e] = v;
-                    }
+                    for (int e = 0; e < 8; ++e) tmp[e] = ring[a1[e] + qcell(e) + tcell(tt)];
                     __builtin_memcpy(&bv, tmp, 16);
                 }
                 acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc[tt], 0, 0, 0);
@@ -439,24 +484,14 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
         if (EPI == EPI_GATE) {
 #pragma unroll
             for (int tt = 0; tt < 4; ++tt) {
-                const int ox = (tt & 1) * 16 + j, oy = 2 * wv + (tt >> 1);
                 uint16_t tmp[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    int tap, ci;
-                    kmap<1>(0, g, e, tap, ci);
-                    uint16_t gv = 0;
-                    if (tap >= 0) {
-                        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-                        gv = gring[((z + dz) & 3) * PCELLS + (ox + 1 + dx) + PX * (oy + 1 + dy)];
-                    }
-                    tmp[e] = gv;
-                }
+                for (int e = 0; e < 8; ++e) tmp[e] = gring[a1[e] + qcell(e) + tcell(tt)];
                 bf16x8 bg;
                 __builtin_memcpy(&bg, tmp, 16);
                 const f32x4 ga = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, bg, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) gate4[tt][r] = bf2f(f2bf(1.0f / (1.0f + __expf(-ga[r]))));
+                for (int r = 0; r < 4; ++r) gate4[tt][r] = bf2f(f2bf(sigmoid(ga[r])));
             }
         }
 #pragma unroll
@@ -884,7 +919,12 @@ int mconv_blocks(int nx, int ny, int nz, int mz) {
 int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv, hipStream_t s,
                 ibm_ctx* timed = nullptr) {
     if (!keep) {
-        // solver path: marching kernels, no activations kept
+        // solver path: marching kernels, no activations kept (their in-plane byte
+        // offsets are 32-bit)
+        if ((long long)nx * ny * 32 >= (1LL << 31)) {
+            set_error("cnn: x-y plane too large for the marching convolutions");
+            return IBM_ERR_ARG;
+        }
         const int mz = mconv_planes(nx, ny, nz);
         const int mb = mconv_blocks(nx, ny, nz, mz);
         const uint16_t* wg = pw(n, PV_WG);

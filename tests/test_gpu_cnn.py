@@ -73,6 +73,47 @@ def test_forward_matches_oracle_ragged_grid():
     net.close()
 
 
+def test_marching_forward_matches_oracle_ragged_grid():
+    """The inference-only network runs the marching kernels of the solver path (z
+    slabs of a 32 x 8 tile, gate computed on the fly): same oracle bar as the kept
+    forward, on the ragged grid (several slabs, short last slab)."""
+    rng = np.random.default_rng(21)
+    shape = (RAGGED[2], RAGGED[1], RAGGED[0])
+    xb = _input(rng, shape)
+    w = inputs.cnn_init_weights(22, scale=4.0)
+    net = ibm.Network(int(np.prod(RAGGED)), w, inference_only=True)
+    y = torch.empty(shape, dtype=torch.float32, device="cuda")
+    print("case cnn marching forward", RAGGED, flush=True)
+    ibm.ibm_cnn_forward(net.net, xb.cuda().contiguous(), y, RAGGED)
+    x = xb.double().numpy()
+    yo, _ = cnn.forward(x[..., 0], x[..., 1], _layers(w), bf16=True)
+    e = rel_l2(y.cpu().numpy(), yo)
+    print("marching forward rel L2 %.2e" % e, flush=True)
+    assert e < 2e-3
+    net.close()
+
+
+def test_marching_forward_equals_kept_forward():
+    """Both forward forms take the same BF16 roundings and accumulate the same MFMA
+    k-steps in the same order, so their outputs agree bit for bit; 250 x 250 x 45
+    gives 6-plane slabs with a short last slab and ragged x-y tiles."""
+    n = (250, 250, 45)
+    shape = (n[2], n[1], n[0])
+    xb = _input(np.random.default_rng(23), shape).cuda().contiguous()
+    w = inputs.cnn_init_weights(24, scale=4.0)
+    ys = []
+    for inference_only in (False, True):
+        net = ibm.Network(int(np.prod(n)), w, inference_only=inference_only)
+        y = torch.empty(shape, dtype=torch.float32, device="cuda")
+        print("case cnn forward forms", n, "inference_only", inference_only, flush=True)
+        ibm.ibm_cnn_forward(net.net, xb, y, n)
+        torch.cuda.synchronize()
+        ys.append(y.cpu().numpy())
+        net.close()
+    assert np.all(np.isfinite(ys[0])) and np.max(np.abs(ys[0])) > 0.0
+    assert np.array_equal(ys[0], ys[1])
+
+
 def test_forward_tile_edges_exact_zero_padding():
     """A unit impulse in x at the last cell of the first 32 x 8 x 4 tile: checked against
     the oracle at every cell, across tile boundaries and up to the domain faces (zero
