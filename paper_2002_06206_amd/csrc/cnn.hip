@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
 // Marching form of a convolution for the solver's preconditioner applications.
 // A block owns a 32 x 8 output tile in x-y and walks a slab of mz planes in z.  The
 // input planes z-1, z, z+1 (34 x 10 cells with halo) sit in a ring of four LDS planes
-// (two 16-byte half-cell planes each for CIN = 16); plane z+2 is loaded into registers
+// (two 16-byte half-cell planes each for CIN = 16, HPC cells apart); plane z+2 is loaded into registers
 // while plane z is computed and written to the free ring slot afterwards (one barrier
 // per plane).  Each wave owns two output rows = four 16-cell MFMA tiles and keeps four
 // independent accumulator chains.  EPI_BF16 and EPI_F32 (COUT channels) as in k_conv;
@@ -308,6 +308,13 @@ constexpr int PX = CTX + 2, PY = CTY + 2;    // 34 x 10 halo plane
 constexpr int PCELLS = PX * PY;              // 340
 constexpr int PCHUNK = (2 * PCELLS + 255) / 256;   // 16-byte chunks per thread per plane (CIN = 16)
 constexpr int PSCAL = (PCELLS + 255) / 256;        // cells per thread per plane (1-channel planes)
+// Stride of the two half-cell planes of a 16-channel ring slot, in cells: padded so
+// that it is a multiple of 256 bytes.  The B-operand read of lane groups 0 and 1 (the
+// two halves of the same cells) then falls on the same LDS banks at the same offset,
+// which is conflict-free; at the unpadded 5440 bytes (64 mod 256) every 16-byte read
+// takes extra bank-conflict cycles (measured with SQ_LDS_BANK_CONFLICT).
+constexpr int HPC = 352;
+static_assert(HPC >= PCELLS && (HPC * 16) % 256 == 0, "half-plane stride");
 
 // halo-plane cell of in-plane tap q = 3 (dy + 1) + (dx + 1), relative to the cell at
 // (dx, dy) = (-1, -1) of the output cell
@@ -323,7 +330,7 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
     static_assert(CIN == 1 || CIN == 16, "marching convolution: 1 or 16 input channels");
     if (sv && sv->converged) return;
     constexpr int KS = ksteps(CIN);
-    constexpr int PLANE = CIN == 16 ? 2 * PCELLS * 8 : PCELLS;   // uint16 per ring plane
+    constexpr int PLANE = CIN == 16 ? 2 * HPC * 8 : PCELLS;      // uint16 per ring plane
     constexpr int NLD = CIN == 16 ? PCHUNK : PSCAL;             // input loads per thread per plane
     constexpr bool ONE = CIN == 1 || EPI == EPI_GATE;           // some 1-channel ring is gathered
     __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
@@ -410,7 +417,7 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
             for (int k = 0; k < PCHUNK; ++k) {
                 const int q = threadIdx.x + 256 * k;
                 if (q < 2 * PCELLS)
-                    *reinterpret_cast<uint4*>(&P[((q & 1) * PCELLS + (q >> 1)) * 8]) = pre[k];
+                    *reinterpret_cast<uint4*>(&P[((q & 1) * HPC + (q >> 1)) * 8]) = pre[k];
             }
         } else {
 #pragma unroll
@@ -453,9 +460,9 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
             }
         }
         // 16-channel gathers (tap16): bases of the three runs of k-steps
-        const uint16_t* b0 = ring + (CIN == 16 ? ((g & 1) * PCELLS + cb) * 8 + (h ? sl2 : sl0) * PLANE : 0);
-        const uint16_t* b1 = ring + (CIN == 16 ? ((g & 1) * PCELLS + cb + h * 2 * PX) * 8 + sl1 * PLANE : 0);
-        const uint16_t* b2 = ring + (CIN == 16 ? ((g & 1) * PCELLS + cb + h * 2) * 8 + sl1 * PLANE : 0);
+        const uint16_t* b0 = ring + (CIN == 16 ? ((g & 1) * HPC + cb) * 8 + (h ? sl2 : sl0) * PLANE : 0);
+        const uint16_t* b1 = ring + (CIN == 16 ? ((g & 1) * HPC + cb + h * 2 * PX) * 8 + sl1 * PLANE : 0);
+        const uint16_t* b2 = ring + (CIN == 16 ? ((g & 1) * HPC + cb + h * 2) * 8 + sl1 * PLANE : 0);
         const int gy0 = ty * CTY + 2 * wv;
         f32x4 acc[4];
 #pragma unroll
