@@ -58,7 +58,21 @@ enum {
     EPI_GATE = 1,     // out = bf16(acc . G); aux (optional) = bf16(acc)
     EPI_SIGMOID = 2,  // out = bf16(sigmoid(acc))
     EPI_BGATE = 3,    // out = bf16(acc . G); dG (float) = [dG +] acc . P
-    EPI_F32 = 4       // out = acc (float, COUT channels, stride ostride)
+    EPI_F32 = 4,      // out = acc (float, COUT channels, stride ostride)
+    EPI_COMBINE = 5   // marching 16 -> 1 only: the preconditioner's z (CombineIO)
+};
+
+// EPI_COMBINE: z = D^-1 r + s acc with D the diagonal of A = -L (open faces / dx^2),
+// and the block's partial sums of <z, r> and <z, rp> (rp may be null) in cpart[b] and
+// cpart[nblocks + b]
+struct CombineIO {
+    const float* r;
+    const float* rp;
+    const uint8_t* pcode;
+    const double* s_in;
+    double dx2;
+    float* z;
+    double* cpart;
 };
 
 // optional operands of the epilogues
@@ -74,15 +88,21 @@ struct ConvIO {
 __host__ __device__ constexpr int ksteps(int cin) { return cin == 16 ? 14 : (27 * cin + 31) / 32; }
 
 // Tap order of the 16-channel k-steps.  Lane groups g = 0, 1 (h = 0) hold the first of
-// the step's two taps, g = 2, 3 (h = 1) the second, and the pairs are chosen so that,
-// within each run of steps, the second tap lies a fixed distance from the first in the
-// halo planes: steps 0..8 pair plane dz = -1 with dz = +1 at the same (dy, dx), steps
-// 9..11 pair row dy = -1 with row dy = +1 of plane dz = 0, step 12 pairs dx = -1 with
-// dx = +1 and step 13 holds the centre tap and a padding slot.  A lane's B-operand
-// addresses are then three per-plane base registers plus compile-time offsets.
-// Taps are numbered 9 (dz + 1) + 3 (dy + 1) + (dx + 1).
+// the step's two taps, g = 2, 3 (h = 1) the second.  Taps are numbered
+// 9 (dz + 1) + 3 (dy + 1) + (dx + 1).
+//   s = 3 (dx + 1) + (dy + 1), s < 9:  (-1, dy, dx) and (+1, dy, dx)
+//   s = 9 + (dy + 1):                  (0, dy, -1) and (0, dy, +1)
+//   s = 12:                            (0, -1, 0) and (0, +1, 0)
+//   s = 13:                            (0, 0, 0) and padding
+// In the first twelve steps both taps of a pair have the same dy, so the B operand of
+// input row i serves the output rows i - dy of all three dy (the marching kernel reads
+// each such operand once for four output rows), and the second tap always lies a fixed
+// distance from the first in the LDS halo planes.
 __host__ __device__ constexpr int tap16(int s, int h) {
-    return s < 9 ? (h ? 18 + s : s) : s < 12 ? (h ? s + 6 : s) : s == 12 ? (h ? 14 : 12) : (h ? -1 : 13);
+    return s < 9    ? (h ? 18 : 0) + 3 * (s % 3) + s / 3
+           : s < 12 ? 9 + 3 * (s - 9) + (h ? 2 : 0)
+           : s == 12 ? (h ? 16 : 10)
+                     : (h ? -1 : 13);
 }
 
 // (tap, input channel) held by element e of lane group g in k-step s; tap = -1 for
@@ -127,6 +147,7 @@ struct PackDesc {
     int bwd;                 // 0 forward conv, 1 backward-data conv (flipped, transposed)
     int cin, cout;           // channels of the conv as launched
     int ks, off;             // k-steps, offset in the packed array (elements)
+    int ymode;               // 1: 16 -> 1 adjoint with A rows = dy + 1 (k_mconv, COUT = 1)
 };
 
 namespace {
@@ -138,6 +159,24 @@ __global__ void k_pack(const float* __restrict__ w, uint16_t* __restrict__ wp, P
     const int e = idx & 7, lane = (idx >> 3) & 63, s = idx >> 9;
     const int g = lane >> 4, row = lane & 15;
     int tap, ci;
+    if (d.ymode) {
+        // K = (dz, dx) pairs x 16 channels in 5 steps, M = dy + 1 (rows 0..2):
+        // s < 3: (-1, s - 1) | (+1, s - 1); s = 3: (0, -1) | (0, +1); s = 4: (0, 0) | padding
+        const int h = g >> 1, dy = row - 1;
+        int dz = 0, dx = 0;
+        if (s < 3) {
+            dz = h ? 1 : -1;
+            dx = s - 1;
+        } else if (s == 3) {
+            dx = h ? 1 : -1;
+        }
+        tap = (row < 3 && !(s == 4 && h)) ? 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1) : -1;
+        ci = 8 * (g & 1) + e;
+        float val = 0.0f;
+        if (tap >= 0) val = w[d.loff + ((26 - tap) * d.lcin + 0) * d.lcout + ci];
+        wp[d.off + idx] = f2bf(val);
+        return;
+    }
     if (d.cin == 16)
         kmap<16>(s, g, e, tap, ci);
     else if (d.cin == 2)
@@ -298,12 +337,14 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
 // Marching form of a convolution for the solver's preconditioner applications.
 // A block owns a 32 x 8 output tile in x-y and walks a slab of mz planes in z.  The
 // input planes z-1, z, z+1 (34 x 10 cells with halo) sit in a ring of four LDS planes
-// (two 16-byte half-cell planes each for CIN = 16, HPC cells apart); plane z+2 is loaded into registers
-// while plane z is computed and written to the free ring slot afterwards (one barrier
-// per plane).  Each wave owns two output rows = four 16-cell MFMA tiles and keeps four
-// independent accumulator chains.  EPI_BF16 and EPI_F32 (COUT channels) as in k_conv;
-// EPI_GATE computes the gate sigmoid(Wg * g) of its output cells on the fly (one more
-// MFMA per tile from a ring of geometry planes) instead of reading a stored gate.
+// (two 16-byte half-cell planes each for CIN = 16, HPC cells apart); plane z+2 is
+// loaded into registers while plane z is computed and written to the free ring slot
+// afterwards (one barrier per plane).  Each wave owns one 16-cell half of four output
+// rows: four MFMA tiles, four independent accumulator chains, and each B operand read
+// from LDS feeds up to three of them (tap16).  EPI_BF16 and EPI_F32 (COUT channels) as
+// in k_conv; EPI_GATE computes the gate sigmoid(Wg * g) of its output cells on the fly
+// (one more MFMA per tile from a ring of geometry planes) instead of reading a stored
+// gate.
 constexpr int PX = CTX + 2, PY = CTY + 2;    // 34 x 10 halo plane
 constexpr int PCELLS = PX * PY;              // 340
 constexpr int PCHUNK = (2 * PCELLS + 255) / 256;   // 16-byte chunks per thread per plane (CIN = 16)
@@ -319,17 +360,121 @@ static_assert(HPC >= PCELLS && (HPC * 16) % 256 == 0, "half-plane stride");
 // halo-plane cell of in-plane tap q = 3 (dy + 1) + (dx + 1), relative to the cell at
 // (dx, dy) = (-1, -1) of the output cell
 __host__ __device__ constexpr int qcell(int q) { return q % 3 + PX * (q / 3); }
-// halo-plane cell offset of a wave's output tile tt (two 16-cell halves of two rows)
-__host__ __device__ constexpr int tcell(int tt) { return (tt & 1) * 16 + PX * (tt >> 1); }
+
+// in-plane cell of tap q = 3 (dy + 1) + (dx + 1) of a plane W cells wide, relative to
+// the (dx, dy) = (-1, -1) neighbour
+template <int W>
+__host__ __device__ constexpr int qcellw(int q) { return q % 3 + W * (q / 3); }
+
+// Per-lane cell offsets of the kmap<1> gathers from a ring of four 1-channel planes of
+// `cells` cells, W wide, around plane p: element e of the lane reads cell
+// a[e] + qcellw<W>(e) + (offset of its output cell).  cb = the output cell's (-1, -1)
+// neighbour in the plane.
+template <int W>
+__device__ __forceinline__ void kmap1_cells(int p, int g, int cb, int cells, int (&a)[8]) {
+    const int base = cb + ((p + (g < 3 ? g : 2) + 3) & 3) * cells;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a[e] = base;
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+        if (g == 3) a[e] = cb + ((p + e + 3) & 3) * cells + qcellw<W>(8) - qcellw<W>(e);
+}
+
+// 16 -> 16 convolution of one plane from a ring of four 16-channel halo planes (34 x 10
+// cells, two half-cell planes HPC cells apart, ring slots (z & 3) of the planes z - 1,
+// z, z + 1 in sl0, sl1, sl2) into the wave's four accumulators: output rows r0 .. r0 + 3
+// of one 16-cell x half, cb = halo cell of the lane's column at dx = -1 in halo row r0.
+// The B operands come in five groups: the dz-pair steps of dx = -1, 0, +1 (halo rows
+// r0 .. r0 + 5 each), the dx-pair steps (same rows), and the dy-pair and centre steps
+// (four each).  The B operand of halo row r0 + ii feeds output row r0 + rr through the
+// step of dy = ii - rr - 1; every chain accumulates its steps in increasing s, as k_conv
+// does.  Group k + 1 is loaded while group k is multiplied.
+__device__ __forceinline__ void conv16_plane(const uint16_t* ring, int cb, int g, int sl0, int sl1, int sl2,
+                                             const bf16x8 (&wa)[14], f32x4 (&acc)[4]) {
+    constexpr int PLANE = 2 * HPC * 8;
+    const int h = g >> 1, hb = (g & 1) * HPC;
+    const uint16_t* b0 = ring + (hb + cb) * 8 + (h ? sl2 : sl0) * PLANE;   // dz = -1 | +1
+    const uint16_t* bx = ring + (hb + cb + 2 * h) * 8 + sl1 * PLANE;       // dx = -1 | +1
+    const uint16_t* by = ring + (hb + cb + 2 * PX * h) * 8 + sl1 * PLANE;  // dy = -1 | +1
+    const uint16_t* bc = ring + (hb + cb) * 8 + sl1 * PLANE;               // centre
+    // six halo rows from base P (stride PX cells) starting at cell offset c0
+    auto load6 = [&](const uint16_t* P, int c0, bf16x8 (&B)[6]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) B[k] = *reinterpret_cast<const bf16x8*>(P + (k * PX + c0) * 8);
+    };
+    // steps s0 + dy + 1: dy outer so that consecutive MFMAs go to four different
+    // accumulators (each still takes its steps in increasing s)
+    auto mma6 = [&](int s0, const bf16x8 (&B)[6]) {
+#pragma unroll
+        for (int dyi = 0; dyi < 3; ++dyi) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+                acc[rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s0 + dyi], B[rr + dyi], acc[rr], 0, 0, 0);
+        }
+    };
+    bf16x8 Ba[6], Bb[6], Bd[4], Be[4];
+    load6(b0, 0, Ba);
+    load6(b0, 1, Bb);
+    mma6(0, Ba);
+    load6(b0, 2, Ba);
+    mma6(3, Bb);
+    load6(bx, 0, Bb);
+    mma6(6, Ba);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        Bd[rr] = *reinterpret_cast<const bf16x8*>(by + (rr * PX + 1) * 8);
+        Be[rr] = *reinterpret_cast<const bf16x8*>(bc + ((rr + 1) * PX + 1) * 8);
+    }
+    mma6(9, Bb);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+        acc[rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[12], Bd[rr], acc[rr], 0, 0, 0);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+        acc[rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[13], Be[rr], acc[rr], 0, 0, 0);
+}
+
+// 16 -> 1 convolution of one plane (PV_W1TY packing): the A rows are m = dy + 1, K runs
+// over (dz, dx) pairs x 16 channels in five steps (s < 3: dz = -1 | +1 at dx = s - 1;
+// s = 3: dx = -1 | +1 in plane z; s = 4: the centre column and padding), so one MFMA
+// chain per halo row ii = 0 .. 5 of the wave gives d[ii][m] = the part of every output
+// row r0 + ii - m.  Lane group 0 then holds, per output row rr, the three parts of its
+// cell: o[rr] = d[rr][0] + d[rr + 1][1] + d[rr + 2][2].  30 MFMAs for four rows instead
+// of 56 with a single useful A row.
+__device__ __forceinline__ void conv16to1_plane(const uint16_t* ring, int cb, int g, int sl0, int sl1, int sl2,
+                                                const bf16x8 (&wa)[5], float (&o)[4]) {
+    constexpr int PLANE = 2 * HPC * 8;
+    const int h = g >> 1, hb = (g & 1) * HPC;
+    const uint16_t* b0 = ring + (hb + cb) * 8 + (h ? sl2 : sl0) * PLANE;   // dz = -1 | +1
+    const uint16_t* bx = ring + (hb + cb + 2 * h) * 8 + sl1 * PLANE;       // dx = -1 | +1
+    const uint16_t* bc = ring + (hb + cb) * 8 + sl1 * PLANE;               // centre
+    f32x4 d[6];
+#pragma unroll
+    for (int ii = 0; ii < 6; ++ii) d[ii] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        bf16x8 B[6];
+#pragma unroll
+        for (int ii = 0; ii < 6; ++ii) {
+            const uint16_t* P = s < 3 ? b0 + (ii * PX + s) * 8 : (s == 3 ? bx + ii * PX * 8 : bc + (ii * PX + 1) * 8);
+            B[ii] = *reinterpret_cast<const bf16x8*>(P);
+        }
+#pragma unroll
+        for (int ii = 0; ii < 6; ++ii) d[ii] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], B[ii], d[ii], 0, 0, 0);
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) o[rr] = d[rr][0] + d[rr + 1][1] + d[rr + 2][2];
+}
 
 template <int CIN, int COUT, int EPI>
-__global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz, const uint16_t* __restrict__ in,
+__global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz, const uint16_t* __restrict__ in,
                                                   const uint16_t* __restrict__ wp, void* __restrict__ out,
                                                   const uint16_t* __restrict__ gsrc, const uint16_t* __restrict__ wgp,
-                                                  const Solver* sv) {
+                                                  const Solver* sv, CombineIO cio) {
     static_assert(CIN == 1 || CIN == 16, "marching convolution: 1 or 16 input channels");
+    static_assert(EPI != EPI_COMBINE || (CIN == 16 && COUT == 1), "combine epilogue: 16 -> 1");
     if (sv && sv->converged) return;
-    constexpr int KS = ksteps(CIN);
+    constexpr int KS = COUT == 1 ? 5 : ksteps(CIN);             // COUT = 1: PV_W1TY packing
     constexpr int PLANE = CIN == 16 ? 2 * HPC * 8 : PCELLS;      // uint16 per ring plane
     constexpr int NLD = CIN == 16 ? PCHUNK : PSCAL;             // input loads per thread per plane
     constexpr bool ONE = CIN == 1 || EPI == EPI_GATE;           // some 1-channel ring is gathered
@@ -339,10 +484,19 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
     const int nslab = (nz + mz - 1) / mz;
     const int t = xcd_chunk(blockIdx.x, gridDim.x);
     const int tx = t % ntx, ty = (t / ntx) % nty, tzs = t / (ntx * nty);
-    if (tzs >= nslab) return;
+    if (tzs >= nslab) {
+        if (EPI == EPI_COMBINE && threadIdx.x == 0) cio.cpart[blockIdx.x] = cio.cpart[gridDim.x + blockIdx.x] = 0.0;
+        return;
+    }
     const int x0 = tx * CTX - 1, y0 = ty * CTY - 1;
     const int z0 = tzs * mz, z1 = min(nz, z0 + mz);
     const long long plane = (long long)nx * ny;
+    __shared__ float invf[EPI == EPI_COMBINE ? 16 : 1];   // dx^2 / (open faces + 2 outlets)
+    __shared__ double shr[EPI == EPI_COMBINE ? 8 : 1];
+    if (EPI == EPI_COMBINE && threadIdx.x < 16)
+        invf[threadIdx.x] = threadIdx.x ? (float)(cio.dx2 / (double)threadIdx.x) : 0.0f;
+    const float sc = EPI == EPI_COMBINE ? (float)*cio.s_in : 0.0f;
+    double zsum[2] = {0.0, 0.0};
     // The thread's loads are the same in every plane: in-plane byte offsets of its
     // chunks (CIN = 16: half cells of 8 channels) and cells (1-channel planes).  Plane
     // loads go through buffer resources sized to the plane, so that a load at an offset
@@ -428,99 +582,332 @@ __global__ void __launch_bounds__(256, 2) k_mconv(int nx, int ny, int nz, int mz
         }
     };
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int j = lane & 15, g = lane >> 4, h = g >> 1;
+    const int j = lane & 15, g = lane >> 4;
+    // the wave's outputs: x half xh (16 cells) of the four rows r0 .. r0 + 3, one MFMA
+    // tile (one accumulator chain) per row
+    const int xh = wv & 1, r0 = 4 * (wv >> 1);
     bf16x8 wa[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) wa[s] = *reinterpret_cast<const bf16x8*>(wp + ((long long)s * 64 + lane) * 8);
     bf16x8 wg;
     if (EPI == EPI_GATE) wg = *reinterpret_cast<const bf16x8*>(wgp + (long long)lane * 8);
-    // halo-plane cell of the lane's output cell in tile 0, shifted to its (-1, -1) neighbour
-    const int cb = j + PX * 2 * wv;
+    // halo-plane cell of the lane's column at dx = -1 in halo row r0 (the row above the
+    // wave's first output row)
+    const int cb = j + 16 * xh + PX * r0;
     // prologue: planes z0-1, z0, z0+1 into ring slots (z & 3)
     for (int pz = z0 - 1; pz <= z0 + 1; ++pz) {
         load_plane(pz);
         store_plane(pz & 3);
     }
     __syncthreads();
+    const int gxo = tx * CTX + 16 * xh + j;   // the lane's output column
     for (int z = z0; z < z1; ++z) {
         load_plane(z + 2);                      // in flight during the compute of plane z
+        // EPI_COMBINE: r, r_prev and the face code of the wave's output cells of this
+        // plane, loaded now so that their latency hides behind the convolution
+        float er[4], erp[4];
+        uint8_t epc[4];
+        if (EPI == EPI_COMBINE) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int gy = ty * CTY + r0 + rr;
+                er[rr] = erp[rr] = 0.0f;
+                epc[rr] = 0;
+                if (g == 0 && gxo < nx && gy < ny) {
+                    const long long c = (long long)gxo + (long long)nx * gy + plane * z;
+                    er[rr] = cio.r[c];
+                    epc[rr] = cio.pcode[c];
+                    if (cio.rp) erp[rr] = cio.rp[c];
+                }
+            }
+        }
         // ring slots of the planes z - 1, z, z + 1
         const int sl0 = (z + 3) & 3, sl1 = z & 3, sl2 = (z + 1) & 3;
         // 1-channel gathers (kmap<1>): element e of the lane reads cell
-        // a1[e] + qcell(e) + tcell(tt) of a 1-channel ring
+        // a1[e] + qcell(e) + PX rr of a 1-channel ring for output row r0 + rr
         int a1[8];
-        if (ONE) {
-            const int base = cb + ((z + (g < 3 ? g : 2) + 3) & 3) * PCELLS;
+        if (ONE) kmap1_cells<PX>(z, g, cb, PCELLS, a1);
+        // gate of the output cells, BF16(sigmoid(Wg * g)) as the stored gate: gathered
+        // first so that its LDS latency hides behind the convolution; computed for every
+        // row (out-of-grid cells read zeros) so that no MFMA sits in a branch
+        f32x4 gacc[4];
+        if (EPI == EPI_GATE) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) a1[e] = base;
+            for (int rr = 0; rr < 4; ++rr) {
+                uint16_t tmp[8];
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                const int sl = e == 0 ? sl0 : (e == 1 ? sl1 : sl2);
-                if (g == 3) a1[e] = cb + sl * PCELLS + qcell(8) - qcell(e);
+                for (int e = 0; e < 8; ++e) tmp[e] = gring[a1[e] + qcell(e) + PX * rr];
+                bf16x8 bg;
+                __builtin_memcpy(&bg, tmp, 16);
+                gacc[rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, bg, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
             }
         }
-        // 16-channel gathers (tap16): bases of the three runs of k-steps
-        const uint16_t* b0 = ring + (CIN == 16 ? ((g & 1) * HPC + cb) * 8 + (h ? sl2 : sl0) * PLANE : 0);
-        const uint16_t* b1 = ring + (CIN == 16 ? ((g & 1) * HPC + cb + h * 2 * PX) * 8 + sl1 * PLANE : 0);
-        const uint16_t* b2 = ring + (CIN == 16 ? ((g & 1) * HPC + cb + h * 2) * 8 + sl1 * PLANE : 0);
-        const int gy0 = ty * CTY + 2 * wv;
         f32x4 acc[4];
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int rr = 0; rr < 4; ++rr) acc[rr] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        float o1[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // COUT = 1: the output of lane group 0
+        if constexpr (COUT == 1) {
+            conv16to1_plane(ring, cb, g, sl0, sl1, sl2, wa, o1);
+        } else if constexpr (CIN == 16) {
+            conv16_plane(ring, cb, g, sl0, sl1, sl2, wa, acc);
+        } else {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
+            for (int rr = 0; rr < 4; ++rr) {
+                uint16_t tmp[8];
 #pragma unroll
-            for (int tt = 0; tt < 4; ++tt) {
+                for (int e = 0; e < 8; ++e) tmp[e] = ring[a1[e] + qcell(e) + PX * rr];
                 bf16x8 bv;
-                if (CIN == 16) {
-                    const uint16_t* P = s < 9 ? b0 : (s < 12 ? b1 : b2);
-                    const int o = s < 9 ? qcell(s) : (s < 12 ? s - 9 : (s == 12 ? PX : PX + 1));
-                    bv = *reinterpret_cast<const bf16x8*>(P + (o + tcell(tt)) * 8);
-                } else {
-                    uint16_t tmp[8];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) tmp[e] = ring[a1[e] + qcell(e) + tcell(tt)];
-                    __builtin_memcpy(&bv, tmp, 16);
-                }
-                acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc[tt], 0, 0, 0);
+                __builtin_memcpy(&bv, tmp, 16);
+                acc[rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0], bv, acc[rr], 0, 0, 0);
             }
         }
-        // gate of the output cells, BF16(sigmoid(Wg * g)) as the stored gate; computed for
-        // every tile (out-of-grid cells read zeros) so that no MFMA sits in a branch
         float gate4[4][4];
         if (EPI == EPI_GATE) {
 #pragma unroll
-            for (int tt = 0; tt < 4; ++tt) {
-                uint16_t tmp[8];
+            for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) tmp[e] = gring[a1[e] + qcell(e) + tcell(tt)];
-                bf16x8 bg;
-                __builtin_memcpy(&bg, tmp, 16);
-                const f32x4 ga = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, bg, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) gate4[tt][r] = bf2f(f2bf(sigmoid(ga[r])));
-            }
+                for (int r = 0; r < 4; ++r) gate4[rr][r] = bf2f(f2bf(sigmoid(gacc[rr][r])));
         }
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            const int gx = tx * CTX + (tt & 1) * 16 + j, gy = gy0 + (tt >> 1);
-            if (gx >= nx || gy >= ny) continue;
-            const long long c = (long long)gx + (long long)nx * gy + plane * z;
-            if (EPI == EPI_F32) {
+        for (int rr = 0; rr < 4; ++rr) {
+            const int gy = ty * CTY + r0 + rr;
+            if (gxo >= nx || gy >= ny) continue;
+            const long long c = (long long)gxo + (long long)nx * gy + plane * z;
+            if (EPI == EPI_COMBINE) {
                 if (g == 0) {
-#pragma unroll
-                    for (int r = 0; r < COUT; ++r) static_cast<float*>(out)[c * COUT + r] = acc[tt][r];
+                    const float zi = invf[jcnt(epc[rr])] * er[rr] + sc * o1[rr];
+                    cio.z[c] = zi;
+                    zsum[0] += (double)zi * (double)er[rr];
+                    zsum[1] += (double)zi * (double)erp[rr];
                 }
+            } else if (EPI == EPI_F32) {
+                static_assert(EPI != EPI_F32 || COUT == 1, "marching F32 epilogue: one channel");
+                if (g == 0) static_cast<float*>(out)[c] = o1[rr];
             } else {
-                float v[4] = {acc[tt][0], acc[tt][1], acc[tt][2], acc[tt][3]};
+                float v[4] = {acc[rr][0], acc[rr][1], acc[rr][2], acc[rr][3]};
                 if (EPI == EPI_GATE) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] *= gate4[tt][r];
+                    for (int r = 0; r < 4; ++r) v[r] *= gate4[rr][r];
                 }
                 *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + c * 16 + 4 * g) = pack4(v);
             }
         }
         store_plane((z + 2) & 3);               // slot of plane z-2, last read for plane z-1
+        __syncthreads();
+    }
+    if (EPI == EPI_COMBINE) {
+        block_reduce<2>(zsum, shr);
+        if (threadIdx.x == 0) {
+            cio.cpart[blockIdx.x] = zsum[0];
+            cio.cpart[gridDim.x + blockIdx.x] = zsum[1];
+        }
+    }
+}
+
+// The combine epilogue's block partials (nb of them per sum, in cpart) summed in block
+// order into the solver's reduction slots: the total in entry 0, zeros in entries
+// 1 .. nparts - 1 (the consumers sum nparts entries of a slot).  zrp_slot < 0: none.
+__global__ void __launch_bounds__(NT) k_relay(const double* __restrict__ cpart, int nb, double* __restrict__ partials,
+                                              int nparts, int zr_slot, int zrp_slot, const Solver* sv) {
+    if (sv && sv->converged) return;
+    __shared__ double sh[8];
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += NT) {
+        v[0] += cpart[b];
+        v[1] += cpart[nb + b];
+    }
+    block_reduce<2>(v, sh);
+    for (int b = threadIdx.x; b < nparts; b += NT) {
+        partials[zr_slot * MAX_BLOCKS + b] = b ? 0.0 : v[0];
+        if (zrp_slot >= 0) partials[zrp_slot * MAX_BLOCKS + b] = b ? 0.0 : v[1];
+    }
+}
+
+// Forward half y = K x = W2 * ((W1 * x) . G) of the preconditioner in one marching
+// pass.  The gated first convolution a1 = (W1 * x) . sigmoid(Wg * g) is recomputed
+// plane by plane on the 34 x 10 halo region the second convolution needs, from an LDS
+// ring of (x, g) pairs over 36 x 12 cells, and kept in a 16-channel LDS ring
+// (the layout of k_mconv's); only y goes to HBM.  Both convolutions take the roundings
+// and k-step orders of k_mconv<1, 16, EPI_GATE> followed by k_mconv<16, 16, EPI_BF16>,
+// so y is the same bit for bit.  a1 is zero outside the grid (the second convolution's
+// zero padding).  Pipeline at plane z: x, g of plane z + 4 load into registers, a1 of
+// plane z + 2 is made from x, g of the planes z + 1 .. z + 3, y of plane z is made from
+// a1 of the planes z - 1 .. z + 1, and x, g of plane z + 4 go to the ring slot of plane
+// z; one barrier per plane.
+constexpr int QX = CTX + 4, QY = CTY + 4;    // 36 x 12
+constexpr int QCELLS = QX * QY;              // 432
+constexpr int QSCAL = (QCELLS + 255) / 256;  // cells per thread per plane
+constexpr int NA1 = (PCELLS + 15) / 16;      // 16-cell MFMA tiles of the 34 x 10 region (22)
+constexpr int NA1W = (NA1 + 3) / 4;          // of them per wave, at most
+
+// RIN: the input is the solver's FP32 residual r and the kernel forms x = BF16(r / s)
+// itself, s^2 = (sum of the nparts partials of <r,r> in rpart) / cells, as k_input does
+// (block 0 stores s in s_out for the combining step); otherwise xin is x (BF16).
+template <bool RIN>
+__global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz, const void* __restrict__ xin,
+                                                 const uint16_t* __restrict__ gsrc,
+                                                 const uint16_t* __restrict__ w1p, const uint16_t* __restrict__ wgp,
+                                                 const uint16_t* __restrict__ w2p, uint16_t* __restrict__ out,
+                                                 const double* __restrict__ rpart, int nparts, double* __restrict__ s_out,
+                                                 const Solver* sv) {
+    if (sv && sv->converged) return;
+    constexpr int PLANE = 2 * HPC * 8;   // uint16 per 16-channel ring plane
+    constexpr int OOB = 0x7FFFFFF0;
+    constexpr int RSRC3 = 0x00020000;
+    __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
+    __shared__ uint32_t xgring[4 * QCELLS];   // per cell: x (low half), g (high half)
+    const int ntx = (nx + CTX - 1) / CTX, nty = (ny + CTY - 1) / CTY;
+    const int nslab = (nz + mz - 1) / mz;
+    const int t = xcd_chunk(blockIdx.x, gridDim.x);
+    const int tx = t % ntx, ty = (t / ntx) % nty, tzs = t / (ntx * nty);
+    if (tzs >= nslab) return;
+    const int z0 = tzs * mz, z1 = min(nz, z0 + mz);
+    const long long plane = (long long)nx * ny;
+    double rs = 0.0;   // RIN: s
+    if (RIN) {
+        __shared__ double sh[4];
+        double v[1] = {0.0};
+        for (int b = threadIdx.x; b < nparts; b += NT) v[0] += rpart[b];
+        block_reduce<1>(v, sh);
+        rs = sqrt(v[0] / (double)(plane * nz));
+        if (blockIdx.x == 0 && threadIdx.x == 0) *s_out = rs;
+    }
+    // loader of the 36 x 12 region of x and g (byte offsets within a plane of g; OOB
+    // outside the grid, where the buffer load returns zero)
+    const int qx0 = tx * CTX - 2, qy0 = ty * CTY - 2;
+    int oq[QSCAL];
+#pragma unroll
+    for (int k = 0; k < QSCAL; ++k) {
+        const int cell = threadIdx.x + 256 * k;
+        int o = OOB;
+        if (cell < QCELLS) {
+            const int gx = qx0 + cell % QX, gy = qy0 + cell / QX;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) o = (gx + nx * gy) * 2;
+        }
+        oq[k] = o;
+    }
+    uint16_t px[QSCAL], pg[QSCAL];
+    float pr[RIN ? QSCAL : 1];
+    auto load_xg = [&](int pz) {
+        const bool zin = pz >= 0 && pz < nz;
+        const long long pb = zin ? (long long)pz * plane : 0;
+        const int bytes = zin ? (int)(plane * 2) : 0;
+        const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(gsrc + pb), 0, bytes, RSRC3);
+        if (RIN) {
+            const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(static_cast<const float*>(xin) + pb), 0, 2 * bytes, RSRC3);
+#pragma unroll
+            for (int k = 0; k < QSCAL; ++k)
+                pr[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, oq[k] == OOB ? OOB : 2 * oq[k], 0, 0));
+        } else {
+            const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(static_cast<const uint16_t*>(xin) + pb), 0, bytes, RSRC3);
+#pragma unroll
+            for (int k = 0; k < QSCAL; ++k) px[k] = __builtin_amdgcn_raw_buffer_load_b16(rx, oq[k], 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < QSCAL; ++k) pg[k] = __builtin_amdgcn_raw_buffer_load_b16(rg, oq[k], 0, 0);
+    };
+    auto store_xg = [&](int slot) {
+#pragma unroll
+        for (int k = 0; k < QSCAL; ++k) {
+            const int cell = threadIdx.x + 256 * k;
+            if (cell < QCELLS) {
+                const uint16_t xv = RIN ? f2bf((float)(rs > 0.0 ? (double)pr[k] / rs : 0.0)) : px[k];
+                xgring[slot * QCELLS + cell] = (uint32_t)xv | ((uint32_t)pg[k] << 16);
+            }
+        }
+    };
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(w1p + (long long)lane * 8);
+    const bf16x8 wg = *reinterpret_cast<const bf16x8*>(wgp + (long long)lane * 8);
+    bf16x8 wa[14];
+#pragma unroll
+    for (int s = 0; s < 14; ++s) wa[s] = *reinterpret_cast<const bf16x8*>(w2p + ((long long)s * 64 + lane) * 8);
+    // a1 tiles of the wave: tile wv + 4 i covers cells 16 (wv + 4 i) .. + 15 of the 34 x 10
+    // region (row-major; cells 340 .. 351 are padding, gathered at a clamped cell and
+    // written to the padding of the half planes).  Per tile: the lane's cell index in
+    // the 36-wide x, g planes (at its (-1, -1) neighbour) and whether its cell is inside
+    // the grid.
+    int qb[NA1W];
+    unsigned inside = 0;
+#pragma unroll
+    for (int i = 0; i < NA1W; ++i) {
+        const int c = 16 * (wv + 4 * i) + j;
+        const int cc = c < PCELLS ? c : PCELLS - 1;
+        const int cx = cc % PX, cy = cc / PX;
+        qb[i] = cx + QX * cy;
+        const int gx = tx * CTX - 1 + cx, gy = ty * CTY - 1 + cy;
+        if (c < PCELLS && gx >= 0 && gx < nx && gy >= 0 && gy < ny) inside |= 1u << i;
+    }
+    // a1 of plane p into its ring slot (zero outside the grid)
+    auto make_a1 = [&](int p) {
+        uint16_t* A = ring + (p & 3) * PLANE;
+        if (p < 0 || p >= nz) {
+            for (int q = threadIdx.x; q < 2 * HPC; q += 256)
+                *reinterpret_cast<uint4*>(&A[q * 8]) = make_uint4(0u, 0u, 0u, 0u);
+            return;
+        }
+        int a[8];
+        kmap1_cells<QX>(p, g, 0, QCELLS, a);
+#pragma unroll
+        for (int i = 0; i < NA1W; ++i) {
+            const int tt = wv + 4 * i;
+            if (tt >= NA1) break;   // uniform in the wave
+            // one 4-byte gather per tap; the two B operands are the low and high halves
+            uint32_t xg8[8], bxw[4], bgw[4];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xg8[e] = xgring[a[e] + qb[i] + qcellw<QX>(e)];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                bxw[e] = __builtin_amdgcn_perm(xg8[2 * e + 1], xg8[2 * e], 0x05040100u);
+                bgw[e] = __builtin_amdgcn_perm(xg8[2 * e + 1], xg8[2 * e], 0x07060302u);
+            }
+            bf16x8 bx, bg;
+            __builtin_memcpy(&bx, bxw, 16);
+            __builtin_memcpy(&bg, bgw, 16);
+            const f32x4 ax = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, bx, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            const f32x4 ag = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, bg, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            float v[4];
+            const bool in = (inside >> i) & 1u;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = in ? ax[r] * bf2f(f2bf(sigmoid(ag[r]))) : 0.0f;
+            // lane (j, g): channels 4 g .. 4 g + 3 of cell 16 tt + j
+            *reinterpret_cast<uint2*>(&A[((g >> 1) * HPC + 16 * tt + j) * 8 + 4 * (g & 1)]) = pack4(v);
+        }
+    };
+    // prologue: x, g of the planes z0 - 2 .. z0 + 3 and a1 of z0 - 1 .. z0 + 1
+    for (int pz = z0 - 2; pz <= z0; ++pz) {
+        load_xg(pz);
+        store_xg(pz & 3);
+    }
+    __syncthreads();
+    for (int p = z0 - 1; p <= z0 + 1; ++p) {
+        make_a1(p);
+        load_xg(p + 2);
+        store_xg((p + 2) & 3);
+        __syncthreads();
+    }
+    const int xh = wv & 1, r0 = 4 * (wv >> 1);
+    const int cb = j + 16 * xh + PX * r0;
+    const int gx = tx * CTX + 16 * xh + j;
+    for (int z = z0; z < z1; ++z) {
+        load_xg(z + 4);
+        make_a1(z + 2);
+        f32x4 acc[4];
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) acc[rr] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        conv16_plane(ring, cb, g, (z + 3) & 3, z & 3, (z + 1) & 3, wa, acc);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int gy = ty * CTY + r0 + rr;
+            if (gx >= nx || gy >= ny) continue;
+            const long long c = (long long)gx + (long long)nx * gy + plane * z;
+            float v[4] = {acc[rr][0], acc[rr][1], acc[rr][2], acc[rr][3]};
+            *reinterpret_cast<uint2*>(out + c * 16 + 4 * g) = pack4(v);
+        }
+        store_xg(z & 3);   // plane z + 4
         __syncthreads();
     }
 }
@@ -785,33 +1172,6 @@ __global__ void k_adam(int n, float* __restrict__ w, const float* __restrict__ g
     w[i] = w[i] - lr * mh / (sqrtf(vh) + 1e-8f);
 }
 
-// Solver step: z = D^-1 r + s y (float); partials <z,r> -> slot zr, <z,rp> -> slot zrp
-__global__ void __launch_bounds__(NT) k_combine(long long n, double dx2, const float* __restrict__ r,
-                                                const float* __restrict__ rp, const uint8_t* __restrict__ pcode,
-                                                const float* __restrict__ y, const double* __restrict__ s_in,
-                                                float* __restrict__ z, double* __restrict__ partials, int zr_slot,
-                                                int zrp_slot, const Solver* sv) {
-    if (sv && sv->converged) return;
-    __shared__ double sh[8];
-    __shared__ float invf[16];
-    if (threadIdx.x < 16) invf[threadIdx.x] = threadIdx.x ? (float)(dx2 / (double)threadIdx.x) : 0.0f;
-    __syncthreads();
-    const float s = (float)*s_in;
-    double v[2] = {0.0, 0.0};
-    for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT) {
-        const float ri = r[i];
-        const float zi = invf[jcnt(pcode[i])] * ri + s * y[i];
-        z[i] = zi;
-        v[0] += (double)zi * (double)ri;
-        if (rp) v[1] += (double)zi * (double)rp[i];
-    }
-    block_reduce<2>(v, sh);
-    if (threadIdx.x == 0) {
-        partials[zr_slot * MAX_BLOCKS + blockIdx.x] = v[0];
-        if (zrp_slot >= 0) partials[zrp_slot * MAX_BLOCKS + blockIdx.x] = v[1];
-    }
-}
-
 }  // namespace
 
 }  // namespace ibm
@@ -827,7 +1187,7 @@ struct ibm_cnn {
     float* dw;       // last gradient
     int adam_t;
     uint16_t* wp;    // packed BF16 A operands of the six convolutions
-    ibm::PackDesc pd[6];
+    ibm::PackDesc pd[7];
     uint16_t* xr;    // network input (residual / s), cells
     uint16_t* xg;    // geometry input, cells
     uint16_t* G;     // gate, cells x 16
@@ -845,6 +1205,8 @@ struct ibm_cnn {
     double* q;       // cap
     double* f;       // cap (loss: -b)
     double* part;    // 3 x MAX_BLOCKS
+    double* cpart;   // 2 x (blocks of the marching kernels of the attached geometry)
+    long long cpart_n;
     double* scal;    // 8: s, k1, k2, loss
     double* h_scal;  // pinned host copy
     int nx, ny, nz;  // dims of the last forward
@@ -855,13 +1217,14 @@ struct ibm_cnn {
 namespace ibm {
 namespace {
 
-enum { PV_W1 = 0, PV_W2, PV_W2T, PV_W1T, PV_WG, PV_WGT, PV_N };
+enum { PV_W1 = 0, PV_W2, PV_W2T, PV_W1T, PV_WG, PV_WGT, PV_W1TY, PV_N };
 constexpr int OFF_W1 = 0, OFF_W2 = 432, OFF_WG = 7344;
 
 void fill_pack_desc(ibm_cnn* n) {
-    // (layer offset, layer cin, layer cout, adjoint)
-    const int spec[PV_N][4] = {{OFF_W1, 1, 16, 0}, {OFF_W2, 16, 16, 0}, {OFF_W2, 16, 16, 1},
-                               {OFF_W1, 1, 16, 1}, {OFF_WG, 1, 16, 0}, {OFF_WG, 1, 16, 1}};
+    // (layer offset, layer cin, layer cout, adjoint, dy rows)
+    const int spec[PV_N][5] = {{OFF_W1, 1, 16, 0, 0}, {OFF_W2, 16, 16, 0, 0}, {OFF_W2, 16, 16, 1, 0},
+                               {OFF_W1, 1, 16, 1, 0}, {OFF_WG, 1, 16, 0, 0}, {OFF_WG, 1, 16, 1, 0},
+                               {OFF_W1, 1, 16, 1, 1}};
     int off = 0;
     for (int v = 0; v < PV_N; ++v) {
         PackDesc d;
@@ -869,9 +1232,10 @@ void fill_pack_desc(ibm_cnn* n) {
         d.lcin = spec[v][1];
         d.lcout = spec[v][2];
         d.bwd = spec[v][3];
+        d.ymode = spec[v][4];
         d.cin = d.bwd ? d.lcout : d.lcin;
         d.cout = d.bwd ? d.lcin : d.lcout;
-        d.ks = ksteps(d.cin);
+        d.ks = d.ymode ? 5 : ksteps(d.cin);
         d.off = off;
         off += d.ks * 512;
         n->pd[v] = d;
@@ -923,8 +1287,7 @@ int mconv_blocks(int nx, int ny, int nz, int mz) {
     return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY) * ((nz + mz - 1) / mz);
 }
 
-int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv, hipStream_t s,
-                ibm_ctx* timed = nullptr) {
+int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv, hipStream_t s) {
     if (!keep) {
         // solver path: marching kernels, no activations kept (their in-plane byte
         // offsets are 32-bit)
@@ -935,16 +1298,13 @@ int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv,
         const int mz = mconv_planes(nx, ny, nz);
         const int mb = mconv_blocks(nx, ny, nz, mz);
         const uint16_t* wg = pw(n, PV_WG);
-        k_mconv<1, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, pw(n, PV_W1), n->a1, n->xg, wg, sv);
-        k_mconv<16, 16, EPI_BF16><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W2), n->y, nullptr, nullptr, sv);
-        // the gated adjoint output reuses a1's buffer (a1 is dead once y exists)
-        if (timed)
-            launch_timed(timed, TK_DIR, k_mconv<16, 16, EPI_GATE>, mb, s, nx, ny, nz, mz, (const uint16_t*)n->y,
-                         pw(n, PV_W2T), (void*)n->a1, (const uint16_t*)n->xg, wg, sv);
-        else
-            k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv);
-        k_mconv<16, 1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1T), n->out, nullptr, nullptr,
-                                                   sv);
+        k_mfwd<false><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y,
+                                         nullptr, 0, nullptr, sv);
+        // the gated adjoint output goes to a1's buffer (the forward half keeps a1 in LDS)
+        k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
+                                                     CombineIO{});
+        k_mconv<16, 1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), n->out, nullptr, nullptr,
+                                                   sv, CombineIO{});
         IBM_HIP(hipGetLastError());
         n->nx = nx;
         n->ny = ny;
@@ -1024,6 +1384,16 @@ int check_grid(const ibm_cnn* n, long long cells) {
 // geometry input of the context (and, for training networks, the stored gate the
 // training kernels use; the solver path computes the gate on the fly)
 int prepare_geometry(ibm_cnn* n, ibm_ctx* c, hipStream_t s) {
+    const Geo& g = c->geo;
+    const long long need = 2LL * mconv_blocks(g.nx, g.ny, g.nz, mconv_planes(g.nx, g.ny, g.nz));
+    if (n->cpart_n < need) {
+        IBM_HIP(hipStreamSynchronize(s));
+        if (n->cpart) IBM_HIP(hipFree(n->cpart));
+        n->cpart = nullptr;
+        n->cpart_n = 0;
+        IBM_HIP(hipMalloc((void**)&n->cpart, need * sizeof(double)));
+        n->cpart_n = need;
+    }
     k_geom<<<2048, 256, 0, s>>>(c->N, c->pcode, n->xg);
     IBM_HIP(hipGetLastError());
     return n->train_ok ? net_gate(n, c->geo.nx, c->geo.ny, c->geo.nz, s) : IBM_OK;
@@ -1075,13 +1445,43 @@ int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* 
                             hipStream_t s) {
     ibm_cnn* n = static_cast<ibm_cnn*>(net);
     const Geo& g = c->geo;
-    k_input<float><<<nparts, NT, 0, s>>>(c->N, r, partials + (long long)rr_slot * MAX_BLOCKS, nparts, n->xr,
-                                         n->scal, sv, it, check);
-    int rc = net_forward(n, g.nx, g.ny, g.nz, false, sv, s, sv ? c : nullptr);
-    if (rc) return rc;
-    k_combine<<<nparts, NT, 0, s>>>(c->N, g.dx * g.dx, r, rp, c->pcode, n->out, n->scal, z, partials, zr_slot,
-                                     zrp_slot, sv);
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    if ((long long)nx * ny * 32 >= (1LL << 31)) {
+        set_error("cnn: x-y plane too large for the marching convolutions");
+        return IBM_ERR_ARG;
+    }
+    const int mz = mconv_planes(nx, ny, nz);
+    const int mb = mconv_blocks(nx, ny, nz, mz);
+    if (2LL * mb > n->cpart_n) {
+        set_error("cnn: geometry not prepared for this network");
+        return IBM_ERR_ARG;
+    }
+    const uint16_t* wg = pw(n, PV_WG);
+    const double* rpart = partials + (long long)rr_slot * MAX_BLOCKS;
+    if (check) {
+        // k_input also stops the solve once <r,r> <= tol^2 |b|^2
+        k_input<float><<<nparts, NT, 0, s>>>(c->N, r, rpart, nparts, n->xr, n->scal, sv, it, check);
+        k_mfwd<false><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y,
+                                         nullptr, 0, nullptr, sv);
+    } else {
+        k_mfwd<true><<<mb, 256, 0, s>>>(nx, ny, nz, mz, r, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart,
+                                        nparts, n->scal, sv);
+    }
+    if (sv)   // inside a solve: the dominant convolution is timed when the context times its kernels
+        launch_timed(c, TK_DIR, k_mconv<16, 16, EPI_GATE>, mb, s, nx, ny, nz, mz, (const uint16_t*)n->y,
+                     pw(n, PV_W2T), (void*)n->a1, (const uint16_t*)n->xg, wg, (const Solver*)sv, CombineIO{});
+    else
+        k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
+                                                     CombineIO{});
+    const CombineIO cio{r, rp, c->pcode, n->scal, g.dx * g.dx, z, n->cpart};
+    k_mconv<16, 1, EPI_COMBINE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), nullptr, nullptr,
+                                                   nullptr, sv, cio);
+    k_relay<<<1, NT, 0, s>>>(n->cpart, mb, partials, nparts, zr_slot, zrp_slot, sv);
     IBM_HIP(hipGetLastError());
+    n->nx = nx;
+    n->ny = ny;
+    n->nz = nz;
+    n->have_fwd = false;
     return IBM_OK;
 }
 
@@ -1099,7 +1499,7 @@ void net_free(ibm_cnn* n) {
     if (!n) return;
     void* bufs[] = {n->w,  n->m,  n->v,      n->dw,     n->wp,  n->xr,    n->xg,  n->G, n->u1, n->a1, n->y,
                     n->vv, n->bb, n->sig[0], n->sig[1], n->dy1, n->dG,    n->out, n->wpart, n->h, n->q,  n->f,
-                    n->part, n->scal};
+                    n->part, n->cpart, n->scal};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (n->h_scal) (void)hipHostFree(n->h_scal);

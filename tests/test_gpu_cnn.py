@@ -93,9 +93,13 @@ def test_marching_forward_matches_oracle_ragged_grid():
     net.close()
 
 
-def test_marching_forward_equals_kept_forward():
-    """Both forward forms take the same BF16 roundings and accumulate the same MFMA
-    k-steps in the same order, so their outputs agree bit for bit; 250 x 250 x 45
+def test_marching_forward_matches_kept_forward():
+    """The two forward forms take the same BF16 roundings in the three 16-channel
+    layers and accumulate their MFMA k-steps in the same order, so those activations
+    agree bit for bit; the last (16 -> 1) layer of the marching form sums the same exact
+    BF16 x BF16 products in another order (three FP32 partial sums per output instead of
+    one chain), so the outputs differ only by FP32 summation error: at most ~432 * 2^-24
+    of the sum of |products| per cell, bounded here by 1e-5 relative L2.  250 x 250 x 45
     gives 6-plane slabs with a short last slab and ragged x-y tiles."""
     n = (250, 250, 45)
     shape = (n[2], n[1], n[0])
@@ -111,7 +115,9 @@ def test_marching_forward_equals_kept_forward():
         ys.append(y.cpu().numpy())
         net.close()
     assert np.all(np.isfinite(ys[0])) and np.max(np.abs(ys[0])) > 0.0
-    assert np.array_equal(ys[0], ys[1])
+    e = rel_l2(ys[1], ys[0])
+    print("marching vs kept forward rel L2 %.2e" % e, flush=True)
+    assert e < 1e-5
 
 
 def test_forward_tile_edges_exact_zero_padding():
