@@ -479,7 +479,9 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
     constexpr int NLD = CIN == 16 ? PCHUNK : PSCAL;             // input loads per thread per plane
     constexpr bool ONE = CIN == 1 || EPI == EPI_GATE;           // some 1-channel ring is gathered
     __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
-    __shared__ uint16_t gring[EPI == EPI_GATE ? 4 * PCELLS : 1];
+    // EPI_GATE: geometry planes as row pairs, cell c holding g(c) (low half) and g of the
+    // cell one row below (high half), so that one 4-byte gather serves two output rows
+    __shared__ uint32_t gring[EPI == EPI_GATE ? 4 * PCELLS : 1];
     const int ntx = (nx + CTX - 1) / CTX, nty = (ny + CTY - 1) / CTY;
     const int nslab = (nz + mz - 1) / mz;
     const int t = xcd_chunk(blockIdx.x, gridDim.x);
@@ -559,10 +561,15 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
     };
     auto store_plane = [&](int slot) {
         if (EPI == EPI_GATE) {
+            uint16_t* G16 = reinterpret_cast<uint16_t*>(gring + slot * PCELLS);
 #pragma unroll
             for (int k = 0; k < PSCAL; ++k) {
                 const int cell = threadIdx.x + 256 * k;
-                if (cell < PCELLS) gring[slot * PCELLS + cell] = preg[k];
+                if (cell < PCELLS) {
+                    G16[2 * cell] = preg[k];
+                    if (cell >= PX) G16[2 * (cell - PX) + 1] = preg[k];
+                    else G16[2 * (cell + (PY - 1) * PX) + 1] = 0;   // last row: no row below
+                }
             }
         }
         uint16_t* P = ring + slot * PLANE;
@@ -633,13 +640,20 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
         f32x4 gacc[4];
         if (EPI == EPI_GATE) {
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                uint16_t tmp[8];
+            for (int pp = 0; pp < 2; ++pp) {   // output rows 2 pp and 2 pp + 1
+                uint32_t w8[8], lo[4], hi[4];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) tmp[e] = gring[a1[e] + qcell(e) + PX * rr];
-                bf16x8 bg;
-                __builtin_memcpy(&bg, tmp, 16);
-                gacc[rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, bg, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                for (int e = 0; e < 8; ++e) w8[e] = gring[a1[e] + qcell(e) + PX * 2 * pp];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    lo[e] = __builtin_amdgcn_perm(w8[2 * e + 1], w8[2 * e], 0x05040100u);
+                    hi[e] = __builtin_amdgcn_perm(w8[2 * e + 1], w8[2 * e], 0x07060302u);
+                }
+                bf16x8 b0, b1;
+                __builtin_memcpy(&b0, lo, 16);
+                __builtin_memcpy(&b1, hi, 16);
+                gacc[2 * pp] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, b0, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                gacc[2 * pp + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, b1, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
             }
         }
         f32x4 acc[4];
