@@ -263,8 +263,9 @@ int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net);
  * pressure solve are bracketed by HIP events on its stream and the elapsed times are
  * collected at the end of each solve.  Slots: 0 = CG pass A (SpMV, <d,q>; for the
  * learned solve: the whole preconditioner application), 1 = CG pass B (update, <r,r>,
- * <r,z>; for the learned solve: passes A and B), 2 = the dominant convolution of the
- * learned preconditioner (gated 16 -> 16 adjoint).  ibm_timing_read fills out[0..2] =
+ * <r,z>; for the learned solve: passes A and B), 2 = the dominant kernel of the
+ * learned preconditioner (its fused forward half, the input scaling and both forward
+ * convolutions).  ibm_timing_read fills out[0..2] =
  * accumulated milliseconds per slot, out[3..5] = launches per slot, out[6] =
  * iterations that did work (launches after convergence exit at once), out[7] =
  * cells, out[8] = cuts, out[9] = precision; reset != 0 zeroes the accumulators.

@@ -1477,16 +1477,15 @@ int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* 
         k_input<float><<<nparts, NT, 0, s>>>(c->N, r, rpart, nparts, n->xr, n->scal, sv, it, check);
         k_mfwd<false><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y,
                                          nullptr, 0, nullptr, sv);
+    } else if (sv) {   // inside a solve: the dominant kernel is timed when the context times its kernels
+        launch_timed(c, TK_DIR, k_mfwd<true>, mb, s, nx, ny, nz, mz, (const void*)r, (const uint16_t*)n->xg,
+                     pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart, nparts, n->scal, (const Solver*)sv);
     } else {
         k_mfwd<true><<<mb, 256, 0, s>>>(nx, ny, nz, mz, r, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart,
                                         nparts, n->scal, sv);
     }
-    if (sv)   // inside a solve: the dominant convolution is timed when the context times its kernels
-        launch_timed(c, TK_DIR, k_mconv<16, 16, EPI_GATE>, mb, s, nx, ny, nz, mz, (const uint16_t*)n->y,
-                     pw(n, PV_W2T), (void*)n->a1, (const uint16_t*)n->xg, wg, (const Solver*)sv, CombineIO{});
-    else
-        k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
-                                                     CombineIO{});
+    k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
+                                                 CombineIO{});
     const CombineIO cio{r, rp, c->pcode, n->scal, g.dx * g.dx, z, n->cpart};
     k_mconv<16, 1, EPI_COMBINE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), nullptr, nullptr,
                                                    nullptr, sv, cio);
