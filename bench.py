@@ -160,7 +160,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
         dt = min(case.dt, 0.3 * case.dx / max(ctl["umax"], 1e-30))
         p = ibm.step_params(dt, case.nu, csm=case.csm, step=step, dt_prev=ctl["dt_prev"],
                             tol=args.tol if tol is None else tol,
-                            max_iter=20000, check_every=16, kind=kind, inner_tol=args.inner_tol,
+                            max_iter=20000, check_every=16, kind=kind,
+                            inner_tol=args.inner_tol_learned if solver == "mixed_learned" else args.inner_tol,
                             inner_max_iter=2000)
         ctl["dt_prev"] = dt
         return p
@@ -290,6 +291,9 @@ def main():
                     help="Poisson tolerance of the untimed warm-up steps (default: --tol)")
     ap.add_argument("--inner-tol", type=float, default=1e-1,
                     help="mixed solve: residual reduction of each FP32 segment between FP64 replacements")
+    ap.add_argument("--inner-tol-learned", type=float, default=1e-5,
+                    help="mixed+learned solve: the same per segment (flexible CG restarts at each "
+                         "replacement, so it favours fewer, longer segments)")
     ap.add_argument("--solver", default="mixed_learned", choices=["mixed", "mixed_learned", "pcg_fp64"],
                     help="headline solver (the metric names mixed+learned); plain FP64 and mixed always run")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned solver")
@@ -362,6 +366,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": case.name, "cells": list(case.n), "triangles": int(len(case.tri)),
                    "cuts": head["cuts"], "solver": head["solver"], "tol": args.tol, "inner_tol": args.inner_tol,
+                   "inner_tol_learned": args.inner_tol_learned,
                    "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm},
         "plain_fp64_value": plain["value"] if plain else None,
         "speedup_vs_plain_fp64": head["value"] / plain["value"] if plain else None,
