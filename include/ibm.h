@@ -205,8 +205,9 @@ int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const vo
  *
  * Operator: a linear, symmetric positive semi-definite convolutional network of four
  * 3x3x3 convolutions with 16 channels and a geometry gate,
- *     G = sigmoid(Wg * g),  K x = W2 * ((W1 * x) . G),  net(x) = K^T K x,
- * with g the open-face fraction of the cell (open pressure faces / 6), "*" a
+ *     G = hsig(Wg * g),  K x = W2 * ((W1 * x) . G),  net(x) = K^T K x,
+ * with hsig(v) = min(max(v/4 + 1/2, 0), 1), g the open-face fraction of the cell
+ * (open pressure faces / 6), "*" a
  * zero-padded 3x3x3 cross-correlation (taps at the grid faces are zero), K^T the
  * adjoint (flipped, transposed convolutions) and "." the per-channel product.  As the
  * preconditioner of IBM_SOLVER_FCG_CNN it maps a residual r to

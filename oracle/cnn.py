@@ -5,11 +5,13 @@ What is computed:
 
 * A linear, symmetric positive semi-definite convolutional operator built from
   four 3x3x3 convolutions with 16 channels and a geometry gate:
-      G      = sigmoid(Wg * g)                      (16 channels, per geometry)
+      G      = hsig(Wg * g)                         (16 channels, per geometry)
       K x    = W2 * ((W1 * x) . G)                  (1 -> 16 channels)
       K^T y  = W1^T * ((W2^T * y) . G)              (16 -> 1, adjoint convolutions)
       net(x) = K^T K x
-  with g the fraction of the six faces of a cell that are open pressure faces, "*"
+  with hsig(v) = min(max(v/4 + 1/2, 0), 1) (the "hard" logistic: the same value and
+  slope as the logistic function at 0, clamped to [0, 1]), g the fraction of the six
+  faces of a cell that are open pressure faces, "*"
   a zero-padded 3x3x3 cross-correlation, "^T *" its adjoint and "." the
   per-channel product.  The operator is linear in x, so a Krylov method sees a
   fixed preconditioner; x^T net(x) = |K x|^2 >= 0.
@@ -129,8 +131,15 @@ def conv_backward_weight(x: np.ndarray, dy: np.ndarray) -> np.ndarray:
 
 # ------------------------------------------------------------------ network
 
-def sigmoid(v):
-    return 1.0 / (1.0 + np.exp(-v))
+def hsig(v):
+    """Gate nonlinearity: v/4 + 1/2 clamped to [0, 1]."""
+    return np.clip(0.25 * v + 0.5, 0.0, 1.0)
+
+
+def hsig_slope(G):
+    """d hsig / dv expressed through the gate value: 1/4 strictly inside (0, 1), 0 where
+    the clamp is active (at the kinks the one-sided slope of the clamp is taken)."""
+    return np.where((G > 0.0) & (G < 1.0), 0.25, 0.0)
 
 
 def forward(x: np.ndarray, g: np.ndarray, ws: list, bf16: bool = False):
@@ -142,7 +151,7 @@ def forward(x: np.ndarray, g: np.ndarray, ws: list, bf16: bool = False):
     W1, W2, Wg = (rnd(w) for w in ws)
     x1 = rnd(x)[..., None]
     g1 = rnd(g)[..., None]
-    G = rnd(sigmoid(conv_forward(g1, Wg)))
+    G = rnd(hsig(conv_forward(g1, Wg)))
     u1 = conv_forward(x1, W1)
     a1 = rnd(u1 * G)
     y = rnd(conv_forward(a1, W2))
@@ -180,8 +189,8 @@ def backward(saved: dict, ws: list, dy: np.ndarray, bf16: bool = False):
     # u1 = W1 * x
     dW1 = dW1 + conv_backward_weight(saved["x"], du1)
     dx = conv_backward_data(du1, W1)[..., 0]
-    # G = sigmoid(Wg * g)
-    dpre = rnd(dG * G * (1.0 - G))
+    # G = hsig(Wg * g)
+    dpre = rnd(dG * hsig_slope(G))
     dWg = conv_backward_weight(saved["g"], dpre)
     dg = conv_backward_data(dpre, Wg)[..., 0]
     return [dW1, dW2, dWg], dx, dg

@@ -4,13 +4,13 @@
 //
 // Operator (linear and symmetric in the residual, so that a Krylov method sees a fixed
 // symmetric positive definite preconditioner):
-//   G = sigmoid(Wg * g)                  geometry gate, 16 channels, once per geometry
+//   G = hsig(Wg * g)                     geometry gate, 16 channels, once per geometry
 //   K x = W2 * ((W1 * x) . G)            conv 1 -> 16, gate, conv 16 -> 16
 //   K^T y = W1^T * ((W2^T * y) . G)      the adjoint convolutions
 //   z = D^-1 r + s K^T K (r / s),        s = RMS(r), D the diagonal of A = -L,
 // "*" a zero-padded 3x3x3 cross-correlation, "^T *" its adjoint (flipped taps,
 // transposed channels) and "." the per-channel product; g is the open-face fraction of
-// the cell.  Four 3x3x3 convolutions with 16 channels per application.
+// the cell and hsig(v) = min(max(v/4 + 1/2, 0), 1), one clamped FMA.  Four 3x3x3 convolutions with 16 channels per application.
 //
 // MI355X design:
 //  * activations channels-last in BF16: 16 channels = 32 bytes per cell, one 16-byte
@@ -22,7 +22,7 @@
 //    tile with its halo (34 x 10 x 6 cells) is staged once in LDS as two 16-byte
 //    half-cell planes so that the B-operand reads of 16 lanes are contiguous;
 //  * the output D tile gives each lane 4 consecutive channels of one cell: one 8-byte
-//    store per lane, 512 contiguous bytes per 16-cell tile; gating, the sigmoid and the
+//    store per lane, 512 contiguous bytes per 16-cell tile; gating, the gate function and the
 //    gradient of the gate are fused into that epilogue;
 //  * an adjoint convolution is the same kernel with flipped, transposed packed weights;
 //  * the weight gradient is an implicit GEMM over cells (K = cells of the tile): both
@@ -56,7 +56,7 @@ constexpr int WG_MAX_BLOCKS = 1024;       // weight-gradient partials
 enum {
     EPI_BF16 = 0,     // out = bf16(acc)
     EPI_GATE = 1,     // out = bf16(acc . G); aux (optional) = bf16(acc)
-    EPI_SIGMOID = 2,  // out = bf16(sigmoid(acc))
+    EPI_HSIG = 2,     // out = bf16(hsig(acc))
     EPI_BGATE = 3,    // out = bf16(acc . G); dG (float) = [dG +] acc . P
     EPI_F32 = 4,      // out = acc (float, COUT channels, stride ostride)
     EPI_COMBINE = 5   // marching 16 -> 1 only: the preconditioner's z (CombineIO)
@@ -216,9 +216,10 @@ __device__ inline uint2 pack4(const float (&f)[4]) {
     __builtin_memcpy(&o, &h, 8);
     return o;
 }
-// logistic function; exp and the hardware reciprocal (about 1 ulp each, far below the
-// BF16 rounding every use of it takes)
-__device__ inline float sigmoid(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
+// gate nonlinearity hsig(v) = v/4 + 1/2 clamped to [0, 1]: one FMA and a clamp (the
+// logistic function it replaces cost two quarter-rate transcendentals per value and
+// dominated the issue time of the gated convolutions)
+__device__ inline float hsig(float x) { return fminf(fmaxf(fmaf(x, 0.25f, 0.5f), 0.0f), 1.0f); }
 
 // One 3x3x3 convolution over an nx x ny x nz grid (zero padding): in = cells x CIN
 // BF16 (channels-last), wp = packed weights, out per the epilogue (see EPI_*).
@@ -308,9 +309,9 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
             } else {
                 float v[4] = {acc[0], acc[1], acc[2], acc[3]};
                 const long long o16 = c * 16 + 4 * g;
-                if (EPI == EPI_SIGMOID) {
+                if (EPI == EPI_HSIG) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = sigmoid(v[r]);
+                    for (int r = 0; r < 4; ++r) v[r] = hsig(v[r]);
                 } else if (EPI == EPI_GATE || EPI == EPI_BGATE) {
                     float gt[4];
                     unpack4(*reinterpret_cast<const uint2*>(io.gate + o16), gt);
@@ -342,7 +343,7 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
 // afterwards (one barrier per plane).  Each wave owns one 16-cell half of four output
 // rows: four MFMA tiles, four independent accumulator chains, and each B operand read
 // from LDS feeds up to three of them (tap16).  EPI_BF16 and EPI_F32 (COUT channels) as
-// in k_conv; EPI_GATE computes the gate sigmoid(Wg * g) of its output cells on the fly
+// in k_conv; EPI_GATE computes the gate hsig(Wg * g) of its output cells on the fly
 // (one more MFMA per tile from a ring of geometry planes) instead of reading a stored
 // gate.
 constexpr int PX = CTX + 2, PY = CTY + 2;    // 34 x 10 halo plane
@@ -634,7 +635,7 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
         // a1[e] + qcell(e) + PX rr of a 1-channel ring for output row r0 + rr
         int a1[8];
         if (ONE) kmap1_cells<PX>(z, g, cb, PCELLS, a1);
-        // gate of the output cells, BF16(sigmoid(Wg * g)) as the stored gate: gathered
+        // gate of the output cells, BF16(hsig(Wg * g)) as the stored gate: gathered
         // first so that its LDS latency hides behind the convolution; computed for every
         // row (out-of-grid cells read zeros) so that no MFMA sits in a branch
         f32x4 gacc[4];
@@ -680,7 +681,7 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) gate4[rr][r] = bf2f(f2bf(sigmoid(gacc[rr][r])));
+                for (int r = 0; r < 4; ++r) gate4[rr][r] = bf2f(f2bf(hsig(gacc[rr][r])));
         }
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
@@ -738,7 +739,7 @@ __global__ void __launch_bounds__(NT) k_relay(const double* __restrict__ cpart, 
 }
 
 // Forward half y = K x = W2 * ((W1 * x) . G) of the preconditioner in one marching
-// pass.  The gated first convolution a1 = (W1 * x) . sigmoid(Wg * g) is recomputed
+// pass.  The gated first convolution a1 = (W1 * x) . hsig(Wg * g) is recomputed
 // plane by plane on the 34 x 10 halo region the second convolution needs, from an LDS
 // ring of (x, g) pairs over 36 x 12 cells, and kept in a 16-channel LDS ring
 // (the layout of k_mconv's); only y goes to HBM.  Both convolutions take the roundings
@@ -755,7 +756,8 @@ constexpr int NA1 = (PCELLS + 15) / 16;      // 16-cell MFMA tiles of the 34 x 1
 constexpr int NA1W = (NA1 + 3) / 4;          // of them per wave, at most
 
 // RIN: the input is the solver's FP32 residual r and the kernel forms x = BF16(r / s)
-// itself, s^2 = (sum of the nparts partials of <r,r> in rpart) / cells, as k_input does
+// itself (as r times 1/s in FP64), s^2 = (sum of the nparts partials of <r,r> in
+// rpart) / cells, as k_input does
 // (block 0 stores s in s_out for the combining step); otherwise xin is x (BF16).
 template <bool RIN>
 __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz, const void* __restrict__ xin,
@@ -777,13 +779,14 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
     if (tzs >= nslab) return;
     const int z0 = tzs * mz, z1 = min(nz, z0 + mz);
     const long long plane = (long long)nx * ny;
-    double rs = 0.0;   // RIN: s
+    double rinv = 0.0;   // RIN: 1 / s (0 when r = 0)
     if (RIN) {
         __shared__ double sh[4];
         double v[1] = {0.0};
         for (int b = threadIdx.x; b < nparts; b += NT) v[0] += rpart[b];
         block_reduce<1>(v, sh);
-        rs = sqrt(v[0] / (double)(plane * nz));
+        const double rs = sqrt(v[0] / (double)(plane * nz));
+        rinv = rs > 0.0 ? 1.0 / rs : 0.0;
         if (blockIdx.x == 0 && threadIdx.x == 0) *s_out = rs;
     }
     // loader of the 36 x 12 region of x and g (byte offsets within a plane of g; OOB
@@ -827,7 +830,7 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
         for (int k = 0; k < QSCAL; ++k) {
             const int cell = threadIdx.x + 256 * k;
             if (cell < QCELLS) {
-                const uint16_t xv = RIN ? f2bf((float)(rs > 0.0 ? (double)pr[k] / rs : 0.0)) : px[k];
+                const uint16_t xv = RIN ? f2bf((float)((double)pr[k] * rinv)) : px[k];
                 xgring[slot * QCELLS + cell] = (uint32_t)xv | ((uint32_t)pg[k] << 16);
             }
         }
@@ -883,10 +886,12 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
             __builtin_memcpy(&bg, bgw, 16);
             const f32x4 ax = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, bx, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
             const f32x4 ag = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, bg, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            // zero outside the grid: a bit mask instead of a branch per value
+            const uint32_t keep = ((inside >> i) & 1u) ? 0xFFFFFFFFu : 0u;
             float v[4];
-            const bool in = (inside >> i) & 1u;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = in ? ax[r] * bf2f(f2bf(sigmoid(ag[r]))) : 0.0f;
+            for (int r = 0; r < 4; ++r)
+                v[r] = __uint_as_float(__float_as_uint(ax[r] * bf2f(f2bf(hsig(ag[r])))) & keep);
             // lane (j, g): channels 4 g .. 4 g + 3 of cell 16 tt + j
             *reinterpret_cast<uint2*>(&A[((g >> 1) * HPC + 16 * tt + j) * 8 + 4 * (g & 1)]) = pack4(v);
         }
@@ -1060,9 +1065,10 @@ __global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__
         }
     }
     const double s = sqrt(ff / (double)n);
+    const double sinv = s > 0.0 ? 1.0 / s : 0.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) *s_out = s;
     for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < n; i += (long long)gridDim.x * NT)
-        x[i] = f2bf((float)(s > 0.0 ? (double)f[i] / s : 0.0));
+        x[i] = f2bf((float)((double)f[i] * sinv));
 }
 
 // geometry input: BF16(open pressure faces / 6)
@@ -1080,12 +1086,12 @@ __global__ void k_split(long long n, const uint16_t* __restrict__ x2, uint16_t* 
     }
 }
 
-// gradient at the gate's pre-activation: BF16(dG . G (1 - G))
+// gradient at the gate's pre-activation: BF16(dG . hsig'), hsig' = 1/4 where 0 < G < 1, else 0
 __global__ void k_dpre(long long n16, const float* __restrict__ dg, const uint16_t* __restrict__ gt,
                        uint16_t* __restrict__ out) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (long long)gridDim.x * blockDim.x) {
         const float gv = bf2f(gt[i]);
-        out[i] = f2bf(dg[i] * gv * (1.0f - gv));
+        out[i] = f2bf(dg[i] * ((gv > 0.0f && gv < 1.0f) ? 0.25f : 0.0f));
     }
 }
 
@@ -1279,9 +1285,9 @@ ConvIO io_bgate(const uint16_t* G, const uint16_t* pre, float* dg, int accum) {
     return ConvIO{G, nullptr, pre, dg, accum, 1};
 }
 
-// G = sigmoid(Wg * xg)
+// G = hsig(Wg * xg)
 int net_gate(ibm_cnn* n, int nx, int ny, int nz, hipStream_t s) {
-    k_conv<1, 16, EPI_SIGMOID><<<conv_blocks(nx, ny, nz), 256, 0, s>>>(nx, ny, nz, n->xg, pw(n, PV_WG), n->G,
+    k_conv<1, 16, EPI_HSIG><<<conv_blocks(nx, ny, nz), 256, 0, s>>>(nx, ny, nz, n->xg, pw(n, PV_WG), n->G,
                                                                         io_none(), nullptr);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
@@ -1378,7 +1384,7 @@ int net_backward(ibm_cnn* n, float* dx, hipStream_t s) {
     if ((rc = wgrad<1, 16>(n, n->xr, n->sig[0], OFF_W1, 1, s))) return rc;
     if (dx)
         k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_W1T), dx, io_none(2), nullptr);
-    // G = sigmoid(Wg * xg)
+    // G = hsig(Wg * xg)
     k_dpre<<<2048, 256, 0, s>>>(cells * 16, n->dG, n->G, n->sig[1]);
     if ((rc = wgrad<1, 16>(n, n->xg, n->sig[1], OFF_WG, 0, s))) return rc;
     if (dx)

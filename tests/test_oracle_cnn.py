@@ -90,14 +90,20 @@ def test_network_backward_matches_finite_differences():
     x = rng.standard_normal((4, 5, 6))
     g = rng.uniform(0, 1, (4, 5, 6))
     ws = cnn.split_weights(inputs.cnn_init_weights(7, scale=5.0).astype(np.float64))
+    ws[2] = ws[2] * 15.0   # gate weights large enough that part of the gate is clamped
     R = rng.standard_normal((4, 5, 6))
 
     def J(ws_, x_, g_):
         y, _ = cnn.forward(x_, g_, ws_)
         return float(np.sum(y * R))
 
+    # the gate's pre-activations cover both the linear part of hsig (|v| < 2) and its
+    # clamps, so the checks below see both branches of its slope
+    inside = np.mean(np.abs(cnn.conv_forward(g[..., None], ws[2])) < 2.0)
+    assert 0.2 < inside < 0.9, inside
     y, saved = cnn.forward(x, g, ws)
     dws, dx, dg = cnn.backward(saved, ws, R)
+    assert np.max(np.abs(dws[2])) > 0.0
     h = 1e-6
     for l in range(3):
         for _ in range(8):
