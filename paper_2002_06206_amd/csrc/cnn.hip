@@ -338,14 +338,15 @@ __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const u
 // Marching form of a convolution for the solver's preconditioner applications.
 // A block owns a 32 x 8 output tile in x-y and walks a slab of mz planes in z.  The
 // input planes z-1, z, z+1 (34 x 10 cells with halo) sit in a ring of four LDS planes
-// (two 16-byte half-cell planes each for CIN = 16, HPC cells apart); plane z+2 is
-// loaded into registers while plane z is computed and written to the free ring slot
-// afterwards (one barrier per plane).  Each wave owns one 16-cell half of four output
-// rows: four MFMA tiles, four independent accumulator chains, and each B operand read
-// from LDS feeds up to three of them (tap16).  EPI_BF16 and EPI_F32 (COUT channels) as
-// in k_conv; EPI_GATE computes the gate hsig(Wg * g) of its output cells on the fly
-// (one more MFMA per tile from a ring of geometry planes) instead of reading a stored
-// gate.
+// (two 16-byte half-cell planes each, HPC cells apart); plane z+2, loaded into
+// registers while plane z is computed (one iteration earlier in the 16 -> 1 kernels,
+// which then have plane z+3 in flight), is written to the free ring slot afterwards
+// (one barrier per plane).  Each wave owns one
+// 16-cell half of four output rows: four MFMA tiles, four independent accumulator
+// chains, and each B operand read from LDS feeds up to three of them (tap16).
+// EPI_BF16 as in k_conv; EPI_GATE computes the gate hsig(Wg * g) of its output cells on
+// the fly (one more MFMA per tile from a ring of geometry planes) instead of reading a
+// stored gate; EPI_F32 and EPI_COMBINE are the 16 -> 1 forms.
 constexpr int PX = CTX + 2, PY = CTY + 2;    // 34 x 10 halo plane
 constexpr int PCELLS = PX * PY;              // 340
 constexpr int PCHUNK = (2 * PCELLS + 255) / 256;   // 16-byte chunks per thread per plane (CIN = 16)
@@ -467,18 +468,30 @@ __device__ __forceinline__ void conv16to1_plane(const uint16_t* ring, int cb, in
     for (int rr = 0; rr < 4; ++rr) o[rr] = d[rr][0] + d[rr + 1][1] + d[rr + 2][2];
 }
 
-template <int CIN, int COUT, int EPI>
+// Prefetch registers of one plane of the march: the thread's chunks of an input plane
+// (and geometry plane for EPI_GATE), and for EPI_COMBINE the r, r_prev and face codes
+// of the lane's output cells of one plane.  Two sets alternate, so that each load has
+// two plane iterations to arrive (the light kernels of the march otherwise wait on HBM
+// latency every plane).
+struct MPre {
+    uint4 pre[PCHUNK];
+    uint16_t preg[PSCAL];
+    float er[4], erp[4];
+    uint8_t epc[4];
+};
+
+// The march of a 16-channel input (see above): COUT = 16 (EPI_BF16, EPI_GATE) or
+// COUT = 1 (EPI_F32, EPI_COMBINE; conv16to1_plane with the PV_W1TY packing).
+template <int COUT, int EPI>
 __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz, const uint16_t* __restrict__ in,
                                                   const uint16_t* __restrict__ wp, void* __restrict__ out,
                                                   const uint16_t* __restrict__ gsrc, const uint16_t* __restrict__ wgp,
                                                   const Solver* sv, CombineIO cio) {
-    static_assert(CIN == 1 || CIN == 16, "marching convolution: 1 or 16 input channels");
-    static_assert(EPI != EPI_COMBINE || (CIN == 16 && COUT == 1), "combine epilogue: 16 -> 1");
+    static_assert(COUT == 16 || COUT == 1, "marching convolution: 16 or 1 output channels");
+    static_assert((EPI == EPI_COMBINE || EPI == EPI_F32) == (COUT == 1), "epilogue / output channels");
     if (sv && sv->converged) return;
-    constexpr int KS = COUT == 1 ? 5 : ksteps(CIN);             // COUT = 1: PV_W1TY packing
-    constexpr int PLANE = CIN == 16 ? 2 * HPC * 8 : PCELLS;      // uint16 per ring plane
-    constexpr int NLD = CIN == 16 ? PCHUNK : PSCAL;             // input loads per thread per plane
-    constexpr bool ONE = CIN == 1 || EPI == EPI_GATE;           // some 1-channel ring is gathered
+    constexpr int KS = COUT == 1 ? 5 : 14;
+    constexpr int PLANE = 2 * HPC * 8;   // uint16 per ring plane
     __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
     // EPI_GATE: geometry planes as row pairs, cell c holding g(c) (low half) and g of the
     // cell one row below (high half), so that one 4-byte gather serves two output rows
@@ -501,43 +514,46 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
     const float sc = EPI == EPI_COMBINE ? (float)*cio.s_in : 0.0f;
     double zsum[2] = {0.0, 0.0};
     // The thread's loads are the same in every plane: in-plane byte offsets of its
-    // chunks (CIN = 16: half cells of 8 channels) and cells (1-channel planes).  Plane
+    // chunks (half cells of 8 channels) and, for the gate, of its geometry cells.  Plane
     // loads go through buffer resources sized to the plane, so that a load at an offset
     // past its end returns zero: halo cells outside the grid (and threads without a
     // chunk) take offset OOB, and planes outside the grid get an empty resource.  The
     // host keeps nx * ny * 32 below 2^31.
     constexpr int OOB = 0x7FFFFFF0;
     constexpr int RSRC3 = 0x00020000;   // word 3 of a raw buffer resource on this target
-    int o16[CIN == 16 ? PCHUNK : 1], o1[PSCAL];
+    int o16[PCHUNK], o1[PSCAL];
 #pragma unroll
-    for (int k = 0; k < NLD; ++k) {
+    for (int k = 0; k < PCHUNK; ++k) {
         const int q = threadIdx.x + 256 * k;
-        const int cell = CIN == 16 ? q >> 1 : q;
+        const int cell = q >> 1;
         int o = OOB;
         if (cell < PCELLS) {
             const int gx = x0 + cell % PX, gy = y0 + cell / PX;
-            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-                o = ((gx + nx * gy) * CIN + (CIN == 16 ? (q & 1) * 8 : 0)) * 2;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) o = ((gx + nx * gy) * 16 + (q & 1) * 8) * 2;
         }
-        if (CIN == 16) o16[k] = o; else o1[k] = o;
+        o16[k] = o;
     }
-    if (CIN == 16 && EPI == EPI_GATE) {
 #pragma unroll
-        for (int k = 0; k < PSCAL; ++k) {
-            const int cell = threadIdx.x + 256 * k;
-            int o = OOB;
-            if (cell < PCELLS) {
-                const int gx = x0 + cell % PX, gy = y0 + cell / PX;
-                if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) o = (gx + nx * gy) * 2;
-            }
-            o1[k] = o;
+    for (int k = 0; k < PSCAL; ++k) {
+        const int cell = threadIdx.x + 256 * k;
+        int o = OOB;
+        if (EPI == EPI_GATE && cell < PCELLS) {
+            const int gx = x0 + cell % PX, gy = y0 + cell / PX;
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) o = (gx + nx * gy) * 2;
         }
+        o1[k] = o;
     }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, g = lane >> 4;
+    // the wave's outputs: x half xh (16 cells) of the four rows r0 .. r0 + 3, one MFMA
+    // tile (one accumulator chain) per row
+    const int xh = wv & 1, r0 = 4 * (wv >> 1);
+    const int gxo = tx * CTX + 16 * xh + j;   // the lane's output column
+    // halo-plane cell of the lane's column at dx = -1 in halo row r0 (the row above the
+    // wave's first output row)
+    const int cb = j + 16 * xh + PX * r0;
     // loader: plane pz of the halo region into registers (zero outside the grid)
-    uint4 pre[CIN == 16 ? PCHUNK : 1];
-    uint16_t pre1[CIN == 16 ? 1 : PSCAL];
-    uint16_t preg[EPI == EPI_GATE ? PSCAL : 1];
-    auto load_plane = [&](int pz) {
+    auto load_plane = [&](int pz, MPre& R) {
         const bool zin = pz >= 0 && pz < nz;
         const long long pb = zin ? (long long)pz * plane : 0;
         const int bytes = zin ? (int)(plane * 2) : 0;   // of one channel
@@ -545,101 +561,77 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
             const __amdgpu_buffer_rsrc_t rg =
                 __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(gsrc + pb), 0, bytes, RSRC3);
 #pragma unroll
-            for (int k = 0; k < PSCAL; ++k) preg[k] = __builtin_amdgcn_raw_buffer_load_b16(rg, o1[k], 0, 0);
+            for (int k = 0; k < PSCAL; ++k) R.preg[k] = __builtin_amdgcn_raw_buffer_load_b16(rg, o1[k], 0, 0);
         }
         const __amdgpu_buffer_rsrc_t ri =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(in + pb * CIN), 0, bytes * CIN, RSRC3);
-        if (CIN == 16) {
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(in + pb * 16), 0, bytes * 16, RSRC3);
 #pragma unroll
-            for (int k = 0; k < PCHUNK; ++k) {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b128(ri, o16[k], 0, 0);
-                pre[k] = make_uint4(v[0], v[1], v[2], v[3]);
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < PSCAL; ++k) pre1[k] = __builtin_amdgcn_raw_buffer_load_b16(ri, o1[k], 0, 0);
+        for (int k = 0; k < PCHUNK; ++k) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(ri, o16[k], 0, 0);
+            R.pre[k] = make_uint4(v[0], v[1], v[2], v[3]);
         }
     };
-    auto store_plane = [&](int slot) {
+    // EPI_COMBINE: r, r_prev and the face code of the wave's output cells of plane pz
+    auto load_epi = [&](int pz, MPre& R) {
+        if (EPI != EPI_COMBINE) return;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int gy = ty * CTY + r0 + rr;
+            R.er[rr] = R.erp[rr] = 0.0f;
+            R.epc[rr] = 0;
+            if (g == 0 && pz < z1 && gxo < nx && gy < ny) {
+                const long long c = (long long)gxo + (long long)nx * gy + plane * pz;
+                R.er[rr] = cio.r[c];
+                R.epc[rr] = cio.pcode[c];
+                if (cio.rp) R.erp[rr] = cio.rp[c];
+            }
+        }
+    };
+    auto store_plane = [&](int slot, const MPre& R) {
         if (EPI == EPI_GATE) {
             uint16_t* G16 = reinterpret_cast<uint16_t*>(gring + slot * PCELLS);
 #pragma unroll
             for (int k = 0; k < PSCAL; ++k) {
                 const int cell = threadIdx.x + 256 * k;
                 if (cell < PCELLS) {
-                    G16[2 * cell] = preg[k];
-                    if (cell >= PX) G16[2 * (cell - PX) + 1] = preg[k];
+                    G16[2 * cell] = R.preg[k];
+                    if (cell >= PX) G16[2 * (cell - PX) + 1] = R.preg[k];
                     else G16[2 * (cell + (PY - 1) * PX) + 1] = 0;   // last row: no row below
                 }
             }
         }
         uint16_t* P = ring + slot * PLANE;
-        if (CIN == 16) {
 #pragma unroll
-            for (int k = 0; k < PCHUNK; ++k) {
-                const int q = threadIdx.x + 256 * k;
-                if (q < 2 * PCELLS)
-                    *reinterpret_cast<uint4*>(&P[((q & 1) * HPC + (q >> 1)) * 8]) = pre[k];
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < PSCAL; ++k) {
-                const int cell = threadIdx.x + 256 * k;
-                if (cell < PCELLS) P[cell] = pre1[k];
-            }
+        for (int k = 0; k < PCHUNK; ++k) {
+            const int q = threadIdx.x + 256 * k;
+            if (q < 2 * PCELLS) *reinterpret_cast<uint4*>(&P[((q & 1) * HPC + (q >> 1)) * 8]) = R.pre[k];
         }
     };
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int j = lane & 15, g = lane >> 4;
-    // the wave's outputs: x half xh (16 cells) of the four rows r0 .. r0 + 3, one MFMA
-    // tile (one accumulator chain) per row
-    const int xh = wv & 1, r0 = 4 * (wv >> 1);
     bf16x8 wa[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) wa[s] = *reinterpret_cast<const bf16x8*>(wp + ((long long)s * 64 + lane) * 8);
     bf16x8 wg;
     if (EPI == EPI_GATE) wg = *reinterpret_cast<const bf16x8*>(wgp + (long long)lane * 8);
-    // halo-plane cell of the lane's column at dx = -1 in halo row r0 (the row above the
-    // wave's first output row)
-    const int cb = j + 16 * xh + PX * r0;
-    // prologue: planes z0-1, z0, z0+1 into ring slots (z & 3)
-    for (int pz = z0 - 1; pz <= z0 + 1; ++pz) {
-        load_plane(pz);
-        store_plane(pz & 3);
-    }
-    __syncthreads();
-    const int gxo = tx * CTX + 16 * xh + j;   // the lane's output column
-    for (int z = z0; z < z1; ++z) {
-        load_plane(z + 2);                      // in flight during the compute of plane z
-        // EPI_COMBINE: r, r_prev and the face code of the wave's output cells of this
-        // plane, loaded now so that their latency hides behind the convolution
-        float er[4], erp[4];
-        uint8_t epc[4];
-        if (EPI == EPI_COMBINE) {
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int gy = ty * CTY + r0 + rr;
-                er[rr] = erp[rr] = 0.0f;
-                epc[rr] = 0;
-                if (g == 0 && gxo < nx && gy < ny) {
-                    const long long c = (long long)gxo + (long long)nx * gy + plane * z;
-                    er[rr] = cio.r[c];
-                    epc[rr] = cio.pcode[c];
-                    if (cio.rp) erp[rr] = cio.rp[c];
-                }
-            }
-        }
+    // The 16 -> 1 kernels (30 MFMAs per plane) keep two planes in flight; the 16 -> 16
+    // kernels (56 to 60 MFMAs per plane, register-bound) one.
+    constexpr bool DEEP = COUT == 1;
+    // one plane z of the march: DEEP: planes z + 3 (input) and z + 1 (combine operands)
+    // load into L while plane z is computed, S holds plane z + 2 and plane z's combine
+    // operands; otherwise L = S and plane z + 2 loads into it.  Plane z + 2 is stored
+    // into the ring slot of plane z - 2 after the compute.
+    auto step = [&](int z, MPre& L, const MPre& S) {
+        load_plane(z + (DEEP ? 3 : 2), L);
+        load_epi(z + 1, L);
         // ring slots of the planes z - 1, z, z + 1
         const int sl0 = (z + 3) & 3, sl1 = z & 3, sl2 = (z + 1) & 3;
-        // 1-channel gathers (kmap<1>): element e of the lane reads cell
-        // a1[e] + qcell(e) + PX rr of a 1-channel ring for output row r0 + rr
-        int a1[8];
-        if (ONE) kmap1_cells<PX>(z, g, cb, PCELLS, a1);
         // gate of the output cells, BF16(hsig(Wg * g)) as the stored gate: gathered
         // first so that its LDS latency hides behind the convolution; computed for every
-        // row (out-of-grid cells read zeros) so that no MFMA sits in a branch
+        // row (out-of-grid cells read zeros) so that no MFMA sits in a branch.  kmap<1>
+        // gathers: element e of the lane reads cell a1[e] + qcell(e) + PX rr of the ring.
         f32x4 gacc[4];
         if (EPI == EPI_GATE) {
+            int a1[8];
+            kmap1_cells<PX>(z, g, cb, PCELLS, a1);
 #pragma unroll
             for (int pp = 0; pp < 2; ++pp) {   // output rows 2 pp and 2 pp + 1
                 uint32_t w8[8], lo[4], hi[4];
@@ -661,21 +653,10 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) acc[rr] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         float o1[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // COUT = 1: the output of lane group 0
-        if constexpr (COUT == 1) {
+        if constexpr (COUT == 1)
             conv16to1_plane(ring, cb, g, sl0, sl1, sl2, wa, o1);
-        } else if constexpr (CIN == 16) {
+        else
             conv16_plane(ring, cb, g, sl0, sl1, sl2, wa, acc);
-        } else {
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                uint16_t tmp[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) tmp[e] = ring[a1[e] + qcell(e) + PX * rr];
-                bf16x8 bv;
-                __builtin_memcpy(&bv, tmp, 16);
-                acc[rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[0], bv, acc[rr], 0, 0, 0);
-            }
-        }
         float gate4[4][4];
         if (EPI == EPI_GATE) {
 #pragma unroll
@@ -690,13 +671,12 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
             const long long c = (long long)gxo + (long long)nx * gy + plane * z;
             if (EPI == EPI_COMBINE) {
                 if (g == 0) {
-                    const float zi = invf[jcnt(epc[rr])] * er[rr] + sc * o1[rr];
+                    const float zi = invf[jcnt(S.epc[rr])] * S.er[rr] + sc * o1[rr];
                     cio.z[c] = zi;
-                    zsum[0] += (double)zi * (double)er[rr];
-                    zsum[1] += (double)zi * (double)erp[rr];
+                    zsum[0] += (double)zi * (double)S.er[rr];
+                    zsum[1] += (double)zi * (double)S.erp[rr];
                 }
             } else if (EPI == EPI_F32) {
-                static_assert(EPI != EPI_F32 || COUT == 1, "marching F32 epilogue: one channel");
                 if (g == 0) static_cast<float*>(out)[c] = o1[rr];
             } else {
                 float v[4] = {acc[rr][0], acc[rr][1], acc[rr][2], acc[rr][3]};
@@ -707,8 +687,28 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
                 *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + c * 16 + 4 * g) = pack4(v);
             }
         }
-        store_plane((z + 2) & 3);               // slot of plane z-2, last read for plane z-1
+        store_plane((z + 2) & 3, S);   // slot of plane z - 2, last read for plane z - 1
         __syncthreads();
+    };
+    // prologue: planes z0 - 1, z0, z0 + 1 into ring slots (z & 3); DEEP: plane z0 + 2 and
+    // the combine operands of plane z0 into registers
+    MPre A, B;
+    for (int pz = z0 - 1; pz <= z0 + 1; ++pz) {
+        load_plane(pz, A);
+        store_plane(pz & 3, A);
+    }
+    if (DEEP) {
+        load_plane(z0 + 2, A);
+        load_epi(z0, A);
+    }
+    __syncthreads();
+    if constexpr (DEEP) {
+        for (int z = z0; z < z1; z += 2) {
+            step(z, B, A);
+            if (z + 1 < z1) step(z + 1, A, B);
+        }
+    } else {
+        for (int z = z0; z < z1; ++z) step(z, A, A);
     }
     if (EPI == EPI_COMBINE) {
         block_reduce<2>(zsum, shr);
@@ -1321,9 +1321,9 @@ int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv,
         k_mfwd<false><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y,
                                          nullptr, 0, nullptr, sv);
         // the gated adjoint output goes to a1's buffer (the forward half keeps a1 in LDS)
-        k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
+        k_mconv<16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
                                                      CombineIO{});
-        k_mconv<16, 1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), n->out, nullptr, nullptr,
+        k_mconv<1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), n->out, nullptr, nullptr,
                                                    sv, CombineIO{});
         IBM_HIP(hipGetLastError());
         n->nx = nx;
@@ -1490,10 +1490,10 @@ int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* 
         k_mfwd<true><<<mb, 256, 0, s>>>(nx, ny, nz, mz, r, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart,
                                         nparts, n->scal, sv);
     }
-    k_mconv<16, 16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
+    k_mconv<16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
                                                  CombineIO{});
     const CombineIO cio{r, rp, c->pcode, n->scal, g.dx * g.dx, z, n->cpart};
-    k_mconv<16, 1, EPI_COMBINE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), nullptr, nullptr,
+    k_mconv<1, EPI_COMBINE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), nullptr, nullptr,
                                                    nullptr, sv, cio);
     k_relay<<<1, NT, 0, s>>>(n->cpart, mb, partials, nparts, zr_slot, zrp_slot, sv);
     IBM_HIP(hipGetLastError());
