@@ -209,12 +209,22 @@ __device__ inline void unpack4(uint2 w, float (&f)[4]) {
     f[2] = bf2f((uint16_t)(w.y & 0xFFFFu));
     f[3] = bf2f((uint16_t)(w.y >> 16));
 }
-__device__ inline uint2 pack4(const float (&f)[4]) {
-    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-    const bf16x4 h = {(__bf16)f[0], (__bf16)f[1], (__bf16)f[2], (__bf16)f[3]};
-    uint2 o;
-    __builtin_memcpy(&o, &h, 8);
-    return o;
+// two floats -> a BF16 pair (round to nearest even; a in the low half): one
+// v_cvt_pk_bf16_f32
+__device__ inline uint32_t pack2(float a, float b) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 h = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    uint32_t u;
+    __builtin_memcpy(&u, &h, 4);
+    return u;
+}
+__device__ inline uint2 pack4(const float (&f)[4]) { return make_uint2(pack2(f[0], f[1]), pack2(f[2], f[3])); }
+// a, b rounded to BF16 (kept as floats)
+__device__ inline void round2(float& a, float& b) {
+    const uint32_t u = pack2(a, b);
+    a = __uint_as_float(u << 16);
+    b = __uint_as_float(u & 0xFFFF0000u);
 }
 // gate nonlinearity hsig(v) = v/4 + 1/2 clamped to [0, 1]: one FMA and a clamp (the
 // logistic function it replaces cost two quarter-rate transcendentals per value and
@@ -660,9 +670,12 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
         float gate4[4][4];
         if (EPI == EPI_GATE) {
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
+            for (int rr = 0; rr < 4; ++rr) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) gate4[rr][r] = bf2f(f2bf(hsig(gacc[rr][r])));
+                for (int r = 0; r < 4; ++r) gate4[rr][r] = hsig(gacc[rr][r]);
+                round2(gate4[rr][0], gate4[rr][1]);
+                round2(gate4[rr][2], gate4[rr][3]);
+            }
         }
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
@@ -847,8 +860,10 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
     // written to the padding of the half planes).  Per tile: the lane's cell index in
     // the 36-wide x, g planes (at its (-1, -1) neighbour) and whether its cell is inside
     // the grid.
+    // The gate's FMA constant carries the zero outside the grid: hsig(v) = clamp(v/4 + c)
+    // with c = 1/2 inside and -1e30 outside, where the gate and so a1 become 0.
     int qb[NA1W];
-    unsigned inside = 0;
+    float gc[NA1W];
 #pragma unroll
     for (int i = 0; i < NA1W; ++i) {
         const int c = 16 * (wv + 4 * i) + j;
@@ -856,7 +871,7 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
         const int cx = cc % PX, cy = cc / PX;
         qb[i] = cx + QX * cy;
         const int gx = tx * CTX - 1 + cx, gy = ty * CTY - 1 + cy;
-        if (c < PCELLS && gx >= 0 && gx < nx && gy >= 0 && gy < ny) inside |= 1u << i;
+        gc[i] = (c < PCELLS && gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? 0.5f : -1e30f;
     }
     // a1 of plane p into its ring slot (zero outside the grid)
     auto make_a1 = [&](int p) {
@@ -886,12 +901,13 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
             __builtin_memcpy(&bg, bgw, 16);
             const f32x4 ax = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, bx, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
             const f32x4 ag = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wg, bg, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-            // zero outside the grid: a bit mask instead of a branch per value
-            const uint32_t keep = ((inside >> i) & 1u) ? 0xFFFFFFFFu : 0u;
-            float v[4];
+            float gt[4], v[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                v[r] = __uint_as_float(__float_as_uint(ax[r] * bf2f(f2bf(hsig(ag[r])))) & keep);
+            for (int r = 0; r < 4; ++r) gt[r] = fminf(fmaxf(fmaf(ag[r], 0.25f, gc[i]), 0.0f), 1.0f);   // hsig
+            round2(gt[0], gt[1]);
+            round2(gt[2], gt[3]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = ax[r] * gt[r];
             // lane (j, g): channels 4 g .. 4 g + 3 of cell 16 tt + j
             *reinterpret_cast<uint2*>(&A[((g >> 1) * HPC + 16 * tt + j) * 8 + 4 * (g & 1)]) = pack4(v);
         }
@@ -1295,12 +1311,41 @@ int net_gate(ibm_cnn* n, int nx, int ny, int nz, hipStream_t s) {
 
 // out = K^T K xr with the current gate; `keep` stores the pre-gate activations for
 // the backward pass
-// planes per slab: up to 32, fewer when the grid would give less than ~2048 blocks
+// Concurrent blocks of the marching kernels on the current device: three per CU (their
+// LDS, 45 to 52 KB per block, and registers, at most 168 VGPRs, are sized for that).
+int mconv_slots() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (!cached[dev]) {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+        cached[dev] = 3 * ncu;
+    }
+    return cached[dev];
+}
+
+// Planes per slab of the march.  A block costs (its planes + 3 prologue planes) plane
+// steps and all block slots run at about the same pace, so the march takes
+// (waves of blocks) x (planes per slab + 3); the slab count minimising that is taken
+// (the fewest slabs among equals).  256^3 on 256 CUs: 3 slabs of 86 planes, 768 blocks
+// in one wave (8 slabs of 32 planes took 2.67 waves).
 int mconv_planes(int nx, int ny, int nz) {
-    const int txy = ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY);
-    const int want_slabs = (2048 + txy - 1) / txy;
-    int mz = (nz + want_slabs - 1) / want_slabs;
-    return mz < 2 ? 2 : (mz > 32 ? 32 : mz);
+    const long long txy = (long long)((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY);
+    const long long slots = mconv_slots();
+    long long best = -1;
+    int best_mz = nz;
+    for (int S = 1; S <= nz; ++S) {
+        const int mz = (nz + S - 1) / S;
+        if ((nz + mz - 1) / mz != S) continue;   // the same slabs as a smaller count
+        const long long cost = ((txy * S + slots - 1) / slots) * (mz + 3);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_mz = mz;
+        }
+    }
+    return best_mz;
 }
 
 int mconv_blocks(int nx, int ny, int nz, int mz) {
