@@ -461,6 +461,7 @@ __device__ __forceinline__ void conv16to1_plane(const uint16_t* ring, int cb, in
     const uint16_t* bx = ring + (hb + cb + 2 * h) * 8 + sl1 * PLANE;       // dx = -1 | +1
     const uint16_t* bc = ring + (hb + cb) * 8 + sl1 * PLANE;               // centre
     f32x4 d[6];
+    __builtin_amdgcn_iglp_opt(0);   // interleave the B reads with the MFMAs (measured: helps here only)
 #pragma unroll
     for (int ii = 0; ii < 6; ++ii) d[ii] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
