@@ -262,7 +262,8 @@ def train_network(args, ibm, torch):
     from paper_2002_06206_amd import inputs, train
     t0 = time.perf_counter()
     # 20 windows x 100 steps, every step from the third on: 1,960 (b, p) pairs
-    data = train.build_dataset(train.TRAIN_SEEDS[:args.train_windows], 64, steps=100, every=1)
+    data = train.build_dataset(train.TRAIN_SEEDS[:args.train_windows], 64, steps=100, every=1,
+                               depths=tuple(int(k) for k in args.train_depths.split(",")))
     held = train.build_dataset(train.EVAL_SEEDS, 64, steps=24, every=3)
     t1 = time.perf_counter()
     net = ibm.Network(64 ** 3, inputs.cnn_init_weights(0))
@@ -276,6 +277,7 @@ def train_network(args, ibm, torch):
     torch.cuda.synchronize()
     info = {"pairs": sum(len(p) for _, p in data), "data_s": round(t1 - t0, 2),
             "train_s": round(time.perf_counter() - t1, 2), "iters": args.train_iters,
+            "depths": args.train_depths,
             "heldout_loss_before": round(before, 4), "heldout_loss_after": round(after, 4)}
     return w, info
 
@@ -300,6 +302,8 @@ def main():
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--train-lr", type=float, default=2e-3)
     ap.add_argument("--train-windows", type=int, default=20, help="64^3 training windows (98 pairs each)")
+    ap.add_argument("--train-depths", default="0,32",
+                    help="Krylov depths of the training pairs, cycled (0: the step's (b, p) itself)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

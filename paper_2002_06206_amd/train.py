@@ -21,11 +21,15 @@ TRAIN_SEEDS = tuple(range(101, 121))   # 20 windows
 EVAL_SEEDS = (201, 202)
 
 
-def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: float = 1e-8, first: int = 2):
+def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: float = 1e-8, first: int = 2,
+                   depths=(0,)):
     """Runs the plain FP64 solver for `steps` CFL-0.3 steps and keeps (b, p) of every
     `every`-th step from step `first` on (b = the compatible Poisson right-hand side,
-    p = its solution).  Returns the solver (it owns the stencil the pairs belong to)
-    and the pairs."""
+    p = its solution).  With depths, the i-th kept pair is taken at Krylov depth
+    k = depths[i % len(depths)]: x_k = k Jacobi-PCG iterates from zero on L x = b and
+    the pair (b - L x_k, p - x_k), which satisfies the same equation and carries the
+    error a Krylov method still has to remove after k iterations.  Returns the solver
+    (it owns the stencil the pairs belong to) and the pairs."""
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
     blocked, _ = s.tag(case.tri, want_theta=False)
     s.build(blocked, None, case.deadend)
@@ -41,14 +45,21 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
         if k >= first and (k - first) % every == 0:
             b = s.rhs()
             if float(torch.linalg.vector_norm(b)) > 0.0:
-                pairs.append((b, st["p"].clone()))
+                p = st["p"].clone()
+                depth = depths[len(pairs) % len(depths)]
+                if depth > 0:
+                    x = torch.zeros_like(b)
+                    s.poisson(b, x, tol=1e-300, max_iter=depth, kind=ibm.SOLVER_PCG_JACOBI)
+                    b, p = b - s.laplacian(x), p - x
+                pairs.append((b, p))
     return s, pairs
 
 
-def build_dataset(seeds, n: int = 64, steps: int = 24, every: int = 3):
+def build_dataset(seeds, n: int = 64, steps: int = 24, every: int = 3, depths=(0,)):
     data = []
     for seed in seeds:
-        s, pairs = generate_pairs(inputs.case_ellipsoid_window(seed, n), steps, every, first=min(2, steps - 1))
+        s, pairs = generate_pairs(inputs.case_ellipsoid_window(seed, n), steps, every, first=min(2, steps - 1),
+                                  depths=depths)
         if pairs:
             data.append((s, pairs))
     return data
