@@ -266,6 +266,30 @@ def test_fcg_cnn_without_network_is_an_error():
     s.close()
 
 
+def test_training_pairs_at_krylov_depth_solve_the_pressure_equation():
+    """A training pair taken at Krylov depth k is (b - L x_k, p - x_k) with x_k the k-th
+    Jacobi-PCG iterate from zero: it must satisfy L p' = b' to the accuracy of the
+    step's solve (tol 1e-8 relative) like a depth-0 pair, and differ from the step's
+    right-hand side."""
+    from paper_2002_06206_amd import train
+    print("case cnn depth pairs", flush=True)
+    case = inputs.case_ellipsoid_window(101, 32)
+    s0, p0 = train.generate_pairs(case, steps=6, every=1, first=2, depths=(0,))
+    s1, p1 = train.generate_pairs(case, steps=6, every=1, first=2, depths=(0, 8))
+    assert len(p0) == len(p1) == 4
+    for s, pairs in ((s0, p0), (s1, p1)):
+        for b, p in pairs:
+            e = float(torch.linalg.vector_norm(s.laplacian(p) - b) / torch.linalg.vector_norm(b))
+            assert e < 1e-6, e
+    # depth 0 pairs agree (same steps); depth 8 pairs carry the residual after 8 iterates
+    assert torch.equal(p0[0][0], p1[0][0]) and torch.equal(p0[2][0], p1[2][0])
+    r = float(torch.linalg.vector_norm(p1[1][0]) / torch.linalg.vector_norm(p0[1][0]))
+    print("depth-8 residual / right-hand side %.3f" % r, flush=True)
+    assert 0.0 < r < 1.0
+    s0.close()
+    s1.close()
+
+
 def test_trained_preconditioner_gains_over_jacobi():
     """What the trained network gains: it is trained on the GPU (library kernels, Adam) on
     (b, p) pairs of the plain FP64 solver from seeded 48^3 windows of the ellipsoid field
