@@ -200,6 +200,26 @@ int ibm_get_rhs(ibm_ctx* ctx, double* out_dev, void* stream);
 int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const void* nut_dev, double nu,
                const double* wall_dev, double out_host[6], void* stream);
 
+/* Near-field surface pressure and pressure force by Shepard interpolation (eq. (force)).
+ * At every vertex X of a triangle (unit normal n from the right-handed vertex order)
+ * the cell-centre pressure is averaged with weights 1/|X - x_k|^2 over the eight cell
+ * centres x_k spanning the dual cell that contains X, separately for the points in
+ * front (n . (x_k - X) > 0) and behind (< 0); points in the triangle's plane and
+ * outside the grid are left out.  A triangle's front / back value is the mean over
+ * its vertices that have one on that side; its force is A n (p_back - p_front), a side
+ * without points contributing nothing.  The thin-plate filter of eq. (force_filter)
+ * is not applied.
+ *   tri_dev   ntri x 3 vertices x 3 doubles (device; the layout ibm_tag_geometry takes)
+ *   p_dev     cell pressure (device, FP64, the context's grid)
+ *   side_dev  optional (device): ntri x 2 doubles, front and back pressure per
+ *             triangle (NaN for a side without points, and for zero-area triangles)
+ *   force_host[3]  the pressure force summed over the triangles (per-block partial
+ *             sums in block order: deterministic).
+ * Needs built stencils (for the grid).  Synchronises the stream.  Returns
+ * IBM_ERR_ARG for ntri < 0 or null pointers. */
+int ibm_shepard_force(ibm_ctx* ctx, const double* tri_dev, int64_t ntri, const double* p_dev, double* side_dev,
+                      double force_host[3], void* stream);
+
 /* ---- Learned preconditioner (an extension layered on the pressure solve of
  * eq. (poisson); the paper itself uses plain Krylov solves).
  *

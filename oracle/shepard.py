@@ -34,10 +34,15 @@ from . import flow
 
 def triangle_frames(tri: np.ndarray):
     """Unit normals (right-handed vertex order) and areas of triangles (ntri, 3, 3);
-    degenerate triangles get normal 0 and area 0."""
+    degenerate triangles get normal 0 and area 0 (non-finite ones NaN).  Sums are
+    written out left to right (one fixed FP64 operation order)."""
     tri = np.asarray(tri, dtype=np.float64)
-    c = np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0])
-    two_a = np.sqrt(np.sum(c * c, axis=1))
+    e1 = tri[:, 1] - tri[:, 0]
+    e2 = tri[:, 2] - tri[:, 0]
+    c = np.stack([e1[:, 1] * e2[:, 2] - e1[:, 2] * e2[:, 1],
+                  e1[:, 2] * e2[:, 0] - e1[:, 0] * e2[:, 2],
+                  e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]], axis=1)
+    two_a = np.sqrt(c[:, 0] * c[:, 0] + c[:, 1] * c[:, 1] + c[:, 2] * c[:, 2])
     n = np.zeros_like(c)
     ok = two_a > 0.0
     n[ok] = c[ok] / two_a[ok, None]
@@ -49,7 +54,11 @@ def vertex_values(g: flow.Grid, p: np.ndarray, X: np.ndarray, n: np.ndarray):
     for a side without points."""
     nz, ny, nx = g.shape
     o = np.asarray(g.origin, dtype=np.float64)
-    base = np.floor((X - o) / g.dx - 0.5).astype(np.int64)
+    fb = np.floor((X - o) / g.dx - 0.5)
+    lim = np.array([nx, ny, nz], dtype=np.float64) + 1.0
+    if not np.all((fb >= -2.0) & (fb <= lim)):
+        return None, None   # dual cell wholly outside the grid (or a non-finite X)
+    base = fb.astype(np.int64)
     num = {1: 0.0, -1: 0.0}
     den = {1: 0.0, -1: 0.0}
     for c in range(2):
@@ -59,11 +68,12 @@ def vertex_values(g: flow.Grid, p: np.ndarray, X: np.ndarray, n: np.ndarray):
                 if not (0 <= i < nx and 0 <= j < ny and 0 <= k < nz):
                     continue
                 x = o + (np.array([i, j, k], dtype=np.float64) + 0.5) * g.dx
-                s = float(np.dot(n, x - X))
+                r = x - X
+                s = float(n[0] * r[0] + n[1] * r[1] + n[2] * r[2])
                 if s == 0.0:
                     continue
                 side = 1 if s > 0.0 else -1
-                d2 = float(np.sum((X - x) ** 2))
+                d2 = float(r[0] * r[0] + r[1] * r[1] + r[2] * r[2])
                 num[side] += float(p[k, j, i]) / d2
                 den[side] += 1.0 / d2
     out = []
@@ -80,7 +90,7 @@ def surface_pressure(g: flow.Grid, p: np.ndarray, tri: np.ndarray):
     side = np.full((len(tri), 2), np.nan)
     force = np.zeros(3)
     for t in range(len(tri)):
-        if area[t] == 0.0:
+        if not (area[t] > 0.0 and np.isfinite(area[t])):   # degenerate, overflowing or non-finite
             continue
         vals = [vertex_values(g, p, tri[t, v], n[t]) for v in range(3)]
         for s in range(2):

@@ -20,6 +20,7 @@ SOURCES = [
     ("step.hip", []),
     ("poisson.hip", []),
     ("cnn.hip", []),
+    ("shepard.hip", ["-ffp-contract=off"]),
     ("api.hip", []),
 ]
 

@@ -320,6 +320,13 @@ int ibm_forces(ibm_ctx* c, void* const u[3], const double* p, const void* nut, d
     return forces_run(c, u, p, nut, nu, wall, out, (hipStream_t)stream);
 }
 
+int ibm_shepard_force(ibm_ctx* c, const double* tri, int64_t ntri, const double* p, double* side, double force[3],
+                      void* stream) {
+    if (int rc = need_stencil(c)) return rc;
+    if (ntri < 0 || (ntri > 0 && !tri) || !p || !force) return bad("ibm_shepard_force: bad arguments");
+    return shepard_run(c, tri, ntri, p, side, force, (hipStream_t)stream);
+}
+
 int ibm_timing_enable(ibm_ctx* c, int32_t on) {
     if (!c) return bad("null context");
     if (int rc = check_device(c)) return rc;

@@ -254,6 +254,8 @@ inline void launch_timed(ibm_ctx* c, int k, F kern, int grid, hipStream_t s, Arg
 void timing_begin(ibm_ctx* c, int k, hipStream_t s);
 void timing_end(ibm_ctx* c, int k, hipStream_t s);
 void timing_collect(ibm_ctx* c);
+int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, double* side, double* force,
+                hipStream_t s);
 int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
                double* out, hipStream_t s);
 }  // namespace ibm

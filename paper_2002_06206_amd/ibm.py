@@ -83,6 +83,7 @@ def _load():
         "ibm_get_nut": ([vp, vp, vp], ctypes.c_int),
         "ibm_get_rhs": ([vp, vp, vp], ctypes.c_int),
         "ibm_forces": ([vp, P3, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
+        "ibm_shepard_force": ([vp, vp, ctypes.c_int64, vp, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
         "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
         "ibm_timing_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
         "ibm_set_progress": ([vp, PROGRESS_FN, vp], ctypes.c_int),
@@ -108,7 +109,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "ibm_build_stencils",
             "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
-            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_timing_enable", "ibm_timing_read", "ibm_set_progress",
+            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_shepard_force", "ibm_timing_enable", "ibm_timing_read",
+            "ibm_set_progress",
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
             "ibm_ctx_set_preconditioner")
@@ -208,6 +210,16 @@ def ibm_forces(ctx, u, p, nu, nut=None, wall=None):
     out = (ctypes.c_double * 6)()
     _check(_lib.ibm_forces(ctx, _p3(u), _ptr(p), _ptr(nut), float(nu), _ptr(wall), out, _stream()), "ibm_forces")
     return list(out[:3]), list(out[3:])
+
+
+def ibm_shepard_force(ctx, tri, p, side=None):
+    """Near-field pressure force (eq. (force)) of triangles tri (ntri, 3, 3, FP64,
+    device) on the cell pressure p; fills side (ntri, 2) when given.  Returns the force
+    as three floats."""
+    out = (ctypes.c_double * 3)()
+    ntri = int(tri.shape[0]) if tri is not None else 0
+    _check(_lib.ibm_shepard_force(ctx, _ptr(tri), ntri, _ptr(p), _ptr(side), out, _stream()), "ibm_shepard_force")
+    return list(out)
 
 
 def ibm_timing_enable(ctx, on=True):
@@ -372,6 +384,9 @@ class Solver:
 
     def forces(self, st, nu, wall=None):
         return ibm_forces(self.ctx, st["u"], st["p"], nu, None, wall)
+
+    def shepard_force(self, tri, p, side=None):
+        return ibm_shepard_force(self.ctx, tri, p, side)
 
 
 class Network:

@@ -1,0 +1,152 @@
+"""GPU parity of the near-field surface force (eq. (force), Shepard interpolation with
+the front/back split) against oracle/shepard.py through the C ABI.
+
+The kernel takes the oracle's FP64 operations in the same order without fused
+multiply-adds, so every triangle's front and back value (and each point's side) is
+compared bit for bit.  The total force is summed in another order (per-block
+partials): compared to 1e-12 of the sum of the magnitudes of its terms."""
+import numpy as np
+import pytest
+
+from oracle import flow, shepard
+from paper_2002_06206_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2002_06206_amd import ibm
+else:  # collected on CPU machines, skipped by the marker filter
+    ibm = None
+
+
+def _solver(case, geometry=True):
+    s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
+    if geometry:
+        blocked, theta = s.tag(case.tri)
+        s.build(blocked, theta, case.deadend)
+    else:
+        shape = (case.n[2], case.n[1], case.n[0])
+        s.build(torch.zeros(shape, dtype=torch.uint8, device="cuda"),
+                torch.zeros(shape + (6,), dtype=torch.float64, device="cuda"))
+    return s
+
+
+def _grid(case):
+    return flow.Grid(case.n, case.dx, case.origin, case.bc, case.u_in)
+
+
+def _same(a, b):
+    """Bit-equal arrays, NaN where the other has NaN."""
+    a, b = np.asarray(a), np.asarray(b)
+    return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
+
+
+def _gpu(s, tri, p):
+    t = torch.from_numpy(np.ascontiguousarray(tri, dtype=np.float64)).cuda()
+    side = torch.empty((len(tri), 2), dtype=torch.float64, device="cuda")
+    f = s.shepard_force(t, p, side)
+    return side.cpu().numpy(), np.array(f)
+
+
+def _force_scale(tri, side):
+    n, area = shepard.triangle_frames(tri)
+    mag = np.nan_to_num(np.abs(side[:, 0])) + np.nan_to_num(np.abs(side[:, 1]))
+    return float(np.sum(np.nan_to_num(area) * mag)) + 1e-300
+
+
+def test_sphere32_after_two_steps_bit_exact():
+    case = inputs.case_sphere32(0)
+    print("case shepard sphere32", len(case.tri), flush=True)
+    s = _solver(case)
+    st = s.new_state(case.u_in)
+    for k in range(2):
+        rc, _ = s.step(st, ibm.step_params(case.dt, case.nu, csm=case.csm, step=k, tol=1e-10))
+        assert rc == 0
+    p = st["p"]
+    side, force = _gpu(s, case.tri, p)
+    so, fo = shepard.surface_pressure(_grid(case), p.cpu().numpy(), case.tri)
+    assert _same(side, so)
+    assert np.max(np.abs(force - fo)) <= 1e-12 * _force_scale(case.tri, so)
+    assert np.any(np.isfinite(side[:, 0])) and np.max(np.abs(fo)) > 0.0
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["dirty_sphere128", "ellipsoids256"])
+def test_full_size_meshes_sampled_bit_exact(name):
+    case = getattr(inputs, "case_" + name)(0)
+    print("case shepard", name, len(case.tri), flush=True)
+    s = _solver(case)
+    rng = np.random.default_rng(31)
+    p_np = rng.standard_normal((case.n[2], case.n[1], case.n[0]))
+    p = torch.from_numpy(p_np).cuda()
+    side, force = _gpu(s, case.tri, p)          # the whole mesh in one launch
+    idx = np.sort(rng.choice(len(case.tri), 1500, replace=False))
+    so, _ = shepard.surface_pressure(_grid(case), p_np, case.tri[idx])
+    assert _same(side[idx], so)
+    # the sampled triangles alone: force total against the oracle's
+    side_s, force_s = _gpu(s, case.tri[idx], p)
+    _, fo = shepard.surface_pressure(_grid(case), p_np, case.tri[idx])
+    assert _same(side_s, so)
+    assert np.max(np.abs(force_s - fo)) <= 1e-12 * _force_scale(case.tri[idx], so)
+    assert np.all(np.isfinite(force))
+    s.close()
+
+
+def _plate_case():
+    return inputs.Case("plate_box", (6, 6, 6), 1.0, (0.0, 0.0, 0.0), (flow.SLIP,) * 6, (0.0, 0.0, 0.0),
+                       np.zeros((0, 3, 3)), nu=0.01, dt=0.1, steps=1, csm=False)
+
+
+def test_closed_forms_on_the_device():
+    # the oracle's closed forms through the C ABI: a two-sided plate in z = 3 with
+    # p = +1 / -1 on its sides (force -2 A e_z for either orientation) and a closed box
+    # [1, 3]^3 with p = c_in inside and c_out outside (front c_out, back
+    # (c_in + 3 c_out)/4, zero net force)
+    case = _plate_case()
+    s = _solver(case, geometry=False)
+    zc = (np.arange(6) + 0.5)[:, None, None] * np.ones((6, 6, 6))
+    p = torch.from_numpy(np.where(zc > 3.0, 1.0, -1.0)).cuda()
+    a, b, c, d = (1.25, 1.25, 3.0), (4.5, 1.25, 3.0), (4.5, 4.5, 3.0), (1.25, 4.5, 3.0)
+    for tri, sgn in ((np.array([[a, b, c], [a, c, d]]), 1.0), (np.array([[a, c, b], [a, d, c]]), -1.0)):
+        side, force = _gpu(s, tri, p)
+        assert np.all(side[:, 0] == sgn) and np.all(side[:, 1] == -sgn)
+        assert np.max(np.abs(force - [0.0, 0.0, -2.0 * 3.25 ** 2])) < 1e-12
+    box = []
+    v = lambda i, j, k: tuple(3.0 if q else 1.0 for q in (i, j, k))  # noqa: E731
+    for f4 in ([v(0, 0, 0), v(0, 1, 0), v(1, 1, 0), v(1, 0, 0)], [v(0, 0, 1), v(1, 0, 1), v(1, 1, 1), v(0, 1, 1)],
+               [v(0, 0, 0), v(1, 0, 0), v(1, 0, 1), v(0, 0, 1)], [v(0, 1, 0), v(0, 1, 1), v(1, 1, 1), v(1, 1, 0)],
+               [v(0, 0, 0), v(0, 0, 1), v(0, 1, 1), v(0, 1, 0)], [v(1, 0, 0), v(1, 1, 0), v(1, 1, 1), v(1, 0, 1)]):
+        box += [[f4[0], f4[1], f4[2]], [f4[0], f4[2], f4[3]]]
+    pb = np.full((6, 6, 6), -0.75)
+    pb[1:3, 1:3, 1:3] = 2.5
+    side, force = _gpu(s, np.array(box), torch.from_numpy(pb).cuda())
+    np.testing.assert_allclose(side[:, 0], -0.75, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(side[:, 1], (2.5 + 3 * -0.75) / 4, rtol=0, atol=1e-14)
+    assert _same(side, shepard.surface_pressure(_grid(case), pb, np.array(box))[0])
+    assert np.max(np.abs(force)) < 1e-12
+    s.close()
+
+
+def test_edge_cases():
+    case = _plate_case()
+    s = _solver(case, geometry=False)
+    p = torch.from_numpy(np.random.default_rng(5).standard_normal((6, 6, 6))).cuda()
+    empty = torch.empty((0, 3, 3), dtype=torch.float64, device="cuda")
+    assert s.shepard_force(empty, p) == [0.0, 0.0, 0.0]
+    tri = np.array([
+        [[1.0, 1.0, 1.0], [2.0, 2.0, 2.0], [3.0, 3.0, 3.0]],          # zero area
+        [[np.nan, 1.0, 1.0], [2.0, 1.0, 1.0], [2.0, 2.0, 1.0]],       # non-finite
+        [[1e300, 1e300, 1e300], [2e300, 1e300, 1e300], [1e300, 2e300, 1e300]],   # far outside
+        [[-50.0, -50.0, 2.0], [-40.0, -50.0, 2.0], [-50.0, -40.0, 2.0]],        # outside the grid
+        [[1.2, 1.3, 2.2], [3.7, 1.1, 2.4], [2.2, 3.9, 2.9]],          # an ordinary one
+    ])
+    side, force = _gpu(s, tri, p)
+    so, fo = shepard.surface_pressure(_grid(case), p.cpu().numpy(), tri)
+    assert _same(side, so)
+    assert np.all(np.isnan(side[:4])) and np.all(np.isfinite(side[4]))
+    assert np.max(np.abs(force - fo)) < 1e-12 * (1.0 + np.max(np.abs(fo)))
+    with pytest.raises(ibm.IBMError):
+        ibm._check(ibm._lib.ibm_shepard_force(s.ctx, None, -1, ibm._ptr(p), None, (ibm.ctypes.c_double * 3)(),
+                                              None), "ibm_shepard_force")
+    s.close()
