@@ -233,6 +233,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
                         "bytes_per_cell": bytes_tab[name], "avg_s": avg_s, "achieved_gbs": achieved,
                         "launches": tim["launches"][k_dom], "launches_with_work": real,
                         "sweeps_ms": {SWEEP_NAMES[k]: round(tim["ms"][k], 2) for k in range(3)}}}
+    if solver == args.solver:
+        out["surface_force"] = shepard_timing(case, s, st, torch)
     if solver == "mixed_learned":
         # slot 0: whole preconditioner applications (three marching MFMA kernels and the
         # relay of the dot products); slot 1: the fused FCG passes; slot 2: the dominant
@@ -253,6 +255,29 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     s.close()
     torch.cuda.synchronize()
     return out
+
+
+# near-field surface force (eq. (force)): per triangle 72 B of vertices read, 16 B of
+# front/back pressure written and 24 pressure gathers of 8 B (no reuse counted)
+SHEPARD_BYTES_PER_TRIANGLE = 72 + 16 + 24 * 8
+
+
+def shepard_timing(case, s, st, torch, calls=20):
+    """Times ibm_shepard_force on the workload's triangles and the final pressure of the
+    run: whole calls (kernel, block-partial sum, copy of the three doubles to the host;
+    each call synchronises), host clock."""
+    tri = torch.as_tensor(case.tri, dtype=torch.float64).cuda().contiguous()
+    side = torch.empty((tri.shape[0], 2), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        s.shepard_force(tri, st["p"], side)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        f = s.shepard_force(tri, st["p"], side)
+    per = (time.perf_counter() - t0) / calls
+    ntri = int(tri.shape[0])
+    return {"triangles": ntri, "us_per_call": round(per * 1e6, 2), "pressure_force": f,
+            "bytes_per_triangle": SHEPARD_BYTES_PER_TRIANGLE,
+            "achieved_gbs_per_call": round(SHEPARD_BYTES_PER_TRIANGLE * ntri / per / 1e9, 1)}
 
 
 def train_network(args, ibm, torch):
@@ -379,6 +404,7 @@ def main():
         "training": train_info,
         "roofline": roofline,
         "roofline_sweeps": roofline_sweeps,
+        "surface_force": head.get("surface_force"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
