@@ -11,8 +11,10 @@ numbered 0..5 = -x, +x, -y, +y, -z, +z (axis = dir // 2, sign = +1 for odd).
 Paper passages followed (Onishi & Tsubokura, arXiv:2002.06206):
   * fractional step, face velocity, Poisson for the face divergence:
     Sec. 2.1, eq. (crank-nicolson) / (correction) / (poisson), Rhie-Chow;
-    explicit Adams-Bashforth in place of Crank-Nicolson (the paper's own
-    verification scheme, Sec. 2.4; AB "represents the same system", Sec. 2.1);
+    explicit Adams-Bashforth (the paper's own verification scheme, Sec. 2.4;
+    AB "represents the same system", Sec. 2.1), and the Crank-Nicolson
+    advection-diffusion predictor of eq. (crank-nicolson) solved by BiCGStab
+    (Sec. 2.1) as the alternative scheme;
   * eddy viscosity and the coherent structure model: Sec. 2.3 (turbulence
     model), eqs. (Smagorinsky), (Q), (FCS), C1 = 1/20;
   * dummy cells, ghosts behind a grid-line crossing: Sec. 2.3.1;
@@ -438,6 +440,129 @@ def predictor(st, u, U, hprev, nut, nu, dt, body, step, wall, dt_prev=0.0):
     return us, H
 
 
+# ------------------------------------------------- Crank-Nicolson predictor
+
+def hom_neighbour(st: Stencil, q: np.ndarray, m: int, d: int) -> np.ndarray:
+    """Value of component m across face d as seen by the part of the momentum
+    right-hand side that is linear in q: the neighbour, the domain-face ghost with a
+    zero inflow velocity (inflow and the normal component at a slip face: -q;
+    otherwise q), and the eq. (q_axis) ghost with a zero wall velocity
+    (a_c q_c + a_o q_o).  The ghosts of `neighbour` are these plus terms that do not
+    depend on q."""
+    g = st.grid
+    k, s = d // 2, (1 if d % 2 else -1)
+    out = shifted(q, k, s)
+    bm = boundary_mask(g, d)
+    odd = g.bc[d] == INFLOW or (g.bc[d] == SLIP and m == k)
+    out = np.where(bm, -q if odd else q, out)
+    sel = st.cut_dir == d
+    if np.any(sel):
+        cells = st.cut_cell[sel]
+        qf = q.ravel()
+        qo = np.where(st.cut_opp[sel] >= 0, qf[np.maximum(st.cut_opp[sel], 0)], 0.0)
+        o = out.ravel().copy()
+        o[cells] = st.a_c[sel] * qf[cells] + st.a_o[sel] * qo
+        out = o.reshape(g.shape)
+    return out
+
+
+def momentum_operator(st: Stencil, q: np.ndarray, m: int, U: list, nut: np.ndarray, nu: float) -> np.ndarray:
+    """L_m q: the part of the momentum right-hand side of eq. (crank-nicolson) that is
+    linear in velocity component m, with the advecting face velocity frozen at U^n and
+    the eddy viscosity at its value from u^n:
+    L q = -(1/dx) sum_f s U_f (q + q_nb)/2 + (1/dx^2) sum_f (nu + nu_t,f)(q_nb - q),
+    q_nb from hom_neighbour.  The full right-hand side is H(u) = L u + (terms from the
+    wall and inflow velocities and the body force)."""
+    g = st.grid
+    out = np.zeros(g.shape)
+    for d in range(6):
+        s = 1 if d % 2 else -1
+        qn = hom_neighbour(st, q, m, d)
+        Uf = face_velocity(g, U, d)
+        out = out - s * Uf * (0.5 * (q + qn)) / g.dx + (nu + face_nut(st, nut, d)) * (qn - q) / (g.dx * g.dx)
+    return out
+
+
+def bicgstab(apply, b: np.ndarray, x0: np.ndarray, tol: float, max_iter: int):
+    """BiCGStab (van der Vorst, SIAM J. Sci. Stat. Comput. 13, 1992), unpreconditioned,
+    for A x = b with a nonsymmetric A (the solver the paper names for its implicit time
+    integration, Sec. 2.1).  Stops when ||r|| <= tol ||b|| at the start of an iteration,
+    or when ||s|| <= tol ||b|| halfway through one (x += alpha p only).  Returns
+    (x, iterations, status), status 'converged', 'max_iter' or 'breakdown'
+    (rho = 0, <r0, v> = 0 or omega = 0 with the residual not yet small)."""
+    bb = float(np.sum(b * b))
+    if bb == 0.0:
+        return np.zeros_like(b), 0, "converged"
+    tol2 = tol * tol * bb
+    x = x0.copy()
+    r = b - apply(x)
+    r0 = r.copy()
+    rho_old, alpha, omega = 1.0, 1.0, 1.0
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    for it in range(max_iter + 1):
+        if float(np.sum(r * r)) <= tol2:
+            return x, it, "converged"
+        if it == max_iter:
+            return x, it, "max_iter"
+        rho = float(np.sum(r0 * r))
+        if rho == 0.0:
+            return x, it, "breakdown"
+        beta = (rho / rho_old) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = apply(p)
+        r0v = float(np.sum(r0 * v))
+        if r0v == 0.0:
+            return x, it, "breakdown"
+        alpha = rho / r0v
+        s = r - alpha * v
+        if float(np.sum(s * s)) <= tol2:
+            return x + alpha * p, it + 1, "converged"
+        t = apply(s)
+        omega = float(np.sum(t * s)) / float(np.sum(t * t))
+        if omega == 0.0:
+            return x, it, "breakdown"
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rho_old = rho
+    raise AssertionError("unreachable")
+
+
+def cn_matrix_apply(st: Stencil, q: np.ndarray, m: int, U: list, nut: np.ndarray, nu: float, dt: float):
+    """(I - dt/2 L_m) q, with identity rows at dead-end cells (Reading R13)."""
+    a = q - 0.5 * dt * momentum_operator(st, q, m, U, nut, nu)
+    return np.where(st.deadend, q, a)
+
+
+def cn_predictor(st, u, U, nut, nu, dt, body, wall, tol, max_iter):
+    """Crank-Nicolson predictor of eq. (crank-nicolson): advection (by the frozen U^n)
+    and diffusion both taken half at u^n and half at u*, the wall, inflow and body
+    terms whole.  With H the full right-hand side and L its linear part
+    (momentum_operator), u* - u^n = dt [H(u^n) + L(u* - u^n)/2], so the increment
+    delta = u* - u^n solves (I - dt/2 L) delta = dt H^n, one system per component,
+    solved by BiCGStab from delta_0 = dt H^n (the explicit Euler increment).
+    Dead-end cells are pinned at their mean wall velocity (identity rows).
+    Returns (u*, H^n with zeros at dead-end cells, iterations per component)."""
+    H = momentum_rhs(st, u, U, nut, nu, body, wall)
+    dead = st.deadend
+    dv = dead_velocity(st, wall) if dead.any() else None
+    us, iters = [], []
+    for m in range(3):
+        b = dt * H[m]
+        if dv is not None:
+            b = np.where(dead, dv[m] - u[m], b)
+        delta, it, status = bicgstab(lambda q, m=m: cn_matrix_apply(st, q, m, U, nut, nu, dt), b, b, tol, max_iter)
+        if status != "converged":
+            raise RuntimeError(f"momentum solve of component {m}: {status} after {it} iterations")
+        v = u[m] + delta
+        if dv is not None:
+            v = np.where(dead, dv[m], v)
+            H[m] = np.where(dead, 0.0, H[m])
+        us.append(v)
+        iters.append(it)
+    return us, H, iters
+
+
 # ---------------------------------------------------------- Poisson / projection
 
 def face_predicted(st: Stencil, us: list, wall) -> list:
@@ -589,14 +714,25 @@ class StepParams:
     tol: float = 1e-10
     max_iter: int = 10000
     dt_prev: float = 0.0
+    scheme: str = "ab2"        # "ab2" (explicit) or "cn" (Crank-Nicolson + BiCGStab)
+    mom_tol: float = 1e-10     # cn: relative residual of each component's system
+    mom_max_iter: int = 200    # cn: BiCGStab iteration cap
 
 
 def step(st: Stencil, u, U, p, hprev, prm: StepParams, step_index: int, wall=None):
-    """One fractional step: CSM -> AB2 predictor -> face velocity + Poisson RHS ->
-    PCG -> gauge -> projection.  Returns (u, U, p, H, stats)."""
+    """One fractional step: CSM -> predictor (AB2, or Crank-Nicolson with BiCGStab) ->
+    face velocity + Poisson RHS -> PCG -> gauge -> projection.
+    Returns (u, U, p, H, stats)."""
     g = st.grid
     nut = csm_nut(st, u, prm.c1, wall) if prm.csm else np.zeros(g.shape)
-    us, H = predictor(st, u, U, hprev, nut, prm.nu, prm.dt, prm.body, step_index, wall, prm.dt_prev)
+    mom_iters = [0, 0, 0]
+    if prm.scheme == "cn":
+        us, H, mom_iters = cn_predictor(st, u, U, nut, prm.nu, prm.dt, prm.body, wall, prm.mom_tol,
+                                        prm.mom_max_iter)
+    elif prm.scheme == "ab2":
+        us, H = predictor(st, u, U, hprev, nut, prm.nu, prm.dt, prm.body, step_index, wall, prm.dt_prev)
+    else:
+        raise ValueError(prm.scheme)
     Us = face_predicted(st, us, wall)
     b = poisson_rhs(st, Us, prm.dt)
     pn, iters = pcg(st, b, p, prm.tol, prm.max_iter)
@@ -608,7 +744,7 @@ def step(st: Stencil, u, U, p, hprev, prm: StepParams, step_index: int, wall=Non
     stats = dict(iters=iters, rel_residual=float(np.sqrt(np.sum(res * res)) / bn) if bn > 0 else 0.0,
                  div_l2=float(np.sqrt(np.sum(div * div))), div_linf=float(np.max(np.abs(div))),
                  umax=float(max(np.max(np.abs(face_velocity(g, Un, d))) for d in range(6))),
-                 nut=nut, b=b)
+                 nut=nut, b=b, mom_iters=mom_iters)
     return un, Un, pn, H, stats
 
 
