@@ -47,6 +47,9 @@ enum {
     IBM_SOLVER_FCG_CNN = 1,    /* FP64 refinement around FP32 flexible CG, CNN precond.   */
     IBM_SOLVER_FCG_JACOBI = 2  /* FP64 refinement around FP32 flexible CG, Jacobi precond.*/
 };
+/* momentum predictor of ibm_step: explicit Adams-Bashforth, or Crank-Nicolson with
+ * BiCGStab (eq. (crank-nicolson), Sec. 2.1) */
+enum { IBM_SCHEME_AB2 = 0, IBM_SCHEME_CN = 1 };
 enum { IBM_OK = 0, IBM_NOT_CONVERGED = 1, IBM_ERR_ARG = -1, IBM_ERR_HIP = -2, IBM_ERR_OOM = -3,
        IBM_ERR_NAN = -4 };
 
@@ -83,10 +86,20 @@ typedef struct {
     int32_t force_stall;     /* test hook: 1 = treat the first sweep as stalled      */
 } ibm_solver_opts;
 
-/* One time step: AB2 momentum predictor (forward Euler when step == 0), coherent
- * structure model (Sec. 2.3) when csm_on, body force, Poisson, projection.
- * Variable-step AB2: u* = u + dt [(1 + r/2) H^n - (r/2) H^{n-1}], r = dt/dt_prev
- * (dt_prev <= 0 means dt_prev = dt, the constant-step 3/2, -1/2 weights). */
+/* One time step: momentum predictor, coherent structure model (Sec. 2.3) when csm_on,
+ * body force, Poisson, projection.
+ * scheme IBM_SCHEME_AB2: variable-step Adams-Bashforth,
+ *   u* = u + dt [(1 + r/2) H^n - (r/2) H^{n-1}], r = dt/dt_prev (dt_prev <= 0 means
+ *   dt_prev = dt, the constant-step 3/2, -1/2 weights); forward Euler when step == 0.
+ * scheme IBM_SCHEME_CN: Crank-Nicolson for advection (by the frozen face velocity U^n)
+ *   and diffusion (nu + the eddy viscosity of u^n) together, eq. (crank-nicolson):
+ *   with H the explicit right-hand side and L its part linear in u,
+ *   (I - dt/2 L) (u* - u^n) = dt H^n for each component, solved by unpreconditioned
+ *   BiCGStab from the explicit Euler increment until ||r|| <= mom_tol ||dt H^n||
+ *   (on IBM_MIXED contexts, where the vectors are FP32, mom_tol is raised to at least
+ *   1e-6).  Dead-end cells keep their mean wall velocity.  h_dev receives H^n.  The
+ *   first CN step of a context allocates its solver workspace: 8 vectors of 3 cell
+ *   fields of the context's cell type. */
 typedef struct {
     double dt;
     double dt_prev;         /* previous step's dt (<= 0: same as dt)                 */
@@ -96,6 +109,9 @@ typedef struct {
     int32_t step;           /* 0 = first step (forward Euler), else AB2              */
     double body_force[3];
     ibm_solver_opts poisson;
+    int32_t scheme;         /* IBM_SCHEME_AB2 or IBM_SCHEME_CN                       */
+    int32_t mom_max_iter;   /* CN: BiCGStab iteration cap (<= 0: 200)                */
+    double mom_tol;         /* CN: relative residual per component (<= 0: 1e-10)     */
 } ibm_step_params;
 
 typedef struct {
@@ -108,6 +124,8 @@ typedef struct {
     double div_l2;           /* ||div U^{n+1}||_2 over all cells (ibm_step only)     */
     double div_linf;         /* max |div U^{n+1}|                                    */
     double umax;             /* max |U| over all faces after the step (CFL control)  */
+    int32_t iters_momentum[3]; /* CN: BiCGStab iterations per component (else 0)     */
+    int32_t pad;
 } ibm_stats;
 
 typedef struct ibm_ctx ibm_ctx;
@@ -184,6 +202,30 @@ int ibm_poisson_solve(ibm_ctx* ctx, const double* b_dev, double* x_dev, const ib
 
 /* y = L x (the operator above), for tests. */
 int ibm_apply_laplacian(ibm_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
+
+/* Crank-Nicolson momentum operator (eq. (crank-nicolson)) for tests and callers with
+ * their own time loop: out = (I - dt/2 L) q for the three components, L the part of the
+ * momentum right-hand side linear in the velocity: flux-form central advection by the
+ * face velocities U_dev (as ibm_step's U) and diffusion with nu + the face eddy
+ * viscosity (mean of the two cells on open faces, the cell's own on closed ones);
+ * ghosts behind blocked faces a_c q_c + a_o q_o (eq. (q_axis) with a zero wall
+ * velocity), behind inflow faces and for the normal component at slip faces -q_c,
+ * otherwise q_c.  Dead-end rows are the identity.  q_dev, out_dev: 3 cell fields of the
+ * context's cell type (double for IBM_FP64, float for IBM_MIXED), out distinct from q;
+ * nut_dev: a cell field of that type, or NULL for zero eddy viscosity. */
+int ibm_momentum_apply(ibm_ctx* ctx, const void* const q_dev[3], double* const U_dev[3], const void* nut_dev,
+                       double nu, double dt, void* const out_dev[3], void* stream);
+
+/* Solves (I - dt/2 L) x = b (the operator of ibm_momentum_apply) for the three
+ * components by unpreconditioned BiCGStab (Sec. 2.1): x_dev holds the initial guess on
+ * entry and the solution on return; b_dev may equal x_dev.  Each component stops when
+ * ||b - A x|| <= tol ||b|| at the start of an iteration or halfway through one; a zero b
+ * gives x = 0.  iters_out (host, or NULL): iterations per component.  Returns
+ * IBM_NOT_CONVERGED at max_iter or on a breakdown (rho = 0, <r0, v> = 0, omega = 0),
+ * IBM_ERR_NAN on a non-finite residual.  Synchronises the stream. */
+int ibm_momentum_solve(ibm_ctx* ctx, const void* const b_dev[3], void* const x_dev[3], double* const U_dev[3],
+                       const void* nut_dev, double nu, double dt, double tol, int32_t max_iter,
+                       int32_t iters_out[3], void* stream);
 
 /* Copies of quantities from the last ibm_step: eddy viscosity (cell type) and the
  * compatible Poisson right-hand side b (double). */
@@ -298,6 +340,11 @@ int ibm_timing_enable(ibm_ctx* ctx, int32_t on);
 typedef void (*ibm_progress_fn)(void* user, int64_t iterations, double rr);
 int ibm_set_progress(ibm_ctx* ctx, ibm_progress_fn fn, void* user);
 int ibm_timing_read(ibm_ctx* ctx, double out[10], int32_t reset);
+/* One timed slot: out[0] = accumulated milliseconds, out[1] = launches; reset != 0 zeroes
+ * that slot.  Slots 0-2 as above, 3 = the near-field force kernel, 4-6 = the three
+ * BiCGStab passes of the Crank-Nicolson predictor (P: new direction and v = A p;
+ * S: t = A s; X: update of x and r). */
+int ibm_timing_slot(ibm_ctx* ctx, int32_t slot, double out[2], int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,7 @@ SOURCES = [
     ("poisson.hip", []),
     ("cnn.hip", []),
     ("shepard.hip", ["-ffp-contract=off"]),
+    ("momentum.hip", []),
     ("api.hip", []),
 ]
 

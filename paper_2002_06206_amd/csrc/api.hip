@@ -155,7 +155,7 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
 }
 
 static void free_events(ibm_ctx* c) {
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < TK_SLOTS_MAX; ++k) {
         if (!c->ev[k]) continue;
         for (int e = 0; e < 2 * c->ev_cap; ++e) (void)hipEventDestroy(c->ev[k][e]);
         delete[] c->ev[k];
@@ -168,6 +168,7 @@ int ibm_destroy(ibm_ctx* c) {
     if (!c) return IBM_OK;
     (void)hipDeviceSynchronize();
     free_events(c);
+    cn_release(c);
     void* ps[] = {c->tagmask, c->theta, c->mask, c->pcode, c->flags, c->label, c->cut_off, c->cut_cell, c->cut_dir,
                   c->cut_theta, c->a_ib, c->a_c, c->a_o, c->cut_opp, c->enc_cells, c->comp_start,
                   c->ustar[0], c->ustar[1], c->ustar[2], c->nut, c->b, c->bwork, c->r, c->d, c->q, c->zbuf, c->x64,
@@ -256,9 +257,19 @@ int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const 
         if (!u[a] || !U[a] || !h[a]) return bad("ibm_step: null field pointer");
     if (!(prm->dt > 0.0) || !(prm->nu >= 0.0) || prm->poisson.max_iter <= 0 || !(prm->poisson.tol > 0.0))
         return bad("ibm_step: need dt > 0, nu >= 0, tol > 0, max_iter > 0");
+    if (prm->scheme != IBM_SCHEME_AB2 && prm->scheme != IBM_SCHEME_CN) return bad("ibm_step: unknown scheme");
     hipStream_t s = (hipStream_t)stream;
+    const bool cn = prm->scheme == IBM_SCHEME_CN;
+    if (cn) {
+        if (int rc = cn_prepare(c)) return rc;
+    }
     int rc = step_predict(c, u, U, h, wall, prm, s);
     if (rc) return rc;
+    int mom_iters[3] = {0, 0, 0};
+    if (cn) {
+        rc = cn_predict(c, u, U, prm, mom_iters, s);
+        if (rc) return rc;
+    }
     rc = step_rhs(c, U, wall, prm->dt, s);
     if (rc) return rc;
     ibm_stats local;
@@ -269,6 +280,7 @@ int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const 
     if (rc) return rc;
     if (st) {
         *st = local;
+        for (int m = 0; m < 3; ++m) st->iters_momentum[m] = mom_iters[m];
         rc = divergence_norms(c, U, &st->div_l2, &st->div_linf, &st->umax, s);
         if (rc) return rc;
     }
@@ -297,6 +309,34 @@ int ibm_apply_laplacian(ibm_ctx* c, const double* x, double* y, void* stream) {
     if (int rc = need_stencil(c)) return rc;
     if (!x || !y) return bad("ibm_apply_laplacian: null argument");
     return laplacian_run(c, x, y, (hipStream_t)stream);
+}
+
+int ibm_momentum_apply(ibm_ctx* c, const void* const q[3], double* const U[3], const void* nut, double nu,
+                       double dt, void* const out[3], void* stream) {
+    if (int rc = need_stencil(c)) return rc;
+    if (!q || !U || !out) return bad("ibm_momentum_apply: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (!q[a] || !U[a] || !out[a]) return bad("ibm_momentum_apply: null field pointer");
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (out[a] == q[b]) return bad("ibm_momentum_apply: out must not alias q");
+    if (!(dt >= 0.0) || !(nu >= 0.0)) return bad("ibm_momentum_apply: need dt >= 0 and nu >= 0");
+    return cn_apply(c, q, U, nut, nu, dt, out, (hipStream_t)stream);
+}
+
+int ibm_momentum_solve(ibm_ctx* c, const void* const b[3], void* const x[3], double* const U[3], const void* nut,
+                       double nu, double dt, double tol, int32_t max_iter, int32_t iters_out[3], void* stream) {
+    if (int rc = need_stencil(c)) return rc;
+    if (!b || !x || !U) return bad("ibm_momentum_solve: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (!b[a] || !x[a] || !U[a]) return bad("ibm_momentum_solve: null field pointer");
+    if (!(dt >= 0.0) || !(nu >= 0.0) || !(tol >= 0.0) || max_iter <= 0)
+        return bad("ibm_momentum_solve: need dt >= 0, nu >= 0, tol >= 0, max_iter > 0");
+    int it[3] = {0, 0, 0};
+    const int rc = cn_solve(c, b, x, U, nut, nu, dt, tol, max_iter, it, (hipStream_t)stream);
+    if (iters_out)
+        for (int a = 0; a < 3; ++a) iters_out[a] = it[a];
+    return rc;
 }
 
 int ibm_get_nut(ibm_ctx* c, void* out, void* stream) {
@@ -332,7 +372,7 @@ int ibm_timing_enable(ibm_ctx* c, int32_t on) {
     if (int rc = check_device(c)) return rc;
     if (on && c->ev_cap == 0) {
         const int cap = 8192;
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < TK_SLOTS_MAX; ++k) {
             c->ev[k] = new (std::nothrow) hipEvent_t[2 * cap];
             if (!c->ev[k]) return bad("ibm_timing_enable: host allocation failed");
             for (int e = 0; e < 2 * cap; ++e) IBM_HIP(hipEventCreate(&c->ev[k][e]));
@@ -340,7 +380,7 @@ int ibm_timing_enable(ibm_ctx* c, int32_t on) {
         c->ev_cap = cap;
     }
     c->timing_on = on ? 1 : 0;
-    for (int k = 0; k < 4; ++k) c->ev_used[k] = 0;
+    for (int k = 0; k < TK_SLOTS_MAX; ++k) c->ev_used[k] = 0;
     return IBM_OK;
 }
 
@@ -348,6 +388,18 @@ int ibm_set_progress(ibm_ctx* c, ibm_progress_fn fn, void* user) {
     if (!c) return bad("null context");
     c->progress = fn;
     c->progress_user = user;
+    return IBM_OK;
+}
+
+int ibm_timing_slot(ibm_ctx* c, int32_t slot, double out[2], int32_t reset) {
+    if (!c || !out) return bad("ibm_timing_slot: null argument");
+    if (slot < 0 || slot >= TK_SLOTS_MAX) return bad("ibm_timing_slot: slot out of range");
+    out[0] = c->t_ms[slot];
+    out[1] = (double)c->t_launches[slot];
+    if (reset) {
+        c->t_ms[slot] = 0.0;
+        c->t_launches[slot] = 0;
+    }
     return IBM_OK;
 }
 
@@ -362,7 +414,7 @@ int ibm_timing_read(ibm_ctx* c, double out[10], int32_t reset) {
     out[8] = (double)c->ncut;
     out[9] = (double)c->precision;
     if (reset) {
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < TK_SLOTS_MAX; ++k) {
             c->t_ms[k] = 0.0;
             c->t_launches[k] = 0;
         }

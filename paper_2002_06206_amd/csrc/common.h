@@ -41,6 +41,24 @@ struct Solver {                 // device-resident scalars of the Krylov loops
     int pad;
 };
 
+// Device-resident state of the batched BiCGStab of the Crank-Nicolson predictor (one
+// system per velocity component).  Scalars of iteration it live in entry [it & 1]:
+// a pass reads the previous iteration's entry while its block 0 writes the current one.
+struct CnState {
+    double tol2[3];             // tol^2 <b,b> per component
+    double bb[3];               // <b,b>
+    double rho[2][3];           // <r0, r_it>
+    double alpha[2][3];
+    double omega[2][3];
+    int active[2][3];           // component still iterating in iteration it
+    int sconv[2][3];            // converged at the half step of iteration it (||s|| small)
+    int iters[3];               // iterations made, set when a component stops
+    int status;                 // CN_* below
+    int done;                   // every component stopped: later passes return at once
+};
+enum { CN_RUNNING = 0, CN_CONVERGED = 1, CN_MAXITER = 2, CN_BREAKDOWN = 3, CN_NAN = 4 };
+constexpr int TK_SLOTS_MAX = 7;  // timed kernel slots (the TK_* launch slots)
+
 }  // namespace ibm
 
 struct ibm_ctx {
@@ -104,11 +122,18 @@ struct ibm_ctx {
     // optional per-kernel event timing of the Krylov sweeps (ibm_timing_enable)
     int timing_on;
     int ev_cap;             // event pairs per timed kernel
-    int ev_used[4];
-    hipEvent_t* ev[4];      // 2 * ev_cap events per timed kernel
-    double t_ms[4];         // accumulated kernel time
-    long long t_launches[4];
+    int ev_used[ibm::TK_SLOTS_MAX];
+    hipEvent_t* ev[ibm::TK_SLOTS_MAX];  // 2 * ev_cap events per timed kernel
+    double t_ms[ibm::TK_SLOTS_MAX];     // accumulated kernel time
+    long long t_launches[ibm::TK_SLOTS_MAX];
     long long t_real_iters; // iterations that did work (the rest exit at once)
+    // Crank-Nicolson predictor workspace, allocated by its first use: eight vectors
+    // (x, r, r0, p twice, v twice, t) of three components of the cell type
+    void* cn_ws;
+    double* cn_part;        // 21 * MAX_BLOCKS partial sums
+    ibm::CnState* cn_state;
+    ibm::CnState* h_cn_state;  // pinned host mirror
+    int cn_last_iters;      // iterations of the previous momentum solve (batch sizing)
     // optional progress hook, called at the solver's host convergence polls
     ibm_progress_fn progress;
     void* progress_user;
@@ -129,6 +154,43 @@ int hip_fail(hipError_t e, const char* what);
 inline int grid_blocks(const Geo& g) {
     long long t = g.ntiles;
     return (int)(t < MAX_BLOCKS ? t : MAX_BLOCKS);
+}
+
+// ---------------------------------------------------------------- stencil view
+
+// Device pointers of the velocity stencil (cut list and coefficients of eq. (q_axis)).
+struct Sten {
+    const uint8_t* mask;
+    const uint32_t* cut_off;
+    const double* a_ib;
+    const double* a_c;
+    const double* a_o;
+    const int32_t* opp;
+    const uint16_t* flags;
+    int has_dead;
+};
+
+template <class T>
+struct V3 {
+    T* p[3];
+};
+template <class T>
+struct C3 {
+    const T* p[3];
+};
+
+inline Sten sten_of(const ibm_ctx* c) {
+    return Sten{c->mask, c->cut_off, c->a_ib, c->a_c, c->a_o, c->cut_opp, c->flags, c->has_dead};
+}
+
+// index of the cut of cell c in direction d (bit d of msk set)
+__device__ inline uint32_t cut_id(const Sten& st, long long c, uint8_t msk, int d) {
+    return st.cut_off[c] + (uint32_t)__builtin_popcount((unsigned)msk & ((1u << d) - 1u));
+}
+
+// dead-end cell (closed in all six directions by the filter of eq. (deadend_filter))
+__device__ inline bool dead_cell(const Sten& st, long long c, uint8_t msk) {
+    return st.has_dead && __builtin_popcount((unsigned)msk) >= 5 && ((st.flags[c] >> 14) & 1);
 }
 
 // ---------------------------------------------------------------- device helpers
@@ -238,7 +300,8 @@ int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s);
 // timing helpers (poisson.hip)
 // timed kernel slots: the two CG passes (or the preconditioner and the passes of the
 // learned solve), the dominant convolution of the learned preconditioner, spare
-enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3 };
+// (other), and the three BiCGStab passes of the Crank-Nicolson predictor
+enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3, TK_CN_P = 4, TK_CN_S = 5, TK_CN_X = 6 };
 // Launches kern<<<grid, NT, 0, s>>>(args...).  When timing slot k is on, the launch
 // carries HIP's dispatch-level start/stop events (hipExtLaunchKernelGGL), so the time
 // collected is the kernel's own, without the gaps between dispatches.
@@ -254,6 +317,14 @@ inline void launch_timed(ibm_ctx* c, int k, F kern, int grid, hipStream_t s, Arg
 void timing_begin(ibm_ctx* c, int k, hipStream_t s);
 void timing_end(ibm_ctx* c, int k, hipStream_t s);
 void timing_collect(ibm_ctx* c);
+// Crank-Nicolson predictor (momentum.hip)
+int cn_predict(ibm_ctx* c, void** u, double** U, const ibm_step_params* prm, int iters[3], hipStream_t s);
+int cn_apply(ibm_ctx* c, const void* const* q, double* const* U, const void* nut, double nu, double dt,
+             void* const* out, hipStream_t s);
+int cn_solve(ibm_ctx* c, const void* const* b, void* const* x, double* const* U, const void* nut, double nu,
+             double dt, double tol, int max_iter, int iters[3], hipStream_t s);
+int cn_prepare(ibm_ctx* c);
+void cn_release(ibm_ctx* c);
 int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, double* side, double* force,
                 hipStream_t s);
 int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,

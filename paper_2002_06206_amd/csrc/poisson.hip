@@ -1019,7 +1019,7 @@ void timing_end(ibm_ctx* c, int k, hipStream_t s) {
 
 void timing_collect(ibm_ctx* c) {
     if (!c->timing_on) return;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < TK_SLOTS_MAX; ++k) {
         for (int e = 0; e < c->ev_used[k]; ++e) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, c->ev[k][2 * e], c->ev[k][2 * e + 1]) == hipSuccess) {

@@ -13,35 +13,7 @@
 
 namespace ibm {
 
-struct Sten {
-    const uint8_t* mask;
-    const uint32_t* cut_off;
-    const double* a_ib;
-    const double* a_c;
-    const double* a_o;
-    const int32_t* opp;
-    const uint16_t* flags;
-    int has_dead;
-};
-
-template <class T>
-struct V3 {
-    T* p[3];
-};
-template <class T>
-struct C3 {
-    const T* p[3];
-};
-
 namespace {
-
-inline Sten sten_of(const ibm_ctx* c) {
-    return Sten{c->mask, c->cut_off, c->a_ib, c->a_c, c->a_o, c->cut_opp, c->flags, c->has_dead};
-}
-
-__device__ inline uint32_t cut_id(const Sten& st, long long c, uint8_t msk, int d) {
-    return st.cut_off[c] + (uint32_t)__builtin_popcount((unsigned)msk & ((1u << d) - 1u));
-}
 
 // eq. (q_axis) ghost of component m behind blocked face d of cell c
 template <class T>
@@ -122,11 +94,14 @@ __global__ void __launch_bounds__(NT) k_csm(Geo g, Sten st, C3<T> u, const doubl
 // u* = u + dt (3/2 H - 1/2 H_prev), forward Euler on the first step.  q_nb is the
 // eq. (q_axis) ghost behind blocked faces, which realises the direct forcing of
 // eq. (forcing_term).  Dead-end cells are frozen at their mean wall velocity.
+// With cn set (Crank-Nicolson, eq. (crank-nicolson)) the kernel writes instead the
+// right-hand side dt H of the increment system into rhs (dv - u at dead-end cells) and
+// u* only at dead-end cells (dv); H goes to hio as in the explicit form.
 template <class T>
 __global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<double> U, const T* nut, V3<T> hio,
                                                 V3<T> us, const double* wall, double dt, double w_now,
                                                 double w_prev, double nu, double bx, double by, double bz,
-                                                int first) {
+                                                int first, int cn, V3<T> rhs) {
     long long t0, t1;
     tile_range(g, t0, t1);
     const double body[3] = {bx, by, bz};
@@ -170,16 +145,23 @@ __global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<doub
                 h = h - s * Uf[d] * qf * idx + visc[d] * (nb[d] - qc) * idx2;
             }
             T v;
-            if (first) v = qc + (T)dt * h;
+            if (first || cn) v = qc + (T)dt * h;
             else v = qc + (T)dt * ((T)w_now * h - (T)w_prev * hio.p[m][c]);
+            T b = (T)dt * h;
             if (dead) {
                 uint32_t id0 = st.cut_off[c];
                 double acc = 0.0;
                 for (int q = 0; q < nbits; ++q) acc += wall ? wall[3 * (long long)(id0 + q) + m] : 0.0;
                 v = (T)(acc / (double)nbits);
+                b = v - qc;
                 h = (T)0;
             }
-            us.p[m][c] = v;
+            if (cn) {
+                rhs.p[m][c] = b;
+                if (dead) us.p[m][c] = v;
+            } else {
+                us.p[m][c] = v;
+            }
             hio.p[m][c] = h;
         }
     }
@@ -484,9 +466,16 @@ int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, co
     V3<T> us{{(T*)c->ustar[0], (T*)c->ustar[1], (T*)c->ustar[2]}};
     // variable-step Adams-Bashforth weights, r = dt / dt_prev
     const double r = prm->dt_prev > 0.0 ? prm->dt / prm->dt_prev : 1.0;
+    const bool cn = prm->scheme == IBM_SCHEME_CN;
+    V3<T> rhs{{nullptr, nullptr, nullptr}};
+    if (cn) {
+        // the increment's right-hand side goes where the solve keeps x (its initial guess)
+        T* x = (T*)c->cn_ws;
+        for (int a = 0; a < 3; ++a) rhs.p[a] = x + (long long)a * c->N;
+    }
     k_predict<T><<<nb, NT, 0, s>>>(g, st, uu, UU, nut, hh, us, wall, prm->dt, 1.0 + 0.5 * r, 0.5 * r, prm->nu,
                                    prm->body_force[0], prm->body_force[1], prm->body_force[2],
-                                   prm->step == 0 ? 1 : 0);
+                                   prm->step == 0 ? 1 : 0, cn ? 1 : 0, rhs);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libibm.so")
 PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 SOLVER_PCG_JACOBI, SOLVER_FCG_CNN, SOLVER_FCG_JACOBI = 0, 1, 2
+SCHEME_AB2, SCHEME_CN = 0, 1
 OK, NOT_CONVERGED = 0, 1
 
 
@@ -45,17 +46,20 @@ class StepParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("dt_prev", ctypes.c_double), ("nu", ctypes.c_double),
                 ("c1", ctypes.c_double),
                 ("csm_on", ctypes.c_int32), ("step", ctypes.c_int32), ("body_force", ctypes.c_double * 3),
-                ("poisson", SolverOpts)]
+                ("poisson", SolverOpts), ("scheme", ctypes.c_int32), ("mom_max_iter", ctypes.c_int32),
+                ("mom_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iters_inner", ctypes.c_int32), ("iters_outer", ctypes.c_int32),
                 ("fallback_used", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("div_l2", ctypes.c_double), ("div_linf", ctypes.c_double),
-                ("umax", ctypes.c_double)]
+                ("umax", ctypes.c_double), ("iters_momentum", ctypes.c_int32 * 3), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+        d["iters_momentum"] = list(d["iters_momentum"])
+        return d
 
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double)
@@ -86,6 +90,10 @@ def _load():
         "ibm_shepard_force": ([vp, vp, ctypes.c_int64, vp, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
         "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
         "ibm_timing_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
+        "ibm_timing_slot": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
+        "ibm_momentum_apply": ([vp, P3, P3, vp, ctypes.c_double, ctypes.c_double, P3, vp], ctypes.c_int),
+        "ibm_momentum_solve": ([vp, P3, P3, P3, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp], ctypes.c_int),
         "ibm_set_progress": ([vp, PROGRESS_FN, vp], ctypes.c_int),
         "ibm_cnn_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int),
         "ibm_cnn_destroy": ([vp], ctypes.c_int),
@@ -110,7 +118,7 @@ _lib = _load()
 EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "ibm_build_stencils",
             "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
             "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_shepard_force", "ibm_timing_enable", "ibm_timing_read",
-            "ibm_set_progress",
+            "ibm_timing_slot", "ibm_set_progress", "ibm_momentum_apply", "ibm_momentum_solve",
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
             "ibm_ctx_set_preconditioner")
@@ -222,6 +230,29 @@ def ibm_shepard_force(ctx, tri, p, side=None):
     return list(out)
 
 
+def ibm_momentum_apply(ctx, q, U, nut, nu, dt, out):
+    """out = (I - dt/2 L) q for the three velocity components (eq. (crank-nicolson));
+    q, out: three cell fields of the context's cell type; nut: cell field or None."""
+    return _check(_lib.ibm_momentum_apply(ctx, _p3(q), _p3(U), _ptr(nut), float(nu), float(dt), _p3(out),
+                                          _stream()), "ibm_momentum_apply")
+
+
+def ibm_momentum_solve(ctx, b, x, U, nut, nu, dt, tol, max_iter):
+    """BiCGStab for (I - dt/2 L) x = b, x in/out (initial guess / solution); returns
+    (return code, iterations per component)."""
+    it = (ctypes.c_int32 * 3)()
+    rc = _check(_lib.ibm_momentum_solve(ctx, _p3(b), _p3(x), _p3(U), _ptr(nut), float(nu), float(dt), float(tol),
+                                        int(max_iter), it, _stream()), "ibm_momentum_solve")
+    return rc, list(it)
+
+
+def ibm_timing_slot(ctx, slot, reset=False):
+    """(milliseconds, launches) accumulated in one timed slot."""
+    out = (ctypes.c_double * 2)()
+    _check(_lib.ibm_timing_slot(ctx, int(slot), out, int(bool(reset))), "ibm_timing_slot")
+    return float(out[0]), int(out[1])
+
+
 def ibm_timing_enable(ctx, on=True):
     return _check(_lib.ibm_timing_enable(ctx, int(bool(on))), "ibm_timing_enable")
 
@@ -305,9 +336,11 @@ def solver_opts(tol=1e-10, max_iter=20000, kind=SOLVER_PCG_JACOBI, inner_tol=1e-
     return SolverOpts(tol, max_iter, kind, inner_tol, inner_max_iter, stall_factor, check_every, force_stall)
 
 
-def step_params(dt, nu, c1=1.0 / 20.0, csm=True, step=0, body=(0.0, 0.0, 0.0), dt_prev=0.0, **solver):
+def step_params(dt, nu, c1=1.0 / 20.0, csm=True, step=0, body=(0.0, 0.0, 0.0), dt_prev=0.0, scheme="ab2",
+                mom_tol=1e-10, mom_max_iter=200, **solver):
+    sc = {"ab2": SCHEME_AB2, "cn": SCHEME_CN}[scheme]
     return StepParams(dt, dt_prev, nu, c1, int(bool(csm)), int(step), (ctypes.c_double * 3)(*body),
-                      solver_opts(**solver))
+                      solver_opts(**solver), sc, int(mom_max_iter), float(mom_tol))
 
 
 class Solver:
@@ -384,6 +417,12 @@ class Solver:
 
     def forces(self, st, nu, wall=None):
         return ibm_forces(self.ctx, st["u"], st["p"], nu, None, wall)
+
+    def momentum_apply(self, q, U, nut, nu, dt, out):
+        return ibm_momentum_apply(self.ctx, q, U, nut, nu, dt, out)
+
+    def momentum_solve(self, b, x, U, nut, nu, dt, tol=1e-10, max_iter=200):
+        return ibm_momentum_solve(self.ctx, b, x, U, nut, nu, dt, tol, max_iter)
 
     def shepard_force(self, tri, p, side=None):
         return ibm_shepard_force(self.ctx, tri, p, side)

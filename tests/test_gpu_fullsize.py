@@ -11,6 +11,8 @@
 * Mixed and learned solves at that size: the FP64 judge residual recomputed by the
   oracle's operator, and the discrete divergence identity div U^{n+1} =
   dt (b - L p) cell by cell (a property at any size).
+* Crank-Nicolson at that size: H^n against the oracle, the momentum system's residual
+  by the oracle's operator (<= tol), the operator itself (relative L2 1e-13).
 * The precision configuration (256^3 plate): relative L2 error of u, p and drag of the
   mixed path against the plain FP64 path after the same steps, stated.
 """
@@ -125,6 +127,54 @@ def test_benchmark_workload_step_pieces_match_oracle():
           (n, e_nut, e_b, e_h, e_u, e_U, res), flush=True)
     assert max(e_nut, e_b, e_h, e_u, e_U) < 1e-10
     assert res <= 1e-6 * 1.0001
+    s.close()
+
+
+def test_benchmark_workload_crank_nicolson_step():
+    """Crank-Nicolson at 256^3 from a developed state, at twice the explicit time step:
+    H^n of the CN step against the oracle; the step's own system solved again through
+    ibm_momentum_solve (same iterations) and its residual measured by the oracle's
+    operator (<= tol); ibm_momentum_apply against the oracle operator on a random field."""
+    case, g, ob, ot, st = _oracle("ellipsoids256")
+    s, *_ = _gpu(case, ibm.FP64)
+    gs = s.new_state(case.u_in)
+    ctl = {"umax": 1.0, "dt_prev": 0.0, "step": 0, "dt": case.dt}
+    print("case full-size crank-nicolson ellipsoids256", flush=True)
+    _cfl_steps(s, gs, case, 2, ibm.SOLVER_PCG_JACOBI, 1e-6, ctl)
+    u0, U0, p0, h0 = _host(gs)
+    dt = 2.0 * ctl["dt"]
+    rc, stats = s.step(gs, ibm.step_params(dt, case.nu, csm=case.csm, step=ctl["step"], tol=1e-6, max_iter=20000,
+                                           scheme="cn", mom_tol=1e-10))
+    assert rc == 0 and stats["rel_residual"] <= 1e-6 * 1.0001
+    nut = s.nut().cpu().numpy()
+    nut_o = flow.csm_nut(st, u0) if case.csm else np.zeros(g.shape)
+    assert rel_l2(nut, nut_o) < 1e-10
+    H = flow.momentum_rhs(st, u0, U0, nut_o, case.nu, (0.0, 0.0, 0.0), None)
+    H = [np.where(st.deadend, 0.0, a) for a in H]
+    e_h = rel_l2(_vec(gs["h"]), _vec(H))
+    # the step's system again, through the solver entry point
+    Ug = [torch.from_numpy(a).cuda() for a in U0]
+    b = [dt * t for t in gs["h"]]
+    x = [t.clone() for t in b]
+    rc, iters = s.momentum_solve(b, x, Ug, s.nut(), case.nu, dt, 1e-10, 200)
+    assert rc == 0 and iters == stats["iters_momentum"], (iters, stats["iters_momentum"])
+    worst = 0.0
+    for m in range(3):
+        bm = b[m].cpu().numpy()
+        res = bm - flow.cn_matrix_apply(st, x[m].cpu().numpy(), m, U0, nut, case.nu, dt)
+        bn = np.sqrt(np.sum(bm * bm))
+        if bn > 0:
+            worst = max(worst, np.sqrt(np.sum(res * res)) / bn)
+    rng = np.random.default_rng(2)
+    q = [torch.from_numpy(rng.standard_normal(g.shape)).cuda() for _ in range(3)]
+    out = [torch.empty_like(t) for t in q]
+    s.momentum_apply(q, Ug, s.nut(), case.nu, dt, out)
+    e_a = rel_l2(out[0].cpu().numpy(), flow.cn_matrix_apply(st, q[0].cpu().numpy(), 0, U0, nut, case.nu, dt))
+    print("256^3 CN step: iterations %s, rel L2 H %.1e, operator %.1e, momentum residual %.2e" %
+          (iters, e_h, e_a, worst), flush=True)
+    assert e_h < 1e-10 and e_a < 1e-13
+    assert worst <= 1e-10 * 1.05
+    assert min(iters[:1]) > 0
     s.close()
 
 
