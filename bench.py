@@ -71,8 +71,9 @@ def workload(name):
 
 
 def kernel_source_hash():
+    """Hash of the sources of every kernel with a committed counter summary."""
     h = hashlib.sha256()
-    for f in ("poisson.hip", "cnn.hip", "common.h"):
+    for f in ("poisson.hip", "cnn.hip", "common.h", "momentum.hip", "shepard.hip"):
         with open(os.path.join(ROOT, "paper_2002_06206_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -235,6 +236,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
                         "sweeps_ms": {SWEEP_NAMES[k]: round(tim["ms"][k], 2) for k in range(3)}}}
     if solver == args.solver:
         out["surface_force"] = shepard_timing(case, s, st, torch)
+    if solver == "pcg_fp64" and args.cn_steps > 0:
+        out["crank_nicolson"] = cn_timing(case, s, st, ctl, step, args, ibm, torch)
     if solver == "mixed_learned":
         # slot 0: whole preconditioner applications (three marching MFMA kernels and the
         # relay of the dot products); slot 1: the fused FCG passes; slot 2: the dominant
@@ -278,6 +281,67 @@ def shepard_timing(case, s, st, torch, calls=20):
     return {"triangles": ntri, "us_per_call": round(per * 1e6, 2), "pressure_force": f,
             "bytes_per_triangle": SHEPARD_BYTES_PER_TRIANGLE,
             "achieved_gbs_per_call": round(SHEPARD_BYTES_PER_TRIANGLE * ntri / per / 1e9, 1)}
+
+
+# Crank-Nicolson predictor (eq. (crank-nicolson)), three velocity components of FP64:
+# algorithmic bytes per cell of each BiCGStab pass (new direction p and v = A p; t = A s;
+# update of x and r), as stated in momentum.hip
+CN_PASSES = ("cn_direction", "cn_stabilise", "cn_update")
+CN_KERNELS = {"cn_direction": "k_cn_p<double>", "cn_stabilise": "k_cn_s<double>", "cn_update": "k_cn_x<double>"}
+CN_BYTES_PER_CELL = {"cn_direction": 144 + 33, "cn_stabilise": 72 + 33, "cn_update": 192}
+
+
+def cn_timing(case, s, st, ctl, step, args, ibm, torch):
+    """Crank-Nicolson steps on the developed plain FP64 state at twice the explicit CFL
+    (0.6): whole steps timed by the host clock, the three BiCGStab passes by dispatch
+    events (timing slots 4-6).  A pass launched after its solve converged returns at
+    once; the per-launch figures divide by the passes that did work (iterations made,
+    the largest component count per solve)."""
+    N = case.n[0] * case.n[1] * case.n[2]
+    dt = min(2.0 * case.dt, 0.6 * case.dx / max(ctl["umax"], 1e-30))
+    prm = lambda k: ibm.step_params(dt, case.nu, csm=case.csm, step=k, tol=args.tol, max_iter=20000,  # noqa: E731
+                                    check_every=16, scheme="cn", mom_tol=args.mom_tol)
+    for _ in range(2):
+        rc, stats = s.step(st, prm(step))
+        step += 1
+    ibm.ibm_timing_enable(s.ctx, True)
+    for k in (4, 5, 6):
+        ibm.ibm_timing_slot(s.ctx, k, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, worked = [], 0
+    for _ in range(args.cn_steps):
+        rc, stats = s.step(st, prm(step))
+        if rc != 0:
+            raise SystemExit("crank-nicolson step did not converge (rc=%d)" % rc)
+        step += 1
+        its.append(stats["iters_momentum"])
+        worked += max(stats["iters_momentum"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    slots = {name: ibm.ibm_timing_slot(s.ctx, k, reset=True) for name, k in zip(CN_PASSES, (4, 5, 6))}
+    ibm.ibm_timing_enable(s.ctx, False)
+    passes = {}
+    for name, (ms, launches) in slots.items():
+        avg = ms / 1e3 / max(worked, 1)
+        passes[name] = {"kernel": CN_KERNELS[name], "ms_total": round(ms, 3), "launches": launches,
+                        "launches_with_work": worked, "avg_launch_us": round(avg * 1e6, 2),
+                        "bytes_per_cell": CN_BYTES_PER_CELL[name],
+                        "achieved_gbs": round(CN_BYTES_PER_CELL[name] * N / avg / 1e9, 1) if avg > 0 else None}
+    dom = max(CN_PASSES, key=lambda n: slots[n][0])
+    d = passes[dom]
+    traffic = committed_traffic(dom, args.workload)
+    return {"dt": dt, "cfl": 0.6, "mom_tol": args.mom_tol, "steps": args.cn_steps,
+            "ms_per_step": round(elapsed / args.cn_steps * 1e3, 2),
+            "value": N * args.cn_steps / elapsed,
+            "iters_per_component": its,
+            "predictor_ms_per_step": round(sum(v[0] for v in slots.values()) / args.cn_steps, 3),
+            "passes": passes,
+            "roofline": {"bound": "hbm", "achieved": d["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(d["achieved_gbs"] / HBM_PEAK_GBS, 4) if d["achieved_gbs"] else None,
+                         "traffic": traffic, "kernel": d["kernel"],
+                         "algorithmic_bytes_per_launch": d["bytes_per_cell"] * N,
+                         "avg_launch_us": d["avg_launch_us"]}}
 
 
 def train_network(args, ibm, torch):
@@ -330,6 +394,9 @@ def main():
     ap.add_argument("--train-depths", default="0,32",
                     help="Krylov depths of the training pairs, cycled (0: the step's (b, p) itself)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cn-steps", type=int, default=5,
+                    help="Crank-Nicolson steps timed after the plain FP64 run (0: none)")
+    ap.add_argument("--mom-tol", type=float, default=1e-10, help="Crank-Nicolson momentum solve tolerance")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (collectives and sharding are not part of it); "
@@ -399,12 +466,14 @@ def main():
                    "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm},
         "plain_fp64_value": plain["value"] if plain else None,
         "speedup_vs_plain_fp64": head["value"] / plain["value"] if plain else None,
-        "solvers": {k: {kk: vv for kk, vv in v.items() if kk != "dominant"} for k, v in runs.items()},
+        "solvers": {k: {kk: vv for kk, vv in v.items() if kk not in ("dominant", "crank_nicolson")}
+                    for k, v in runs.items()},
         "speedups_vs_plain_fp64": {k: round(v["value"] / plain["value"], 4) for k, v in runs.items()} if plain else None,
         "training": train_info,
         "roofline": roofline,
         "roofline_sweeps": roofline_sweeps,
         "surface_force": head.get("surface_force"),
+        "crank_nicolson": plain.get("crank_nicolson") if plain else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
