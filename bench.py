@@ -284,17 +284,19 @@ def shepard_timing(case, s, st, torch, calls=20):
 
 
 # Crank-Nicolson predictor (eq. (crank-nicolson)), three velocity components of FP64:
-# algorithmic bytes per cell of each BiCGStab pass (new direction p and v = A p; t = A s;
-# update of x and r), as stated in momentum.hip
-CN_PASSES = ("cn_direction", "cn_stabilise", "cn_update")
-CN_KERNELS = {"cn_direction": "k_cn_p<double>", "cn_stabilise": "k_cn_s<double>", "cn_update": "k_cn_x<double>"}
-CN_BYTES_PER_CELL = {"cn_direction": 144 + 33, "cn_stabilise": 72 + 33, "cn_update": 192}
+# algorithmic bytes per cell of each BiCGStab pass, as stated in momentum.hip (timing
+# slots 4-8 in this order)
+CN_PASSES = ("cn_direction", "cn_apply_p", "cn_stabilise", "cn_apply_s", "cn_update")
+CN_KERNELS = {"cn_direction": "k_cn_dir<double>", "cn_apply_p": "k_cn_ap<double>", "cn_stabilise": "k_cn_s<double>",
+              "cn_apply_s": "k_cn_as<double>", "cn_update": "k_cn_x<double>"}
+CN_BYTES_PER_CELL = {"cn_direction": 96, "cn_apply_p": 105, "cn_stabilise": 72, "cn_apply_s": 81,
+                     "cn_update": 168}
 
 
 def cn_timing(case, s, st, ctl, step, args, ibm, torch):
     """Crank-Nicolson steps on the developed plain FP64 state at twice the explicit CFL
-    (0.6): whole steps timed by the host clock, the three BiCGStab passes by dispatch
-    events (timing slots 4-6).  A pass launched after its solve converged returns at
+    (0.6): whole steps timed by the host clock, the five BiCGStab passes by dispatch
+    events (timing slots 4-8).  A pass launched after its solve converged returns at
     once; the per-launch figures divide by the passes that did work (iterations made,
     the largest component count per solve)."""
     N = case.n[0] * case.n[1] * case.n[2]
@@ -305,7 +307,7 @@ def cn_timing(case, s, st, ctl, step, args, ibm, torch):
         rc, stats = s.step(st, prm(step))
         step += 1
     ibm.ibm_timing_enable(s.ctx, True)
-    for k in (4, 5, 6):
+    for k in (4, 5, 6, 7, 8):
         ibm.ibm_timing_slot(s.ctx, k, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -319,7 +321,7 @@ def cn_timing(case, s, st, ctl, step, args, ibm, torch):
         worked += max(stats["iters_momentum"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    slots = {name: ibm.ibm_timing_slot(s.ctx, k, reset=True) for name, k in zip(CN_PASSES, (4, 5, 6))}
+    slots = {name: ibm.ibm_timing_slot(s.ctx, k, reset=True) for name, k in zip(CN_PASSES, (4, 5, 6, 7, 8))}
     ibm.ibm_timing_enable(s.ctx, False)
     passes = {}
     for name, (ms, launches) in slots.items():

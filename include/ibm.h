@@ -341,9 +341,9 @@ typedef void (*ibm_progress_fn)(void* user, int64_t iterations, double rr);
 int ibm_set_progress(ibm_ctx* ctx, ibm_progress_fn fn, void* user);
 int ibm_timing_read(ibm_ctx* ctx, double out[10], int32_t reset);
 /* One timed slot: out[0] = accumulated milliseconds, out[1] = launches; reset != 0 zeroes
- * that slot.  Slots 0-2 as above, 3 = the near-field force kernel, 4-6 = the three
- * BiCGStab passes of the Crank-Nicolson predictor (P: new direction and v = A p;
- * S: t = A s; X: update of x and r). */
+ * that slot.  Slots 0-2 as above, 3 = the near-field force kernel, 4-8 = the five
+ * BiCGStab passes of the Crank-Nicolson predictor (4: new direction p; 5: v = A p;
+ * 6: s = r - alpha v; 7: t = A s; 8: update of x and r). */
 int ibm_timing_slot(ibm_ctx* ctx, int32_t slot, double out[2], int32_t reset);
 
 #ifdef __cplusplus

@@ -57,7 +57,7 @@ struct CnState {
     int done;                   // every component stopped: later passes return at once
 };
 enum { CN_RUNNING = 0, CN_CONVERGED = 1, CN_MAXITER = 2, CN_BREAKDOWN = 3, CN_NAN = 4 };
-constexpr int TK_SLOTS_MAX = 7;  // timed kernel slots (the TK_* launch slots)
+constexpr int TK_SLOTS_MAX = 9;  // timed kernel slots (the TK_* launch slots)
 
 }  // namespace ibm
 
@@ -127,8 +127,8 @@ struct ibm_ctx {
     double t_ms[ibm::TK_SLOTS_MAX];     // accumulated kernel time
     long long t_launches[ibm::TK_SLOTS_MAX];
     long long t_real_iters; // iterations that did work (the rest exit at once)
-    // Crank-Nicolson predictor workspace, allocated by its first use: eight vectors
-    // (x, r, r0, p twice, v twice, t) of three components of the cell type
+    // Crank-Nicolson predictor workspace, allocated by its first use: six vectors
+    // (x, r, r0, p, v, t) of three components of the cell type
     void* cn_ws;
     double* cn_part;        // 21 * MAX_BLOCKS partial sums
     ibm::CnState* cn_state;
@@ -202,6 +202,15 @@ __device__ inline int xcd_chunk(int b, int nb) {
     int full = per * NXCD;
     if (b >= full) return b;
     return (b % NXCD) * per + b / NXCD;
+}
+
+// z-slabs of the marching sweeps (pressure passes, Crank-Nicolson passes): about 32
+// planes per slab, a multiple of the XCD count
+__host__ __device__ inline int slab_count(int nz) {
+    int want = (nz + 31) / 32;
+    want = ((want + 7) / 8) * 8;
+    if (want > nz) want = nz;
+    return want < 1 ? 1 : want;
 }
 
 // Tile range [t0, t1) of this block.
@@ -300,8 +309,9 @@ int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s);
 // timing helpers (poisson.hip)
 // timed kernel slots: the two CG passes (or the preconditioner and the passes of the
 // learned solve), the dominant convolution of the learned preconditioner, spare
-// (other), and the three BiCGStab passes of the Crank-Nicolson predictor
-enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3, TK_CN_P = 4, TK_CN_S = 5, TK_CN_X = 6 };
+// (other), and the five BiCGStab passes of the Crank-Nicolson predictor
+enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3, TK_CN_D = 4, TK_CN_AP = 5, TK_CN_S = 6, TK_CN_AS = 7,
+       TK_CN_X = 8 };
 // Launches kern<<<grid, NT, 0, s>>>(args...).  When timing slot k is on, the launch
 // carries HIP's dispatch-level start/stop events (hipExtLaunchKernelGGL), so the time
 // collected is the kernel's own, without the gaps between dispatches.

@@ -11,19 +11,22 @@
 // cell and its neighbours, the blocked mask) are read once for three systems, while
 // each component keeps its own BiCGStab scalars and stops on its own.
 //
-// BiCGStab iteration it in three passes, each ending in per-block partial sums that
-// the next pass adds up in block order (every block computes the same totals):
-//   P_it: stop test on ||r||; rho = <r0, r>; beta = (rho/rho_prev)(alpha/omega);
-//         p = r + beta (p_prev - omega v_prev) formed on the fly for the cell and its
-//         neighbours (p and v ping-pong between two buffers); v = A p;  <r0, v>
-//   S_it: alpha = rho / <r0, v>; s = r - alpha v formed on the fly; t = A s;
-//         <t, s>, <t, t>, <s, s>
-//   X_it: omega = <t,s>/<t,t> (0 when ||s|| is already small: the half-step exit);
-//         x += alpha p + omega s; r = s - omega t;  <r0, r>, <r, r>
-// Algorithmic traffic per cell and iteration, three components of T = double:
-// P reads r, p, v, r0 and writes p, v (144 B); S reads r, v and writes t (72 B); X reads
-// x, p, r, v, t, r0 and writes x, r (192 B); P and S each read U on three faces, nu_t
-// and the mask (33 B).  474 B in all.
+// BiCGStab iteration it in five passes; the scalars come from per-block partial sums
+// that the next pass adds up in block order (every block computes the same totals):
+//   D_it  (elementwise): stop test on ||r||; rho = <r0, r>; beta = (rho/rho_prev)
+//         (alpha/omega); p = r + beta (p - omega v)   (p = r at it = 0)
+//   AP_it (stencil):     v = A p;  <r0, v>
+//   S_it  (elementwise): alpha = rho / <r0, v>;  s = r - alpha v, stored over r
+//   AS_it (stencil):     t = A s;  <t, s>, <t, t>, <s, s>
+//   X_it  (elementwise): omega = <t,s>/<t,t> (0 when ||s|| is already small: the
+//         half-step exit); x += alpha p + omega s; r = s - omega t;  <r0, r>, <r, r>
+// The vector updates are kept out of the stencil passes so each stencil gathers one
+// array (forming p or s on the fly at seven points gathered three or two arrays per
+// component, and measured slower).  Algorithmic traffic per cell and iteration, three
+// components of T = double: D reads r, p, v, writes p (96 B); AP reads p, r0, U on
+// three faces, nu_t and the mask and writes v (105 B); S reads r, v, writes r (72 B);
+// AS reads s and the coefficients and writes t (81 B); X reads x, p, s, t, r0 and
+// writes x, r (168 B).  522 B in all.
 
 #include "common.h"
 
@@ -40,94 +43,144 @@ constexpr int CS_TT = 15;   // <t, t>       x3  (S)
 constexpr int CS_SS = 18;   // <s, s>       x3  (S)
 constexpr int CS_SLOTS = 21;
 
-// Operator coefficients of one cell, shared by the three components.
-template <class T>
-struct Coef {
-    T Uf[6];          // normal face velocity on each face
-    T visc[6];        // nu + nu_t on each face
-    long long nb[6];  // neighbour index (wrapped)
-    bool bnd[6];      // non-periodic domain face
-    uint8_t msk;
-    bool dead;
-};
-
-template <class T>
-__device__ inline void coef_of(const Geo& g, const Sten& st, const C3<double>& U, const T* nut, T nu, int i, int j,
-                               int k, long long c, Coef<T>& f) {
-    f.msk = st.mask[c];
-    f.dead = dead_cell(st, c, f.msk);
-    const T nut_c = nut ? nut[c] : (T)0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-        bool bnd;
-        const long long n = nb_index(g, i, j, k, d, bnd);
-        f.nb[d] = n;
-        f.bnd[d] = bnd;
-        const bool closed = bnd || ((f.msk >> d) & 1);
-        f.visc[d] = nu + (closed ? nut_c : (T)0.5 * (nut_c + (nut ? nut[n] : (T)0)));
-        const int ax = d >> 1;
-        if (d & 1) f.Uf[d] = (T)U.p[ax][c];
-        else if (bnd) f.Uf[d] = g.bc[d] == IBM_BC_INFLOW ? (T)g.uin[ax] : (T)0;
-        else f.Uf[d] = (T)U.p[ax][n];
-    }
-}
-
-// (A q)_c for component m, A = I - dt/2 L (identity at dead-end cells); src(m, n) gives
-// the value of q at cell n, qc = src(m, c).
+// (A q)_c for component m, A = I - dt/2 L (identity at dead-end cells), from the value
+// qc at the cell and nb[d] across each face (the neighbour, or anything where the face
+// is blocked or a non-periodic domain face: those take the ghosts); src(m, n) gives q
+// at cell n for the opposite cell of an eq. (q_axis) ghost.
 template <class T, class Src>
-__device__ inline T apply_at(const Geo& g, const Sten& st, const Coef<T>& f, const Src& src, int m, long long c, T qc,
+__device__ inline T apply_nb(const Geo& g, const Sten& st, const Src& src, int m, long long c, uint8_t msk,
+                             const bool (&bnd)[6], const T (&Uf)[6], const T (&visc)[6], T qc, const T (&nb)[6],
                              T hdt, T idx, T idx2) {
-    if (f.dead) return qc;
     T L = (T)0;
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
         T qn;
-        if ((f.msk >> d) & 1) {
+        if ((msk >> d) & 1) {
             // eq. (q_axis) ghost with a zero wall velocity
-            const uint32_t id = cut_id(st, c, f.msk, d);
+            const uint32_t id = cut_id(st, c, msk, d);
             double v = st.a_c[id] * (double)qc;
             const int32_t o = st.opp[id];
             if (o >= 0) v += st.a_o[id] * (double)src(m, o);
             qn = (T)v;
-        } else if (f.bnd[d]) {
+        } else if (bnd[d]) {
             const int kind = g.bc[d];
             qn = (kind == IBM_BC_INFLOW || (kind == IBM_BC_SLIP && m == (d >> 1))) ? -qc : qc;
         } else {
-            qn = src(m, f.nb[d]);
+            qn = nb[d];
         }
         const T s = (d & 1) ? (T)1 : (T)-1;
-        L = L - s * f.Uf[d] * ((T)0.5 * (qc + qn)) * idx + f.visc[d] * (qn - qc) * idx2;
+        L = L - s * Uf[d] * ((T)0.5 * (qc + qn)) * idx + visc[d] * (qn - qc) * idx2;
     }
     return qc - hdt * L;
+}
+
+// Z-marching sweep over (64x4 tile, z-slab) items, the order of the pressure passes:
+// each thread walks one column of its slab and carries the values of the vector at
+// z-1, z and z+1 (three components), the eddy viscosity of the three planes and the
+// face velocity under the cell, so a z-neighbour is read once; x and y neighbours
+// come from the cache lines the wavefront and the neighbouring tiles read.  For
+// every cell and active component it calls emit(c, m, q_c, (A q)_c).
+template <class T, class Src, class Emit>
+__device__ inline void cn_march(const Geo& g, const Sten& st, const C3<double>& U, const T* nut, T nu, T hdt,
+                                const int (&act)[3], const Src& src, Emit&& emit) {
+    const T idx = (T)(1.0 / g.dx), idx2 = (T)(1.0 / (g.dx * g.dx));
+    const int nzc = slab_count(g.nz);
+    const long long tiles = (long long)g.ntx * g.nty;
+    const long long items = tiles * nzc;
+    const int nblk = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nblk);
+    const long long w0 = items * ch / nblk, w1 = items * (ch + 1) / nblk;
+    const long long plane = (long long)g.nx * g.ny;
+    const T uin[3] = {(T)g.uin[0], (T)g.uin[1], (T)g.uin[2]};
+    for (long long w = w0; w < w1; ++w) {
+        const int zc = (int)(w / tiles);
+        const long long t = w % tiles;
+        const int i = (int)(t % g.ntx) * TX + (threadIdx.x % TX);
+        const int j = (int)(t / g.ntx) * TY + (threadIdx.x / TX);
+        const int z0 = (int)((long long)g.nz * zc / nzc), z1 = (int)((long long)g.nz * (zc + 1) / nzc);
+        if (i >= g.nx || j >= g.ny) continue;
+        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i == g.nx - 1 ? 0 : i + 1;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+        const long long col = (long long)i + (long long)g.nx * j;
+        const long long ow = (long long)iw + (long long)g.nx * j - col;
+        const long long oe = (long long)ie + (long long)g.nx * j - col;
+        const long long os = (long long)i + (long long)g.nx * js - col;
+        const long long on = (long long)i + (long long)g.nx * jn - col;
+        bool bnd[6];
+        bnd[0] = i == 0 && g.bc[0] != IBM_BC_PERIODIC;
+        bnd[1] = i == g.nx - 1 && g.bc[1] != IBM_BC_PERIODIC;
+        bnd[2] = j == 0 && g.bc[2] != IBM_BC_PERIODIC;
+        bnd[3] = j == g.ny - 1 && g.bc[3] != IBM_BC_PERIODIC;
+        const int zb = z0 == 0 ? g.nz - 1 : z0 - 1;
+        T qb[3], qc[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            qb[m] = act[m] ? src(m, col + plane * zb) : (T)0;
+            qc[m] = act[m] ? src(m, col + plane * z0) : (T)0;
+        }
+        T nb_b = nut ? nut[col + plane * zb] : (T)0;
+        T nb_c = nut ? nut[col + plane * z0] : (T)0;
+        T uz_b = (T)U.p[2][col + plane * zb];
+        for (int k = z0; k < z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = col + plane * k;
+            const long long ct = col + plane * zt;
+            bnd[4] = k == 0 && g.bc[4] != IBM_BC_PERIODIC;
+            bnd[5] = k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC;
+            T qt[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) qt[m] = act[m] ? src(m, ct) : (T)0;
+            const T nb_t = nut ? nut[ct] : (T)0;
+            const uint8_t msk = st.mask[c];
+            const bool dead = dead_cell(st, c, msk);
+            T Uf[6];
+            Uf[0] = bnd[0] ? (g.bc[0] == IBM_BC_INFLOW ? uin[0] : (T)0) : (T)U.p[0][c + ow];
+            Uf[1] = (T)U.p[0][c];
+            Uf[2] = bnd[2] ? (g.bc[2] == IBM_BC_INFLOW ? uin[1] : (T)0) : (T)U.p[1][c + os];
+            Uf[3] = (T)U.p[1][c];
+            Uf[4] = bnd[4] ? (g.bc[4] == IBM_BC_INFLOW ? uin[2] : (T)0) : uz_b;
+            Uf[5] = (T)U.p[2][c];
+            T nn[6];
+            nn[0] = nut ? nut[c + ow] : (T)0;
+            nn[1] = nut ? nut[c + oe] : (T)0;
+            nn[2] = nut ? nut[c + os] : (T)0;
+            nn[3] = nut ? nut[c + on] : (T)0;
+            nn[4] = nb_b;
+            nn[5] = nb_t;
+            T visc[6];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const bool closed = bnd[d] || ((msk >> d) & 1);
+                visc[d] = nu + (closed ? nb_c : (T)0.5 * (nb_c + nn[d]));
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                if (!act[m]) continue;
+                T out;
+                if (dead) {
+                    out = qc[m];
+                } else {
+                    const T nbv[6] = {src(m, c + ow), src(m, c + oe), src(m, c + os), src(m, c + on), qb[m], qt[m]};
+                    out = apply_nb(g, st, src, m, c, msk, bnd, Uf, visc, qc[m], nbv, hdt, idx, idx2);
+                }
+                emit(c, m, qc[m], out);
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                qb[m] = qc[m];
+                qc[m] = qt[m];
+            }
+            nb_b = nb_c;
+            nb_c = nb_t;
+            uz_b = Uf[5];
+        }
+    }
 }
 
 template <class T>
 struct SrcPlain {
     const T* q[3];
     __device__ T operator()(int m, long long n) const { return q[m][n]; }
-};
-
-// p = r + beta (p_prev - omega v_prev), or r on the first iteration
-template <class T>
-struct SrcDir {
-    const T* r[3];
-    const T* p[3];
-    const T* v[3];
-    T beta[3], omega[3];
-    int first;
-    __device__ T operator()(int m, long long n) const {
-        if (first) return r[m][n];
-        return r[m][n] + beta[m] * (p[m][n] - omega[m] * v[m][n]);
-    }
-};
-
-// s = r - alpha v
-template <class T>
-struct SrcS {
-    const T* r[3];
-    const T* v[3];
-    T alpha[3];
-    __device__ T operator()(int m, long long n) const { return r[m][n] - alpha[m] * v[m][n]; }
 };
 
 // totals of K slots (three components each) over nparts blocks, in block order
@@ -176,19 +229,9 @@ __device__ inline bool block_done(const CnState* cs) {
 template <class T>
 __global__ void __launch_bounds__(NT) k_cn_apply(Geo g, Sten st, C3<double> U, const T* nut, T nu, T hdt, C3<T> q,
                                                  V3<T> y) {
-    const T idx = (T)(1.0 / g.dx), idx2 = (T)(1.0 / (g.dx * g.dx));
     SrcPlain<T> src{{q.p[0], q.p[1], q.p[2]}};
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        const long long c = cidx(g, i, j, k);
-        Coef<T> f;
-        coef_of(g, st, U, nut, nu, i, j, k, c, f);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) y.p[m][c] = apply_at(g, st, f, src, m, c, q.p[m][c], hdt, idx, idx2);
-    }
+    const int act[3] = {1, 1, 1};
+    cn_march(g, st, U, nut, nu, hdt, act, src, [&](long long c, int m, T, T aq) { y.p[m][c] = aq; });
 }
 
 // r = b - A x, r0 = r; partials <r0,r> (= <r,r>), <r,r>, <b,b>.  b may alias x: b is
@@ -197,29 +240,19 @@ template <class T>
 __global__ void __launch_bounds__(NT) k_cn_init(Geo g, Sten st, C3<double> U, const T* nut, T nu, T hdt, C3<T> b,
                                                 C3<T> x, V3<T> r, V3<T> r0, double* part) {
     __shared__ double sh[4 * 9];
-    const T idx = (T)(1.0 / g.dx), idx2 = (T)(1.0 / (g.dx * g.dx));
     SrcPlain<T> src{{x.p[0], x.p[1], x.p[2]}};
     double v[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) v[q] = 0.0;
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        const long long c = cidx(g, i, j, k);
-        Coef<T> f;
-        coef_of(g, st, U, nut, nu, i, j, k, c, f);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const T bc = b.p[m][c];
-            const T rc = bc - apply_at(g, st, f, src, m, c, x.p[m][c], hdt, idx, idx2);
-            r.p[m][c] = rc;
-            r0.p[m][c] = rc;
-            v[m] += (double)rc * (double)rc;
-            v[6 + m] += (double)bc * (double)bc;
-        }
-    }
+    const int act[3] = {1, 1, 1};
+    cn_march(g, st, U, nut, nu, hdt, act, src, [&](long long c, int m, T, T ax) {
+        const T bc = b.p[m][c];
+        const T rc = bc - ax;
+        r.p[m][c] = rc;
+        r0.p[m][c] = rc;
+        v[m] += (double)rc * (double)rc;
+        v[6 + m] += (double)bc * (double)bc;
+    });
 #pragma unroll
     for (int m = 0; m < 3; ++m) v[3 + m] = v[m];
     block_reduce<9>(v, sh);
@@ -227,16 +260,16 @@ __global__ void __launch_bounds__(NT) k_cn_init(Geo g, Sten st, C3<double> U, co
     write_partials<3>(part, sl, v);
 }
 
-// Pass P of iteration it (see the file comment).  At it == 0 it also turns the init
+#define CN_CELLS(c, N) \
+    for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < (N); c += (long long)gridDim.x * NT)
+
+// Pass D of iteration it (see the file comment).  At it == 0 it also turns the init
 // partials into the per-component tolerances and zeroes x of a component with b = 0.
 template <class T>
-__global__ void __launch_bounds__(NT) k_cn_p(Geo g, Sten st, C3<double> U, const T* nut, T nu, T hdt, V3<T> x,
-                                             C3<T> r, C3<T> r0, C3<T> pprev, C3<T> vprev, V3<T> p, V3<T> v,
-                                             double* part, int nparts, int it, int max_iter, double tol,
-                                             CnState* cs) {
+__global__ void __launch_bounds__(NT) k_cn_dir(Geo g, V3<T> x, C3<T> r, V3<T> p, C3<T> v, double* part, int nparts,
+                                               int it, int max_iter, double tol, CnState* cs) {
     if (block_done(cs)) return;
     __shared__ double sh[4 * 9];
-    __shared__ double sh3[4 * 3];
     const int par = it & 1, pp = (it + 1) & 1;
     double tot[3][3];
     const int sl[3] = {CS_R0R, CS_RR, CS_BB};
@@ -294,50 +327,47 @@ __global__ void __launch_bounds__(NT) k_cn_p(Geo g, Sten st, C3<double> U, const
         else if (!any && cs->status == CN_RUNNING) cs->status = CN_CONVERGED;
         if (stop) cs->done = 1;
     }
-    const bool zero_x = it == 0 && (tot[2][0] == 0.0 || tot[2][1] == 0.0 || tot[2][2] == 0.0);
-    if (stop && !zero_x) return;
-    const T idx = (T)(1.0 / g.dx), idx2 = (T)(1.0 / (g.dx * g.dx));
-    SrcDir<T> src{{r.p[0], r.p[1], r.p[2]},
-                  {pprev.p[0], pprev.p[1], pprev.p[2]},
-                  {vprev.p[0], vprev.p[1], vprev.p[2]},
-                  {beta[0], beta[1], beta[2]},
-                  {omega[0], omega[1], omega[2]},
-                  it == 0 ? 1 : 0};
-    double acc[3] = {0.0, 0.0, 0.0};
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        const long long c = cidx(g, i, j, k);
-        if (zero_x) {
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    if (it == 0 && (tot[2][0] == 0.0 || tot[2][1] == 0.0 || tot[2][2] == 0.0)) {
+        CN_CELLS(c, N)
 #pragma unroll
-            for (int m = 0; m < 3; ++m)
-                if (tot[2][m] == 0.0) x.p[m][c] = (T)0;
-        }
-        if (stop) continue;
-        Coef<T> f;
-        coef_of(g, st, U, nut, nu, i, j, k, c, f);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            if (!act[m]) continue;
-            const T pc = src(m, c);
-            const T vc = apply_at(g, st, f, src, m, c, pc, hdt, idx, idx2);
-            p.p[m][c] = pc;
-            v.p[m][c] = vc;
-            acc[m] += (double)r0.p[m][c] * (double)vc;
-        }
+        for (int m = 0; m < 3; ++m)
+            if (tot[2][m] == 0.0) x.p[m][c] = (T)0;
     }
     if (stop) return;
+    CN_CELLS(c, N)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        if (!act[m]) continue;
+        p.p[m][c] = it == 0 ? r.p[m][c] : r.p[m][c] + beta[m] * (p.p[m][c] - omega[m] * v.p[m][c]);
+    }
+}
+
+// Pass AP of iteration it: v = A p, <r0, v>.
+template <class T>
+__global__ void __launch_bounds__(NT) k_cn_ap(Geo g, Sten st, C3<double> U, const T* nut, T nu, T hdt, C3<T> p,
+                                              V3<T> v, C3<T> r0, double* part, int it, CnState* cs) {
+    if (block_done(cs)) return;
+    __shared__ double sh3[4 * 3];
+    const int par = it & 1;
+    int act[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) act[m] = cs->active[par][m];
+    SrcPlain<T> src{{p.p[0], p.p[1], p.p[2]}};
+    double acc[3] = {0.0, 0.0, 0.0};
+    cn_march(g, st, U, nut, nu, hdt, act, src, [&](long long c, int m, T, T vc) {
+        v.p[m][c] = vc;
+        acc[m] += (double)r0.p[m][c] * (double)vc;
+    });
     block_reduce<3>(acc, sh3);
     const int so[1] = {CS_R0V};
     write_partials<1>(part, so, acc);
 }
 
-// Pass S of iteration it.
+// Pass S of iteration it: alpha = rho / <r0, v>; s = r - alpha v over r.
 template <class T>
-__global__ void __launch_bounds__(NT) k_cn_s(Geo g, Sten st, C3<double> U, const T* nut, T nu, T hdt, C3<T> r,
-                                             C3<T> v, V3<T> tv, double* part, int nparts, int it, CnState* cs) {
+__global__ void __launch_bounds__(NT) k_cn_s(Geo g, V3<T> r, C3<T> v, double* part, int nparts, int it,
+                                             CnState* cs) {
     if (block_done(cs)) return;
     __shared__ double sh[4 * 9];
     const int par = it & 1;
@@ -364,39 +394,42 @@ __global__ void __launch_bounds__(NT) k_cn_s(Geo g, Sten st, C3<double> U, const
         }
     }
     if (broke) return;
-    const T idx = (T)(1.0 / g.dx), idx2 = (T)(1.0 / (g.dx * g.dx));
-    SrcS<T> src{{r.p[0], r.p[1], r.p[2]}, {v.p[0], v.p[1], v.p[2]}, {alpha[0], alpha[1], alpha[2]}};
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    CN_CELLS(c, N)
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+        if (act[m]) r.p[m][c] = r.p[m][c] - alpha[m] * v.p[m][c];
+}
+
+// Pass AS of iteration it: t = A s, <t, s>, <t, t>, <s, s>.
+template <class T>
+__global__ void __launch_bounds__(NT) k_cn_as(Geo g, Sten st, C3<double> U, const T* nut, T nu, T hdt, C3<T> sv,
+                                              V3<T> tv, double* part, int it, CnState* cs) {
+    if (block_done(cs)) return;
+    __shared__ double sh[4 * 9];
+    const int par = it & 1;
+    int act[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) act[m] = cs->active[par][m];
+    SrcPlain<T> src{{sv.p[0], sv.p[1], sv.p[2]}};
     double acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = 0.0;
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        const long long c = cidx(g, i, j, k);
-        Coef<T> f;
-        coef_of(g, st, U, nut, nu, i, j, k, c, f);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            if (!act[m]) continue;
-            const T sc = src(m, c);
-            const T tc = apply_at(g, st, f, src, m, c, sc, hdt, idx, idx2);
-            tv.p[m][c] = tc;
-            acc[m] += (double)tc * (double)sc;
-            acc[3 + m] += (double)tc * (double)tc;
-            acc[6 + m] += (double)sc * (double)sc;
-        }
-    }
+    cn_march(g, st, U, nut, nu, hdt, act, src, [&](long long c, int m, T sc, T tc) {
+        tv.p[m][c] = tc;
+        acc[m] += (double)tc * (double)sc;
+        acc[3 + m] += (double)tc * (double)tc;
+        acc[6 + m] += (double)sc * (double)sc;
+    });
     block_reduce<9>(acc, sh);
     const int so[3] = {CS_TS, CS_TT, CS_SS};
     write_partials<3>(part, so, acc);
 }
 
-// Pass X of iteration it (elementwise; same blocks and tiles as the stencil passes).
+// Pass X of iteration it: omega; x += alpha p + omega s; r = s - omega t (s is in r).
 template <class T>
-__global__ void __launch_bounds__(NT) k_cn_x(Geo g, V3<T> x, V3<T> r, C3<T> r0, C3<T> p, C3<T> v, C3<T> tv,
-                                             double* part, int nparts, int it, CnState* cs) {
+__global__ void __launch_bounds__(NT) k_cn_x(Geo g, V3<T> x, V3<T> r, C3<T> r0, C3<T> p, C3<T> tv, double* part,
+                                             int nparts, int it, CnState* cs) {
     if (block_done(cs)) return;
     __shared__ double sh[4 * 9];
     const int par = it & 1;
@@ -434,26 +467,20 @@ __global__ void __launch_bounds__(NT) k_cn_x(Geo g, V3<T> x, V3<T> r, C3<T> r0, 
     }
     if (broke) return;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        const long long c = cidx(g, i, j, k);
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    CN_CELLS(c, N) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             if (!act[m]) continue;
-            const T sc = r.p[m][c] - alpha[m] * v.p[m][c];
-            T xn, rn;
+            const T sc = r.p[m][c];
+            T rn = sc;
             if (sconv[m]) {
-                xn = x.p[m][c] + alpha[m] * p.p[m][c];
-                rn = sc;
+                x.p[m][c] = x.p[m][c] + alpha[m] * p.p[m][c];
             } else {
-                xn = x.p[m][c] + alpha[m] * p.p[m][c] + omega[m] * sc;
+                x.p[m][c] = x.p[m][c] + alpha[m] * p.p[m][c] + omega[m] * sc;
                 rn = sc - omega[m] * tv.p[m][c];
+                r.p[m][c] = rn;
             }
-            x.p[m][c] = xn;
-            r.p[m][c] = rn;
             acc[m] += (double)r0.p[m][c] * (double)rn;
             acc[3 + m] += (double)rn * (double)rn;
         }
@@ -490,7 +517,7 @@ __global__ void k_cn_reset(CnState* cs) {
     }
 }
 
-// workspace vector w (0 x, 1 r, 2 r0, 3-4 p, 5-6 v, 7 t), component m
+// workspace vector w (0 x, 1 r, 2 r0, 3 p, 4 v, 5 t), component m
 template <class T>
 inline T* ws_vec(ibm_ctx* c, int w, int m) {
     return (T*)c->cn_ws + ((long long)w * 3 + m) * c->N;
@@ -501,7 +528,7 @@ int cn_solve_t(ibm_ctx* c, const T* const* b, T* const* x, double* const* U, con
                double tol, int max_iter, int iters[3], hipStream_t s) {
     const Geo& g = c->geo;
     const Sten st = sten_of(c);
-    const int nb = grid_blocks(g);
+    const int nb = march_blocks(g);   // the marching passes set the count; all passes share it
     const C3<double> UU{{U[0], U[1], U[2]}};
     const T tnu = (T)nu, hdt = (T)(0.5 * dt);
     auto cv = [&](int w) { return C3<T>{{ws_vec<T>(c, w, 0), ws_vec<T>(c, w, 1), ws_vec<T>(c, w, 2)}}; };
@@ -512,34 +539,38 @@ int cn_solve_t(ibm_ctx* c, const T* const* b, T* const* x, double* const* U, con
     k_cn_reset<<<1, 64, 0, s>>>(c->cn_state);
     k_cn_init<T><<<nb, NT, 0, s>>>(g, st, UU, nut, tnu, hdt, bb, xc, vv(1), vv(2), c->cn_part);
     IBM_HIP(hipGetLastError());
-    // passes in order P_0 S_0 X_0 P_1 ...; every batch ends with a pass P, whose stop
-    // test the host then reads
+    // passes in order D_0 AP_0 S_0 AS_0 X_0 D_1 ...; every batch ends with a pass D,
+    // whose stop test the host then reads
+    constexpr int NP = 5;
     long long pass = 0;
     auto launch = [&](long long q) {
-        const int it = (int)(q / 3), kind = (int)(q % 3);
-        const int pn = 3 + (it & 1), po = 3 + ((it + 1) & 1);
-        const int vn = 5 + (it & 1), vo = 5 + ((it + 1) & 1);
+        const int it = (int)(q / NP), kind = (int)(q % NP);
         if (kind == 0)
-            launch_timed(c, TK_CN_P, k_cn_p<T>, nb, s, g, st, UU, nut, tnu, hdt, xx, cv(1), cv(2), cv(po), cv(vo),
-                         vv(pn), vv(vn), c->cn_part, nb, it, max_iter, tol, c->cn_state);
+            launch_timed(c, TK_CN_D, k_cn_dir<T>, nb, s, g, xx, cv(1), vv(3), cv(4), c->cn_part, nb, it, max_iter, tol,
+                         c->cn_state);
         else if (kind == 1)
-            launch_timed(c, TK_CN_S, k_cn_s<T>, nb, s, g, st, UU, nut, tnu, hdt, cv(1), cv(vn), vv(7), c->cn_part,
-                         nb, it, c->cn_state);
+            launch_timed(c, TK_CN_AP, k_cn_ap<T>, nb, s, g, st, UU, nut, tnu, hdt, cv(3), vv(4), cv(2), c->cn_part, it,
+                         c->cn_state);
+        else if (kind == 2)
+            launch_timed(c, TK_CN_S, k_cn_s<T>, nb, s, g, vv(1), cv(4), c->cn_part, nb, it, c->cn_state);
+        else if (kind == 3)
+            launch_timed(c, TK_CN_AS, k_cn_as<T>, nb, s, g, st, UU, nut, tnu, hdt, cv(1), vv(5), c->cn_part, it,
+                         c->cn_state);
         else
-            launch_timed(c, TK_CN_X, k_cn_x<T>, nb, s, g, xx, vv(1), cv(2), cv(pn), cv(vn), cv(7), c->cn_part, nb,
-                         it, c->cn_state);
+            launch_timed(c, TK_CN_X, k_cn_x<T>, nb, s, g, xx, vv(1), cv(2), cv(3), cv(5), c->cn_part, nb, it,
+                         c->cn_state);
     };
     int batch = c->cn_last_iters > 0 ? c->cn_last_iters + 1 : 4;
     while (true) {
-        // iterations pass/3 .. pass/3 + batch - 1, then the next pass P
-        const long long end = (pass / 3 + batch) * 3;
-        const long long last = end < 3LL * max_iter ? end : 3LL * max_iter;
+        // iterations pass/NP .. pass/NP + batch - 1, then the next pass D
+        const long long end = (pass / NP + batch) * NP;
+        const long long last = end < (long long)NP * max_iter ? end : (long long)NP * max_iter;
         for (; pass <= last; ++pass) launch(pass);
         IBM_HIP(hipGetLastError());
         IBM_HIP(hipMemcpyAsync(c->h_cn_state, c->cn_state, sizeof(CnState), hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
         if (c->h_cn_state->done) break;
-        if (pass > 3LL * max_iter) {
+        if (pass > (long long)NP * max_iter) {
             set_error("momentum solve: state not final after the iteration cap");
             return IBM_ERR_HIP;
         }
@@ -568,7 +599,7 @@ int cn_solve_t(ibm_ctx* c, const T* const* b, T* const* x, double* const* U, con
 int cn_prepare(ibm_ctx* c) {
     if (c->cn_ws) return IBM_OK;
     const size_t ts = c->precision == IBM_FP64 ? sizeof(double) : sizeof(float);
-    const size_t bytes = ts * 24 * (size_t)c->N;
+    const size_t bytes = ts * 18 * (size_t)c->N;
     hipError_t e = hipMalloc(&c->cn_ws, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -588,12 +619,12 @@ int cn_apply(ibm_ctx* c, const void* const* q, double* const* U, const void* nut
     const Geo& g = c->geo;
     const C3<double> UU{{U[0], U[1], U[2]}};
     if (c->precision == IBM_FP64) {
-        k_cn_apply<double><<<grid_blocks(g), NT, 0, s>>>(
+        k_cn_apply<double><<<march_blocks(g), NT, 0, s>>>(
             g, sten_of(c), UU, (const double*)nut, nu, 0.5 * dt,
             C3<double>{{(const double*)q[0], (const double*)q[1], (const double*)q[2]}},
             V3<double>{{(double*)out[0], (double*)out[1], (double*)out[2]}});
     } else {
-        k_cn_apply<float><<<grid_blocks(g), NT, 0, s>>>(
+        k_cn_apply<float><<<march_blocks(g), NT, 0, s>>>(
             g, sten_of(c), UU, (const float*)nut, (float)nu, (float)(0.5 * dt),
             C3<float>{{(const float*)q[0], (const float*)q[1], (const float*)q[2]}},
             V3<float>{{(float*)out[0], (float*)out[1], (float*)out[2]}});

@@ -39,12 +39,6 @@ struct Slabs {
     long long items; // tiles_xy * nzc
 };
 
-__host__ __device__ inline int slab_count(int nz) {
-    int want = (nz + 31) / 32;               // about 32 planes per slab
-    want = ((want + 7) / 8) * 8;             // multiple of the XCD count
-    if (want > nz) want = nz;
-    return want < 1 ? 1 : want;
-}
 
 // (L x)_c from the pressure code and the three planes of the column
 __device__ inline double lap_code(uint8_t pc, double xc, double xw, double xe, double xs, double xn, double xb,
