@@ -385,23 +385,50 @@ def csm_nut(st: Stencil, u: list, c1: float = 1.0 / 20.0, wall=None) -> np.ndarr
 
 # ------------------------------------------------------------ predictor
 
-def momentum_rhs(st: Stencil, u: list, U: list, nut: np.ndarray, nu: float, body, wall) -> list:
+def second_neighbour(st: Stencil, q: np.ndarray, m: int, d: int, wall, n1: np.ndarray) -> np.ndarray:
+    """Value of component m two cells away across face d (the far cell of a QUICK
+    stencil, the S2 ghost of the dummy cells, Sec. 2.3.1): across an open interior face,
+    the neighbour's own value across its face d (its ghost or domain-face ghost where
+    that face is closed); across a blocked or domain face, the ghost line of n1 continued
+    one cell further, 2 n1 - q (Reading Q2).  n1 = neighbour(st, q, m, d, wall)."""
+    g = st.grid
+    k, s = d // 2, (1 if d % 2 else -1)
+    closed = boundary_mask(g, d) | (((st.blocked >> d) & 1) == 1)
+    far = shifted(n1, k, s)
+    return np.where(closed, 2.0 * n1 - q, far)
+
+
+def quick_face(q, n1, n2, b1, out):
+    """QUICK face value (Leonard, 1979) between a cell (q) and its neighbour across the
+    face (n1): with the flow leaving the cell through the face (out), upstream q,
+    downstream n1 and far upstream b1 (the cell's value across its opposite face):
+    (6 q + 3 n1 - b1)/8; otherwise upstream n1, downstream q, far upstream n2:
+    (6 n1 + 3 q - n2)/8."""
+    return np.where(out, (6.0 * q + 3.0 * n1 - b1) / 8.0, (6.0 * n1 + 3.0 * q - n2) / 8.0)
+
+
+def momentum_rhs(st: Stencil, u: list, U: list, nut: np.ndarray, nu: float, body, wall, quick: float = 0.0) -> list:
     """H = -(1/dx) sum_f s U_f q_f + (1/dx^2) sum_f (nu + nu_t,f)(q_nb - q_c) + g,
     flux form with the stored face velocity U^n (Sec. 2.1; on blocked faces it
-    holds the wall normal velocity of the last projection), central face value q_f, and the
-    ghost of eq. (q_axis) behind blocked faces (direct forcing of eq. (forcing_term)
-    realised through the ghost, Reading R9)."""
+    holds the wall normal velocity of the last projection), the ghost of eq. (q_axis)
+    behind blocked faces (direct forcing of eq. (forcing_term) realised through the
+    ghost, Reading R9) and the face value q_f of the hybrid scheme (Sec. 3): central
+    (q + q_nb)/2 blended with the QUICK value by the weight `quick` (0.1 in the paper's
+    Ahmed-body and sphere runs; 0 = pure central)."""
     g = st.grid
     H = []
     for m in range(3):
         q = u[m]
         h = np.full(g.shape, float(body[m]))
+        nbs = [neighbour(st, q, m, d, wall) for d in range(6)]
         for d in range(6):
             s = 1 if d % 2 else -1
-            qn = neighbour(st, q, m, d, wall)
-            k = d // 2
+            qn = nbs[d]
             Uf = face_velocity(g, U, d)
             qf = 0.5 * (q + qn)
+            if quick != 0.0:
+                qq = quick_face(q, qn, second_neighbour(st, q, m, d, wall, qn), nbs[d ^ 1], s * Uf > 0.0)
+                qf = (1.0 - quick) * qf + quick * qq
             h = h - s * Uf * qf / g.dx + (nu + face_nut(st, nut, d)) * (qn - q) / (g.dx * g.dx)
         H.append(h)
     return H
@@ -421,10 +448,10 @@ def dead_velocity(st: Stencil, wall) -> list:
     return out
 
 
-def predictor(st, u, U, hprev, nut, nu, dt, body, step, wall, dt_prev=0.0):
+def predictor(st, u, U, hprev, nut, nu, dt, body, step, wall, dt_prev=0.0, quick=0.0):
     """u* = u^n + dt ((1 + r/2) H^n - (r/2) H^{n-1}), r = dt/dt_prev: second-order
     Adams-Bashforth with a variable step (r = 1 gives 3/2, -1/2); forward Euler at step 0."""
-    H = momentum_rhs(st, u, U, nut, nu, body, wall)
+    H = momentum_rhs(st, u, U, nut, nu, body, wall, quick)
     us = []
     dv = dead_velocity(st, wall) if st.deadend.any() else None
     r = dt / dt_prev if dt_prev > 0 else 1.0
@@ -534,16 +561,18 @@ def cn_matrix_apply(st: Stencil, q: np.ndarray, m: int, U: list, nut: np.ndarray
     return np.where(st.deadend, q, a)
 
 
-def cn_predictor(st, u, U, nut, nu, dt, body, wall, tol, max_iter):
+def cn_predictor(st, u, U, nut, nu, dt, body, wall, tol, max_iter, quick=0.0):
     """Crank-Nicolson predictor of eq. (crank-nicolson): advection (by the frozen U^n)
     and diffusion both taken half at u^n and half at u*, the wall, inflow and body
     terms whole.  With H the full right-hand side and L its linear part
     (momentum_operator), u* - u^n = dt [H(u^n) + L(u* - u^n)/2], so the increment
     delta = u* - u^n solves (I - dt/2 L) delta = dt H^n, one system per component,
     solved by BiCGStab from delta_0 = dt H^n (the explicit Euler increment).
-    Dead-end cells are pinned at their mean wall velocity (identity rows).
+    Dead-end cells are pinned at their mean wall velocity (identity rows).  With a QUICK
+    blend the blended part of the face value stays explicit (in H^n only; L is the
+    central operator, Reading Q3).
     Returns (u*, H^n with zeros at dead-end cells, iterations per component)."""
-    H = momentum_rhs(st, u, U, nut, nu, body, wall)
+    H = momentum_rhs(st, u, U, nut, nu, body, wall, quick)
     dead = st.deadend
     dv = dead_velocity(st, wall) if dead.any() else None
     us, iters = [], []
@@ -717,6 +746,7 @@ class StepParams:
     scheme: str = "ab2"        # "ab2" (explicit) or "cn" (Crank-Nicolson + BiCGStab)
     mom_tol: float = 1e-10     # cn: relative residual of each component's system
     mom_max_iter: int = 200    # cn: BiCGStab iteration cap
+    quick: float = 0.0         # weight of the QUICK face value in the hybrid scheme
 
 
 def step(st: Stencil, u, U, p, hprev, prm: StepParams, step_index: int, wall=None):
@@ -728,9 +758,10 @@ def step(st: Stencil, u, U, p, hprev, prm: StepParams, step_index: int, wall=Non
     mom_iters = [0, 0, 0]
     if prm.scheme == "cn":
         us, H, mom_iters = cn_predictor(st, u, U, nut, prm.nu, prm.dt, prm.body, wall, prm.mom_tol,
-                                        prm.mom_max_iter)
+                                        prm.mom_max_iter, prm.quick)
     elif prm.scheme == "ab2":
-        us, H = predictor(st, u, U, hprev, nut, prm.nu, prm.dt, prm.body, step_index, wall, prm.dt_prev)
+        us, H = predictor(st, u, U, hprev, nut, prm.nu, prm.dt, prm.body, step_index, wall, prm.dt_prev,
+                          prm.quick)
     else:
         raise ValueError(prm.scheme)
     Us = face_predicted(st, us, wall)
