@@ -91,6 +91,10 @@ typedef struct {
  * scheme IBM_SCHEME_AB2: variable-step Adams-Bashforth,
  *   u* = u + dt [(1 + r/2) H^n - (r/2) H^{n-1}], r = dt/dt_prev (dt_prev <= 0 means
  *   dt_prev = dt, the constant-step 3/2, -1/2 weights); forward Euler when step == 0.
+ * Advective face value: central, or with quick > 0 the hybrid of Sec. 3 blending the
+ * QUICK value (Leonard 1979: (6 q_up + 3 q_down - q_farup)/8, upstream by the outward
+ * face velocity); the far cell across a blocked or domain face is the first ghost's
+ * line continued one cell (2 q_GC - q_c), elsewhere the neighbour's own neighbour.
  * scheme IBM_SCHEME_CN: Crank-Nicolson for advection (by the frozen face velocity U^n)
  *   and diffusion (nu + the eddy viscosity of u^n) together, eq. (crank-nicolson):
  *   with H the explicit right-hand side and L its part linear in u,
@@ -112,6 +116,10 @@ typedef struct {
     int32_t scheme;         /* IBM_SCHEME_AB2 or IBM_SCHEME_CN                       */
     int32_t mom_max_iter;   /* CN: BiCGStab iteration cap (<= 0: 200)                */
     double mom_tol;         /* CN: relative residual per component (<= 0: 1e-10)     */
+    double quick;           /* weight w of the QUICK face value in the advective     */
+                            /* flux, q_f = (1 - w) q_central + w q_QUICK (Sec. 3:    */
+                            /* 0.1 in the paper's runs; 0 = central); explicit in    */
+                            /* both schemes (the CN operator keeps central)          */
 } ibm_step_params;
 
 typedef struct {

@@ -49,6 +49,28 @@ __device__ inline void nbvals(const Geo& g, const Sten& st, const T* q, int m, i
     }
 }
 
+// Value of component m two cells away across face d of cell (i, j, k), that face being
+// open (interior or periodic): the neighbour's own value across its face d, i.e. its
+// eq. (q_axis) ghost where that face is blocked, its domain-face ghost at a domain
+// face, else the next cell (the far cell of a QUICK stencil).
+template <class T>
+__device__ inline double far_value(const Geo& g, const Sten& st, const T* q, int m, int i, int j, int k, int d,
+                                   const double* wall) {
+    const int ax = d >> 1;
+    const int n_ax = ax == 0 ? g.nx : (ax == 1 ? g.ny : g.nz);
+    int co = (ax == 0 ? i : (ax == 1 ? j : k)) + ((d & 1) ? 1 : -1);
+    co = co < 0 ? co + n_ax : (co >= n_ax ? co - n_ax : co);
+    const int ii = ax == 0 ? co : i, jj = ax == 1 ? co : j, kk = ax == 2 ? co : k;
+    const long long n = cidx(g, ii, jj, kk);
+    const uint8_t mn = st.mask[n];
+    const double qn = (double)q[n];
+    if ((mn >> d) & 1) return ghost(st, q, n, mn, d, m, wall, qn);
+    bool bnd;
+    const long long nn = nb_index(g, ii, jj, kk, d, bnd);
+    if (bnd) return bc_ghost(g, d, m, qn);
+    return (double)q[nn];
+}
+
 // Coherent structure model (Sec. 2.3): G_ij by central differences, S, W, Q, E,
 // F_CS = Q/E, C = C1 |F_CS|^(3/2), nu_t = C dx^2 sqrt(S_ij S_ij).
 template <class T>
@@ -94,6 +116,10 @@ __global__ void __launch_bounds__(NT) k_csm(Geo g, Sten st, C3<T> u, const doubl
 // u* = u + dt (3/2 H - 1/2 H_prev), forward Euler on the first step.  q_nb is the
 // eq. (q_axis) ghost behind blocked faces, which realises the direct forcing of
 // eq. (forcing_term).  Dead-end cells are frozen at their mean wall velocity.
+// The face value is the hybrid of Sec. 3: the central (q_c + q_nb)/2 blended with
+// weight `quick` with the QUICK value (Leonard 1979) (6 q_up + 3 q_down - q_farup)/8,
+// upstream by the sign of the outward face velocity; the far cell beyond a blocked or
+// domain face is the first ghost's line continued, 2 q_nb - q_c.
 // With cn set (Crank-Nicolson, eq. (crank-nicolson)) the kernel writes instead the
 // right-hand side dt H of the increment system into rhs (dv - u at dead-end cells) and
 // u* only at dead-end cells (dv); H goes to hio as in the explicit form.
@@ -101,7 +127,7 @@ template <class T>
 __global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<double> U, const T* nut, V3<T> hio,
                                                 V3<T> us, const double* wall, double dt, double w_now,
                                                 double w_prev, double nu, double bx, double by, double bz,
-                                                int first, int cn, V3<T> rhs) {
+                                                int first, int cn, V3<T> rhs, double quick) {
     long long t0, t1;
     tile_range(g, t0, t1);
     const double body[3] = {bx, by, bz};
@@ -142,6 +168,19 @@ __global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<doub
             for (int d = 0; d < 6; ++d) {
                 T s = (d & 1) ? (T)1 : (T)-1;
                 T qf = (T)0.5 * (qc + nb[d]);
+                if (quick != 0.0) {
+                    T qq;
+                    if (s * Uf[d] > (T)0) {
+                        qq = ((T)6 * qc + (T)3 * nb[d] - nb[d ^ 1]) / (T)8;
+                    } else {
+                        bool bnd;
+                        (void)nb_index(g, i, j, k, d, bnd);
+                        const T n2 = (bnd || ((msk >> d) & 1)) ? (T)2 * nb[d] - qc
+                                                               : (T)far_value(g, st, u.p[m], m, i, j, k, d, wall);
+                        qq = ((T)6 * nb[d] + (T)3 * qc - n2) / (T)8;
+                    }
+                    qf = (T)(1.0 - quick) * qf + (T)quick * qq;
+                }
                 h = h - s * Uf[d] * qf * idx + visc[d] * (nb[d] - qc) * idx2;
             }
             T v;
@@ -475,7 +514,7 @@ int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, co
     }
     k_predict<T><<<nb, NT, 0, s>>>(g, st, uu, UU, nut, hh, us, wall, prm->dt, 1.0 + 0.5 * r, 0.5 * r, prm->nu,
                                    prm->body_force[0], prm->body_force[1], prm->body_force[2],
-                                   prm->step == 0 ? 1 : 0, cn ? 1 : 0, rhs);
+                                   prm->step == 0 ? 1 : 0, cn ? 1 : 0, rhs, prm->quick);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
