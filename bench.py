@@ -213,6 +213,7 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
             raise SystemExit("%s: step %d did not converge (rc=%d)" % (solver, step, rc))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    pred = ibm.ibm_timing_slot(s.ctx, 9, reset=True)
     tim = ibm.ibm_timing_read(s.ctx, reset=True)
     ibm.ibm_timing_enable(s.ctx, False)
     if cb is not None:
@@ -236,6 +237,11 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
                         "sweeps_ms": {SWEEP_NAMES[k]: round(tim["ms"][k], 2) for k in range(3)}}}
     if solver == args.solver:
         out["surface_force"] = shepard_timing(case, s, st, torch)
+    if solver == "pcg_fp64":
+        out["predictor"] = predictor_record(case, pred, "central")
+        if args.quick_steps > 0:
+            out["hybrid_quick"] = quick_timing(case, s, st, ctl, step, args, ibm, torch)
+            step += 2 + args.quick_steps
     if solver == "pcg_fp64" and args.cn_steps > 0:
         out["crank_nicolson"] = cn_timing(case, s, st, ctl, step, args, ibm, torch)
     if solver == "mixed_learned":
@@ -291,6 +297,61 @@ CN_KERNELS = {"cn_direction": "k_cn_dir<double>", "cn_apply_p": "k_cn_ap<double>
               "cn_apply_s": "k_cn_as<double>", "cn_update": "k_cn_x<double>"}
 CN_BYTES_PER_CELL = {"cn_direction": 96, "cn_apply_p": 105, "cn_stabilise": 72, "cn_apply_s": 81,
                      "cn_update": 168}
+
+
+# momentum predictor kernel k_predict<double>: reads u, U, H^{n-1} (24 B each), nu_t
+# (8 B) and the mask, writes u* and H (24 B each)
+PREDICT_BYTES_PER_CELL = 129
+
+
+def predictor_record(case, slot, face):
+    N = case.n[0] * case.n[1] * case.n[2]
+    ms, launches = slot
+    avg = ms / 1e3 / max(launches, 1)
+    return {"kernel": "k_predict<double>", "face_value": face, "launches": launches,
+            "avg_launch_us": round(avg * 1e6, 2), "bytes_per_cell": PREDICT_BYTES_PER_CELL,
+            "achieved_gbs": round(PREDICT_BYTES_PER_CELL * N / avg / 1e9, 1) if avg > 0 else None,
+            "frac": round(PREDICT_BYTES_PER_CELL * N / avg / 1e9 / HBM_PEAK_GBS, 4) if avg > 0 else None}
+
+
+def quick_timing(case, s, st, ctl, step, args, ibm, torch):
+    """The hybrid face value of Sec. 3 (central blended with args.quick of QUICK) on the
+    developed plain FP64 state, explicit scheme at the benchmark's CFL 0.3: whole steps
+    by the host clock and the predictor kernel by dispatch events (slot 9)."""
+    N = case.n[0] * case.n[1] * case.n[2]
+
+    def prm(k):
+        dt = min(case.dt, 0.3 * case.dx / max(ctl["umax"], 1e-30))
+        p = ibm.step_params(dt, case.nu, csm=case.csm, step=k, dt_prev=ctl["dt_prev"], tol=args.tol, max_iter=20000,
+                            check_every=16, quick=args.quick)
+        ctl["dt_prev"] = dt
+        return p
+    for _ in range(2):
+        rc, stats = s.step(st, prm(step))
+        ctl["umax"] = stats["umax"]
+        step += 1
+    ibm.ibm_timing_enable(s.ctx, True)
+    ibm.ibm_timing_read(s.ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.quick_steps):
+        rc, stats = s.step(st, prm(step))
+        if rc != 0:
+            raise SystemExit("hybrid QUICK step did not converge (rc=%d)" % rc)
+        ctl["umax"] = stats["umax"]
+        step += 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pred = ibm.ibm_timing_slot(s.ctx, 9, reset=True)
+    ibm.ibm_timing_read(s.ctx, reset=True)
+    ibm.ibm_timing_enable(s.ctx, False)
+    rec = predictor_record(case, pred, "central + %g QUICK" % args.quick)
+    return {"weight": args.quick, "steps": args.quick_steps, "ms_per_step": round(elapsed / args.quick_steps * 1e3, 2),
+            "value": N * args.quick_steps / elapsed, "predictor": rec,
+            "roofline": {"bound": "hbm", "achieved": rec["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": rec["frac"], "traffic": committed_traffic("predict", args.workload),
+                         "kernel": rec["kernel"], "algorithmic_bytes_per_launch": PREDICT_BYTES_PER_CELL * N,
+                         "avg_launch_us": rec["avg_launch_us"]}}
 
 
 def cn_timing(case, s, st, ctl, step, args, ibm, torch):
@@ -399,6 +460,9 @@ def main():
     ap.add_argument("--cn-steps", type=int, default=5,
                     help="Crank-Nicolson steps timed after the plain FP64 run (0: none)")
     ap.add_argument("--mom-tol", type=float, default=1e-10, help="Crank-Nicolson momentum solve tolerance")
+    ap.add_argument("--quick-steps", type=int, default=5,
+                    help="explicit steps with the hybrid central/QUICK face value timed after the plain run (0: none)")
+    ap.add_argument("--quick", type=float, default=0.1, help="QUICK weight of the hybrid face value")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (collectives and sharding are not part of it); "
@@ -468,7 +532,8 @@ def main():
                    "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm},
         "plain_fp64_value": plain["value"] if plain else None,
         "speedup_vs_plain_fp64": head["value"] / plain["value"] if plain else None,
-        "solvers": {k: {kk: vv for kk, vv in v.items() if kk not in ("dominant", "crank_nicolson")}
+        "solvers": {k: {kk: vv for kk, vv in v.items()
+                        if kk not in ("dominant", "crank_nicolson", "hybrid_quick", "predictor")}
                     for k, v in runs.items()},
         "speedups_vs_plain_fp64": {k: round(v["value"] / plain["value"], 4) for k, v in runs.items()} if plain else None,
         "training": train_info,
@@ -476,6 +541,8 @@ def main():
         "roofline_sweeps": roofline_sweeps,
         "surface_force": head.get("surface_force"),
         "crank_nicolson": plain.get("crank_nicolson") if plain else None,
+        "hybrid_quick": plain.get("hybrid_quick") if plain else None,
+        "predictor": plain.get("predictor") if plain else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

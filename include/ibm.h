@@ -351,7 +351,9 @@ int ibm_timing_read(ibm_ctx* ctx, double out[10], int32_t reset);
 /* One timed slot: out[0] = accumulated milliseconds, out[1] = launches; reset != 0 zeroes
  * that slot.  Slots 0-2 as above, 3 = the near-field force kernel, 4-8 = the five
  * BiCGStab passes of the Crank-Nicolson predictor (4: new direction p; 5: v = A p;
- * 6: s = r - alpha v; 7: t = A s; 8: update of x and r). */
+ * 6: s = r - alpha v; 7: t = A s; 8: update of x and r), 9 = the momentum predictor
+ * kernel of ibm_step (right-hand side H with its face values, and the AB2 update or
+ * the Crank-Nicolson right-hand side). */
 int ibm_timing_slot(ibm_ctx* ctx, int32_t slot, double out[2], int32_t reset);
 
 #ifdef __cplusplus

@@ -57,7 +57,7 @@ struct CnState {
     int done;                   // every component stopped: later passes return at once
 };
 enum { CN_RUNNING = 0, CN_CONVERGED = 1, CN_MAXITER = 2, CN_BREAKDOWN = 3, CN_NAN = 4 };
-constexpr int TK_SLOTS_MAX = 9;  // timed kernel slots (the TK_* launch slots)
+constexpr int TK_SLOTS_MAX = 10;  // timed kernel slots (the TK_* launch slots)
 
 }  // namespace ibm
 
@@ -309,9 +309,10 @@ int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s);
 // timing helpers (poisson.hip)
 // timed kernel slots: the two CG passes (or the preconditioner and the passes of the
 // learned solve), the dominant convolution of the learned preconditioner, spare
-// (other), and the five BiCGStab passes of the Crank-Nicolson predictor
+// (other), the five BiCGStab passes of the Crank-Nicolson predictor, the momentum
+// right-hand side / predictor kernel
 enum { TK_SPMV = 0, TK_UPDATE = 1, TK_DIR = 2, TK_OTHER = 3, TK_CN_D = 4, TK_CN_AP = 5, TK_CN_S = 6, TK_CN_AS = 7,
-       TK_CN_X = 8 };
+       TK_CN_X = 8, TK_PREDICT = 9 };
 // Launches kern<<<grid, NT, 0, s>>>(args...).  When timing slot k is on, the launch
 // carries HIP's dispatch-level start/stop events (hipExtLaunchKernelGGL), so the time
 // collected is the kernel's own, without the gaps between dispatches.

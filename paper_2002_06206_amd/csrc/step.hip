@@ -512,10 +512,10 @@ int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, co
         T* x = (T*)c->cn_ws;
         for (int a = 0; a < 3; ++a) rhs.p[a] = x + (long long)a * c->N;
     }
-    k_predict<T><<<nb, NT, 0, s>>>(g, st, uu, UU, nut, hh, us, wall, prm->dt, 1.0 + 0.5 * r, 0.5 * r, prm->nu,
-                                   prm->body_force[0], prm->body_force[1], prm->body_force[2],
-                                   prm->step == 0 ? 1 : 0, cn ? 1 : 0, rhs, prm->quick);
-    IBM_HIP(hipGetLastError());
+    launch_timed(c, TK_PREDICT, k_predict<T>, nb, s, g, st, uu, UU, (const T*)nut, hh, us, wall, prm->dt,
+                 1.0 + 0.5 * r, 0.5 * r, prm->nu, prm->body_force[0], prm->body_force[1], prm->body_force[2],
+                 prm->step == 0 ? 1 : 0, cn ? 1 : 0, rhs, prm->quick);
+    IBM_HIP(hipGetLastError());   // its events are collected after the solve's next synchronisation
     return IBM_OK;
 }
 
