@@ -45,7 +45,8 @@ enum { IBM_FP64 = 0, IBM_MIXED = 1 };
 enum {
     IBM_SOLVER_PCG_JACOBI = 0, /* FP64 Jacobi-preconditioned CG                          */
     IBM_SOLVER_FCG_CNN = 1,    /* FP64 refinement around FP32 flexible CG, CNN precond.   */
-    IBM_SOLVER_FCG_JACOBI = 2  /* FP64 refinement around FP32 flexible CG, Jacobi precond.*/
+    IBM_SOLVER_FCG_JACOBI = 2, /* FP64 refinement around FP32 flexible CG, Jacobi precond.*/
+    IBM_SOLVER_RBSOR = 3       /* FP64 red-black SOR (Sec. 2.1)                          */
 };
 /* momentum predictor of ibm_step: explicit Adams-Bashforth, or Crank-Nicolson with
  * BiCGStab (eq. (crank-nicolson), Sec. 2.1) */
@@ -84,6 +85,13 @@ typedef struct {
                              /* reduces the FP64 residual by less than this factor  */
     int32_t check_every;     /* iterations enqueued between host convergence polls  */
     int32_t force_stall;     /* test hook: 1 = treat the first sweep as stalled      */
+    double omega;            /* IBM_SOLVER_RBSOR: relaxation factor in (0, 2); <= 0: */
+                             /* 2 / (1 + sin(pi / n_max)).  Cells are coloured by the */
+                             /* parity of i + j + k; a sweep updates colour 0, then 1, */
+                             /* x_c += omega (b_c - (L x)_c) / L_cc; the true residual */
+                             /* is tested every check_every sweeps; max_iter counts  */
+                             /* sweeps.  Periodic axes need an even cell count       */
+                             /* (IBM_ERR_ARG otherwise).                              */
 } ibm_solver_opts;
 
 /* One time step: momentum predictor, coherent structure model (Sec. 2.3) when csm_on,

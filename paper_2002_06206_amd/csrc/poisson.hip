@@ -23,6 +23,8 @@
 
 #include <type_traits>
 
+#include <cmath>
+
 #include "common.h"
 
 namespace ibm {
@@ -1495,6 +1497,107 @@ int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts*
         s);
 }
 
+// ------------------------------------------------------------- red-black SOR
+
+// One half sweep of red-black successive over-relaxation on L x = b (Sec. 2.1): every
+// cell of the given colour (parity of i + j + k) with L_cc != 0 gets
+// x_c += omega (b_c - (L x)_c) / L_cc.  All neighbours of such a cell have the other
+// colour (periodic axes have even counts, checked by the host), so the cells of one
+// half sweep read only values that it does not write.  Columns of (tile, z-slab) items
+// as in the conjugate-gradient passes.
+__global__ void __launch_bounds__(NT) k_sor(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ b,
+                                            double* __restrict__ x, int colour, double omega) {
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    const int nzc = slab_count(g.nz);
+    const long long tiles = (long long)g.ntx * g.nty;
+    const long long items = tiles * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
+    for (long long w = w0; w < w1; ++w) {
+        const int zc = (int)(w / tiles);
+        const long long t = w % tiles;
+        const int i = (int)(t % g.ntx) * TX + (threadIdx.x % TX);
+        const int j = (int)(t / g.ntx) * TY + (threadIdx.x / TX);
+        const int z0 = (int)((long long)g.nz * zc / nzc), z1 = (int)((long long)g.nz * (zc + 1) / nzc);
+        if (i >= g.nx || j >= g.ny) continue;
+        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i == g.nx - 1 ? 0 : i + 1;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+        const long long col = (long long)i + (long long)g.nx * j;
+        const long long ow = (long long)iw + (long long)g.nx * j - col;
+        const long long oe = (long long)ie + (long long)g.nx * j - col;
+        const long long os = (long long)i + (long long)g.nx * js - col;
+        const long long on = (long long)i + (long long)g.nx * jn - col;
+        // first plane of the slab with the wanted colour, then every second plane
+        const int k0 = z0 + (((i + j + z0) & 1) != colour ? 1 : 0);
+        for (int k = k0; k < z1; k += 2) {
+            const long long c = col + plane * k;
+            const uint8_t pc = pcode[c];
+            const double cnt = jacobi_count(pc);
+            if (cnt == 0.0) continue;
+            const int zb = k == 0 ? g.nz - 1 : k - 1, zt = k == g.nz - 1 ? 0 : k + 1;
+            const double xc = x[c];
+            const double lx = lap_code(pc, xc, x[c + ow], x[c + oe], x[c + os], x[c + on], x[col + plane * zb],
+                                       x[col + plane * zt], idx2);
+            x[c] = xc + omega * (b[c] - lx) / (-cnt * idx2);
+        }
+    }
+}
+
+// Red-black SOR on L x = b (b already compatible); x in/out.  The true residual is
+// tested every check_every sweeps (and at the cap); sets *sweeps.
+static int rbsor64(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, int* sweeps, hipStream_t s) {
+    const Geo& g = c->geo;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    for (int k = 0; k < 3; ++k)
+        if (g.bc[2 * k] == IBM_BC_PERIODIC && (n[k] & 1)) {
+            set_error("red-black SOR: periodic axes need an even number of cells");
+            return IBM_ERR_ARG;
+        }
+    const int nmax = n[0] > n[1] ? (n[0] > n[2] ? n[0] : n[2]) : (n[1] > n[2] ? n[1] : n[2]);
+    const double omega = o->omega > 0.0 ? o->omega : 2.0 / (1.0 + sin(M_PI / (double)nmax));
+    if (!(omega > 0.0 && omega < 2.0)) {
+        set_error("red-black SOR: need 0 < omega < 2");
+        return IBM_ERR_ARG;
+    }
+    const int check = o->check_every > 0 ? o->check_every : 16;
+    const int nb = march_blocks(g);
+    int it = 0;
+    *sweeps = 0;
+    while (true) {
+        double rel = 0.0;
+        if (int rc = true_residual(c, b, x, &rel, s)) return rc;
+        if (c->h_red[1] == 0.0) {   // b = 0: x = 0
+            k_zero_f64<<<1024, 256, 0, s>>>(c->N, x);
+            IBM_HIP(hipGetLastError());
+            break;
+        }
+        if (!(rel == rel)) {
+            set_error("red-black SOR: non-finite residual");
+            return IBM_ERR_NAN;
+        }
+        if (c->progress) c->progress(c->progress_user, it, rel * rel * c->h_red[1]);
+        if (rel <= o->tol) break;
+        if (it >= o->max_iter) {
+            *sweeps = it;
+            timing_collect(c);
+            return IBM_NOT_CONVERGED;
+        }
+        const int todo = check < o->max_iter - it ? check : o->max_iter - it;
+        for (int q = 0; q < todo; ++q) {
+            launch_timed(c, TK_SPMV, k_sor, nb, s, g, (const uint8_t*)c->pcode, b, x, 0, omega);
+            launch_timed(c, TK_SPMV, k_sor, nb, s, g, (const uint8_t*)c->pcode, b, x, 1, omega);
+        }
+        IBM_HIP(hipGetLastError());
+        it += todo;
+    }
+    *sweeps = it;
+    timing_collect(c);
+    if (c->timing_on) c->t_real_iters += it;
+    return IBM_OK;
+}
+
 int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s) {
     int iters = 0;
     int rc;
@@ -1510,6 +1613,10 @@ int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
     } else if (o->kind == IBM_SOLVER_FCG_CNN) {
         rc = cnn_fcg_solve(c, b, x, o, &local, s);
         iters = local.iters_inner;
+    } else if (o->kind == IBM_SOLVER_RBSOR) {
+        rc = rbsor64(c, b, x, o, &iters, s);
+        local.iters_outer = 0;
+        local.fallback_used = 0;
     } else {
         set_error("unknown solver kind");
         return IBM_ERR_ARG;

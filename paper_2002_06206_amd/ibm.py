@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libibm.so")
 
 PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
 FP64, MIXED = 0, 1
-SOLVER_PCG_JACOBI, SOLVER_FCG_CNN, SOLVER_FCG_JACOBI = 0, 1, 2
+SOLVER_PCG_JACOBI, SOLVER_FCG_CNN, SOLVER_FCG_JACOBI, SOLVER_RBSOR = 0, 1, 2, 3
 SCHEME_AB2, SCHEME_CN = 0, 1
 OK, NOT_CONVERGED = 0, 1
 
@@ -39,7 +39,7 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("kind", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32),
                 ("stall_factor", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("force_stall", ctypes.c_int32)]
+                ("force_stall", ctypes.c_int32), ("omega", ctypes.c_double)]
 
 
 class StepParams(ctypes.Structure):
@@ -332,8 +332,9 @@ def ibm_ctx_set_preconditioner(ctx, net):
 # ------------------------------------------------------------- convenience
 
 def solver_opts(tol=1e-10, max_iter=20000, kind=SOLVER_PCG_JACOBI, inner_tol=1e-2, inner_max_iter=200,
-                stall_factor=2.0, check_every=16, force_stall=0):
-    return SolverOpts(tol, max_iter, kind, inner_tol, inner_max_iter, stall_factor, check_every, force_stall)
+                stall_factor=2.0, check_every=16, force_stall=0, omega=0.0):
+    return SolverOpts(tol, max_iter, kind, inner_tol, inner_max_iter, stall_factor, check_every, force_stall,
+                      float(omega))
 
 
 def step_params(dt, nu, c1=1.0 / 20.0, csm=True, step=0, body=(0.0, 0.0, 0.0), dt_prev=0.0, scheme="ab2",
