@@ -242,6 +242,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
         if args.quick_steps > 0:
             out["hybrid_quick"] = quick_timing(case, s, st, ctl, step, args, ibm, torch)
             step += 2 + args.quick_steps
+    if solver == "pcg_fp64" and args.sor:
+        out["red_black_sor"] = sor_timing(case, s, args, ibm, torch)
     if solver == "pcg_fp64" and args.cn_steps > 0:
         out["crank_nicolson"] = cn_timing(case, s, st, ctl, step, args, ibm, torch)
     if solver == "mixed_learned":
@@ -354,6 +356,47 @@ def quick_timing(case, s, st, ctl, step, args, ibm, torch):
                          "avg_launch_us": rec["avg_launch_us"]}}
 
 
+# one red-black SOR half sweep (one colour): x read at every cell (8 B), b and the
+# code byte at the cells of the colour (4 + 0.5 B), x written there (4 B)
+SOR_BYTES_PER_CELL = 16.5
+
+
+def sor_timing(case, s, args, ibm, torch):
+    """Red-black SOR (Sec. 2.1) against the plain FP64 PCG on the same right-hand side
+    (the last step's compatible b), both from x = 0 to the benchmark tolerance: whole
+    solves by the host clock, the half sweeps by dispatch events (slot 0)."""
+    N = case.n[0] * case.n[1] * case.n[2]
+    b = s.rhs()
+    out = {}
+    for name, kw in (("pcg_fp64", dict(kind=ibm.SOLVER_PCG_JACOBI)),
+                     ("rbsor", dict(kind=ibm.SOLVER_RBSOR, omega=args.sor_omega))):
+        x = torch.zeros_like(b)
+        ibm.ibm_timing_enable(s.ctx, True)
+        ibm.ibm_timing_read(s.ctx, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, stats = s.poisson(b, x, tol=args.tol, max_iter=200000, check_every=16, **kw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        tim = ibm.ibm_timing_read(s.ctx, reset=True)
+        ibm.ibm_timing_enable(s.ctx, False)
+        rec = {"rc": rc, "iterations": stats["iters_inner"], "ms": round(el * 1e3, 2),
+               "rel_residual": stats["rel_residual"]}
+        if name == "rbsor":
+            half = tim["ms"][0] / 1e3 / max(tim["launches"][0], 1)
+            rec.update({"omega": args.sor_omega if args.sor_omega > 0 else "2/(1+sin(pi/n))",
+                        "kernel": "k_sor", "half_sweep_us": round(half * 1e6, 2),
+                        "bytes_per_cell": SOR_BYTES_PER_CELL,
+                        "achieved_gbs": round(SOR_BYTES_PER_CELL * N / half / 1e9, 1) if half > 0 else None})
+            rec["roofline"] = {"bound": "hbm", "achieved": rec["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(rec["achieved_gbs"] / HBM_PEAK_GBS, 4) if rec["achieved_gbs"] else None,
+                               "traffic": committed_traffic("sor_half_sweep", args.workload), "kernel": "k_sor",
+                               "algorithmic_bytes_per_launch": SOR_BYTES_PER_CELL * N,
+                               "avg_launch_us": rec["half_sweep_us"]}
+        out[name] = rec
+    return out
+
+
 def cn_timing(case, s, st, ctl, step, args, ibm, torch):
     """Crank-Nicolson steps on the developed plain FP64 state at twice the explicit CFL
     (0.6): whole steps timed by the host clock, the five BiCGStab passes by dispatch
@@ -463,6 +506,8 @@ def main():
     ap.add_argument("--quick-steps", type=int, default=5,
                     help="explicit steps with the hybrid central/QUICK face value timed after the plain run (0: none)")
     ap.add_argument("--quick", type=float, default=0.1, help="QUICK weight of the hybrid face value")
+    ap.add_argument("--sor", type=int, default=1, help="time red-black SOR against PCG on one right-hand side")
+    ap.add_argument("--sor-omega", type=float, default=0.0, help="SOR relaxation (0: 2/(1+sin(pi/n)))")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (collectives and sharding are not part of it); "
@@ -533,7 +578,7 @@ def main():
         "plain_fp64_value": plain["value"] if plain else None,
         "speedup_vs_plain_fp64": head["value"] / plain["value"] if plain else None,
         "solvers": {k: {kk: vv for kk, vv in v.items()
-                        if kk not in ("dominant", "crank_nicolson", "hybrid_quick", "predictor")}
+                        if kk not in ("dominant", "crank_nicolson", "hybrid_quick", "predictor", "red_black_sor")}
                     for k, v in runs.items()},
         "speedups_vs_plain_fp64": {k: round(v["value"] / plain["value"], 4) for k, v in runs.items()} if plain else None,
         "training": train_info,
@@ -542,6 +587,7 @@ def main():
         "surface_force": head.get("surface_force"),
         "crank_nicolson": plain.get("crank_nicolson") if plain else None,
         "hybrid_quick": plain.get("hybrid_quick") if plain else None,
+        "red_black_sor": plain.get("red_black_sor") if plain else None,
         "predictor": plain.get("predictor") if plain else None,
         "cpu_baseline": cpu,
     }
