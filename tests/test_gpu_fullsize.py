@@ -13,6 +13,8 @@
   dt (b - L p) cell by cell (a property at any size).
 * Crank-Nicolson at that size: H^n against the oracle, the momentum system's residual
   by the oracle's operator (<= tol), the operator itself (relative L2 1e-13).
+* The hybrid QUICK face value at that size (H against the oracle) and red-black SOR on
+  the step's right-hand side (residual by the oracle's operator <= tol).
 * The precision configuration (256^3 plate): relative L2 error of u, p and drag of the
   mixed path against the plain FP64 path after the same steps, stated.
 """
@@ -175,6 +177,38 @@ def test_benchmark_workload_crank_nicolson_step():
     assert e_h < 1e-10 and e_a < 1e-13
     assert worst <= 1e-10 * 1.05
     assert min(iters[:1]) > 0
+    s.close()
+
+
+def test_benchmark_workload_quick_rhs_and_sor_solve():
+    """The hybrid QUICK face value (w = 0.1) and red-black SOR at 256^3 from a developed
+    state: H of the step against the oracle's (relative L2 1e-10), and the step's
+    right-hand side solved by SOR from zero with its residual measured by the oracle's
+    operator (<= tol)."""
+    case, g, ob, ot, st = _oracle("ellipsoids256")
+    s, *_ = _gpu(case, ibm.FP64)
+    gs = s.new_state(case.u_in)
+    ctl = {"umax": 1.0, "dt_prev": 0.0, "step": 0, "dt": case.dt}
+    print("case full-size quick + sor ellipsoids256", flush=True)
+    _cfl_steps(s, gs, case, 2, ibm.SOLVER_PCG_JACOBI, 1e-6, ctl)
+    u0, U0, p0, h0 = _host(gs)
+    dt = min(case.dt, 0.3 * case.dx / ctl["umax"])
+    rc, stats = s.step(gs, ibm.step_params(dt, case.nu, csm=case.csm, step=ctl["step"], dt_prev=ctl["dt_prev"],
+                                           tol=1e-6, max_iter=20000, quick=0.1))
+    assert rc == 0
+    nut = flow.csm_nut(st, u0) if case.csm else np.zeros(g.shape)
+    H = flow.momentum_rhs(st, u0, U0, nut, case.nu, (0.0, 0.0, 0.0), None, quick=0.1)
+    H = [np.where(st.deadend, 0.0, a) for a in H]
+    e_h = rel_l2(_vec(gs["h"]), _vec(H))
+    b = s.rhs()
+    x = torch.zeros_like(b)
+    rc, sst = s.poisson(b, x, tol=1e-6, max_iter=200000, kind=ibm.SOLVER_RBSOR, check_every=16)
+    assert rc == 0
+    bn = b.cpu().numpy()
+    res = rel_l2(flow.laplacian(st, x.cpu().numpy()), bn)
+    print("256^3 QUICK: rel L2 H %.1e; SOR: %d sweeps, residual %.3e" % (e_h, sst["iters_inner"], res), flush=True)
+    assert e_h < 1e-10
+    assert res <= 1e-6 * 1.0001
     s.close()
 
 
