@@ -23,7 +23,15 @@ What is computed (plain FP64 numpy, one vertex at a time in the paper's notation
 Readings (the paper leaves these open): the eight dual-cell points as the
 "surrounding fluid points", the sign convention of the front/back split, vertex values
 combined per triangle by their mean, and the triangle area as the integration weight.
-The thin-plate filter Z of eq. (force_filter) is not included.
+
+Thin-plate filter Z of eq. (force_filter) (optional, `thin_filter`): a surrounding point
+x^(k) gets weight zero at the vertex X when the segment from X to x^(k) crosses a
+triangle of the surface at a parameter t in (T_MIN, 1] (t = 0 at X; contacts at X
+itself, where the neighbouring triangles of the vertex meet, do not count).  Such a
+point lies behind another surface, as the back side of a plate thinner than a cell does
+from its front face; the paper cancels exactly those values.  The crossing test is
+Moller and Trumbore's (J. Graphics Tools 2, 1997; the paper names the method for its
+ray tests), edges inclusive, with its FP64 operations in one fixed order.
 """
 from __future__ import annotations
 
@@ -49,9 +57,40 @@ def triangle_frames(tri: np.ndarray):
     return n, 0.5 * two_a
 
 
-def vertex_values(g: flow.Grid, p: np.ndarray, X: np.ndarray, n: np.ndarray):
+T_MIN = 1e-6
+
+
+def _cross(a, b):
+    return (a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0])
+
+
+def _dot(a, b):
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]
+
+
+def segment_hits(P, Q, tri: np.ndarray) -> np.ndarray:
+    """For each triangle (ntri, 3, 3): whether the segment P + t (Q - P) meets it at
+    some t in (T_MIN, 1] (Moller-Trumbore, edges inclusive, parallel never)."""
+    D = tuple(float(Q[a]) - float(P[a]) for a in range(3))
+    V0, V1, V2 = tri[:, 0], tri[:, 1], tri[:, 2]
+    E1 = (V1[:, 0] - V0[:, 0], V1[:, 1] - V0[:, 1], V1[:, 2] - V0[:, 2])
+    E2 = (V2[:, 0] - V0[:, 0], V2[:, 1] - V0[:, 1], V2[:, 2] - V0[:, 2])
+    Pv = _cross(D, E2)
+    det = _dot(E1, Pv)
+    ok = det != 0.0
+    inv = np.divide(1.0, det, out=np.zeros_like(det), where=ok)
+    T = (float(P[0]) - V0[:, 0], float(P[1]) - V0[:, 1], float(P[2]) - V0[:, 2])
+    u = _dot(T, Pv) * inv
+    Qv = _cross(T, E1)
+    v = _dot(D, Qv) * inv
+    t = _dot(E2, Qv) * inv
+    return ok & (u >= 0.0) & (u <= 1.0) & (v >= 0.0) & (u + v <= 1.0) & (t > T_MIN) & (t <= 1.0)
+
+
+def vertex_values(g: flow.Grid, p: np.ndarray, X: np.ndarray, n: np.ndarray, occluders=None):
     """Front and back Shepard values of p at point X for normal n (eq. (force)); None
-    for a side without points."""
+    for a side without points.  occluders (ntri, 3, 3): apply the thin-plate filter Z
+    against these triangles."""
     nz, ny, nx = g.shape
     o = np.asarray(g.origin, dtype=np.float64)
     fb = np.floor((X - o) / g.dx - 0.5)
@@ -72,6 +111,8 @@ def vertex_values(g: flow.Grid, p: np.ndarray, X: np.ndarray, n: np.ndarray):
                 s = float(n[0] * r[0] + n[1] * r[1] + n[2] * r[2])
                 if s == 0.0:
                     continue
+                if occluders is not None and len(occluders) and np.any(segment_hits(X, x, occluders)):
+                    continue
                 side = 1 if s > 0.0 else -1
                 d2 = float(r[0] * r[0] + r[1] * r[1] + r[2] * r[2])
                 num[side] += float(p[k, j, i]) / d2
@@ -82,17 +123,31 @@ def vertex_values(g: flow.Grid, p: np.ndarray, X: np.ndarray, n: np.ndarray):
     return out[0], out[1]
 
 
-def surface_pressure(g: flow.Grid, p: np.ndarray, tri: np.ndarray):
+def _near(tri: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """Triangles whose bounding box meets the box [lo, hi] (a prefilter only)."""
+    tmin = tri.min(axis=1)
+    tmax = tri.max(axis=1)
+    return tri[np.all((tmax >= lo) & (tmin <= hi), axis=1)]
+
+
+def surface_pressure(g: flow.Grid, p: np.ndarray, tri: np.ndarray, thin_filter: bool = False, surface=None):
     """Per triangle: (front, back) pressure (NaN for a side without value), and the
-    total pressure force sum A n (p- - p+) over the triangles."""
+    total pressure force sum A n (p- - p+) over the triangles.  thin_filter: the filter
+    Z of eq. (force_filter) against the triangles of `surface` (default: tri itself)."""
     tri = np.asarray(tri, dtype=np.float64)
+    surf = tri if surface is None else np.asarray(surface, dtype=np.float64)
     n, area = triangle_frames(tri)
     side = np.full((len(tri), 2), np.nan)
     force = np.zeros(3)
     for t in range(len(tri)):
         if not (area[t] > 0.0 and np.isfinite(area[t])):   # degenerate, overflowing or non-finite
             continue
-        vals = [vertex_values(g, p, tri[t, v], n[t]) for v in range(3)]
+        occ = None
+        if thin_filter:
+            lo = tri[t].min(axis=0) - 2.0 * g.dx
+            hi = tri[t].max(axis=0) + 2.0 * g.dx
+            occ = _near(surf, lo, hi)
+        vals = [vertex_values(g, p, tri[t, v], n[t], occ) for v in range(3)]
         for s in range(2):
             have = [vv[s] for vv in vals if vv[s] is not None]
             if have:

@@ -130,3 +130,64 @@ def test_inverse_square_weights_worked_example():
     f, b = shepard.vertex_values(g, p, np.array([2.25, 2.0, 2.0]), np.array([1.0, 1.0, 0.0]) / np.sqrt(2.0))
     assert abs(f - 7.0) < 1e-15
     assert abs(b - 17.0 / 35.0) < 1e-15
+
+
+# ------------------------------------------------------------ thin-plate filter Z
+
+def test_segment_crossing_cases():
+    tri = np.array([[[0.0, 0.0, 1.0], [2.0, 0.0, 1.0], [0.0, 2.0, 1.0]]])
+    hit = lambda P, Q: bool(shepard.segment_hits(np.array(P), np.array(Q), tri)[0])  # noqa: E731
+    assert hit((0.5, 0.5, 0.0), (0.5, 0.5, 2.0))          # through the interior
+    assert not hit((1.5, 1.5, 0.0), (1.5, 1.5, 2.0))      # beside the hypotenuse
+    assert hit((1.0, 1.0, 0.0), (1.0, 1.0, 2.0))          # through the hypotenuse (edges count)
+    assert hit((0.5, 0.5, 0.0), (0.5, 0.5, 1.0))          # ending on it (t = 1)
+    assert not hit((0.5, 0.5, 1.0), (0.5, 0.5, 2.0))      # starting on it (t = 0)
+    assert not hit((0.5, 0.5, 0.0), (0.5, 0.5, 0.9))      # stopping short
+    assert not hit((0.5, 0.5, 1.0), (1.5, 0.2, 1.0))      # in its plane
+
+
+def _plate(z, lo, hi, up):
+    a, b, c, d = (lo, lo, z), (hi, lo, z), (hi, hi, z), (lo, hi, z)
+    return np.array([[a, b, c], [a, c, d]] if up else [[a, c, b], [a, d, c]], dtype=np.float64)
+
+
+def _sheet(z, up, n=3, L=6.0):
+    """Triangulated square [0, L]^2 in the plane z on an (n+1)^2 vertex grid."""
+    xs = np.linspace(0.0, L, n + 1)
+    tri = []
+    for i in range(n):
+        for j in range(n):
+            a, b = (xs[i], xs[j], z), (xs[i + 1], xs[j], z)
+            c, d = (xs[i + 1], xs[j + 1], z), (xs[i], xs[j + 1], z)
+            tri += [[a, b, c], [a, c, d]] if up else [[a, c, b], [a, d, c]]
+    return np.array(tri, dtype=np.float64)
+
+
+def test_thin_plate_filter_counts_the_plate_once():
+    # a plate 0.3 cells thick across the whole domain between the cell centres z = 2.5
+    # and 3.5 (faces at 3.15 with normal +z and 2.85 with -z), p = +1 above, -1 below.
+    # Unfiltered, each face also averages the points beyond the other face and the force
+    # is counted twice (-4 A e_z, A = 36); the filter cancels those values: -2 A e_z,
+    # every triangle with its front value only
+    g = flow.Grid((6, 6, 6), 1.0, (0.0, 0.0, 0.0), (flow.SLIP,) * 6)
+    zc = (np.arange(6) + 0.5)[:, None, None] * np.ones((6, 6, 6))
+    p = np.where(zc > 3.0, 1.0, -1.0)
+    up, lo = _sheet(3.15, True), _sheet(2.85, False)
+    tri = np.concatenate([up, lo])
+    side, f_raw = shepard.surface_pressure(g, p, tri)
+    np.testing.assert_allclose(f_raw, [0.0, 0.0, -4.0 * 36.0], atol=1e-11)
+    side, f = shepard.surface_pressure(g, p, tri, thin_filter=True)
+    np.testing.assert_allclose(f, [0.0, 0.0, -2.0 * 36.0], atol=1e-11)
+    nu = len(up)
+    assert np.all(side[:nu, 0] == 1.0) and np.all(np.isnan(side[:nu, 1]))     # upper face: front only
+    assert np.all(side[nu:, 0] == -1.0) and np.all(np.isnan(side[nu:, 1]))    # lower face: front only
+
+
+def test_filter_leaves_single_surfaces_unchanged():
+    g = flow.Grid((6, 6, 6), 1.0, (0.0, 0.0, 0.0), (flow.SLIP,) * 6)
+    p = np.random.default_rng(8).standard_normal((6, 6, 6))
+    for tri in (_plate(3.0, 1.25, 4.5, True), _box(1.0, 3.0)):
+        s0, f0 = shepard.surface_pressure(g, p, tri)
+        s1, f1 = shepard.surface_pressure(g, p, tri, thin_filter=True)
+        assert np.array_equal(np.isnan(s0), np.isnan(s1)) and np.array_equal(s0[~np.isnan(s0)], s1[~np.isnan(s1)])
+        assert np.array_equal(f0, f1)
