@@ -265,8 +265,14 @@ int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const vo
  * front (n . (x_k - X) > 0) and behind (< 0); points in the triangle's plane and
  * outside the grid are left out.  A triangle's front / back value is the mean over
  * its vertices that have one on that side; its force is A n (p_back - p_front), a side
- * without points contributing nothing.  The thin-plate filter of eq. (force_filter)
- * is not applied.
+ * without points contributing nothing.
+ * thin_filter != 0 applies the filter Z of eq. (force_filter): a point gets weight zero
+ * at a vertex when the segment from the vertex to it crosses a triangle of tri_dev at a
+ * parameter t in (1e-6, 1] (Moller-Trumbore, edges inclusive; contacts at the vertex
+ * itself do not count), so values from beyond the other face of a plate thinner than a
+ * cell are cancelled.  The first filtered call allocates its triangle bins (4x4x4
+ * cells, grow-only, freed by ibm_destroy); IBM_ERR_ARG when the bin lists would exceed
+ * 2^31 entries.
  *   tri_dev   ntri x 3 vertices x 3 doubles (device; the layout ibm_tag_geometry takes)
  *   p_dev     cell pressure (device, FP64, the context's grid)
  *   side_dev  optional (device): ntri x 2 doubles, front and back pressure per
@@ -275,8 +281,8 @@ int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const vo
  *             sums in block order: deterministic).
  * Needs built stencils (for the grid).  Synchronises the stream.  Returns
  * IBM_ERR_ARG for ntri < 0 or null pointers. */
-int ibm_shepard_force(ibm_ctx* ctx, const double* tri_dev, int64_t ntri, const double* p_dev, double* side_dev,
-                      double force_host[3], void* stream);
+int ibm_shepard_force(ibm_ctx* ctx, const double* tri_dev, int64_t ntri, const double* p_dev, int32_t thin_filter,
+                      double* side_dev, double force_host[3], void* stream);
 
 /* ---- Learned preconditioner (an extension layered on the pressure solve of
  * eq. (poisson); the paper itself uses plain Krylov solves).

@@ -169,6 +169,7 @@ int ibm_destroy(ibm_ctx* c) {
     (void)hipDeviceSynchronize();
     free_events(c);
     cn_release(c);
+    shepard_release(c);
     void* ps[] = {c->tagmask, c->theta, c->mask, c->pcode, c->flags, c->label, c->cut_off, c->cut_cell, c->cut_dir,
                   c->cut_theta, c->a_ib, c->a_c, c->a_o, c->cut_opp, c->enc_cells, c->comp_start,
                   c->ustar[0], c->ustar[1], c->ustar[2], c->nut, c->b, c->bwork, c->r, c->d, c->q, c->zbuf, c->x64,
@@ -360,11 +361,11 @@ int ibm_forces(ibm_ctx* c, void* const u[3], const double* p, const void* nut, d
     return forces_run(c, u, p, nut, nu, wall, out, (hipStream_t)stream);
 }
 
-int ibm_shepard_force(ibm_ctx* c, const double* tri, int64_t ntri, const double* p, double* side, double force[3],
-                      void* stream) {
+int ibm_shepard_force(ibm_ctx* c, const double* tri, int64_t ntri, const double* p, int32_t thin_filter,
+                      double* side, double force[3], void* stream) {
     if (int rc = need_stencil(c)) return rc;
     if (ntri < 0 || (ntri > 0 && !tri) || !p || !force) return bad("ibm_shepard_force: bad arguments");
-    return shepard_run(c, tri, ntri, p, side, force, (hipStream_t)stream);
+    return shepard_run(c, tri, ntri, p, thin_filter ? 1 : 0, side, force, (hipStream_t)stream);
 }
 
 int ibm_timing_enable(ibm_ctx* c, int32_t on) {

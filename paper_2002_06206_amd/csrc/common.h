@@ -134,6 +134,11 @@ struct ibm_ctx {
     ibm::CnState* cn_state;
     ibm::CnState* h_cn_state;  // pinned host mirror
     int cn_last_iters;      // iterations of the previous momentum solve (batch sizing)
+    // triangle bins of the near-field force's thin-plate filter (grow-only, first use)
+    int* bin_count;         // 2 * (bins + 1): counts / fill cursor, then offsets
+    int* bin_ids;
+    long long* bin_tot;
+    long long bin_cap, bin_ids_cap, bin_tot_cap;
     // optional progress hook, called at the solver's host convergence polls
     ibm_progress_fn progress;
     void* progress_user;
@@ -336,8 +341,9 @@ int cn_solve(ibm_ctx* c, const void* const* b, void* const* x, double* const* U,
              double dt, double tol, int max_iter, int iters[3], hipStream_t s);
 int cn_prepare(ibm_ctx* c);
 void cn_release(ibm_ctx* c);
-int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, double* side, double* force,
-                hipStream_t s);
+int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, int filter, double* side,
+                double* force, hipStream_t s);
+void shepard_release(ibm_ctx* c);
 int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
                double* out, hipStream_t s);
 }  // namespace ibm

@@ -11,6 +11,14 @@
 // FMA contraction and every sum is written out left to right, so that each triangle's
 // values (and the front/back decision of every point) are one fixed FP64 computation.
 // The force is summed over the triangles through per-block partials in block order.
+//
+// Thin-plate filter Z of eq. (force_filter), optional: a point is left out at a vertex
+// when the segment from the vertex to it crosses a triangle of the surface at a
+// parameter t in (T_MIN, 1] (Moller-Trumbore, edges inclusive), i.e. when the point lies
+// behind another face, as the far side of a plate thinner than a cell does.  Candidate
+// triangles come from uniform bins of 4x4x4 cells (counted with global atomics, an
+// exclusive scan, filled with global atomics); the order inside a bin does not matter,
+// since only whether some triangle is crossed counts.
 
 #include <cfloat>
 #include <cmath>
@@ -20,9 +28,133 @@
 namespace ibm {
 namespace {
 
+constexpr double T_MIN = 1e-6;
+constexpr int BIN_CELLS = 4;
+
+struct Bins {
+    int nbx, nby, nbz;
+    double bdx, ox, oy, oz;
+    const int* off;   // nbins + 1 offsets into ids
+    const int* ids;   // triangle ids per bin
+};
+
+__device__ inline int bin_of(double v, double o, double bdx, int nb) {
+    const double f = floor((v - o) / bdx);
+    if (!(f >= 0.0)) return 0;
+    if (f > (double)(nb - 1)) return nb - 1;
+    return (int)f;
+}
+
+// whether the segment P + t (Q - P) meets triangle v at some t in (T_MIN, 1]
+__device__ inline bool seg_hits(double px, double py, double pz, double dx_, double dy, double dz,
+                                const double* __restrict__ v) {
+    const double e1x = v[3] - v[0], e1y = v[4] - v[1], e1z = v[5] - v[2];
+    const double e2x = v[6] - v[0], e2y = v[7] - v[1], e2z = v[8] - v[2];
+    const double pvx = dy * e2z - dz * e2y, pvy = dz * e2x - dx_ * e2z, pvz = dx_ * e2y - dy * e2x;
+    const double det = e1x * pvx + e1y * pvy + e1z * pvz;
+    if (det == 0.0) return false;
+    const double inv = 1.0 / det;
+    const double tx = px - v[0], ty = py - v[1], tz = pz - v[2];
+    const double u = (tx * pvx + ty * pvy + tz * pvz) * inv;
+    const double qx = ty * e1z - tz * e1y, qy = tz * e1x - tx * e1z, qz = tx * e1y - ty * e1x;
+    const double w = (dx_ * qx + dy * qy + dz * qz) * inv;
+    const double t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+    return u >= 0.0 && u <= 1.0 && w >= 0.0 && u + w <= 1.0 && t > T_MIN && t <= 1.0;
+}
+
+__device__ inline bool occluded(const Bins& B, const double* __restrict__ tri, double px, double py, double pz,
+                                double qx, double qy, double qz) {
+    const int x0 = bin_of(fmin(px, qx), B.ox, B.bdx, B.nbx), x1 = bin_of(fmax(px, qx), B.ox, B.bdx, B.nbx);
+    const int y0 = bin_of(fmin(py, qy), B.oy, B.bdx, B.nby), y1 = bin_of(fmax(py, qy), B.oy, B.bdx, B.nby);
+    const int z0 = bin_of(fmin(pz, qz), B.oz, B.bdx, B.nbz), z1 = bin_of(fmax(pz, qz), B.oz, B.bdx, B.nbz);
+    const double dx_ = qx - px, dy = qy - py, dz = qz - pz;
+    for (int bz = z0; bz <= z1; ++bz)
+        for (int by = y0; by <= y1; ++by)
+            for (int bx = x0; bx <= x1; ++bx) {
+                const long long b = bx + (long long)B.nbx * (by + (long long)B.nby * bz);
+                for (int e = B.off[b]; e < B.off[b + 1]; ++e)
+                    if (seg_hits(px, py, pz, dx_, dy, dz, tri + 9 * (long long)B.ids[e])) return true;
+            }
+    return false;
+}
+
+// bin range of triangle t's bounding box; false for a non-finite triangle
+__device__ inline bool tri_bins(const Bins& B, const double* __restrict__ v, int (&lo)[3], int (&hi)[3]) {
+    const double o[3] = {B.ox, B.oy, B.oz};
+    const int nb[3] = {B.nbx, B.nby, B.nbz};
+    for (int a = 0; a < 3; ++a) {
+        const double c0 = v[a], c1 = v[3 + a], c2 = v[6 + a];
+        if (!(c0 - c0 == 0.0 && c1 - c1 == 0.0 && c2 - c2 == 0.0)) return false;
+        lo[a] = bin_of(fmin(c0, fmin(c1, c2)), o[a], B.bdx, nb[a]);
+        hi[a] = bin_of(fmax(c0, fmax(c1, c2)), o[a], B.bdx, nb[a]);
+    }
+    return true;
+}
+
+__global__ void __launch_bounds__(NT) k_bin_count(Bins B, const double* __restrict__ tri, long long ntri,
+                                                  int* __restrict__ count) {
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < ntri; t += (long long)gridDim.x * NT) {
+        int lo[3], hi[3];
+        if (!tri_bins(B, tri + 9 * t, lo, hi)) continue;
+        for (int bz = lo[2]; bz <= hi[2]; ++bz)
+            for (int by = lo[1]; by <= hi[1]; ++by)
+                for (int bx = lo[0]; bx <= hi[0]; ++bx)
+                    atomicAdd(&count[bx + (long long)B.nbx * (by + (long long)B.nby * bz)], 1);
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_bin_fill(Bins B, const double* __restrict__ tri, long long ntri,
+                                                 int* __restrict__ cursor, int* __restrict__ ids) {
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < ntri; t += (long long)gridDim.x * NT) {
+        int lo[3], hi[3];
+        if (!tri_bins(B, tri + 9 * t, lo, hi)) continue;
+        for (int bz = lo[2]; bz <= hi[2]; ++bz)
+            for (int by = lo[1]; by <= hi[1]; ++by)
+                for (int bx = lo[0]; bx <= hi[0]; ++bx) {
+                    const long long b = bx + (long long)B.nbx * (by + (long long)B.nby * bz);
+                    const int pos = atomicAdd(&cursor[b], 1);
+                    ids[B.off[b] + pos] = (int)t;
+                }
+    }
+}
+
+// exclusive scan of count[0..n) into off[0..n] by one block (off[n] = total, as a
+// 64-bit sum in tot for the overflow check)
+__global__ void __launch_bounds__(1024) k_bin_scan(const int* __restrict__ count, long long n, int* __restrict__ off,
+                                                   long long* __restrict__ tot) {
+    __shared__ long long part[1024];
+    const long long per = (n + 1023) / 1024;
+    const long long a = threadIdx.x * per, b = a + per < n ? a + per : n;
+    long long sum = 0;
+    for (long long i = a; i < b; ++i) sum += count[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long run = 0;
+        for (int q = 0; q < 1024; ++q) {
+            const long long v = part[q];
+            part[q] = run;
+            run += v;
+        }
+        *tot = run;
+        off[n] = (int)(run < 0x7fffffffLL ? run : 0x7fffffffLL);
+    }
+    __syncthreads();
+    long long run = part[threadIdx.x];
+    for (long long i = a; i < b; ++i) {
+        off[i] = (int)(run < 0x7fffffffLL ? run : 0x7fffffffLL);
+        run += count[i];
+    }
+}
+
+__global__ void k_fill_int(int* __restrict__ a, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+
 __global__ void __launch_bounds__(NT) k_shepard(Geo g, const double* __restrict__ tri, long long ntri,
                                                 const double* __restrict__ p, double* __restrict__ side,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, Bins B, int filter) {
     __shared__ double sh[3 * (NT / 64)];
     double f[3] = {0.0, 0.0, 0.0};
     const long long cells_x = g.nx, cells_xy = (long long)g.nx * g.ny;
@@ -53,11 +185,13 @@ __global__ void __launch_bounds__(NT) k_shepard(Geo g, const double* __restrict_
                         for (int a = 0; a < 2; ++a) {
                             const long long i = i0 + a, j = j0 + b, k = k0 + c;
                             if (i < 0 || i >= g.nx || j < 0 || j >= g.ny || k < 0 || k >= g.nz) continue;
-                            const double rx = (g.ox + ((double)i + 0.5) * g.dx) - X;
-                            const double ry = (g.oy + ((double)j + 0.5) * g.dx) - Y;
-                            const double rz = (g.oz + ((double)k + 0.5) * g.dx) - Z;
+                            const double xc = g.ox + ((double)i + 0.5) * g.dx;
+                            const double yc = g.oy + ((double)j + 0.5) * g.dx;
+                            const double zc = g.oz + ((double)k + 0.5) * g.dx;
+                            const double rx = xc - X, ry = yc - Y, rz = zc - Z;
                             const double s = nxv * rx + nyv * ry + nzv * rz;
                             if (s == 0.0) continue;
+                            if (filter && occluded(B, tri, X, Y, Z, xc, yc, zc)) continue;
                             const int sd = s > 0.0 ? 0 : 1;
                             const double d2 = rx * rx + ry * ry + rz * rz;
                             num[sd] += p[i + cells_x * j + cells_xy * k] / d2;
@@ -96,22 +230,80 @@ __global__ void __launch_bounds__(NT) k_sum3(const double* __restrict__ part, in
 
 }  // namespace
 
-int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, double* side, double* force,
-                hipStream_t s) {
+// grow-only device buffer
+template <class P>
+static int grow(P** buf, long long* cap, long long need) {
+    if (need <= *cap) return IBM_OK;
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    if (hipMalloc((void**)buf, sizeof(P) * (size_t)(need > 1 ? need : 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        *buf = nullptr;
+        set_error("near-field force: out of device memory for the triangle bins");
+        return IBM_ERR_OOM;
+    }
+    *cap = need;
+    return IBM_OK;
+}
+
+int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, int filter, double* side,
+                double* force, hipStream_t s) {
     for (int a = 0; a < 3; ++a) force[a] = 0.0;
     if (ntri == 0) return IBM_OK;
+    const Geo& g = c->geo;
     const long long nbk = (ntri + NT - 1) / NT;
     const int nb = (int)(nbk < 2048 ? nbk : 2048);
+    Bins B{};
+    if (filter) {
+        B.nbx = (g.nx + BIN_CELLS - 1) / BIN_CELLS;
+        B.nby = (g.ny + BIN_CELLS - 1) / BIN_CELLS;
+        B.nbz = (g.nz + BIN_CELLS - 1) / BIN_CELLS;
+        B.bdx = BIN_CELLS * g.dx;
+        B.ox = g.ox;
+        B.oy = g.oy;
+        B.oz = g.oz;
+        const long long nbins = (long long)B.nbx * B.nby * B.nbz;
+        if (int rc = grow(&c->bin_count, &c->bin_cap, 2 * (nbins + 1))) return rc;
+        if (int rc = grow(&c->bin_tot, &c->bin_tot_cap, 1)) return rc;
+        int* count = c->bin_count;
+        int* off = c->bin_count + (nbins + 1);
+        k_fill_int<<<1024, 256, 0, s>>>(count, nbins + 1);
+        k_bin_count<<<nb, NT, 0, s>>>(B, tri, ntri, count);
+        k_bin_scan<<<1, 1024, 0, s>>>(count, nbins, off, c->bin_tot);
+        long long total = 0;
+        IBM_HIP(hipMemcpyAsync(&total, c->bin_tot, sizeof(long long), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        if (total >= 0x7fffffffLL) {
+            set_error("near-field force: too many triangle-bin entries for the thin-plate filter");
+            return IBM_ERR_ARG;
+        }
+        if (int rc = grow(&c->bin_ids, &c->bin_ids_cap, total)) return rc;
+        k_fill_int<<<1024, 256, 0, s>>>(count, nbins + 1);   // reused as the fill cursor
+        B.off = off;
+        B.ids = c->bin_ids;
+        k_bin_fill<<<nb, NT, 0, s>>>(B, tri, ntri, count, c->bin_ids);
+        IBM_HIP(hipGetLastError());
+    }
     if (c->timing_on)
-        launch_timed(c, TK_OTHER, k_shepard, nb, s, c->geo, tri, ntri, p, side, c->partials);
+        launch_timed(c, TK_OTHER, k_shepard, nb, s, c->geo, tri, ntri, p, side, c->partials, B, filter);
     else
-        k_shepard<<<nb, NT, 0, s>>>(c->geo, tri, ntri, p, side, c->partials);
+        k_shepard<<<nb, NT, 0, s>>>(c->geo, tri, ntri, p, side, c->partials, B, filter);
     k_sum3<<<1, NT, 0, s>>>(c->partials, nb, c->red);
     IBM_HIP(hipGetLastError());
     IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     IBM_HIP(hipStreamSynchronize(s));
     for (int a = 0; a < 3; ++a) force[a] = c->h_red[a];
     return IBM_OK;
+}
+
+void shepard_release(ibm_ctx* c) {
+    if (c->bin_count) (void)hipFree(c->bin_count);
+    if (c->bin_ids) (void)hipFree(c->bin_ids);
+    if (c->bin_tot) (void)hipFree(c->bin_tot);
+    c->bin_count = c->bin_ids = nullptr;
+    c->bin_tot = nullptr;
+    c->bin_cap = c->bin_ids_cap = c->bin_tot_cap = 0;
 }
 
 }  // namespace ibm

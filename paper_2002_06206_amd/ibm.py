@@ -87,7 +87,8 @@ def _load():
         "ibm_get_nut": ([vp, vp, vp], ctypes.c_int),
         "ibm_get_rhs": ([vp, vp, vp], ctypes.c_int),
         "ibm_forces": ([vp, P3, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
-        "ibm_shepard_force": ([vp, vp, ctypes.c_int64, vp, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
+        "ibm_shepard_force": ([vp, vp, ctypes.c_int64, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double), vp],
+                              ctypes.c_int),
         "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
         "ibm_timing_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
         "ibm_timing_slot": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
@@ -220,13 +221,14 @@ def ibm_forces(ctx, u, p, nu, nut=None, wall=None):
     return list(out[:3]), list(out[3:])
 
 
-def ibm_shepard_force(ctx, tri, p, side=None):
+def ibm_shepard_force(ctx, tri, p, side=None, thin_filter=False):
     """Near-field pressure force (eq. (force)) of triangles tri (ntri, 3, 3, FP64,
-    device) on the cell pressure p; fills side (ntri, 2) when given.  Returns the force
-    as three floats."""
+    device) on the cell pressure p; fills side (ntri, 2) when given; thin_filter applies
+    the filter Z of eq. (force_filter).  Returns the force as three floats."""
     out = (ctypes.c_double * 3)()
     ntri = int(tri.shape[0]) if tri is not None else 0
-    _check(_lib.ibm_shepard_force(ctx, _ptr(tri), ntri, _ptr(p), _ptr(side), out, _stream()), "ibm_shepard_force")
+    _check(_lib.ibm_shepard_force(ctx, _ptr(tri), ntri, _ptr(p), int(bool(thin_filter)), _ptr(side), out, _stream()),
+           "ibm_shepard_force")
     return list(out)
 
 
@@ -425,8 +427,8 @@ class Solver:
     def momentum_solve(self, b, x, U, nut, nu, dt, tol=1e-10, max_iter=200):
         return ibm_momentum_solve(self.ctx, b, x, U, nut, nu, dt, tol, max_iter)
 
-    def shepard_force(self, tri, p, side=None):
-        return ibm_shepard_force(self.ctx, tri, p, side)
+    def shepard_force(self, tri, p, side=None, thin_filter=False):
+        return ibm_shepard_force(self.ctx, tri, p, side, thin_filter)
 
 
 class Network:

@@ -1,5 +1,6 @@
 """GPU parity of the near-field surface force (eq. (force), Shepard interpolation with
-the front/back split) against oracle/shepard.py through the C ABI.
+the front/back split, optionally with the thin-plate filter Z of eq. (force_filter))
+against oracle/shepard.py through the C ABI.
 
 The kernel takes the oracle's FP64 operations in the same order without fused
 multiply-adds, so every triangle's front and back value (and each point's side) is
@@ -42,10 +43,10 @@ def _same(a, b):
     return np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(a[~np.isnan(a)], b[~np.isnan(b)])
 
 
-def _gpu(s, tri, p):
+def _gpu(s, tri, p, thin_filter=False):
     t = torch.from_numpy(np.ascontiguousarray(tri, dtype=np.float64)).cuda()
     side = torch.empty((len(tri), 2), dtype=torch.float64, device="cuda")
-    f = s.shepard_force(t, p, side)
+    f = s.shepard_force(t, p, side, thin_filter)
     return side.cpu().numpy(), np.array(f)
 
 
@@ -147,6 +148,70 @@ def test_edge_cases():
     assert np.all(np.isnan(side[:4])) and np.all(np.isfinite(side[4]))
     assert np.max(np.abs(force - fo)) < 1e-12 * (1.0 + np.max(np.abs(fo)))
     with pytest.raises(ibm.IBMError):
-        ibm._check(ibm._lib.ibm_shepard_force(s.ctx, None, -1, ibm._ptr(p), None, (ibm.ctypes.c_double * 3)(),
+        ibm._check(ibm._lib.ibm_shepard_force(s.ctx, None, -1, ibm._ptr(p), 0, None, (ibm.ctypes.c_double * 3)(),
                                               None), "ibm_shepard_force")
+    s.close()
+
+
+# ------------------------------------------------------------ thin-plate filter Z
+
+def _sheet(z, up, n=3, L=6.0):
+    xs = np.linspace(0.0, L, n + 1)
+    tri = []
+    for i in range(n):
+        for j in range(n):
+            a, b = (xs[i], xs[j], z), (xs[i + 1], xs[j], z)
+            c, d = (xs[i + 1], xs[j + 1], z), (xs[i], xs[j + 1], z)
+            tri += [[a, b, c], [a, c, d]] if up else [[a, c, b], [a, d, c]]
+    return np.array(tri, dtype=np.float64)
+
+
+def test_thin_plate_filter_on_the_device():
+    # a 0.3-cell plate across the domain, p = +1 above, -1 below: filtered, the force is
+    # counted once (-2 A e_z, A = 36) and each face keeps its front value only
+    case = _plate_case()
+    s = _solver(case, geometry=False)
+    zc = (np.arange(6) + 0.5)[:, None, None] * np.ones((6, 6, 6))
+    p = torch.from_numpy(np.where(zc > 3.0, 1.0, -1.0)).cuda()
+    tri = np.concatenate([_sheet(3.15, True), _sheet(2.85, False)])
+    side, force = _gpu(s, tri, p, thin_filter=True)
+    so, fo = shepard.surface_pressure(_grid(case), p.cpu().numpy(), tri, thin_filter=True)
+    assert _same(side, so)
+    assert np.max(np.abs(force - [0.0, 0.0, -72.0])) < 1e-11
+    side, force = _gpu(s, tri, p)
+    assert np.max(np.abs(force - [0.0, 0.0, -144.0])) < 1e-11
+    s.close()
+
+
+def test_filter_sphere32_bit_exact():
+    case = inputs.case_sphere32(0)
+    print("case shepard filter sphere32", flush=True)
+    s = _solver(case)
+    rng = np.random.default_rng(7)
+    p_np = rng.standard_normal((case.n[2], case.n[1], case.n[0]))
+    side, force = _gpu(s, case.tri, torch.from_numpy(p_np).cuda(), thin_filter=True)
+    so, fo = shepard.surface_pressure(_grid(case), p_np, case.tri, thin_filter=True)
+    assert _same(side, so)
+    assert np.max(np.abs(force - fo)) <= 1e-12 * _force_scale(case.tri, so)
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["dirty_sphere128", "ellipsoids256"])
+def test_filter_full_size_sampled_bit_exact(name):
+    # the whole mesh is the occluding surface on both sides; the dirty sphere's
+    # duplicate shell is a thin plate that the filter acts on
+    case = getattr(inputs, "case_" + name)(0)
+    print("case shepard filter", name, len(case.tri), flush=True)
+    s = _solver(case)
+    rng = np.random.default_rng(32)
+    p_np = rng.standard_normal((case.n[2], case.n[1], case.n[0]))
+    side, _ = _gpu(s, case.tri, torch.from_numpy(p_np).cuda(), thin_filter=True)
+    raw, _ = _gpu(s, case.tri, torch.from_numpy(p_np).cuda())
+    idx = np.sort(rng.choice(len(case.tri), 600, replace=False))
+    so, _ = shepard.surface_pressure(_grid(case), p_np, case.tri[idx], thin_filter=True, surface=case.tri)
+    assert _same(side[idx], so)
+    changed = np.sum(~((side == raw) | (np.isnan(side) & np.isnan(raw))))
+    print("values changed by the filter: %d of %d" % (changed, side.size), flush=True)
+    if name == "dirty_sphere128":
+        assert changed > 0
     s.close()
