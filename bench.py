@@ -275,30 +275,24 @@ SHEPARD_BYTES_PER_TRIANGLE = 72 + 16 + 24 * 8
 
 def shepard_timing(case, s, st, torch, calls=20):
     """Times ibm_shepard_force on the workload's triangles and the final pressure of the
-    run: whole calls (kernel, block-partial sum, copy of the three doubles to the host;
-    each call synchronises), host clock."""
+    run, without and with the thin-plate filter Z (the filtered call includes building
+    its triangle bins): whole calls (kernels, block-partial sum, copy of the three
+    doubles to the host; each call synchronises), host clock."""
     tri = torch.as_tensor(case.tri, dtype=torch.float64).cuda().contiguous()
     side = torch.empty((tri.shape[0], 2), dtype=torch.float64, device="cuda")
-    for _ in range(3):
-        s.shepard_force(tri, st["p"], side)
-    t0 = time.perf_counter()
-    for _ in range(calls):
-        f = s.shepard_force(tri, st["p"], side)
-    per = (time.perf_counter() - t0) / calls
     ntri = int(tri.shape[0])
-    return {"triangles": ntri, "us_per_call": round(per * 1e6, 2), "pressure_force": f,
-            "bytes_per_triangle": SHEPARD_BYTES_PER_TRIANGLE,
-            "achieved_gbs_per_call": round(SHEPARD_BYTES_PER_TRIANGLE * ntri / per / 1e9, 1)}
-
-
-# Crank-Nicolson predictor (eq. (crank-nicolson)), three velocity components of FP64:
-# algorithmic bytes per cell of each BiCGStab pass, as stated in momentum.hip (timing
-# slots 4-8 in this order)
-CN_PASSES = ("cn_direction", "cn_apply_p", "cn_stabilise", "cn_apply_s", "cn_update")
-CN_KERNELS = {"cn_direction": "k_cn_dir<double>", "cn_apply_p": "k_cn_ap<double>", "cn_stabilise": "k_cn_s<double>",
-              "cn_apply_s": "k_cn_as<double>", "cn_update": "k_cn_x<double>"}
-CN_BYTES_PER_CELL = {"cn_direction": 96, "cn_apply_p": 105, "cn_stabilise": 72, "cn_apply_s": 81,
-                     "cn_update": 168}
+    out = {"triangles": ntri, "bytes_per_triangle": SHEPARD_BYTES_PER_TRIANGLE}
+    for key, flt in (("", False), ("filtered_", True)):
+        for _ in range(3):
+            s.shepard_force(tri, st["p"], side, flt)
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            f = s.shepard_force(tri, st["p"], side, flt)
+        per = (time.perf_counter() - t0) / calls
+        out[key + "us_per_call"] = round(per * 1e6, 2)
+        out[key + "pressure_force"] = f
+    out["achieved_gbs_per_call"] = round(SHEPARD_BYTES_PER_TRIANGLE * ntri / (out["us_per_call"] * 1e-6) / 1e9, 1)
+    return out
 
 
 # momentum predictor kernel k_predict<double>: reads u, U, H^{n-1} (24 B each), nu_t
