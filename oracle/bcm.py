@@ -1,0 +1,170 @@
+"""Building-cube (BCM) two-level grid oracle (test infrastructure only; the product path
+never imports it): cubes, halo exchange and the pressure operator on the cubes
+(Sec. 2.2, discretization of the grid system).
+
+What is computed (plain FP64 numpy, one halo cell at a time, from the definitions):
+
+* The domain is tiled by K = (Kx, Ky, Kz) coarse cubes of n^3 cells of size dx0; a
+  coarse cube marked for refinement is replaced by 8 fine cubes of n^3 cells of size
+  dx0/2 (the two fixed levels of the paper, a factor of two apart).  Cube order: coarse
+  cubes in z, y, x order; a refined one contributes its 8 fine cubes in z, y, x order.
+* Every cube stores its n^3 cells with H = 2 halo layers on each face ((n + 2H)^3
+  values, x fastest).  The exchange fills only the face halos (axis directions; edges and
+  corners of the halo are not used by an axis stencil and are left alone).
+* A halo cell of cube A takes its value from the cube that covers its centre: from a
+  cube of the same level or a coarser one, the value of the cell that contains the centre
+  (a copy, the paper's zero-order interpolation); from finer cubes, the mean of the 8
+  fine cells inside the halo cell (the paper's averaging), summed in z, y, x order.
+  Outside the domain the halo mirrors the cube's own cells (zero normal gradient): layer
+  l takes interior cell l - 1 counted from the face.
+* The operator on a cube: (L x)_c = (sum of the six axis neighbours - 6 x_c) / dx^2,
+  the neighbours summed in the order -x, +x, -y, +y, -z, +z, read from the cube's own
+  storage (halos included).
+
+Readings: n = 16 cells per cube axis (the paper's figure shows 8, its text gives the
+structure only); mirror halos at the domain boundary (the paper omits the outer boundary
+conditions); the cube order above (an interface, chosen to make the fine cubes of one
+coarse cube contiguous).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+H = 2
+
+
+class Cubes:
+    def __init__(self, K, n, dx0, origin, refine):
+        """refine: bool array (Kz, Ky, Kx)."""
+        self.K = tuple(int(k) for k in K)
+        self.n = int(n)
+        self.dx0 = float(dx0)
+        self.origin = np.asarray(origin, dtype=np.float64)
+        self.refine = np.asarray(refine, dtype=bool)
+        self.cubes = []          # (level, integer origin in fine-cell units (x, y, z))
+        self.first = np.zeros(self.K[::-1], dtype=np.int64)   # first cube of each coarse cube
+        for kz in range(self.K[2]):
+            for ky in range(self.K[1]):
+                for kx in range(self.K[0]):
+                    self.first[kz, ky, kx] = len(self.cubes)
+                    base = np.array([kx, ky, kz]) * 2 * self.n
+                    if self.refine[kz, ky, kx]:
+                        for cz in range(2):
+                            for cy in range(2):
+                                for cx in range(2):
+                                    self.cubes.append((1, base + np.array([cx, cy, cz]) * self.n))
+                    else:
+                        self.cubes.append((0, base))
+        self.side = self.n + 2 * H
+
+    def dx(self, level):
+        return self.dx0 if level == 0 else 0.5 * self.dx0
+
+    def size(self):
+        return len(self.cubes) * self.side ** 3
+
+    def index(self, q, i, j, k):
+        """Storage index of cell (i, j, k) of cube q (interior 0..n-1, halo -H..n+H-1)."""
+        s = self.side
+        return q * s ** 3 + (i + H) + s * ((j + H) + s * (k + H))
+
+    def locate(self, p):
+        """Cube and cell containing the point p (fine-cell units), or None outside."""
+        K2 = np.array(self.K) * 2 * self.n
+        if np.any(p < 0) or np.any(p >= K2):
+            return None
+        kc = (p // (2 * self.n)).astype(int)
+        first = int(self.first[kc[2], kc[1], kc[0]])
+        if self.refine[kc[2], kc[1], kc[0]]:
+            sub = ((p - kc * 2 * self.n) // self.n).astype(int)
+            q = first + sub[0] + 2 * sub[1] + 4 * sub[2]
+            lvl, o = self.cubes[q]
+            cell = (p - o).astype(int)
+        else:
+            q = first
+            lvl, o = self.cubes[q]
+            cell = ((p - o) // 2).astype(int)
+        return q, lvl, cell
+
+    def exchange(self, data):
+        """Fills the face halos of every cube (returns a new array)."""
+        out = data.copy()
+        n = self.n
+        for q, (lvl, o) in enumerate(self.cubes):
+            w = 1 if lvl == 1 else 2                     # this cube's cell size in fine units
+            for axis in range(3):
+                for sgn in (-1, 1):
+                    for layer in range(1, H + 1):
+                        ci = n - 1 + layer if sgn > 0 else -layer
+                        for a in range(n):
+                            for b in range(n):
+                                c = [0, 0, 0]
+                                c[axis] = ci
+                                c[(axis + 1) % 3] = a
+                                c[(axis + 2) % 3] = b
+                                centre = o + (np.array(c) + 0.5) * w     # fine-cell units
+                                hit = self.locate(centre)
+                                if hit is None:
+                                    m = list(c)
+                                    m[axis] = n - layer if sgn > 0 else layer - 1
+                                    v = data[self.index(q, *m)]
+                                else:
+                                    qq, l2, cell = hit
+                                    if l2 <= lvl or lvl == 1:
+                                        v = data[self.index(qq, *cell)]
+                                    else:
+                                        # coarse halo cell over fine cells: mean of the 8,
+                                        # summed in z, y, x order
+                                        s = 0.0
+                                        lo = o + np.array(c) * 2
+                                        for dz in range(2):
+                                            for dy in range(2):
+                                                for dxx in range(2):
+                                                    pp = lo + np.array([dxx, dy, dz]) + 0.5
+                                                    q3, _, c3 = self.locate(pp)
+                                                    s += data[self.index(q3, *c3)]
+                                        v = s / 8.0
+                                out[self.index(q, *c)] = v
+        return out
+
+    def laplacian(self, data):
+        """(L x) on every cube interior (halos of the result are zero)."""
+        out = np.zeros_like(data)
+        n = self.n
+        for q, (lvl, o) in enumerate(self.cubes):
+            dx = self.dx(lvl)
+            for k in range(n):
+                for j in range(n):
+                    for i in range(n):
+                        xc = data[self.index(q, i, j, k)]
+                        s = data[self.index(q, i - 1, j, k)]
+                        s = s + data[self.index(q, i + 1, j, k)]
+                        s = s + data[self.index(q, i, j - 1, k)]
+                        s = s + data[self.index(q, i, j + 1, k)]
+                        s = s + data[self.index(q, i, j, k - 1)]
+                        s = s + data[self.index(q, i, j, k + 1)]
+                        out[self.index(q, i, j, k)] = (s - 6.0 * xc) / (dx * dx)
+        return out
+
+    def cell_centres(self, q):
+        """Physical centres (n, n, n, 3) of cube q's interior cells, array order (k, j, i)."""
+        lvl, o = self.cubes[q]
+        w = 1 if lvl == 1 else 2
+        ax = [(o[a] + (np.arange(self.n) + 0.5) * w) * 0.5 * self.dx0 + self.origin[a] for a in range(3)]
+        zz, yy, xx = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        return np.stack([xx, yy, zz], axis=-1)
+
+    def fill(self, f):
+        """Cube storage with f(x, y, z) at every interior cell, zero halos."""
+        data = np.zeros(self.size())
+        s = self.side
+        for q in range(len(self.cubes)):
+            cc = self.cell_centres(q)
+            block = data[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)
+            block[H:H + self.n, H:H + self.n, H:H + self.n] = f(cc[..., 0], cc[..., 1], cc[..., 2])
+        return data
+
+    def interior(self, data, q):
+        s = self.side
+        block = data[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)
+        return block[H:H + self.n, H:H + self.n, H:H + self.n]

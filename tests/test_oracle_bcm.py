@@ -1,0 +1,103 @@
+"""Pins of the building-cube (BCM) grid oracle (oracle/bcm.py; Sec. 2.2): one level of
+cubes reproduces the uniform-grid operator bit for bit; on two levels a constant field
+stays constant across the halos with a zero operator, fine-to-coarse averages of a
+linear field are exact and coarse-to-fine copies take the covering coarse cell; only
+face halos are written."""
+import numpy as np
+
+from oracle import bcm
+
+
+def test_one_level_equals_the_uniform_grid():
+    K, n, dx = (2, 3, 2), 4, 0.7
+    C = bcm.Cubes(K, n, dx, (0.0, 0.0, 0.0), np.zeros(K[::-1], bool))
+    rng = np.random.default_rng(0)
+    N = (K[0] * n, K[1] * n, K[2] * n)
+    u = rng.standard_normal(N[::-1])          # (z, y, x)
+    data = np.zeros(C.size())
+    s = C.side
+    for q, (lvl, o) in enumerate(C.cubes):
+        i0, j0, k0 = o // 2
+        blk = data[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)
+        blk[bcm.H:bcm.H + n, bcm.H:bcm.H + n, bcm.H:bcm.H + n] = u[k0:k0 + n, j0:j0 + n, i0:i0 + n]
+    ex = C.exchange(data)
+    # every face halo (both layers) equals the uniform field padded symmetrically by two
+    # cells: neighbour values inside the domain, mirrored cells 0 and 1 outside
+    pad = np.pad(u, bcm.H, mode="symmetric")
+    h = bcm.H
+    for q, (lvl, o) in enumerate(C.cubes):
+        i0, j0, k0 = o // 2
+        blk = ex[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)
+        ref = pad[k0:k0 + n + 2 * h, j0:j0 + n + 2 * h, i0:i0 + n + 2 * h]
+        for sl in ((slice(h, h + n), slice(h, h + n), slice(None)),
+                   (slice(h, h + n), slice(None), slice(h, h + n)),
+                   (slice(None), slice(h, h + n), slice(h, h + n))):
+            assert np.array_equal(blk[sl], ref[sl])
+    L = C.laplacian(ex)
+    # the uniform grid with mirror (zero-gradient) boundaries, neighbours in the same order
+    g = np.pad(u, 1, mode="edge")
+    c = g[1:-1, 1:-1, 1:-1]
+    ref = (g[1:-1, 1:-1, :-2] + g[1:-1, 1:-1, 2:] + g[1:-1, :-2, 1:-1] + g[1:-1, 2:, 1:-1] + g[:-2, 1:-1, 1:-1]
+           + g[2:, 1:-1, 1:-1] - 6.0 * c) / (dx * dx)
+    for q, (lvl, o) in enumerate(C.cubes):
+        i0, j0, k0 = o // 2
+        assert np.array_equal(C.interior(L, q), ref[k0:k0 + n, j0:j0 + n, i0:i0 + n])
+
+
+def _two_level():
+    K, n, dx = (3, 2, 2), 4, 1.0
+    refine = np.zeros(K[::-1], bool)
+    refine[0, 0, 1] = True
+    refine[1, 1, 2] = True
+    return bcm.Cubes(K, n, dx, (0.5, -1.0, 2.0), refine)
+
+
+def test_constant_field_on_two_levels():
+    C = _two_level()
+    assert len(C.cubes) == 3 * 2 * 2 - 2 + 16
+    data = C.exchange(C.fill(lambda x, y, z: np.full_like(x, 3.25)))
+    s, n, h = C.side, C.n, bcm.H
+    for q in range(len(C.cubes)):
+        blk = data[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)
+        assert np.all(blk[h:h + n, h:h + n, :] == 3.25)     # x-face halos
+        assert np.all(blk[h:h + n, :, h:h + n] == 3.25)
+        assert np.all(blk[:, h:h + n, h:h + n] == 3.25)
+        assert blk[0, 0, 0] == 0.0                           # corners untouched
+    assert np.max(np.abs(C.laplacian(data))) == 0.0
+
+
+def test_linear_field_averages_and_copies():
+    C = _two_level()
+    f = lambda x, y, z: 0.3 + 1.7 * x - 0.9 * y + 0.4 * z  # noqa: E731
+    data = C.exchange(C.fill(f))
+    n, h = C.n, bcm.H
+    checked = {"avg": 0, "copy": 0}
+    for q, (lvl, o) in enumerate(C.cubes):
+        w = 1 if lvl == 1 else 2
+        for axis in range(3):
+            for sgn in (-1, 1):
+                for layer in (1, 2):
+                    c = [1, 2, 3]
+                    c[axis] = n - 1 + layer if sgn > 0 else -layer
+                    centre = o + (np.array(c) + 0.5) * w
+                    hit = C.locate(centre)
+                    if hit is None:
+                        continue
+                    q2, l2, cell = hit
+                    v = data[C.index(q, *c)]
+                    x = (centre * 0.5 * C.dx0) + C.origin
+                    if lvl == 0 and l2 == 1:          # average of fine cells: exact for linear
+                        assert abs(v - f(*x)) < 1e-12
+                        checked["avg"] += 1
+                    elif lvl == 1 and l2 == 0:        # copy of the covering coarse cell
+                        cc = C.cell_centres(q2)[cell[2], cell[1], cell[0]]
+                        assert v == data[C.index(q2, *cell)] and abs(v - f(*cc)) < 1e-12
+                        checked["copy"] += 1
+                    else:                             # same level: the neighbour's own cell
+                        assert abs(v - f(*x)) < 1e-12
+    assert checked["avg"] > 0 and checked["copy"] > 0
+    # the operator of a linear field vanishes away from the level interfaces
+    L = C.laplacian(data)
+    q0 = 0                                            # coarse cube at the corner (0, 0, 0)
+    assert C.cubes[q0][0] == 0
+    assert np.max(np.abs(C.interior(L, q0)[1:3, 1:3, 1:3])) < 1e-12   # clear of boundary and interface
