@@ -344,6 +344,33 @@ int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* 
  * must cover the grid and outlive its use. */
 int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net);
 
+/* Building-cube grid (Sec. 2.2): the domain is tiled by K[0] x K[1] x K[2] coarse cubes
+ * of n^3 cells of size dx0 (n even); a coarse cube with refine_host[kx + K0 (ky + K1 kz)]
+ * != 0 is replaced by 8 fine cubes of n^3 cells of size dx0/2 (two fixed levels, a
+ * factor of two apart).  Cube order: coarse cubes in z, y, x order, a refined one
+ * contributing its 8 fine cubes in z, y, x order.  Each cube is stored as (n + 4)^3
+ * doubles (two halo layers per face, x fastest); cube q starts at q (n + 4)^3.
+ * Allocates the halo tables on the current device (host memory is read once). */
+typedef struct ibm_bcm ibm_bcm;
+int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origin[3], const uint8_t* refine_host,
+                   ibm_bcm** out);
+int ibm_bcm_destroy(ibm_bcm* grid);
+/* Counts (any of the outputs may be NULL): cubes, values of the storage, face-halo
+ * cells; levels_host[ncubes] (0 coarse, 1 fine) and origins_host[3 ncubes] (x, y, z of
+ * each cube's first cell in fine-cell units). */
+int ibm_bcm_info(const ibm_bcm* grid, int64_t* ncubes, int64_t* size, int64_t* nhalo, int32_t* levels_host,
+                 int32_t* origins_host);
+/* Fills the face halos (both layers; edges and corners untouched) of every cube of
+ * data_dev in place: from a cube of the same or a coarser level the cell containing the
+ * halo cell's centre (a copy, the paper's zero-order interpolation), from finer cubes the
+ * mean of the 8 fine cells inside it (averaging), at the domain boundary the mirror of
+ * the cube's own cells (layer l takes interior cell l - 1 from the face). */
+int ibm_bcm_exchange(const ibm_bcm* grid, double* data_dev, void* stream);
+/* y = L x on every cube interior: (sum of the six axis neighbours - 6 x_c) / dx^2 with the
+ * cube's own dx, neighbours read from its storage (exchange first); halos of y are not
+ * written; x and y distinct. */
+int ibm_bcm_laplacian(const ibm_bcm* grid, const double* x_dev, double* y_dev, void* stream);
+
 /* Measurement support (not part of the method).  When enabled, launches of the
  * pressure solve are bracketed by HIP events on its stream and the elapsed times are
  * collected at the end of each solve.  Slots: 0 = CG pass A (SpMV, <d,q>; for the

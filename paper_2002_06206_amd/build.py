@@ -22,6 +22,7 @@ SOURCES = [
     ("cnn.hip", []),
     ("shepard.hip", ["-ffp-contract=off"]),
     ("momentum.hip", []),
+    ("bcm.hip", ["-ffp-contract=off"]),
     ("api.hip", []),
 ]
 

@@ -107,6 +107,13 @@ def _load():
                                ctypes.c_int),
         "ibm_cnn_precondition": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "ibm_ctx_set_preconditioner": ([vp, vp], ctypes.c_int),
+        "ibm_bcm_create": ([ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
+                            ctypes.POINTER(ctypes.c_double), vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "ibm_bcm_destroy": ([vp], ctypes.c_int),
+        "ibm_bcm_info": ([vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_int64), vp, vp], ctypes.c_int),
+        "ibm_bcm_exchange": ([vp, vp, vp], ctypes.c_int),
+        "ibm_bcm_laplacian": ([vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -122,7 +129,8 @@ EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "
             "ibm_timing_slot", "ibm_set_progress", "ibm_momentum_apply", "ibm_momentum_solve",
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
-            "ibm_ctx_set_preconditioner")
+            "ibm_ctx_set_preconditioner", "ibm_bcm_create", "ibm_bcm_destroy", "ibm_bcm_info", "ibm_bcm_exchange",
+            "ibm_bcm_laplacian")
 CNN_NWEIGHTS = 7776
 
 
@@ -466,3 +474,47 @@ class Network:
 
     def attach(self, solver: "Solver"):
         ibm_ctx_set_preconditioner(solver.ctx, self.net)
+
+
+class BCM:
+    """Building-cube grid (Sec. 2.2) on the current HIP device: two levels of n^3-cell
+    cubes, halo exchange and the 7-point operator (ibm_bcm_*)."""
+
+    def __init__(self, K, n, dx0, origin, refine):
+        import numpy as np
+        ref = np.ascontiguousarray(np.asarray(refine, dtype=np.uint8).reshape(K[2], K[1], K[0]))
+        out = ctypes.c_void_p()
+        _check(_lib.ibm_bcm_create((ctypes.c_int32 * 3)(*K), int(n), float(dx0), (ctypes.c_double * 3)(*origin),
+                                   ref.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)), "ibm_bcm_create")
+        self.grid = out
+        nc, size, nh = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.ibm_bcm_info(self.grid, ctypes.byref(nc), ctypes.byref(size), ctypes.byref(nh), None, None),
+               "ibm_bcm_info")
+        self.ncubes, self.size, self.nhalo = nc.value, size.value, nh.value
+        lv = np.zeros(self.ncubes, dtype=np.int32)
+        org = np.zeros((self.ncubes, 3), dtype=np.int32)
+        _check(_lib.ibm_bcm_info(self.grid, None, None, None, lv.ctypes.data_as(ctypes.c_void_p),
+                                 org.ctypes.data_as(ctypes.c_void_p)), "ibm_bcm_info")
+        self.levels, self.origins = lv, org
+        self.n = int(n)
+
+    def exchange(self, data):
+        return _check(_lib.ibm_bcm_exchange(self.grid, _ptr(data), _stream()), "ibm_bcm_exchange")
+
+    def laplacian(self, x, y):
+        return _check(_lib.ibm_bcm_laplacian(self.grid, _ptr(x), _ptr(y), _stream()), "ibm_bcm_laplacian")
+
+    def close(self):
+        if self.grid:
+            ibm_bcm_destroy(self.grid)
+            self.grid = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ibm_bcm_destroy(grid):
+    return _check(_lib.ibm_bcm_destroy(grid), "ibm_bcm_destroy")

@@ -1,0 +1,52 @@
+"""GPU parity of the building-cube grid (Sec. 2.2) against oracle/bcm.py through the C
+ABI: cube order and levels equal to the oracle's, the halo exchange (copies, means of
+8 fine cells, mirrors) and the 7-point operator on the cubes bit for bit, on a one-level
+grid against the uniform operator, and on two levels with several refined cubes."""
+import numpy as np
+import pytest
+
+from oracle import bcm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2002_06206_amd import ibm
+else:  # collected on CPU machines, skipped by the marker filter
+    ibm = None
+
+
+@pytest.mark.parametrize("K,n,cells", [((2, 3, 2), 4, ((0, 0, 1), (1, 2, 0))),
+                                        ((3, 2, 2), 8, ((0, 0, 0), (1, 1, 2), (0, 1, 1))),
+                                        ((2, 2, 2), 16, ())])
+def test_exchange_and_operator_bit_exact(K, n, cells):
+    refine = np.zeros(K[::-1], bool)
+    for c in cells:
+        refine[c] = True
+    dx0, origin = 0.8, (0.5, -1.0, 2.0)
+    print("case bcm", K, n, cells, flush=True)
+    C = bcm.Cubes(K, n, dx0, origin, refine)
+    G = ibm.BCM(K, n, dx0, origin, refine)
+    assert G.ncubes == len(C.cubes) and G.size == C.size()
+    assert np.array_equal(G.levels, [lv for lv, _ in C.cubes])
+    assert np.array_equal(G.origins, np.array([o for _, o in C.cubes]))
+    rng = np.random.default_rng(1)
+    data = rng.standard_normal(C.size())
+    ref = C.exchange(data)
+    d = torch.from_numpy(data.copy()).cuda()
+    G.exchange(d)
+    got = d.cpu().numpy()
+    assert np.array_equal(got, ref)
+    y = torch.zeros_like(d)
+    G.laplacian(d, y)
+    L = C.laplacian(ref)
+    for q in range(len(C.cubes)):
+        assert np.array_equal(C.interior(y.cpu().numpy(), q), C.interior(L, q))
+    G.close()
+
+
+def test_bad_arguments_rejected():
+    with pytest.raises(ibm.IBMError):
+        ibm.BCM((2, 2, 2), 5, 1.0, (0, 0, 0), np.zeros((2, 2, 2), bool))      # odd n
+    with pytest.raises(ibm.IBMError):
+        ibm.BCM((0, 2, 2), 4, 1.0, (0, 0, 0), np.zeros((2, 2, 0), bool))
