@@ -242,6 +242,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
         if args.quick_steps > 0:
             out["hybrid_quick"] = quick_timing(case, s, st, ctl, step, args, ibm, torch)
             step += 2 + args.quick_steps
+    if solver == "pcg_fp64" and args.bcm:
+        out["building_cubes"] = bcm_timing(case, blocked, args, ibm, torch)
     if solver == "pcg_fp64" and args.sor:
         out["red_black_sor"] = sor_timing(case, s, args, ibm, torch)
     if solver == "pcg_fp64" and args.cn_steps > 0:
@@ -391,6 +393,64 @@ def sor_timing(case, s, args, ibm, torch):
     return out
 
 
+def bcm_timing(case, blocked, args, ibm, torch, reps=20):
+    """The building-cube grid (Sec. 2.2) over the workload's domain: coarse cubes of 16^3
+    cells of twice the workload's cell size, refined (8 cubes of 16^3 cells at the
+    workload's cell size) wherever the geometry cuts a grid line inside them; the halo
+    exchange and the 7-point operator timed with events on the stream they run on."""
+    n = 16
+    N = case.n
+    if any(v % (2 * n) for v in N):
+        return None
+    K = tuple(v // (2 * n) for v in N)
+    b = blocked.reshape(N[2], N[1], N[0]).to(torch.bool)
+    refine = b.reshape(K[2], 2 * n, K[1], 2 * n, K[0], 2 * n).any(dim=5).any(dim=3).any(dim=1).cpu().numpy()
+    G = ibm.BCM(K, n, 2.0 * case.dx, case.origin, refine)
+    x = torch.randn(G.size, dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    for _ in range(3):
+        G.exchange(x)
+        G.laplacian(x, y)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        G.exchange(x)
+    ev[1].record()
+    for _ in range(reps):
+        G.laplacian(x, y)
+    ev[2].record()
+    torch.cuda.synchronize()
+    ex_us = ev[0].elapsed_time(ev[1]) / reps * 1e3
+    lap_us = ev[1].elapsed_time(ev[2]) / reps * 1e3
+    cells = G.ncubes * n ** 3
+    fine = int(refine.sum())
+    # algorithmic bytes: operator 16 B per cell (x read once, y written); exchange per
+    # halo cell the destination, two offsets and one source index (16 B), the value
+    # read and written (16 B), plus 7 more source reads and indices for a mean
+    lap_bytes = 16 * cells
+    out = {"coarse_cubes": math.prod(K), "refined": fine, "cubes": int(G.ncubes), "cells": int(cells),
+           "halo_cells": int(G.nhalo), "exchange_us": round(ex_us, 2), "laplacian_us": round(lap_us, 2),
+           "laplacian_bytes_per_cell": 16,
+           "laplacian_achieved_gbs": round(lap_bytes / (lap_us * 1e-6) / 1e9, 1),
+           "roofline": {"bound": "hbm", "achieved": round(lap_bytes / (lap_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(lap_bytes / (lap_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": committed_traffic("bcm_laplacian", args.workload), "kernel": "k_bcm_lap",
+                        "algorithmic_bytes_per_launch": lap_bytes, "avg_launch_us": round(lap_us, 2)}}
+    G.close()
+    return out
+
+
+# Crank-Nicolson predictor (eq. (crank-nicolson)), three velocity components of FP64:
+# algorithmic bytes per cell of each BiCGStab pass, as stated in momentum.hip (timing
+# slots 4-8 in this order)
+CN_PASSES = ("cn_direction", "cn_apply_p", "cn_stabilise", "cn_apply_s", "cn_update")
+CN_KERNELS = {"cn_direction": "k_cn_dir<double>", "cn_apply_p": "k_cn_ap<double>", "cn_stabilise": "k_cn_s<double>",
+              "cn_apply_s": "k_cn_as<double>", "cn_update": "k_cn_x<double>"}
+CN_BYTES_PER_CELL = {"cn_direction": 96, "cn_apply_p": 105, "cn_stabilise": 72, "cn_apply_s": 81,
+                     "cn_update": 168}
+
+
 def cn_timing(case, s, st, ctl, step, args, ibm, torch):
     """Crank-Nicolson steps on the developed plain FP64 state at twice the explicit CFL
     (0.6): whole steps timed by the host clock, the five BiCGStab passes by dispatch
@@ -501,6 +561,7 @@ def main():
                     help="explicit steps with the hybrid central/QUICK face value timed after the plain run (0: none)")
     ap.add_argument("--quick", type=float, default=0.1, help="QUICK weight of the hybrid face value")
     ap.add_argument("--sor", type=int, default=1, help="time red-black SOR against PCG on one right-hand side")
+    ap.add_argument("--bcm", type=int, default=1, help="time the building-cube halo exchange and operator")
     ap.add_argument("--sor-omega", type=float, default=0.0, help="SOR relaxation (0: 2/(1+sin(pi/n)))")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -572,7 +633,8 @@ def main():
         "plain_fp64_value": plain["value"] if plain else None,
         "speedup_vs_plain_fp64": head["value"] / plain["value"] if plain else None,
         "solvers": {k: {kk: vv for kk, vv in v.items()
-                        if kk not in ("dominant", "crank_nicolson", "hybrid_quick", "predictor", "red_black_sor")}
+                        if kk not in ("dominant", "crank_nicolson", "hybrid_quick", "predictor", "red_black_sor",
+                                      "building_cubes")}
                     for k, v in runs.items()},
         "speedups_vs_plain_fp64": {k: round(v["value"] / plain["value"], 4) for k, v in runs.items()} if plain else None,
         "training": train_info,
@@ -582,6 +644,7 @@ def main():
         "crank_nicolson": plain.get("crank_nicolson") if plain else None,
         "hybrid_quick": plain.get("hybrid_quick") if plain else None,
         "red_black_sor": plain.get("red_black_sor") if plain else None,
+        "building_cubes": plain.get("building_cubes") if plain else None,
         "predictor": plain.get("predictor") if plain else None,
         "cpu_baseline": cpu,
     }
