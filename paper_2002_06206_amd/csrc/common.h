@@ -135,10 +135,11 @@ struct ibm_ctx {
     ibm::CnState* h_cn_state;  // pinned host mirror
     int cn_last_iters;      // iterations of the previous momentum solve (batch sizing)
     // triangle bins of the near-field force's thin-plate filter (grow-only, first use)
-    int* bin_count;         // 2 * (bins + 1): counts / fill cursor, then offsets
+    long long* bin_count;   // 2 * (bins + 1): counts / fill cursor, then offsets
     int* bin_ids;
-    long long* bin_tot;
-    long long bin_cap, bin_ids_cap, bin_tot_cap;
+    uint8_t* bin_occ;       // 24 crossing flags per triangle
+    char* bin_tmp;          // scan workspace
+    long long bin_cap, bin_ids_cap, bin_occ_cap, bin_tmp_cap;
     // optional progress hook, called at the solver's host convergence polls
     ibm_progress_fn progress;
     void* progress_user;

@@ -16,12 +16,15 @@
 // when the segment from the vertex to it crosses a triangle of the surface at a
 // parameter t in (T_MIN, 1] (Moller-Trumbore, edges inclusive), i.e. when the point lies
 // behind another face, as the far side of a plate thinner than a cell does.  Candidate
-// triangles come from uniform bins of 4x4x4 cells (counted with global atomics, an
+// triangles come from uniform bins of 2x2x2 cells (counted with global atomics, an
 // exclusive scan, filled with global atomics); the order inside a bin does not matter,
-// since only whether some triangle is crossed counts.
+// since only whether some triangle is crossed counts.  The crossing flags of all
+// (triangle, vertex, corner) triples are computed first, one thread each.
 
 #include <cfloat>
 #include <cmath>
+
+#include <hipcub/hipcub.hpp>
 
 #include "common.h"
 
@@ -29,12 +32,12 @@ namespace ibm {
 namespace {
 
 constexpr double T_MIN = 1e-6;
-constexpr int BIN_CELLS = 4;
+constexpr int BIN_CELLS = 2;
 
 struct Bins {
     int nbx, nby, nbz;
     double bdx, ox, oy, oz;
-    const int* off;   // nbins + 1 offsets into ids
+    const long long* off;   // nbins + 1 offsets into ids
     const int* ids;   // triangle ids per bin
 };
 
@@ -72,7 +75,7 @@ __device__ inline bool occluded(const Bins& B, const double* __restrict__ tri, d
         for (int by = y0; by <= y1; ++by)
             for (int bx = x0; bx <= x1; ++bx) {
                 const long long b = bx + (long long)B.nbx * (by + (long long)B.nby * bz);
-                for (int e = B.off[b]; e < B.off[b + 1]; ++e)
+                for (long long e = B.off[b]; e < B.off[b + 1]; ++e)
                     if (seg_hits(px, py, pz, dx_, dy, dz, tri + 9 * (long long)B.ids[e])) return true;
             }
     return false;
@@ -91,70 +94,79 @@ __device__ inline bool tri_bins(const Bins& B, const double* __restrict__ v, int
     return true;
 }
 
+// One wavefront per triangle: its lanes walk the triangle's bin range together (a plate
+// triangle can span thousands of bins; one thread per triangle serialised those).
 __global__ void __launch_bounds__(NT) k_bin_count(Bins B, const double* __restrict__ tri, long long ntri,
-                                                  int* __restrict__ count) {
-    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < ntri; t += (long long)gridDim.x * NT) {
+                                                  long long* __restrict__ count) {
+    const int lane = threadIdx.x & 63;
+    const long long waves = (long long)gridDim.x * (NT / 64);
+    for (long long t = (long long)blockIdx.x * (NT / 64) + (threadIdx.x >> 6); t < ntri; t += waves) {
         int lo[3], hi[3];
         if (!tri_bins(B, tri + 9 * t, lo, hi)) continue;
-        for (int bz = lo[2]; bz <= hi[2]; ++bz)
-            for (int by = lo[1]; by <= hi[1]; ++by)
-                for (int bx = lo[0]; bx <= hi[0]; ++bx)
-                    atomicAdd(&count[bx + (long long)B.nbx * (by + (long long)B.nby * bz)], 1);
+        const long long ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1;
+        const long long nbt = ex * ey * (hi[2] - lo[2] + 1);
+        for (long long e = lane; e < nbt; e += 64) {
+            const int bx = lo[0] + (int)(e % ex), by = lo[1] + (int)((e / ex) % ey), bz = lo[2] + (int)(e / (ex * ey));
+            atomicAdd((unsigned long long*)&count[bx + (long long)B.nbx * (by + (long long)B.nby * bz)], 1ULL);
+        }
     }
 }
 
 __global__ void __launch_bounds__(NT) k_bin_fill(Bins B, const double* __restrict__ tri, long long ntri,
-                                                 int* __restrict__ cursor, int* __restrict__ ids) {
-    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < ntri; t += (long long)gridDim.x * NT) {
+                                                 long long* __restrict__ cursor, int* __restrict__ ids) {
+    const int lane = threadIdx.x & 63;
+    const long long waves = (long long)gridDim.x * (NT / 64);
+    for (long long t = (long long)blockIdx.x * (NT / 64) + (threadIdx.x >> 6); t < ntri; t += waves) {
         int lo[3], hi[3];
         if (!tri_bins(B, tri + 9 * t, lo, hi)) continue;
-        for (int bz = lo[2]; bz <= hi[2]; ++bz)
-            for (int by = lo[1]; by <= hi[1]; ++by)
-                for (int bx = lo[0]; bx <= hi[0]; ++bx) {
-                    const long long b = bx + (long long)B.nbx * (by + (long long)B.nby * bz);
-                    const int pos = atomicAdd(&cursor[b], 1);
-                    ids[B.off[b] + pos] = (int)t;
-                }
-    }
-}
-
-// exclusive scan of count[0..n) into off[0..n] by one block (off[n] = total, as a
-// 64-bit sum in tot for the overflow check)
-__global__ void __launch_bounds__(1024) k_bin_scan(const int* __restrict__ count, long long n, int* __restrict__ off,
-                                                   long long* __restrict__ tot) {
-    __shared__ long long part[1024];
-    const long long per = (n + 1023) / 1024;
-    const long long a = threadIdx.x * per, b = a + per < n ? a + per : n;
-    long long sum = 0;
-    for (long long i = a; i < b; ++i) sum += count[i];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        long long run = 0;
-        for (int q = 0; q < 1024; ++q) {
-            const long long v = part[q];
-            part[q] = run;
-            run += v;
+        const long long ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1;
+        const long long nbt = ex * ey * (hi[2] - lo[2] + 1);
+        for (long long e = lane; e < nbt; e += 64) {
+            const int bx = lo[0] + (int)(e % ex), by = lo[1] + (int)((e / ex) % ey), bz = lo[2] + (int)(e / (ex * ey));
+            const long long b = bx + (long long)B.nbx * (by + (long long)B.nby * bz);
+            const long long pos = (long long)atomicAdd((unsigned long long*)&cursor[b], 1ULL);
+            ids[B.off[b] + pos] = (int)t;
         }
-        *tot = run;
-        off[n] = (int)(run < 0x7fffffffLL ? run : 0x7fffffffLL);
-    }
-    __syncthreads();
-    long long run = part[threadIdx.x];
-    for (long long i = a; i < b; ++i) {
-        off[i] = (int)(run < 0x7fffffffLL ? run : 0x7fffffffLL);
-        run += count[i];
     }
 }
 
-__global__ void k_fill_int(int* __restrict__ a, long long n) {
+__global__ void k_fill_ll(long long* __restrict__ a, long long n) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         a[i] = 0;
 }
 
+// Filter flag of every (triangle, vertex, dual-cell corner) in the corner order of
+// k_shepard (a + 2 b + 4 c): whether the segment from the vertex to that cell centre
+// crosses a triangle.  One thread per flag, so the long candidate loops spread over 24
+// threads per triangle; k_shepard decides everything else as without the filter.
+__global__ void __launch_bounds__(NT) k_occlude(Geo g, const double* __restrict__ tri, long long ntri, Bins B,
+                                                uint8_t* __restrict__ occ) {
+    for (long long w = (long long)blockIdx.x * NT + threadIdx.x; w < 24 * ntri; w += (long long)gridDim.x * NT) {
+        const long long t = w / 24;
+        const int r = (int)(w - 24 * t), q = r >> 3, corner = r & 7;
+        const double* v = tri + 9 * t + 3 * q;
+        const double X = v[0], Y = v[1], Z = v[2];
+        uint8_t hit = 0;
+        const double fi = floor((X - g.ox) / g.dx - 0.5), fj = floor((Y - g.oy) / g.dx - 0.5),
+                     fk = floor((Z - g.oz) / g.dx - 0.5);
+        if (fi >= -2.0 && fi <= g.nx + 1.0 && fj >= -2.0 && fj <= g.ny + 1.0 && fk >= -2.0 && fk <= g.nz + 1.0) {
+            const long long i = (long long)fi + (corner & 1), j = (long long)fj + ((corner >> 1) & 1),
+                            k = (long long)fk + (corner >> 2);
+            if (i >= 0 && i < g.nx && j >= 0 && j < g.ny && k >= 0 && k < g.nz) {
+                const double xc = g.ox + ((double)i + 0.5) * g.dx;
+                const double yc = g.oy + ((double)j + 0.5) * g.dx;
+                const double zc = g.oz + ((double)k + 0.5) * g.dx;
+                hit = occluded(B, tri, X, Y, Z, xc, yc, zc) ? 1 : 0;
+            }
+        }
+        occ[w] = hit;
+    }
+}
+
 __global__ void __launch_bounds__(NT) k_shepard(Geo g, const double* __restrict__ tri, long long ntri,
                                                 const double* __restrict__ p, double* __restrict__ side,
-                                                double* __restrict__ part, Bins B, int filter) {
+                                                double* __restrict__ part, const uint8_t* __restrict__ occ,
+                                                int filter) {
     __shared__ double sh[3 * (NT / 64)];
     double f[3] = {0.0, 0.0, 0.0};
     const long long cells_x = g.nx, cells_xy = (long long)g.nx * g.ny;
@@ -191,7 +203,7 @@ __global__ void __launch_bounds__(NT) k_shepard(Geo g, const double* __restrict_
                             const double rx = xc - X, ry = yc - Y, rz = zc - Z;
                             const double s = nxv * rx + nyv * ry + nzv * rz;
                             if (s == 0.0) continue;
-                            if (filter && occluded(B, tri, X, Y, Z, xc, yc, zc)) continue;
+                            if (filter && occ[24 * t + 8 * q + (a + 2 * b + 4 * c)]) continue;
                             const int sd = s > 0.0 ? 0 : 1;
                             const double d2 = rx * rx + ry * ry + rz * rz;
                             num[sd] += p[i + cells_x * j + cells_xy * k] / d2;
@@ -255,6 +267,7 @@ int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, 
     const long long nbk = (ntri + NT - 1) / NT;
     const int nb = (int)(nbk < 2048 ? nbk : 2048);
     Bins B{};
+    uint8_t* occ = nullptr;
     if (filter) {
         B.nbx = (g.nx + BIN_CELLS - 1) / BIN_CELLS;
         B.nby = (g.ny + BIN_CELLS - 1) / BIN_CELLS;
@@ -265,30 +278,39 @@ int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, 
         B.oz = g.oz;
         const long long nbins = (long long)B.nbx * B.nby * B.nbz;
         if (int rc = grow(&c->bin_count, &c->bin_cap, 2 * (nbins + 1))) return rc;
-        if (int rc = grow(&c->bin_tot, &c->bin_tot_cap, 1)) return rc;
-        int* count = c->bin_count;
-        int* off = c->bin_count + (nbins + 1);
-        k_fill_int<<<1024, 256, 0, s>>>(count, nbins + 1);
-        k_bin_count<<<nb, NT, 0, s>>>(B, tri, ntri, count);
-        k_bin_scan<<<1, 1024, 0, s>>>(count, nbins, off, c->bin_tot);
+        if (int rc = grow(&c->bin_occ, &c->bin_occ_cap, 24 * ntri)) return rc;
+        long long* count = c->bin_count;
+        long long* off = c->bin_count + (nbins + 1);
+        const long long nbw = (ntri + NT / 64 - 1) / (NT / 64);   // one wavefront per triangle
+        const int nbb = (int)(nbw < 8192 ? nbw : 8192);
+        k_fill_ll<<<1024, 256, 0, s>>>(count, nbins + 1);
+        k_bin_count<<<nbb, NT, 0, s>>>(B, tri, ntri, count);
+        size_t tmp_bytes = 0;
+        IBM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, count, off, (int)(nbins + 1), s));
+        if (int rc = grow(&c->bin_tmp, &c->bin_tmp_cap, (long long)tmp_bytes)) return rc;
+        IBM_HIP(hipcub::DeviceScan::ExclusiveSum(c->bin_tmp, tmp_bytes, count, off, (int)(nbins + 1), s));
         long long total = 0;
-        IBM_HIP(hipMemcpyAsync(&total, c->bin_tot, sizeof(long long), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipMemcpyAsync(&total, off + nbins, sizeof(long long), hipMemcpyDeviceToHost, s));
         IBM_HIP(hipStreamSynchronize(s));
         if (total >= 0x7fffffffLL) {
             set_error("near-field force: too many triangle-bin entries for the thin-plate filter");
             return IBM_ERR_ARG;
         }
         if (int rc = grow(&c->bin_ids, &c->bin_ids_cap, total)) return rc;
-        k_fill_int<<<1024, 256, 0, s>>>(count, nbins + 1);   // reused as the fill cursor
+        k_fill_ll<<<1024, 256, 0, s>>>(count, nbins + 1);   // reused as the fill cursor
         B.off = off;
         B.ids = c->bin_ids;
-        k_bin_fill<<<nb, NT, 0, s>>>(B, tri, ntri, count, c->bin_ids);
+        k_bin_fill<<<nbb, NT, 0, s>>>(B, tri, ntri, count, c->bin_ids);
+        const long long nbo = (24 * ntri + NT - 1) / NT;
+        k_occlude<<<(int)(nbo < 16384 ? nbo : 16384), NT, 0, s>>>(c->geo, tri, ntri, B, c->bin_occ);
+        occ = c->bin_occ;
         IBM_HIP(hipGetLastError());
     }
     if (c->timing_on)
-        launch_timed(c, TK_OTHER, k_shepard, nb, s, c->geo, tri, ntri, p, side, c->partials, B, filter);
+        launch_timed(c, TK_OTHER, k_shepard, nb, s, c->geo, tri, ntri, p, side, c->partials, (const uint8_t*)occ,
+                     filter);
     else
-        k_shepard<<<nb, NT, 0, s>>>(c->geo, tri, ntri, p, side, c->partials, B, filter);
+        k_shepard<<<nb, NT, 0, s>>>(c->geo, tri, ntri, p, side, c->partials, occ, filter);
     k_sum3<<<1, NT, 0, s>>>(c->partials, nb, c->red);
     IBM_HIP(hipGetLastError());
     IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -300,10 +322,13 @@ int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, 
 void shepard_release(ibm_ctx* c) {
     if (c->bin_count) (void)hipFree(c->bin_count);
     if (c->bin_ids) (void)hipFree(c->bin_ids);
-    if (c->bin_tot) (void)hipFree(c->bin_tot);
-    c->bin_count = c->bin_ids = nullptr;
-    c->bin_tot = nullptr;
-    c->bin_cap = c->bin_ids_cap = c->bin_tot_cap = 0;
+    if (c->bin_occ) (void)hipFree(c->bin_occ);
+    if (c->bin_tmp) (void)hipFree(c->bin_tmp);
+    c->bin_count = nullptr;
+    c->bin_ids = nullptr;
+    c->bin_occ = nullptr;
+    c->bin_tmp = nullptr;
+    c->bin_cap = c->bin_ids_cap = c->bin_occ_cap = c->bin_tmp_cap = 0;
 }
 
 }  // namespace ibm
