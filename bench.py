@@ -73,7 +73,7 @@ def workload(name):
 def kernel_source_hash():
     """Hash of the sources of every kernel with a committed counter summary."""
     h = hashlib.sha256()
-    for f in ("poisson.hip", "cnn.hip", "common.h", "momentum.hip", "shepard.hip"):
+    for f in ("poisson.hip", "cnn.hip", "common.h", "momentum.hip", "shepard.hip", "step.hip", "bcm.hip"):
         with open(os.path.join(ROOT, "paper_2002_06206_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
