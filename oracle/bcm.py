@@ -87,8 +87,24 @@ class Cubes:
         return q, lvl, cell
 
     def exchange(self, data):
-        """Fills the face halos of every cube (returns a new array)."""
+        """Fills the face halos of every cube (returns a new array).  The sources of every
+        halo cell are resolved once from the definition below (halo_sources) and kept;
+        a mean adds its 8 values in their listed order."""
+        if not hasattr(self, "_plan"):
+            self._plan = self.halo_sources()
+        dst1, src1, dst8, src8 = self._plan
         out = data.copy()
+        out[dst1] = data[src1]
+        acc = np.zeros(len(dst8))
+        for e in range(8):
+            acc = acc + data[src8[:, e]]
+        out[dst8] = acc / 8.0
+        return out
+
+    def halo_sources(self):
+        """Per face-halo cell, its storage index and the indices it takes its value from:
+        (dst of copies, their source, dst of means, their 8 sources in z, y, x order)."""
+        dst1, src1, dst8, src8 = [], [], [], []
         n = self.n
         for q, (lvl, o) in enumerate(self.cubes):
             w = 1 if lvl == 1 else 2                     # this cube's cell size in fine units
@@ -104,47 +120,81 @@ class Cubes:
                                 c[(axis + 2) % 3] = b
                                 centre = o + (np.array(c) + 0.5) * w     # fine-cell units
                                 hit = self.locate(centre)
+                                dst = self.index(q, *c)
                                 if hit is None:
                                     m = list(c)
                                     m[axis] = n - layer if sgn > 0 else layer - 1
-                                    v = data[self.index(q, *m)]
+                                    dst1.append(dst)
+                                    src1.append(self.index(q, *m))
                                 else:
                                     qq, l2, cell = hit
                                     if l2 <= lvl or lvl == 1:
-                                        v = data[self.index(qq, *cell)]
+                                        dst1.append(dst)
+                                        src1.append(self.index(qq, *cell))
                                     else:
-                                        # coarse halo cell over fine cells: mean of the 8,
-                                        # summed in z, y, x order
-                                        s = 0.0
+                                        # coarse halo cell over fine cells: the 8 inside it,
+                                        # in z, y, x order
                                         lo = o + np.array(c) * 2
+                                        srcs = []
                                         for dz in range(2):
                                             for dy in range(2):
                                                 for dxx in range(2):
                                                     pp = lo + np.array([dxx, dy, dz]) + 0.5
                                                     q3, _, c3 = self.locate(pp)
-                                                    s += data[self.index(q3, *c3)]
-                                        v = s / 8.0
-                                out[self.index(q, *c)] = v
-        return out
+                                                    srcs.append(self.index(q3, *c3))
+                                        dst8.append(dst)
+                                        src8.append(srcs)
+        return (np.array(dst1, dtype=np.int64), np.array(src1, dtype=np.int64), np.array(dst8, dtype=np.int64),
+                np.array(src8, dtype=np.int64).reshape(-1, 8))
 
     def laplacian(self, data):
         """(L x) on every cube interior (halos of the result are zero)."""
         out = np.zeros_like(data)
-        n = self.n
+        n, sd = self.n, self.side
         for q, (lvl, o) in enumerate(self.cubes):
             dx = self.dx(lvl)
-            for k in range(n):
-                for j in range(n):
-                    for i in range(n):
-                        xc = data[self.index(q, i, j, k)]
-                        s = data[self.index(q, i - 1, j, k)]
-                        s = s + data[self.index(q, i + 1, j, k)]
-                        s = s + data[self.index(q, i, j - 1, k)]
-                        s = s + data[self.index(q, i, j + 1, k)]
-                        s = s + data[self.index(q, i, j, k - 1)]
-                        s = s + data[self.index(q, i, j, k + 1)]
-                        out[self.index(q, i, j, k)] = (s - 6.0 * xc) / (dx * dx)
+            blk = data[q * sd ** 3:(q + 1) * sd ** 3].reshape(sd, sd, sd)
+            ob = out[q * sd ** 3:(q + 1) * sd ** 3].reshape(sd, sd, sd)
+            c = slice(H, H + n)
+            m, p = slice(H - 1, H + n - 1), slice(H + 1, H + n + 1)
+            s = blk[c, c, m]
+            s = s + blk[c, c, p]
+            s = s + blk[c, m, c]
+            s = s + blk[c, p, c]
+            s = s + blk[m, c, c]
+            s = s + blk[p, c, c]
+            ob[c, c, c] = (s - 6.0 * blk[c, c, c]) / (dx * dx)
         return out
+
+    def rbsor(self, b, x0, omega, sweeps):
+        """Red-black SOR on the cubes (Sec. 2.1's alternative solver on the Sec. 2.2 grid):
+        each half sweep exchanges the halos, then updates every interior cell of one
+        colour (parity of its cube-local i + j + k; cube origins are multiples of n, so
+        this is the parity within its level) in every cube by
+        x_c += omega (b_c - (L x)_c) / (-6 / dx^2), reading only cells of the other colour
+        and the halo copies.  Returns x after `sweeps` sweeps (halos as last exchanged)."""
+        x = x0.copy()
+        for _ in range(sweeps):
+            for c in (0, 1):
+                x = self.half_sweep(b, x, omega, c)
+        return x
+
+    def half_sweep(self, b, x, omega, colour):
+        """One half sweep: exchange, then the cells of one colour (see rbsor)."""
+        n = self.n
+        kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        mine = (ii + jj + kk) % 2 == colour
+        s = self.side
+        x = self.exchange(x)
+        L = self.laplacian(x)
+        for q, (lvl, _) in enumerate(self.cubes):
+            dx = self.dx(lvl)
+            diag = -6.0 / (dx * dx)
+            blk = x[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)
+            inner = blk[H:H + n, H:H + n, H:H + n]
+            r = self.interior(b, q) - self.interior(L, q)
+            inner[...] = np.where(mine, inner + omega * r / diag, inner)
+        return x
 
     def cell_centres(self, q):
         """Physical centres (n, n, n, 3) of cube q's interior cells, array order (k, j, i)."""

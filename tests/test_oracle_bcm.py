@@ -101,3 +101,26 @@ def test_linear_field_averages_and_copies():
     q0 = 0                                            # coarse cube at the corner (0, 0, 0)
     assert C.cubes[q0][0] == 0
     assert np.max(np.abs(C.interior(L, q0)[1:3, 1:3, 1:3])) < 1e-12   # clear of boundary and interface
+
+
+def test_rbsor_half_sweeps_and_convergence():
+    # at omega = 1 a half sweep zeroes the residual of its colour (against the halos it
+    # exchanged); on a consistent two-level system b = L u the iteration converges to u
+    # up to the constant of the Neumann problem
+    C = _two_level()
+    u = C.exchange(C.fill(lambda x, y, z: np.sin(0.7 * x) + 0.3 * np.cos(0.5 * y + 0.2 * z)))
+    b = C.laplacian(u)
+    x0 = np.zeros(C.size())
+    n = C.n
+    kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    for colour in (0, 1):
+        y = C.half_sweep(b, x0 + 0.1, 1.0, colour)
+        r = b - C.laplacian(y)
+        mine = (ii + jj + kk) % 2 == colour
+        worst = max(np.max(np.abs(C.interior(r, q)[mine])) for q in range(len(C.cubes)))
+        other = max(np.max(np.abs(C.interior(r, q)[~mine])) for q in range(len(C.cubes)))
+        assert worst < 1e-12 * np.max(np.abs(b)) and other > 1e-3
+    x = C.rbsor(b, x0, 1.6, 400)
+    d = np.concatenate([(C.interior(x, q) - C.interior(u, q)).ravel() for q in range(len(C.cubes))])
+    ref = np.concatenate([C.interior(u, q).ravel() for q in range(len(C.cubes))])
+    assert np.std(d) < 1e-6 * np.std(ref)
