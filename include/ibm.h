@@ -370,6 +370,13 @@ int ibm_bcm_exchange(const ibm_bcm* grid, double* data_dev, void* stream);
  * cube's own dx, neighbours read from its storage (exchange first); halos of y are not
  * written; x and y distinct. */
 int ibm_bcm_laplacian(const ibm_bcm* grid, const double* x_dev, double* y_dev, void* stream);
+/* Red-black SOR on the cubes (Sec. 2.1's alternative solver on this grid): `sweeps`
+ * sweeps, each two half sweeps of an exchange of x followed by the update of every
+ * interior cell of one colour (parity of its cube-local i + j + k) by
+ * x_c += omega (b_c - (L x)_c) / (-6 / dx^2).  b_dev (cube storage; interiors read) and
+ * x_dev (in/out) distinct; 0 < omega < 2.  Asynchronous on the stream. */
+int ibm_bcm_sor(const ibm_bcm* grid, const double* b_dev, double* x_dev, double omega, int32_t sweeps,
+                void* stream);
 
 /* Measurement support (not part of the method).  When enabled, launches of the
  * pressure solve are bracketed by HIP events on its stream and the elapsed times are

@@ -116,6 +116,35 @@ __global__ void __launch_bounds__(256) k_bcm_lap(long long ncubes, int n, int si
     }
 }
 
+// One half sweep of red-black SOR on the cubes: every interior cell of the colour
+// (parity of its cube-local i + j + k) gets x_c += omega (b_c - (L x)_c) / (-6 / dx^2);
+// it reads cells of the other colour and halo copies only (exchanged before the launch).
+__global__ void __launch_bounds__(256) k_bcm_sor(long long ncubes, int n, int side, double dx0,
+                                                 const uint8_t* __restrict__ level, const double* __restrict__ b,
+                                                 double* __restrict__ x, int colour, double omega) {
+    const long long per = (long long)n * n * n;
+    const long long total = ncubes * per;
+    const long long s2 = (long long)side * side, s3 = s2 * side;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+        const long long q = t / per;
+        const long long r = t - q * per;
+        const int i = (int)(r % n), j = (int)((r / n) % n), k = (int)(r / ((long long)n * n));
+        if (((i + j + k) & 1) != colour) continue;
+        const long long c = q * s3 + (i + BCM_H) + side * ((j + BCM_H) + (long long)side * (k + BCM_H));
+        const double dx = level[q] ? 0.5 * dx0 : dx0;
+        double s = x[c - 1];
+        s = s + x[c + 1];
+        s = s + x[c - side];
+        s = s + x[c + side];
+        s = s + x[c - s2];
+        s = s + x[c + s2];
+        const double xc = x[c];
+        const double lx = (s - 6.0 * xc) / (dx * dx);
+        const double diag = -6.0 / (dx * dx);
+        x[c] = xc + omega * (b[c] - lx) / diag;
+    }
+}
+
 }  // namespace
 }  // namespace ibm
 
@@ -336,6 +365,23 @@ int ibm_bcm_laplacian(const ibm_bcm* m, const double* x_dev, double* y_dev, void
     if (nb > 0)
         k_bcm_lap<<<(int)nb, 256, 0, (hipStream_t)stream>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level, x_dev,
                                                              y_dev);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int ibm_bcm_sor(const ibm_bcm* m, const double* b_dev, double* x_dev, double omega, int32_t sweeps, void* stream) {
+    if (!m || !b_dev || !x_dev || b_dev == x_dev || sweeps < 0 || !(omega > 0.0 && omega < 2.0)) {
+        set_error("ibm_bcm_sor: need distinct b and x, sweeps >= 0, 0 < omega < 2");
+        return IBM_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const long long total = m->ncubes * (long long)m->n * m->n * m->n;
+    const int nb = (int)std::min<long long>((total + 255) / 256, 16384);
+    for (int it = 0; it < sweeps; ++it)
+        for (int colour = 0; colour < 2; ++colour) {
+            if (int rc = ibm_bcm_exchange(m, x_dev, stream)) return rc;
+            k_bcm_sor<<<nb, 256, 0, s>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level, b_dev, x_dev, colour, omega);
+        }
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }

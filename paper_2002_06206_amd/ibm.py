@@ -114,6 +114,7 @@ def _load():
                           ctypes.POINTER(ctypes.c_int64), vp, vp], ctypes.c_int),
         "ibm_bcm_exchange": ([vp, vp, vp], ctypes.c_int),
         "ibm_bcm_laplacian": ([vp, vp, vp, vp], ctypes.c_int),
+        "ibm_bcm_sor": ([vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -130,7 +131,7 @@ EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
             "ibm_ctx_set_preconditioner", "ibm_bcm_create", "ibm_bcm_destroy", "ibm_bcm_info", "ibm_bcm_exchange",
-            "ibm_bcm_laplacian")
+            "ibm_bcm_laplacian", "ibm_bcm_sor")
 CNN_NWEIGHTS = 7776
 
 
@@ -503,6 +504,10 @@ class BCM:
 
     def laplacian(self, x, y):
         return _check(_lib.ibm_bcm_laplacian(self.grid, _ptr(x), _ptr(y), _stream()), "ibm_bcm_laplacian")
+
+    def sor(self, b, x, omega, sweeps):
+        return _check(_lib.ibm_bcm_sor(self.grid, _ptr(b), _ptr(x), float(omega), int(sweeps), _stream()),
+                      "ibm_bcm_sor")
 
     def close(self):
         if self.grid:

@@ -1,7 +1,8 @@
 """GPU parity of the building-cube grid (Sec. 2.2) against oracle/bcm.py through the C
 ABI: cube order and levels equal to the oracle's, the halo exchange (copies, means of
 8 fine cells, mirrors) and the 7-point operator on the cubes bit for bit, on a one-level
-grid against the uniform operator, and on two levels with several refined cubes."""
+grid against the uniform operator, and on two levels with several refined cubes; red-black
+SOR sweeps on the cubes bit for bit."""
 import numpy as np
 import pytest
 
@@ -42,6 +43,26 @@ def test_exchange_and_operator_bit_exact(K, n, cells):
     L = C.laplacian(ref)
     for q in range(len(C.cubes)):
         assert np.array_equal(C.interior(y.cpu().numpy(), q), C.interior(L, q))
+    G.close()
+
+
+@pytest.mark.parametrize("K,n,cells", [((3, 2, 2), 4, ((0, 0, 1), (1, 1, 2))), ((2, 2, 1), 8, ((0, 1, 1),))])
+def test_sor_sweeps_bit_exact(K, n, cells):
+    refine = np.zeros(K[::-1], bool)
+    for c in cells:
+        refine[c] = True
+    print("case bcm sor", K, n, cells, flush=True)
+    C = bcm.Cubes(K, n, 1.0, (0.0, 0.0, 0.0), refine)
+    G = ibm.BCM(K, n, 1.0, (0.0, 0.0, 0.0), refine)
+    rng = np.random.default_rng(6)
+    b = rng.standard_normal(C.size())
+    x0 = rng.standard_normal(C.size())
+    ref = C.rbsor(b, x0, 1.5, 3)
+    x = torch.from_numpy(x0.copy()).cuda()
+    G.sor(torch.from_numpy(b).cuda(), x, 1.5, 3)
+    got = x.cpu().numpy()
+    for q in range(len(C.cubes)):
+        assert np.array_equal(C.interior(got, q), C.interior(ref, q))
     G.close()
 
 
