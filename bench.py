@@ -397,7 +397,8 @@ def bcm_timing(case, blocked, args, ibm, torch, reps=20):
     """The building-cube grid (Sec. 2.2) over the workload's domain: coarse cubes of 16^3
     cells of twice the workload's cell size, refined (8 cubes of 16^3 cells at the
     workload's cell size) wherever the geometry cuts a grid line inside them; the halo
-    exchange and the 7-point operator timed with events on the stream they run on."""
+    exchange, the 7-point operator and red-black SOR sweeps (two exchanges and two half
+    sweeps each) timed with events on the stream they run on."""
     n = 16
     N = case.n
     if any(v % (2 * n) for v in N):
@@ -420,9 +421,13 @@ def bcm_timing(case, blocked, args, ibm, torch, reps=20):
     for _ in range(reps):
         G.laplacian(x, y)
     ev[2].record()
+    ev.append(torch.cuda.Event(enable_timing=True))
+    G.sor(y, x, 1.8, reps)
+    ev[3].record()
     torch.cuda.synchronize()
     ex_us = ev[0].elapsed_time(ev[1]) / reps * 1e3
     lap_us = ev[1].elapsed_time(ev[2]) / reps * 1e3
+    sor_us = ev[2].elapsed_time(ev[3]) / reps * 1e3
     cells = G.ncubes * n ** 3
     fine = int(refine.sum())
     # algorithmic bytes: operator 16 B per cell (x read once, y written); exchange per
@@ -431,6 +436,7 @@ def bcm_timing(case, blocked, args, ibm, torch, reps=20):
     lap_bytes = 16 * cells
     out = {"coarse_cubes": math.prod(K), "refined": fine, "cubes": int(G.ncubes), "cells": int(cells),
            "halo_cells": int(G.nhalo), "exchange_us": round(ex_us, 2), "laplacian_us": round(lap_us, 2),
+           "sor_sweep_us": round(sor_us, 2),
            "laplacian_bytes_per_cell": 16,
            "laplacian_achieved_gbs": round(lap_bytes / (lap_us * 1e-6) / 1e9, 1),
            "roofline": {"bound": "hbm", "achieved": round(lap_bytes / (lap_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
