@@ -109,9 +109,8 @@ typedef struct {
  *   (I - dt/2 L) (u* - u^n) = dt H^n for each component, solved by unpreconditioned
  *   BiCGStab from the explicit Euler increment until ||r|| <= mom_tol ||dt H^n||
  *   (on IBM_MIXED contexts, where the vectors are FP32, mom_tol is raised to at least
- *   1e-6).  Dead-end cells keep their mean wall velocity.  h_dev receives H^n.  The
- *   first CN step of a context allocates its solver workspace: 8 vectors of 3 cell
- *   fields of the context's cell type. */
+ *   1e-6).  Dead-end cells keep their mean wall velocity.  h_dev receives H^n.  Needs
+ *   ibm_prepare_crank_nicolson on the context first (IBM_ERR_ARG otherwise). */
 typedef struct {
     double dt;
     double dt_prev;         /* previous step's dt (<= 0: same as dt)                 */
@@ -219,6 +218,12 @@ int ibm_poisson_solve(ibm_ctx* ctx, const double* b_dev, double* x_dev, const ib
 /* y = L x (the operator above), for tests. */
 int ibm_apply_laplacian(ibm_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
 
+/* Allocates the Crank-Nicolson solver workspace of a context once (6 vectors of 3 cell
+ * fields of the context's cell type, partial sums, a device state and its pinned host
+ * mirror; freed by ibm_destroy), so that ibm_step and ibm_momentum_solve never allocate.
+ * Idempotent. */
+int ibm_prepare_crank_nicolson(ibm_ctx* ctx);
+
 /* Crank-Nicolson momentum operator (eq. (crank-nicolson)) for tests and callers with
  * their own time loop: out = (I - dt/2 L) q for the three components, L the part of the
  * momentum right-hand side linear in the velocity: flux-form central advection by the
@@ -236,7 +241,8 @@ int ibm_momentum_apply(ibm_ctx* ctx, const void* const q_dev[3], double* const U
  * components by unpreconditioned BiCGStab (Sec. 2.1): x_dev holds the initial guess on
  * entry and the solution on return; b_dev may equal x_dev.  Each component stops when
  * ||b - A x|| <= tol ||b|| at the start of an iteration or halfway through one; a zero b
- * gives x = 0.  iters_out (host, or NULL): iterations per component.  Returns
+ * gives x = 0.  iters_out (host, or NULL): iterations per component.  Needs
+ * ibm_prepare_crank_nicolson first.  Returns
  * IBM_NOT_CONVERGED at max_iter or on a breakdown (rho = 0, <r0, v> = 0, omega = 0),
  * IBM_ERR_NAN on a non-finite residual.  Synchronises the stream. */
 int ibm_momentum_solve(ibm_ctx* ctx, const void* const b_dev[3], void* const x_dev[3], double* const U_dev[3],

@@ -261,9 +261,9 @@ int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const 
     if (prm->scheme != IBM_SCHEME_AB2 && prm->scheme != IBM_SCHEME_CN) return bad("ibm_step: unknown scheme");
     hipStream_t s = (hipStream_t)stream;
     const bool cn = prm->scheme == IBM_SCHEME_CN;
-    if (cn) {
-        if (int rc = cn_prepare(c)) return rc;
-    }
+    if (cn && !c->cn_ws)
+        return bad("ibm_step: the Crank-Nicolson scheme needs ibm_prepare_crank_nicolson first (it allocates the "
+                   "solver workspace, so that ibm_step itself never allocates)");
     int rc = step_predict(c, u, U, h, wall, prm, s);
     if (rc) return rc;
     int mom_iters[3] = {0, 0, 0};
@@ -310,6 +310,12 @@ int ibm_apply_laplacian(ibm_ctx* c, const double* x, double* y, void* stream) {
     if (int rc = need_stencil(c)) return rc;
     if (!x || !y) return bad("ibm_apply_laplacian: null argument");
     return laplacian_run(c, x, y, (hipStream_t)stream);
+}
+
+int ibm_prepare_crank_nicolson(ibm_ctx* c) {
+    if (!c) return bad("null context");
+    if (int rc = check_device(c)) return rc;
+    return cn_prepare(c);
 }
 
 int ibm_momentum_apply(ibm_ctx* c, const void* const q[3], double* const U[3], const void* nut, double nu,

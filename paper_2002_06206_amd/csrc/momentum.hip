@@ -635,7 +635,10 @@ int cn_apply(ibm_ctx* c, const void* const* q, double* const* U, const void* nut
 
 int cn_solve(ibm_ctx* c, const void* const* b, void* const* x, double* const* U, const void* nut, double nu,
              double dt, double tol, int max_iter, int iters[3], hipStream_t s) {
-    if (int rc = cn_prepare(c)) return rc;
+    if (!c->cn_ws) {
+        set_error("Crank-Nicolson: call ibm_prepare_crank_nicolson first (it allocates the solver workspace)");
+        return IBM_ERR_ARG;
+    }
     if (c->precision == IBM_FP64) {
         const double* bp[3] = {(const double*)b[0], (const double*)b[1], (const double*)b[2]};
         double* xp[3] = {(double*)x[0], (double*)x[1], (double*)x[2]};

@@ -92,6 +92,7 @@ def _load():
         "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
         "ibm_timing_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
         "ibm_timing_slot": ([vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32], ctypes.c_int),
+        "ibm_prepare_crank_nicolson": ([vp], ctypes.c_int),
         "ibm_momentum_apply": ([vp, P3, P3, vp, ctypes.c_double, ctypes.c_double, P3, vp], ctypes.c_int),
         "ibm_momentum_solve": ([vp, P3, P3, P3, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp], ctypes.c_int),
@@ -127,7 +128,8 @@ _lib = _load()
 EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "ibm_build_stencils",
             "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
             "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_shepard_force", "ibm_timing_enable", "ibm_timing_read",
-            "ibm_timing_slot", "ibm_set_progress", "ibm_momentum_apply", "ibm_momentum_solve",
+            "ibm_timing_slot", "ibm_set_progress", "ibm_prepare_crank_nicolson", "ibm_momentum_apply",
+            "ibm_momentum_solve",
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
             "ibm_ctx_set_preconditioner", "ibm_bcm_create", "ibm_bcm_destroy", "ibm_bcm_info", "ibm_bcm_exchange",
@@ -239,6 +241,10 @@ def ibm_shepard_force(ctx, tri, p, side=None, thin_filter=False):
     _check(_lib.ibm_shepard_force(ctx, _ptr(tri), ntri, _ptr(p), int(bool(thin_filter)), _ptr(side), out, _stream()),
            "ibm_shepard_force")
     return list(out)
+
+
+def ibm_prepare_crank_nicolson(ctx):
+    return _check(_lib.ibm_prepare_crank_nicolson(ctx), "ibm_prepare_crank_nicolson")
 
 
 def ibm_momentum_apply(ctx, q, U, nut, nu, dt, out):
@@ -407,7 +413,15 @@ class Solver:
         return st
 
     def step(self, st, params, wall=None, want_stats=True):
+        if params.scheme == SCHEME_CN:
+            self.prepare_crank_nicolson()
         return ibm_step(self.ctx, st["u"], st["U"], st["p"], st["h"], params, wall, want_stats)
+
+    def prepare_crank_nicolson(self):
+        """Allocates the Crank-Nicolson workspace once (set-up, outside the time step)."""
+        if not getattr(self, "_cn_ready", False):
+            ibm_prepare_crank_nicolson(self.ctx)
+            self._cn_ready = True
 
     def poisson(self, b, x, **opts):
         return ibm_poisson_solve(self.ctx, b, x, solver_opts(**opts))
@@ -434,6 +448,7 @@ class Solver:
         return ibm_momentum_apply(self.ctx, q, U, nut, nu, dt, out)
 
     def momentum_solve(self, b, x, U, nut, nu, dt, tol=1e-10, max_iter=200):
+        self.prepare_crank_nicolson()
         return ibm_momentum_solve(self.ctx, b, x, U, nut, nu, dt, tol, max_iter)
 
     def shepard_force(self, tri, p, side=None, thin_filter=False):

@@ -238,3 +238,19 @@ def test_cn_step_mixed_precision_error_stated():
     print("mixed CN: rel L2 u %.2e" % eu, flush=True)
     assert eu < 1e-6
     s.close()
+
+
+def test_cn_step_needs_its_workspace_prepared():
+    # ibm_step never allocates: without ibm_prepare_crank_nicolson the CN scheme is refused
+    case = inputs.case_sphere32()
+    g = flow.Grid(case.n, case.dx, case.origin, case.bc, case.u_in)
+    ob, ot = tagging.tag(case.tri, g.n, g.dx, g.origin)
+    s, _ = _build(g, ob, ot)
+    gs = s.new_state(g.u_in)
+    prm = ibm.step_params(case.dt, case.nu, tol=1e-8, max_iter=20000, scheme="cn")
+    with pytest.raises(ibm.IBMError):
+        ibm.ibm_step(s.ctx, gs["u"], gs["U"], gs["p"], gs["h"], prm)
+    s.prepare_crank_nicolson()
+    rc, _ = ibm.ibm_step(s.ctx, gs["u"], gs["U"], gs["p"], gs["h"], prm)
+    assert rc == 0
+    s.close()
