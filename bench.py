@@ -517,7 +517,8 @@ def train_network(args, ibm, torch):
     from paper_2002_06206_amd import inputs, train
     t0 = time.perf_counter()
     # 20 windows x 100 steps, every step from the third on: 1,960 (b, p) pairs
-    data = train.build_dataset(train.TRAIN_SEEDS[:args.train_windows], 64, steps=100, every=1,
+    seeds = tuple(range(train.TRAIN_SEEDS[0], train.TRAIN_SEEDS[0] + args.train_windows))   # disjoint from EVAL_SEEDS
+    data = train.build_dataset(seeds, 64, steps=100, every=1,
                                depths=tuple(int(k) for k in args.train_depths.split(",")))
     held = train.build_dataset(train.EVAL_SEEDS, 64, steps=24, every=3)
     t1 = time.perf_counter()
