@@ -41,18 +41,19 @@ def _build(g, tri):
     return s, st
 
 
-def _walled():
+def _walled(nx=20):
     rng = np.random.default_rng(0)
-    g = flow.Grid((20, 16, 12), 1.0, (0.0, 0.0, 0.0), (1, 2, 3, 3, 0, 0))
+    g = flow.Grid((nx, 16, 12), 1.0, (0.0, 0.0, 0.0), (1, 2, 3, 3, 0, 0))
     tri = np.concatenate([inputs.icosphere(2, 3.2, (8.3, 8.1, 6.1), inputs.random_rotation(rng)),
                           inputs.rectangle((14.2, 7.1, 6.0), (0, 8.0, 0), (0, 0, 7.0))])
     return g, tri, rng
 
 
-@pytest.mark.parametrize("omega", [1.0, 1.75])
-def test_solve_matches_oracle(omega):
-    g, tri, rng = _walled()
-    print("case rbsor walled omega", omega, flush=True)
+@pytest.mark.parametrize("omega,nx", [(1.0, 20), (1.75, 20), (1.75, 21)])
+def test_solve_matches_oracle(omega, nx):
+    # even nx: one x-pair of cells per lane; odd nx: one cell per lane
+    g, tri, rng = _walled(nx)
+    print("case rbsor walled omega", omega, "nx", nx, flush=True)
     s, st = _build(g, tri)
     b = flow.remove_component_means(st, rng.standard_normal(g.shape))
     x0 = rng.standard_normal(g.shape) * 0.1
