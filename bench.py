@@ -9,8 +9,8 @@ velocity and right-hand side, pressure solve to relative residual 1e-6,
 projection, FP64 divergence check and surface force.  Tagging and the stencil
 build happen once per geometry before the timed region (reported as setup).
 
-Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: this build
-runs on one GPU.
+Prints ONE JSON line.  `python bench.py --gpus N` with N > 1 exits: the library and
+this benchmark run on one GPU.
 """
 from __future__ import annotations
 
@@ -572,7 +572,8 @@ def main():
     ap.add_argument("--sor-omega", type=float, default=0.0, help="SOR relaxation (0: 2/(1+sin(pi/n)))")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (collectives and sharding are not part of it); "
+        print("bench.py: the library and this benchmark run on one GPU only (collectives and sharding are "
+              "not part of them); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

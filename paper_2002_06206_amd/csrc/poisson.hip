@@ -904,7 +904,7 @@ __global__ void __launch_bounds__(NT) k_pcg_b_f4(Geo g, const uint8_t* __restric
 
 // One block: totals after a residual replacement (an init sweep with parity it) ->
 // solver state of the next FP32 segment, which stops once its recursive <r,r> falls
-// below max(delta^2 <r,r>, (eta_tol)^2 <b,b>).  The host judges the FP64 residual.
+// below max(delta^2 <r,r>, (eta_tol)^2 <b,b>).  The host checks the FP64 residual.
 __global__ void __launch_bounds__(NT) k_seg_start(const double* partials, int nparts, Solver* sv, int it,
                                                   double delta, double eta_tol) {
     __shared__ double sh[4 * NT];
@@ -1195,7 +1195,7 @@ __global__ void __launch_bounds__(NT) k_fcg_dir(long long n, const float* __rest
     if (!(zr > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             if (zr == zr) {
-                sv->converged = 1;   // no descent: end the segment, the FP64 judge decides
+                sv->converged = 1;   // no descent: end the segment, the FP64 check decides
             } else {
                 sv->nan_seen = 1;
                 sv->converged = 3;
@@ -1369,7 +1369,7 @@ static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_ev
 }
 
 // FP64 iterative refinement with residual replacement around FP32 segments.  The FP64
-// residual r64 = b - L x (the judge) is rounded to FP32 and a segment works on
+// residual r64 = b - L x (the convergence check) is rounded to FP32 and a segment works on
 // A e = -r64 until its recursive residual has fallen by inner_tol (or below
 // eta tol ||b||); then x += e in FP64, e = 0, and r64 is recomputed and replaces the
 // FP32 residual.  Stops when ||r64|| <= tol ||b||.  A segment that shrinks ||r64|| by

@@ -8,7 +8,7 @@
   GPU's own input state: eddy viscosity, Poisson right-hand side, H, and the
   projected u and U from the GPU's pressure (relative L2 1e-10); the pressure itself
   by the FP64 residual of the oracle's operator (<= tol).
-* Mixed and learned solves at that size: the FP64 judge residual recomputed by the
+* Mixed and learned solves at that size: the FP64 residual recomputed by the
   oracle's operator, and the discrete divergence identity div U^{n+1} =
   dt (b - L p) cell by cell (a property at any size).
 * Crank-Nicolson at that size: H^n against the oracle, the momentum system's residual
@@ -213,7 +213,7 @@ def test_benchmark_workload_quick_rhs_and_sor_solve():
 
 
 @pytest.mark.parametrize("kind", ["mixed", "learned"])
-def test_benchmark_workload_judge_and_divergence_identity(kind):
+def test_benchmark_workload_fp64_residual_and_divergence_identity(kind):
     """Mixed (FP32 fields, FP32 CG in FP64 refinement) and learned (FCG with the network,
     untrained weights: the properties hold for any weights) at 256^3."""
     case, g, ob, ot, st = _oracle("ellipsoids256")
@@ -225,7 +225,7 @@ def test_benchmark_workload_judge_and_divergence_identity(kind):
     solver = ibm.SOLVER_FCG_CNN if kind == "learned" else ibm.SOLVER_FCG_JACOBI
     gs = s.new_state(case.u_in)
     ctl = {"umax": 1.0, "dt_prev": 0.0, "step": 0, "dt": case.dt}
-    print("case full-size judge", kind, flush=True)
+    print("case full-size fp64 residual", kind, flush=True)
     stats = _cfl_steps(s, gs, case, 3, solver, 1e-6, ctl)
     dt = ctl["dt"]
     b = s.rhs().cpu().numpy()
@@ -276,7 +276,7 @@ def test_vehicle1024_subboxes_and_mixed_step_properties():
     around the body are tagged and built by the oracle and compared with the GPU's
     full-grid result away from the sub-box faces (blocked bits: 1-cell rim excluded;
     flags without the enclosed bit: 2-cell rim, the reach of the dead-end filter and
-    the class layer).  After one step at tolerance 1e-6 the FP64 judge is checked and
+    the class layer).  After one step at tolerance 1e-6 the FP64 residual is checked and
     the divergence identity div U = dt (b - L p) is checked in the same sub-boxes with
     the oracle's operator.  The step solves to 1e-4 from rest (the identity holds for
     any pressure; the full 1e-6 first step takes ~18k FP32 iterations, ~3 min)."""

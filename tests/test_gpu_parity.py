@@ -311,7 +311,7 @@ def _manufactured(seed=7, n=(32, 24, 20), bc=(1, 2, 3, 3, 0, 0)):
 
 @pytest.mark.parametrize("tol", [1e-6, 1e-12])
 def test_mixed_refinement_reaches_fp64_accuracy(tol):
-    """FP32 CG corrections inside FP64 iterative refinement: the FP64 residual judge
+    """FP32 CG corrections inside FP64 iterative refinement: the FP64 residual check
     drives the solution below what FP32 alone can represent."""
     g, s, st, p_true, b = _manufactured()
     print("case mixed refinement tol", tol, flush=True)
