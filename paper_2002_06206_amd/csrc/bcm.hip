@@ -31,10 +31,10 @@ struct ibm_bcm {
     long long ncubes;
     long long size;                // values of the cube storage
     long long nhalo;
-    int* d_dst;                    // storage index of each halo cell
-    int* d_off;                    // nhalo + 1 offsets into d_src
-    int* d_src;                    // source storage indices
-    uint8_t* d_level;              // per cube
+    int* d_dst = nullptr;          // storage index of each halo cell
+    int* d_off = nullptr;          // nhalo + 1 offsets into d_src
+    int* d_src = nullptr;          // source storage indices
+    uint8_t* d_level = nullptr;    // per cube
 };
 
 namespace ibm {
@@ -168,7 +168,12 @@ int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origi
         set_error("ibm_bcm_create: host allocation failed");
         return IBM_ERR_OOM;
     }
-    IBM_HIP(hipGetDevice(&m->device));
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete m;
+        set_error("ibm_bcm_create: no current HIP device");
+        return IBM_ERR_HIP;
+    }
     for (int a = 0; a < 3; ++a) {
         m->K[a] = K[a];
         m->origin[a] = origin[a];
@@ -309,10 +314,15 @@ int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origi
         delete m;
         return IBM_ERR_OOM;
     }
-    IBM_HIP(hipMemcpy(m->d_dst, dst.data(), sizeof(int) * dst.size(), hipMemcpyHostToDevice));
-    IBM_HIP(hipMemcpy(m->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
-    IBM_HIP(hipMemcpy(m->d_src, src.data(), sizeof(int) * src.size(), hipMemcpyHostToDevice));
-    IBM_HIP(hipMemcpy(m->d_level, lv.data(), lv.size(), hipMemcpyHostToDevice));
+    if (hipMemcpy(m->d_dst, dst.data(), sizeof(int) * dst.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->d_src, src.data(), sizeof(int) * src.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->d_level, lv.data(), lv.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("ibm_bcm_create: copy of the halo tables failed");
+        ibm_bcm_destroy(m);
+        return IBM_ERR_HIP;
+    }
     *out = m;
     return IBM_OK;
 }
@@ -343,11 +353,23 @@ int ibm_bcm_info(const ibm_bcm* m, int64_t* ncubes, int64_t* size, int64_t* nhal
     return IBM_OK;
 }
 
+// the grid's tables live on the device it was created on
+static int bcm_device_ok(const ibm_bcm* m) {
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess || d != m->device) {
+        (void)hipGetLastError();
+        set_error("building-cube grid used on another device than the one it was created on");
+        return IBM_ERR_ARG;
+    }
+    return IBM_OK;
+}
+
 int ibm_bcm_exchange(const ibm_bcm* m, double* data_dev, void* stream) {
     if (!m || !data_dev) {
         set_error("ibm_bcm_exchange: null argument");
         return IBM_ERR_ARG;
     }
+    if (int rc = bcm_device_ok(m)) return rc;
     const long long nb = std::min<long long>((m->nhalo + 255) / 256, 8192);
     if (nb > 0)
         k_bcm_exchange<<<(int)nb, 256, 0, (hipStream_t)stream>>>(m->nhalo, m->d_dst, m->d_off, m->d_src, data_dev);
@@ -360,6 +382,7 @@ int ibm_bcm_laplacian(const ibm_bcm* m, const double* x_dev, double* y_dev, void
         set_error("ibm_bcm_laplacian: null or aliased argument");
         return IBM_ERR_ARG;
     }
+    if (int rc = bcm_device_ok(m)) return rc;
     const long long total = m->ncubes * (long long)m->n * m->n * m->n;
     const long long nb = std::min<long long>((total + 255) / 256, 16384);
     if (nb > 0)
@@ -374,6 +397,7 @@ int ibm_bcm_sor(const ibm_bcm* m, const double* b_dev, double* x_dev, double ome
         set_error("ibm_bcm_sor: need distinct b and x, sweeps >= 0, 0 < omega < 2");
         return IBM_ERR_ARG;
     }
+    if (int rc = bcm_device_ok(m)) return rc;
     hipStream_t s = (hipStream_t)stream;
     const long long total = m->ncubes * (long long)m->n * m->n * m->n;
     const int nb = (int)std::min<long long>((total + 255) / 256, 16384);

@@ -600,16 +600,16 @@ int cn_prepare(ibm_ctx* c) {
     if (c->cn_ws) return IBM_OK;
     const size_t ts = c->precision == IBM_FP64 ? sizeof(double) : sizeof(float);
     const size_t bytes = ts * 18 * (size_t)c->N;
-    hipError_t e = hipMalloc(&c->cn_ws, bytes);
-    if (e != hipSuccess) {
+    // all or nothing: a partly allocated workspace would pass the readiness check
+    if (hipMalloc(&c->cn_ws, bytes) != hipSuccess ||
+        hipMalloc((void**)&c->cn_part, sizeof(double) * CS_SLOTS * MAX_BLOCKS) != hipSuccess ||
+        hipMalloc((void**)&c->cn_state, sizeof(CnState)) != hipSuccess ||
+        hipHostMalloc((void**)&c->h_cn_state, sizeof(CnState), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
-        c->cn_ws = nullptr;
-        set_error("Crank-Nicolson workspace: out of device memory");
+        cn_release(c);
+        set_error("Crank-Nicolson workspace: out of memory");
         return IBM_ERR_OOM;
     }
-    IBM_HIP(hipMalloc((void**)&c->cn_part, sizeof(double) * CS_SLOTS * MAX_BLOCKS));
-    IBM_HIP(hipMalloc((void**)&c->cn_state, sizeof(CnState)));
-    IBM_HIP(hipHostMalloc((void**)&c->h_cn_state, sizeof(CnState), hipHostMallocDefault));
     c->cn_last_iters = 0;
     return IBM_OK;
 }
