@@ -86,13 +86,16 @@ class Cubes:
             cell = ((p - o) // 2).astype(int)
         return q, lvl, cell
 
-    def exchange(self, data):
-        """Fills the face halos of every cube (returns a new array).  The sources of every
-        halo cell are resolved once from the definition below (halo_sources) and kept;
-        a mean adds its 8 values in their listed order."""
-        if not hasattr(self, "_plan"):
-            self._plan = self.halo_sources()
-        dst1, src1, dst8, src8 = self._plan
+    def exchange(self, data, cubes=None):
+        """Fills the face halos of every cube, or of the listed cubes only (returns a new
+        array).  The sources of every halo cell are resolved once from the definition
+        below (halo_sources) and kept; a mean adds its 8 values in their listed order."""
+        key = None if cubes is None else tuple(sorted(int(q) for q in cubes))
+        if not hasattr(self, "_plans"):
+            self._plans = {}
+        if key not in self._plans:
+            self._plans[key] = self.halo_sources(key)
+        dst1, src1, dst8, src8 = self._plans[key]
         out = data.copy()
         out[dst1] = data[src1]
         acc = np.zeros(len(dst8))
@@ -101,12 +104,14 @@ class Cubes:
         out[dst8] = acc / 8.0
         return out
 
-    def halo_sources(self):
-        """Per face-halo cell, its storage index and the indices it takes its value from:
-        (dst of copies, their source, dst of means, their 8 sources in z, y, x order)."""
+    def halo_sources(self, cubes=None):
+        """Per face-halo cell (of every cube, or of the listed cubes), its storage index and
+        the indices it takes its value from: (dst of copies, their source, dst of means,
+        their 8 sources in z, y, x order)."""
         dst1, src1, dst8, src8 = [], [], [], []
         n = self.n
-        for q, (lvl, o) in enumerate(self.cubes):
+        for q in (range(len(self.cubes)) if cubes is None else cubes):
+            lvl, o = self.cubes[q]
             w = 1 if lvl == 1 else 2                     # this cube's cell size in fine units
             for axis in range(3):
                 for sgn in (-1, 1):
@@ -147,11 +152,13 @@ class Cubes:
         return (np.array(dst1, dtype=np.int64), np.array(src1, dtype=np.int64), np.array(dst8, dtype=np.int64),
                 np.array(src8, dtype=np.int64).reshape(-1, 8))
 
-    def laplacian(self, data):
-        """(L x) on every cube interior (halos of the result are zero)."""
+    def laplacian(self, data, cubes=None):
+        """(L x) on every cube interior, or on the listed cubes' (halos of the result and
+        cubes not listed are zero)."""
         out = np.zeros_like(data)
         n, sd = self.n, self.side
-        for q, (lvl, o) in enumerate(self.cubes):
+        for q in (range(len(self.cubes)) if cubes is None else cubes):
+            lvl, o = self.cubes[q]
             dx = self.dx(lvl)
             blk = data[q * sd ** 3:(q + 1) * sd ** 3].reshape(sd, sd, sd)
             ob = out[q * sd ** 3:(q + 1) * sd ** 3].reshape(sd, sd, sd)
@@ -179,15 +186,19 @@ class Cubes:
                 x = self.half_sweep(b, x, omega, c)
         return x
 
-    def half_sweep(self, b, x, omega, colour):
-        """One half sweep: exchange, then the cells of one colour (see rbsor)."""
+    def half_sweep(self, b, x, omega, colour, cubes=None):
+        """One half sweep: exchange, then the cells of one colour (see rbsor).  With a
+        list of cubes, only their halos and interiors are updated; that equals the full
+        half sweep on them when every cube their halos read from holds its full-sweep
+        values."""
         n = self.n
         kk, jj, ii = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
         mine = (ii + jj + kk) % 2 == colour
         s = self.side
-        x = self.exchange(x)
-        L = self.laplacian(x)
-        for q, (lvl, _) in enumerate(self.cubes):
+        x = self.exchange(x, cubes)
+        L = self.laplacian(x, cubes)
+        for q in (range(len(self.cubes)) if cubes is None else cubes):
+            lvl = self.cubes[q][0]
             dx = self.dx(lvl)
             diag = -6.0 / (dx * dx)
             blk = x[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)

@@ -15,6 +15,8 @@
   by the oracle's operator (<= tol), the operator itself (relative L2 1e-13).
 * The hybrid QUICK face value at that size (H against the oracle) and red-black SOR on
   the step's right-hand side (residual by the oracle's operator <= tol).
+* The building-cube grid over the benchmark domain: cube order and levels in full; the
+  halo exchange, the operator and one SOR sweep on sampled cubes, bit-exact.
 * The precision configuration (256^3 plate): relative L2 error of u, p and drag of the
   mixed path against the plain FP64 path after the same steps, stated.
 """
@@ -210,6 +212,77 @@ def test_benchmark_workload_quick_rhs_and_sor_solve():
     assert e_h < 1e-10
     assert res <= 1e-6 * 1.0001
     s.close()
+
+
+def test_benchmark_workload_building_cubes_sampled():
+    # the building-cube grid over the benchmark domain as bench.py builds it: coarse
+    # cubes of 16^3 cells at twice the cell size, refined where the geometry blocks a
+    # face inside them.  Cube order, levels and origins over the whole grid; on sampled
+    # cubes (coarse beside refined, fine beside coarse, on the domain boundary, random)
+    # the exchanged halos, the operator and one red-black SOR sweep, bit for bit.
+    from oracle import bcm
+    case, g, ob, ot, st = _oracle("ellipsoids256")
+    n = 16
+    N = case.n
+    K = tuple(v // (2 * n) for v in N)
+    b3 = (np.asarray(ob) != 0).reshape(N[2], N[1], N[0])
+    refine = b3.reshape(K[2], 2 * n, K[1], 2 * n, K[0], 2 * n).any(axis=(1, 3, 5))
+    print("case full-size building cubes ellipsoids256: %d refined of %d" % (refine.sum(), refine.size), flush=True)
+    C = bcm.Cubes(K, n, 2.0 * case.dx, case.origin, refine)
+    G = ibm.BCM(K, n, 2.0 * case.dx, case.origin, refine)
+    assert G.ncubes == len(C.cubes) and G.size == C.size()
+    assert np.array_equal(G.levels, [lv for lv, _ in C.cubes])
+    assert np.array_equal(G.origins, np.array([o for _, o in C.cubes]))
+    rng = np.random.default_rng(21)
+    x0 = rng.standard_normal(C.size())
+    b = rng.standard_normal(C.size())
+    omega = 1.8
+    xd = torch.from_numpy(x0.copy()).cuda()
+    G.exchange(xd)
+    y = torch.zeros_like(xd)
+    G.laplacian(xd, y)
+    ex, L = xd.cpu().numpy(), y.cpu().numpy()
+    del y
+    xs = torch.from_numpy(x0.copy()).cuda()
+    G.sor(torch.from_numpy(b.copy()).cuda(), xs, omega, 1)
+    sw = xs.cpu().numpy()
+    del xd, xs
+    G.close()
+    # face neighbours of every cube: the level of the cube across each face centre
+    mean, coarse_src, mirror = [], [], []
+    for q, (lv, o) in enumerate(C.cubes):
+        w = n * (2 if lv == 0 else 1)
+        levels = []
+        for a in range(3):
+            for sgn in (-1, 1):
+                p = o + 0.5 * w
+                p[a] = o[a] - 0.5 if sgn < 0 else o[a] + w + 0.5
+                hit = C.locate(p)
+                levels.append(None if hit is None else hit[1])
+        if lv == 0 and 1 in levels:
+            mean.append(q)
+        if lv == 1 and 0 in levels:
+            coarse_src.append(q)
+        if None in levels:
+            mirror.append(q)
+    assert mean and coarse_src and mirror
+    lvl = np.array([lv for lv, _ in C.cubes])
+    pick = lambda pool, k: list(rng.choice(pool, size=min(k, len(pool)), replace=False))  # noqa: E731
+    samples = sorted(set(pick(mean, 2) + pick(coarse_src, 2) + pick(mirror, 2) +
+                         pick(np.flatnonzero(lvl == 0), 2) + pick(np.flatnonzero(lvl == 1), 2)))
+    s3 = C.side ** 3
+    for q in samples:
+        q = int(q)
+        exo = C.exchange(x0, [q])
+        assert np.array_equal(ex[q * s3:(q + 1) * s3], exo[q * s3:(q + 1) * s3]), q
+        assert np.array_equal(C.interior(L, q), C.interior(C.laplacian(exo, [q]), q)), q
+        d1, s1, d8, s8 = C.halo_sources([q])
+        src = sorted(set((np.concatenate([s1, s8.ravel()]) // s3).tolist()) | {q})
+        x1 = C.half_sweep(b, x0, omega, 0, src)
+        x2 = C.half_sweep(b, x1, omega, 1, [q])
+        assert np.array_equal(C.interior(sw, q), C.interior(x2, q)), q
+    print("256^3 building cubes: %d cubes, %d sampled (levels %s) bit-exact" %
+          (len(C.cubes), len(samples), [int(lvl[q]) for q in samples]), flush=True)
 
 
 @pytest.mark.parametrize("kind", ["mixed", "learned"])

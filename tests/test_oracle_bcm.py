@@ -2,7 +2,8 @@
 cubes reproduces the uniform-grid operator bit for bit; on two levels a constant field
 stays constant across the halos with a zero operator, fine-to-coarse averages of a
 linear field are exact and coarse-to-fine copies take the covering coarse cell; only
-face halos are written."""
+face halos are written; the listed-cube forms (used to sample large grids) equal the
+full forms on the listed cubes."""
 import numpy as np
 
 from oracle import bcm
@@ -124,3 +125,34 @@ def test_rbsor_half_sweeps_and_convergence():
     d = np.concatenate([(C.interior(x, q) - C.interior(u, q)).ravel() for q in range(len(C.cubes))])
     ref = np.concatenate([C.interior(u, q).ravel() for q in range(len(C.cubes))])
     assert np.std(d) < 1e-6 * np.std(ref)
+
+
+def test_listed_cubes_equal_the_full_grid():
+    # the listed-cube forms of the exchange, the operator and a sweep (used to sample
+    # the large grid) give the full forms' values on the listed cubes: halos of a cube
+    # and of the cubes its halos read from are filled before its second half sweep
+    K, n = (3, 2, 2), 4
+    refine = np.zeros(K[::-1], bool)
+    refine[0, 1, 1] = refine[1, 0, 2] = True
+    C = bcm.Cubes(K, n, 0.9, (0.0, 0.0, 0.0), refine)
+    rng = np.random.default_rng(12)
+    x0 = rng.standard_normal(C.size())
+    b = rng.standard_normal(C.size())
+    full_ex = C.exchange(x0)
+    full_L = C.laplacian(full_ex)
+    full_sw = C.rbsor(b, x0, 1.4, 1)
+    s3 = C.side ** 3
+    for q in (0, 3, len(C.cubes) - 1):
+        ex = C.exchange(x0, [q])
+        assert np.array_equal(ex[q * s3:(q + 1) * s3], full_ex[q * s3:(q + 1) * s3])
+        assert np.array_equal(C.interior(C.laplacian(ex, [q]), q), C.interior(full_L, q))
+        d1, s1, d8, s8 = C.halo_sources([q])
+        src = sorted(set((np.concatenate([s1, s8.ravel()]) // s3).tolist()) | {q})
+        x1 = C.half_sweep(b, x0, 1.4, 0, src)
+        x2 = C.half_sweep(b, x1, 1.4, 1, [q])
+        assert np.array_equal(C.interior(x2, q), C.interior(full_sw, q))
+        # a cube of the list updates nothing outside its own storage
+        other = np.ones(C.size(), bool)
+        for r in src:
+            other[r * s3:(r + 1) * s3] = False
+        assert np.array_equal(x1[other], x0[other])
