@@ -221,7 +221,8 @@ int ibm_apply_laplacian(ibm_ctx* ctx, const double* x_dev, double* y_dev, void* 
 /* Allocates the Crank-Nicolson solver workspace of a context once (6 vectors of 3 cell
  * fields of the context's cell type, partial sums, a device state and its pinned host
  * mirror; freed by ibm_destroy), so that ibm_step and ibm_momentum_solve never allocate.
- * Idempotent. */
+ * Idempotent.  IBM_ERR_OOM when any part cannot be allocated; nothing is then kept, so
+ * the context stays without a workspace. */
 int ibm_prepare_crank_nicolson(ibm_ctx* ctx);
 
 /* Crank-Nicolson momentum operator (eq. (crank-nicolson)) for tests and callers with
@@ -356,7 +357,9 @@ int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net);
  * factor of two apart).  Cube order: coarse cubes in z, y, x order, a refined one
  * contributing its 8 fine cubes in z, y, x order.  Each cube is stored as (n + 4)^3
  * doubles (two halo layers per face, x fastest); cube q starts at q (n + 4)^3.
- * Allocates the halo tables on the current device (host memory is read once). */
+ * Allocates the halo tables on the current device (host memory is read once); the
+ * exchange, operator and SOR calls must run with that device current, else they return
+ * IBM_ERR_ARG.  A failed create leaves *out untouched and frees what it allocated. */
 typedef struct ibm_bcm ibm_bcm;
 int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origin[3], const uint8_t* refine_host,
                    ibm_bcm** out);
