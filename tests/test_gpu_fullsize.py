@@ -17,6 +17,8 @@
   the step's right-hand side (residual by the oracle's operator <= tol).
 * The building-cube grid over the benchmark domain: cube order and levels in full; the
   halo exchange, the operator and one SOR sweep on sampled cubes, bit-exact.
+* The learned preconditioner at that size through the solver's marching kernels, on
+  sampled cells against the oracle network evaluated on each cell's 11^3 window.
 * The precision configuration (256^3 plate): relative L2 error of u, p and drag of the
   mixed path against the plain FP64 path after the same steps, stated.
 """
@@ -283,6 +285,59 @@ def test_benchmark_workload_building_cubes_sampled():
         assert np.array_equal(C.interior(sw, q), C.interior(x2, q)), q
     print("256^3 building cubes: %d cubes, %d sampled (levels %s) bit-exact" %
           (len(C.cubes), len(samples), [int(lvl[q]) for q in samples]), flush=True)
+
+
+def test_benchmark_workload_learned_preconditioner_sampled():
+    # the learned preconditioner z = D^-1 r + s net(r / s) at 256^3 through the solver's
+    # marching kernels (the launch the benchmark times: slabs of 86 planes, 32 x 8 tiles),
+    # against the oracle on sampled cells: a cell's output depends on r and the geometry
+    # channel within 4 cells (four 3^3 layers), so the oracle evaluates the network on
+    # the 11^3 window around it (clipped at the domain faces, where both sides pad with
+    # zeros); s = RMS of r over the whole grid.  Samples: random cells, the slab
+    # boundaries, tile edges, domain faces and cut cells.  Bar: relative L2 2e-4 over the
+    # samples (measured 2.0e-5; the differences are BF16 activations rounded from FP32
+    # sums against FP64 sums, the small-grid comparison allows 2e-3).
+    from oracle import cnn
+    case, g, ob, ot, st = _oracle("ellipsoids256")
+    s, *_ = _gpu(case, ibm.MIXED)
+    w = inputs.cnn_init_weights(8, scale=3.0)
+    net = ibm.Network(int(np.prod(case.n)), w, inference_only=True)
+    nx, ny, nz = case.n
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    z = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+    print("case full-size learned preconditioner ellipsoids256", flush=True)
+    ibm.ibm_cnn_precondition(net.net, s.ctx, torch.from_numpy(r).cuda(), z)
+    zg = z.cpu().numpy().astype(np.float64)
+    net.close()
+    s.close()
+    r64 = r.astype(np.float64)
+    sc = cnn.rms(r64)
+    gch = cnn.geometry_channel(st)
+    jinv = cnn.jacobi_inverse(st)
+    ws = cnn.split_weights(np.asarray(w, dtype=np.float64))
+    pts = {(int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(150)}
+    for zz in (0, 1, 85, 86, 171, 172, nz - 1):
+        pts |= {(zz, int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(6)}
+    for xx in (0, 31, 32, nx - 1):
+        pts |= {(int(rng.integers(nz)), int(rng.integers(ny)), xx) for _ in range(6)}
+    for yy in (0, 7, 8, ny - 1):
+        pts |= {(int(rng.integers(nz)), yy, int(rng.integers(nx))) for _ in range(6)}
+    cut = np.argwhere(st.blocked != 0)
+    pts |= {tuple(int(v) for v in cut[i]) for i in rng.choice(len(cut), size=40, replace=False)}
+    R = 5
+    got, ref = [], []
+    for (k, j, i) in sorted(pts):
+        lo = [max(0, k - R), max(0, j - R), max(0, i - R)]
+        hi = [min(nz, k + R + 1), min(ny, j + R + 1), min(nx, i + R + 1)]
+        win = (slice(lo[0], hi[0]), slice(lo[1], hi[1]), slice(lo[2], hi[2]))
+        y, _ = cnn.forward(r64[win] / sc, gch[win], ws, bf16=True)
+        ref.append(jinv[k, j, i] * r64[k, j, i] + sc * y[k - lo[0], j - lo[1], i - lo[2]])
+        got.append(zg[k, j, i])
+    e = rel_l2(got, ref)
+    print("256^3 learned preconditioner: %d sampled cells, rel L2 %.2e" % (len(ref), e), flush=True)
+    assert np.all(np.isfinite(got))
+    assert e < 2e-4
 
 
 @pytest.mark.parametrize("kind", ["mixed", "learned"])

@@ -277,3 +277,29 @@ def test_fcg_with_learned_preconditioner_solves():
     x, it = cnn.fcg(st, b, np.zeros(g.shape), lambda r: cnn.precondition(st, r, ws), 1e-10, 500)
     assert it > 3
     assert np.max(np.abs(x - p)) < 1e-7 * np.max(np.abs(p))
+
+
+def test_network_receptive_field_is_four_cells():
+    # four 3^3 layers: the output at a cell depends on the input and the geometry
+    # channel within 4 cells, so the network evaluated on the 9^3 window around a cell
+    # (clipped at the grid faces, where both forms pad with zeros) gives the full
+    # evaluation's value exactly; a 7^3 window does not (the full-size sampled parity
+    # test of the device preconditioner relies on the first fact)
+    rng = np.random.default_rng(41)
+    shape = (14, 13, 15)
+    x = rng.standard_normal(shape)
+    g = rng.random(shape)
+    ws = cnn.split_weights(inputs.cnn_init_weights(5, scale=4.0).astype(np.float64))
+    full, _ = cnn.forward(x, g, ws, bf16=True)
+    short = 0
+    for (k, j, i) in [(7, 6, 7), (0, 0, 0), (13, 12, 14), (2, 9, 4), (11, 3, 10)]:
+        for R, exact in ((4, True), (3, False)):
+            lo = (max(0, k - R), max(0, j - R), max(0, i - R))
+            win = tuple(slice(lo[a], min(shape[a], c + R + 1)) for a, c in enumerate((k, j, i)))
+            y, _ = cnn.forward(x[win], g[win], ws, bf16=True)
+            v = y[k - lo[0], j - lo[1], i - lo[2]]
+            if exact:
+                assert v == full[k, j, i]
+            elif v != full[k, j, i]:
+                short += 1
+    assert short >= 1   # the interior cell's 7^3 window misses part of its dependence
