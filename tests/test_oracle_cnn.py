@@ -1,7 +1,8 @@
 """Pins for the CNN-preconditioner oracle (oracle/cnn.py) against library routines
 (scipy's n-d correlation, torch's bfloat16 conversion, scipy's scalar minimiser, a
 dense solve), brute-force loops, adjoint identities, finite differences and the
-closed forms of Adam and conjugate gradients.
+closed forms of Adam and conjugate gradients, and the network's four-cell receptive
+field (window evaluation equals the full one).
 """
 import numpy as np
 import pytest
