@@ -7,7 +7,8 @@
   developed state, each piece checked against the oracle functions evaluated on the
   GPU's own input state: eddy viscosity, Poisson right-hand side, H, and the
   projected u and U from the GPU's pressure (relative L2 1e-10); the pressure itself
-  by the FP64 residual of the oracle's operator (<= tol).
+  by the FP64 residual of the oracle's operator (<= tol); the surface forces of the
+  end state (relative 1e-9 of the largest component).
 * Mixed and learned solves at that size: the FP64 residual recomputed by the
   oracle's operator, and the discrete divergence identity div U^{n+1} =
   dt (b - L p) cell by cell (a property at any size).
@@ -129,10 +130,16 @@ def test_benchmark_workload_step_pieces_match_oracle():
     uo, Uo = flow.project(st, us, Us, p1, dt)
     e_u = rel_l2(_vec(u1), _vec(uo))
     e_U = rel_l2(_vec(U1), _vec(Uo))
-    print("256^3 step %d: rel L2 nut %.1e b %.1e H %.1e u %.1e U %.1e; FP64 residual %.3e" %
-          (n, e_nut, e_b, e_h, e_u, e_U, res), flush=True)
+    # forces on the surface from the step's end state and its eddy viscosity
+    Fp, Fv = (np.array(f) for f in s.forces(gs, case.nu))
+    oFp, oFv = flow.forces(st, u1, p1, nut, case.nu)
+    e_f = max(float(np.max(np.abs(Fp - oFp))) / float(np.max(np.abs(oFp))),
+              float(np.max(np.abs(Fv - oFv))) / float(np.max(np.abs(oFv))))
+    print("256^3 step %d: rel L2 nut %.1e b %.1e H %.1e u %.1e U %.1e; FP64 residual %.3e; forces %.1e" %
+          (n, e_nut, e_b, e_h, e_u, e_U, res, e_f), flush=True)
     assert max(e_nut, e_b, e_h, e_u, e_U) < 1e-10
     assert res <= 1e-6 * 1.0001
+    assert e_f < 1e-9
     s.close()
 
 
