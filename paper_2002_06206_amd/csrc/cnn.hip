@@ -487,8 +487,8 @@ __device__ __forceinline__ void conv16to1_plane(const uint16_t* ring, int cb, in
 struct MPre {
     uint4 pre[PCHUNK];
     uint16_t preg[PSCAL];
-    float er[4], erp[4];
-    uint8_t epc[4];
+    float er, erp;   // EPI_COMBINE: r and r_prev of the lane's output cell (row g)
+    uint8_t epc;     // and its face code
 };
 
 // The march of a 16-channel input (see above): COUT = 16 (EPI_BF16, EPI_GATE) or
@@ -582,20 +582,19 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
             R.pre[k] = make_uint4(v[0], v[1], v[2], v[3]);
         }
     };
-    // EPI_COMBINE: r, r_prev and the face code of the wave's output cells of plane pz
+    // EPI_COMBINE: r, r_prev and the face code of output row g of the wave's cells of
+    // plane pz: every lane loads one cell, so the four rows take one load each per array
+    // (the wave's combine epilogue is spread over its four lane groups)
+    const int gye = ty * CTY + r0 + g;
     auto load_epi = [&](int pz, MPre& R) {
         if (EPI != EPI_COMBINE) return;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int gy = ty * CTY + r0 + rr;
-            R.er[rr] = R.erp[rr] = 0.0f;
-            R.epc[rr] = 0;
-            if (g == 0 && pz < z1 && gxo < nx && gy < ny) {
-                const long long c = (long long)gxo + (long long)nx * gy + plane * pz;
-                R.er[rr] = cio.r[c];
-                R.epc[rr] = cio.pcode[c];
-                if (cio.rp) R.erp[rr] = cio.rp[c];
-            }
+        R.er = R.erp = 0.0f;
+        R.epc = 0;
+        if (pz < z1 && gxo < nx && gye < ny) {
+            const long long c = (long long)gxo + (long long)nx * gye + plane * pz;
+            R.er = cio.r[c];
+            R.epc = cio.pcode[c];
+            if (cio.rp) R.erp = cio.rp[c];
         }
     };
     auto store_plane = [&](int slot, const MPre& R) {
@@ -678,18 +677,25 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
                 round2(gate4[rr][2], gate4[rr][3]);
             }
         }
+        if (EPI == EPI_COMBINE) {
+            // output row g of the lane's column: lane group 0 holds the four rows' sums
+            const float t1 = __shfl(o1[1], j), t2 = __shfl(o1[2], j), t3 = __shfl(o1[3], j);
+            const float om = g == 0 ? o1[0] : (g == 1 ? t1 : (g == 2 ? t2 : t3));
+            if (gxo < nx && gye < ny) {
+                const long long c = (long long)gxo + (long long)nx * gye + plane * z;
+                const float zi = invf[jcnt(S.epc)] * S.er + sc * om;
+                cio.z[c] = zi;
+                zsum[0] += (double)zi * (double)S.er;
+                zsum[1] += (double)zi * (double)S.erp;
+            }
+        }
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const int gy = ty * CTY + r0 + rr;
             if (gxo >= nx || gy >= ny) continue;
             const long long c = (long long)gxo + (long long)nx * gy + plane * z;
             if (EPI == EPI_COMBINE) {
-                if (g == 0) {
-                    const float zi = invf[jcnt(S.epc[rr])] * S.er[rr] + sc * o1[rr];
-                    cio.z[c] = zi;
-                    zsum[0] += (double)zi * (double)S.er[rr];
-                    zsum[1] += (double)zi * (double)S.erp[rr];
-                }
+                // done above
             } else if (EPI == EPI_F32) {
                 if (g == 0) static_cast<float*>(out)[c] = o1[rr];
             } else {
