@@ -677,28 +677,28 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
                 round2(gate4[rr][2], gate4[rr][3]);
             }
         }
-        if (EPI == EPI_COMBINE) {
+        if (EPI == EPI_COMBINE || EPI == EPI_F32) {
             // output row g of the lane's column: lane group 0 holds the four rows' sums
             const float t1 = __shfl(o1[1], j), t2 = __shfl(o1[2], j), t3 = __shfl(o1[3], j);
             const float om = g == 0 ? o1[0] : (g == 1 ? t1 : (g == 2 ? t2 : t3));
             if (gxo < nx && gye < ny) {
                 const long long c = (long long)gxo + (long long)nx * gye + plane * z;
-                const float zi = invf[jcnt(S.epc)] * S.er + sc * om;
-                cio.z[c] = zi;
-                zsum[0] += (double)zi * (double)S.er;
-                zsum[1] += (double)zi * (double)S.erp;
+                if (EPI == EPI_COMBINE) {
+                    const float zi = invf[jcnt(S.epc)] * S.er + sc * om;
+                    cio.z[c] = zi;
+                    zsum[0] += (double)zi * (double)S.er;
+                    zsum[1] += (double)zi * (double)S.erp;
+                } else {
+                    static_cast<float*>(out)[c] = om;
+                }
             }
         }
+        if constexpr (COUT == 16) {
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int gy = ty * CTY + r0 + rr;
-            if (gxo >= nx || gy >= ny) continue;
-            const long long c = (long long)gxo + (long long)nx * gy + plane * z;
-            if (EPI == EPI_COMBINE) {
-                // done above
-            } else if (EPI == EPI_F32) {
-                if (g == 0) static_cast<float*>(out)[c] = o1[rr];
-            } else {
+            for (int rr = 0; rr < 4; ++rr) {
+                const int gy = ty * CTY + r0 + rr;
+                if (gxo >= nx || gy >= ny) continue;
+                const long long c = (long long)gxo + (long long)nx * gy + plane * z;
                 float v[4] = {acc[rr][0], acc[rr][1], acc[rr][2], acc[rr][3]};
                 if (EPI == EPI_GATE) {
 #pragma unroll
