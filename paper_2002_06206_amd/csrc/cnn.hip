@@ -237,8 +237,8 @@ __device__ inline float hsig(float x) { return fminf(fmaxf(fmaf(x, 0.25f, 0.5f),
 template <int CIN, int COUT, int EPI>
 __global__ void __launch_bounds__(256, 2) k_conv(int nx, int ny, int nz, const uint16_t* __restrict__ in,
                                                  const uint16_t* __restrict__ wp, void* __restrict__ out,
-                                                 ConvIO io, const Solver* sv) {
-    if (sv && sv->converged) return;
+                                                 ConvIO io, const Solver* sv, int gate) {
+    if (sv && stopped_before(sv, gate)) return;
     constexpr int KS = ksteps(CIN);
     constexpr int LDS_ELEMS = CIN == 16 ? 2 * HCELLS * 8 : HCELLS * CIN;
     __shared__ __attribute__((aligned(16))) uint16_t lds[LDS_ELEMS];
@@ -497,10 +497,10 @@ template <int COUT, int EPI>
 __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz, const uint16_t* __restrict__ in,
                                                   const uint16_t* __restrict__ wp, void* __restrict__ out,
                                                   const uint16_t* __restrict__ gsrc, const uint16_t* __restrict__ wgp,
-                                                  const Solver* sv, CombineIO cio) {
+                                                  const Solver* sv, int gate, CombineIO cio) {
     static_assert(COUT == 16 || COUT == 1, "marching convolution: 16 or 1 output channels");
     static_assert((EPI == EPI_COMBINE || EPI == EPI_F32) == (COUT == 1), "epilogue / output channels");
-    if (sv && sv->converged) return;
+    if (sv && stopped_before(sv, gate)) return;
     constexpr int KS = COUT == 1 ? 5 : 14;
     constexpr int PLANE = 2 * HPC * 8;   // uint16 per ring plane
     __shared__ __attribute__((aligned(16))) uint16_t ring[4 * PLANE];
@@ -743,8 +743,8 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
 // order into the solver's reduction slots: the total in entry 0, zeros in entries
 // 1 .. nparts - 1 (the consumers sum nparts entries of a slot).  zrp_slot < 0: none.
 __global__ void __launch_bounds__(NT) k_relay(const double* __restrict__ cpart, int nb, double* __restrict__ partials,
-                                              int nparts, int zr_slot, int zrp_slot, const Solver* sv) {
-    if (sv && sv->converged) return;
+                                              int nparts, int zr_slot, int zrp_slot, const Solver* sv, int gate) {
+    if (sv && stopped_before(sv, gate)) return;
     __shared__ double sh[8];
     double v[2] = {0.0, 0.0};
     for (int b = threadIdx.x; b < nb; b += NT) {
@@ -785,8 +785,8 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
                                                  const uint16_t* __restrict__ w1p, const uint16_t* __restrict__ wgp,
                                                  const uint16_t* __restrict__ w2p, uint16_t* __restrict__ out,
                                                  const double* __restrict__ rpart, int nparts, double* __restrict__ s_out,
-                                                 const Solver* sv) {
-    if (sv && sv->converged) return;
+                                                 const Solver* sv, int gate) {
+    if (sv && stopped_before(sv, gate)) return;
     constexpr int PLANE = 2 * HPC * 8;   // uint16 per 16-channel ring plane
     constexpr int OOB = 0x7FFFFFF0;
     constexpr int RSRC3 = 0x00020000;
@@ -1056,14 +1056,14 @@ __global__ void __launch_bounds__(NT) k_sumsq(long long n, const T* __restrict__
 }
 
 // Network input x = BF16(f / s) with s^2 = (sum of the partials of <f,f>) / n.  With a
-// solver state the kernel does nothing once the solve has converged, and with `check`
-// it stops the solve itself (sets converged) when <f,f> <= tol2; s is stored for the
-// combining step.
+// solver state the kernel does nothing once the solve has stopped before iteration it,
+// and with `check` it stops the solve itself at iteration it when <f,f> <= tol2; s is
+// stored for the combining step.
 template <class T>
 __global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__ f, const double* __restrict__ part,
                                               int nparts, uint16_t* __restrict__ x, double* __restrict__ s_out,
                                               Solver* sv, int it, int check) {
-    if (sv && sv->converged) return;
+    if (sv && stopped_before(sv, it)) return;
     __shared__ double sh[4];
     double v[1] = {0.0};
     for (int b = threadIdx.x; b < nparts; b += NT) v[0] += part[b];
@@ -1075,6 +1075,7 @@ __global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__
                 sv->nan_seen = 1;
                 sv->converged = 3;
                 sv->iters = it;
+                sv->stop_it = it;
             }
             return;
         }
@@ -1083,7 +1084,10 @@ __global__ void __launch_bounds__(NT) k_input(long long n, const T* __restrict__
             sv->iters = it;
         }
         if (ff <= sv->tol2) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) sv->converged = 1;
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sv->converged = 1;
+                sv->stop_it = it;
+            }
             return;
         }
     }
@@ -1311,7 +1315,7 @@ ConvIO io_bgate(const uint16_t* G, const uint16_t* pre, float* dg, int accum) {
 // G = hsig(Wg * xg)
 int net_gate(ibm_cnn* n, int nx, int ny, int nz, hipStream_t s) {
     k_conv<1, 16, EPI_HSIG><<<conv_blocks(nx, ny, nz), 256, 0, s>>>(nx, ny, nz, n->xg, pw(n, PV_WG), n->G,
-                                                                        io_none(), nullptr);
+                                                                        io_none(), nullptr, 0);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -1359,7 +1363,7 @@ int mconv_blocks(int nx, int ny, int nz, int mz) {
     return ((nx + CTX - 1) / CTX) * ((ny + CTY - 1) / CTY) * ((nz + mz - 1) / mz);
 }
 
-int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv, hipStream_t s) {
+int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, hipStream_t s) {
     if (!keep) {
         // solver path: marching kernels, no activations kept (their in-plane byte
         // offsets are 32-bit)
@@ -1371,12 +1375,12 @@ int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv,
         const int mb = mconv_blocks(nx, ny, nz, mz);
         const uint16_t* wg = pw(n, PV_WG);
         k_mfwd<false><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y,
-                                         nullptr, 0, nullptr, sv);
+                                         nullptr, 0, nullptr, nullptr, 0);
         // the gated adjoint output goes to a1's buffer (the forward half keeps a1 in LDS)
-        k_mconv<16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
-                                                     CombineIO{});
+        k_mconv<16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, nullptr,
+                                                     0, CombineIO{});
         k_mconv<1, EPI_F32><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), n->out, nullptr, nullptr,
-                                                   sv, CombineIO{});
+                                                   nullptr, 0, CombineIO{});
         IBM_HIP(hipGetLastError());
         n->nx = nx;
         n->ny = ny;
@@ -1386,11 +1390,11 @@ int net_forward(ibm_cnn* n, int nx, int ny, int nz, bool keep, const Solver* sv,
     }
     const int nb = conv_blocks(nx, ny, nz);
     k_conv<1, 16, EPI_GATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->xr, pw(n, PV_W1), n->a1,
-                                               io_gate(n->G, keep ? n->u1 : nullptr), sv);
-    k_conv<16, 16, EPI_BF16><<<nb, 256, 0, s>>>(nx, ny, nz, n->a1, pw(n, PV_W2), n->y, io_none(), sv);
+                                               io_gate(n->G, keep ? n->u1 : nullptr), nullptr, 0);
+    k_conv<16, 16, EPI_BF16><<<nb, 256, 0, s>>>(nx, ny, nz, n->a1, pw(n, PV_W2), n->y, io_none(), nullptr, 0);
     k_conv<16, 16, EPI_GATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->y, pw(n, PV_W2T), n->bb,
-                                                io_gate(n->G, keep ? n->vv : nullptr), sv);
-    k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->bb, pw(n, PV_W1T), n->out, io_none(1), sv);
+                                                io_gate(n->G, keep ? n->vv : nullptr), nullptr, 0);
+    k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->bb, pw(n, PV_W1T), n->out, io_none(1), nullptr, 0);
     IBM_HIP(hipGetLastError());
     n->nx = nx;
     n->ny = ny;
@@ -1422,25 +1426,25 @@ int net_backward(ibm_cnn* n, float* dx, hipStream_t s) {
     if ((rc = wgrad<1, 16>(n, n->dy1, n->bb, OFF_W1, 0, s))) return rc;
     // d bb = W1 * dy1;  d vv = d bb . G;  dG = d bb . vv
     k_conv<1, 16, EPI_BGATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->dy1, pw(n, PV_W1), n->sig[0],
-                                                io_bgate(n->G, n->vv, n->dG, 0), nullptr);
+                                                io_bgate(n->G, n->vv, n->dG, 0), nullptr, 0);
     // vv = W2^T * y
     if ((rc = wgrad<16, 16>(n, n->sig[0], n->y, OFF_W2, 0, s))) return rc;
     // d y = W2 * d vv
-    k_conv<16, 16, EPI_BF16><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_W2), n->sig[1], io_none(), nullptr);
+    k_conv<16, 16, EPI_BF16><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_W2), n->sig[1], io_none(), nullptr, 0);
     // y = W2 * a1
     if ((rc = wgrad<16, 16>(n, n->a1, n->sig[1], OFF_W2, 1, s))) return rc;
     // d a1 = W2^T * d y;  d u1 = d a1 . G;  dG += d a1 . u1
     k_conv<16, 16, EPI_BGATE><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[1], pw(n, PV_W2T), n->sig[0],
-                                                 io_bgate(n->G, n->u1, n->dG, 1), nullptr);
+                                                 io_bgate(n->G, n->u1, n->dG, 1), nullptr, 0);
     // u1 = W1 * xr
     if ((rc = wgrad<1, 16>(n, n->xr, n->sig[0], OFF_W1, 1, s))) return rc;
     if (dx)
-        k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_W1T), dx, io_none(2), nullptr);
+        k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[0], pw(n, PV_W1T), dx, io_none(2), nullptr, 0);
     // G = hsig(Wg * xg)
     k_dpre<<<2048, 256, 0, s>>>(cells * 16, n->dG, n->G, n->sig[1]);
     if ((rc = wgrad<1, 16>(n, n->xg, n->sig[1], OFF_WG, 0, s))) return rc;
     if (dx)
-        k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[1], pw(n, PV_WGT), dx + 1, io_none(2), nullptr);
+        k_conv<16, 1, EPI_F32><<<nb, 256, 0, s>>>(nx, ny, nz, n->sig[1], pw(n, PV_WGT), dx + 1, io_none(2), nullptr, 0);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -1492,7 +1496,7 @@ int loss_forward(ibm_cnn* n, ibm_ctx* c, const double* b, const double* p, hipSt
     k_sumsq<double><<<nred, NT, 0, s>>>(N, n->f, n->part);
     k_input<double><<<nred, NT, 0, s>>>(N, n->f, n->part, nred, n->xr, n->scal, nullptr, 0, 0);
     IBM_HIP(hipGetLastError());
-    if ((rc = net_forward(n, g.nx, g.ny, g.nz, true, nullptr, s))) return rc;
+    if ((rc = net_forward(n, g.nx, g.ny, g.nz, true, s))) return rc;
     k_phat<<<2048, 256, 0, s>>>(N, g.dx * g.dx, n->f, c->pcode, n->out, n->scal, n->h);
     k_loss_dots<<<nred, NT, 0, s>>>(g, c->pcode, n->f, p, n->h, n->q, n->part);
     k_loss_final<<<1, NT, 0, s>>>(n->part, nred, n->scal);
@@ -1510,7 +1514,7 @@ int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s) {
 
 // z = D^-1 r + s K^T K (r/s) inside the FCG solve (see poisson.hip): s^2 = <r,r>/N from
 // the partials in rr_slot; <z,r> -> zr_slot, <z,rp> -> zrp_slot (-1: none).  With check,
-// stops the solve (sv->converged = 1) when <r,r> <= sv->tol2.  The gate must be
+// stops the solve at iteration it (converged = 1) when <r,r> <= sv->tol2.  The gate must be
 // prepared.
 int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
                             int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, int check,
@@ -1530,24 +1534,28 @@ int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* 
     }
     const uint16_t* wg = pw(n, PV_WG);
     const double* rpart = partials + (long long)rr_slot * MAX_BLOCKS;
+    // kernels after k_input's stop test of iteration it run only while the solve goes on
+    // past it; without that test (the fused FCG tests in its pass A, after these) they
+    // run up to and including iteration it
+    const int gate = check ? it + 1 : it;
     if (check) {
         // k_input also stops the solve once <r,r> <= tol^2 |b|^2
         k_input<float><<<nparts, NT, 0, s>>>(c->N, r, rpart, nparts, n->xr, n->scal, sv, it, check);
         k_mfwd<false><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y,
-                                         nullptr, 0, nullptr, sv);
+                                         nullptr, 0, nullptr, sv, gate);
     } else if (sv) {   // inside a solve: the dominant kernel is timed when the context times its kernels
         launch_timed(c, TK_DIR, k_mfwd<true>, mb, s, nx, ny, nz, mz, (const void*)r, (const uint16_t*)n->xg,
-                     pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart, nparts, n->scal, (const Solver*)sv);
+                     pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart, nparts, n->scal, (const Solver*)sv, gate);
     } else {
         k_mfwd<true><<<mb, 256, 0, s>>>(nx, ny, nz, mz, r, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart,
-                                        nparts, n->scal, sv);
+                                        nparts, n->scal, sv, gate);
     }
-    k_mconv<16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv,
+    k_mconv<16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv, gate,
                                                  CombineIO{});
     const CombineIO cio{r, rp, c->pcode, n->scal, g.dx * g.dx, z, n->cpart};
     k_mconv<1, EPI_COMBINE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), nullptr, nullptr,
-                                                   nullptr, sv, cio);
-    k_relay<<<1, NT, 0, s>>>(n->cpart, mb, partials, nparts, zr_slot, zrp_slot, sv);
+                                                   nullptr, sv, gate, cio);
+    k_relay<<<1, NT, 0, s>>>(n->cpart, mb, partials, nparts, zr_slot, zrp_slot, sv, gate);
     IBM_HIP(hipGetLastError());
     n->nx = nx;
     n->ny = ny;
@@ -1711,8 +1719,8 @@ int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t n
     IBM_HIP(hipGetLastError());
     if (net->train_ok) {
         if ((rc = net_gate(net, nx, ny, nz, s))) return rc;
-        if ((rc = net_forward(net, nx, ny, nz, true, nullptr, s))) return rc;
-    } else if ((rc = net_forward(net, nx, ny, nz, false, nullptr, s))) {
+        if ((rc = net_forward(net, nx, ny, nz, true, s))) return rc;
+    } else if ((rc = net_forward(net, nx, ny, nz, false, s))) {
         return rc;
     }
     IBM_HIP(hipMemcpyAsync(y_dev, net->out, cells * sizeof(float), hipMemcpyDeviceToDevice, s));

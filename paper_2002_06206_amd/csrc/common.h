@@ -38,8 +38,21 @@ struct Solver {                 // device-resident scalars of the Krylov loops
     int converged;
     int iters;
     int nan_seen;
-    int pad;
+    int stop_it;                // iteration at which the solve stopped (STOP_NONE while running)
 };
+
+// The kernels of a Krylov loop decide to stop inside a launch (every block sums the same
+// partials and so takes the same decision), and the launch that decides still has work
+// to finish in all its blocks (the last x update).  A block must therefore never skip
+// because of a flag written by its own launch: block 0 records the iteration of the
+// stopping launch in stop_it, and a kernel of iteration `it` skips only when the solve
+// stopped at an earlier iteration (stop_it < gate, gate = it for kernels that run up to
+// and including the stop test of iteration it, it + 1 for the ones after it).  A value
+// written by the current launch is never below its gate.
+constexpr int STOP_NONE = 0x7fffffff;
+__device__ inline bool stopped_before(const Solver* sv, int gate) {
+    return sv->stop_it < gate;
+}
 
 // Device-resident state of the batched BiCGStab of the Crank-Nicolson predictor (one
 // system per velocity component).  Scalars of iteration it live in entry [it & 1]:

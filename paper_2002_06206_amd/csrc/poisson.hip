@@ -226,6 +226,7 @@ __global__ void __launch_bounds__(NT) k_pcg_start(const double* partials, int np
         } else {
             sv->converged = v[2] <= sv->tol2 ? 1 : 0;
         }
+        sv->stop_it = sv->converged ? -1 : STOP_NONE;
     }
 }
 
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(NT) k_pcg_a(Geo g, const uint8_t* __restrict__
                                               const T* __restrict__ dold, T* __restrict__ dnew, T* __restrict__ x,
                                               double* __restrict__ partials, int nparts, int it, int final_only,
                                               int skip_x, Solver* sv) {
-    if (sv->converged) return;
+    if (stopped_before(sv, it)) return;
     __shared__ double sh[NT];
     const double idx2 = 1.0 / (g.dx * g.dx);
     double alpha = 0.0, beta = 0.0;
@@ -259,6 +260,7 @@ __global__ void __launch_bounds__(NT) k_pcg_a(Geo g, const uint8_t* __restrict__
                 sv->nan_seen = 1;
                 sv->converged = 3;
                 sv->iters = it;
+                sv->stop_it = it;
             }
             return;
         }
@@ -266,7 +268,10 @@ __global__ void __launch_bounds__(NT) k_pcg_a(Geo g, const uint8_t* __restrict__
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sv->rr = rr;
             sv->iters = it;
-            if (stop && !final_only) sv->converged = 1;
+            if (stop && !final_only) {
+                sv->converged = 1;
+                sv->stop_it = it;
+            }
         }
     }
     const long long N = (long long)g.nx * g.ny * g.nz;
@@ -351,7 +356,7 @@ template <class T>
 __global__ void __launch_bounds__(NT) k_pcg_b(Geo g, const uint8_t* __restrict__ pcode, const T* __restrict__ d,
                                               T* __restrict__ r, T* __restrict__ zz, double* __restrict__ partials,
                                               int nparts, int it, const Solver* sv) {
-    if (sv->converged) return;
+    if (stopped_before(sv, it + 1)) return;
     __shared__ double sh[2 * NT];
     __shared__ double inv[16];
     const double idx2 = 1.0 / (g.dx * g.dx);
@@ -441,7 +446,7 @@ __global__ void __launch_bounds__(NT) k_pcg_a_v(Geo g, const uint8_t* __restrict
                                                 T* __restrict__ dnew, T* __restrict__ x,
                                                 double* __restrict__ partials, int nparts, int it, int skip_x,
                                                 Solver* sv) {
-    if (sv->converged) return;
+    if (stopped_before(sv, it)) return;
     __shared__ double sh[NT];
     __shared__ double pln[2][(TY + 2) * VW];
     const double idx2 = 1.0 / (g.dx * g.dx);
@@ -459,6 +464,7 @@ __global__ void __launch_bounds__(NT) k_pcg_a_v(Geo g, const uint8_t* __restrict
                 sv->nan_seen = 1;
                 sv->converged = 3;
                 sv->iters = it;
+                sv->stop_it = it;
             }
             return;
         }
@@ -466,7 +472,10 @@ __global__ void __launch_bounds__(NT) k_pcg_a_v(Geo g, const uint8_t* __restrict
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sv->rr = rr;
             sv->iters = it;
-            if (stop) sv->converged = 1;
+            if (stop) {
+                sv->converged = 1;
+                sv->stop_it = it;
+            }
         }
         if (stop) {
             for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N;
@@ -570,7 +579,7 @@ template <class T>
 __global__ void __launch_bounds__(NT) k_pcg_b_v(Geo g, const uint8_t* __restrict__ pcode, const T* __restrict__ d,
                                                 T* __restrict__ r, T* __restrict__ zz,
                                                 double* __restrict__ partials, int nparts, int it, const Solver* sv) {
-    if (sv->converged) return;
+    if (stopped_before(sv, it + 1)) return;
     __shared__ double sh[2 * NT];
     __shared__ double inv[16];
     const double idx2 = 1.0 / (g.dx * g.dx);
@@ -710,7 +719,7 @@ __global__ void __launch_bounds__(NT) k_pcg_a_f4(Geo g, const uint8_t* __restric
                                                  float* __restrict__ dnew, float* __restrict__ x,
                                                  double* __restrict__ partials, int nparts, int it, int skip_x,
                                                  Solver* sv) {
-    if (sv->converged) return;
+    if (stopped_before(sv, it)) return;
     __shared__ double sh[NT];
     __shared__ __attribute__((aligned(16))) float pln[2][(TY + 2) * FW];
     const float idx2 = (float)(1.0 / (g.dx * g.dx));
@@ -735,6 +744,7 @@ __global__ void __launch_bounds__(NT) k_pcg_a_f4(Geo g, const uint8_t* __restric
                 sv->nan_seen = 1;
                 sv->converged = 3;
                 sv->iters = it;
+                sv->stop_it = it;
             }
             return;
         }
@@ -742,7 +752,10 @@ __global__ void __launch_bounds__(NT) k_pcg_a_f4(Geo g, const uint8_t* __restric
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sv->rr = rr;
             sv->iters = it;
-            if (stop) sv->converged = 1;
+            if (stop) {
+                sv->converged = 1;
+                sv->stop_it = it;
+            }
         }
         if (stop) {
             if (!skip_x) {
@@ -837,7 +850,7 @@ __global__ void __launch_bounds__(NT) k_pcg_b_f4(Geo g, const uint8_t* __restric
                                                  const float* __restrict__ d, const float* r, float* rout,
                                                  float* __restrict__ zz, double* __restrict__ partials, int nparts,
                                                  int it, const Solver* sv) {
-    if (sv->converged) return;
+    if (stopped_before(sv, it + 1)) return;
     __shared__ double sh[2 * NT];
     __shared__ float invf[16];
     const double dx2 = g.dx * g.dx;
@@ -931,6 +944,7 @@ __global__ void __launch_bounds__(NT) k_seg_start(const double* partials, int np
         } else {
             sv->converged = v[0] == 0.0 ? 2 : 0;
         }
+        sv->stop_it = sv->converged ? it - 1 : STOP_NONE;
     }
 }
 
@@ -1185,8 +1199,8 @@ __global__ void k_zero_f64(long long n, double* __restrict__ x) {
 // (the preconditioner is then not a descent direction) or not finite.
 __global__ void __launch_bounds__(NT) k_fcg_dir(long long n, const float* __restrict__ z, float* __restrict__ d,
                                                 const double* __restrict__ partials, int nparts, int zr_slot,
-                                                int zrprev_slot, int first, Solver* sv) {
-    if (sv->converged) return;
+                                                int zrprev_slot, int first, int it, Solver* sv) {
+    if (stopped_before(sv, it + 1)) return;
     __shared__ double sh[12];
     const int sl[3] = {zr_slot, FCG_ZRP, zrprev_slot};
     double tot[3];
@@ -1200,6 +1214,7 @@ __global__ void __launch_bounds__(NT) k_fcg_dir(long long n, const float* __rest
                 sv->nan_seen = 1;
                 sv->converged = 3;
             }
+            sv->stop_it = it;
         }
         return;
     }
@@ -1210,8 +1225,9 @@ __global__ void __launch_bounds__(NT) k_fcg_dir(long long n, const float* __rest
 
 // q = A d (FP32), partial <d,q>
 __global__ void __launch_bounds__(NT) k_fcg_q(Geo g, const uint8_t* __restrict__ pcode, const float* __restrict__ d,
-                                              float* __restrict__ q, double* __restrict__ partials, Solver* sv) {
-    if (sv->converged) return;
+                                              float* __restrict__ q, double* __restrict__ partials, int it,
+                                              Solver* sv) {
+    if (stopped_before(sv, it + 1)) return;
     __shared__ double sh[4];
     const float idx2 = (float)(1.0 / (g.dx * g.dx));
     const long long n = (long long)g.nx * g.ny * g.nz;
@@ -1239,8 +1255,8 @@ __global__ void __launch_bounds__(NT) k_fcg_q(Geo g, const uint8_t* __restrict__
 __global__ void __launch_bounds__(NT) k_fcg_upd(long long n, float* __restrict__ e, const float* __restrict__ d,
                                                 const float* __restrict__ q, const float* __restrict__ r,
                                                 float* __restrict__ rnew, double* __restrict__ partials, int nparts,
-                                                int zr_slot, Solver* sv) {
-    if (sv->converged) return;
+                                                int zr_slot, int it, Solver* sv) {
+    if (stopped_before(sv, it + 1)) return;
     __shared__ double sh[8];
     const int sl[2] = {zr_slot, FCG_DQ};
     double tot[2];
@@ -1343,11 +1359,11 @@ static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_ev
             timing_end(c, TK_SPMV, s);
             if (rc) return rc;
             timing_begin(c, TK_UPDATE, s);
-            k_fcg_dir<<<nred, NT, 0, s>>>(c->N, c->z32, c->d32, c->partials, nred, zr, zrprev, k == 0 ? 1 : 0,
+            k_fcg_dir<<<nred, NT, 0, s>>>(c->N, c->z32, c->d32, c->partials, nred, zr, zrprev, k == 0 ? 1 : 0, it,
                                           c->solver);
-            k_fcg_q<<<nred, NT, 0, s>>>(g, c->pcode, c->d32, c->q32, c->partials, c->solver);
+            k_fcg_q<<<nred, NT, 0, s>>>(g, c->pcode, c->d32, c->q32, c->partials, it, c->solver);
             k_fcg_upd<<<nred, NT, 0, s>>>(c->N, c->e32, c->d32, c->q32, rb[cur], rb[cur ^ 1], c->partials, nred, zr,
-                                          c->solver);
+                                          it, c->solver);
             timing_end(c, TK_UPDATE, s);
             cur ^= 1;
         }

@@ -6,9 +6,11 @@ activations, backward signals, weights) and sums exactly in FP64; the GPU sums t
 same BF16 products in FP32 (relative error ~ K * 2^-24, K <= 432 products).  The two
 therefore differ only where that FP32 error moves a value across a BF16 rounding
 boundary, which flips one stored activation by one BF16 unit (2^-8 relative) with
-probability ~ 1e-4 per value.  The resulting relative L2 differences are ~1e-4;
-the bars below are 2e-3 (outputs, gradients of the network) and 1e-4 absolute on
-the loss, which lies in [0, 1].
+probability ~ 1e-4 per value.  The resulting relative L2 differences measured at
+the seeds below are 6e-6 to 6e-5 (the kernels are deterministic, so a seed gives the
+same value on every run); each bar is about three times its measured value (stated
+next to it), so one wrong tap or channel confined to a tile edge fails.  The loss,
+which lies in [0, 1], is checked to 1e-4 absolute.
 """
 import numpy as np
 import pytest
@@ -66,7 +68,7 @@ def test_forward_matches_oracle_ragged_grid():
     e = rel_l2(y, yo)
     print("forward rel L2 %.2e" % e, flush=True)
     assert np.all(np.isfinite(y))
-    assert e < 2e-3
+    assert e < 6e-5          # measured 2.0e-5
     # without the BF16 rounding points the FP64 network is still close (stated, loose)
     yf, _ = cnn.forward(x[..., 0], x[..., 1], _layers(w), bf16=False)
     assert rel_l2(y, yf) < 5e-2
@@ -89,7 +91,7 @@ def test_marching_forward_matches_oracle_ragged_grid():
     yo, _ = cnn.forward(x[..., 0], x[..., 1], _layers(w), bf16=True)
     e = rel_l2(y.cpu().numpy(), yo)
     print("marching forward rel L2 %.2e" % e, flush=True)
-    assert e < 2e-3
+    assert e < 4e-5          # measured 1.3e-5
     net.close()
 
 
@@ -163,12 +165,12 @@ def test_backward_matches_oracle_ragged_grid():
     for l in range(3):
         e = rel_l2(gw[l], dws[l])
         print("%s weight-gradient rel L2 %.2e" % (cnn.LAYERS[l][0], e), flush=True)
-        assert e < 2e-3
+        assert e < 1.6e-4    # measured 4.2e-5 (W1), 1.0e-5 (W2), 5.2e-5 (Wg)
     dxg = dx.cpu().numpy()
     e = rel_l2(dxg[..., 0], dxo)
     eg = rel_l2(dxg[..., 1], dgo)
     print("input-gradient rel L2 %.2e, geometry-gradient rel L2 %.2e" % (e, eg), flush=True)
-    assert e < 2e-3 and eg < 2e-3
+    assert e < 2e-5 and eg < 1.8e-4    # measured 6.3e-6, 5.8e-5
     net.close()
 
 
@@ -200,7 +202,7 @@ def test_loss_and_gradient_match_oracle():
     for l in range(3):
         e = rel_l2(gw[l], dws[l])
         print("%s loss-gradient rel L2 %.2e" % (cnn.LAYERS[l][0], e), flush=True)
-        assert e < 2e-3
+        assert e < 8e-5      # measured 2.0e-5 (W1), 1.6e-5 (W2), 2.6e-5 (Wg)
     net.close()
     s.close()
 
@@ -235,7 +237,58 @@ def test_preconditioner_matches_oracle():
     zo = cnn.precondition(st, r.astype(np.float64), _layers(w), bf16=True)
     e = rel_l2(z.cpu().numpy(), zo)
     print("preconditioner rel L2 %.2e" % e, flush=True)
-    assert e < 2e-3
+    assert e < 8e-5          # measured 2.7e-5
+    net.close()
+    s.close()
+
+
+def test_preconditioner_matches_oracle_ragged_rows():
+    """The solver's marching launch on a grid whose ny is not a multiple of the 8-row
+    tile (40 x 37 x 24): the partial row tile at the +y edge goes through the guarded
+    loads and stores of the combine epilogue."""
+    n = (40, 37, 24)
+    rng = np.random.default_rng(31)
+    tri = inputs.icosphere(2, 7.0, (19.6, 18.3, 11.7), inputs.random_rotation(rng))
+    g = flow.Grid(n, 1.0, (0.0, 0.0, 0.0), (1, 2, 3, 3, 3, 3), (1.0, 0.0, 0.0))
+    ob, ot = tagging.tag(tri, g.n, g.dx, g.origin)
+    st = flow.build_stencils(g, ob, ot)
+    s = ibm.Solver(g.n, g.dx, g.origin, g.bc, g.u_in, ibm.MIXED)
+    s.build(torch.from_numpy(ob).cuda(), torch.from_numpy(ot).cuda())
+    w = inputs.cnn_init_weights(32, scale=3.0)
+    net = ibm.Network(g.ncell, w)
+    r = rng.standard_normal(g.shape).astype(np.float32)
+    z = torch.empty(g.shape, dtype=torch.float32, device="cuda")
+    print("case cnn precondition ragged rows", n, flush=True)
+    ibm.ibm_cnn_precondition(net.net, s.ctx, torch.from_numpy(r).cuda(), z)
+    zo = cnn.precondition(st, r.astype(np.float64), _layers(w), bf16=True)
+    zg = z.cpu().numpy()
+    e = rel_l2(zg, zo)
+    e_edge = rel_l2(zg[:, 32:, :], zo[:, 32:, :])
+    print("preconditioner rel L2 %.2e (rows 32-36: %.2e)" % (e, e_edge), flush=True)
+    assert e < 1.4e-4 and e_edge < 1.4e-4    # measured 4.6e-5, 4.6e-5
+    net.close()
+    s.close()
+
+
+@pytest.mark.parametrize("how", ["force_stall", "nan_weights"])
+def test_fcg_cnn_falls_back_to_fp64(how):
+    """A learned solve that stalls (the test hook) or whose network gives non-finite
+    values (NaN weights) hands the solve to FP64 Jacobi PCG from the current x: the
+    fallback is reported, x is finite and the FP64 residual meets the tolerance."""
+    g, st, s, b, p = _geometry_case(3, 32)
+    w = inputs.cnn_init_weights(1, scale=3.0)
+    if how == "nan_weights":
+        w = np.full_like(w, np.nan)
+    net = ibm.Network(g.ncell, w)
+    net.attach(s)
+    x = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    print("case fcg cnn fallback", how, flush=True)
+    rc, stats = s.poisson(torch.from_numpy(b).cuda(), x, tol=1e-10, max_iter=20000, kind=ibm.SOLVER_FCG_CNN,
+                          inner_tol=0.1, inner_max_iter=500, force_stall=1 if how == "force_stall" else 0)
+    print("  %s" % stats, flush=True)
+    assert rc == 0 and stats["fallback_used"] == 1
+    assert bool(torch.isfinite(x).all())
+    assert stats["rel_residual"] <= 1e-10 * 1.0001
     net.close()
     s.close()
 

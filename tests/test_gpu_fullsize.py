@@ -301,9 +301,9 @@ def test_benchmark_workload_learned_preconditioner_sampled():
     # channel within 4 cells (four 3^3 layers), so the oracle evaluates the network on
     # the 11^3 window around it (clipped at the domain faces, where both sides pad with
     # zeros); s = RMS of r over the whole grid.  Samples: random cells, the slab
-    # boundaries, tile edges, domain faces and cut cells.  Bar: relative L2 2e-4 over the
+    # boundaries, tile edges, domain faces and cut cells.  Bar: relative L2 6e-5 over the
     # samples (measured 2.0e-5; the differences are BF16 activations rounded from FP32
-    # sums against FP64 sums, the small-grid comparison allows 2e-3).
+    # sums against FP64 sums).
     from oracle import cnn
     case, g, ob, ot, st = _oracle("ellipsoids256")
     s, *_ = _gpu(case, ibm.MIXED)
@@ -344,7 +344,7 @@ def test_benchmark_workload_learned_preconditioner_sampled():
     e = rel_l2(got, ref)
     print("256^3 learned preconditioner: %d sampled cells, rel L2 %.2e" % (len(ref), e), flush=True)
     assert np.all(np.isfinite(got))
-    assert e < 2e-4
+    assert e < 6e-5
 
 
 @pytest.mark.parametrize("kind", ["mixed", "learned"])
