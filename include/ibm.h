@@ -152,6 +152,11 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
 int ibm_destroy(ibm_ctx* ctx);
 const char* ibm_last_error(void);
 
+/* Diagnostic: number of device and pinned-host allocations the library has made in this
+ * process (every context, network and grid); *count_out receives it.  Comparing two
+ * readings shows whether the calls between them allocated anything. */
+int ibm_alloc_count(int64_t* count_out);
+
 /* Tagging (Sec. 2.3.1): tri_dev = ntri x 3 vertices x xyz doubles (device).  For every
  * segment between face-adjacent cell centres inside the domain, decides exactly
  * whether the closed segment meets a closed triangle (edges and vertices inclusive;
@@ -348,7 +353,10 @@ int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const do
 /* z = D^-1 r + s net(r/s) on the context's grid and geometry (r, z: cells floats). */
 int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, void* stream);
 /* Preconditioner used by IBM_SOLVER_FCG_CNN on this context (NULL detaches); the network
- * must cover the grid and outlive its use. */
+ * must cover the grid and outlive its use.  Attaching is set-up: it sizes the network's
+ * per-grid partial sums (a device allocation when the grid is larger than any it was
+ * attached to before), so ibm_step and ibm_poisson_solve allocate nothing; a solve on a
+ * grid the network was not attached to fails with IBM_ERR_ARG. */
 int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net);
 
 /* Building-cube grid (Sec. 2.2): the domain is tiled by K[0] x K[1] x K[2] coarse cubes

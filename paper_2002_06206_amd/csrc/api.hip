@@ -2,6 +2,7 @@
 // launch sequencing.  All arithmetic of the step runs in the kernels of the other
 // translation units; nothing here touches field data on the host.
 
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -12,8 +13,20 @@
 namespace ibm {
 
 static thread_local std::string g_err;
+static std::atomic<long long> g_allocs{0};
 
 void set_error(const std::string& msg) { g_err = msg; }
+
+void count_alloc() { g_allocs.fetch_add(1, std::memory_order_relaxed); }
+
+int abi_exception(bool oom, const char* what) {
+    try {
+        g_err = std::string(oom ? "host allocation failed: " : "internal error: ") + (what ? what : "");
+    } catch (...) {
+        g_err.clear();
+    }
+    return oom ? IBM_ERR_OOM : IBM_ERR_ARG;
+}
 
 int hip_fail(hipError_t e, const char* what) {
     g_err = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
@@ -35,7 +48,7 @@ int bad(const char* msg) {
 
 template <class P>
 int dalloc(P** p, size_t bytes) {
-    hipError_t e = hipMalloc((void**)p, bytes < 256 ? 256 : bytes);
+    hipError_t e = ibm::dev_malloc((void**)p, bytes < 256 ? 256 : bytes);
     if (e != hipSuccess) {
         *p = nullptr;
         set_error(std::string("device allocation of ") + std::to_string(bytes) + " bytes failed");
@@ -67,7 +80,13 @@ extern "C" {
 
 const char* ibm_last_error(void) { return g_err.c_str(); }
 
-int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ctx** out) {
+int ibm_alloc_count(int64_t* count_out) try {
+    if (!count_out) return bad("ibm_alloc_count: null argument");
+    *count_out = g_allocs.load(std::memory_order_relaxed);
+    return IBM_OK;
+} IBM_CATCH_ALL
+
+int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ctx** out) try {
     if (!grid || !bc || !out) return bad("ibm_create: null argument");
     *out = nullptr;
     for (int a = 0; a < 3; ++a)
@@ -136,8 +155,8 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
     if (!rc) rc = dalloc(&c->solver, sizeof(Solver));
     if (!rc) rc = dalloc(&c->red, sizeof(double) * 8);
     if (!rc) {
-        hipError_t e1 = hipHostMalloc((void**)&c->h_solver, sizeof(Solver), hipHostMallocDefault);
-        hipError_t e2 = hipHostMalloc((void**)&c->h_red, sizeof(double) * 8, hipHostMallocDefault);
+        hipError_t e1 = ibm::host_malloc(&c->h_solver, sizeof(Solver));
+        hipError_t e2 = ibm::host_malloc(&c->h_red, sizeof(double) * 8);
         if (e1 != hipSuccess || e2 != hipSuccess) rc = hip_fail(e1 != hipSuccess ? e1 : e2, "hipHostMalloc");
     }
     if (!rc) {
@@ -152,7 +171,7 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
     }
     *out = c;
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 static void free_events(ibm_ctx* c) {
     for (int k = 0; k < TK_SLOTS_MAX; ++k) {
@@ -164,7 +183,7 @@ static void free_events(ibm_ctx* c) {
     c->ev_cap = 0;
 }
 
-int ibm_destroy(ibm_ctx* c) {
+int ibm_destroy(ibm_ctx* c) try {
     if (!c) return IBM_OK;
     (void)hipDeviceSynchronize();
     free_events(c);
@@ -179,9 +198,9 @@ int ibm_destroy(ibm_ctx* c) {
     if (c->h_red) (void)hipHostFree(c->h_red);
     delete c;
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_tag_geometry(ibm_ctx* c, const double* tri, int64_t ntri, uint8_t* blocked, double* theta, void* stream) {
+int ibm_tag_geometry(ibm_ctx* c, const double* tri, int64_t ntri, uint8_t* blocked, double* theta, void* stream) try {
     if (!c) return bad("null context");
     if (int rc = check_device(c)) return rc;
     if (ntri < 0 || (ntri > 0 && !tri) || !blocked) return bad("ibm_tag_geometry: bad triangle or output pointer");
@@ -199,10 +218,10 @@ int ibm_tag_geometry(ibm_ctx* c, const double* tri, int64_t ntri, uint8_t* block
     IBM_HIP(hipMemcpyAsync(blocked, c->tagmask, N, hipMemcpyDeviceToDevice, s));
     if (theta) IBM_HIP(hipMemcpyAsync(theta, c->theta, sizeof(double) * 6 * N, hipMemcpyDeviceToDevice, s));
     return rc;
-}
+} IBM_CATCH_ALL
 
 int ibm_build_stencils(ibm_ctx* c, const uint8_t* blocked, const double* theta, int32_t deadend, uint16_t* flags,
-                       int32_t* label, int64_t* n_cut_out, void* stream) {
+                       int32_t* label, int64_t* n_cut_out, void* stream) try {
     if (!c) return bad("null context");
     if (int rc = check_device(c)) return rc;
     if (!blocked) return bad("ibm_build_stencils: null blocked");
@@ -233,25 +252,25 @@ int ibm_build_stencils(ibm_ctx* c, const uint8_t* blocked, const double* theta, 
         c->tagged = false;
     }
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_cut_points(ibm_ctx* c, double* xyz, void* stream) {
+int ibm_cut_points(ibm_ctx* c, double* xyz, void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!xyz && c->ncut > 0) return bad("ibm_cut_points: null output");
     return cut_points_run(c, xyz, (hipStream_t)stream);
-}
+} IBM_CATCH_ALL
 
 int ibm_init_state(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const double u0[3],
-                   const double* wall, void* stream) {
+                   const double* wall, void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!u || !U || !p || !h || !u0) return bad("ibm_init_state: null argument");
     for (int a = 0; a < 3; ++a)
         if (!u[a] || !U[a] || !h[a]) return bad("ibm_init_state: null field pointer");
     return init_state_run(c, u, U, p, h, u0, wall, (hipStream_t)stream);
-}
+} IBM_CATCH_ALL
 
 int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const double* wall,
-             const ibm_step_params* prm, ibm_stats* st, void* stream) {
+             const ibm_step_params* prm, ibm_stats* st, void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!u || !U || !p || !h || !prm) return bad("ibm_step: null argument");
     for (int a = 0; a < 3; ++a)
@@ -286,10 +305,10 @@ int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const 
         if (rc) return rc;
     }
     return prc;
-}
+} IBM_CATCH_ALL
 
 int ibm_poisson_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st,
-                      void* stream) {
+                      void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!b || !x || !o) return bad("ibm_poisson_solve: null argument");
     if (o->max_iter <= 0 || !(o->tol > 0.0)) return bad("ibm_poisson_solve: need tol > 0 and max_iter > 0");
@@ -304,22 +323,22 @@ int ibm_poisson_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_o
     if (st && rc >= 0) *st = local;
     if (rc >= 0) IBM_HIP(hipStreamSynchronize(s));
     return rc;
-}
+} IBM_CATCH_ALL
 
-int ibm_apply_laplacian(ibm_ctx* c, const double* x, double* y, void* stream) {
+int ibm_apply_laplacian(ibm_ctx* c, const double* x, double* y, void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!x || !y) return bad("ibm_apply_laplacian: null argument");
     return laplacian_run(c, x, y, (hipStream_t)stream);
-}
+} IBM_CATCH_ALL
 
-int ibm_prepare_crank_nicolson(ibm_ctx* c) {
+int ibm_prepare_crank_nicolson(ibm_ctx* c) try {
     if (!c) return bad("null context");
     if (int rc = check_device(c)) return rc;
     return cn_prepare(c);
-}
+} IBM_CATCH_ALL
 
 int ibm_momentum_apply(ibm_ctx* c, const void* const q[3], double* const U[3], const void* nut, double nu,
-                       double dt, void* const out[3], void* stream) {
+                       double dt, void* const out[3], void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!q || !U || !out) return bad("ibm_momentum_apply: null argument");
     for (int a = 0; a < 3; ++a)
@@ -329,10 +348,10 @@ int ibm_momentum_apply(ibm_ctx* c, const void* const q[3], double* const U[3], c
             if (out[a] == q[b]) return bad("ibm_momentum_apply: out must not alias q");
     if (!(dt >= 0.0) || !(nu >= 0.0)) return bad("ibm_momentum_apply: need dt >= 0 and nu >= 0");
     return cn_apply(c, q, U, nut, nu, dt, out, (hipStream_t)stream);
-}
+} IBM_CATCH_ALL
 
 int ibm_momentum_solve(ibm_ctx* c, const void* const b[3], void* const x[3], double* const U[3], const void* nut,
-                       double nu, double dt, double tol, int32_t max_iter, int32_t iters_out[3], void* stream) {
+                       double nu, double dt, double tol, int32_t max_iter, int32_t iters_out[3], void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!b || !x || !U) return bad("ibm_momentum_solve: null argument");
     for (int a = 0; a < 3; ++a)
@@ -344,37 +363,37 @@ int ibm_momentum_solve(ibm_ctx* c, const void* const b[3], void* const x[3], dou
     if (iters_out)
         for (int a = 0; a < 3; ++a) iters_out[a] = it[a];
     return rc;
-}
+} IBM_CATCH_ALL
 
-int ibm_get_nut(ibm_ctx* c, void* out, void* stream) {
+int ibm_get_nut(ibm_ctx* c, void* out, void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!out) return bad("ibm_get_nut: null output");
     return copy_cells(c, c->nut, out, c->precision == IBM_FP64, (hipStream_t)stream);
-}
+} IBM_CATCH_ALL
 
-int ibm_get_rhs(ibm_ctx* c, double* out, void* stream) {
+int ibm_get_rhs(ibm_ctx* c, double* out, void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!out) return bad("ibm_get_rhs: null output");
     return copy_cells(c, c->b, out, true, (hipStream_t)stream);
-}
+} IBM_CATCH_ALL
 
 int ibm_forces(ibm_ctx* c, void* const u[3], const double* p, const void* nut, double nu, const double* wall,
-               double out[6], void* stream) {
+               double out[6], void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (!u || !p || !out) return bad("ibm_forces: null argument");
     for (int a = 0; a < 3; ++a)
         if (!u[a]) return bad("ibm_forces: null velocity pointer");
     return forces_run(c, u, p, nut, nu, wall, out, (hipStream_t)stream);
-}
+} IBM_CATCH_ALL
 
 int ibm_shepard_force(ibm_ctx* c, const double* tri, int64_t ntri, const double* p, int32_t thin_filter,
-                      double* side, double force[3], void* stream) {
+                      double* side, double force[3], void* stream) try {
     if (int rc = need_stencil(c)) return rc;
     if (ntri < 0 || (ntri > 0 && !tri) || !p || !force) return bad("ibm_shepard_force: bad arguments");
     return shepard_run(c, tri, ntri, p, thin_filter ? 1 : 0, side, force, (hipStream_t)stream);
-}
+} IBM_CATCH_ALL
 
-int ibm_timing_enable(ibm_ctx* c, int32_t on) {
+int ibm_timing_enable(ibm_ctx* c, int32_t on) try {
     if (!c) return bad("null context");
     if (int rc = check_device(c)) return rc;
     if (on && c->ev_cap == 0) {
@@ -389,16 +408,16 @@ int ibm_timing_enable(ibm_ctx* c, int32_t on) {
     c->timing_on = on ? 1 : 0;
     for (int k = 0; k < TK_SLOTS_MAX; ++k) c->ev_used[k] = 0;
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_set_progress(ibm_ctx* c, ibm_progress_fn fn, void* user) {
+int ibm_set_progress(ibm_ctx* c, ibm_progress_fn fn, void* user) try {
     if (!c) return bad("null context");
     c->progress = fn;
     c->progress_user = user;
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_timing_slot(ibm_ctx* c, int32_t slot, double out[2], int32_t reset) {
+int ibm_timing_slot(ibm_ctx* c, int32_t slot, double out[2], int32_t reset) try {
     if (!c || !out) return bad("ibm_timing_slot: null argument");
     if (slot < 0 || slot >= TK_SLOTS_MAX) return bad("ibm_timing_slot: slot out of range");
     out[0] = c->t_ms[slot];
@@ -408,9 +427,9 @@ int ibm_timing_slot(ibm_ctx* c, int32_t slot, double out[2], int32_t reset) {
         c->t_launches[slot] = 0;
     }
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_timing_read(ibm_ctx* c, double out[10], int32_t reset) {
+int ibm_timing_read(ibm_ctx* c, double out[10], int32_t reset) try {
     if (!c || !out) return bad("ibm_timing_read: null argument");
     for (int k = 0; k < 3; ++k) {
         out[k] = c->t_ms[k];
@@ -428,6 +447,6 @@ int ibm_timing_read(ibm_ctx* c, double out[10], int32_t reset) {
         c->t_real_iters = 0;
     }
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 }  // extern "C"

@@ -153,7 +153,7 @@ using namespace ibm;
 extern "C" {
 
 int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origin[3], const uint8_t* refine_host,
-                   ibm_bcm** out) {
+                   ibm_bcm** out) try {
     if (!K || !origin || !refine_host || !out) {
         set_error("ibm_bcm_create: null argument");
         return IBM_ERR_ARG;
@@ -208,9 +208,12 @@ int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origi
             }
     m->ncubes = (long long)m->level.size();
     m->size = m->ncubes * (long long)m->side * m->side * m->side;
-    if (m->size >= 0x7fffffffLL) {
+    // the halo tables hold 32-bit storage indices and 32-bit source offsets (up to 8
+    // sources per halo cell)
+    const long long halo_bound = m->ncubes * 6LL * BCM_H * n * n;
+    if (m->size >= 0x7fffffffLL || 8 * halo_bound >= 0x7fffffffLL) {
         delete m;
-        set_error("ibm_bcm_create: cube storage exceeds 2^31 values");
+        set_error("ibm_bcm_create: cube storage or halo tables exceed 2^31 entries");
         return IBM_ERR_ARG;
     }
     // face-halo sources
@@ -301,10 +304,10 @@ int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origi
         }
     }
     std::vector<uint8_t> lv(m->level.begin(), m->level.end());
-    if (hipMalloc((void**)&m->d_dst, sizeof(int) * dst.size()) != hipSuccess ||
-        hipMalloc((void**)&m->d_off, sizeof(int) * off.size()) != hipSuccess ||
-        hipMalloc((void**)&m->d_src, sizeof(int) * src.size()) != hipSuccess ||
-        hipMalloc((void**)&m->d_level, lv.size()) != hipSuccess) {
+    if (ibm::dev_malloc((void**)&m->d_dst, sizeof(int) * dst.size()) != hipSuccess ||
+        ibm::dev_malloc((void**)&m->d_off, sizeof(int) * off.size()) != hipSuccess ||
+        ibm::dev_malloc((void**)&m->d_src, sizeof(int) * src.size()) != hipSuccess ||
+        ibm::dev_malloc((void**)&m->d_level, lv.size()) != hipSuccess) {
         (void)hipGetLastError();
         set_error("ibm_bcm_create: out of device memory");
         (void)hipFree(m->d_dst);
@@ -325,9 +328,9 @@ int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origi
     }
     *out = m;
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_bcm_destroy(ibm_bcm* m) {
+int ibm_bcm_destroy(ibm_bcm* m) try {
     if (!m) return IBM_OK;
     (void)hipFree(m->d_dst);
     (void)hipFree(m->d_off);
@@ -335,10 +338,10 @@ int ibm_bcm_destroy(ibm_bcm* m) {
     (void)hipFree(m->d_level);
     delete m;
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 int ibm_bcm_info(const ibm_bcm* m, int64_t* ncubes, int64_t* size, int64_t* nhalo, int32_t* levels_host,
-                 int32_t* origins_host) {
+                 int32_t* origins_host) try {
     if (!m) {
         set_error("ibm_bcm_info: null grid");
         return IBM_ERR_ARG;
@@ -351,7 +354,7 @@ int ibm_bcm_info(const ibm_bcm* m, int64_t* ncubes, int64_t* size, int64_t* nhal
     if (origins_host)
         for (long long q = 0; q < 3 * m->ncubes; ++q) origins_host[q] = m->org[q];
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 // the grid's tables live on the device it was created on
 static int bcm_device_ok(const ibm_bcm* m) {
@@ -364,7 +367,7 @@ static int bcm_device_ok(const ibm_bcm* m) {
     return IBM_OK;
 }
 
-int ibm_bcm_exchange(const ibm_bcm* m, double* data_dev, void* stream) {
+int ibm_bcm_exchange(const ibm_bcm* m, double* data_dev, void* stream) try {
     if (!m || !data_dev) {
         set_error("ibm_bcm_exchange: null argument");
         return IBM_ERR_ARG;
@@ -375,9 +378,9 @@ int ibm_bcm_exchange(const ibm_bcm* m, double* data_dev, void* stream) {
         k_bcm_exchange<<<(int)nb, 256, 0, (hipStream_t)stream>>>(m->nhalo, m->d_dst, m->d_off, m->d_src, data_dev);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_bcm_laplacian(const ibm_bcm* m, const double* x_dev, double* y_dev, void* stream) {
+int ibm_bcm_laplacian(const ibm_bcm* m, const double* x_dev, double* y_dev, void* stream) try {
     if (!m || !x_dev || !y_dev || x_dev == y_dev) {
         set_error("ibm_bcm_laplacian: null or aliased argument");
         return IBM_ERR_ARG;
@@ -390,9 +393,9 @@ int ibm_bcm_laplacian(const ibm_bcm* m, const double* x_dev, double* y_dev, void
                                                              y_dev);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_bcm_sor(const ibm_bcm* m, const double* b_dev, double* x_dev, double omega, int32_t sweeps, void* stream) {
+int ibm_bcm_sor(const ibm_bcm* m, const double* b_dev, double* x_dev, double omega, int32_t sweeps, void* stream) try {
     if (!m || !b_dev || !x_dev || b_dev == x_dev || sweeps < 0 || !(omega > 0.0 && omega < 2.0)) {
         set_error("ibm_bcm_sor: need distinct b and x, sweeps >= 0, 0 < omega < 2");
         return IBM_ERR_ARG;
@@ -408,6 +411,6 @@ int ibm_bcm_sor(const ibm_bcm* m, const double* b_dev, double* x_dev, double ome
         }
     IBM_HIP(hipGetLastError());
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 }  // extern "C"

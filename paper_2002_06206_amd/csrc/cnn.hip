@@ -1459,16 +1459,29 @@ int check_grid(const ibm_cnn* n, long long cells) {
 
 // geometry input of the context (and, for training networks, the stored gate the
 // training kernels use; the solver path computes the gate on the fly)
+// Block partials of the combine epilogue for the context's grid: two sums per block of
+// the marching launch.  Grow-only; sized by ibm_ctx_set_preconditioner (set-up), and by
+// the stand-alone network calls, never inside a solve.
+int size_partials(ibm_cnn* n, const Geo& g, hipStream_t s) {
+    const long long need = 2LL * mconv_blocks(g.nx, g.ny, g.nz, mconv_planes(g.nx, g.ny, g.nz));
+    if (n->cpart_n >= need) return IBM_OK;
+    IBM_HIP(hipStreamSynchronize(s));
+    if (n->cpart) IBM_HIP(hipFree(n->cpart));
+    n->cpart = nullptr;
+    n->cpart_n = 0;
+    IBM_HIP(ibm::dev_malloc((void**)&n->cpart, need * sizeof(double)));
+    n->cpart_n = need;
+    return IBM_OK;
+}
+
+// Geometry channel (and, for a trainable network, its gate) of the context's grid.
+// Allocates nothing: the partials must already be sized for this grid.
 int prepare_geometry(ibm_cnn* n, ibm_ctx* c, hipStream_t s) {
     const Geo& g = c->geo;
     const long long need = 2LL * mconv_blocks(g.nx, g.ny, g.nz, mconv_planes(g.nx, g.ny, g.nz));
     if (n->cpart_n < need) {
-        IBM_HIP(hipStreamSynchronize(s));
-        if (n->cpart) IBM_HIP(hipFree(n->cpart));
-        n->cpart = nullptr;
-        n->cpart_n = 0;
-        IBM_HIP(hipMalloc((void**)&n->cpart, need * sizeof(double)));
-        n->cpart_n = need;
+        set_error("cnn: network not prepared for this grid (attach it with ibm_ctx_set_preconditioner)");
+        return IBM_ERR_ARG;
     }
     k_geom<<<2048, 256, 0, s>>>(c->N, c->pcode, n->xg);
     IBM_HIP(hipGetLastError());
@@ -1490,7 +1503,8 @@ int loss_forward(ibm_cnn* n, ibm_ctx* c, const double* b, const double* p, hipSt
     const Geo& g = c->geo;
     const long long N = c->N;
     const int nred = 1024;
-    int rc = prepare_geometry(n, c, s);
+    int rc = size_partials(n, g, s);
+    if (!rc) rc = prepare_geometry(n, c, s);
     if (rc) return rc;
     k_neg<<<2048, 256, 0, s>>>(N, b, n->f);
     k_sumsq<double><<<nred, NT, 0, s>>>(N, n->f, n->part);
@@ -1602,7 +1616,7 @@ int net_check(const ibm_cnn* n) {
 
 extern "C" {
 
-int ibm_cnn_create(int64_t max_cells, int32_t flags, ibm_cnn** out) {
+int ibm_cnn_create(int64_t max_cells, int32_t flags, ibm_cnn** out) try {
     if (!out || max_cells <= 0 || (flags & ~IBM_CNN_INFERENCE_ONLY)) {
         set_error("ibm_cnn_create: bad arguments");
         return IBM_ERR_ARG;
@@ -1625,7 +1639,7 @@ int ibm_cnn_create(int64_t max_cells, int32_t flags, ibm_cnn** out) {
     const size_t cap = (size_t)max_cells;
     bool ok = true;
     auto alloc = [&](void** p, size_t bytes) {
-        if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false;
+        if (ok && ibm::dev_malloc(p, bytes) != hipSuccess) ok = false;
     };
     alloc((void**)&n->w, NWTS * sizeof(float));
     alloc((void**)&n->m, NWTS * sizeof(float));
@@ -1649,7 +1663,7 @@ int ibm_cnn_create(int64_t max_cells, int32_t flags, ibm_cnn** out) {
         alloc((void**)&n->q, cap * sizeof(double));
         alloc((void**)&n->f, cap * sizeof(double));
     }
-    if (ok && hipHostMalloc((void**)&n->h_scal, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) ok = false;
+    if (ok && ibm::host_malloc(&n->h_scal, 8 * sizeof(double)) != hipSuccess) ok = false;
     if (!ok) {
         net_free(n);
         set_error("ibm_cnn_create: device allocation failed");
@@ -1666,16 +1680,16 @@ int ibm_cnn_create(int64_t max_cells, int32_t flags, ibm_cnn** out) {
     }
     *out = n;
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_cnn_destroy(ibm_cnn* net) {
+int ibm_cnn_destroy(ibm_cnn* net) try {
     if (!net) return IBM_OK;
     (void)hipDeviceSynchronize();
     net_free(net);
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_cnn_set_weights(ibm_cnn* net, const float* w_host, int64_t n) {
+int ibm_cnn_set_weights(ibm_cnn* net, const float* w_host, int64_t n) try {
     int rc = net_check(net);
     if (rc) return rc;
     if (!w_host || n != NWTS) {
@@ -1690,9 +1704,9 @@ int ibm_cnn_set_weights(ibm_cnn* net, const float* w_host, int64_t n) {
     if (rc) return rc;
     IBM_HIP(hipDeviceSynchronize());
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_cnn_get_weights(ibm_cnn* net, float* w_host, int64_t n) {
+int ibm_cnn_get_weights(ibm_cnn* net, float* w_host, int64_t n) try {
     int rc = net_check(net);
     if (rc) return rc;
     if (!w_host || n != NWTS) {
@@ -1702,10 +1716,10 @@ int ibm_cnn_get_weights(ibm_cnn* net, float* w_host, int64_t n) {
     IBM_HIP(hipDeviceSynchronize());
     IBM_HIP(hipMemcpy(w_host, net->w, NWTS * sizeof(float), hipMemcpyDeviceToHost));
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t nx, int32_t ny, int32_t nz,
-                    void* stream) {
+                    void* stream) try {
     int rc = net_check(net);
     if (rc) return rc;
     if (!x_dev || !y_dev || nx <= 0 || ny <= 0 || nz <= 0) {
@@ -1725,9 +1739,9 @@ int ibm_cnn_forward(ibm_cnn* net, const uint16_t* x_dev, float* y_dev, int32_t n
     }
     IBM_HIP(hipMemcpyAsync(y_dev, net->out, cells * sizeof(float), hipMemcpyDeviceToDevice, s));
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx_dev, void* stream) {
+int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx_dev, void* stream) try {
     int rc = net_check(net);
     if (rc) return rc;
     if ((rc = need_training(net, "ibm_cnn_backward"))) return rc;
@@ -1746,10 +1760,10 @@ int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx
     if ((rc = net_backward(net, dx_dev, s))) return rc;
     IBM_HIP(hipMemcpyAsync(dw_dev, net->dw, NWTS * sizeof(float), hipMemcpyDeviceToDevice, s));
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, double* loss_out,
-                 float* dw_dev, void* stream) {
+                 float* dw_dev, void* stream) try {
     int rc = net_check(net);
     if (rc) return rc;
     if ((rc = need_training(net, "ibm_cnn_loss"))) return rc;
@@ -1768,10 +1782,10 @@ int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* 
     IBM_HIP(hipStreamSynchronize(s));
     if (loss_out) *loss_out = net->h_scal[3];
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, float lr,
-                       double* loss_out, void* stream) {
+                       double* loss_out, void* stream) try {
     int rc = net_check(net);
     if (rc) return rc;
     if ((rc = need_training(net, "ibm_cnn_train_step"))) return rc;
@@ -1791,9 +1805,9 @@ int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const do
     IBM_HIP(hipStreamSynchronize(s));
     if (loss_out) *loss_out = net->h_scal[3];
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
-int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, void* stream) {
+int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, void* stream) try {
     int rc = net_check(net);
     if (rc) return rc;
     if (!ctx || !ctx->stencil_ready || !r_dev || !z_dev) {
@@ -1803,14 +1817,15 @@ int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* 
     if ((rc = check_grid(net, ctx->N))) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int nred = 1024;
+    if ((rc = size_partials(net, ctx->geo, s))) return rc;
     if ((rc = prepare_geometry(net, ctx, s))) return rc;
     k_sumsq<float><<<nred, NT, 0, s>>>(ctx->N, r_dev, net->part);
     IBM_HIP(hipGetLastError());
     // partial slot 0 of net->part holds <r,r>; <z,r> goes to slot 1
     return cnn_precondition_solver(net, ctx, r_dev, nullptr, z_dev, net->part, nred, 0, 1, -1, nullptr, 0, 0, s);
-}
+} IBM_CATCH_ALL
 
-int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net) {
+int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net) try {
     if (!ctx) {
         set_error("ibm_ctx_set_preconditioner: null context");
         return IBM_ERR_ARG;
@@ -1822,9 +1837,11 @@ int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net) {
             set_error("ibm_ctx_set_preconditioner: network workspace smaller than the grid");
             return IBM_ERR_ARG;
         }
+        // set-up: size the network's partials for this grid so the solves never allocate
+        if ((rc = size_partials(net, ctx->geo, nullptr))) return rc;
     }
     ctx->cnn = net;
     return IBM_OK;
-}
+} IBM_CATCH_ALL
 
 }  // extern "C"

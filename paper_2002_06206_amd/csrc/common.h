@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 
 #include "ibm.h"
@@ -358,6 +360,38 @@ void cn_release(ibm_ctx* c);
 int shepard_run(ibm_ctx* c, const double* tri, long long ntri, const double* p, int filter, double* side,
                 double* force, hipStream_t s);
 void shepard_release(ibm_ctx* c);
+// Every device and pinned-host allocation of the library goes through these (the
+// count is reported by ibm_alloc_count, so a caller can check that a call allocated
+// nothing).
+void count_alloc();
+template <class P>
+inline hipError_t dev_malloc(P** p, size_t bytes) {
+    const hipError_t e = hipMalloc((void**)p, bytes);
+    if (e == hipSuccess) count_alloc();
+    return e;
+}
+template <class P>
+inline hipError_t dev_malloc_async(P** p, size_t bytes, hipStream_t s) {
+    const hipError_t e = hipMallocAsync((void**)p, bytes, s);
+    if (e == hipSuccess) count_alloc();
+    return e;
+}
+template <class P>
+inline hipError_t host_malloc(P** p, size_t bytes) {
+    const hipError_t e = hipHostMalloc((void**)p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) count_alloc();
+    return e;
+}
+
+// Every C entry point is a function-try-block closed by IBM_CATCH_ALL, so no C++
+// exception (a failed host allocation inside a container, ...) crosses the C ABI:
+// std::bad_alloc becomes IBM_ERR_OOM, anything else IBM_ERR_ARG, with a message.
+int abi_exception(bool oom, const char* what);
+#define IBM_CATCH_ALL                                                                 \
+    catch (const std::bad_alloc& e) { return ibm::abi_exception(true, e.what()); }     \
+    catch (const std::exception& e) { return ibm::abi_exception(false, e.what()); }    \
+    catch (...) { return ibm::abi_exception(false, "unknown exception"); }
+
 int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
                double* out, hipStream_t s);
 }  // namespace ibm

@@ -601,10 +601,10 @@ int cn_prepare(ibm_ctx* c) {
     const size_t ts = c->precision == IBM_FP64 ? sizeof(double) : sizeof(float);
     const size_t bytes = ts * 18 * (size_t)c->N;
     // all or nothing: a partly allocated workspace would pass the readiness check
-    if (hipMalloc(&c->cn_ws, bytes) != hipSuccess ||
-        hipMalloc((void**)&c->cn_part, sizeof(double) * CS_SLOTS * MAX_BLOCKS) != hipSuccess ||
-        hipMalloc((void**)&c->cn_state, sizeof(CnState)) != hipSuccess ||
-        hipHostMalloc((void**)&c->h_cn_state, sizeof(CnState), hipHostMallocDefault) != hipSuccess) {
+    if (ibm::dev_malloc(&c->cn_ws, bytes) != hipSuccess ||
+        ibm::dev_malloc((void**)&c->cn_part, sizeof(double) * CS_SLOTS * MAX_BLOCKS) != hipSuccess ||
+        ibm::dev_malloc((void**)&c->cn_state, sizeof(CnState)) != hipSuccess ||
+        ibm::host_malloc(&c->h_cn_state, sizeof(CnState)) != hipSuccess) {
         (void)hipGetLastError();
         cn_release(c);
         set_error("Crank-Nicolson workspace: out of memory");

@@ -249,7 +249,7 @@ static int grow(P** buf, long long* cap, long long need) {
     if (*buf) (void)hipFree(*buf);
     *buf = nullptr;
     *cap = 0;
-    if (hipMalloc((void**)buf, sizeof(P) * (size_t)(need > 1 ? need : 1)) != hipSuccess) {
+    if (ibm::dev_malloc((void**)buf, sizeof(P) * (size_t)(need > 1 ? need : 1)) != hipSuccess) {
         (void)hipGetLastError();
         *buf = nullptr;
         set_error("near-field force: out of device memory for the triangle bins");

@@ -320,7 +320,7 @@ int scan_exclusive(const T* in, T* out, long long n, hipStream_t s) {
     void* tmp = nullptr;
     size_t bytes = 0;
     IBM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, (int)n, s));
-    IBM_HIP(hipMallocAsync(&tmp, bytes, s));
+    IBM_HIP(ibm::dev_malloc_async(&tmp, bytes, s));
     IBM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, (int)n, s));
     IBM_HIP(hipFreeAsync(tmp, s));
     return IBM_OK;
@@ -329,7 +329,7 @@ int scan_exclusive(const T* in, T* out, long long n, hipStream_t s) {
 int grow(void** p, size_t bytes) {
     if (*p) IBM_HIP(hipFree(*p));
     *p = nullptr;
-    hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);
+    hipError_t e = ibm::dev_malloc(p, bytes < 256 ? 256 : bytes);
     if (e != hipSuccess) {
         set_error("device allocation failed in ibm_build_stencils");
         return IBM_ERR_OOM;
@@ -355,7 +355,7 @@ int stencil_run(ibm_ctx* c, const uint8_t* blocked, const double* theta, int dea
         size_t bytes = 0;
         hipcub::TransformInputIterator<uint32_t, PopcountOp, const uint8_t*> it(c->mask, PopcountOp());
         IBM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, it, c->cut_off, (int)N, s));
-        IBM_HIP(hipMallocAsync(&tmp, bytes, s));
+        IBM_HIP(ibm::dev_malloc_async(&tmp, bytes, s));
         IBM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, bytes, it, c->cut_off, (int)N, s));
         IBM_HIP(hipFreeAsync(tmp, s));
     }
@@ -438,9 +438,9 @@ int stencil_run(ibm_ctx* c, const uint8_t* blocked, const double* theta, int dea
             c->comp_cap = ncomp + 1;
         }
         int32_t *cells_in = nullptr, *keys_in = nullptr, *keys_out = nullptr;
-        IBM_HIP(hipMallocAsync((void**)&cells_in, sizeof(int32_t) * nenc, s));
-        IBM_HIP(hipMallocAsync((void**)&keys_in, sizeof(int32_t) * nenc, s));
-        IBM_HIP(hipMallocAsync((void**)&keys_out, sizeof(int32_t) * nenc, s));
+        IBM_HIP(ibm::dev_malloc_async((void**)&cells_in, sizeof(int32_t) * nenc, s));
+        IBM_HIP(ibm::dev_malloc_async((void**)&keys_in, sizeof(int32_t) * nenc, s));
+        IBM_HIP(ibm::dev_malloc_async((void**)&keys_out, sizeof(int32_t) * nenc, s));
         k_compact<<<4096, 256, 0, s>>>(N, is_enc, enc_pos, c->label, root_pos, cells_in, keys_in);
         IBM_HIP(hipGetLastError());
         void* tmp = nullptr;
@@ -449,7 +449,7 @@ int stencil_run(ibm_ctx* c, const uint8_t* blocked, const double* theta, int dea
         while ((1ll << endbit) < (long long)ncomp + 1 && endbit < 32) ++endbit;
         IBM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, keys_in, keys_out, cells_in, c->enc_cells,
                                                    (int)nenc, 0, endbit, s));
-        IBM_HIP(hipMallocAsync(&tmp, bytes, s));
+        IBM_HIP(ibm::dev_malloc_async(&tmp, bytes, s));
         IBM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, bytes, keys_in, keys_out, cells_in, c->enc_cells,
                                                    (int)nenc, 0, endbit, s));
         k_comp_start<<<4096, 256, 0, s>>>(nenc, keys_out, c->comp_start, ncomp);

@@ -366,15 +366,15 @@ int tag_run(ibm_ctx* c, const double* tri, long long ntri, hipStream_t s) {
     int* bad = nullptr;
     void* tmp = nullptr;
     size_t tmp_bytes = 0;
-    IBM_HIP(hipMallocAsync((void**)&cnt, sizeof(unsigned long long) * (ntk + 1), s));
-    IBM_HIP(hipMallocAsync((void**)&off, sizeof(unsigned long long) * (ntk + 1), s));
-    IBM_HIP(hipMallocAsync((void**)&bad, sizeof(int), s));
+    IBM_HIP(ibm::dev_malloc_async((void**)&cnt, sizeof(unsigned long long) * (ntk + 1), s));
+    IBM_HIP(ibm::dev_malloc_async((void**)&off, sizeof(unsigned long long) * (ntk + 1), s));
+    IBM_HIP(ibm::dev_malloc_async((void**)&bad, sizeof(int), s));
     k_fill_i32<<<1, 1, 0, s>>>(bad, 1, 0);
     // cnt[ntk] = 0, so the exclusive scan over ntk+1 entries ends with the total
     k_count<<<(unsigned)((ntk + 1 + 255) / 256), 256, 0, s>>>(a, cnt, bad);
     IBM_HIP(hipGetLastError());
     IBM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, off, (int)(ntk + 1), s));
-    IBM_HIP(hipMallocAsync(&tmp, tmp_bytes, s));
+    IBM_HIP(ibm::dev_malloc_async(&tmp, tmp_bytes, s));
     IBM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, off, (int)(ntk + 1), s));
     unsigned long long total = 0;
     int hbad = 0;

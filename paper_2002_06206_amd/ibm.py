@@ -75,6 +75,7 @@ def _load():
         "ibm_create": ([ctypes.POINTER(Grid), ctypes.POINTER(BC), ctypes.c_int32, ctypes.POINTER(vp)], ctypes.c_int),
         "ibm_destroy": ([vp], ctypes.c_int),
         "ibm_last_error": ([], ctypes.c_char_p),
+        "ibm_alloc_count": ([ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "ibm_tag_geometry": ([vp, vp, ctypes.c_int64, vp, vp, vp], ctypes.c_int),
         "ibm_build_stencils": ([vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.POINTER(ctypes.c_int64), vp],
                                ctypes.c_int),
@@ -125,7 +126,7 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_tag_geometry", "ibm_build_stencils",
+EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_alloc_count", "ibm_tag_geometry", "ibm_build_stencils",
             "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
             "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_shepard_force", "ibm_timing_enable", "ibm_timing_read",
             "ibm_timing_slot", "ibm_set_progress", "ibm_prepare_crank_nicolson", "ibm_momentum_apply",
@@ -172,6 +173,13 @@ def ibm_create(n, dx, origin, bc, u_in=(0.0, 0.0, 0.0), precision=FP64):
     out = ctypes.c_void_p()
     _check(_lib.ibm_create(ctypes.byref(g), ctypes.byref(b), int(precision), ctypes.byref(out)), "ibm_create")
     return out
+
+
+def alloc_count():
+    """Device and pinned-host allocations the library has made in this process."""
+    n = ctypes.c_int64(0)
+    _check(_lib.ibm_alloc_count(ctypes.byref(n)), "ibm_alloc_count")
+    return int(n.value)
 
 
 def ibm_destroy(ctx):
