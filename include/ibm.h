@@ -270,6 +270,18 @@ int ibm_get_rhs(ibm_ctx* ctx, double* out_dev, void* stream);
 int ibm_forces(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const void* nut_dev, double nu,
                const double* wall_dev, double out_host[6], void* stream);
 
+/* For callers that cannot allocate device memory or wait on the host (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the forces of
+ * ibm_forces, same arguments, with the six sums F_p xyz, F_v xyz written to out_dev
+ * (device, 6 doubles) asynchronously on the stream.  The call allocates nothing and does
+ * not synchronise: its block partials live in a 48 KiB array that the library holds on
+ * each GPU for the life of the process (6 sums x 1,024 blocks; the launch is capped at
+ * 1,024 blocks, so every cut count fits).  The sums are bit-identical to ibm_forces'.
+ * All calls on one GPU share that array: calls that overlap on one GPU (different
+ * streams, or different contexts on concurrent streams) race; serialise them. */
+int ibm_forces_noalloc(ibm_ctx* ctx, void* const u_dev[3], const double* p_dev, const void* nut_dev, double nu,
+                       const double* wall_dev, double* out_dev, void* stream);
+
 /* Near-field surface pressure and pressure force by Shepard interpolation (eq. (force)).
  * At every vertex X of a triangle (unit normal n from the right-handed vertex order)
  * the cell-centre pressure is averaged with weights 1/|X - x_k|^2 over the eight cell

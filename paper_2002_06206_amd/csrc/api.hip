@@ -159,6 +159,7 @@ int ibm_create(const ibm_grid* grid, const ibm_bc* bc, int32_t precision, ibm_ct
         hipError_t e2 = ibm::host_malloc(&c->h_red, sizeof(double) * 8);
         if (e1 != hipSuccess || e2 != hipSuccess) rc = hip_fail(e1 != hipSuccess ? e1 : e2, "hipHostMalloc");
     }
+    if (!rc) rc = force_scratch_init(c->device);
     if (!rc) {
         hipError_t e = hipMemset(c->counter, 0, sizeof(unsigned int) * 16);
         if (e == hipSuccess) e = hipMemset(c->solver, 0, sizeof(Solver));
@@ -384,6 +385,15 @@ int ibm_forces(ibm_ctx* c, void* const u[3], const double* p, const void* nut, d
     for (int a = 0; a < 3; ++a)
         if (!u[a]) return bad("ibm_forces: null velocity pointer");
     return forces_run(c, u, p, nut, nu, wall, out, (hipStream_t)stream);
+} IBM_CATCH_ALL
+
+int ibm_forces_noalloc(ibm_ctx* c, void* const u[3], const double* p, const void* nut, double nu,
+                       const double* wall, double* out_dev, void* stream) try {
+    if (int rc = need_stencil(c)) return rc;
+    if (!u || !p || !out_dev) return bad("ibm_forces_noalloc: null argument");
+    for (int a = 0; a < 3; ++a)
+        if (!u[a]) return bad("ibm_forces_noalloc: null velocity pointer");
+    return forces_noalloc_run(c, u, p, nut, nu, wall, out_dev, (hipStream_t)stream);
 } IBM_CATCH_ALL
 
 int ibm_shepard_force(ibm_ctx* c, const double* tri, int64_t ntri, const double* p, int32_t thin_filter,

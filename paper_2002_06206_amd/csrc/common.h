@@ -392,6 +392,9 @@ int abi_exception(bool oom, const char* what);
     catch (const std::exception& e) { return ibm::abi_exception(false, e.what()); }    \
     catch (...) { return ibm::abi_exception(false, "unknown exception"); }
 
+int force_scratch_init(int device);
+int forces_noalloc_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu,
+                       const double* wall, double* out_dev, hipStream_t s);
 int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
                double* out, hipStream_t s);
 }  // namespace ibm

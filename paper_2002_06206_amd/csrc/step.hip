@@ -9,6 +9,8 @@
 // comes from HBM about once.  Cells with a blocked face take the one branch that
 // looks up the cut list (the paper's single 'if' into the dummy-cell data, Sec. 2.3.1).
 
+#include <mutex>
+
 #include "common.h"
 
 namespace ibm {
@@ -426,7 +428,8 @@ template <class T>
 __global__ void __launch_bounds__(NT) k_forces(long long ncut, const int32_t* cell, const uint8_t* dir,
                                                const double* a_ib, const double* a_c, const double* a_o,
                                                const int32_t* opp, C3<T> u, const double* p, const T* nut,
-                                               double nu, double dx, const double* wall, double* partials) {
+                                               double nu, double dx, const double* wall, double* partials,
+                                               int pstride) {
     __shared__ double sh[6 * NT];
     double v[6] = {0, 0, 0, 0, 0, 0};
     const double A = dx * dx;
@@ -450,14 +453,15 @@ __global__ void __launch_bounds__(NT) k_forces(long long ncut, const int32_t* ce
     }
     block_reduce<6>(v, sh);
     if (threadIdx.x == 0)
-        for (int a = 0; a < 6; ++a) partials[a * MAX_BLOCKS + blockIdx.x] = v[a];
+        for (int a = 0; a < 6; ++a) partials[a * pstride + blockIdx.x] = v[a];
 }
 
-__global__ void __launch_bounds__(NT) k_sum6(const double* partials, int nparts, double* out) {
+// sum a (0..5) of the block partials (stride pstride between sums) in block order
+__global__ void __launch_bounds__(NT) k_sum6(const double* partials, int nparts, int pstride, double* out) {
     __shared__ double sh[6 * NT];
     double v[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nparts; b += NT)
-        for (int a = 0; a < 6; ++a) v[a] += partials[a * MAX_BLOCKS + b];
+        for (int a = 0; a < 6; ++a) v[a] += partials[a * pstride + b];
     block_reduce<6>(v, sh);
     if (threadIdx.x == 0)
         for (int a = 0; a < 6; ++a) out[a] = v[a];
@@ -552,6 +556,22 @@ int init_t(ibm_ctx* c, void** u, double** U, double* p, void** h, const double* 
     return IBM_OK;
 }
 
+// blocks of the force reduction: one cut per thread, at most FORCE_BLOCKS blocks
+constexpr int FORCE_BLOCKS = 1024;
+inline int force_blocks(long long ncut) {
+    const long long nbk = (ncut + NT - 1) / NT;
+    return (int)(nbk < FORCE_BLOCKS ? nbk : FORCE_BLOCKS);
+}
+
+// Block partials of the allocation-free force entry point (ibm_forces_noalloc): six
+// sums x FORCE_BLOCKS blocks, 48 KiB per GPU for the life of the process.  Host code
+// never uses this name as an address: force_scratch_init stores each device's own
+// address of the array (hipGetSymbolAddress) and the launches take that pointer.
+static __device__ __align__(256) double scratch[6 * FORCE_BLOCKS];
+constexpr int SCRATCH_DEVICES = 64;
+static double* g_scratch_ptr[SCRATCH_DEVICES];
+static std::mutex g_scratch_mu;
+
 template <class T>
 int forces_t(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu, const double* wall,
              double* out, hipStream_t s) {
@@ -561,11 +581,10 @@ int forces_t(ibm_ctx* c, void* const* u, const double* p, const void* nut, doubl
         for (int a = 0; a < 6; ++a) out[a] = 0.0;
         return IBM_OK;
     }
-    long long nbk = (c->ncut + NT - 1) / NT;
-    int nb = (int)(nbk < 1024 ? nbk : 1024);
+    const int nb = force_blocks(c->ncut);
     k_forces<T><<<nb, NT, 0, s>>>(c->ncut, c->cut_cell, c->cut_dir, c->a_ib, c->a_c, c->a_o, c->cut_opp, uu, p, nt,
-                                  nu, c->geo.dx, wall, c->partials);
-    k_sum6<<<1, NT, 0, s>>>(c->partials, nb, c->red);
+                                  nu, c->geo.dx, wall, c->partials, MAX_BLOCKS);
+    k_sum6<<<1, NT, 0, s>>>(c->partials, nb, MAX_BLOCKS, c->red);
     IBM_HIP(hipGetLastError());
     IBM_HIP(hipMemcpyAsync(c->h_red, c->red, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
     IBM_HIP(hipStreamSynchronize(s));
@@ -629,6 +648,57 @@ int forces_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, dou
                double* out, hipStream_t s) {
     return c->precision == IBM_FP64 ? forces_t<double>(c, u, p, nut, nu, wall, out, s)
                                     : forces_t<float>(c, u, p, nut, nu, wall, out, s);
+}
+
+// Resolves the current device's address of the force scratch array, once per device
+// (called by ibm_create with the context's device current).
+int force_scratch_init(int device) {
+    if (device < 0 || device >= SCRATCH_DEVICES) {
+        set_error("force scratch: device index beyond the supported range");
+        return IBM_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return IBM_OK;
+    void* ptr = nullptr;
+    IBM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+    return IBM_OK;
+}
+
+// ibm_forces with the block partials in the per-device scratch array and the six sums
+// left on the device (out_dev); no allocation, no host synchronisation.  Same launch
+// shape and summation order as forces_t, so the sums are bit-identical.
+template <class T>
+static int forces_noalloc_t(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu,
+                            const double* wall, double* out_dev, hipStream_t s) {
+    double* part = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        part = g_scratch_ptr[c->device];
+    }
+    if (!part) {
+        set_error("ibm_forces_noalloc: force scratch not resolved for this device");
+        return IBM_ERR_ARG;
+    }
+    C3<T> uu{{(const T*)u[0], (const T*)u[1], (const T*)u[2]}};
+    const T* nt = nut ? (const T*)nut : (c->nut_valid ? (const T*)c->nut : nullptr);
+    const int nb = force_blocks(c->ncut);
+    if (nb > FORCE_BLOCKS) {
+        set_error("ibm_forces_noalloc: more block partials than the scratch array holds");
+        return IBM_ERR_ARG;
+    }
+    if (nb > 0)
+        k_forces<T><<<nb, NT, 0, s>>>(c->ncut, c->cut_cell, c->cut_dir, c->a_ib, c->a_c, c->a_o, c->cut_opp, uu, p,
+                                      nt, nu, c->geo.dx, wall, part, FORCE_BLOCKS);
+    k_sum6<<<1, NT, 0, s>>>(part, nb, FORCE_BLOCKS, out_dev);   // nb = 0 writes zeros
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int forces_noalloc_run(ibm_ctx* c, void* const* u, const double* p, const void* nut, double nu,
+                       const double* wall, double* out_dev, hipStream_t s) {
+    return c->precision == IBM_FP64 ? forces_noalloc_t<double>(c, u, p, nut, nu, wall, out_dev, s)
+                                    : forces_noalloc_t<float>(c, u, p, nut, nu, wall, out_dev, s);
 }
 
 int copy_cells(ibm_ctx* c, const void* src, void* dst, bool is_double, hipStream_t s) {

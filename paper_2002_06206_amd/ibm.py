@@ -88,6 +88,7 @@ def _load():
         "ibm_get_nut": ([vp, vp, vp], ctypes.c_int),
         "ibm_get_rhs": ([vp, vp, vp], ctypes.c_int),
         "ibm_forces": ([vp, P3, vp, vp, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
+        "ibm_forces_noalloc": ([vp, P3, vp, vp, ctypes.c_double, vp, vp, vp], ctypes.c_int),
         "ibm_shepard_force": ([vp, vp, ctypes.c_int64, vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_double), vp],
                               ctypes.c_int),
         "ibm_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
@@ -128,7 +129,7 @@ def _load():
 _lib = _load()
 EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_alloc_count", "ibm_tag_geometry", "ibm_build_stencils",
             "ibm_cut_points", "ibm_init_state", "ibm_step", "ibm_poisson_solve", "ibm_apply_laplacian",
-            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_shepard_force", "ibm_timing_enable", "ibm_timing_read",
+            "ibm_get_nut", "ibm_get_rhs", "ibm_forces", "ibm_forces_noalloc", "ibm_shepard_force", "ibm_timing_enable", "ibm_timing_read",
             "ibm_timing_slot", "ibm_set_progress", "ibm_prepare_crank_nicolson", "ibm_momentum_apply",
             "ibm_momentum_solve",
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
@@ -238,6 +239,13 @@ def ibm_forces(ctx, u, p, nu, nut=None, wall=None):
     out = (ctypes.c_double * 6)()
     _check(_lib.ibm_forces(ctx, _p3(u), _ptr(p), _ptr(nut), float(nu), _ptr(wall), out, _stream()), "ibm_forces")
     return list(out[:3]), list(out[3:])
+
+
+def ibm_forces_noalloc(ctx, u, p, nu, out, nut=None, wall=None):
+    """ibm_forces without allocation or host wait: the six sums (F_p xyz, F_v xyz) go to
+    the device tensor out (6 doubles) on the current stream."""
+    return _check(_lib.ibm_forces_noalloc(ctx, _p3(u), _ptr(p), _ptr(nut), float(nu), _ptr(wall), _ptr(out),
+                                          _stream()), "ibm_forces_noalloc")
 
 
 def ibm_shepard_force(ctx, tri, p, side=None, thin_filter=False):
