@@ -97,14 +97,18 @@ def committed_traffic(kernel, wl):
     return None
 
 
-def cpu_baseline(case, gpu_iters_per_step, n_pcg=3):
-    """The FP64 oracle on a bounded sample of the same workload: one time step with
-    eddy viscosity, predictor, face velocity + right-hand side and projection timed
-    in full, and `n_pcg` conjugate-gradient iterations timed and scaled to the
-    iterations per step the GPU solve needed (same algorithm)."""
+CPU_PCG_ITERS = 50
+
+
+def cpu_worker(workload_name, n_pcg):
+    """One oracle process (one thread) on the workload: set-up untimed, then one FP64
+    time step's eddy viscosity, predictor, face velocity + right-hand side and
+    projection timed in full, and n_pcg conjugate-gradient iterations of its pressure
+    solve timed.  Prints one JSON line."""
     import numpy as np
 
     from oracle import flow, tagging
+    case = workload(workload_name)
     g = flow.Grid(case.n, case.dx, case.origin, case.bc, case.u_in)
     b, th = tagging.tag(case.tri, case.n, case.dx, case.origin)
     st = flow.build_stencils(g, b, th, case.deadend)
@@ -119,19 +123,70 @@ def cpu_baseline(case, gpu_iters_per_step, n_pcg=3):
     t2 = time.perf_counter()
     flow.project(st, us, Us, x, case.dt)
     t3 = time.perf_counter()
-    t_fixed = (t1 - t0) + (t3 - t2)
-    t_iter = (t2 - t1) / max(it, 1)
+    print(json.dumps({"t_fixed": (t1 - t0) + (t3 - t2), "t_pcg": t2 - t1, "pcg_iters": int(it),
+                      "cells": g.ncell}), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_samples(workload_name, workers, n_pcg=CPU_PCG_ITERS):
+    """Runs `workers` oracle processes at once, one thread each (the host's cores), each
+    on its own copy of the workload; started before this process touches the GPU.
+    Returns their measurements and the wall time of the whole sample."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, "-c", "import bench; bench.cpu_worker(%r, %d)" % (workload_name, n_pcg)]
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen(cmd, cwd=ROOT, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+             for _ in range(workers)]
+    res = []
+    for pr in procs:
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            raise SystemExit("cpu baseline worker failed (rc %d): %s" % (pr.returncode, err[-2000:]))
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    return res, time.perf_counter() - t0
+
+
+def cpu_baseline(case, samples, wall_s, gpu_iters_per_step):
+    """The oracle on all host cores: P concurrent single-thread oracle processes, each
+    solving its own copy of the same workload (independent problems, so the job's
+    throughput is P cells x steps over the time of one step).  Per process, the
+    non-solver parts of a step are measured in full and CPU_PCG_ITERS conjugate-gradient
+    iterations are measured; the remaining iterations of the step (the GPU plain solve's
+    count per step, same algorithm and stopping rule) are extrapolated at the measured
+    rate.  The slowest process sets the step time."""
+    P = len(samples)
+    N = samples[0]["cells"]
+    t_fixed = max(r["t_fixed"] for r in samples)
+    t_iter = max(r["t_pcg"] / max(r["pcg_iters"], 1) for r in samples)
     t_step = t_fixed + gpu_iters_per_step * t_iter
+    one = samples[0]
+    t_one = one["t_fixed"] + gpu_iters_per_step * one["t_pcg"] / max(one["pcg_iters"], 1)
     return {
-        "value": float(g.ncell / t_step),
+        "value": float(P * N / t_step),
         "unit": "cell-steps/s",
-        "cores": 1,
+        "cores": P,
         "kind": "oracle",
-        "sample": ("one FP64 oracle step on the same %dx%dx%d workload: eddy viscosity, predictor, face "
-                   "velocity/RHS and projection timed in full (%.1f s); %d PCG iterations timed (%.2f s each) "
-                   "and scaled to the %.1f iterations per step of the GPU solve (numpy, single thread)"
-                   % (case.n[0], case.n[1], case.n[2], t_fixed, it, t_iter, gpu_iters_per_step)),
-        "seconds_measured": round(t3 - t0, 2),
+        "sample": ("%d concurrent 1-thread numpy oracle processes, one %dx%dx%d step each: CSM, predictor, RHS, "
+                   "projection measured (%.1f s); %d PCG iterations measured (%.2f s each), the other %.0f of the "
+                   "step extrapolated" % (P, case.n[0], case.n[1], case.n[2], t_fixed, samples[0]["pcg_iters"],
+                                          t_iter, max(gpu_iters_per_step - samples[0]["pcg_iters"], 0))),
+        "host_cpus": os.cpu_count(),
+        "cpu_model": cpu_model(),
+        "threads_per_process": 1,
+        "single_process_value": float(N / t_one),
+        "measured_pcg_iters": samples[0]["pcg_iters"],
+        "extrapolated_pcg_iters": max(gpu_iters_per_step - samples[0]["pcg_iters"], 0.0),
+        "sample_wall_s": round(wall_s, 1),
     }
 
 
@@ -538,6 +593,45 @@ def train_network(args, ibm, torch):
     return w, info
 
 
+def probe(ibm, torch, n=384, reps=10):
+    """Practical bandwidth ceilings and the counter calibration kernel.  Two plain
+    streaming kernels of the library on n^3 doubles: the cell copy (ibm_get_rhs, k_copy:
+    8 B read and 8 B written per cell) and the FP64 7-point operator (ibm_apply_laplacian:
+    x and the code byte read, y written; 17 B per cell), each launched on buffers rotated
+    over three pairs (3 x 2 x 432 MiB at n = 384, beyond the 256 MB Infinity Cache) and
+    timed with events on the stream they run on.  Under rocprofv3 --pmc the k_copy
+    dispatches calibrate FETCH_SIZE / WRITE_SIZE against their known 2 x 8 B per cell."""
+    torch.cuda.set_device(0)
+    bc = (ibm.INFLOW, ibm.OUTFLOW) + (ibm.SLIP,) * 4
+    s = ibm.Solver((n, n, n), 1.0, (0.0, 0.0, 0.0), bc, (1.0, 0.0, 0.0))
+    s.build(torch.zeros((n, n, n), dtype=torch.uint8, device="cuda"),
+            torch.full((n, n, n, 6), 2.0, dtype=torch.float64, device="cuda"))
+    bufs = [(torch.randn((n, n, n), dtype=torch.float64, device="cuda"),
+             torch.empty((n, n, n), dtype=torch.float64, device="cuda")) for _ in range(3)]
+    out = {"cells": n ** 3}
+    for name, bytes_per_cell in (("copy", 16), ("laplacian", 17)):
+        def run(k):
+            x, y = bufs[k % 3]
+            if name == "copy":
+                ibm.ibm_get_rhs(s.ctx, y)   # the context's right-hand side buffer into y (values unused)
+            else:
+                ibm.ibm_apply_laplacian(s.ctx, x, y)
+        for k in range(3):
+            run(k)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        stream = torch.cuda.current_stream()
+        ev[0].record(stream)
+        for k in range(reps):
+            run(k)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        us = ev[0].elapsed_time(ev[1]) / reps * 1e3
+        out[name] = {"us_per_launch": round(us, 2), "bytes_per_cell": bytes_per_cell,
+                     "gbs": round(bytes_per_cell * n ** 3 / (us * 1e-6) / 1e9, 1)}
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -561,6 +655,8 @@ def main():
     ap.add_argument("--train-depths", default="0,32",
                     help="Krylov depths of the training pairs, cycled (0: the step's (b, p) itself)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle processes of the CPU baseline (0: min(16, host CPUs))")
     ap.add_argument("--cn-steps", type=int, default=5,
                     help="Crank-Nicolson steps timed after the plain FP64 run (0: none)")
     ap.add_argument("--mom-tol", type=float, default=1e-10, help="Crank-Nicolson momentum solve tolerance")
@@ -570,6 +666,8 @@ def main():
     ap.add_argument("--sor", type=int, default=1, help="time red-black SOR against PCG on one right-hand side")
     ap.add_argument("--bcm", type=int, default=1, help="time the building-cube halo exchange and operator")
     ap.add_argument("--sor-omega", type=float, default=0.0, help="SOR relaxation (0: 2/(1+sin(pi/n)))")
+    ap.add_argument("--probe", action="store_true",
+                    help="only measure the copy and 7-point-operator bandwidth ceilings (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the library and this benchmark run on one GPU only (collectives and sharding are "
@@ -577,12 +675,25 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.probe:
+        import torch
+
+        from paper_2002_06206_amd import ibm
+        print(json.dumps({"probe": probe(ibm, torch)}))
+        return
+    case = workload(args.workload)
+    N = case.n[0] * case.n[1] * case.n[2]
+    # the CPU sample runs first, before this process touches the GPU, on the host's cores
+    # (at most 16: the CPU share of one GPU on the benchmark hosts)
+    cpu_runs = None
+    if not args.no_cpu_baseline and N <= 512 ** 3:
+        workers = args.cpu_workers if args.cpu_workers > 0 else min(16, os.cpu_count() or 1)
+        cpu_runs = cpu_samples(args.workload, workers)
+
     import torch
 
     from paper_2002_06206_amd import ibm
     torch.cuda.set_device(0)
-    case = workload(args.workload)
-    N = case.n[0] * case.n[1] * case.n[2]
 
     # the plain FP64 context and state (~330 B per cell) do not fit one GPU at 1024^3
     plain = run_solver(case, "pcg_fp64", args, ibm, torch) if N <= 512 ** 3 else None
@@ -619,8 +730,8 @@ def main():
                     "avg_launch_us": round(dom["avg_s"] * 1e6, 2), "launches": dom["launches"],
                     "launches_with_work": dom["launches_with_work"], "sweeps_ms": dom["sweeps_ms"]}
     cpu = None
-    if not args.no_cpu_baseline and plain is not None:
-        cpu = cpu_baseline(case, plain["iters_per_step"])
+    if cpu_runs is not None and plain is not None:
+        cpu = cpu_baseline(case, cpu_runs[0], cpu_runs[1], plain["iters_per_step"])
     out = {
         "metric": METRIC,
         "value": head["value"],

@@ -69,3 +69,18 @@ def test_more_than_one_gpu_exits_with_a_message():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_cpu_baseline_runs_concurrent_oracle_processes():
+    """The CPU baseline leg on the small sphere workload: two concurrent one-thread oracle
+    processes, each with its measured step parts; the record states the process count as
+    cores, the host's CPU count and model, and what was measured and extrapolated."""
+    sys.path.insert(0, ROOT)
+    import bench
+    samples, wall = bench.cpu_samples("sphere32", 2, n_pcg=4)
+    assert len(samples) == 2 and all(r["pcg_iters"] == 4 and r["t_fixed"] > 0 for r in samples)
+    case = bench.workload("sphere32")
+    rec = bench.cpu_baseline(case, samples, wall, 40.0)
+    assert rec["cores"] == 2 and rec["kind"] == "oracle" and rec["host_cpus"] == os.cpu_count()
+    assert rec["measured_pcg_iters"] == 4 and rec["extrapolated_pcg_iters"] == 36.0
+    assert rec["value"] > rec["single_process_value"] > 0
