@@ -235,7 +235,9 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
         last = [time.perf_counter()]
 
         def on_poll(iters, rr):
-            if time.perf_counter() - last[0] > 20.0:
+            if rr < 0.0:   # an FP64 residual check of the mixed solve
+                progress("FP64 relative residual %.3e after %d iterations" % (-rr, iters))
+            elif time.perf_counter() - last[0] > 20.0:
                 last[0] = time.perf_counter()
                 progress("solving, %d iterations" % iters)
         cb = ibm.ibm_set_progress(s.ctx, on_poll)
@@ -249,7 +251,7 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     ibm.ibm_timing_read(s.ctx, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, outers, fallbacks = [], [], 0
+    iters, outers, fallbacks, fb_iters = [], [], 0, []
     worst_res = 0.0
     worst_div = 0.0
     forces = None
@@ -261,6 +263,7 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
         iters.append(stats["iters_inner"])
         outers.append(stats["iters_outer"])
         fallbacks += stats["fallback_used"]
+        fb_iters.append(stats["iters_fallback"])
         worst_res = max(worst_res, stats["rel_residual"])
         worst_div = max(worst_div, stats["div_linf"])
         progress("timed step %d: %d iterations" % (step, stats["iters_inner"]))
@@ -283,7 +286,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     Fp, Fv = forces
     out = {"solver": solver, "value": N * args.steps / elapsed, "ms_per_step": elapsed / args.steps * 1e3,
            "iters_per_step": sum(iters) / len(iters), "refinement_sweeps_per_step": sum(outers) / len(outers),
-           "fallbacks": fallbacks, "max_rel_residual": worst_res, "max_div_linf": worst_div,
+           "fallbacks": fallbacks, "fp64_fallback_iters_per_step": sum(fb_iters) / len(fb_iters),
+           "max_rel_residual": worst_res, "max_div_linf": worst_div,
            "setup_s": round(t_setup, 3), "cuts": s.ncut, "dt_last": ctl["dt_prev"],
            "force_last_step": [a + b for a, b in zip(Fp, Fv)],
            "dominant": {"name": name, "kernel": (KERNEL_SYMBOL if precision == ibm.FP64 else KERNEL_SYMBOL_F32)[name],

@@ -84,7 +84,8 @@ typedef struct {
     double stall_factor;     /* mixed kinds: fall back to FP64 PCG when a segment   */
                              /* reduces the FP64 residual by less than this factor  */
     int32_t check_every;     /* iterations enqueued between host convergence polls  */
-    int32_t force_stall;     /* test hook: 1 = treat the first sweep as stalled      */
+    int32_t force_stall;     /* test hook: treat the first sweep as stalled; 1 = fall */
+                             /* back to FP64 PCG, 2 = the retry of inner_restart 0   */
     double omega;            /* IBM_SOLVER_RBSOR: relaxation factor in (0, 2); <= 0: */
                              /* 2 / (1 + sin(pi / n_max)).  Cells are coloured by the */
                              /* parity of i + j + k; a sweep updates colour 0, then 1, */
@@ -92,6 +93,12 @@ typedef struct {
                              /* is tested every check_every sweeps; max_iter counts  */
                              /* sweeps.  Periodic axes need an even cell count       */
                              /* (IBM_ERR_ARG otherwise).                              */
+    int32_t inner_restart;   /* IBM_SOLVER_FCG_JACOBI: 0 = keep the search direction */
+                             /* across residual replacements, and retry a stalled    */
+                             /* segment from a fresh direction (up to 3 times per    */
+                             /* solve) before the FP64 fallback; 1 = start every     */
+                             /* segment from a fresh direction                       */
+    int32_t pad;
 } ibm_solver_opts;
 
 /* One time step: momentum predictor, coherent structure model (Sec. 2.3) when csm_on,
@@ -130,7 +137,7 @@ typedef struct {
 } ibm_step_params;
 
 typedef struct {
-    int32_t iters_inner;     /* CG / FCG iterations                                  */
+    int32_t iters_inner;     /* CG / FCG iterations, FP64 fallback iterations included */
     int32_t iters_outer;     /* FP32 segments between FP64 residual replacements     */
                              /* (0 for plain PCG)                                    */
     int32_t fallback_used;   /* 1 when the FP64 PCG fallback ran                     */
@@ -140,7 +147,7 @@ typedef struct {
     double div_linf;         /* max |div U^{n+1}|                                    */
     double umax;             /* max |U| over all faces after the step (CFL control)  */
     int32_t iters_momentum[3]; /* CN: BiCGStab iterations per component (else 0)     */
-    int32_t pad;
+    int32_t iters_fallback;  /* of iters_inner, the FP64 PCG fallback's iterations    */
 } ibm_stats;
 
 typedef struct ibm_ctx ibm_ctx;
@@ -162,19 +169,31 @@ int ibm_alloc_count(int64_t* count_out);
  * whether the closed segment meets a closed triangle (edges and vertices inclusive;
  * triangles parallel to the segment never block), sets bit d of blocked_dev[c]
  * and bit d^1 of the neighbour, and stores theta = distance from the cell centre to
- * its nearest crossing / dx in [0,1] at theta_dev[6*c + d] (2.0 where open).
+ * its nearest crossing / dx in [0,1] (2.0 where open).
  * theta uses one fixed double formula: the crossing coordinate is the barycentric
  * combination of the vertex coordinates weighted by the double 2-D sub-areas.
+ * bary_eps (in [0, 0.5]; 0 = exact) is the tolerance of the paper's ray / triangle test
+ * (Sec. 2.3.1: adjusting it keeps rays from slipping through gaps between triangles):
+ * a grid line that misses a triangle exactly still meets it when each of the three
+ * double sub-areas, signed by the exact orientation of the projected triangle, is at
+ * least -bary_eps |sum of the sub-areas| (barycentric coordinates >= -bary_eps); the
+ * crossed segment is still decided exactly.  The blocked set grows with bary_eps.
  * Domain and periodic-wrap faces are never tagged.  Coordinates must be finite
  * with magnitude 0 or within [2^-200, 2^200] (IBM_ERR_ARG otherwise).
- * blocked_dev: N bytes.  theta_dev: N*6 doubles, or NULL (the context keeps its own
- * copy either way, for ibm_build_stencils). */
-int ibm_tag_geometry(ibm_ctx* ctx, const double* tri_dev, int64_t ntri, uint8_t* blocked_dev,
+ * blocked_dev: N bytes.  theta_dev: N*6 doubles (theta_dev[6*c + d]) for callers that
+ * want the dense array, or NULL.  The context always keeps the tagging in compact form
+ * for ibm_build_stencils: the blocked bits, a 32-bit offset per cell and one double per
+ * blocked (cell, dir), about 5 B per cell plus 8 B per cut instead of the 48 B per
+ * cell of a dense theta (which at 1024^3 would be 48 GiB).  Tagging runs the line
+ * tests twice (bits, then the compact list); it allocates on the first call and when
+ * the list outgrows its capacity. */
+int ibm_tag_geometry(ibm_ctx* ctx, const double* tri_dev, int64_t ntri, double bary_eps, uint8_t* blocked_dev,
                      double* theta_dev, void* stream);
 
 /* Stencil build (Sec. 2.3.1-2.3.2): from blocked bits and theta (theta_dev NULL = the
- * context's copy from the last ibm_tag_geometry, which the build then releases: 48 B per
- * cell; building again from it needs a new ibm_tag_geometry), applies the dead-end filter of
+ * context's compact tagging from the last ibm_tag_geometry, whose blocked bits
+ * blocked_dev must equal (IBM_ERR_ARG otherwise); the build then releases it, and
+ * building again from it needs a new ibm_tag_geometry), applies the dead-end filter of
  * eq. (deadend_filter) when deadend != 0 (a cell closed in >= 5 directions is closed
  * in all six and frozen at the wall velocity; its open neighbours see a wall at its
  * centre, theta = 1), builds the cut list (one entry per blocked (cell, dir),
@@ -421,7 +440,9 @@ int ibm_bcm_sor(const ibm_bcm* grid, const double* b_dev, double* x_dev, double 
 int ibm_timing_enable(ibm_ctx* ctx, int32_t on);
 /* Progress hook (measurement support): when set, the pressure solve calls
  * fn(user, iterations so far in this solve, current <r,r> of the recursive residual)
- * from the calling thread at each of its host convergence polls.  NULL removes it. */
+ * from the calling thread at each of its host convergence polls, and for the mixed kinds
+ * fn(user, iterations so far, -(relative FP64 residual)) at each FP64 residual check
+ * (a negative third argument).  NULL removes it. */
 typedef void (*ibm_progress_fn)(void* user, int64_t iterations, double rr);
 int ibm_set_progress(ibm_ctx* ctx, ibm_progress_fn fn, void* user);
 int ibm_timing_read(ibm_ctx* ctx, double out[10], int32_t reset);

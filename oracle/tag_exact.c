@@ -24,6 +24,15 @@
  *
  * Domain faces (including periodic wrap faces) are never tagged.
  *
+ * bary_eps (>= 0, at most 0.5): the paper's tuned tolerance of the ray / triangle
+ * test (Sec. 2.3.1: adjusting it keeps rays from slipping through gaps).  With
+ * bary_eps > 0 a grid line also meets the triangle when it misses it by at most
+ * bary_eps in barycentric terms: each plain double sub-triangle area w_m (the theta
+ * weights above), taken with the exact orientation sign of the projected triangle,
+ * is at least -bary_eps |w_a + w_b + w_c|.  The exact test alone decides at 0, so
+ * the blocked set only grows with bary_eps.  The segment that is crossed is still
+ * decided exactly.
+ *
  * Cell index c = i + nx*(j + ny*k).  Direction bits 0..5 = -x,+x,-y,+y,-z,+z.
  * theta layout: theta[6*c + dir], 2.0 where the direction is open.
  */
@@ -256,7 +265,7 @@ static void put_theta(double *theta, int64_t c, int dir, double th)
 
 /* Returns 0 on success, -1 on a non-finite coordinate. */
 int oracle_tag(const double *tri, int64_t ntri, const int32_t *n, double dx, const double *origin,
-               uint8_t *blocked, double *theta)
+               double bary_eps, uint8_t *blocked, double *theta)
 {
     const int64_t nx = n[0], ny = n[1], nz = n[2];
     const int64_t ncell = nx * ny * nz;
@@ -273,6 +282,14 @@ int oracle_tag(const double *tri, int64_t ntri, const int32_t *n, double dx, con
             double umin = fmin(A[u], fmin(B[u], C[u])), umax = fmax(A[u], fmax(B[u], C[u]));
             double vmin = fmin(A[v], fmin(B[v], C[v])), vmax = fmax(A[v], fmax(B[v], C[v]));
             double kmin = fmin(A[k], fmin(B[k], C[k])), kmax = fmax(A[k], fmax(B[k], C[k]));
+            /* the triangle grown by bary_eps in barycentric terms stays inside its bounding
+               box widened by 2 bary_eps times the extent on each side (its corners are
+               a + bary_eps (2a - b - c) and the like) */
+            const double gu = 2.0 * bary_eps * (umax - umin), gv = 2.0 * bary_eps * (vmax - vmin);
+            const double gk = 2.0 * bary_eps * (kmax - kmin);
+            umin -= gu; umax += gu; vmin -= gv; vmax += gv; kmin -= gk; kmax += gk;
+            /* exact orientation of the projected triangle (zero: parallel to the lines) */
+            const int sT = orient2d_sign(A[u], A[v], B[u], B[v], C[u], C[v]);
             /* candidate grid lines: generous bounding box, the exact test decides */
             int64_t j0 = clampi(floor((umin - origin[u]) / dx - 0.5) - 1.0, 0, nn[u]);
             int64_t j1 = clampi(ceil((umax - origin[u]) / dx - 0.5) + 1.0, -1, nn[u] - 1);
@@ -291,7 +308,7 @@ int oracle_tag(const double *tri, int64_t ntri, const int32_t *n, double dx, con
                     int sW;
                     if (sa >= 0 && sb >= 0 && sc >= 0 && (sa + sb + sc) > 0) sW = 1;
                     else if (sa <= 0 && sb <= 0 && sc <= 0 && (sa + sb + sc) < 0) sW = -1;
-                    else continue;
+                    else sW = 0;
                     /* double crossing coordinate, fixed operation order */
                     double dau = A[u] - pu, dav = A[v] - pv;
                     double dbu = B[u] - pu, dbv = B[v] - pv;
@@ -301,6 +318,13 @@ int oracle_tag(const double *tri, int64_t ntri, const int32_t *n, double dx, con
                     double wc = dau * dbv - dav * dbu;
                     double num = (wa * A[k] + wb * B[k]) + wc * C[k];
                     double den = (wa + wb) + wc;
+                    if (sW == 0) {
+                        /* missed exactly: hit within the tolerance only */
+                        if (!(bary_eps > 0.0) || sT == 0) continue;
+                        const double st = (double)sT, lim = -bary_eps * fabs(den);
+                        if (!(wa * st >= lim && wb * st >= lim && wc * st >= lim)) continue;
+                        sW = sT;
+                    }
                     double xs = num / den;
                     for (int64_t i = i0; i <= i1; ++i) {
                         const double xa = centre(origin, dx, k, i), xb = centre(origin, dx, k, i + 1);

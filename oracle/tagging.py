@@ -34,7 +34,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         lib.oracle_tag.argtypes = [dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_double,
-                                   dp, ctypes.POINTER(ctypes.c_uint8), dp]
+                                   dp, ctypes.c_double, ctypes.POINTER(ctypes.c_uint8), dp]
         lib.oracle_tag.restype = ctypes.c_int
         lib.oracle_orient2d_sign.argtypes = [ctypes.c_double] * 6
         lib.oracle_orient2d_sign.restype = ctypes.c_int
@@ -48,8 +48,11 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def tag(tri: np.ndarray, n, dx: float, origin):
-    """Returns (blocked uint8 (nz,ny,nx), theta float64 (nz,ny,nx,6))."""
+def tag(tri: np.ndarray, n, dx: float, origin, bary_eps: float = 0.0):
+    """Returns (blocked uint8 (nz,ny,nx), theta float64 (nz,ny,nx,6)).  bary_eps: the
+    ray test's tolerance in barycentric terms (0 = exact)."""
+    if not (0.0 <= bary_eps <= 0.5):
+        raise ValueError("bary_eps must lie in [0, 0.5]")
     lib = _load()
     tri = np.ascontiguousarray(tri, dtype=np.float64)
     nn = np.asarray(n, dtype=np.int32)
@@ -58,7 +61,8 @@ def tag(tri: np.ndarray, n, dx: float, origin):
     blocked = np.zeros(ncell, dtype=np.uint8)
     theta = np.zeros(ncell * 6, dtype=np.float64)
     rc = lib.oracle_tag(_dp(tri), len(tri), nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(dx),
-                        _dp(org), blocked.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _dp(theta))
+                        _dp(org), float(bary_eps), blocked.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                        _dp(theta))
     if rc != 0:
         raise ValueError("oracle_tag: non-finite coordinate")
     shape = (int(nn[2]), int(nn[1]), int(nn[0]))

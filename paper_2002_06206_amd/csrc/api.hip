@@ -190,7 +190,8 @@ int ibm_destroy(ibm_ctx* c) try {
     free_events(c);
     cn_release(c);
     shepard_release(c);
-    void* ps[] = {c->tagmask, c->theta, c->mask, c->pcode, c->flags, c->label, c->cut_off, c->cut_cell, c->cut_dir,
+    tag_release(c);
+    void* ps[] = {c->mask, c->pcode, c->flags, c->label, c->cut_off, c->cut_cell, c->cut_dir,
                   c->cut_theta, c->a_ib, c->a_c, c->a_o, c->cut_opp, c->enc_cells, c->comp_start,
                   c->ustar[0], c->ustar[1], c->ustar[2], c->nut, c->b, c->bwork, c->r, c->d, c->q, c->zbuf, c->x64,
                   c->r32, c->z32, c->d32, c->q32, c->e32, c->zprev32, c->partials, c->counter, c->solver, c->red};
@@ -201,23 +202,27 @@ int ibm_destroy(ibm_ctx* c) try {
     return IBM_OK;
 } IBM_CATCH_ALL
 
-int ibm_tag_geometry(ibm_ctx* c, const double* tri, int64_t ntri, uint8_t* blocked, double* theta, void* stream) try {
+int ibm_tag_geometry(ibm_ctx* c, const double* tri, int64_t ntri, double bary_eps, uint8_t* blocked, double* theta,
+                     void* stream) try {
     if (!c) return bad("null context");
     if (int rc = check_device(c)) return rc;
     if (ntri < 0 || (ntri > 0 && !tri) || !blocked) return bad("ibm_tag_geometry: bad triangle or output pointer");
     if (ntri > (1ll << 40)) return bad("ibm_tag_geometry: too many triangles");
+    if (!(bary_eps >= 0.0 && bary_eps <= 0.5)) return bad("ibm_tag_geometry: bary_eps must lie in [0, 0.5]");
     hipStream_t s = (hipStream_t)stream;
     const long long N = c->N;
     if (!c->tagmask) {
         if (int rc = dalloc(&c->tagmask, (size_t)((N + 3) / 4) * 4 + 64)) return rc;
     }
-    if (!c->theta) {
-        if (int rc = dalloc(&c->theta, sizeof(double) * 6 * N)) return rc;
+    if (!c->tag_off) {
+        if (int rc = dalloc(&c->tag_off, sizeof(uint32_t) * N)) return rc;
     }
-    int rc = tag_run(c, tri, ntri, s);
+    int rc = tag_run(c, tri, ntri, bary_eps, s);
     if (rc < 0) return rc;
     IBM_HIP(hipMemcpyAsync(blocked, c->tagmask, N, hipMemcpyDeviceToDevice, s));
-    if (theta) IBM_HIP(hipMemcpyAsync(theta, c->theta, sizeof(double) * 6 * N, hipMemcpyDeviceToDevice, s));
+    if (theta) {
+        if ((rc = tag_expand(c, theta, s))) return rc;
+    }
     return rc;
 } IBM_CATCH_ALL
 
@@ -226,31 +231,31 @@ int ibm_build_stencils(ibm_ctx* c, const uint8_t* blocked, const double* theta, 
     if (!c) return bad("null context");
     if (int rc = check_device(c)) return rc;
     if (!blocked) return bad("ibm_build_stencils: null blocked");
-    if (!theta) {
+    hipStream_t s = (hipStream_t)stream;
+    ThetaSrc src{theta, nullptr, nullptr, nullptr};
+    const bool own = theta == nullptr;
+    if (own) {
         if (!c->tagged)
             return bad("ibm_build_stencils: theta is NULL and the context holds no tagging (none ran, or a "
                        "previous build consumed it)");
-        theta = c->theta;
+        bool same = false;
+        if (int rc = tag_matches(c, blocked, &same, s)) return rc;
+        if (!same) return bad("ibm_build_stencils: with theta NULL, blocked must be the context's tagging output");
+        src = ThetaSrc{nullptr, reinterpret_cast<const uint8_t*>(c->tagmask), c->tag_off, c->tag_list};
     }
-    hipStream_t s = (hipStream_t)stream;
     c->stencil_ready = false;
     c->last_iters = 0;
     c->nut_valid = false;
-    const bool own_theta = theta == c->theta;
-    int rc = stencil_run(c, blocked, theta, deadend ? 1 : 0, s);
+    int rc = stencil_run(c, blocked, src, deadend ? 1 : 0, s);
     if (rc) return rc;
     if (flags) IBM_HIP(hipMemcpyAsync(flags, c->flags, sizeof(uint16_t) * c->N, hipMemcpyDeviceToDevice, s));
     if (label) IBM_HIP(hipMemcpyAsync(label, c->label, sizeof(int32_t) * c->N, hipMemcpyDeviceToDevice, s));
     if (n_cut_out) *n_cut_out = c->ncut;
-    if (own_theta) {
-        // the compact cut list now holds what the step needs: release the dense copy
-        // (48 B per cell) and the tagging mask
+    if (own) {
+        // the cut list now holds what the step needs: release the tagging (the blocked
+        // bits, 4 B of offsets per cell and the theta list)
         IBM_HIP(hipStreamSynchronize(s));
-        IBM_HIP(hipFree(c->theta));
-        IBM_HIP(hipFree(c->tagmask));
-        c->theta = nullptr;
-        c->tagmask = nullptr;
-        c->tagged = false;
+        tag_release(c);
     }
     return IBM_OK;
 } IBM_CATCH_ALL

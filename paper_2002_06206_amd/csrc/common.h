@@ -82,8 +82,14 @@ struct ibm_ctx {
     ibm::Geo geo;
     long long N;
     // tagging output kept for the stencil build
-    uint32_t* tagmask;      // padded 4-byte words, one byte per cell
-    double* theta;          // N*6
+    // tagging kept for the stencil build: blocked bits (padded 4-byte words, one byte
+    // per cell) and the compact theta list, one entry per blocked (cell, dir) in cell
+    // then direction order, tag_off[c] = index of cell c's first entry
+    uint32_t* tagmask;
+    uint32_t* tag_off;
+    double* tag_list;
+    long long tag_cap;      // entries tag_list holds
+    long long tag_ncut;     // entries in use
     bool tagged;
     // stencil
     uint8_t* mask;          // effective blocked bits
@@ -302,8 +308,26 @@ __device__ inline void block_reduce(double (&v)[NV], double* sh /* at least 4 * 
 
 // Host-side launchers implemented in the .hip files.
 namespace ibm {
-int tag_run(ibm_ctx* c, const double* tri, long long ntri, hipStream_t s);
-int stencil_run(ibm_ctx* c, const uint8_t* blocked, const double* theta, int deadend, hipStream_t s);
+// theta of the stencil build: a dense cells x 6 array, or the compact list of the
+// context's tagging (2.0 where a direction is open)
+struct ThetaSrc {
+    const double* dense;
+    const uint8_t* mask;
+    const uint32_t* off;
+    const double* list;
+};
+__device__ inline double theta_of(const ThetaSrc& t, long long c, int d) {
+    if (t.dense) return t.dense[6 * c + d];
+    const unsigned m = t.mask[c];
+    if (!((m >> d) & 1u)) return 2.0;
+    return t.list[t.off[c] + (uint32_t)__builtin_popcount(m & ((1u << d) - 1u))];
+}
+
+int tag_run(ibm_ctx* c, const double* tri, long long ntri, double bary_eps, hipStream_t s);
+int tag_expand(ibm_ctx* c, double* theta, hipStream_t s);
+int tag_matches(ibm_ctx* c, const uint8_t* blocked, bool* same, hipStream_t s);
+void tag_release(ibm_ctx* c);
+int stencil_run(ibm_ctx* c, const uint8_t* blocked, const ThetaSrc& theta, int deadend, hipStream_t s);
 int cut_points_run(ibm_ctx* c, double* xyz, hipStream_t s);
 int remove_means(ibm_ctx* c, double* a, hipStream_t s);
 int laplacian_run(ibm_ctx* c, const double* x, double* y, hipStream_t s);

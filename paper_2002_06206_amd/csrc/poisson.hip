@@ -242,7 +242,7 @@ template <class T>
 __global__ void __launch_bounds__(NT) k_pcg_a(Geo g, const uint8_t* __restrict__ pcode, const T* __restrict__ zz,
                                               const T* __restrict__ dold, T* __restrict__ dnew, T* __restrict__ x,
                                               double* __restrict__ partials, int nparts, int it, int final_only,
-                                              int skip_x, Solver* sv) {
+                                              int skip_x, int fresh, Solver* sv) {
     if (stopped_before(sv, it)) return;
     __shared__ double sh[NT];
     const double idx2 = 1.0 / (g.dx * g.dx);
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__(NT) k_pcg_a(Geo g, const uint8_t* __restrict__
             x[c] = (T)((double)x[c] + alpha * (double)dold[c]);
         return;
     }
-    const bool first = it == 0;
+    const bool first = it == 0 || fresh;
     double v[1] = {0.0};
     const int nzc = slab_count(g.nz);
     const long long tiles = (long long)g.ntx * g.nty;
@@ -1065,9 +1065,11 @@ int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hip
 // flag (0 not converged at the cap, 1 converged, 2 trivial, 3 NaN).
 template <class T>
 static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nred, int start_it, int max_iter,
-                   int check_every, int* last_iters, int* done, hipStream_t s) {
+                   int check_every, int* last_iters, int* done, hipStream_t s, bool fresh = false) {
     const Geo& g = c->geo;
     T* dbuf[2] = {d0, d1};
+    // the first pass A of a fresh start takes d = z (no previous direction, no x update)
+    auto first_pass = [&](int it) { return it == 0 || (fresh && it == start_it); };
     auto pass_a = [&](int it) {
         T* dnew = dbuf[it & 1];
         T* dold = dbuf[(it + 1) & 1];
@@ -1075,7 +1077,7 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nre
         const int K = TK_SPMV;
         if constexpr (std::is_same<T, float>::value) {
             if (path == 2) {
-                if (it == 0)
+                if (first_pass(it))
                     launch_timed(c, K, k_pcg_a_f4<true>, nred, s, g, (const uint8_t*)c->pcode, (const float*)z,
                                  (const float*)dold, dnew, x, c->partials, nred, it, 0, c->solver);
                 else
@@ -1085,7 +1087,7 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nre
             }
         }
         if (path == 1) {
-            if (it == 0)
+            if (first_pass(it))
                 launch_timed(c, K, k_pcg_a_v<T, true>, nred, s, g, (const uint8_t*)c->pcode, (const T*)z,
                              (const T*)dold, dnew, x, c->partials, nred, it, 0, c->solver);
             else
@@ -1093,7 +1095,7 @@ static int cg_loop(ibm_ctx* c, T* x, T* r, T* z, T* d0, T* d1, int path, int nre
                              (const T*)dold, dnew, x, c->partials, nred, it, skip, c->solver);
         } else {
             launch_timed(c, K, k_pcg_a<T>, nred, s, g, (const uint8_t*)c->pcode, (const T*)z, (const T*)dold, dnew, x,
-                         c->partials, nred, it, 0, skip, c->solver);
+                         c->partials, nred, it, 0, skip, (fresh && it == start_it) ? 1 : 0, c->solver);
         }
     };
     auto pass_b = [&](int it) {
@@ -1394,7 +1396,7 @@ static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_ev
 // seg(it, &made) runs one segment from global iteration it and returns its flag.
 template <class Seg>
 static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, int nred,
-                        Seg&& seg, hipStream_t s) {
+                        bool can_retry, Seg&& seg, hipStream_t s) {
     const Geo& g = c->geo;
     const long long N = c->N;
     const double delta = (o->inner_tol > 0.0 && o->inner_tol < 1.0) ? o->inner_tol : 0.1;
@@ -1404,6 +1406,11 @@ static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver
     int total_inner = 0, sweeps = 0, it = 0;
     double prev_rel = -1.0;
     bool fallback = false;
+    // a stalled segment is retried from a fresh direction (when the segments keep theirs)
+    // up to max_retries times before the FP64 fallback
+    const int max_retries = 3;
+    int retries = 0;
+    bool fresh = false, last_fresh = false;
     int rc = IBM_OK;
     c->progress_iters = 0;
     k_zero_f32<<<2048, 256, 0, s>>>(N, c->e32);
@@ -1420,14 +1427,22 @@ static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver
             break;
         }
         const double rel = sqrt(rn2 / bn2);
+        if (c->progress) c->progress(c->progress_user, total_inner, -rel);
         if (!(rel == rel) || c->h_solver->converged == 3) {
             fallback = true;
             break;
         }
         if (rel <= o->tol) break;
+        fresh = false;
         if (prev_rel >= 0.0 && (rel * stall > prev_rel || (o->force_stall && sweeps == 1))) {
-            fallback = true;
-            break;
+            // a segment that kept the previous Krylov direction gets one retry from a
+            // fresh one; a fresh segment that stalls (or the test hook) falls back
+            if (!can_retry || last_fresh || retries >= max_retries || o->force_stall == 1) {
+                fallback = true;
+                break;
+            }
+            ++retries;
+            fresh = true;
         }
         if (sweeps >= max_sweeps || total_inner >= o->max_iter) {
             fallback = true;
@@ -1436,7 +1451,8 @@ static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver
         prev_rel = rel;
         int made = 0;
         c->progress_iters = total_inner;
-        int flag = seg(it, &made);
+        int flag = seg(it, fresh, &made);
+        last_fresh = fresh;
         if (flag < 0) return flag;
         total_inner += made;
         it += made;
@@ -1460,6 +1476,7 @@ static int refine_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver
         st->iters_inner = total_inner + fb_iters;
         st->iters_outer = sweeps;
         st->fallback_used = fallback ? 1 : 0;
+        st->iters_fallback = fb_iters;
     }
     return rc;
 }
@@ -1476,10 +1493,10 @@ int mixed_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
     const int nred = quad ? fmarch_blocks(g) : (pair ? vmarch_blocks(g) : march_blocks(g));
     const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : 1000;
     return refine_solve(
-        c, b, x, o, st, nred,
-        [&](int it, int* made) {
+        c, b, x, o, st, nred, o->inner_restart == 0,
+        [&](int it, bool fresh, int* made) {
             return cg_loop<float>(c, c->e32, c->r32, c->z32, c->d32, c->q32, path, nred, it, inner_max,
-                                  o->check_every, &c->last_iters_inner, made, s);
+                                  o->check_every, &c->last_iters_inner, made, s, fresh || o->inner_restart != 0);
         },
         s);
 }
@@ -1505,8 +1522,8 @@ int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts*
     int rc = cnn_prepare_geometry(c->cnn, c, s);
     if (rc) return rc;
     return refine_solve(
-        c, b, x, o, st, nred,
-        [&](int it, int* made) {
+        c, b, x, o, st, nred, false,
+        [&](int it, bool, int* made) {
             return quad ? fcg_segment_fused(c, nred, it, inner_max, o->check_every, made, s)
                         : fcg_segment(c, nred, it, inner_max, o->check_every, made, s);
         },
@@ -1626,6 +1643,7 @@ int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
         rc = pcg64(c, b, x, o->tol, o->max_iter, o->check_every, &iters, s);
         local.iters_outer = 0;
         local.fallback_used = 0;
+        local.iters_fallback = 0;
     } else if (o->kind == IBM_SOLVER_FCG_CNN) {
         rc = cnn_fcg_solve(c, b, x, o, &local, s);
         iters = local.iters_inner;
@@ -1633,6 +1651,7 @@ int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
         rc = rbsor64(c, b, x, o, &iters, s);
         local.iters_outer = 0;
         local.fallback_used = 0;
+        local.iters_fallback = 0;
     } else {
         set_error("unknown solver kind");
         return IBM_ERR_ARG;
@@ -1644,6 +1663,7 @@ int poisson_run(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o
         st->iters_inner = iters;
         st->iters_outer = local.iters_outer;
         st->fallback_used = local.fallback_used;
+        st->iters_fallback = local.iters_fallback;
         st->status = rc;
         int rc3 = true_residual(c, b, x, &st->rel_residual, s);
         if (rc3) return rc3;

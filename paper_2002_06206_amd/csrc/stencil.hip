@@ -64,9 +64,9 @@ __global__ void k_eff_mask(Geo g, const uint8_t* raw, const uint16_t* flags, uin
 // theta seen after the filter: unfiltered cuts keep their theta; a dead cell's new
 // cuts have theta 0; a neighbour's new cut toward a dead cell has theta 1 (the dead
 // cell's centre); when both cells are dead the smaller value, 0, wins.
-__device__ inline double theta_eff(const uint8_t* raw, const uint16_t* flags, const double* theta, long long c,
+__device__ inline double theta_eff(const uint8_t* raw, const uint16_t* flags, const ThetaSrc& theta, long long c,
                                    int d, long long nb) {
-    if ((raw[c] >> d) & 1) return theta[6 * c + d];
+    if ((raw[c] >> d) & 1) return theta_of(theta, c, d);
     if (is_dead(flags, c)) return 0.0;
     (void)nb;
     return 1.0;
@@ -88,7 +88,7 @@ struct CutOut {
 // with q_o the neighbour opposite the cut.  When that opposite face is itself blocked
 // or is a domain face, the image point falls back to the cell centre: q_GC = 2 q_IB - q_c.
 __global__ void k_fill_cuts(Geo g, const uint8_t* raw, const uint8_t* eff, const uint16_t* flags,
-                            const uint32_t* cut_off, const double* theta, CutOut o) {
+                            const uint32_t* cut_off, ThetaSrc theta, CutOut o) {
     long long t0, t1;
     tile_range(g, t0, t1);
     for (long long t = t0; t < t1; ++t) {
@@ -139,7 +139,7 @@ __global__ void k_ncut(const uint32_t* cut_off, const uint8_t* eff, long long N,
 }
 
 // wall-including class: some blocked direction with theta <= 0.5; near bits theta < 0.5
-__global__ void k_class_inc(Geo g, const uint8_t* raw, const uint8_t* eff, const double* theta, uint16_t* flags) {
+__global__ void k_class_inc(Geo g, const uint8_t* raw, const uint8_t* eff, ThetaSrc theta, uint16_t* flags) {
     long long t0, t1;
     tile_range(g, t0, t1);
     for (long long t = t0; t < t1; ++t) {
@@ -339,7 +339,7 @@ int grow(void** p, size_t bytes) {
 
 }  // namespace
 
-int stencil_run(ibm_ctx* c, const uint8_t* blocked, const double* theta, int deadend, hipStream_t s) {
+int stencil_run(ibm_ctx* c, const uint8_t* blocked, const ThetaSrc& theta, int deadend, hipStream_t s) {
     const Geo& g = c->geo;
     const long long N = c->N;
     const int nb = grid_blocks(g);

@@ -73,43 +73,133 @@ __device__ inline double far_value(const Geo& g, const Sten& st, const T* q, int
     return (double)q[nn];
 }
 
+// Work items of the z-marching step kernels: (64 x 4 column tile, z slab) pairs,
+// slab-major, so the XCD chunk map gives every XCD a contiguous run of slabs and the
+// x- and y-neighbour rows of a tile come from that XCD's L2.  The thread owns column
+// (i, j) and walks the slab's planes, carrying the values it needs from the planes
+// below and above in registers: each value comes from HBM once.
+struct ZCol {
+    int i, j, z0, z1;
+    long long col;                // i + nx j
+    long long ow, oe, os, on;     // offsets of the -x, +x, -y, +y neighbours (wrapping)
+    bool bw, be, bs, bn;          // those faces are domain faces
+    bool valid;
+};
+
+__device__ inline ZCol zcol(const Geo& g, long long w) {
+    const long long tiles = (long long)g.ntx * g.nty;
+    const int nzc = slab_count(g.nz);
+    ZCol z;
+    const int zc = (int)(w / tiles);
+    const long long t = w % tiles;
+    z.i = (int)(t % g.ntx) * TX + (int)(threadIdx.x % TX);
+    z.j = (int)(t / g.ntx) * TY + (int)(threadIdx.x / TX);
+    z.z0 = (int)((long long)g.nz * zc / nzc);
+    z.z1 = (int)((long long)g.nz * (zc + 1) / nzc);
+    z.valid = z.i < g.nx && z.j < g.ny;
+    const int i = z.i, j = z.j;
+    const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i == g.nx - 1 ? 0 : i + 1;
+    const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+    z.col = (long long)i + (long long)g.nx * j;
+    z.ow = (long long)iw - i;
+    z.oe = (long long)ie - i;
+    z.os = (long long)g.nx * (js - j);
+    z.on = (long long)g.nx * (jn - j);
+    z.bw = i == 0 && g.bc[0] != IBM_BC_PERIODIC;
+    z.be = i == g.nx - 1 && g.bc[1] != IBM_BC_PERIODIC;
+    z.bs = j == 0 && g.bc[2] != IBM_BC_PERIODIC;
+    z.bn = j == g.ny - 1 && g.bc[3] != IBM_BC_PERIODIC;
+    return z;
+}
+
+// [w0, w1) of this block's items (XCD chunk map)
+__device__ inline void zcol_range(const Geo& g, long long& w0, long long& w1) {
+    const long long items = (long long)g.ntx * g.nty * slab_count(g.nz);
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    w0 = items * ch / nb;
+    w1 = items * (ch + 1) / nb;
+}
+
+inline int zcol_blocks(const Geo& g) {
+    const long long items = (long long)g.ntx * g.nty * slab_count(g.nz);
+    return (int)(items < MAX_BLOCKS ? items : MAX_BLOCKS);
+}
+
+// value of component m seen across face d of cell c: the eq. (q_axis) ghost behind a
+// blocked face, the domain-face ghost at a domain face, else the neighbour's value
+template <class T>
+__device__ inline T nb_value(const Geo& g, const Sten& st, const T* q, int m, long long c, uint8_t msk, int d,
+                             bool bnd, T inner, T qc, const double* wall) {
+    if ((msk >> d) & 1) return (T)ghost(st, q, c, msk, d, m, wall, (double)qc);
+    if (bnd) return (T)bc_ghost(g, d, m, (double)qc);
+    return inner;
+}
+
 // Coherent structure model (Sec. 2.3): G_ij by central differences, S, W, Q, E,
-// F_CS = Q/E, C = C1 |F_CS|^(3/2), nu_t = C dx^2 sqrt(S_ij S_ij).
+// F_CS = Q/E, C = C1 |F_CS|^(3/2), nu_t = C dx^2 sqrt(S_ij S_ij).  z-marching (see ZCol).
 template <class T>
 __global__ void __launch_bounds__(NT) k_csm(Geo g, Sten st, C3<T> u, const double* wall, T* nut, double c1) {
-    long long t0, t1;
-    tile_range(g, t0, t1);
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        uint8_t msk = st.mask[c];
-        T G[3][3];
-        const T inv2dx = (T)(1.0 / (2.0 * g.dx));
+    long long w0, w1;
+    zcol_range(g, w0, w1);
+    const long long plane = (long long)g.nx * g.ny;
+    const T inv2dx = (T)(1.0 / (2.0 * g.dx));
+    for (long long w = w0; w < w1; ++w) {
+        const ZCol zc = zcol(g, w);
+        if (!zc.valid) continue;
+        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
+        T qb[3], qm[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            T nb[6];
-            T qc = u.p[a][c];
-            nbvals<T, T>(g, st, u.p[a], a, i, j, k, c, msk, wall, qc, nb);
-#pragma unroll
-            for (int b = 0; b < 3; ++b) G[a][b] = (nb[2 * b + 1] - nb[2 * b]) * inv2dx;
+            qb[a] = u.p[a][zc.col + plane * zb];
+            qm[a] = u.p[a][zc.col + plane * zc.z0];
         }
-        T SS = 0, WW = 0;
+        for (int k = zc.z0; k < zc.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = zc.col + plane * k;
+            const bool bb = k == 0 && g.bc[4] != IBM_BC_PERIODIC;
+            const bool bt = k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC;
+            const uint8_t msk = st.mask[c];
+            T qt[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+            for (int a = 0; a < 3; ++a) qt[a] = u.p[a][zc.col + plane * zt];
+            T G[3][3];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                T s = (T)0.5 * (G[a][b] + G[b][a]);
-                T w = (T)0.5 * (G[a][b] - G[b][a]);
-                SS += s * s;
-                WW += w * w;
+            for (int a = 0; a < 3; ++a) {
+                const T* q = u.p[a];
+                const T qc = qm[a];
+                T nb[6];
+                nb[0] = nb_value<T>(g, st, q, a, c, msk, 0, zc.bw, q[c + zc.ow], qc, wall);
+                nb[1] = nb_value<T>(g, st, q, a, c, msk, 1, zc.be, q[c + zc.oe], qc, wall);
+                nb[2] = nb_value<T>(g, st, q, a, c, msk, 2, zc.bs, q[c + zc.os], qc, wall);
+                nb[3] = nb_value<T>(g, st, q, a, c, msk, 3, zc.bn, q[c + zc.on], qc, wall);
+                nb[4] = nb_value<T>(g, st, q, a, c, msk, 4, bb, qb[a], qc, wall);
+                nb[5] = nb_value<T>(g, st, q, a, c, msk, 5, bt, qt[a], qc, wall);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) G[a][b] = (nb[2 * b + 1] - nb[2 * b]) * inv2dx;
             }
-        T Q = (T)0.5 * (WW - SS);
-        T E = (T)0.5 * (WW + SS);
-        T F = E > (T)0 ? Q / E : (T)0;
-        T aF = F < (T)0 ? -F : F;
-        T C = (T)c1 * aF * sqrt(aF);
-        nut[c] = C * (T)(g.dx * g.dx) * sqrt(SS);
+            T SS = 0, WW = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    T s = (T)0.5 * (G[a][b] + G[b][a]);
+                    T w = (T)0.5 * (G[a][b] - G[b][a]);
+                    SS += s * s;
+                    WW += w * w;
+                }
+            T Q = (T)0.5 * (WW - SS);
+            T E = (T)0.5 * (WW + SS);
+            T F = E > (T)0 ? Q / E : (T)0;
+            T aF = F < (T)0 ? -F : F;
+            T C = (T)c1 * aF * sqrt(aF);
+            nut[c] = C * (T)(g.dx * g.dx) * sqrt(SS);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                qb[a] = qm[a];
+                qm[a] = qt[a];
+            }
+        }
     }
 }
 
@@ -130,80 +220,112 @@ __global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<doub
                                                 V3<T> us, const double* wall, double dt, double w_now,
                                                 double w_prev, double nu, double bx, double by, double bz,
                                                 int first, int cn, V3<T> rhs, double quick) {
-    long long t0, t1;
-    tile_range(g, t0, t1);
+    long long w0, w1;
+    zcol_range(g, w0, w1);
+    const long long plane = (long long)g.nx * g.ny;
     const double body[3] = {bx, by, bz};
     const T idx = (T)(1.0 / g.dx);
     const T idx2 = (T)(1.0 / (g.dx * g.dx));
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        uint8_t msk = st.mask[c];
-        T nut_c = nut[c];
-        T visc[6];
-        T Uf[6];
-#pragma unroll
-        for (int d = 0; d < 6; ++d) {
-            bool bnd;
-            long long n = nb_index(g, i, j, k, d, bnd);
-            bool closed = bnd || ((msk >> d) & 1);
-            visc[d] = (T)nu + (closed ? nut_c : (T)0.5 * (nut_c + nut[n]));
-            int ax = d >> 1;
-            if (d & 1) {
-                Uf[d] = (T)U.p[ax][c];
-            } else if (bnd) {
-                Uf[d] = g.bc[d] == IBM_BC_INFLOW ? (T)g.uin[ax] : (T)0;
-            } else {
-                Uf[d] = (T)U.p[ax][n];
-            }
-        }
-        const int nbits = __builtin_popcount((unsigned)msk);
-        bool dead = st.has_dead && nbits >= 5 && ((st.flags[c] >> 14) & 1);
+    for (long long w = w0; w < w1; ++w) {
+        const ZCol zc = zcol(g, w);
+        if (!zc.valid) continue;
+        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
+        // carried from the planes below / of the cell: u (3), nu_t, and U_z on the +z face
+        // of the plane below (the cell's -z face)
+        T qb[3], qm[3];
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            T qc = u.p[m][c];
-            T nb[6];
-            nbvals<T, T>(g, st, u.p[m], m, i, j, k, c, msk, wall, qc, nb);
-            T h = (T)body[m];
+            qb[m] = u.p[m][zc.col + plane * zb];
+            qm[m] = u.p[m][zc.col + plane * zc.z0];
+        }
+        T nub = nut[zc.col + plane * zb], num = nut[zc.col + plane * zc.z0];
+        double uzb = U.p[2][zc.col + plane * zb];
+        for (int k = zc.z0; k < zc.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = zc.col + plane * k;
+            const bool bnd[6] = {zc.bw, zc.be, zc.bs, zc.bn, k == 0 && g.bc[4] != IBM_BC_PERIODIC,
+                                 k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC};
+            const long long off[4] = {zc.ow, zc.oe, zc.os, zc.on};
+            const uint8_t msk = st.mask[c];
+            T qt[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) qt[m] = u.p[m][zc.col + plane * zt];
+            const T nut_t = nut[zc.col + plane * zt];
+            const T nut_c = num;
+            const T nutn[6] = {nut[c + zc.ow], nut[c + zc.oe], nut[c + zc.os], nut[c + zc.on], nub, nut_t};
+            T visc[6];
+            T Uf[6];
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
-                T s = (d & 1) ? (T)1 : (T)-1;
-                T qf = (T)0.5 * (qc + nb[d]);
-                if (quick != 0.0) {
-                    T qq;
-                    if (s * Uf[d] > (T)0) {
-                        qq = ((T)6 * qc + (T)3 * nb[d] - nb[d ^ 1]) / (T)8;
-                    } else {
-                        bool bnd;
-                        (void)nb_index(g, i, j, k, d, bnd);
-                        const T n2 = (bnd || ((msk >> d) & 1)) ? (T)2 * nb[d] - qc
-                                                               : (T)far_value(g, st, u.p[m], m, i, j, k, d, wall);
-                        qq = ((T)6 * nb[d] + (T)3 * qc - n2) / (T)8;
-                    }
-                    qf = (T)(1.0 - quick) * qf + (T)quick * qq;
+                const bool closed = bnd[d] || ((msk >> d) & 1);
+                visc[d] = (T)nu + (closed ? nut_c : (T)0.5 * (nut_c + nutn[d]));
+                const int ax = d >> 1;
+                if (d & 1) {
+                    Uf[d] = (T)U.p[ax][c];
+                } else if (bnd[d]) {
+                    Uf[d] = g.bc[d] == IBM_BC_INFLOW ? (T)g.uin[ax] : (T)0;
+                } else {
+                    Uf[d] = d == 4 ? (T)uzb : (T)U.p[ax][c + off[d]];
                 }
-                h = h - s * Uf[d] * qf * idx + visc[d] * (nb[d] - qc) * idx2;
             }
-            T v;
-            if (first || cn) v = qc + (T)dt * h;
-            else v = qc + (T)dt * ((T)w_now * h - (T)w_prev * hio.p[m][c]);
-            T b = (T)dt * h;
-            if (dead) {
-                uint32_t id0 = st.cut_off[c];
-                double acc = 0.0;
-                for (int q = 0; q < nbits; ++q) acc += wall ? wall[3 * (long long)(id0 + q) + m] : 0.0;
-                v = (T)(acc / (double)nbits);
-                b = v - qc;
-                h = (T)0;
+            const int nbits = __builtin_popcount((unsigned)msk);
+            bool dead = st.has_dead && nbits >= 5 && ((st.flags[c] >> 14) & 1);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const T* q = u.p[m];
+                const T qc = qm[m];
+                T nb[6];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) nb[d] = nb_value<T>(g, st, q, m, c, msk, d, bnd[d], q[c + off[d]], qc, wall);
+                nb[4] = nb_value<T>(g, st, q, m, c, msk, 4, bnd[4], qb[m], qc, wall);
+                nb[5] = nb_value<T>(g, st, q, m, c, msk, 5, bnd[5], qt[m], qc, wall);
+                T h = (T)body[m];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) {
+                    T s = (d & 1) ? (T)1 : (T)-1;
+                    T qf = (T)0.5 * (qc + nb[d]);
+                    if (quick != 0.0) {
+                        T qq;
+                        if (s * Uf[d] > (T)0) {
+                            qq = ((T)6 * qc + (T)3 * nb[d] - nb[d ^ 1]) / (T)8;
+                        } else {
+                            const T n2 = (bnd[d] || ((msk >> d) & 1))
+                                             ? (T)2 * nb[d] - qc
+                                             : (T)far_value(g, st, q, m, zc.i, zc.j, k, d, wall);
+                            qq = ((T)6 * nb[d] + (T)3 * qc - n2) / (T)8;
+                        }
+                        qf = (T)(1.0 - quick) * qf + (T)quick * qq;
+                    }
+                    h = h - s * Uf[d] * qf * idx + visc[d] * (nb[d] - qc) * idx2;
+                }
+                T v;
+                if (first || cn) v = qc + (T)dt * h;
+                else v = qc + (T)dt * ((T)w_now * h - (T)w_prev * hio.p[m][c]);
+                T b = (T)dt * h;
+                if (dead) {
+                    uint32_t id0 = st.cut_off[c];
+                    double acc = 0.0;
+                    for (int qi = 0; qi < nbits; ++qi) acc += wall ? wall[3 * (long long)(id0 + qi) + m] : 0.0;
+                    v = (T)(acc / (double)nbits);
+                    b = v - qc;
+                    h = (T)0;
+                }
+                if (cn) {
+                    rhs.p[m][c] = b;
+                    if (dead) us.p[m][c] = v;
+                } else {
+                    us.p[m][c] = v;
+                }
+                hio.p[m][c] = h;
             }
-            if (cn) {
-                rhs.p[m][c] = b;
-                if (dead) us.p[m][c] = v;
-            } else {
-                us.p[m][c] = v;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                qb[m] = qm[m];
+                qm[m] = qt[m];
             }
-            hio.p[m][c] = h;
+            nub = num;
+            num = nut_t;
+            uzb = U.p[2][c];
         }
     }
 }
@@ -227,33 +349,49 @@ __device__ inline double wall_face(const Sten& st, long long c, uint8_t msk, lon
 template <class T>
 __global__ void __launch_bounds__(NT) k_rhs(Geo g, Sten st, C3<T> us, V3<double> U, double* b,
                                             const double* wall, double dt) {
-    long long t0, t1;
-    tile_range(g, t0, t1);
+    long long w0, w1;
+    zcol_range(g, w0, w1);
+    const long long plane = (long long)g.nx * g.ny;
     const double idx = 1.0 / g.dx;
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        uint8_t msk = st.mask[c];
-        double div = 0.0;
+    for (long long w = w0; w < w1; ++w) {
+        const ZCol zc = zcol(g, w);
+        if (!zc.valid) continue;
+        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
+        // u*_z of the planes below and of the cell (the only component needed across z)
+        double wb = (double)us.p[2][zc.col + plane * zb], wm = (double)us.p[2][zc.col + plane * zc.z0];
+        for (int k = zc.z0; k < zc.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = zc.col + plane * k;
+            const double wt = (double)us.p[2][zc.col + plane * zt];
+            const uint8_t msk = st.mask[c];
+            const bool bp3[3] = {zc.be, zc.bn, k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC};
+            const bool bm3[3] = {zc.bw, zc.bs, k == 0 && g.bc[4] != IBM_BC_PERIODIC};
+            const int kb = k == 0 ? g.nz - 1 : k - 1;
+            const long long np3[3] = {c + zc.oe, c + zc.on, zc.col + plane * zt};
+            const long long nm3[3] = {c + zc.ow, c + zc.os, zc.col + plane * kb};
+            double div = 0.0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double qc = (double)us.p[a][c];
-            int dp = 2 * a + 1, dm = 2 * a;
-            bool bp, bm;
-            long long np = nb_index(g, i, j, k, dp, bp);
-            long long nm = nb_index(g, i, j, k, dm, bm);
-            double Up, Um;
-            if ((msk >> dp) & 1) Up = wall_face<T>(st, c, msk, np, a, wall);
-            else if (bp) Up = g.bc[dp] == IBM_BC_INFLOW ? g.uin[a] : (g.bc[dp] == IBM_BC_OUTFLOW ? qc : 0.0);
-            else Up = 0.5 * (qc + (double)us.p[a][np]);
-            if ((msk >> dm) & 1) Um = wall_face<T>(st, nm, st.mask[nm], c, a, wall);
-            else if (bm) Um = g.bc[dm] == IBM_BC_INFLOW ? g.uin[a] : 0.0;
-            else Um = 0.5 * ((double)us.p[a][nm] + qc);
-            U.p[a][c] = Up;
-            div += (Up - Um) * idx;
+            for (int a = 0; a < 3; ++a) {
+                const double qc = a == 2 ? wm : (double)us.p[a][c];
+                const int dp = 2 * a + 1, dm = 2 * a;
+                const bool bp = bp3[a], bm = bm3[a];
+                const long long np = np3[a], nm = nm3[a];
+                const double qp = a == 2 ? wt : (double)us.p[a][np];
+                const double qmv = a == 2 ? wb : (double)us.p[a][nm];
+                double Up, Um;
+                if ((msk >> dp) & 1) Up = wall_face<T>(st, c, msk, np, a, wall);
+                else if (bp) Up = g.bc[dp] == IBM_BC_INFLOW ? g.uin[a] : (g.bc[dp] == IBM_BC_OUTFLOW ? qc : 0.0);
+                else Up = 0.5 * (qc + qp);
+                if ((msk >> dm) & 1) Um = wall_face<T>(st, nm, st.mask[nm], c, a, wall);
+                else if (bm) Um = g.bc[dm] == IBM_BC_INFLOW ? g.uin[a] : 0.0;
+                else Um = 0.5 * (qmv + qc);
+                U.p[a][c] = Up;
+                div += (Up - Um) * idx;
+            }
+            b[c] = div / dt;
+            wb = wm;
+            wm = wt;
         }
-        b[c] = div / dt;
     }
 }
 
@@ -264,35 +402,46 @@ __global__ void __launch_bounds__(NT) k_rhs(Geo g, Sten st, C3<T> us, V3<double>
 template <class T>
 __global__ void __launch_bounds__(NT) k_project(Geo g, Sten st, C3<T> us, V3<double> U, const double* p, V3<T> u,
                                                 double dt) {
-    long long t0, t1;
-    tile_range(g, t0, t1);
+    long long w0, w1;
+    zcol_range(g, w0, w1);
+    const long long plane = (long long)g.nx * g.ny;
     const double idx = 1.0 / g.dx;
-    for (long long t = t0; t < t1; ++t) {
-        int i, j, k;
-        if (!tile_cell(g, t, i, j, k)) continue;
-        long long c = cidx(g, i, j, k);
-        uint8_t msk = st.mask[c];
-        double pc = p[c];
-        bool dead = st.has_dead && __builtin_popcount((unsigned)msk) >= 5 && ((st.flags[c] >> 14) & 1);
+    for (long long w = w0; w < w1; ++w) {
+        const ZCol zc = zcol(g, w);
+        if (!zc.valid) continue;
+        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
+        double pb = p[zc.col + plane * zb], pm = p[zc.col + plane * zc.z0];
+        for (int k = zc.z0; k < zc.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = zc.col + plane * k;
+            const double pt = p[zc.col + plane * zt];
+            const uint8_t msk = st.mask[c];
+            const double pc = pm;
+            const bool bp3[3] = {zc.be, zc.bn, k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC};
+            const bool bm3[3] = {zc.bw, zc.bs, k == 0 && g.bc[4] != IBM_BC_PERIODIC};
+            const bool dead = st.has_dead && __builtin_popcount((unsigned)msk) >= 5 && ((st.flags[c] >> 14) & 1);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            int dp = 2 * a + 1, dm = 2 * a;
-            bool bp, bm;
-            long long np = nb_index(g, i, j, k, dp, bp);
-            long long nm = nb_index(g, i, j, k, dm, bm);
-            bool openp = !bp && !((msk >> dp) & 1);
-            bool openm = !bm && !((msk >> dm) & 1);
-            bool outp = bp && g.bc[dp] == IBM_BC_OUTFLOW;
-            bool outm = bm && g.bc[dm] == IBM_BC_OUTFLOW;
-            double pE = openp ? p[np] : (outp ? -pc : pc);
-            double pW = openm ? p[nm] : (outm ? -pc : pc);
-            double Uc = U.p[a][c];
-            if (openp) Uc = Uc - dt * (pE - pc) * idx;
-            else if (outp) Uc = Uc + 2.0 * dt * pc * idx;
-            U.p[a][c] = Uc;
-            double usc = (double)us.p[a][c];
-            double v = dead ? usc : usc - dt * (pE - pW) / (2.0 * g.dx);
-            u.p[a][c] = (T)v;
+            for (int a = 0; a < 3; ++a) {
+                const int dp = 2 * a + 1, dm = 2 * a;
+                const bool bp = bp3[a], bm = bm3[a];
+                const bool openp = !bp && !((msk >> dp) & 1);
+                const bool openm = !bm && !((msk >> dm) & 1);
+                const bool outp = bp && g.bc[dp] == IBM_BC_OUTFLOW;
+                const bool outm = bm && g.bc[dm] == IBM_BC_OUTFLOW;
+                const double pnp = a == 0 ? p[c + zc.oe] : (a == 1 ? p[c + zc.on] : pt);
+                const double pnm = a == 0 ? p[c + zc.ow] : (a == 1 ? p[c + zc.os] : pb);
+                const double pE = openp ? pnp : (outp ? -pc : pc);
+                const double pW = openm ? pnm : (outm ? -pc : pc);
+                double Uc = U.p[a][c];
+                if (openp) Uc = Uc - dt * (pE - pc) * idx;
+                else if (outp) Uc = Uc + 2.0 * dt * pc * idx;
+                U.p[a][c] = Uc;
+                const double usc = (double)us.p[a][c];
+                const double v = dead ? usc : usc - dt * (pE - pW) / (2.0 * g.dx);
+                u.p[a][c] = (T)v;
+            }
+            pb = pm;
+            pm = pt;
         }
     }
 }
@@ -495,11 +644,10 @@ int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, co
               hipStream_t s) {
     const Geo& g = c->geo;
     Sten st = sten_of(c);
-    int nb = grid_blocks(g);
     C3<T> uu{{(const T*)u[0], (const T*)u[1], (const T*)u[2]}};
     T* nut = (T*)c->nut;
     if (prm->csm_on) {
-        k_csm<T><<<nb, NT, 0, s>>>(g, st, uu, wall, nut, prm->c1);
+        k_csm<T><<<zcol_blocks(g), NT, 0, s>>>(g, st, uu, wall, nut, prm->c1);
     } else {
         k_zero<T><<<2048, 256, 0, s>>>(nut, c->N);
     }
@@ -516,7 +664,7 @@ int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, co
         T* x = (T*)c->cn_ws;
         for (int a = 0; a < 3; ++a) rhs.p[a] = x + (long long)a * c->N;
     }
-    launch_timed(c, TK_PREDICT, k_predict<T>, nb, s, g, st, uu, UU, (const T*)nut, hh, us, wall, prm->dt,
+    launch_timed(c, TK_PREDICT, k_predict<T>, zcol_blocks(g), s, g, st, uu, UU, (const T*)nut, hh, us, wall, prm->dt,
                  1.0 + 0.5 * r, 0.5 * r, prm->nu, prm->body_force[0], prm->body_force[1], prm->body_force[2],
                  prm->step == 0 ? 1 : 0, cn ? 1 : 0, rhs, prm->quick);
     IBM_HIP(hipGetLastError());   // its events are collected after the solve's next synchronisation
@@ -528,7 +676,7 @@ int rhs_t(ibm_ctx* c, double** U, const double* wall, double dt, hipStream_t s) 
     const Geo& g = c->geo;
     C3<T> us{{(const T*)c->ustar[0], (const T*)c->ustar[1], (const T*)c->ustar[2]}};
     V3<double> UU{{U[0], U[1], U[2]}};
-    k_rhs<T><<<grid_blocks(g), NT, 0, s>>>(g, sten_of(c), us, UU, c->b, wall, dt);
+    k_rhs<T><<<zcol_blocks(g), NT, 0, s>>>(g, sten_of(c), us, UU, c->b, wall, dt);
     IBM_HIP(hipGetLastError());
     return remove_means(c, c->b, s);
 }
@@ -539,7 +687,7 @@ int project_t(ibm_ctx* c, void** u, double** U, const double* p, double dt, hipS
     C3<T> us{{(const T*)c->ustar[0], (const T*)c->ustar[1], (const T*)c->ustar[2]}};
     V3<double> UU{{U[0], U[1], U[2]}};
     V3<T> uu{{(T*)u[0], (T*)u[1], (T*)u[2]}};
-    k_project<T><<<grid_blocks(g), NT, 0, s>>>(g, sten_of(c), us, UU, p, uu, dt);
+    k_project<T><<<zcol_blocks(g), NT, 0, s>>>(g, sten_of(c), us, UU, p, uu, dt);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }

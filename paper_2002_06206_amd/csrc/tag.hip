@@ -202,7 +202,19 @@ struct TagArgs {
     int n[3];
     double dx;
     double o[3];
+    double eps;          // bary_eps: tolerance of the ray / triangle test (0 = exact)
 };
+
+// Bounding box of a triangle along axis x, grown so that it holds the triangle grown by
+// eps in barycentric terms (its corners are a + eps (2a - b - c) and the like, at most
+// 2 eps times the extent beyond the box).
+__device__ inline void grown_range(const double* p, int x, double eps, double& lo, double& hi) {
+    lo = fmin(p[x], fmin(p[3 + x], p[6 + x]));
+    hi = fmax(p[x], fmax(p[3 + x], p[6 + x]));
+    const double gr = 2.0 * eps * (hi - lo);
+    lo -= gr;
+    hi += gr;
+}
 
 // Candidate-line count per (triangle, axis).
 __global__ void k_count(TagArgs a, unsigned long long* cnt, int* bad) {
@@ -220,8 +232,9 @@ __global__ void k_count(TagArgs a, unsigned long long* cnt, int* bad) {
         return;
     }
     int u = (k + 1) % 3, v = (k + 2) % 3;
-    double umin = fmin(p[u], fmin(p[3 + u], p[6 + u])), umax = fmax(p[u], fmax(p[3 + u], p[6 + u]));
-    double vmin = fmin(p[v], fmin(p[3 + v], p[6 + v])), vmax = fmax(p[v], fmax(p[3 + v], p[6 + v]));
+    double umin, umax, vmin, vmax;
+    grown_range(p, u, a.eps, umin, umax);
+    grown_range(p, v, a.eps, vmin, vmax);
     long long j0 = lfloor((umin - a.o[u]) / a.dx - 0.5 - 1.0, 0, a.n[u]);
     long long j1 = lfloor(ceil((umax - a.o[u]) / a.dx - 0.5) + 1.0, -1, a.n[u] - 1);
     long long l0 = lfloor((vmin - a.o[v]) / a.dx - 0.5 - 1.0, 0, a.n[v]);
@@ -234,8 +247,13 @@ __global__ void k_count(TagArgs a, unsigned long long* cnt, int* bad) {
     cnt[id] = (unsigned long long)((j1 - j0 + 1) * (l1 - l0 + 1));
 }
 
+// One thread per candidate (triangle, axis, line).  Pass 1 (list == null) sets the
+// blocked bits of both cells of every crossed segment; pass 2 (the mask complete and
+// coff its exclusive popcount prefix) keeps the nearest crossing of each blocked
+// (cell, dir) in the compact list by an atomic minimum on the bits of the non-negative
+// theta.  Both passes take the same decisions.
 __global__ void k_lines(TagArgs a, const unsigned long long* off, unsigned long long total, uint32_t* maskw,
-                        unsigned long long* theta_bits) {
+                        const uint32_t* coff, unsigned long long* list) {
     const long long ntk = a.ntri * 3;
     for (unsigned long long q = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
          q += (unsigned long long)gridDim.x * blockDim.x) {
@@ -256,9 +274,11 @@ __global__ void k_lines(TagArgs a, const unsigned long long* off, unsigned long 
             T.b[x] = p[3 + x];
             T.c[x] = p[6 + x];
         }
-        double umin = fmin(T.a[u], fmin(T.b[u], T.c[u]));
-        double vmin = fmin(T.a[v], fmin(T.b[v], T.c[v])), vmax = fmax(T.a[v], fmax(T.b[v], T.c[v]));
-        double kmin = fmin(T.a[k], fmin(T.b[k], T.c[k])), kmax = fmax(T.a[k], fmax(T.b[k], T.c[k]));
+        double umin, umax, vmin, vmax, kmin, kmax;
+        grown_range(p, u, a.eps, umin, umax);
+        grown_range(p, v, a.eps, vmin, vmax);
+        grown_range(p, k, a.eps, kmin, kmax);
+        (void)umax;
         long long j0 = lfloor((umin - a.o[u]) / a.dx - 0.5 - 1.0, 0, a.n[u]);
         long long l0 = lfloor((vmin - a.o[v]) / a.dx - 0.5 - 1.0, 0, a.n[v]);
         long long l1 = lfloor(ceil((vmax - a.o[v]) / a.dx - 0.5) + 1.0, -1, a.n[v] - 1);
@@ -274,7 +294,7 @@ __global__ void k_lines(TagArgs a, const unsigned long long* off, unsigned long 
         int sW;
         if (sa >= 0 && sb >= 0 && sc >= 0 && sa + sb + sc > 0) sW = 1;
         else if (sa <= 0 && sb <= 0 && sc <= 0 && sa + sb + sc < 0) sW = -1;
-        else continue;
+        else sW = 0;
 
         // double crossing coordinate, fixed operation order
         double dau = T.a[u] - pu, dav = T.a[v] - pv;
@@ -285,6 +305,17 @@ __global__ void k_lines(TagArgs a, const unsigned long long* off, unsigned long 
         double wc = dau * dbv - dav * dbu;
         double num = (wa * T.a[k] + wb * T.b[k]) + wc * T.c[k];
         double den = (wa + wb) + wc;
+        if (sW == 0) {
+            // missed exactly: a hit only within the tolerance, each sub-triangle area
+            // (with the exact orientation sign of the projected triangle) at least
+            // -eps |w_a + w_b + w_c|
+            if (!(a.eps > 0.0)) continue;
+            const int sT = orient2d_sign(T.a[u], T.a[v], T.b[u], T.b[v], T.c[u], T.c[v]);
+            if (sT == 0) continue;
+            const double st = (double)sT, lim = -a.eps * fabs(den);
+            if (!(wa * st >= lim && wb * st >= lim && wc * st >= lim)) continue;
+            sW = sT;
+        }
         double xs = num / den;
 
         // first centre index along k with x_i > x* (exact), bisection over a bracket
@@ -318,10 +349,16 @@ __global__ void k_lines(TagArgs a, const unsigned long long* off, unsigned long 
             idx[k] = sidx + 1;
             long long cb = idx[0] + (long long)a.n[0] * (idx[1] + (long long)a.n[1] * idx[2]);
             int da = 2 * k + 1, db = 2 * k;
-            atomicOr(&maskw[ca >> 2], (1u << da) << (8 * (ca & 3)));
-            atomicOr(&maskw[cb >> 2], (1u << db) << (8 * (cb & 3)));
-            atomicMin(&theta_bits[6 * ca + da], (unsigned long long)__double_as_longlong(tl));
-            atomicMin(&theta_bits[6 * cb + db], (unsigned long long)__double_as_longlong(th));
+            if (!list) {
+                atomicOr(&maskw[ca >> 2], (1u << da) << (8 * (ca & 3)));
+                atomicOr(&maskw[cb >> 2], (1u << db) << (8 * (cb & 3)));
+            } else {
+                const uint8_t* mb = reinterpret_cast<const uint8_t*>(maskw);
+                const uint32_t ia = coff[ca] + (uint32_t)__builtin_popcount((unsigned)mb[ca] & ((1u << da) - 1u));
+                const uint32_t ib = coff[cb] + (uint32_t)__builtin_popcount((unsigned)mb[cb] & ((1u << db) - 1u));
+                atomicMin(&list[ia], (unsigned long long)__double_as_longlong(tl));
+                atomicMin(&list[ib], (unsigned long long)__double_as_longlong(th));
+            }
         }
     }
 }
@@ -331,7 +368,7 @@ __global__ void k_fill_u32(uint32_t* p, long long n, uint32_t v) {
         p[i] = v;
 }
 
-__global__ void k_fill_f64(double* p, long long n, double v) {
+__global__ void k_fill_u64(unsigned long long* p, long long n, unsigned long long v) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = v;
 }
@@ -341,16 +378,39 @@ __global__ void k_fill_i32(int* p, long long n, int v) {
         p[i] = v;
 }
 
+struct PopcountByte {
+    __host__ __device__ uint32_t operator()(uint8_t m) const { return (uint32_t)__builtin_popcount((unsigned)m); }
+};
+
+// number of list entries: last offset + popcount of the last cell
+__global__ void k_list_total(const uint32_t* coff, const uint8_t* mask, long long N, unsigned long long* out) {
+    *out = (unsigned long long)coff[N - 1] + (unsigned long long)__builtin_popcount((unsigned)mask[N - 1]);
+}
+
+// dense theta (cells x 6, 2.0 where open) from the compact list
+__global__ void k_expand(long long N, ThetaSrc t, double* theta) {
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x)
+        for (int d = 0; d < 6; ++d) theta[6 * c + d] = theta_of(t, c, d);
+}
+
+__global__ void k_differs(long long N, const uint8_t* a, const uint8_t* b, int* flag) {
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x)
+        if (a[c] != b[c]) *flag = 1;
+}
+
 }  // namespace
 
-int tag_run(ibm_ctx* c, const double* tri, long long ntri, hipStream_t s) {
+// Tagging into the context: pass 1 sets the blocked bits, an exclusive scan of their
+// popcounts gives each cell's first entry of the compact theta list, pass 2 fills the
+// list with the nearest crossings.  Memory: one byte and one 32-bit offset per cell and
+// 8 bytes per blocked (cell, dir), instead of 48 bytes per cell for a dense theta.
+int tag_run(ibm_ctx* c, const double* tri, long long ntri, double bary_eps, hipStream_t s) {
     const long long N = c->N;
     const long long nw = (N + 3) / 4;
     k_fill_u32<<<2048, 256, 0, s>>>(c->tagmask, nw, 0u);
-    k_fill_f64<<<4096, 256, 0, s>>>(c->theta, 6 * N, 2.0);
     IBM_HIP(hipGetLastError());
-    c->tagged = true;
-    if (ntri == 0) return IBM_OK;
+    c->tagged = false;
+    c->tag_ncut = 0;
     TagArgs a;
     a.tri = tri;
     a.ntri = ntri;
@@ -361,41 +421,121 @@ int tag_run(ibm_ctx* c, const double* tri, long long ntri, hipStream_t s) {
     a.o[0] = c->geo.ox;
     a.o[1] = c->geo.oy;
     a.o[2] = c->geo.oz;
+    a.eps = bary_eps;
     const long long ntk = ntri * 3;
-    unsigned long long *cnt = nullptr, *off = nullptr;
+    unsigned long long *cnt = nullptr, *off = nullptr, *dtotal = nullptr;
     int* bad = nullptr;
     void* tmp = nullptr;
     size_t tmp_bytes = 0;
-    IBM_HIP(ibm::dev_malloc_async((void**)&cnt, sizeof(unsigned long long) * (ntk + 1), s));
-    IBM_HIP(ibm::dev_malloc_async((void**)&off, sizeof(unsigned long long) * (ntk + 1), s));
-    IBM_HIP(ibm::dev_malloc_async((void**)&bad, sizeof(int), s));
-    k_fill_i32<<<1, 1, 0, s>>>(bad, 1, 0);
-    // cnt[ntk] = 0, so the exclusive scan over ntk+1 entries ends with the total
-    k_count<<<(unsigned)((ntk + 1 + 255) / 256), 256, 0, s>>>(a, cnt, bad);
-    IBM_HIP(hipGetLastError());
-    IBM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, off, (int)(ntk + 1), s));
-    IBM_HIP(ibm::dev_malloc_async(&tmp, tmp_bytes, s));
-    IBM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, off, (int)(ntk + 1), s));
     unsigned long long total = 0;
-    int hbad = 0;
-    IBM_HIP(hipMemcpyAsync(&total, off + ntk, sizeof(total), hipMemcpyDeviceToHost, s));
-    IBM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-    IBM_HIP(hipStreamSynchronize(s));
     int rc = IBM_OK;
-    if (hbad) {
-        set_error("ibm_tag_geometry: triangle coordinates must be finite with magnitude 0 or in [2^-200, 2^200]");
-        rc = IBM_ERR_ARG;
-    } else if (total > 0) {
-        unsigned blocks = (unsigned)((total + 255) / 256);
-        if (blocks > 65536u * 4u) blocks = 65536u * 4u;
-        k_lines<<<blocks, 256, 0, s>>>(a, off, total, c->tagmask, (unsigned long long*)c->theta);
+    if (ntri > 0) {
+        IBM_HIP(ibm::dev_malloc_async((void**)&cnt, sizeof(unsigned long long) * (ntk + 1), s));
+        IBM_HIP(ibm::dev_malloc_async((void**)&off, sizeof(unsigned long long) * (ntk + 1), s));
+        IBM_HIP(ibm::dev_malloc_async((void**)&bad, sizeof(int), s));
+        k_fill_i32<<<1, 1, 0, s>>>(bad, 1, 0);
+        // cnt[ntk] = 0, so the exclusive scan over ntk+1 entries ends with the total
+        k_count<<<(unsigned)((ntk + 1 + 255) / 256), 256, 0, s>>>(a, cnt, bad);
+        IBM_HIP(hipGetLastError());
+        IBM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, off, (int)(ntk + 1), s));
+        IBM_HIP(ibm::dev_malloc_async(&tmp, tmp_bytes, s));
+        IBM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, off, (int)(ntk + 1), s));
+        int hbad = 0;
+        IBM_HIP(hipMemcpyAsync(&total, off + ntk, sizeof(total), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        IBM_HIP(hipFreeAsync(tmp, s));
+        tmp = nullptr;
+        if (hbad) {
+            set_error("ibm_tag_geometry: triangle coordinates must be finite with magnitude 0 or in [2^-200, 2^200]");
+            rc = IBM_ERR_ARG;
+        }
+    }
+    unsigned blocks = (unsigned)((total + 255) / 256);
+    if (blocks > 65536u * 4u) blocks = 65536u * 4u;
+    if (rc == IBM_OK && total > 0) {
+        k_lines<<<blocks, 256, 0, s>>>(a, off, total, c->tagmask, nullptr, nullptr);
         IBM_HIP(hipGetLastError());
     }
-    IBM_HIP(hipFreeAsync(tmp, s));
-    IBM_HIP(hipFreeAsync(cnt, s));
-    IBM_HIP(hipFreeAsync(off, s));
-    IBM_HIP(hipFreeAsync(bad, s));
+    // offsets of the compact list
+    unsigned long long nlist = 0;
+    if (rc == IBM_OK) {
+        const uint8_t* mb = reinterpret_cast<const uint8_t*>(c->tagmask);
+        hipcub::TransformInputIterator<uint32_t, PopcountByte, const uint8_t*> it(mb, PopcountByte());
+        size_t bytes = 0;
+        IBM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, it, c->tag_off, (int)N, s));
+        IBM_HIP(ibm::dev_malloc_async(&tmp, bytes, s));
+        IBM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, bytes, it, c->tag_off, (int)N, s));
+        IBM_HIP(ibm::dev_malloc_async((void**)&dtotal, sizeof(unsigned long long), s));
+        k_list_total<<<1, 1, 0, s>>>(c->tag_off, mb, N, dtotal);
+        IBM_HIP(hipGetLastError());
+        IBM_HIP(hipMemcpyAsync(&nlist, dtotal, sizeof(nlist), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        IBM_HIP(hipFreeAsync(tmp, s));
+        IBM_HIP(hipFreeAsync(dtotal, s));
+        // the per-cell offsets are 32-bit and a scan of N popcounts is exact below 2^32
+        if (nlist >= 0xFFFFFFFFull) {
+            set_error("ibm_tag_geometry: more than 2^32-1 blocked (cell, direction) pairs");
+            rc = IBM_ERR_ARG;
+        }
+    }
+    if (rc == IBM_OK && (long long)nlist > c->tag_cap) {
+        if (c->tag_list) IBM_HIP(hipFree(c->tag_list));
+        c->tag_list = nullptr;
+        c->tag_cap = 0;
+        const long long cap = (long long)nlist + (long long)nlist / 8 + 64;
+        if (ibm::dev_malloc(&c->tag_list, sizeof(double) * (size_t)cap) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("ibm_tag_geometry: out of device memory for the theta list");
+            rc = IBM_ERR_OOM;
+        } else {
+            c->tag_cap = cap;
+        }
+    }
+    if (rc == IBM_OK && nlist > 0) {
+        const unsigned long long two = 0x4000000000000000ull;   // bits of 2.0 (open)
+        k_fill_u64<<<2048, 256, 0, s>>>((unsigned long long*)c->tag_list, (long long)nlist, two);
+        k_lines<<<blocks, 256, 0, s>>>(a, off, total, c->tagmask, c->tag_off, (unsigned long long*)c->tag_list);
+        IBM_HIP(hipGetLastError());
+    }
+    if (cnt) IBM_HIP(hipFreeAsync(cnt, s));
+    if (off) IBM_HIP(hipFreeAsync(off, s));
+    if (bad) IBM_HIP(hipFreeAsync(bad, s));
+    if (rc == IBM_OK) {
+        c->tag_ncut = (long long)nlist;
+        c->tagged = true;
+    }
     return rc;
+}
+
+int tag_expand(ibm_ctx* c, double* theta, hipStream_t s) {
+    ThetaSrc t{nullptr, reinterpret_cast<const uint8_t*>(c->tagmask), c->tag_off, c->tag_list};
+    k_expand<<<4096, 256, 0, s>>>(c->N, t, theta);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int tag_matches(ibm_ctx* c, const uint8_t* blocked, bool* same, hipStream_t s) {
+    int* flag = (int*)c->counter + 9;   // spare slot of the ticket array
+    k_fill_i32<<<1, 1, 0, s>>>(flag, 1, 0);
+    k_differs<<<4096, 256, 0, s>>>(c->N, blocked, reinterpret_cast<const uint8_t*>(c->tagmask), flag);
+    int h = 0;
+    IBM_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    IBM_HIP(hipStreamSynchronize(s));
+    *same = h == 0;
+    return IBM_OK;
+}
+
+void tag_release(ibm_ctx* c) {
+    if (c->tagmask) (void)hipFree(c->tagmask);
+    if (c->tag_off) (void)hipFree(c->tag_off);
+    if (c->tag_list) (void)hipFree(c->tag_list);
+    c->tagmask = nullptr;
+    c->tag_off = nullptr;
+    c->tag_list = nullptr;
+    c->tag_cap = 0;
+    c->tag_ncut = 0;
+    c->tagged = false;
 }
 
 }  // namespace ibm

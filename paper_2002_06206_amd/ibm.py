@@ -39,7 +39,8 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("kind", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32),
                 ("stall_factor", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("force_stall", ctypes.c_int32), ("omega", ctypes.c_double)]
+                ("force_stall", ctypes.c_int32), ("omega", ctypes.c_double), ("inner_restart", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class StepParams(ctypes.Structure):
@@ -54,7 +55,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("iters_inner", ctypes.c_int32), ("iters_outer", ctypes.c_int32),
                 ("fallback_used", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("div_l2", ctypes.c_double), ("div_linf", ctypes.c_double),
-                ("umax", ctypes.c_double), ("iters_momentum", ctypes.c_int32 * 3), ("pad", ctypes.c_int32)]
+                ("umax", ctypes.c_double), ("iters_momentum", ctypes.c_int32 * 3),
+                ("iters_fallback", ctypes.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
@@ -76,7 +78,7 @@ def _load():
         "ibm_destroy": ([vp], ctypes.c_int),
         "ibm_last_error": ([], ctypes.c_char_p),
         "ibm_alloc_count": ([ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
-        "ibm_tag_geometry": ([vp, vp, ctypes.c_int64, vp, vp, vp], ctypes.c_int),
+        "ibm_tag_geometry": ([vp, vp, ctypes.c_int64, ctypes.c_double, vp, vp, vp], ctypes.c_int),
         "ibm_build_stencils": ([vp, vp, vp, ctypes.c_int32, vp, vp, ctypes.POINTER(ctypes.c_int64), vp],
                                ctypes.c_int),
         "ibm_cut_points": ([vp, vp, vp], ctypes.c_int),
@@ -187,10 +189,10 @@ def ibm_destroy(ctx):
     return _check(_lib.ibm_destroy(ctx), "ibm_destroy")
 
 
-def ibm_tag_geometry(ctx, tri, blocked, theta=None):
+def ibm_tag_geometry(ctx, tri, blocked, theta=None, bary_eps=0.0):
     assert tri.dtype == torch.float64 and blocked.dtype == torch.uint8
-    return _check(_lib.ibm_tag_geometry(ctx, _ptr(tri), tri.shape[0] if tri.numel() else 0, _ptr(blocked),
-                                        _ptr(theta), _stream()), "ibm_tag_geometry")
+    return _check(_lib.ibm_tag_geometry(ctx, _ptr(tri), tri.shape[0] if tri.numel() else 0, float(bary_eps),
+                                        _ptr(blocked), _ptr(theta), _stream()), "ibm_tag_geometry")
 
 
 def ibm_build_stencils(ctx, blocked, theta=None, deadend=False, flags=None, label=None):
@@ -365,9 +367,9 @@ def ibm_ctx_set_preconditioner(ctx, net):
 # ------------------------------------------------------------- convenience
 
 def solver_opts(tol=1e-10, max_iter=20000, kind=SOLVER_PCG_JACOBI, inner_tol=1e-2, inner_max_iter=200,
-                stall_factor=2.0, check_every=16, force_stall=0, omega=0.0):
+                stall_factor=2.0, check_every=16, force_stall=0, omega=0.0, inner_restart=0):
     return SolverOpts(tol, max_iter, kind, inner_tol, inner_max_iter, stall_factor, check_every, force_stall,
-                      float(omega))
+                      float(omega), int(inner_restart), 0)
 
 
 def step_params(dt, nu, c1=1.0 / 20.0, csm=True, step=0, body=(0.0, 0.0, 0.0), dt_prev=0.0, scheme="ab2",
@@ -400,13 +402,13 @@ class Solver:
         except Exception:
             pass
 
-    def tag(self, tri, want_theta=True):
-        """Blocked bits and (when want_theta) a copy of theta; the context keeps its own
-        theta for the next build either way."""
+    def tag(self, tri, want_theta=True, bary_eps=0.0):
+        """Blocked bits and (when want_theta) the dense theta; the context keeps its own
+        compact tagging for the next build either way."""
         tri_t = torch.as_tensor(tri, dtype=torch.float64).to(self.dev).contiguous()
         blocked = torch.zeros(self.shape, dtype=torch.uint8, device=self.dev)
         theta = torch.empty(self.shape + (6,), dtype=torch.float64, device=self.dev) if want_theta else None
-        ibm_tag_geometry(self.ctx, tri_t.reshape(-1, 3, 3), blocked, theta)
+        ibm_tag_geometry(self.ctx, tri_t.reshape(-1, 3, 3), blocked, theta, bary_eps)
         del tri_t
         return blocked, theta
 

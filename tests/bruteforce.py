@@ -15,8 +15,10 @@ def _det3(a, b, c):
             + a[2] * (b[0] * c[1] - b[1] * c[0]))
 
 
-def seg_tri(P0, P1, A, B, C):
-    """Exact closed-segment / closed-triangle test; returns the parameter t in [0,1] or None."""
+def seg_tri(P0, P1, A, B, C, eps=0):
+    """Exact closed-segment / closed-triangle test; returns the parameter t in [0,1] or None.
+    eps > 0 widens the triangle: barycentric coordinates down to -eps count as inside
+    (the ray test's tolerance)."""
     D = [P1[i] - P0[i] for i in range(3)]
     E1 = [B[i] - A[i] for i in range(3)]
     E2 = [C[i] - A[i] for i in range(3)]
@@ -36,12 +38,13 @@ def seg_tri(P0, P1, A, B, C):
     t = Fr(rep(0)) / det
     beta = Fr(rep(1)) / det
     gamma = Fr(rep(2)) / det
-    if t < 0 or t > 1 or beta < 0 or gamma < 0 or beta + gamma > 1:
+    e = Fr(eps)
+    if t < 0 or t > 1 or beta < -e or gamma < -e or beta + gamma > 1 + e:
         return None
     return t
 
 
-def brute_tag(tri, n, dx, origin):
+def brute_tag(tri, n, dx, origin, eps=0):
     """Returns dict (flat cell, dir) -> exact theta (Fraction) over all blocked pairs."""
     nx, ny, nz = n
     dxf = Fr(dx)
@@ -64,14 +67,14 @@ def brute_tag(tri, n, dx, origin):
                     P0, P1 = centre(i, j, k), centre(i2, j2, k2)
                     best = None
                     for (A, B, C) in T:
-                        t = seg_tri(P0, P1, A, B, C)
+                        t = seg_tri(P0, P1, A, B, C, eps)
                         if t is not None:
                             best = t if best is None else min(best, t)
                     if best is None:
                         continue
                     worst = None
                     for (A, B, C) in T:
-                        t = seg_tri(P0, P1, A, B, C)
+                        t = seg_tri(P0, P1, A, B, C, eps)
                         if t is not None:
                             worst = t if worst is None else max(worst, t)
                     out[(ca, 2 * ax + 1)] = best

@@ -79,6 +79,53 @@ def test_tag_sphere32_and_dirty128_bit_exact():
         assert np.array_equal(ot.view(np.uint64), gt.view(np.uint64))
 
 
+@pytest.mark.parametrize("eps", [0.02, 0.3])
+def test_tag_bary_eps_bit_exact(eps):
+    """The ray test's tolerance: blocked bits and theta bit-exact with the oracle at the
+    same bary_eps on a random soup and on the dirty sphere (its gaps partly close), and
+    the stencils built from the context's compact tagging bit-exact too."""
+    rng = np.random.default_rng(11)
+    g = _grid((13, 11, 9), 0.7, (-0.3, 0.2, 0.1))
+    soup = rng.uniform(0, 1, (60, 3, 3)) * np.array([13, 11, 9]) * 0.7 + np.array([-0.3, 0.2, 0.1])
+    case = inputs.case_dirty_sphere128()
+    for gg, tri in ((g, soup), (_grid(case.n, case.dx, case.origin, case.bc, case.u_in), case.tri)):
+        print("case bary_eps", eps, gg.n, flush=True)
+        ob, ot = tagging.tag(tri, gg.n, gg.dx, gg.origin, eps)
+        o0, _ = tagging.tag(tri, gg.n, gg.dx, gg.origin)
+        s = _solver(gg)
+        gb, gt = s.tag(tri, bary_eps=eps)
+        assert np.array_equal(ob, gb.cpu().numpy())
+        assert np.array_equal(ot.view(np.uint64), gt.cpu().numpy().view(np.uint64))
+        assert np.count_nonzero(ob & ~o0) > 0
+        st = flow.build_stencils(gg, ob, ot)
+        flags, label = s.build(gb)
+        assert np.array_equal(flags.cpu().numpy().view(np.uint16), st.flags)
+        assert np.array_equal(label.cpu().numpy(), st.label)
+        s.close()
+
+
+def test_build_from_compact_tagging_checks_the_blocked_bits():
+    """Without theta the build reads the context's compact tagging, which belongs to the
+    tagging's own blocked bits: other bits are refused, and a second build from the same
+    (released) tagging is refused."""
+    case = inputs.case_sphere32()
+    g = _grid(case.n, case.dx, case.origin, case.bc, case.u_in)
+    s = _solver(g)
+    gb, _ = s.tag(case.tri, want_theta=False)
+    other = gb.clone()
+    other.view(-1)[int(torch.nonzero(gb.view(-1))[0])] ^= 1
+    print("case compact tagging checks", flush=True)
+    with pytest.raises(ibm.IBMError):
+        s.build(other)
+    s.build(gb)
+    with pytest.raises(ibm.IBMError):
+        s.build(gb)
+    for bad in (-0.1, 0.6):
+        with pytest.raises(ibm.IBMError):
+            s.tag(case.tri, bary_eps=bad)
+    s.close()
+
+
 def test_tag_invalid_coordinates_rejected():
     g = _grid((8, 8, 8))
     s = _solver(g)
@@ -331,8 +378,24 @@ def test_mixed_forced_stall_falls_back_to_fp64():
     x = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
     rc, stats = s.poisson(torch.from_numpy(b).cuda(), x, tol=1e-10, max_iter=20000,
                           kind=ibm.SOLVER_FCG_JACOBI, inner_tol=1e-2, force_stall=1)
-    assert rc == 0 and stats["fallback_used"] == 1
+    assert rc == 0 and stats["fallback_used"] == 1 and stats["iters_fallback"] > 0
     assert stats["rel_residual"] <= 1e-10 * 1.0001
+
+
+@pytest.mark.parametrize("restart", [0, 1])
+def test_mixed_fresh_direction_segments(restart):
+    """Segments restarted from a fresh direction (every segment, or the retry of a
+    stalled one, forced by the test hook) reach the FP64 tolerance without the FP64
+    fallback."""
+    g, s, st, p_true, b = _manufactured(9)
+    print("case mixed fresh segments", restart, flush=True)
+    x = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    rc, stats = s.poisson(torch.from_numpy(b).cuda(), x, tol=1e-10, max_iter=20000,
+                          kind=ibm.SOLVER_FCG_JACOBI, inner_tol=1e-2, inner_restart=restart,
+                          force_stall=0 if restart else 2)
+    print("  %s" % stats, flush=True)
+    assert rc == 0 and stats["fallback_used"] == 0 and stats["iters_fallback"] == 0
+    assert stats["rel_residual"] <= 1e-10 * 1.0001 and stats["iters_outer"] >= 2
 
 
 def test_mixed_precision_step_error_stated():

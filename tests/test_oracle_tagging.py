@@ -66,9 +66,9 @@ def test_crossing_sign_matches_rationals():
         assert tagging.crossing_sign(pu, pv, t, A, B, C, k) == (s > 0) - (s < 0)
 
 
-def _compare_brute(tri, n, dx=1.0, origin=(0.0, 0.0, 0.0)):
-    blocked, theta = tagging.tag(tri, n, dx, origin)
-    ref = brute_tag(tri, n, dx, origin)
+def _compare_brute(tri, n, dx=1.0, origin=(0.0, 0.0, 0.0), eps=0.0):
+    blocked, theta = tagging.tag(tri, n, dx, origin, eps)
+    ref = brute_tag(tri, n, dx, origin, eps)
     bf = blocked.ravel()
     tf = theta.reshape(-1, 6)
     got = {(c, d) for c in range(len(bf)) for d in range(6) if (bf[c] >> d) & 1}
@@ -233,3 +233,56 @@ def test_geometry_outside_domain_ignored():
     tri = _box((-3.0, -3.0, -3.0), (-1.0, -1.0, -1.0))
     b, th = tagging.tag(tri, (4, 4, 4), 1.0, (0, 0, 0))
     assert b.sum() == 0 and np.all(th == 2.0)
+
+
+# ------------------------------------------------- tolerance of the ray test
+
+@pytest.mark.parametrize("eps", [0.02, 0.1, 0.5])
+def test_bary_eps_brute_force_random_soup(eps):
+    """With the tolerance the oracle blocks exactly the segments that meet some triangle
+    widened to barycentric coordinates >= -eps, solved in rational arithmetic, and its
+    theta is the nearest such crossing (rounding aside)."""
+    rng = np.random.default_rng(13)
+    n = (6, 5, 4)
+    tri = rng.uniform(0.0, 6.0, (14, 3, 3)) * np.array([1.0, 5 / 6, 4 / 6])
+    _compare_brute(tri, n, eps=eps)
+
+
+def test_bary_eps_closes_a_gap_between_triangles():
+    """Two triangles of a plate z = 2.3 that leave a slit between them: the grid line
+    through the slit passes at barycentric distance 0.0204 from the nearer triangle, so
+    it leaks at eps = 0 and 0.015 and is blocked from 0.025 on, with theta the plane's
+    distance from the cell centre."""
+    h = 3.0
+    # the line x = y = 1.5 would lie on the hypotenuse x + y = 3 of a right triangle with
+    # 3-cell legs; the legs end at 2.94 instead (barycentric distance 0.0204 from the
+    # line); the second triangle's hypotenuse x + y = 3.56 is 0.23 away
+    A1 = [(0.0, 0.0, 2.3), (h - 0.06, 0.0, 2.3), (0.0, h - 0.06, 2.3)]
+    A2 = [(h, h, 2.3), (0.56, h, 2.3), (h, 0.56, 2.3)]
+    tri = np.array([A1, A2])
+    n = (4, 4, 4)
+    seg = (1 + 4 * (1 + 4 * 1), 5)     # cell (1, 1, 1), +z: crosses z = 2.3 only through the slit
+    for eps, blocked in ((0.0, False), (0.015, False), (0.025, True), (0.2, True)):
+        b, th = tagging.tag(tri, n, 1.0, (0, 0, 0), eps)
+        bit = (b.ravel()[seg[0]] >> seg[1]) & 1
+        assert bool(bit) == blocked, eps
+        if blocked:
+            assert abs(th.reshape(-1, 6)[seg] - 0.8) < 1e-12
+            assert (b.ravel()[seg[0] + 16] >> 4) & 1          # the cell above sees it too
+
+
+def test_bary_eps_is_monotone():
+    """A larger tolerance blocks a superset of segments, and where both block, the
+    nearest crossing can only come closer."""
+    tri = inputs.dirty_sphere(16, 5.0, seed=3, level=3) + np.array([0.3, -0.2, 0.1])
+    n = (16, 16, 16)
+    prev_b, prev_t = tagging.tag(tri, n, 1.0, (0, 0, 0), 0.0)
+    for eps in (0.01, 0.05, 0.2):
+        b, t = tagging.tag(tri, n, 1.0, (0, 0, 0), eps)
+        assert np.all((prev_b & ~b) == 0)
+        both = (prev_b[..., None] >> np.arange(6)) & (b[..., None] >> np.arange(6)) & 1
+        assert np.all(t[both == 1] <= prev_t[both == 1])
+        assert (b & ~prev_b).any() or eps == 0.01
+        prev_b, prev_t = b, t
+    with pytest.raises(ValueError):
+        tagging.tag(tri, n, 1.0, (0, 0, 0), 0.6)
