@@ -218,7 +218,7 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
                             tol=args.tol if tol is None else tol,
                             max_iter=20000, check_every=16, kind=kind,
                             inner_tol=args.inner_tol_learned if solver == "mixed_learned" else args.inner_tol,
-                            inner_max_iter=2000)
+                            inner_max_iter=2000, inner_restart=args.inner_restart)
         ctl["dt_prev"] = dt
         return p
 
@@ -356,8 +356,11 @@ def shepard_timing(case, s, st, torch, calls=20):
     return out
 
 
-# momentum predictor kernel k_predict<double>: reads u, U, H^{n-1} (24 B each), nu_t
-# (8 B) and the mask, writes u* and H (24 B each)
+# momentum predictor, FP64 (timing slot 9 brackets both of its parts: the plain sweep
+# k_predict_fast<double, 2> over the cells without a blocked or domain face and the
+# per-cell form k_fix<PredictOp<double>> over the others; with the hybrid QUICK face
+# value the per-cell form k_all<PredictOp<double>> covers every cell): reads u, U, H^{n-1}
+# (24 B each), nu_t (8 B) and the mask, writes u* and H (24 B each)
 PREDICT_BYTES_PER_CELL = 129
 
 
@@ -365,7 +368,9 @@ def predictor_record(case, slot, face):
     N = case.n[0] * case.n[1] * case.n[2]
     ms, launches = slot
     avg = ms / 1e3 / max(launches, 1)
-    return {"kernel": "k_predict<double>", "face_value": face, "launches": launches,
+    kern = ("k_predict_fast<double, 2> + k_fix<PredictOp<double>>" if face == "central"
+            else "k_all<PredictOp<double>>")
+    return {"kernel": kern, "face_value": face, "launches": launches,
             "avg_launch_us": round(avg * 1e6, 2), "bytes_per_cell": PREDICT_BYTES_PER_CELL,
             "achieved_gbs": round(PREDICT_BYTES_PER_CELL * N / avg / 1e9, 1) if avg > 0 else None,
             "frac": round(PREDICT_BYTES_PER_CELL * N / avg / 1e9 / HBM_PEAK_GBS, 4) if avg > 0 else None}
@@ -650,6 +655,8 @@ def main():
     ap.add_argument("--inner-tol-learned", type=float, default=1e-5,
                     help="mixed+learned solve: the same per segment (flexible CG restarts at each "
                          "replacement, so it favours fewer, longer segments)")
+    ap.add_argument("--inner-restart", type=int, default=0,
+                    help="mixed solve: 1 = start every FP32 segment from a fresh search direction")
     ap.add_argument("--solver", default="mixed_learned", choices=["mixed", "mixed_learned", "pcg_fp64"],
                     help="headline solver (the metric names mixed+learned); plain FP64 and mixed always run")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned solver")

@@ -194,7 +194,8 @@ int ibm_destroy(ibm_ctx* c) try {
     void* ps[] = {c->mask, c->pcode, c->flags, c->label, c->cut_off, c->cut_cell, c->cut_dir,
                   c->cut_theta, c->a_ib, c->a_c, c->a_o, c->cut_opp, c->enc_cells, c->comp_start,
                   c->ustar[0], c->ustar[1], c->ustar[2], c->nut, c->b, c->bwork, c->r, c->d, c->q, c->zbuf, c->x64,
-                  c->r32, c->z32, c->d32, c->q32, c->e32, c->zprev32, c->partials, c->counter, c->solver, c->red};
+                  c->r32, c->z32, c->d32, c->q32, c->e32, c->zprev32, c->partials, c->counter, c->solver, c->red,
+                  c->spec_cells};
     for (void* p : ps) dfree(p);
     if (c->h_solver) (void)hipHostFree(c->h_solver);
     if (c->h_red) (void)hipHostFree(c->h_red);

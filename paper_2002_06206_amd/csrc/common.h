@@ -114,6 +114,12 @@ struct ibm_ctx {
     int comp_cap;
     int has_dead;
     bool stencil_ready;
+    // cells with a blocked face or on a non-periodic domain face, in cell order: the step
+    // kernels give them the full ghost and boundary treatment after a plain sweep
+    int32_t* spec_cells;
+    long long nspec;
+    long long spec_cap;
+    bool spec_ready;
     // per-step workspace
     void* ustar[3];
     void* nut;

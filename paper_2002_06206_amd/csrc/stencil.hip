@@ -326,6 +326,26 @@ int scan_exclusive(const T* in, T* out, long long n, hipStream_t s) {
     return IBM_OK;
 }
 
+// a cell with a blocked face (effective mask) or on a non-periodic domain face
+struct SpecialCell {
+    const uint8_t* mask;
+    int nx, ny, nz;
+    bool x0, x1, y0, y1, z0, z1;   // the domain face is not periodic
+    __host__ __device__ int operator()(int c) const {
+        if (mask[c]) return 1;
+        const int i = c % nx, r = c / nx, j = r % ny, k = r / ny;
+        return ((x0 && i == 0) || (x1 && i == nx - 1) || (y0 && j == 0) || (y1 && j == ny - 1) || (z0 && k == 0) ||
+                (z1 && k == nz - 1))
+                   ? 1
+                   : 0;
+    }
+};
+
+struct IsSpecial {
+    SpecialCell f;
+    __host__ __device__ bool operator()(int c) const { return f(c) != 0; }
+};
+
 int grow(void** p, size_t bytes) {
     if (*p) IBM_HIP(hipFree(*p));
     *p = nullptr;
@@ -458,6 +478,39 @@ int stencil_run(ibm_ctx* c, const uint8_t* blocked, const ThetaSrc& theta, int d
         IBM_HIP(hipFreeAsync(cells_in, s));
         IBM_HIP(hipFreeAsync(keys_in, s));
         IBM_HIP(hipFreeAsync(keys_out, s));
+    }
+    // the special-cell list of the step kernels (count, size, select in cell order)
+    {
+        c->spec_ready = false;
+        const SpecialCell f{c->mask, g.nx, g.ny, g.nz, g.bc[0] != IBM_BC_PERIODIC, g.bc[1] != IBM_BC_PERIODIC,
+                            g.bc[2] != IBM_BC_PERIODIC, g.bc[3] != IBM_BC_PERIODIC, g.bc[4] != IBM_BC_PERIODIC,
+                            g.bc[5] != IBM_BC_PERIODIC};
+        hipcub::CountingInputIterator<int> cells(0);
+        hipcub::TransformInputIterator<int, SpecialCell, hipcub::CountingInputIterator<int>> flags(cells, f);
+        int* dcount = (int*)c->counter + 10;   // spare slot of the ticket array
+        void* tmp = nullptr;
+        size_t bytes = 0;
+        IBM_HIP(hipcub::DeviceReduce::Sum(nullptr, bytes, flags, dcount, (int)N, s));
+        IBM_HIP(ibm::dev_malloc_async(&tmp, bytes, s));
+        IBM_HIP(hipcub::DeviceReduce::Sum(tmp, bytes, flags, dcount, (int)N, s));
+        IBM_HIP(hipFreeAsync(tmp, s));
+        int hcount = 0;
+        IBM_HIP(hipMemcpyAsync(&hcount, dcount, sizeof(int), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        c->nspec = hcount;
+        if (hcount > c->spec_cap) {
+            if ((rc = grow((void**)&c->spec_cells, sizeof(int32_t) * (size_t)hcount))) return rc;
+            c->spec_cap = hcount;
+        }
+        if (hcount > 0) {
+            tmp = nullptr;
+            bytes = 0;
+            IBM_HIP(hipcub::DeviceSelect::If(nullptr, bytes, cells, c->spec_cells, dcount, (int)N, IsSpecial{f}, s));
+            IBM_HIP(ibm::dev_malloc_async(&tmp, bytes, s));
+            IBM_HIP(hipcub::DeviceSelect::If(tmp, bytes, cells, c->spec_cells, dcount, (int)N, IsSpecial{f}, s));
+            IBM_HIP(hipFreeAsync(tmp, s));
+        }
+        c->spec_ready = true;
     }
     c->stencil_ready = true;
     return IBM_OK;

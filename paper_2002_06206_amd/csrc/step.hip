@@ -9,6 +9,7 @@
 // comes from HBM about once.  Cells with a blocked face take the one branch that
 // looks up the cut list (the paper's single 'if' into the dummy-cell data, Sec. 2.3.1).
 
+#include <initializer_list>
 #include <mutex>
 
 #include "common.h"
@@ -73,139 +74,66 @@ __device__ inline double far_value(const Geo& g, const Sten& st, const T* q, int
     return (double)q[nn];
 }
 
-// Work items of the z-marching step kernels: (64 x 4 column tile, z slab) pairs,
-// slab-major, so the XCD chunk map gives every XCD a contiguous run of slabs and the
-// x- and y-neighbour rows of a tile come from that XCD's L2.  The thread owns column
-// (i, j) and walks the slab's planes, carrying the values it needs from the planes
-// below and above in registers: each value comes from HBM once.
-struct ZCol {
-    int i, j, z0, z1;
-    long long col;                // i + nx j
-    long long ow, oe, os, on;     // offsets of the -x, +x, -y, +y neighbours (wrapping)
-    bool bw, be, bs, bn;          // those faces are domain faces
-    bool valid;
-};
-
-__device__ inline ZCol zcol(const Geo& g, long long w) {
-    const long long tiles = (long long)g.ntx * g.nty;
-    const int nzc = slab_count(g.nz);
-    ZCol z;
-    const int zc = (int)(w / tiles);
-    const long long t = w % tiles;
-    z.i = (int)(t % g.ntx) * TX + (int)(threadIdx.x % TX);
-    z.j = (int)(t / g.ntx) * TY + (int)(threadIdx.x / TX);
-    z.z0 = (int)((long long)g.nz * zc / nzc);
-    z.z1 = (int)((long long)g.nz * (zc + 1) / nzc);
-    z.valid = z.i < g.nx && z.j < g.ny;
-    const int i = z.i, j = z.j;
-    const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i == g.nx - 1 ? 0 : i + 1;
-    const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
-    z.col = (long long)i + (long long)g.nx * j;
-    z.ow = (long long)iw - i;
-    z.oe = (long long)ie - i;
-    z.os = (long long)g.nx * (js - j);
-    z.on = (long long)g.nx * (jn - j);
-    z.bw = i == 0 && g.bc[0] != IBM_BC_PERIODIC;
-    z.be = i == g.nx - 1 && g.bc[1] != IBM_BC_PERIODIC;
-    z.bs = j == 0 && g.bc[2] != IBM_BC_PERIODIC;
-    z.bn = j == g.ny - 1 && g.bc[3] != IBM_BC_PERIODIC;
-    return z;
-}
-
-// [w0, w1) of this block's items (XCD chunk map)
-__device__ inline void zcol_range(const Geo& g, long long& w0, long long& w1) {
-    const long long items = (long long)g.ntx * g.nty * slab_count(g.nz);
-    const int nb = gridDim.x;
-    const int ch = xcd_chunk(blockIdx.x, nb);
-    w0 = items * ch / nb;
-    w1 = items * (ch + 1) / nb;
-}
-
-inline int zcol_blocks(const Geo& g) {
-    const long long items = (long long)g.ntx * g.nty * slab_count(g.nz);
-    return (int)(items < MAX_BLOCKS ? items : MAX_BLOCKS);
-}
-
-// value of component m seen across face d of cell c: the eq. (q_axis) ghost behind a
-// blocked face, the domain-face ghost at a domain face, else the neighbour's value
-template <class T>
-__device__ inline T nb_value(const Geo& g, const Sten& st, const T* q, int m, long long c, uint8_t msk, int d,
-                             bool bnd, T inner, T qc, const double* wall) {
-    if ((msk >> d) & 1) return (T)ghost(st, q, c, msk, d, m, wall, (double)qc);
-    if (bnd) return (T)bc_ghost(g, d, m, (double)qc);
-    return inner;
-}
+// ------------------------------------------------------------------ per-cell forms
+//
+// The step kernels run in two parts.  A cell is "special" when it has a blocked face or
+// lies on a non-periodic domain face (dead-end cells are closed on all six faces): only
+// there do ghosts and boundary values enter.  The fast sweeps below compute every other
+// cell with the plain 7-point stencil, branch-free, several cells per lane; the per-cell
+// forms here then process the context's list of special cells (one thread each) with the
+// full ghost and boundary logic, which is the paper's single branch into the dummy-cell
+// data (Sec. 2.3.1).  The two parts write disjoint cells.  On grids the fast sweeps do
+// not cover (nx not a multiple of their vector width, or the hybrid QUICK face value),
+// the per-cell forms run over every cell.
 
 // Coherent structure model (Sec. 2.3): G_ij by central differences, S, W, Q, E,
-// F_CS = Q/E, C = C1 |F_CS|^(3/2), nu_t = C dx^2 sqrt(S_ij S_ij).  z-marching (see ZCol).
+// F_CS = Q/E, C = C1 |F_CS|^(3/2), nu_t = C dx^2 sqrt(S_ij S_ij).
 template <class T>
-__global__ void __launch_bounds__(NT) k_csm(Geo g, Sten st, C3<T> u, const double* wall, T* nut, double c1) {
-    long long w0, w1;
-    zcol_range(g, w0, w1);
-    const long long plane = (long long)g.nx * g.ny;
-    const T inv2dx = (T)(1.0 / (2.0 * g.dx));
-    for (long long w = w0; w < w1; ++w) {
-        const ZCol zc = zcol(g, w);
-        if (!zc.valid) continue;
-        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
-        T qb[3], qm[3];
+struct CsmOp {
+    Sten st;
+    C3<T> u;
+    const double* wall;
+    T* nut;
+    double c1;
+    __device__ void operator()(const Geo& g, int i, int j, int k) const {
+        const long long c = cidx(g, i, j, k);
+        const uint8_t msk = st.mask[c];
+        T G[3][3];
+        const T inv2dx = (T)(1.0 / (2.0 * g.dx));
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            qb[a] = u.p[a][zc.col + plane * zb];
-            qm[a] = u.p[a][zc.col + plane * zc.z0];
+            T nb[6];
+            T qc = u.p[a][c];
+            nbvals<T, T>(g, st, u.p[a], a, i, j, k, c, msk, wall, qc, nb);
+#pragma unroll
+            for (int b = 0; b < 3; ++b) G[a][b] = (nb[2 * b + 1] - nb[2 * b]) * inv2dx;
         }
-        for (int k = zc.z0; k < zc.z1; ++k) {
-            const int zt = k == g.nz - 1 ? 0 : k + 1;
-            const long long c = zc.col + plane * k;
-            const bool bb = k == 0 && g.bc[4] != IBM_BC_PERIODIC;
-            const bool bt = k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC;
-            const uint8_t msk = st.mask[c];
-            T qt[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) qt[a] = u.p[a][zc.col + plane * zt];
-            T G[3][3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const T* q = u.p[a];
-                const T qc = qm[a];
-                T nb[6];
-                nb[0] = nb_value<T>(g, st, q, a, c, msk, 0, zc.bw, q[c + zc.ow], qc, wall);
-                nb[1] = nb_value<T>(g, st, q, a, c, msk, 1, zc.be, q[c + zc.oe], qc, wall);
-                nb[2] = nb_value<T>(g, st, q, a, c, msk, 2, zc.bs, q[c + zc.os], qc, wall);
-                nb[3] = nb_value<T>(g, st, q, a, c, msk, 3, zc.bn, q[c + zc.on], qc, wall);
-                nb[4] = nb_value<T>(g, st, q, a, c, msk, 4, bb, qb[a], qc, wall);
-                nb[5] = nb_value<T>(g, st, q, a, c, msk, 5, bt, qt[a], qc, wall);
-#pragma unroll
-                for (int b = 0; b < 3; ++b) G[a][b] = (nb[2 * b + 1] - nb[2 * b]) * inv2dx;
-            }
-            T SS = 0, WW = 0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    T s = (T)0.5 * (G[a][b] + G[b][a]);
-                    T w = (T)0.5 * (G[a][b] - G[b][a]);
-                    SS += s * s;
-                    WW += w * w;
-                }
-            T Q = (T)0.5 * (WW - SS);
-            T E = (T)0.5 * (WW + SS);
-            T F = E > (T)0 ? Q / E : (T)0;
-            T aF = F < (T)0 ? -F : F;
-            T C = (T)c1 * aF * sqrt(aF);
-            nut[c] = C * (T)(g.dx * g.dx) * sqrt(SS);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                qb[a] = qm[a];
-                qm[a] = qt[a];
-            }
-        }
+        nut[c] = csm_value<T>(G, c1, g.dx);
     }
-}
+    template <class TT>
+    __device__ static TT csm_value(const TT (&G)[3][3], double c1, double dx) {
+        TT SS = 0, WW = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                TT s = (TT)0.5 * (G[a][b] + G[b][a]);
+                TT w = (TT)0.5 * (G[a][b] - G[b][a]);
+                SS += s * s;
+                WW += w * w;
+            }
+        TT Q = (TT)0.5 * (WW - SS);
+        TT E = (TT)0.5 * (WW + SS);
+        TT F = E > (TT)0 ? Q / E : (TT)0;
+        TT aF = F < (TT)0 ? -F : F;
+        TT C = (TT)c1 * aF * sqrt(aF);
+        return C * (TT)(dx * dx) * sqrt(SS);
+    }
+};
 
 // Momentum predictor (Sec. 2.1, explicit Adams-Bashforth form):
 // H = -(1/dx) sum_f s U_f (q_c + q_nb)/2 + (1/dx^2) sum_f (nu + nu_t,f)(q_nb - q_c) + g,
-// u* = u + dt (3/2 H - 1/2 H_prev), forward Euler on the first step.  q_nb is the
+// u* = u + dt ((1 + r/2) H - (r/2) H_prev), forward Euler on the first step.  q_nb is the
 // eq. (q_axis) ghost behind blocked faces, which realises the direct forcing of
 // eq. (forcing_term).  Dead-end cells are frozen at their mean wall velocity.
 // The face value is the hybrid of Sec. 3: the central (q_c + q_nb)/2 blended with
@@ -216,119 +144,87 @@ __global__ void __launch_bounds__(NT) k_csm(Geo g, Sten st, C3<T> u, const doubl
 // right-hand side dt H of the increment system into rhs (dv - u at dead-end cells) and
 // u* only at dead-end cells (dv); H goes to hio as in the explicit form.
 template <class T>
-__global__ void __launch_bounds__(NT) k_predict(Geo g, Sten st, C3<T> u, C3<double> U, const T* nut, V3<T> hio,
-                                                V3<T> us, const double* wall, double dt, double w_now,
-                                                double w_prev, double nu, double bx, double by, double bz,
-                                                int first, int cn, V3<T> rhs, double quick) {
-    long long w0, w1;
-    zcol_range(g, w0, w1);
-    const long long plane = (long long)g.nx * g.ny;
-    const double body[3] = {bx, by, bz};
-    const T idx = (T)(1.0 / g.dx);
-    const T idx2 = (T)(1.0 / (g.dx * g.dx));
-    for (long long w = w0; w < w1; ++w) {
-        const ZCol zc = zcol(g, w);
-        if (!zc.valid) continue;
-        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
-        // carried from the planes below / of the cell: u (3), nu_t, and U_z on the +z face
-        // of the plane below (the cell's -z face)
-        T qb[3], qm[3];
+struct PredictOp {
+    Sten st;
+    C3<T> u;
+    C3<double> U;
+    const T* nut;
+    V3<T> hio, us, rhs;
+    const double* wall;
+    double dt, w_now, w_prev, nu, body[3], quick;
+    int first, cn;
+    __device__ void operator()(const Geo& g, int i, int j, int k) const {
+        const T idx = (T)(1.0 / g.dx);
+        const T idx2 = (T)(1.0 / (g.dx * g.dx));
+        const long long c = cidx(g, i, j, k);
+        const uint8_t msk = st.mask[c];
+        const T nut_c = nut[c];
+        T visc[6];
+        T Uf[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            bool bnd;
+            const long long n = nb_index(g, i, j, k, d, bnd);
+            const bool closed = bnd || ((msk >> d) & 1);
+            visc[d] = (T)nu + (closed ? nut_c : (T)0.5 * (nut_c + nut[n]));
+            const int ax = d >> 1;
+            if (d & 1) {
+                Uf[d] = (T)U.p[ax][c];
+            } else if (bnd) {
+                Uf[d] = g.bc[d] == IBM_BC_INFLOW ? (T)g.uin[ax] : (T)0;
+            } else {
+                Uf[d] = (T)U.p[ax][n];
+            }
+        }
+        const int nbits = __builtin_popcount((unsigned)msk);
+        const bool dead = st.has_dead && nbits >= 5 && ((st.flags[c] >> 14) & 1);
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            qb[m] = u.p[m][zc.col + plane * zb];
-            qm[m] = u.p[m][zc.col + plane * zc.z0];
-        }
-        T nub = nut[zc.col + plane * zb], num = nut[zc.col + plane * zc.z0];
-        double uzb = U.p[2][zc.col + plane * zb];
-        for (int k = zc.z0; k < zc.z1; ++k) {
-            const int zt = k == g.nz - 1 ? 0 : k + 1;
-            const long long c = zc.col + plane * k;
-            const bool bnd[6] = {zc.bw, zc.be, zc.bs, zc.bn, k == 0 && g.bc[4] != IBM_BC_PERIODIC,
-                                 k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC};
-            const long long off[4] = {zc.ow, zc.oe, zc.os, zc.on};
-            const uint8_t msk = st.mask[c];
-            T qt[3];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) qt[m] = u.p[m][zc.col + plane * zt];
-            const T nut_t = nut[zc.col + plane * zt];
-            const T nut_c = num;
-            const T nutn[6] = {nut[c + zc.ow], nut[c + zc.oe], nut[c + zc.os], nut[c + zc.on], nub, nut_t};
-            T visc[6];
-            T Uf[6];
+            const T qc = u.p[m][c];
+            T nb[6];
+            nbvals<T, T>(g, st, u.p[m], m, i, j, k, c, msk, wall, qc, nb);
+            T h = (T)body[m];
 #pragma unroll
             for (int d = 0; d < 6; ++d) {
-                const bool closed = bnd[d] || ((msk >> d) & 1);
-                visc[d] = (T)nu + (closed ? nut_c : (T)0.5 * (nut_c + nutn[d]));
-                const int ax = d >> 1;
-                if (d & 1) {
-                    Uf[d] = (T)U.p[ax][c];
-                } else if (bnd[d]) {
-                    Uf[d] = g.bc[d] == IBM_BC_INFLOW ? (T)g.uin[ax] : (T)0;
-                } else {
-                    Uf[d] = d == 4 ? (T)uzb : (T)U.p[ax][c + off[d]];
-                }
-            }
-            const int nbits = __builtin_popcount((unsigned)msk);
-            bool dead = st.has_dead && nbits >= 5 && ((st.flags[c] >> 14) & 1);
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const T* q = u.p[m];
-                const T qc = qm[m];
-                T nb[6];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) nb[d] = nb_value<T>(g, st, q, m, c, msk, d, bnd[d], q[c + off[d]], qc, wall);
-                nb[4] = nb_value<T>(g, st, q, m, c, msk, 4, bnd[4], qb[m], qc, wall);
-                nb[5] = nb_value<T>(g, st, q, m, c, msk, 5, bnd[5], qt[m], qc, wall);
-                T h = (T)body[m];
-#pragma unroll
-                for (int d = 0; d < 6; ++d) {
-                    T s = (d & 1) ? (T)1 : (T)-1;
-                    T qf = (T)0.5 * (qc + nb[d]);
-                    if (quick != 0.0) {
-                        T qq;
-                        if (s * Uf[d] > (T)0) {
-                            qq = ((T)6 * qc + (T)3 * nb[d] - nb[d ^ 1]) / (T)8;
-                        } else {
-                            const T n2 = (bnd[d] || ((msk >> d) & 1))
-                                             ? (T)2 * nb[d] - qc
-                                             : (T)far_value(g, st, q, m, zc.i, zc.j, k, d, wall);
-                            qq = ((T)6 * nb[d] + (T)3 * qc - n2) / (T)8;
-                        }
-                        qf = (T)(1.0 - quick) * qf + (T)quick * qq;
+                const T s = (d & 1) ? (T)1 : (T)-1;
+                T qf = (T)0.5 * (qc + nb[d]);
+                if (quick != 0.0) {
+                    T qq;
+                    if (s * Uf[d] > (T)0) {
+                        qq = ((T)6 * qc + (T)3 * nb[d] - nb[d ^ 1]) / (T)8;
+                    } else {
+                        bool bnd;
+                        (void)nb_index(g, i, j, k, d, bnd);
+                        const T n2 = (bnd || ((msk >> d) & 1)) ? (T)2 * nb[d] - qc
+                                                               : (T)far_value(g, st, u.p[m], m, i, j, k, d, wall);
+                        qq = ((T)6 * nb[d] + (T)3 * qc - n2) / (T)8;
                     }
-                    h = h - s * Uf[d] * qf * idx + visc[d] * (nb[d] - qc) * idx2;
+                    qf = (T)(1.0 - quick) * qf + (T)quick * qq;
                 }
-                T v;
-                if (first || cn) v = qc + (T)dt * h;
-                else v = qc + (T)dt * ((T)w_now * h - (T)w_prev * hio.p[m][c]);
-                T b = (T)dt * h;
-                if (dead) {
-                    uint32_t id0 = st.cut_off[c];
-                    double acc = 0.0;
-                    for (int qi = 0; qi < nbits; ++qi) acc += wall ? wall[3 * (long long)(id0 + qi) + m] : 0.0;
-                    v = (T)(acc / (double)nbits);
-                    b = v - qc;
-                    h = (T)0;
-                }
-                if (cn) {
-                    rhs.p[m][c] = b;
-                    if (dead) us.p[m][c] = v;
-                } else {
-                    us.p[m][c] = v;
-                }
-                hio.p[m][c] = h;
+                h = h - s * Uf[d] * qf * idx + visc[d] * (nb[d] - qc) * idx2;
             }
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                qb[m] = qm[m];
-                qm[m] = qt[m];
+            T v;
+            if (first || cn) v = qc + (T)dt * h;
+            else v = qc + (T)dt * ((T)w_now * h - (T)w_prev * hio.p[m][c]);
+            T b = (T)dt * h;
+            if (dead) {
+                const uint32_t id0 = st.cut_off[c];
+                double acc = 0.0;
+                for (int q = 0; q < nbits; ++q) acc += wall ? wall[3 * (long long)(id0 + q) + m] : 0.0;
+                v = (T)(acc / (double)nbits);
+                b = v - qc;
+                h = (T)0;
             }
-            nub = num;
-            num = nut_t;
-            uzb = U.p[2][c];
+            if (cn) {
+                rhs.p[m][c] = b;
+                if (dead) us.p[m][c] = v;
+            } else {
+                us.p[m][c] = v;
+            }
+            hio.p[m][c] = h;
         }
     }
-}
+};
 
 // normal wall velocity on the +k face of cell c (blocked): mean of the two cuts
 // that see the face, one from each side
@@ -344,104 +240,509 @@ __device__ inline double wall_face(const Sten& st, long long c, uint8_t msk, lon
 
 // Face velocity U* and b = div(U*)/dt (eq. poisson).  U* is the mean of the two
 // predicted cell velocities on open faces, the wall normal velocity on blocked faces
-// and the boundary value on domain faces.  Each thread also evaluates its -faces, so
-// the kernel needs no second pass.
+// and the boundary value on domain faces.  Each cell also evaluates its -faces, so no
+// second pass is needed.
 template <class T>
-__global__ void __launch_bounds__(NT) k_rhs(Geo g, Sten st, C3<T> us, V3<double> U, double* b,
-                                            const double* wall, double dt) {
-    long long w0, w1;
-    zcol_range(g, w0, w1);
-    const long long plane = (long long)g.nx * g.ny;
-    const double idx = 1.0 / g.dx;
-    for (long long w = w0; w < w1; ++w) {
-        const ZCol zc = zcol(g, w);
-        if (!zc.valid) continue;
-        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
-        // u*_z of the planes below and of the cell (the only component needed across z)
-        double wb = (double)us.p[2][zc.col + plane * zb], wm = (double)us.p[2][zc.col + plane * zc.z0];
-        for (int k = zc.z0; k < zc.z1; ++k) {
-            const int zt = k == g.nz - 1 ? 0 : k + 1;
-            const long long c = zc.col + plane * k;
-            const double wt = (double)us.p[2][zc.col + plane * zt];
-            const uint8_t msk = st.mask[c];
-            const bool bp3[3] = {zc.be, zc.bn, k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC};
-            const bool bm3[3] = {zc.bw, zc.bs, k == 0 && g.bc[4] != IBM_BC_PERIODIC};
-            const int kb = k == 0 ? g.nz - 1 : k - 1;
-            const long long np3[3] = {c + zc.oe, c + zc.on, zc.col + plane * zt};
-            const long long nm3[3] = {c + zc.ow, c + zc.os, zc.col + plane * kb};
-            double div = 0.0;
+struct RhsOp {
+    Sten st;
+    C3<T> us;
+    V3<double> U;
+    double* b;
+    const double* wall;
+    double dt;
+    __device__ void operator()(const Geo& g, int i, int j, int k) const {
+        const double idx = 1.0 / g.dx;
+        const long long c = cidx(g, i, j, k);
+        const uint8_t msk = st.mask[c];
+        double div = 0.0;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double qc = a == 2 ? wm : (double)us.p[a][c];
-                const int dp = 2 * a + 1, dm = 2 * a;
-                const bool bp = bp3[a], bm = bm3[a];
-                const long long np = np3[a], nm = nm3[a];
-                const double qp = a == 2 ? wt : (double)us.p[a][np];
-                const double qmv = a == 2 ? wb : (double)us.p[a][nm];
-                double Up, Um;
-                if ((msk >> dp) & 1) Up = wall_face<T>(st, c, msk, np, a, wall);
-                else if (bp) Up = g.bc[dp] == IBM_BC_INFLOW ? g.uin[a] : (g.bc[dp] == IBM_BC_OUTFLOW ? qc : 0.0);
-                else Up = 0.5 * (qc + qp);
-                if ((msk >> dm) & 1) Um = wall_face<T>(st, nm, st.mask[nm], c, a, wall);
-                else if (bm) Um = g.bc[dm] == IBM_BC_INFLOW ? g.uin[a] : 0.0;
-                else Um = 0.5 * (qmv + qc);
-                U.p[a][c] = Up;
-                div += (Up - Um) * idx;
-            }
-            b[c] = div / dt;
-            wb = wm;
-            wm = wt;
+        for (int a = 0; a < 3; ++a) {
+            const double qc = (double)us.p[a][c];
+            const int dp = 2 * a + 1, dm = 2 * a;
+            bool bp, bm;
+            const long long np = nb_index(g, i, j, k, dp, bp);
+            const long long nm = nb_index(g, i, j, k, dm, bm);
+            double Up, Um;
+            if ((msk >> dp) & 1) Up = wall_face<T>(st, c, msk, np, a, wall);
+            else if (bp) Up = g.bc[dp] == IBM_BC_INFLOW ? g.uin[a] : (g.bc[dp] == IBM_BC_OUTFLOW ? qc : 0.0);
+            else Up = 0.5 * (qc + (double)us.p[a][np]);
+            if ((msk >> dm) & 1) Um = wall_face<T>(st, nm, st.mask[nm], c, a, wall);
+            else if (bm) Um = g.bc[dm] == IBM_BC_INFLOW ? g.uin[a] : 0.0;
+            else Um = 0.5 * ((double)us.p[a][nm] + qc);
+            U.p[a][c] = Up;
+            div += (Up - Um) * idx;
         }
+        b[c] = div / dt;
     }
-}
+};
 
 // Correction (eq. correction): U = U* - dt (p_nb - p_c)/dx on open faces, U* + 2 dt p_c/dx
 // on outlet faces (p = 0 on the face), unchanged on blocked/inflow/slip faces;
 // u = u* - dt (p_E - p_W)/(2 dx) with the Neumann ghost p_c behind blocked, inflow and
 // slip faces and the Dirichlet ghost -p_c behind outlet faces.
 template <class T>
-__global__ void __launch_bounds__(NT) k_project(Geo g, Sten st, C3<T> us, V3<double> U, const double* p, V3<T> u,
-                                                double dt) {
-    long long w0, w1;
-    zcol_range(g, w0, w1);
+struct ProjectOp {
+    Sten st;
+    C3<T> us;
+    V3<double> U;
+    const double* p;
+    V3<T> u;
+    double dt;
+    __device__ void operator()(const Geo& g, int i, int j, int k) const {
+        const double idx = 1.0 / g.dx;
+        const long long c = cidx(g, i, j, k);
+        const uint8_t msk = st.mask[c];
+        const double pc = p[c];
+        const bool dead = st.has_dead && __builtin_popcount((unsigned)msk) >= 5 && ((st.flags[c] >> 14) & 1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int dp = 2 * a + 1, dm = 2 * a;
+            bool bp, bm;
+            const long long np = nb_index(g, i, j, k, dp, bp);
+            const long long nm = nb_index(g, i, j, k, dm, bm);
+            const bool openp = !bp && !((msk >> dp) & 1);
+            const bool openm = !bm && !((msk >> dm) & 1);
+            const bool outp = bp && g.bc[dp] == IBM_BC_OUTFLOW;
+            const bool outm = bm && g.bc[dm] == IBM_BC_OUTFLOW;
+            const double pE = openp ? p[np] : (outp ? -pc : pc);
+            const double pW = openm ? p[nm] : (outm ? -pc : pc);
+            double Uc = U.p[a][c];
+            if (openp) Uc = Uc - dt * (pE - pc) * idx;
+            else if (outp) Uc = Uc + 2.0 * dt * pc * idx;
+            U.p[a][c] = Uc;
+            const double usc = (double)us.p[a][c];
+            const double v = dead ? usc : usc - dt * (pE - pW) / (2.0 * g.dx);
+            u.p[a][c] = (T)v;
+        }
+    }
+};
+
+// every cell (tile walk with the XCD chunk map)
+template <class Op>
+__global__ void __launch_bounds__(NT) k_all(Geo g, Op op) {
+    long long t0, t1;
+    tile_range(g, t0, t1);
+    for (long long t = t0; t < t1; ++t) {
+        int i, j, k;
+        if (!tile_cell(g, t, i, j, k)) continue;
+        op(g, i, j, k);
+    }
+}
+
+// the listed (special) cells, one thread each
+template <class Op>
+__global__ void __launch_bounds__(NT) k_fix(Geo g, const int32_t* __restrict__ cells, long long n, Op op) {
+    for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n; e += (long long)gridDim.x * NT) {
+        const long long c = cells[e];
+        const int i = (int)(c % g.nx);
+        const int j = (int)((c / g.nx) % g.ny);
+        const int k = (int)(c / ((long long)g.nx * g.ny));
+        op(g, i, j, k);
+    }
+}
+
+// ------------------------------------------------------------------ fast sweeps
+//
+// Work item = (tile of 64 lanes x V cells in x by TY rows, z slab), slab-major with the
+// XCD chunk map.  Each lane owns V consecutive cells of one row and walks the slab's
+// planes, carrying the planes below and above in registers; x neighbours inside the V
+// cells are register shifts, the two outer ones single loads, y neighbours vector loads
+// from the L2.  A cell is written only when it is not special.
+
+template <class T, int V>
+__device__ inline void vload(const T* __restrict__ p, long long c, T (&o)[V]) {
+    constexpr int B = (int)sizeof(T) * V;
+    static_assert(B == 8 || B == 16 || B == 32, "vector width");
+    if constexpr (B == 8) {
+        const uint2 w = *reinterpret_cast<const uint2*>(p + c);
+        __builtin_memcpy(o, &w, 8);
+    } else if constexpr (B == 16) {
+        const uint4 w = *reinterpret_cast<const uint4*>(p + c);
+        __builtin_memcpy(o, &w, 16);
+    } else {
+        const uint4 w0 = *reinterpret_cast<const uint4*>(p + c);
+        const uint4 w1 = *reinterpret_cast<const uint4*>(p + c + V / 2);
+        __builtin_memcpy(o, &w0, 16);
+        __builtin_memcpy(reinterpret_cast<char*>(o) + 16, &w1, 16);
+    }
+}
+
+// store the cells whose bit is set in keep (all V: one vector store)
+template <class T, int V>
+__device__ inline void vstore(T* __restrict__ p, long long c, const T (&o)[V], unsigned keep) {
+    constexpr unsigned ALL = (1u << V) - 1u;
+    constexpr int B = (int)sizeof(T) * V;
+    if (keep == ALL) {
+        if constexpr (B == 8) {
+            uint2 w;
+            __builtin_memcpy(&w, o, 8);
+            *reinterpret_cast<uint2*>(p + c) = w;
+        } else if constexpr (B == 16) {
+            uint4 w;
+            __builtin_memcpy(&w, o, 16);
+            *reinterpret_cast<uint4*>(p + c) = w;
+        } else {
+            uint4 w0, w1;
+            __builtin_memcpy(&w0, o, 16);
+            __builtin_memcpy(&w1, reinterpret_cast<const char*>(o) + 16, 16);
+            *reinterpret_cast<uint4*>(p + c) = w0;
+            *reinterpret_cast<uint4*>(p + c + V / 2) = w1;
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if ((keep >> v) & 1u) p[c + v] = o[v];
+    }
+}
+
+// Column of a fast-sweep work item: V cells (i0 .. i0 + V - 1) of row j, planes z0 .. z1 - 1.
+struct VCol {
+    int i0, j, z0, z1;
+    long long col, ow, oe, os, on;   // row start; cells i0 - 1 and i0 + V; rows j -+ 1 (wrapping)
+    bool bw, be, bsn;                // first / last cell on a -x / +x domain face; row on a y domain face
+    bool valid;
+};
+
+template <int V>
+__device__ inline VCol vcol(const Geo& g, long long w, int ntxv, long long tiles, int nzc) {
+    VCol z;
+    const int zc = (int)(w / tiles);
+    const long long t = w % tiles;
+    z.i0 = (int)(t % ntxv) * (64 * V) + V * (int)(threadIdx.x % 64);
+    z.j = (int)(t / ntxv) * TY + (int)(threadIdx.x / 64);
+    z.z0 = (int)((long long)g.nz * zc / nzc);
+    z.z1 = (int)((long long)g.nz * (zc + 1) / nzc);
+    z.valid = z.i0 < g.nx && z.j < g.ny;
+    const int iw = z.i0 == 0 ? g.nx - 1 : z.i0 - 1;
+    const int ie = z.i0 + V >= g.nx ? 0 : z.i0 + V;
+    const int js = z.j == 0 ? g.ny - 1 : z.j - 1, jn = z.j == g.ny - 1 ? 0 : z.j + 1;
+    z.col = (long long)z.i0 + (long long)g.nx * z.j;
+    z.ow = (long long)iw - z.i0;
+    z.oe = (long long)ie - z.i0;
+    z.os = (long long)g.nx * (js - z.j);
+    z.on = (long long)g.nx * (jn - z.j);
+    z.bw = z.i0 == 0 && g.bc[0] != IBM_BC_PERIODIC;
+    z.be = z.i0 + V >= g.nx && g.bc[1] != IBM_BC_PERIODIC;
+    z.bsn = (z.j == 0 && g.bc[2] != IBM_BC_PERIODIC) || (z.j == g.ny - 1 && g.bc[3] != IBM_BC_PERIODIC);
+    return z;
+}
+
+// the lane's cells that are not special in plane k (bit v = cell i0 + v)
+template <int V>
+__device__ inline unsigned plain_cells(const Geo& g, const VCol& z, const uint8_t* __restrict__ mask, long long c,
+                                       int k) {
+    if (z.bsn || (k == 0 && g.bc[4] != IBM_BC_PERIODIC) || (k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC)) return 0u;
+    uint8_t m[V];
+    if constexpr (V == 4) {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(mask + c);
+        __builtin_memcpy(m, &w, 4);
+    } else {
+        const uint16_t w = *reinterpret_cast<const uint16_t*>(mask + c);
+        __builtin_memcpy(m, &w, 2);
+    }
+    unsigned keep = 0u;
+#pragma unroll
+    for (int v = 0; v < V; ++v) keep |= (m[v] == 0 ? 1u : 0u) << v;
+    if (z.bw) keep &= ~1u;
+    if (z.be) keep &= ~(1u << (V - 1));
+    return keep;
+}
+
+template <int V>
+__device__ inline void vcol_range(const Geo& g, int& ntxv, long long& tiles, int& nzc, long long& w0, long long& w1) {
+    ntxv = (g.nx + 64 * V - 1) / (64 * V);
+    tiles = (long long)ntxv * g.nty;
+    nzc = slab_count(g.nz);
+    const long long items = tiles * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    w0 = items * ch / nb;
+    w1 = items * (ch + 1) / nb;
+}
+
+template <int V>
+inline int vcol_blocks(const Geo& g) {
+    const long long items = (long long)((g.nx + 64 * V - 1) / (64 * V)) * g.nty * slab_count(g.nz);
+    return (int)(items < MAX_BLOCKS ? items : MAX_BLOCKS);
+}
+
+template <class T, int V>
+__global__ void __launch_bounds__(NT) k_csm_fast(Geo g, const uint8_t* __restrict__ mask, C3<T> u,
+                                                 T* __restrict__ nut, double c1) {
+    int ntxv, nzc;
+    long long tiles, w0, w1;
+    vcol_range<V>(g, ntxv, tiles, nzc, w0, w1);
     const long long plane = (long long)g.nx * g.ny;
-    const double idx = 1.0 / g.dx;
+    const T inv2dx = (T)(1.0 / (2.0 * g.dx));
     for (long long w = w0; w < w1; ++w) {
-        const ZCol zc = zcol(g, w);
+        const VCol zc = vcol<V>(g, w, ntxv, tiles, nzc);
         if (!zc.valid) continue;
         const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
-        double pb = p[zc.col + plane * zb], pm = p[zc.col + plane * zc.z0];
+        T qb[3][V], qm[3][V];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            vload<T, V>(u.p[a], zc.col + plane * zb, qb[a]);
+            vload<T, V>(u.p[a], zc.col + plane * zc.z0, qm[a]);
+        }
         for (int k = zc.z0; k < zc.z1; ++k) {
             const int zt = k == g.nz - 1 ? 0 : k + 1;
             const long long c = zc.col + plane * k;
-            const double pt = p[zc.col + plane * zt];
-            const uint8_t msk = st.mask[c];
-            const double pc = pm;
-            const bool bp3[3] = {zc.be, zc.bn, k == g.nz - 1 && g.bc[5] != IBM_BC_PERIODIC};
-            const bool bm3[3] = {zc.bw, zc.bs, k == 0 && g.bc[4] != IBM_BC_PERIODIC};
-            const bool dead = st.has_dead && __builtin_popcount((unsigned)msk) >= 5 && ((st.flags[c] >> 14) & 1);
+            T qt[3][V];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int dp = 2 * a + 1, dm = 2 * a;
-                const bool bp = bp3[a], bm = bm3[a];
-                const bool openp = !bp && !((msk >> dp) & 1);
-                const bool openm = !bm && !((msk >> dm) & 1);
-                const bool outp = bp && g.bc[dp] == IBM_BC_OUTFLOW;
-                const bool outm = bm && g.bc[dm] == IBM_BC_OUTFLOW;
-                const double pnp = a == 0 ? p[c + zc.oe] : (a == 1 ? p[c + zc.on] : pt);
-                const double pnm = a == 0 ? p[c + zc.ow] : (a == 1 ? p[c + zc.os] : pb);
-                const double pE = openp ? pnp : (outp ? -pc : pc);
-                const double pW = openm ? pnm : (outm ? -pc : pc);
-                double Uc = U.p[a][c];
-                if (openp) Uc = Uc - dt * (pE - pc) * idx;
-                else if (outp) Uc = Uc + 2.0 * dt * pc * idx;
-                U.p[a][c] = Uc;
-                const double usc = (double)us.p[a][c];
-                const double v = dead ? usc : usc - dt * (pE - pW) / (2.0 * g.dx);
-                u.p[a][c] = (T)v;
+            for (int a = 0; a < 3; ++a) vload<T, V>(u.p[a], zc.col + plane * zt, qt[a]);
+            const unsigned keep = plain_cells<V>(g, zc, mask, c, k);
+            if (keep) {
+                T G[V][3][3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const T* q = u.p[a];
+                    T ys[V], yn[V];
+                    vload<T, V>(q, c + zc.os, ys);
+                    vload<T, V>(q, c + zc.on, yn);
+                    const T xw = q[c + zc.ow], xe = q[c + zc.oe];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const T left = v ? qm[a][v - 1] : xw;
+                        const T right = v < V - 1 ? qm[a][v + 1] : xe;
+                        G[v][a][0] = (right - left) * inv2dx;
+                        G[v][a][1] = (yn[v] - ys[v]) * inv2dx;
+                        G[v][a][2] = (qt[a][v] - qb[a][v]) * inv2dx;
+                    }
+                }
+                T o[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) o[v] = CsmOp<T>::template csm_value<T>(G[v], c1, g.dx);
+                vstore<T, V>(nut, c, o, keep);
             }
-            pb = pm;
-            pm = pt;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    qb[a][v] = qm[a][v];
+                    qm[a][v] = qt[a][v];
+                }
+        }
+    }
+}
+
+// central face value only (the hybrid QUICK value takes the per-cell form everywhere)
+template <class T, int V>
+__global__ void __launch_bounds__(NT) k_predict_fast(Geo g, const uint8_t* __restrict__ mask, PredictOp<T> op) {
+    int ntxv, nzc;
+    long long tiles, w0, w1;
+    vcol_range<V>(g, ntxv, tiles, nzc, w0, w1);
+    const long long plane = (long long)g.nx * g.ny;
+    const T idx = (T)(1.0 / g.dx);
+    const T idx2 = (T)(1.0 / (g.dx * g.dx));
+    for (long long w = w0; w < w1; ++w) {
+        const VCol zc = vcol<V>(g, w, ntxv, tiles, nzc);
+        if (!zc.valid) continue;
+        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
+        T qb[3][V], qm[3][V], nb_[V], nm_[V];
+        double uzb[V];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            vload<T, V>(op.u.p[m], zc.col + plane * zb, qb[m]);
+            vload<T, V>(op.u.p[m], zc.col + plane * zc.z0, qm[m]);
+        }
+        vload<T, V>(op.nut, zc.col + plane * zb, nb_);
+        vload<T, V>(op.nut, zc.col + plane * zc.z0, nm_);
+        vload<double, V>(op.U.p[2], zc.col + plane * zb, uzb);
+        for (int k = zc.z0; k < zc.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = zc.col + plane * k;
+            T qt[3][V], nt_[V];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) vload<T, V>(op.u.p[m], zc.col + plane * zt, qt[m]);
+            vload<T, V>(op.nut, zc.col + plane * zt, nt_);
+            double uzc[V];
+            vload<double, V>(op.U.p[2], c, uzc);
+            const unsigned keep = plain_cells<V>(g, zc, mask, c, k);
+            if (keep) {
+                // face eddy viscosity and face velocities of the V cells, faces 0..5
+                T nys[V], nyn[V];
+                vload<T, V>(op.nut, c + zc.os, nys);
+                vload<T, V>(op.nut, c + zc.on, nyn);
+                const T nxw = op.nut[c + zc.ow], nxe = op.nut[c + zc.oe];
+                double ux[V], uy[V], uys[V];
+                vload<double, V>(op.U.p[0], c, ux);
+                vload<double, V>(op.U.p[1], c, uy);
+                vload<double, V>(op.U.p[1], c + zc.os, uys);
+                const double uxw = op.U.p[0][c + zc.ow];
+                T visc[V][6], Uf[V][6];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T nc = nm_[v];
+                    const T nn[6] = {v ? nm_[v - 1] : nxw, v < V - 1 ? nm_[v + 1] : nxe, nys[v], nyn[v], nb_[v], nt_[v]};
+#pragma unroll
+                    for (int d = 0; d < 6; ++d) visc[v][d] = (T)op.nu + (T)0.5 * (nc + nn[d]);
+                    Uf[v][0] = (T)(v ? ux[v - 1] : uxw);
+                    Uf[v][1] = (T)ux[v];
+                    Uf[v][2] = (T)uys[v];
+                    Uf[v][3] = (T)uy[v];
+                    Uf[v][4] = (T)uzb[v];
+                    Uf[v][5] = (T)uzc[v];
+                }
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const T* q = op.u.p[m];
+                    T ys[V], yn[V], hp[V];
+                    vload<T, V>(q, c + zc.os, ys);
+                    vload<T, V>(q, c + zc.on, yn);
+                    const T xw = q[c + zc.ow], xe = q[c + zc.oe];
+                    if (!(op.first || op.cn)) vload<T, V>(op.hio.p[m], c, hp);
+                    T ov[V], oh[V];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const T qc = qm[m][v];
+                        const T nb[6] = {v ? qm[m][v - 1] : xw, v < V - 1 ? qm[m][v + 1] : xe, ys[v], yn[v],
+                                         qb[m][v], qt[m][v]};
+                        T h = (T)op.body[m];
+#pragma unroll
+                        for (int d = 0; d < 6; ++d) {
+                            const T s = (d & 1) ? (T)1 : (T)-1;
+                            const T qf = (T)0.5 * (qc + nb[d]);
+                            h = h - s * Uf[v][d] * qf * idx + visc[v][d] * (nb[d] - qc) * idx2;
+                        }
+                        if (op.cn) ov[v] = (T)op.dt * h;
+                        else if (op.first) ov[v] = qc + (T)op.dt * h;
+                        else ov[v] = qc + (T)op.dt * ((T)op.w_now * h - (T)op.w_prev * hp[v]);
+                        oh[v] = h;
+                    }
+                    vstore<T, V>(op.cn ? op.rhs.p[m] : op.us.p[m], c, ov, keep);
+                    vstore<T, V>(op.hio.p[m], c, oh, keep);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    qb[m][v] = qm[m][v];
+                    qm[m][v] = qt[m][v];
+                }
+                nb_[v] = nm_[v];
+                nm_[v] = nt_[v];
+                uzb[v] = uzc[v];
+            }
+        }
+    }
+}
+
+template <class T, int V>
+__global__ void __launch_bounds__(NT) k_rhs_fast(Geo g, const uint8_t* __restrict__ mask, RhsOp<T> op) {
+    int ntxv, nzc;
+    long long tiles, w0, w1;
+    vcol_range<V>(g, ntxv, tiles, nzc, w0, w1);
+    const long long plane = (long long)g.nx * g.ny;
+    const double idx = 1.0 / g.dx;
+    for (long long w = w0; w < w1; ++w) {
+        const VCol zc = vcol<V>(g, w, ntxv, tiles, nzc);
+        if (!zc.valid) continue;
+        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
+        T wb[V], wm[V];
+        vload<T, V>(op.us.p[2], zc.col + plane * zb, wb);
+        vload<T, V>(op.us.p[2], zc.col + plane * zc.z0, wm);
+        for (int k = zc.z0; k < zc.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = zc.col + plane * k;
+            T wt[V];
+            vload<T, V>(op.us.p[2], zc.col + plane * zt, wt);
+            const unsigned keep = plain_cells<V>(g, zc, mask, c, k);
+            if (keep) {
+                double div[V], Ux[V], Uy[V], Uz[V];
+                T qx[V], qy[V], qys[V], qyn[V];
+                vload<T, V>(op.us.p[0], c, qx);
+                const double xw = (double)op.us.p[0][c + zc.ow], xe = (double)op.us.p[0][c + zc.oe];
+                vload<T, V>(op.us.p[1], c, qy);
+                vload<T, V>(op.us.p[1], c + zc.os, qys);
+                vload<T, V>(op.us.p[1], c + zc.on, qyn);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    double qc = (double)qx[v];
+                    double Up = 0.5 * (qc + (v < V - 1 ? (double)qx[v + 1] : xe));
+                    double Um = 0.5 * ((v ? (double)qx[v - 1] : xw) + qc);
+                    Ux[v] = Up;
+                    div[v] = 0.0;
+                    div[v] += (Up - Um) * idx;
+                    qc = (double)qy[v];
+                    Up = 0.5 * (qc + (double)qyn[v]);
+                    Um = 0.5 * ((double)qys[v] + qc);
+                    Uy[v] = Up;
+                    div[v] += (Up - Um) * idx;
+                    qc = (double)wm[v];
+                    Up = 0.5 * (qc + (double)wt[v]);
+                    Um = 0.5 * ((double)wb[v] + qc);
+                    Uz[v] = Up;
+                    div[v] += (Up - Um) * idx;
+                    div[v] = div[v] / op.dt;
+                }
+                vstore<double, V>(op.U.p[0], c, Ux, keep);
+                vstore<double, V>(op.U.p[1], c, Uy, keep);
+                vstore<double, V>(op.U.p[2], c, Uz, keep);
+                vstore<double, V>(op.b, c, div, keep);
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                wb[v] = wm[v];
+                wm[v] = wt[v];
+            }
+        }
+    }
+}
+
+template <class T, int V>
+__global__ void __launch_bounds__(NT) k_project_fast(Geo g, const uint8_t* __restrict__ mask, ProjectOp<T> op) {
+    int ntxv, nzc;
+    long long tiles, w0, w1;
+    vcol_range<V>(g, ntxv, tiles, nzc, w0, w1);
+    const long long plane = (long long)g.nx * g.ny;
+    const double idx = 1.0 / g.dx;
+    for (long long w = w0; w < w1; ++w) {
+        const VCol zc = vcol<V>(g, w, ntxv, tiles, nzc);
+        if (!zc.valid) continue;
+        const int zb = zc.z0 == 0 ? g.nz - 1 : zc.z0 - 1;
+        double pb[V], pm[V];
+        vload<double, V>(op.p, zc.col + plane * zb, pb);
+        vload<double, V>(op.p, zc.col + plane * zc.z0, pm);
+        for (int k = zc.z0; k < zc.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = zc.col + plane * k;
+            double pt[V];
+            vload<double, V>(op.p, zc.col + plane * zt, pt);
+            const unsigned keep = plain_cells<V>(g, zc, mask, c, k);
+            if (keep) {
+                double ps[V], pn[V];
+                vload<double, V>(op.p, c + zc.os, ps);
+                vload<double, V>(op.p, c + zc.on, pn);
+                const double pw = op.p[c + zc.ow], pe = op.p[c + zc.oe];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    double Ua[V];
+                    T ua[V];
+                    vload<double, V>(op.U.p[a], c, Ua);
+                    vload<T, V>(op.us.p[a], c, ua);
+                    double Uo[V];
+                    T uo[V];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const double pc = pm[v];
+                        const double pE = a == 0 ? (v < V - 1 ? pm[v + 1] : pe) : (a == 1 ? pn[v] : pt[v]);
+                        const double pW = a == 0 ? (v ? pm[v - 1] : pw) : (a == 1 ? ps[v] : pb[v]);
+                        double Uc = Ua[v];
+                        Uc = Uc - op.dt * (pE - pc) * idx;
+                        Uo[v] = Uc;
+                        const double usc = (double)ua[v];
+                        uo[v] = (T)(usc - op.dt * (pE - pW) / (2.0 * g.dx));
+                    }
+                    vstore<double, V>(op.U.p[a], c, Uo, keep);
+                    vstore<T, V>(op.u.p[a], c, uo, keep);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                pb[v] = pm[v];
+                pm[v] = pt[v];
+            }
         }
     }
 }
@@ -639,15 +940,52 @@ __global__ void k_zero(T* a, long long n) {
         a[i] = (T)0;
 }
 
+// vector width of the fast sweeps: 16 bytes of cell-field type per lane
+template <class T>
+constexpr int vwidth() {
+    return sizeof(T) == 4 ? 4 : 2;
+}
+
+inline bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// the fast sweeps need nx divisible by their width, aligned cell fields (T) and 16-byte
+// aligned double fields, and the special-cell list of the stencil build
+template <class T>
+bool fast_ok(const ibm_ctx* c, std::initializer_list<const void*> tf, std::initializer_list<const void*> df) {
+    constexpr int V = vwidth<T>();
+    if (c->geo.nx % V != 0 || !c->spec_ready) return false;
+    for (const void* p : tf)
+        if (!aligned(p, sizeof(T) * V)) return false;
+    for (const void* p : df)
+        if (!aligned(p, 16)) return false;
+    return aligned(c->mask, 4);
+}
+
+template <class Op>
+void fix_special(const ibm_ctx* c, const Op& op, hipStream_t s) {
+    if (c->nspec == 0) return;
+    const long long nbk = (c->nspec + NT - 1) / NT;
+    k_fix<Op><<<(int)(nbk < 16384 ? nbk : 16384), NT, 0, s>>>(c->geo, c->spec_cells, c->nspec, op);
+}
+
 template <class T>
 int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, const ibm_step_params* prm,
               hipStream_t s) {
+    constexpr int V = vwidth<T>();
     const Geo& g = c->geo;
     Sten st = sten_of(c);
     C3<T> uu{{(const T*)u[0], (const T*)u[1], (const T*)u[2]}};
     T* nut = (T*)c->nut;
+    const bool fast = fast_ok<T>(c, {u[0], u[1], u[2], h[0], h[1], h[2], nut, c->ustar[0], c->ustar[1], c->ustar[2]},
+                                 {U[0], U[1], U[2]});
     if (prm->csm_on) {
-        k_csm<T><<<zcol_blocks(g), NT, 0, s>>>(g, st, uu, wall, nut, prm->c1);
+        const CsmOp<T> op{st, uu, wall, nut, prm->c1};
+        if (fast) {
+            k_csm_fast<T, V><<<vcol_blocks<V>(g), NT, 0, s>>>(g, c->mask, uu, nut, prm->c1);
+            fix_special(c, op, s);
+        } else {
+            k_all<CsmOp<T>><<<grid_blocks(g), NT, 0, s>>>(g, op);
+        }
     } else {
         k_zero<T><<<2048, 256, 0, s>>>(nut, c->N);
     }
@@ -664,30 +1002,54 @@ int predict_t(ibm_ctx* c, void** u, double** U, void** h, const double* wall, co
         T* x = (T*)c->cn_ws;
         for (int a = 0; a < 3; ++a) rhs.p[a] = x + (long long)a * c->N;
     }
-    launch_timed(c, TK_PREDICT, k_predict<T>, zcol_blocks(g), s, g, st, uu, UU, (const T*)nut, hh, us, wall, prm->dt,
-                 1.0 + 0.5 * r, 0.5 * r, prm->nu, prm->body_force[0], prm->body_force[1], prm->body_force[2],
-                 prm->step == 0 ? 1 : 0, cn ? 1 : 0, rhs, prm->quick);
+    const PredictOp<T> op{st, uu, UU, (const T*)nut, hh, us, rhs, wall, prm->dt, 1.0 + 0.5 * r, 0.5 * r, prm->nu,
+                          {prm->body_force[0], prm->body_force[1], prm->body_force[2]}, prm->quick,
+                          prm->step == 0 ? 1 : 0, cn ? 1 : 0};
+    const bool fast_p = fast && prm->quick == 0.0 && (!cn || aligned(rhs.p[0], sizeof(T) * V));
+    // both parts of the predictor are timed together (slot TK_PREDICT)
+    timing_begin(c, TK_PREDICT, s);
+    if (fast_p) {
+        k_predict_fast<T, V><<<vcol_blocks<V>(g), NT, 0, s>>>(g, c->mask, op);
+        fix_special(c, op, s);
+    } else {
+        k_all<PredictOp<T>><<<grid_blocks(g), NT, 0, s>>>(g, op);
+    }
+    timing_end(c, TK_PREDICT, s);
     IBM_HIP(hipGetLastError());   // its events are collected after the solve's next synchronisation
     return IBM_OK;
 }
 
 template <class T>
 int rhs_t(ibm_ctx* c, double** U, const double* wall, double dt, hipStream_t s) {
+    constexpr int V = vwidth<T>();
     const Geo& g = c->geo;
     C3<T> us{{(const T*)c->ustar[0], (const T*)c->ustar[1], (const T*)c->ustar[2]}};
     V3<double> UU{{U[0], U[1], U[2]}};
-    k_rhs<T><<<zcol_blocks(g), NT, 0, s>>>(g, sten_of(c), us, UU, c->b, wall, dt);
+    const RhsOp<T> op{sten_of(c), us, UU, c->b, wall, dt};
+    if (fast_ok<T>(c, {c->ustar[0], c->ustar[1], c->ustar[2]}, {U[0], U[1], U[2], c->b})) {
+        k_rhs_fast<T, V><<<vcol_blocks<V>(g), NT, 0, s>>>(g, c->mask, op);
+        fix_special(c, op, s);
+    } else {
+        k_all<RhsOp<T>><<<grid_blocks(g), NT, 0, s>>>(g, op);
+    }
     IBM_HIP(hipGetLastError());
     return remove_means(c, c->b, s);
 }
 
 template <class T>
 int project_t(ibm_ctx* c, void** u, double** U, const double* p, double dt, hipStream_t s) {
+    constexpr int V = vwidth<T>();
     const Geo& g = c->geo;
     C3<T> us{{(const T*)c->ustar[0], (const T*)c->ustar[1], (const T*)c->ustar[2]}};
     V3<double> UU{{U[0], U[1], U[2]}};
     V3<T> uu{{(T*)u[0], (T*)u[1], (T*)u[2]}};
-    k_project<T><<<zcol_blocks(g), NT, 0, s>>>(g, sten_of(c), us, UU, p, uu, dt);
+    const ProjectOp<T> op{sten_of(c), us, UU, p, uu, dt};
+    if (fast_ok<T>(c, {c->ustar[0], c->ustar[1], c->ustar[2], u[0], u[1], u[2]}, {U[0], U[1], U[2], p})) {
+        k_project_fast<T, V><<<vcol_blocks<V>(g), NT, 0, s>>>(g, c->mask, op);
+        fix_special(c, op, s);
+    } else {
+        k_all<ProjectOp<T>><<<grid_blocks(g), NT, 0, s>>>(g, op);
+    }
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
