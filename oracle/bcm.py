@@ -21,10 +21,19 @@ What is computed (plain FP64 numpy, one halo cell at a time, from the definition
   the neighbours summed in the order -x, +x, -y, +y, -z, +z, read from the cube's own
   storage (halos included).
 
+* Immersed geometry on the cubes (set_blocked): each level is tagged as a uniform grid
+  of its own cell size over the whole domain (Sec. 2.3.1, the axis-projected segment
+  test), and every cube takes the blocked bits of its cells from its level's grid.  A
+  blocked face carries the pressure ghost p_GC = p_c (the Neumann case of eq. (Mittal),
+  reading G3), so the operator adds x_c in place of the neighbour; a red-black SOR
+  update divides by the number of open faces (-open / dx^2), and a cell without open
+  faces keeps its value.
+
 Readings: n = 16 cells per cube axis (the paper's figure shows 8, its text gives the
 structure only); mirror halos at the domain boundary (the paper omits the outer boundary
 conditions); the cube order above (an interface, chosen to make the fine cubes of one
-coarse cube contiguous).
+coarse cube contiguous); a cube cell's faces are blocked as the segments of its own
+level's grid, also where the neighbour across the face belongs to the other level.
 """
 from __future__ import annotations
 
@@ -59,6 +68,26 @@ class Cubes:
 
     def dx(self, level):
         return self.dx0 if level == 0 else 0.5 * self.dx0
+
+    def level_shape(self, level):
+        """Cells (nz, ny, nx) of the uniform grid of one level over the whole domain."""
+        f = 1 if level == 0 else 2
+        return tuple(int(self.K[a] * self.n * f) for a in (2, 1, 0))
+
+    def set_blocked(self, level, blocked):
+        """Blocked bits of the cubes of one level from that level's uniform-grid tagging
+        (uint8 array of level_shape(level)): cube cell (i, j, k) takes the bits of grid
+        cell (origin + (i, j, k)) of its level."""
+        blocked = np.asarray(blocked, dtype=np.uint8)
+        assert blocked.shape == self.level_shape(level)
+        if not hasattr(self, "mask"):
+            self.mask = np.zeros((len(self.cubes), self.n, self.n, self.n), dtype=np.uint8)
+        n = self.n
+        for q, (lvl, o) in enumerate(self.cubes):
+            if lvl != level:
+                continue
+            c0 = o // 2 if lvl == 0 else o
+            self.mask[q] = blocked[c0[2]:c0[2] + n, c0[1]:c0[1] + n, c0[0]:c0[0] + n]
 
     def size(self):
         return len(self.cubes) * self.side ** 3
@@ -164,21 +193,31 @@ class Cubes:
             ob = out[q * sd ** 3:(q + 1) * sd ** 3].reshape(sd, sd, sd)
             c = slice(H, H + n)
             m, p = slice(H - 1, H + n - 1), slice(H + 1, H + n + 1)
-            s = blk[c, c, m]
-            s = s + blk[c, c, p]
-            s = s + blk[c, m, c]
-            s = s + blk[c, p, c]
-            s = s + blk[m, c, c]
-            s = s + blk[p, c, c]
-            ob[c, c, c] = (s - 6.0 * blk[c, c, c]) / (dx * dx)
+            xc = blk[c, c, c]
+            nbs = (blk[c, c, m], blk[c, c, p], blk[c, m, c], blk[c, p, c], blk[m, c, c], blk[p, c, c])
+            if hasattr(self, "mask"):
+                # behind a blocked face the Neumann ghost p_GC = p_c
+                nbs = tuple(np.where(((self.mask[q] >> d) & 1) == 1, xc, nbs[d]) for d in range(6))
+            s = nbs[0]
+            for d in range(1, 6):
+                s = s + nbs[d]
+            ob[c, c, c] = (s - 6.0 * xc) / (dx * dx)
         return out
+
+    def open_faces(self, q):
+        """Open faces (0..6) of cube q's cells."""
+        if not hasattr(self, "mask"):
+            return np.full((self.n,) * 3, 6)
+        m = self.mask[q]
+        return sum(((m >> d) & 1) == 0 for d in range(6)).astype(np.int64)
 
     def rbsor(self, b, x0, omega, sweeps):
         """Red-black SOR on the cubes (Sec. 2.1's alternative solver on the Sec. 2.2 grid):
         each half sweep exchanges the halos, then updates every interior cell of one
         colour (parity of its cube-local i + j + k; cube origins are multiples of n, so
         this is the parity within its level) in every cube by
-        x_c += omega (b_c - (L x)_c) / (-6 / dx^2), reading only cells of the other colour
+        x_c += omega (b_c - (L x)_c) / (-open / dx^2) (open = 6 without geometry; a cell
+        without open faces keeps its value), reading only cells of the other colour
         and the halo copies.  Returns x after `sweeps` sweeps (halos as last exchanged)."""
         x = x0.copy()
         for _ in range(sweeps):
@@ -200,11 +239,13 @@ class Cubes:
         for q in (range(len(self.cubes)) if cubes is None else cubes):
             lvl = self.cubes[q][0]
             dx = self.dx(lvl)
-            diag = -6.0 / (dx * dx)
+            nopen = self.open_faces(q)
+            diag = -nopen / (dx * dx)
             blk = x[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)
             inner = blk[H:H + n, H:H + n, H:H + n]
             r = self.interior(b, q) - self.interior(L, q)
-            inner[...] = np.where(mine, inner + omega * r / diag, inner)
+            upd = mine & (nopen > 0)
+            inner[...] = np.where(upd, inner + omega * r / np.where(upd, diag, 1.0), inner)
         return x
 
     def cell_centres(self, q):

@@ -156,3 +156,87 @@ def test_listed_cubes_equal_the_full_grid():
         for r in src:
             other[r * s3:(r + 1) * s3] = False
         assert np.array_equal(x1[other], x0[other])
+
+
+# ----------------------------------------------- immersed geometry on the cubes
+
+def _scatter(C, u):
+    """Cube storage holding the level-0 uniform field u (z, y, x) in every (coarse) cube."""
+    data = np.zeros(C.size())
+    s, n = C.side, C.n
+    for q, (lvl, o) in enumerate(C.cubes):
+        i0, j0, k0 = o // 2
+        blk = data[q * s ** 3:(q + 1) * s ** 3].reshape(s, s, s)
+        blk[bcm.H:bcm.H + n, bcm.H:bcm.H + n, bcm.H:bcm.H + n] = u[k0:k0 + n, j0:j0 + n, i0:i0 + n]
+    return data
+
+
+def _sphere(centre, radius, seed=0):
+    from paper_2002_06206_amd import inputs
+    return inputs.icosphere(3, radius, centre, inputs.random_rotation(np.random.default_rng(seed)))
+
+
+def test_one_level_with_geometry_equals_the_uniform_pressure_operator():
+    """One level of cubes carrying the blocked bits of a tagged sphere is the uniform
+    grid's pressure operator with those bits and zero-gradient (slip) domain faces: the
+    flow oracle's L p over open faces (Neumann ghost behind blocked faces, Sec. 2.3.2
+    reading G3), to rounding (the two sum the same terms in a different order)."""
+    from oracle import flow, tagging
+    K, n, dx = (3, 2, 2), 8, 0.5
+    N = (K[0] * n, K[1] * n, K[2] * n)
+    C = bcm.Cubes(K, n, dx, (0.0, 0.0, 0.0), np.zeros(K[::-1], bool))
+    tri = _sphere((6.1, 3.9, 4.2), 2.7)
+    blocked, theta = tagging.tag(tri, N, dx, (0.0, 0.0, 0.0))
+    assert np.count_nonzero(blocked) > 50
+    C.set_blocked(0, blocked)
+    S = flow.SLIP
+    g = flow.Grid(N, dx, (0.0, 0.0, 0.0), (S,) * 6)
+    st = flow.build_stencils(g, blocked, theta)
+    u = np.random.default_rng(4).standard_normal(N[::-1])
+    L = C.laplacian(C.exchange(_scatter(C, u)))
+    ref = flow.laplacian(st, u)
+    got = np.zeros(N[::-1])
+    for q, (lvl, o) in enumerate(C.cubes):
+        i0, j0, k0 = o // 2
+        got[k0:k0 + n, j0:j0 + n, i0:i0 + n] = C.interior(L, q)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_two_level_geometry_masks_and_sor():
+    """Two levels with a sphere inside the refined cubes: every cube cell takes the bits
+    of its own level's tagging (blocked faces seen from both cells within a level), and
+    red-black SOR with the open-face diagonal drives the residual of a consistent system
+    b = L u down on both levels; a planted mistake (the blocked neighbour's own value
+    instead of the ghost) changes the operator next to the wall."""
+    from oracle import tagging
+    K, n, dx0 = (2, 2, 2), 8, 1.0
+    refine = np.zeros(K[::-1], bool)
+    refine[0, 0, 0] = refine[0, 0, 1] = True
+    C = bcm.Cubes(K, n, dx0, (0.0, 0.0, 0.0), refine)
+    tri = _sphere((8.0, 4.1, 3.9), 2.6, seed=2)
+    for lvl in (0, 1):
+        shape = C.level_shape(lvl)
+        dx = C.dx(lvl)
+        b, _ = tagging.tag(tri, shape[::-1], dx, (0.0, 0.0, 0.0))
+        C.set_blocked(lvl, b)
+        if lvl == 1:
+            # within the level grid a blocked face is blocked from both sides
+            assert np.count_nonzero(b) > 50
+            assert np.array_equal((b >> 1) & 1, np.roll((b >> 0) & 1, -1, axis=2) * (np.arange(shape[2]) <
+                                                                                    shape[2] - 1))
+    fine = [q for q, (l, _) in enumerate(C.cubes) if l == 1]
+    assert sum(np.count_nonzero(C.mask[q]) for q in fine) > 50
+    u = C.fill(lambda x, y, z: np.sin(0.7 * x) * np.cos(0.4 * y) + 0.3 * z)
+    b = C.laplacian(C.exchange(u))
+    x = np.zeros_like(u)
+    r0 = np.linalg.norm(b)
+    x = C.rbsor(b, x, 1.7, 300)
+    r = np.linalg.norm(b - C.laplacian(C.exchange(x)))
+    assert r < 1e-3 * r0, (r, r0)
+    # planted mistake: ignore the masks
+    L_masked = C.laplacian(C.exchange(u))
+    mask = C.mask
+    del C.mask
+    L_plain = C.laplacian(C.exchange(u))
+    C.mask = mask
+    assert np.max(np.abs(L_masked - L_plain)) > 1e-3
