@@ -208,6 +208,13 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     st = s.new_state(case.u_in)
+    # device memory in use with the context, the state (and the network) resident: the
+    # whole device's figure after torch's cache is released, of which torch_live are
+    # this process's live torch tensors (the state, the inputs)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free_b, total_b = torch.cuda.mem_get_info()
+    torch_live_b = torch.cuda.memory_allocated()
     # time step: CFL 0.3 on the largest face velocity of the previous step, capped at
     # the configured dt (= CFL 0.3 on the inflow velocity); variable-step AB2
     ctl = {"dt_prev": 0.0, "umax": max(abs(v) for v in case.u_in)}
@@ -289,6 +296,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
            "fallbacks": fallbacks, "fp64_fallback_iters_per_step": sum(fb_iters) / len(fb_iters),
            "max_rel_residual": worst_res, "max_div_linf": worst_div,
            "setup_s": round(t_setup, 3), "cuts": s.ncut, "dt_last": ctl["dt_prev"],
+           "device_gib_in_use": round((total_b - free_b) / 2 ** 30, 2),
+           "torch_live_gib": round(torch_live_b / 2 ** 30, 2),
            "force_last_step": [a + b for a, b in zip(Fp, Fv)],
            "dominant": {"name": name, "kernel": (KERNEL_SYMBOL if precision == ibm.FP64 else KERNEL_SYMBOL_F32)[name],
                         "bytes_per_cell": bytes_tab[name], "avg_s": avg_s, "achieved_gbs": achieved,
@@ -462,7 +471,8 @@ def bcm_timing(case, blocked, args, ibm, torch, reps=20):
     cells of twice the workload's cell size, refined (8 cubes of 16^3 cells at the
     workload's cell size) wherever the geometry cuts a grid line inside them; the halo
     exchange, the 7-point operator and red-black SOR sweeps (two exchanges and two half
-    sweeps each) timed with events on the stream they run on."""
+    sweeps each) timed with events on the stream they run on; then the operator and the
+    sweeps again with the workload's geometry on both levels (ibm_bcm_set_blocked)."""
     n = 16
     N = case.n
     if any(v % (2 * n) for v in N):
@@ -492,6 +502,27 @@ def bcm_timing(case, blocked, args, ibm, torch, reps=20):
     ex_us = ev[0].elapsed_time(ev[1]) / reps * 1e3
     lap_us = ev[1].elapsed_time(ev[2]) / reps * 1e3
     sor_us = ev[2].elapsed_time(ev[3]) / reps * 1e3
+    # immersed geometry on the cubes: level 1 takes the workload's own tagging, level 0 a
+    # tagging of the same triangles on the grid of twice the cell size
+    coarse = ibm.Solver(tuple(v // 2 for v in N), 2.0 * case.dx, case.origin, case.bc, case.u_in)
+    cb, _ = coarse.tag(case.tri, want_theta=False)
+    G.set_blocked(0, cb)
+    G.set_blocked(1, blocked.reshape(N[2], N[1], N[0]).contiguous())
+    coarse.close()
+    del cb
+    for _ in range(2):
+        G.laplacian(x, y)
+    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    ev2[0].record()
+    for _ in range(reps):
+        G.laplacian(x, y)
+    ev2[1].record()
+    G.sor(y, x, 1.8, reps)
+    ev2[2].record()
+    torch.cuda.synchronize()
+    mlap_us = ev2[0].elapsed_time(ev2[1]) / reps * 1e3
+    msor_us = ev2[1].elapsed_time(ev2[2]) / reps * 1e3
     cells = G.ncubes * n ** 3
     fine = int(refine.sum())
     # algorithmic bytes: operator 16 B per cell (x read once, y written); exchange per
@@ -501,6 +532,8 @@ def bcm_timing(case, blocked, args, ibm, torch, reps=20):
     out = {"coarse_cubes": math.prod(K), "refined": fine, "cubes": int(G.ncubes), "cells": int(cells),
            "halo_cells": int(G.nhalo), "exchange_us": round(ex_us, 2), "laplacian_us": round(lap_us, 2),
            "sor_sweep_us": round(sor_us, 2),
+           "with_geometry": {"laplacian_us": round(mlap_us, 2), "sor_sweep_us": round(msor_us, 2),
+                             "mask_bytes_per_cell": 1},
            "laplacian_bytes_per_cell": 16,
            "laplacian_achieved_gbs": round(lap_bytes / (lap_us * 1e-6) / 1e9, 1),
            "roofline": {"bound": "hbm", "achieved": round(lap_bytes / (lap_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,

@@ -426,6 +426,17 @@ int ibm_bcm_laplacian(const ibm_bcm* grid, const double* x_dev, double* y_dev, v
 int ibm_bcm_sor(const ibm_bcm* grid, const double* b_dev, double* x_dev, double omega, int32_t sweeps,
                 void* stream);
 
+/* Immersed geometry on the cubes: blocked_dev holds the blocked bits (one byte per cell,
+ * bit d = direction d, as ibm_tag_geometry writes them) of the uniform grid of one level
+ * over the whole domain: level 0 has K[a] n cells per axis of size dx0, level 1 twice as
+ * many of size dx0 / 2, cell c = i + nx (j + ny k).  Every cube of that level takes the
+ * bits of its own cells; a cube cell's face is blocked as the segment of its level's
+ * grid, also toward a cube of the other level.  From then on ibm_bcm_laplacian and
+ * ibm_bcm_sor give blocked faces the pressure ghost p_GC = p_c (Neumann, Sec. 2.3.2) and
+ * SOR divides by the open-face count (a cell without open faces keeps its value).  The
+ * first call allocates one byte per cube cell (set-up); call once per level. */
+int ibm_bcm_set_blocked(ibm_bcm* grid, int32_t level, const uint8_t* blocked_dev, void* stream);
+
 /* Measurement support (not part of the method).  When enabled, launches of the
  * pressure solve are bracketed by HIP events on its stream and the elapsed times are
  * collected at the end of each solve.  Slots: 0 = CG pass A (SpMV, <d,q>; for the

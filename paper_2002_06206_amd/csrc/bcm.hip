@@ -35,6 +35,8 @@ struct ibm_bcm {
     int* d_off = nullptr;          // nhalo + 1 offsets into d_src
     int* d_src = nullptr;          // source storage indices
     uint8_t* d_level = nullptr;    // per cube
+    uint8_t* d_mask = nullptr;     // blocked bits per interior cell (ncubes * n^3), or null
+    int32_t* d_org = nullptr;      // per cube, origin in fine-cell units (for set_blocked)
 };
 
 namespace ibm {
@@ -94,9 +96,23 @@ __global__ void __launch_bounds__(256) k_bcm_exchange(long long nhalo, const int
 
 // (L x)_c = (x_-x + x_+x + x_-y + x_+y + x_-z + x_+z - 6 x_c) / dx^2 on every interior
 // cell, from the cube's own storage (halos included)
+// sum of the six neighbours of storage cell c in the order -x, +x, -y, +y, -z, +z, with
+// the Neumann ghost x_c behind a blocked face (bit d of msk)
+__device__ inline double bcm_nbsum(const double* __restrict__ x, long long c, long long side, long long s2,
+                                   unsigned msk) {
+    const double xc = x[c];
+    double s = (msk & 1u) ? xc : x[c - 1];
+    s = s + ((msk & 2u) ? xc : x[c + 1]);
+    s = s + ((msk & 4u) ? xc : x[c - side]);
+    s = s + ((msk & 8u) ? xc : x[c + side]);
+    s = s + ((msk & 16u) ? xc : x[c - s2]);
+    s = s + ((msk & 32u) ? xc : x[c + s2]);
+    return s;
+}
+
 __global__ void __launch_bounds__(256) k_bcm_lap(long long ncubes, int n, int side, double dx0,
-                                                 const uint8_t* __restrict__ level, const double* __restrict__ x,
-                                                 double* __restrict__ y) {
+                                                 const uint8_t* __restrict__ level, const uint8_t* __restrict__ mask,
+                                                 const double* __restrict__ x, double* __restrict__ y) {
     const long long per = (long long)n * n * n;
     const long long total = ncubes * per;
     const long long s2 = (long long)side * side, s3 = s2 * side;
@@ -106,13 +122,30 @@ __global__ void __launch_bounds__(256) k_bcm_lap(long long ncubes, int n, int si
         const int i = (int)(r % n), j = (int)((r / n) % n), k = (int)(r / ((long long)n * n));
         const long long c = q * s3 + (i + BCM_H) + side * ((j + BCM_H) + (long long)side * (k + BCM_H));
         const double dx = level[q] ? 0.5 * dx0 : dx0;
-        double s = x[c - 1];
-        s = s + x[c + 1];
-        s = s + x[c - side];
-        s = s + x[c + side];
-        s = s + x[c - s2];
-        s = s + x[c + s2];
+        const double s = bcm_nbsum(x, c, side, s2, mask ? (unsigned)mask[t] : 0u);
         y[c] = (s - 6.0 * x[c]) / (dx * dx);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bcm_zero(long long n, uint8_t* __restrict__ p) {
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256) p[t] = 0;
+}
+
+// blocked bits of the cubes of one level from the level's uniform-grid tagging
+// (gn cells per axis): cube cell (i, j, k) takes grid cell origin + (i, j, k)
+__global__ void __launch_bounds__(256) k_bcm_mask(long long ncubes, int n, int lvl, const uint8_t* __restrict__ level,
+                                                  const int32_t* __restrict__ org, int gx, int gy,
+                                                  const uint8_t* __restrict__ blocked, uint8_t* __restrict__ mask) {
+    const long long per = (long long)n * n * n;
+    const long long total = ncubes * per;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+        const long long q = t / per;
+        if (level[q] != lvl) continue;
+        const long long r = t - q * per;
+        const int i = (int)(r % n), j = (int)((r / n) % n), k = (int)(r / ((long long)n * n));
+        const int f = lvl ? 1 : 2;   // the cube's cell size in fine units
+        const long long ci = org[3 * q] / f + i, cj = org[3 * q + 1] / f + j, ck = org[3 * q + 2] / f + k;
+        mask[t] = blocked[ci + (long long)gx * (cj + (long long)gy * ck)];
     }
 }
 
@@ -120,8 +153,9 @@ __global__ void __launch_bounds__(256) k_bcm_lap(long long ncubes, int n, int si
 // (parity of its cube-local i + j + k) gets x_c += omega (b_c - (L x)_c) / (-6 / dx^2);
 // it reads cells of the other colour and halo copies only (exchanged before the launch).
 __global__ void __launch_bounds__(256) k_bcm_sor(long long ncubes, int n, int side, double dx0,
-                                                 const uint8_t* __restrict__ level, const double* __restrict__ b,
-                                                 double* __restrict__ x, int colour, double omega) {
+                                                 const uint8_t* __restrict__ level, const uint8_t* __restrict__ mask,
+                                                 const double* __restrict__ b, double* __restrict__ x, int colour,
+                                                 double omega) {
     const long long per = (long long)n * n * n;
     const long long total = ncubes * per;
     const long long s2 = (long long)side * side, s3 = s2 * side;
@@ -132,15 +166,13 @@ __global__ void __launch_bounds__(256) k_bcm_sor(long long ncubes, int n, int si
         if (((i + j + k) & 1) != colour) continue;
         const long long c = q * s3 + (i + BCM_H) + side * ((j + BCM_H) + (long long)side * (k + BCM_H));
         const double dx = level[q] ? 0.5 * dx0 : dx0;
-        double s = x[c - 1];
-        s = s + x[c + 1];
-        s = s + x[c - side];
-        s = s + x[c + side];
-        s = s + x[c - s2];
-        s = s + x[c + s2];
+        const unsigned msk = mask ? (unsigned)mask[t] : 0u;
+        const int nopen = 6 - __builtin_popcount(msk & 63u);
+        if (nopen == 0) continue;   // a cell without open faces keeps its value
+        const double s = bcm_nbsum(x, c, side, s2, msk);
         const double xc = x[c];
         const double lx = (s - 6.0 * xc) / (dx * dx);
-        const double diag = -6.0 / (dx * dx);
+        const double diag = -(double)nopen / (dx * dx);
         x[c] = xc + omega * (b[c] - lx) / diag;
     }
 }
@@ -307,20 +339,23 @@ int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origi
     if (ibm::dev_malloc((void**)&m->d_dst, sizeof(int) * dst.size()) != hipSuccess ||
         ibm::dev_malloc((void**)&m->d_off, sizeof(int) * off.size()) != hipSuccess ||
         ibm::dev_malloc((void**)&m->d_src, sizeof(int) * src.size()) != hipSuccess ||
-        ibm::dev_malloc((void**)&m->d_level, lv.size()) != hipSuccess) {
+        ibm::dev_malloc((void**)&m->d_level, lv.size()) != hipSuccess ||
+        ibm::dev_malloc((void**)&m->d_org, sizeof(int32_t) * m->org.size()) != hipSuccess) {
         (void)hipGetLastError();
         set_error("ibm_bcm_create: out of device memory");
         (void)hipFree(m->d_dst);
         (void)hipFree(m->d_off);
         (void)hipFree(m->d_src);
         (void)hipFree(m->d_level);
+        (void)hipFree(m->d_org);
         delete m;
         return IBM_ERR_OOM;
     }
     if (hipMemcpy(m->d_dst, dst.data(), sizeof(int) * dst.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(m->d_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(m->d_src, src.data(), sizeof(int) * src.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m->d_level, lv.data(), lv.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(m->d_level, lv.data(), lv.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->d_org, m->org.data(), sizeof(int32_t) * m->org.size(), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipGetLastError();
         set_error("ibm_bcm_create: copy of the halo tables failed");
         ibm_bcm_destroy(m);
@@ -336,6 +371,8 @@ int ibm_bcm_destroy(ibm_bcm* m) try {
     (void)hipFree(m->d_off);
     (void)hipFree(m->d_src);
     (void)hipFree(m->d_level);
+    (void)hipFree(m->d_org);
+    (void)hipFree(m->d_mask);
     delete m;
     return IBM_OK;
 } IBM_CATCH_ALL
@@ -389,8 +426,8 @@ int ibm_bcm_laplacian(const ibm_bcm* m, const double* x_dev, double* y_dev, void
     const long long total = m->ncubes * (long long)m->n * m->n * m->n;
     const long long nb = std::min<long long>((total + 255) / 256, 16384);
     if (nb > 0)
-        k_bcm_lap<<<(int)nb, 256, 0, (hipStream_t)stream>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level, x_dev,
-                                                             y_dev);
+        k_bcm_lap<<<(int)nb, 256, 0, (hipStream_t)stream>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level,
+                                                             m->d_mask, x_dev, y_dev);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 } IBM_CATCH_ALL
@@ -407,8 +444,35 @@ int ibm_bcm_sor(const ibm_bcm* m, const double* b_dev, double* x_dev, double ome
     for (int it = 0; it < sweeps; ++it)
         for (int colour = 0; colour < 2; ++colour) {
             if (int rc = ibm_bcm_exchange(m, x_dev, stream)) return rc;
-            k_bcm_sor<<<nb, 256, 0, s>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level, b_dev, x_dev, colour, omega);
+            k_bcm_sor<<<nb, 256, 0, s>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level, m->d_mask, b_dev, x_dev,
+                                         colour, omega);
         }
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+} IBM_CATCH_ALL
+
+int ibm_bcm_set_blocked(ibm_bcm* m, int32_t level, const uint8_t* blocked_dev, void* stream) try {
+    if (!m || !blocked_dev || (level != 0 && level != 1)) {
+        set_error("ibm_bcm_set_blocked: need a grid, level 0 or 1 and the level's blocked bits");
+        return IBM_ERR_ARG;
+    }
+    if (int rc = bcm_device_ok(m)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const long long total = m->ncubes * (long long)m->n * m->n * m->n;
+    if (!m->d_mask) {
+        // set-up: the mask starts all open, each level is filled by its own call
+        if (ibm::dev_malloc((void**)&m->d_mask, (size_t)total) != hipSuccess) {
+            (void)hipGetLastError();
+            m->d_mask = nullptr;
+            set_error("ibm_bcm_set_blocked: out of device memory for the cube masks");
+            return IBM_ERR_OOM;
+        }
+        k_bcm_zero<<<(int)std::min<long long>((total + 255) / 256, 16384), 256, 0, s>>>(total, m->d_mask);
+    }
+    const int f = level ? 2 : 1;
+    const int gx = m->K[0] * m->n * f, gy = m->K[1] * m->n * f;
+    const int nb = (int)std::min<long long>((total + 255) / 256, 16384);
+    k_bcm_mask<<<nb, 256, 0, s>>>(m->ncubes, m->n, level, m->d_level, m->d_org, gx, gy, blocked_dev, m->d_mask);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 } IBM_CATCH_ALL

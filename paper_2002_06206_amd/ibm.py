@@ -120,6 +120,7 @@ def _load():
         "ibm_bcm_exchange": ([vp, vp, vp], ctypes.c_int),
         "ibm_bcm_laplacian": ([vp, vp, vp, vp], ctypes.c_int),
         "ibm_bcm_sor": ([vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
+        "ibm_bcm_set_blocked": ([vp, ctypes.c_int32, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -137,7 +138,7 @@ EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_alloc_count", "i
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
             "ibm_ctx_set_preconditioner", "ibm_bcm_create", "ibm_bcm_destroy", "ibm_bcm_info", "ibm_bcm_exchange",
-            "ibm_bcm_laplacian", "ibm_bcm_sor")
+            "ibm_bcm_laplacian", "ibm_bcm_sor", "ibm_bcm_set_blocked")
 CNN_NWEIGHTS = 7776
 
 
@@ -541,6 +542,13 @@ class BCM:
     def sor(self, b, x, omega, sweeps):
         return _check(_lib.ibm_bcm_sor(self.grid, _ptr(b), _ptr(x), float(omega), int(sweeps), _stream()),
                       "ibm_bcm_sor")
+
+    def set_blocked(self, level, blocked):
+        """Blocked bits of one level's uniform grid over the domain (uint8 device tensor,
+        (nz, ny, nx) of that level) for the cubes of that level."""
+        assert blocked.dtype == torch.uint8 and blocked.is_contiguous()
+        return _check(_lib.ibm_bcm_set_blocked(self.grid, int(level), _ptr(blocked), _stream()),
+                      "ibm_bcm_set_blocked")
 
     def close(self):
         if self.grid:
