@@ -29,6 +29,13 @@ What is computed (plain FP64 numpy, one halo cell at a time, from the definition
   update divides by the number of open faces (-open / dx^2), and a cell without open
   faces keeps its value.
 
+* The pressure solve on the cubes (Sec. 2.1 names BiCGStab and red-black SOR for the
+  Poisson equation; Sec. 2.2 puts it on this grid): the unknowns are the cube
+  interiors, the operator is "exchange, then L".  bicgstab runs the flow oracle's
+  BiCGStab on that operator (stopping on the recursive residual); sor_solve runs
+  red-black SOR in groups of check_every sweeps and stops at the first check where the
+  true residual ||b - L x|| <= tol ||b|| (norms over the interiors).
+
 Readings: n = 16 cells per cube axis (the paper's figure shows 8, its text gives the
 structure only); mirror halos at the domain boundary (the paper omits the outer boundary
 conditions); the cube order above (an interface, chosen to make the fine cubes of one
@@ -247,6 +254,52 @@ class Cubes:
             upd = mine & (nopen > 0)
             inner[...] = np.where(upd, inner + omega * r / np.where(upd, diag, 1.0), inner)
         return x
+
+    # ------------------------------------------------------- the solve on the cubes
+    def pack(self, data):
+        """The interiors of every cube, concatenated in cube order ((k, j, i) inside)."""
+        return np.concatenate([self.interior(data, q).ravel() for q in range(len(self.cubes))])
+
+    def unpack(self, v):
+        """Cube storage with v (as pack returns it) in the interiors and zero halos."""
+        data = np.zeros(self.size())
+        n, n3 = self.n, self.n ** 3
+        for q in range(len(self.cubes)):
+            self.interior(data, q)[...] = np.asarray(v[q * n3:(q + 1) * n3]).reshape(n, n, n)
+        return data
+
+    def apply(self, v):
+        """The pressure operator on packed interiors: exchange the halos, then L."""
+        return self.pack(self.laplacian(self.exchange(self.unpack(v))))
+
+    def residual(self, b, x):
+        """||b - L x|| / ||b|| over the interiors (x's halos exchanged first); 0 for b = 0."""
+        r = self.pack(b) - self.pack(self.laplacian(self.exchange(x)))
+        bb = float(np.sum(self.pack(b) ** 2))
+        return 0.0 if bb == 0.0 else float(np.sqrt(np.sum(r * r) / bb))
+
+    def bicgstab(self, b, x0, tol, max_iter):
+        """BiCGStab for L x = b on the cubes (b, x0: cube storage, interiors used).
+        Returns (x as cube storage with zero halos, iterations, status)."""
+        from oracle import flow
+        x, it, status = flow.bicgstab(self.apply, self.pack(b), self.pack(x0), tol, max_iter)
+        return self.unpack(x), it, status
+
+    def sor_solve(self, b, x0, omega, tol, check_every, max_sweeps):
+        """Red-black SOR to a tolerance: the true residual is checked before the first
+        sweep and after every check_every sweeps; returns (x, sweeps, status) at the
+        first check with residual <= tol ('converged'), or after max_sweeps sweeps
+        ('max_iter', with a last check there).  x keeps its halos as last exchanged."""
+        x = x0.copy()
+        sweeps = 0
+        while True:
+            if self.residual(b, x) <= tol:
+                return x, sweeps, "converged"
+            if sweeps >= max_sweeps:
+                return x, sweeps, "max_iter"
+            k = min(check_every, max_sweeps - sweeps)
+            x = self.rbsor(b, x, omega, k)
+            sweeps += k
 
     def cell_centres(self, q):
         """Physical centres (n, n, n, 3) of cube q's interior cells, array order (k, j, i)."""

@@ -5,6 +5,7 @@ linear field are exact and coarse-to-fine copies take the covering coarse cell; 
 face halos are written; the listed-cube forms (used to sample large grids) equal the
 full forms on the listed cubes."""
 import numpy as np
+import pytest
 
 from oracle import bcm
 
@@ -240,3 +241,89 @@ def test_two_level_geometry_masks_and_sor():
     L_plain = C.laplacian(C.exchange(u))
     C.mask = mask
     assert np.max(np.abs(L_masked - L_plain)) > 1e-3
+
+
+# ------------------------------------------------ the pressure solve on the cubes
+
+def _two_level_small():
+    refine = np.zeros((1, 1, 2), bool)
+    refine[0, 0, 1] = True
+    return bcm.Cubes((2, 1, 1), 4, 1.0, (0.0, 0.0, 0.0), refine)
+
+
+def _dense(C):
+    m = len(C.cubes) * C.n ** 3
+    A = np.zeros((m, m))
+    for k in range(m):
+        e = np.zeros(m)
+        e[k] = 1.0
+        A[:, k] = C.apply(e)
+    return A
+
+
+def _off_null(A, d):
+    """The part of d orthogonal to the null space of A (from its SVD)."""
+    _, sv, vt = np.linalg.svd(A)
+    null = vt[sv < 1e-10 * sv[0]]
+    return d - null.T @ (null @ d), len(null)
+
+
+def test_pack_unpack_and_the_operator_on_packed_interiors():
+    """pack / unpack are inverse on the interiors, and apply is exchange-then-L whatever
+    the input's halos hold (the exchange rewrites every face halo L reads)."""
+    C = _two_level_small()
+    data = np.random.default_rng(3).standard_normal(C.size())
+    v = C.pack(data)
+    assert v.shape == (len(C.cubes) * C.n ** 3,)
+    assert np.array_equal(C.pack(C.unpack(v)), v)
+    assert np.array_equal(C.apply(v), C.pack(C.laplacian(C.exchange(data))))
+    assert np.array_equal(C.pack(C.unpack(v)), C.pack(data))
+
+
+@pytest.mark.parametrize("geometry", [False, True])
+def test_bicgstab_on_cubes_equals_the_dense_solve(geometry):
+    """On a two-level grid (one coarse cube, one refined into 8), with and without a
+    blocked slab, BiCGStab on the cubes reaches the solution of the dense system built
+    from the operator, up to the null space (the constants of the all-Neumann problem,
+    one per component); the all-Neumann operator annihilates constants."""
+    C = _two_level_small()
+    if geometry:
+        for lvl in (0, 1):
+            nz, ny, nx = C.level_shape(lvl)
+            blk = np.zeros((nz, ny, nx), np.uint8)
+            f = 1 if lvl == 0 else 2
+            j = 2 * f                     # a wall between rows j - 1 and j, over part of x
+            blk[:, j - 1, : 3 * nx // 4] |= 8
+            blk[:, j, : 3 * nx // 4] |= 4
+            C.set_blocked(lvl, blk)
+    A = _dense(C)
+    m = A.shape[0]
+    assert np.max(np.abs(A @ np.ones(m))) < 1e-12
+    u = np.random.default_rng(7).standard_normal(m)
+    b = C.unpack(A @ u)
+    x, it, status = C.bicgstab(b, np.zeros_like(b), 1e-12, 4000)
+    assert status == "converged" and it > 5
+    xs = np.linalg.lstsq(A, A @ u, rcond=None)[0]
+    d, nnull = _off_null(A, C.pack(x) - xs)
+    assert nnull == 1
+    assert np.linalg.norm(d) <= 1e-8 * np.linalg.norm(xs)
+    assert C.residual(b, x) <= 1e-12
+
+
+def test_sor_solve_stops_at_the_first_check_below_tol():
+    """SOR to a tolerance is plain red-black SOR stopped at the first multiple of
+    check_every whose true residual is at or below tol: the same sweeps give the same
+    x bit for bit, one group fewer is still above tol, and the cap is honoured."""
+    C = _two_level_small()
+    u = C.fill(lambda x, y, z: np.sin(0.7 * x) * np.cos(0.4 * y) + 0.3 * z)
+    b = C.laplacian(C.exchange(u))
+    x0 = np.zeros_like(b)
+    x, sweeps, status = C.sor_solve(b, x0, 1.6, 1e-6, 10, 5000)
+    assert status == "converged" and sweeps % 10 == 0 and sweeps >= 20
+    assert C.residual(b, x) <= 1e-6
+    assert np.array_equal(x, C.rbsor(b, x0, 1.6, sweeps))
+    assert C.residual(b, C.rbsor(b, x0, 1.6, sweeps - 10)) > 1e-6
+    x2, s2, st2 = C.sor_solve(b, x0, 1.6, 1e-6, 10, 25)
+    assert st2 == "max_iter" and s2 == 25 and np.array_equal(x2, C.rbsor(b, x0, 1.6, 25))
+    xz, sz, stz = C.sor_solve(np.zeros_like(b), x0, 1.6, 1e-6, 10, 100)
+    assert stz == "converged" and sz == 0
