@@ -437,6 +437,32 @@ int ibm_bcm_sor(const ibm_bcm* grid, const double* b_dev, double* x_dev, double 
  * first call allocates one byte per cube cell (set-up); call once per level. */
 int ibm_bcm_set_blocked(ibm_bcm* grid, int32_t level, const uint8_t* blocked_dev, void* stream);
 
+/* The pressure solve on the cubes: L x = b over the cube interiors (Sec. 2.1 names
+ * BiCGStab and red-black SOR for the Poisson equation; Sec. 2.2 puts it on this grid),
+ * L = ibm_bcm_exchange followed by ibm_bcm_laplacian (with the geometry of
+ * ibm_bcm_set_blocked, if set).  b_dev and x_dev are cube storage (interiors read; x in/out:
+ * its interiors are the initial guess and the result, its face halos are left as last
+ * exchanged); distinct.
+ *  kind IBM_BCM_BICGSTAB: unpreconditioned BiCGStab from x (van der Vorst 1992); stops
+ *    when ||r|| <= tol ||b|| at the start of an iteration or ||s|| <= tol ||b|| halfway
+ *    (then x += alpha p only); max_iter iterations; the scalars stay on the device and
+ *    the host reads them every check_every iterations (launches issued after the stop
+ *    do nothing).  b = 0 gives x = 0.  A breakdown (r0.r = 0, r0.v = 0, t.s = 0 or
+ *    t.t = 0) returns IBM_NOT_CONVERGED with x as it stands.
+ *  kind IBM_BCM_SOR: red-black SOR sweeps with relaxation omega (0 < omega < 2), the true
+ *    residual checked before the first sweep and after every check_every sweeps; stops
+ *    at the first check with ||b - L x|| <= tol ||b||, or after max_iter sweeps.
+ * Norms are over the interiors (sums in a fixed block order).  iters_out: iterations or
+ * sweeps made; rel_residual_out: the true residual ||b - L x|| / ||b|| of the returned x
+ * (0 for b = 0).  Returns IBM_OK, IBM_NOT_CONVERGED, IBM_ERR_NAN (non-finite residual).
+ * The first call allocates the workspace, kept by the grid until ibm_bcm_destroy:
+ * partial sums and a small state, and for BiCGStab six vectors of the storage size.
+ * Synchronises the stream. */
+enum { IBM_BCM_BICGSTAB = 0, IBM_BCM_SOR = 1 };
+int ibm_bcm_solve(ibm_bcm* grid, int32_t kind, const double* b_dev, double* x_dev, double omega, double tol,
+                  int32_t max_iter, int32_t check_every, int32_t* iters_out, double* rel_residual_out,
+                  void* stream);
+
 /* Measurement support (not part of the method).  When enabled, launches of the
  * pressure solve are bracketed by HIP events on its stream and the elapsed times are
  * collected at the end of each solve.  Slots: 0 = CG pass A (SpMV, <d,q>; for the

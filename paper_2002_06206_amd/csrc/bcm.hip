@@ -9,13 +9,30 @@
 // one gather per halo cell.  It reads interior cells only and writes halo cells only, so
 // all halo cells of all cubes are filled by one launch without ordering.  Compiled
 // without FMA contraction: means and operator values are one fixed FP64 computation.
+//
+// The pressure solve on the cubes (Sec. 2.1's BiCGStab and red-black SOR on this grid)
+// keeps its scalars on the device: each dot product is a launch of block partials and a
+// one-block launch that sums them in block order and takes the iteration's decision
+// (stop, breakdown, the next coefficient) into a small state; every later vector
+// kernel reads that state and does nothing once the solve has stopped.  The host only
+// reads the state every check_every iterations.
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <new>
 #include <vector>
 
 #include "common.h"
+
+namespace ibm {
+// device state of a solve on the cubes
+struct BcmState {
+    double bb, rr, rho, rho_old, alpha, omega, beta;
+    int done;    // BCM_RUNNING or the reason the solve stopped
+    int iters;   // iterations made when it stopped
+};
+}  // namespace ibm
 
 struct ibm_bcm {
     int device;
@@ -37,6 +54,9 @@ struct ibm_bcm {
     uint8_t* d_level = nullptr;    // per cube
     uint8_t* d_mask = nullptr;     // blocked bits per interior cell (ncubes * n^3), or null
     int32_t* d_org = nullptr;      // per cube, origin in fine-cell units (for set_blocked)
+    double* d_ws = nullptr;        // BiCGStab vectors r, r0, p, v, s, t (storage size each)
+    double* d_part = nullptr;      // block partial sums of the solve (2 x BCM_NB)
+    ibm::BcmState* d_state = nullptr;
 };
 
 namespace ibm {
@@ -174,6 +194,236 @@ __global__ void __launch_bounds__(256) k_bcm_sor(long long ncubes, int n, int si
         const double lx = (s - 6.0 * xc) / (dx * dx);
         const double diag = -(double)nopen / (dx * dx);
         x[c] = xc + omega * (b[c] - lx) / diag;
+    }
+}
+
+// ------------------------------------------------------------ solve on the cubes
+
+constexpr int BCM_NB = 1024;   // blocks of the reduction launches (partials per sum)
+enum { BCM_RUNNING = 0, BCM_CONVERGED = 1, BCM_CONVERGED_HALF = 2, BCM_BREAKDOWN = 3, BCM_MAX_ITER = 4,
+       BCM_NAN = 5, BCM_ZERO_RHS = 6 };
+enum { BS_INIT, BS_RHO, BS_ALPHA, BS_HALF, BS_OMEGA, BS_RES };
+
+// storage index of interior cell t = q n^3 + i + n (j + n k)
+__device__ inline long long bcm_cell(long long t, long long per, int n, long long side) {
+    const long long q = t / per;
+    const long long r = t - q * per;
+    const long long i = r % n, j = (r / n) % n, k = r / ((long long)n * n);
+    return q * side * side * side + (i + BCM_H) + side * ((j + BCM_H) + side * (k + BCM_H));
+}
+
+// block partials of a0 . b0 (and a1 . b1) over the interiors, written to part[blockIdx]
+// (and part[gridDim + blockIdx]); nothing once the solve has stopped
+template <int NV>
+__global__ void __launch_bounds__(NT) k_bcm_dot(long long total, int n, int side, const double* __restrict__ a0,
+                                                const double* __restrict__ b0, const double* __restrict__ a1,
+                                                const double* __restrict__ b1, double* __restrict__ part,
+                                                const BcmState* __restrict__ st) {
+    if (st->done) return;
+    const long long per = (long long)n * n * n;
+    double v[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) v[a] = 0.0;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < total; t += (long long)gridDim.x * NT) {
+        const long long c = bcm_cell(t, per, n, side);
+        v[0] += a0[c] * b0[c];
+        if (NV > 1) v[NV - 1] += a1[c] * b1[c];
+    }
+    __shared__ double sh[4 * NV];
+    block_reduce<NV>(v, sh);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < NV; ++a) part[a * gridDim.x + blockIdx.x] = v[a];
+}
+
+// One block: the two sums of nb partials each (in block order), then the decision of
+// the step `mode` of iteration it (the BiCGStab steps of the flow solver's algorithm;
+// BS_RES stores a residual check).
+__global__ void __launch_bounds__(NT) k_bcm_scalar(const double* __restrict__ part, int nb, BcmState* st, int mode,
+                                                   int it, int max_iter, double tol) {
+    if (st->done && mode != BS_RES) return;
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += NT) {
+        v[0] += part[b];
+        v[1] += part[nb + b];
+    }
+    __shared__ double sh[8];
+    block_reduce<2>(v, sh);
+    if (threadIdx.x != 0) return;
+    const double tol2 = tol * tol * st->bb;
+    auto stop = [&](int why, int iters) {
+        st->done = why;
+        st->iters = iters;
+    };
+    switch (mode) {
+    case BS_INIT:   // v = (b . b, r . r)
+        st->bb = v[0];
+        st->rr = v[1];
+        st->rho_old = st->alpha = st->omega = 1.0;
+        st->beta = 0.0;
+        st->iters = 0;
+        if (!(v[0] == v[0]) || !(v[1] == v[1])) st->done = BCM_NAN;
+        else if (v[0] == 0.0) st->done = BCM_ZERO_RHS;
+        break;
+    case BS_RHO:    // v = (r0 . r, r . r), at the start of iteration it
+        st->rr = v[1];
+        if (!(v[1] == v[1]) || !(v[0] == v[0])) stop(BCM_NAN, it);
+        else if (v[1] <= tol2) stop(BCM_CONVERGED, it);
+        else if (it >= max_iter) stop(BCM_MAX_ITER, it);
+        else if (v[0] == 0.0) stop(BCM_BREAKDOWN, it);
+        else {
+            st->beta = (v[0] / st->rho_old) * (st->alpha / st->omega);
+            st->rho = v[0];
+        }
+        break;
+    case BS_ALPHA:  // v = (r0 . v, -)
+        if (!(v[0] == v[0])) stop(BCM_NAN, it);
+        else if (v[0] == 0.0) stop(BCM_BREAKDOWN, it);
+        else st->alpha = st->rho / v[0];
+        break;
+    case BS_HALF:   // v = (s . s, -): halfway stop, x += alpha p follows
+        if (!(v[0] == v[0])) stop(BCM_NAN, it);
+        else if (v[0] <= tol2) stop(BCM_CONVERGED_HALF, it + 1);
+        break;
+    case BS_OMEGA:  // v = (t . s, t . t)
+        if (!(v[0] == v[0]) || !(v[1] == v[1])) stop(BCM_NAN, it);
+        else if (v[1] == 0.0 || v[0] == 0.0) stop(BCM_BREAKDOWN, it);
+        else {
+            st->omega = v[0] / v[1];
+            st->rho_old = st->rho;
+        }
+        break;
+    default:        // BS_RES: v = ((b - L x) . (b - L x), b . b)
+        st->rr = v[0];
+        st->bb = v[1];
+        break;
+    }
+}
+
+// r = b - y (y = L x), r0 = r, p = v = 0; partials of b . b and r . r
+__global__ void __launch_bounds__(NT) k_bcm_bs_init(long long total, int n, int side, const double* __restrict__ b,
+                                                    const double* __restrict__ y, double* __restrict__ r,
+                                                    double* __restrict__ r0, double* __restrict__ p,
+                                                    double* __restrict__ v, double* __restrict__ part) {
+    const long long per = (long long)n * n * n;
+    double acc[2] = {0.0, 0.0};
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < total; t += (long long)gridDim.x * NT) {
+        const long long c = bcm_cell(t, per, n, side);
+        const double rc = b[c] - y[c];
+        r[c] = rc;
+        r0[c] = rc;
+        p[c] = 0.0;
+        v[c] = 0.0;
+        acc[0] += b[c] * b[c];
+        acc[1] += rc * rc;
+    }
+    __shared__ double sh[8];
+    block_reduce<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc[0];
+        part[gridDim.x + blockIdx.x] = acc[1];
+    }
+}
+
+// p = r + beta (p - omega v)
+__global__ void __launch_bounds__(NT) k_bcm_bs_p(long long total, int n, int side, const double* __restrict__ r,
+                                                 const double* __restrict__ v, double* __restrict__ p,
+                                                 const BcmState* __restrict__ st) {
+    if (st->done) return;
+    const long long per = (long long)n * n * n;
+    const double beta = st->beta, omega = st->omega;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < total; t += (long long)gridDim.x * NT) {
+        const long long c = bcm_cell(t, per, n, side);
+        p[c] = r[c] + beta * (p[c] - omega * v[c]);
+    }
+}
+
+// s = r - alpha v, with partials of s . s
+__global__ void __launch_bounds__(NT) k_bcm_bs_s(long long total, int n, int side, const double* __restrict__ r,
+                                                 const double* __restrict__ v, double* __restrict__ s,
+                                                 double* __restrict__ part, const BcmState* __restrict__ st) {
+    if (st->done) return;
+    const long long per = (long long)n * n * n;
+    const double alpha = st->alpha;
+    double acc[1] = {0.0};
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < total; t += (long long)gridDim.x * NT) {
+        const long long c = bcm_cell(t, per, n, side);
+        const double sc = r[c] - alpha * v[c];
+        s[c] = sc;
+        acc[0] += sc * sc;
+    }
+    __shared__ double sh[4];
+    block_reduce<1>(acc, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc[0];
+        part[gridDim.x + blockIdx.x] = 0.0;
+    }
+}
+
+// the halfway stop of iteration it: x += alpha p (exactly once: only the launch of the
+// iteration that stopped there matches)
+__global__ void __launch_bounds__(NT) k_bcm_bs_xhalf(long long total, int n, int side, const double* __restrict__ p,
+                                                     double* __restrict__ x, const BcmState* __restrict__ st, int it) {
+    if (st->done != BCM_CONVERGED_HALF || st->iters != it + 1) return;
+    const long long per = (long long)n * n * n;
+    const double alpha = st->alpha;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < total; t += (long long)gridDim.x * NT) {
+        const long long c = bcm_cell(t, per, n, side);
+        x[c] = x[c] + alpha * p[c];
+    }
+}
+
+// x += alpha p + omega s; r = s - omega t
+__global__ void __launch_bounds__(NT) k_bcm_bs_xr(long long total, int n, int side, const double* __restrict__ p,
+                                                  const double* __restrict__ s, const double* __restrict__ tv,
+                                                  double* __restrict__ x, double* __restrict__ r,
+                                                  const BcmState* __restrict__ st) {
+    if (st->done) return;
+    const long long per = (long long)n * n * n;
+    const double alpha = st->alpha, omega = st->omega;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < total; t += (long long)gridDim.x * NT) {
+        const long long c = bcm_cell(t, per, n, side);
+        x[c] = x[c] + alpha * p[c] + omega * s[c];
+        r[c] = s[c] - omega * tv[c];
+    }
+}
+
+// partials of |b - L x|^2 and |b|^2 over the interiors (x exchanged before the launch)
+__global__ void __launch_bounds__(NT) k_bcm_resid(long long ncubes, int n, int side, double dx0,
+                                                  const uint8_t* __restrict__ level, const uint8_t* __restrict__ mask,
+                                                  const double* __restrict__ b, const double* __restrict__ x,
+                                                  double* __restrict__ part) {
+    const long long per = (long long)n * n * n;
+    const long long total = ncubes * per;
+    const long long s2 = (long long)side * side;
+    double acc[2] = {0.0, 0.0};
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < total; t += (long long)gridDim.x * NT) {
+        const long long q = t / per;
+        const long long c = bcm_cell(t, per, n, side);
+        const double dx = level[q] ? 0.5 * dx0 : dx0;
+        const double lx = (bcm_nbsum(x, c, side, s2, mask ? (unsigned)mask[t] : 0u) - 6.0 * x[c]) / (dx * dx);
+        const double rc = b[c] - lx;
+        acc[0] += rc * rc;
+        acc[1] += b[c] * b[c];
+    }
+    __shared__ double sh[8];
+    block_reduce<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc[0];
+        part[gridDim.x + blockIdx.x] = acc[1];
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_bcm_zero_interior(long long total, int n, int side, double* __restrict__ x) {
+    const long long per = (long long)n * n * n;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < total; t += (long long)gridDim.x * NT)
+        x[bcm_cell(t, per, n, side)] = 0.0;
+}
+
+__global__ void k_bcm_state_reset(BcmState* st) {
+    if (threadIdx.x == 0) {
+        st->bb = st->rr = st->rho = st->rho_old = st->alpha = st->omega = st->beta = 0.0;
+        st->done = BCM_RUNNING;
+        st->iters = 0;
     }
 }
 
@@ -373,6 +623,9 @@ int ibm_bcm_destroy(ibm_bcm* m) try {
     (void)hipFree(m->d_level);
     (void)hipFree(m->d_org);
     (void)hipFree(m->d_mask);
+    (void)hipFree(m->d_ws);
+    (void)hipFree(m->d_part);
+    (void)hipFree(m->d_state);
     delete m;
     return IBM_OK;
 } IBM_CATCH_ALL
@@ -475,6 +728,144 @@ int ibm_bcm_set_blocked(ibm_bcm* m, int32_t level, const uint8_t* blocked_dev, v
     k_bcm_mask<<<nb, 256, 0, s>>>(m->ncubes, m->n, level, m->d_level, m->d_org, gx, gy, blocked_dev, m->d_mask);
     IBM_HIP(hipGetLastError());
     return IBM_OK;
+} IBM_CATCH_ALL
+
+int ibm_bcm_solve(ibm_bcm* m, int32_t kind, const double* b_dev, double* x_dev, double omega, double tol,
+                  int32_t max_iter, int32_t check_every, int32_t* iters_out, double* rel_residual_out,
+                  void* stream) try {
+    if (!m || !b_dev || !x_dev || b_dev == x_dev || (kind != IBM_BCM_BICGSTAB && kind != IBM_BCM_SOR) ||
+        !(tol > 0.0) || max_iter < 0 || check_every < 1 ||
+        (kind == IBM_BCM_SOR && !(omega > 0.0 && omega < 2.0))) {
+        set_error("ibm_bcm_solve: need distinct b and x, kind BICGSTAB or SOR, tol > 0, max_iter >= 0, "
+                  "check_every >= 1 and 0 < omega < 2 for SOR");
+        return IBM_ERR_ARG;
+    }
+    if (int rc = bcm_device_ok(m)) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const long long total = m->ncubes * (long long)m->n * m->n * m->n;
+    const int nb = (int)std::max<long long>(1, std::min<long long>((total + NT - 1) / NT, BCM_NB));
+    const int nbc = (int)std::min<long long>((total + 255) / 256, 16384);
+    // set-up: the partial sums and the state, and for BiCGStab its six vectors
+    auto grab = [&](void** p, size_t bytes) {
+        if (*p) return true;
+        if (ibm::dev_malloc(p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            return false;
+        }
+        return true;
+    };
+    if (!grab((void**)&m->d_part, 2 * BCM_NB * sizeof(double)) || !grab((void**)&m->d_state, sizeof(BcmState)) ||
+        (kind == IBM_BCM_BICGSTAB && !grab((void**)&m->d_ws, 6 * (size_t)m->size * sizeof(double)))) {
+        set_error("ibm_bcm_solve: out of device memory for the solve's workspace");
+        return IBM_ERR_OOM;
+    }
+    BcmState* st = m->d_state;
+    double* part = m->d_part;
+    BcmState h{};
+    auto read_state = [&]() -> int {
+        IBM_HIP(hipMemcpyAsync(&h, st, sizeof(BcmState), hipMemcpyDeviceToHost, s));
+        IBM_HIP(hipStreamSynchronize(s));
+        return IBM_OK;
+    };
+    auto exchange = [&](double* v) {
+        const long long nbx = std::min<long long>((m->nhalo + 255) / 256, 8192);
+        if (nbx > 0) k_bcm_exchange<<<(int)nbx, 256, 0, s>>>(m->nhalo, m->d_dst, m->d_off, m->d_src, v);
+    };
+    auto lap = [&](const double* v, double* y) {
+        k_bcm_lap<<<nbc, 256, 0, s>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level, m->d_mask, v, y);
+    };
+    // the true relative residual of x into h (rr, bb)
+    auto true_residual = [&]() -> int {
+        exchange(x_dev);
+        k_bcm_resid<<<nb, NT, 0, s>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level, m->d_mask, b_dev, x_dev, part);
+        k_bcm_scalar<<<1, NT, 0, s>>>(part, nb, st, BS_RES, 0, 0, tol);
+        IBM_HIP(hipGetLastError());
+        return read_state();
+    };
+    k_bcm_state_reset<<<1, 64, 0, s>>>(st);
+    IBM_HIP(hipGetLastError());
+    int iters = 0, rc = IBM_OK;
+    double rel = 0.0;
+    if (kind == IBM_BCM_SOR) {
+        // red-black SOR in groups of check_every sweeps, the true residual checked
+        // before the first and after every group
+        while (true) {
+            if (int e = true_residual()) return e;
+            if (!(h.rr == h.rr) || !(h.bb == h.bb)) {
+                rc = IBM_ERR_NAN;
+                rel = h.rr;
+                break;
+            }
+            rel = h.bb == 0.0 ? 0.0 : std::sqrt(h.rr / h.bb);
+            if (rel <= tol) break;
+            if (iters >= max_iter) {
+                rc = IBM_NOT_CONVERGED;
+                break;
+            }
+            const int k = std::min(check_every, max_iter - iters);
+            for (int it = 0; it < k; ++it)
+                for (int colour = 0; colour < 2; ++colour) {
+                    exchange(x_dev);
+                    k_bcm_sor<<<nbc, 256, 0, s>>>(m->ncubes, m->n, m->side, m->dx0, m->d_level, m->d_mask, b_dev,
+                                                  x_dev, colour, omega);
+                }
+            IBM_HIP(hipGetLastError());
+            iters += k;
+        }
+    } else {
+        const long long sz = m->size;
+        double *r = m->d_ws, *r0 = r + sz, *p = r0 + sz, *v = p + sz, *sv = v + sz, *tv = sv + sz;
+        // r = b - L x (L x into t, free until the first iteration's second product)
+        exchange(x_dev);
+        lap(x_dev, tv);
+        k_bcm_bs_init<<<nb, NT, 0, s>>>(total, m->n, m->side, b_dev, tv, r, r0, p, v, part);
+        k_bcm_scalar<<<1, NT, 0, s>>>(part, nb, st, BS_INIT, 0, max_iter, tol);
+        IBM_HIP(hipGetLastError());
+        if (int e = read_state()) return e;
+        if (h.done == BCM_ZERO_RHS) {
+            // b = 0: x = 0
+            k_bcm_zero_interior<<<nb, NT, 0, s>>>(total, m->n, m->side, x_dev);
+            IBM_HIP(hipGetLastError());
+        } else if (h.done == BCM_RUNNING) {
+            for (int it = 0; it <= max_iter; ++it) {
+                k_bcm_dot<2><<<nb, NT, 0, s>>>(total, m->n, m->side, r0, r, r, r, part, st);
+                k_bcm_scalar<<<1, NT, 0, s>>>(part, nb, st, BS_RHO, it, max_iter, tol);
+                if (it == max_iter) break;
+                k_bcm_bs_p<<<nb, NT, 0, s>>>(total, m->n, m->side, r, v, p, st);
+                exchange(p);
+                lap(p, v);
+                k_bcm_dot<1><<<nb, NT, 0, s>>>(total, m->n, m->side, r0, v, nullptr, nullptr, part, st);
+                k_bcm_scalar<<<1, NT, 0, s>>>(part, nb, st, BS_ALPHA, it, max_iter, tol);
+                k_bcm_bs_s<<<nb, NT, 0, s>>>(total, m->n, m->side, r, v, sv, part, st);
+                k_bcm_scalar<<<1, NT, 0, s>>>(part, nb, st, BS_HALF, it, max_iter, tol);
+                k_bcm_bs_xhalf<<<nb, NT, 0, s>>>(total, m->n, m->side, p, x_dev, st, it);
+                exchange(sv);
+                lap(sv, tv);
+                k_bcm_dot<2><<<nb, NT, 0, s>>>(total, m->n, m->side, tv, sv, tv, tv, part, st);
+                k_bcm_scalar<<<1, NT, 0, s>>>(part, nb, st, BS_OMEGA, it, max_iter, tol);
+                k_bcm_bs_xr<<<nb, NT, 0, s>>>(total, m->n, m->side, p, sv, tv, x_dev, r, st);
+                IBM_HIP(hipGetLastError());
+                if ((it + 1) % check_every == 0) {
+                    if (int e = read_state()) return e;
+                    if (h.done != BCM_RUNNING) break;
+                }
+            }
+            if (int e = read_state()) return e;
+        }
+        const int why = h.done;
+        iters = h.iters;
+        if (why == BCM_NAN) rc = IBM_ERR_NAN;
+        else if (why == BCM_MAX_ITER || why == BCM_BREAKDOWN) rc = IBM_NOT_CONVERGED;
+        if (int e = true_residual()) return e;
+        rel = h.bb == 0.0 ? 0.0 : std::sqrt(h.rr / h.bb);
+        if (rc == IBM_OK && !(rel == rel)) rc = IBM_ERR_NAN;
+    }
+    if (iters_out) *iters_out = iters;
+    if (rel_residual_out) *rel_residual_out = rel;
+    if (rc == IBM_ERR_NAN) set_error("ibm_bcm_solve: non-finite residual");
+    else if (rc == IBM_NOT_CONVERGED) set_error("ibm_bcm_solve: tolerance not met (iteration cap or breakdown)");
+    return rc;
 } IBM_CATCH_ALL
 
 }  // extern "C"

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libibm.so")
 PERIODIC, INFLOW, OUTFLOW, SLIP = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 SOLVER_PCG_JACOBI, SOLVER_FCG_CNN, SOLVER_FCG_JACOBI, SOLVER_RBSOR = 0, 1, 2, 3
+BCM_BICGSTAB, BCM_SOR = 0, 1
 SCHEME_AB2, SCHEME_CN = 0, 1
 OK, NOT_CONVERGED = 0, 1
 
@@ -121,6 +122,9 @@ def _load():
         "ibm_bcm_laplacian": ([vp, vp, vp, vp], ctypes.c_int),
         "ibm_bcm_sor": ([vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
         "ibm_bcm_set_blocked": ([vp, ctypes.c_int32, vp, vp], ctypes.c_int),
+        "ibm_bcm_solve": ([vp, ctypes.c_int32, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                           ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp],
+                          ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -138,7 +142,7 @@ EXPORTED = ("ibm_create", "ibm_destroy", "ibm_last_error", "ibm_alloc_count", "i
             "ibm_cnn_create", "ibm_cnn_destroy", "ibm_cnn_set_weights", "ibm_cnn_get_weights", "ibm_cnn_forward",
             "ibm_cnn_backward", "ibm_cnn_loss", "ibm_cnn_train_step", "ibm_cnn_precondition",
             "ibm_ctx_set_preconditioner", "ibm_bcm_create", "ibm_bcm_destroy", "ibm_bcm_info", "ibm_bcm_exchange",
-            "ibm_bcm_laplacian", "ibm_bcm_sor", "ibm_bcm_set_blocked")
+            "ibm_bcm_laplacian", "ibm_bcm_sor", "ibm_bcm_set_blocked", "ibm_bcm_solve")
 CNN_NWEIGHTS = 7776
 
 
@@ -549,6 +553,15 @@ class BCM:
         assert blocked.dtype == torch.uint8 and blocked.is_contiguous()
         return _check(_lib.ibm_bcm_set_blocked(self.grid, int(level), _ptr(blocked), _stream()),
                       "ibm_bcm_set_blocked")
+
+    def solve(self, b, x, kind=BCM_BICGSTAB, omega=1.0, tol=1e-8, max_iter=10000, check_every=16):
+        """L x = b on the cube interiors (ibm_bcm_solve); x (cube storage) in/out.
+        Returns (rc, iterations or sweeps, true relative residual)."""
+        it, rel = ctypes.c_int32(), ctypes.c_double()
+        rc = _check(_lib.ibm_bcm_solve(self.grid, int(kind), _ptr(b), _ptr(x), float(omega), float(tol),
+                                       int(max_iter), int(check_every), ctypes.byref(it), ctypes.byref(rel),
+                                       _stream()), "ibm_bcm_solve")
+        return rc, it.value, rel.value
 
     def close(self):
         if self.grid:

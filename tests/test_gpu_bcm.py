@@ -115,3 +115,120 @@ def test_geometry_operator_and_sor_bit_exact():
     for q in range(len(C.cubes)):
         assert np.array_equal(C.interior(got, q), C.interior(refx, q))
     G.close()
+
+
+def _sphere_grid(with_geometry):
+    """Two levels (3 of 12 coarse cubes refined) with, optionally, a tagged sphere across
+    both levels, as a (oracle, GPU) pair."""
+    from oracle import tagging
+    from paper_2002_06206_amd import inputs
+    K, n, dx0 = (3, 2, 2), 8, 1.0
+    refine = np.zeros(K[::-1], bool)
+    refine[0, 0, 1] = refine[0, 1, 1] = refine[1, 0, 1] = True
+    C = bcm.Cubes(K, n, dx0, (0.0, 0.0, 0.0), refine)
+    G = ibm.BCM(K, n, dx0, (0.0, 0.0, 0.0), refine)
+    if with_geometry:
+        tri = inputs.icosphere(3, 3.3, (14.5, 7.7, 4.1), inputs.random_rotation(np.random.default_rng(3)))
+        for lvl in (0, 1):
+            b, _ = tagging.tag(tri, C.level_shape(lvl)[::-1], C.dx(lvl), (0.0, 0.0, 0.0))
+            C.set_blocked(lvl, b)
+            G.set_blocked(lvl, torch.from_numpy(np.ascontiguousarray(b)).cuda())
+    return C, G
+
+
+def _interiors(C, data):
+    return np.concatenate([C.interior(data, q).ravel() for q in range(len(C.cubes))])
+
+
+@pytest.mark.parametrize("geometry", [False, True])
+def test_bicgstab_solve_matches_oracle(geometry):
+    """BiCGStab on the cubes (ibm_bcm_solve) against the oracle's, from the same start, on
+    a consistent right-hand side b = L u.  The iterates after 1, 3 and 10 iterations agree
+    element by element (1e-9: the same steps, the dot products summed in another order).
+    Over hundreds of iterations BiCGStab amplifies that rounding difference, so the
+    converged runs are compared by what fixes them: both meet the tolerance, and the
+    GPU's x meets it by the oracle's operator with the reported residual."""
+    C, G = _sphere_grid(geometry)
+    print("case bcm bicgstab geometry", geometry, flush=True)
+    u = C.fill(lambda x, y, z: np.sin(0.45 * x) * np.cos(0.3 * y) + 0.2 * z * z / 10)
+    b = C.laplacian(C.exchange(u))
+    bd = torch.from_numpy(b).cuda()
+    x0 = np.zeros_like(b)
+    for k in (1, 3, 10):
+        ref, it_ref, status = C.bicgstab(b, x0, 1e-10, k)
+        assert status == "max_iter" and it_ref == k
+        x = torch.from_numpy(x0.copy()).cuda()
+        rc, it, rel = G.solve(bd, x, ibm.BCM_BICGSTAB, tol=1e-10, max_iter=k, check_every=4)
+        d = np.linalg.norm(_interiors(C, x.cpu().numpy()) - _interiors(C, ref)) / np.linalg.norm(_interiors(C, ref))
+        print("  after %d iterations: relative difference %.2e" % (k, d), flush=True)
+        assert rc == ibm.NOT_CONVERGED and it == k and d <= 1e-9
+    ref, it_ref, status = C.bicgstab(b, x0, 1e-10, 2000)
+    assert status == "converged"
+    x = torch.from_numpy(x0.copy()).cuda()
+    rc, it, rel = G.solve(bd, x, ibm.BCM_BICGSTAB, tol=1e-10, max_iter=2000, check_every=8)
+    got = x.cpu().numpy()
+    print("  iterations oracle %d gpu %d, residual %.3e" % (it_ref, it, rel), flush=True)
+    assert rc == ibm.OK and it <= 2 * it_ref
+    # the recursive residual met 1e-10; the true one may sit slightly above it
+    assert rel <= 1e-9
+    assert abs(rel - C.residual(b, got)) <= 1e-3 * rel + 1e-16
+    G.close()
+
+
+@pytest.mark.parametrize("geometry", [False, True])
+def test_sor_solve_matches_oracle(geometry):
+    """Red-black SOR to a tolerance on the cubes: the same sweep count as the oracle's
+    (checks every 10 sweeps) and the same x bit for bit (the sweeps are)."""
+    C, G = _sphere_grid(geometry)
+    print("case bcm sor solve geometry", geometry, flush=True)
+    u = C.fill(lambda x, y, z: np.sin(0.45 * x) * np.cos(0.3 * y) + 0.02 * z * z)
+    b = C.laplacian(C.exchange(u))
+    x0 = np.zeros_like(b)
+    ref, sw_ref, status = C.sor_solve(b, x0, 1.7, 1e-7, 10, 20000)
+    assert status == "converged"
+    x = torch.from_numpy(x0.copy()).cuda()
+    rc, sw, rel = G.solve(torch.from_numpy(b).cuda(), x, ibm.BCM_SOR, omega=1.7, tol=1e-7, max_iter=20000,
+                          check_every=10)
+    print("  sweeps oracle %d gpu %d, residual %.3e" % (sw_ref, sw, rel), flush=True)
+    assert rc == ibm.OK and sw == sw_ref
+    got = x.cpu().numpy()
+    assert np.array_equal(_interiors(C, got), _interiors(C, ref))
+    assert rel <= 1e-7 and abs(rel - C.residual(b, ref)) <= 1e-6 * rel
+    G.close()
+
+
+def test_solve_edge_cases():
+    """b = 0 gives x = 0 for BiCGStab and leaves x for SOR (zero residual at the first
+    check); the iteration cap returns IBM_NOT_CONVERGED after exactly max_iter
+    iterations or sweeps; bad arguments are rejected."""
+    C, G = _sphere_grid(False)
+    zero = torch.zeros(C.size(), dtype=torch.float64, device="cuda")
+    x = torch.ones_like(zero)
+    rc, it, rel = G.solve(zero, x, ibm.BCM_BICGSTAB, tol=1e-8)
+    assert rc == ibm.OK and it == 0 and rel == 0.0
+    assert np.all(_interiors(C, x.cpu().numpy()) == 0.0)
+    x = torch.ones_like(zero)
+    rc, it, rel = G.solve(zero, x, ibm.BCM_SOR, omega=1.5, tol=1e-8)
+    assert rc == ibm.OK and it == 0 and np.all(_interiors(C, x.cpu().numpy()) == 1.0)
+    u = C.fill(lambda x, y, z: np.sin(0.45 * x) + 0.1 * y)
+    b = torch.from_numpy(C.laplacian(C.exchange(u))).cuda()
+    x = torch.zeros_like(b)
+    rc, it, rel = G.solve(b, x, ibm.BCM_BICGSTAB, tol=1e-12, max_iter=3, check_every=2)
+    assert rc == ibm.NOT_CONVERGED and it == 3 and rel > 1e-12
+    ref, it_ref, st = C.bicgstab(b.cpu().numpy(), np.zeros(C.size()), 1e-12, 3)
+    assert st == "max_iter"
+    d = np.linalg.norm(_interiors(C, x.cpu().numpy()) - _interiors(C, ref)) / np.linalg.norm(_interiors(C, ref))
+    assert d <= 1e-10
+    x = torch.zeros_like(b)
+    rc, it, rel = G.solve(b, x, ibm.BCM_SOR, omega=1.5, tol=1e-12, max_iter=7, check_every=5)
+    assert rc == ibm.NOT_CONVERGED and it == 7
+    assert np.array_equal(_interiors(C, x.cpu().numpy()),
+                          _interiors(C, C.rbsor(b.cpu().numpy(), np.zeros(C.size()), 1.5, 7)))
+    for bad in (dict(kind=5), dict(tol=0.0), dict(check_every=0), dict(kind=ibm.BCM_SOR, omega=2.0)):
+        kw = dict(kind=ibm.BCM_BICGSTAB, omega=1.0, tol=1e-8, max_iter=10, check_every=1)
+        kw.update(bad)
+        with pytest.raises(ibm.IBMError):
+            G.solve(b, x, **kw)
+    with pytest.raises(ibm.IBMError):
+        G.solve(b, b)
+    G.close()
