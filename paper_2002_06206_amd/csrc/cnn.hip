@@ -586,15 +586,57 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
     // plane pz: every lane loads one cell, so the four rows take one load each per array
     // (the wave's combine epilogue is spread over its four lane groups)
     const int gye = ty * CTY + r0 + g;
+    // the lane's output cell of row g within a plane (OOB outside the grid: buffer loads
+    // there return zero, buffer stores are dropped)
+    const int ecell = (gxo < nx && gye < ny) ? gxo + nx * gye : -1;
     auto load_epi = [&](int pz, MPre& R) {
         if (EPI != EPI_COMBINE) return;
-        R.er = R.erp = 0.0f;
-        R.epc = 0;
-        if (pz < z1 && gxo < nx && gye < ny) {
-            const long long c = (long long)gxo + (long long)nx * gye + plane * pz;
-            R.er = cio.r[c];
-            R.epc = cio.pcode[c];
-            if (cio.rp) R.erp = cio.rp[c];
+        // branch-free: planes at or past z1 get empty resources (zeros)
+        const bool zin = pz < z1;
+        const long long pb = zin ? (long long)pz * plane : 0;
+        const int cells = zin ? (int)plane : 0;
+        const __amdgpu_buffer_rsrc_t rr_ =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(cio.r + pb), 0, 4 * cells, RSRC3);
+        const __amdgpu_buffer_rsrc_t rc_ =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(cio.pcode + pb), 0, cells, RSRC3);
+        const __amdgpu_buffer_rsrc_t rp_ = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(cio.rp ? cio.rp + pb : cio.r), 0, cio.rp ? 4 * cells : 0, RSRC3);
+        R.er = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rr_, ecell < 0 ? OOB : 4 * ecell, 0, 0));
+        R.erp = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp_, ecell < 0 ? OOB : 4 * ecell, 0, 0));
+        R.epc = __builtin_amdgcn_raw_buffer_load_b8(rc_, ecell < 0 ? OOB : ecell, 0, 0);
+    };
+    // Output stores, branch-free and one plane late (as in k_mfwd): plane z's values wait
+    // in `held` / `held1` and are stored right after the loads at the top of the next
+    // plane's step, with loop-invariant offsets and a per-plane resource (an empty one
+    // before the first plane).
+    int so[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int gy = ty * CTY + r0 + rr;
+        so[rr] = (gxo < nx && gy < ny) ? ((gxo + nx * gy) * 16 + 4 * g) * 2 : OOB;
+    }
+    uint2 held[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) held[rr] = make_uint2(0u, 0u);
+    float held1 = 0.0f;
+    auto store_held = [&](int zp) {
+        const bool any = zp >= z0;
+        if constexpr (COUT == 16) {
+            const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+                static_cast<uint16_t*>(out) + (any ? (long long)zp * plane * 16 : 0), 0, any ? (int)(plane * 32) : 0,
+                RSRC3);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+                const v2u w = {held[rr].x, held[rr].y};
+                __builtin_amdgcn_raw_buffer_store_b64(w, ro, so[rr], 0, 0);
+            }
+        } else {
+            float* dst = EPI == EPI_COMBINE ? cio.z : static_cast<float*>(out);
+            const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+                dst + (any ? (long long)zp * plane : 0), 0, any ? (int)(plane * 4) : 0, RSRC3);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, held1), ro,
+                                                  ecell < 0 ? OOB : 4 * ecell, 0, 0);
         }
     };
     auto store_plane = [&](int slot, const MPre& R) {
@@ -632,6 +674,7 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
     auto step = [&](int z, MPre& L, const MPre& S) {
         load_plane(z + (DEEP ? 3 : 2), L);
         load_epi(z + 1, L);
+        store_held(z - 1);
         // ring slots of the planes z - 1, z, z + 1
         const int sl0 = (z + 3) & 3, sl1 = z & 3, sl2 = (z + 1) & 3;
         // gate of the output cells, BF16(hsig(Wg * g)) as the stored gate: gathered
@@ -681,30 +724,25 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
             // output row g of the lane's column: lane group 0 holds the four rows' sums
             const float t1 = __shfl(o1[1], j), t2 = __shfl(o1[2], j), t3 = __shfl(o1[3], j);
             const float om = g == 0 ? o1[0] : (g == 1 ? t1 : (g == 2 ? t2 : t3));
-            if (gxo < nx && gye < ny) {
-                const long long c = (long long)gxo + (long long)nx * gye + plane * z;
-                if (EPI == EPI_COMBINE) {
-                    const float zi = invf[jcnt(S.epc)] * S.er + sc * om;
-                    cio.z[c] = zi;
-                    zsum[0] += (double)zi * (double)S.er;
-                    zsum[1] += (double)zi * (double)S.erp;
-                } else {
-                    static_cast<float*>(out)[c] = om;
-                }
+            if (EPI == EPI_COMBINE) {
+                // outside the grid r = r_prev = 0 and the code is 0: no contribution
+                const float zi = invf[jcnt(S.epc)] * S.er + sc * om;
+                held1 = zi;
+                zsum[0] += (double)zi * (double)S.er;
+                zsum[1] += (double)zi * (double)S.erp;
+            } else {
+                held1 = om;
             }
         }
         if constexpr (COUT == 16) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-                const int gy = ty * CTY + r0 + rr;
-                if (gxo >= nx || gy >= ny) continue;
-                const long long c = (long long)gxo + (long long)nx * gy + plane * z;
                 float v[4] = {acc[rr][0], acc[rr][1], acc[rr][2], acc[rr][3]};
                 if (EPI == EPI_GATE) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) v[r] *= gate4[rr][r];
                 }
-                *reinterpret_cast<uint2*>(static_cast<uint16_t*>(out) + c * 16 + 4 * g) = pack4(v);
+                held[rr] = pack4(v);
             }
         }
         store_plane((z + 2) & 3, S);   // slot of plane z - 2, last read for plane z - 1
@@ -730,6 +768,7 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
     } else {
         for (int z = z0; z < z1; ++z) step(z, A, A);
     }
+    store_held(z1 - 1);
     if (EPI == EPI_COMBINE) {
         block_reduce<2>(zsum, shr);
         if (threadIdx.x == 0) {
@@ -934,8 +973,37 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
     const int xh = wv & 1, r0 = 4 * (wv >> 1);
     const int cb = j + 16 * xh + PX * r0;
     const int gx = tx * CTX + 16 * xh + j;
+    // Output stores, branch-free and one plane late.  Each lane's four 8-byte stores use
+    // loop-invariant byte offsets within a plane (OOB for cells outside the grid, where
+    // the buffer store is dropped) and a per-plane resource.  Plane z's packed values
+    // stay in `held` until the stores issued at the top of iteration z + 1 have read them
+    // (they are overwritten only after that iteration's convolution), and those stores
+    // are issued after the iteration's loads, so that waiting for the loads never waits
+    // for a store and no register a store still reads is reused early.
+    int so[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int gy = ty * CTY + r0 + rr;
+        so[rr] = (gx < nx && gy < ny) ? ((gx + nx * gy) * 16 + 4 * g) * 2 : OOB;
+    }
+    uint2 held[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) held[rr] = make_uint2(0u, 0u);
+    // the stores of plane zp (an empty resource before the first plane: dropped)
+    auto store_held = [&](int zp) {
+        const bool any = zp >= z0;
+        const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+            out + (any ? (long long)zp * plane * 16 : 0), 0, any ? (int)(plane * 32) : 0, RSRC3);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+            const v2u w = {held[rr].x, held[rr].y};
+            __builtin_amdgcn_raw_buffer_store_b64(w, ro, so[rr], 0, 0);
+        }
+    };
     for (int z = z0; z < z1; ++z) {
         load_xg(z + 4);
+        store_held(z - 1);
         make_a1(z + 2);
         f32x4 acc[4];
 #pragma unroll
@@ -943,15 +1011,13 @@ __global__ void __launch_bounds__(256, 3) k_mfwd(int nx, int ny, int nz, int mz,
         conv16_plane(ring, cb, g, (z + 3) & 3, z & 3, (z + 1) & 3, wa, acc);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-            const int gy = ty * CTY + r0 + rr;
-            if (gx >= nx || gy >= ny) continue;
-            const long long c = (long long)gx + (long long)nx * gy + plane * z;
             float v[4] = {acc[rr][0], acc[rr][1], acc[rr][2], acc[rr][3]};
-            *reinterpret_cast<uint2*>(out + c * 16 + 4 * g) = pack4(v);
+            held[rr] = pack4(v);
         }
         store_xg(z & 3);   // plane z + 4
         __syncthreads();
     }
+    store_held(z1 - 1);
 }
 
 // Weight gradient of one layer: dW[t][ci][co] = sum over cells c of X[c + off_t][ci] dY[c][co].
