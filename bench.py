@@ -466,13 +466,48 @@ def sor_timing(case, s, args, ibm, torch):
     return out
 
 
+def bcm_solve_timing(G, case, n, ibm, torch):
+    """The pressure solve on the cubes (ibm_bcm_solve) with the geometry set: b = L u for
+    a smooth u sampled at the cube cell centres (a consistent right-hand side), from
+    x = 0 to a relative residual of 1e-6, by BiCGStab and by red-black SOR (capped at 4,000
+    sweeps), timed by the host clock (the call synchronises)."""
+    L = [case.n[a] * case.dx for a in range(3)]
+    org = torch.from_numpy(G.origins).cuda().to(torch.float64)            # fine-cell units
+    w = torch.where(torch.from_numpy(G.levels).cuda() == 1, 1.0, 2.0).to(torch.float64)
+    ar = torch.arange(n, dtype=torch.float64, device="cuda") + 0.5
+    side = n + 4
+    u = torch.zeros(G.size, dtype=torch.float64, device="cuda")
+    ui = u.view(G.ncubes, side, side, side)[:, 2:2 + n, 2:2 + n, 2:2 + n]
+    fine_dx = 0.5 * 2.0 * case.dx
+    xc = case.origin[0] + (org[:, 0, None] + ar[None, :] * w[:, None]) * fine_dx
+    yc = case.origin[1] + (org[:, 1, None] + ar[None, :] * w[:, None]) * fine_dx
+    zc = case.origin[2] + (org[:, 2, None] + ar[None, :] * w[:, None]) * fine_dx
+    ui.copy_(torch.sin(3.0 * xc[:, None, None, :] / L[0]) * torch.cos(2.0 * yc[:, None, :, None] / L[1])
+             + 0.5 * zc[:, :, None, None] / L[2])
+    G.exchange(u)
+    b = torch.zeros_like(u)
+    G.laplacian(u, b)
+    out = {}
+    for name, kw in (("bicgstab", dict(kind=ibm.BCM_BICGSTAB, max_iter=20000, check_every=16)),
+                     ("rbsor", dict(kind=ibm.BCM_SOR, omega=1.95, max_iter=4000, check_every=100))):
+        x = torch.zeros_like(u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, it, rel = G.solve(b, x, tol=1e-6, **kw)
+        el = time.perf_counter() - t0
+        out[name] = {"rc": rc, "iterations": it, "ms": round(el * 1e3, 2), "rel_residual": rel,
+                     "us_per_iteration": round(el * 1e6 / max(it, 1), 1)}
+    return out
+
+
 def bcm_timing(case, blocked, args, ibm, torch, reps=20):
     """The building-cube grid (Sec. 2.2) over the workload's domain: coarse cubes of 16^3
     cells of twice the workload's cell size, refined (8 cubes of 16^3 cells at the
     workload's cell size) wherever the geometry cuts a grid line inside them; the halo
     exchange, the 7-point operator and red-black SOR sweeps (two exchanges and two half
     sweeps each) timed with events on the stream they run on; then the operator and the
-    sweeps again with the workload's geometry on both levels (ibm_bcm_set_blocked)."""
+    sweeps again with the workload's geometry on both levels (ibm_bcm_set_blocked), and the
+    pressure solve on the cubes with that geometry (bcm_solve_timing)."""
     n = 16
     N = case.n
     if any(v % (2 * n) for v in N):
@@ -523,6 +558,7 @@ def bcm_timing(case, blocked, args, ibm, torch, reps=20):
     torch.cuda.synchronize()
     mlap_us = ev2[0].elapsed_time(ev2[1]) / reps * 1e3
     msor_us = ev2[1].elapsed_time(ev2[2]) / reps * 1e3
+    solve = bcm_solve_timing(G, case, n, ibm, torch)
     cells = G.ncubes * n ** 3
     fine = int(refine.sum())
     # algorithmic bytes: operator 16 B per cell (x read once, y written); exchange per
@@ -533,7 +569,7 @@ def bcm_timing(case, blocked, args, ibm, torch, reps=20):
            "halo_cells": int(G.nhalo), "exchange_us": round(ex_us, 2), "laplacian_us": round(lap_us, 2),
            "sor_sweep_us": round(sor_us, 2),
            "with_geometry": {"laplacian_us": round(mlap_us, 2), "sor_sweep_us": round(msor_us, 2),
-                             "mask_bytes_per_cell": 1},
+                             "mask_bytes_per_cell": 1, "solve": solve},
            "laplacian_bytes_per_cell": 16,
            "laplacian_achieved_gbs": round(lap_bytes / (lap_us * 1e-6) / 1e9, 1),
            "roofline": {"bound": "hbm", "achieved": round(lap_bytes / (lap_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
