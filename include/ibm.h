@@ -456,8 +456,8 @@ int ibm_bcm_set_blocked(ibm_bcm* grid, int32_t level, const uint8_t* blocked_dev
  * sweeps made; rel_residual_out: the true residual ||b - L x|| / ||b|| of the returned x
  * (0 for b = 0).  Returns IBM_OK, IBM_NOT_CONVERGED, IBM_ERR_NAN (non-finite residual).
  * The first call allocates the workspace, kept by the grid until ibm_bcm_destroy:
- * partial sums and a small state, and for BiCGStab six vectors of the storage size.
- * Synchronises the stream. */
+ * partial sums and a small state, and for BiCGStab six vectors of the storage size;
+ * solves on one grid share it, so they must not overlap.  Synchronises the stream. */
 enum { IBM_BCM_BICGSTAB = 0, IBM_BCM_SOR = 1 };
 int ibm_bcm_solve(ibm_bcm* grid, int32_t kind, const double* b_dev, double* x_dev, double omega, double tol,
                   int32_t max_iter, int32_t check_every, int32_t* iters_out, double* rel_residual_out,
