@@ -208,6 +208,9 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     st = s.new_state(case.u_in)
+    # pressure history for the solve's initial guess 2 p^n - p^{n-1} (at the first step
+    # p_prev = p, so the guess is p)
+    p_prev = st["p"].clone() if args.p_guess == "extrapolate" else None
     # device memory in use with the context, the state (and the network) resident: the
     # whole device's figure after torch's cache is released, of which torch_live are
     # this process's live torch tensors (the state, the inputs)
@@ -225,7 +228,7 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
                             tol=args.tol if tol is None else tol,
                             max_iter=20000, check_every=16, kind=kind,
                             inner_tol=args.inner_tol_learned if solver == "mixed_learned" else args.inner_tol,
-                            inner_max_iter=2000, inner_restart=args.inner_restart)
+                            inner_max_iter=2000, inner_restart=args.inner_restart, p_prev=p_prev)
         ctl["dt_prev"] = dt
         return p
 
@@ -726,6 +729,8 @@ def main():
                          "replacement, so it favours fewer, longer segments)")
     ap.add_argument("--inner-restart", type=int, default=0,
                     help="mixed solve: 1 = start every FP32 segment from a fresh search direction")
+    ap.add_argument("--p-guess", default="extrapolate", choices=["extrapolate", "previous"],
+                    help="initial guess of each step's pressure solve: 2 p^n - p^{n-1} or p^n")
     ap.add_argument("--solver", default="mixed_learned", choices=["mixed", "mixed_learned", "pcg_fp64"],
                     help="headline solver (the metric names mixed+learned); plain FP64 and mixed always run")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned solver")
@@ -828,7 +833,8 @@ def main():
         "config": {"workload": case.name, "cells": list(case.n), "triangles": int(len(case.tri)),
                    "cuts": head["cuts"], "solver": head["solver"], "tol": args.tol, "inner_tol": args.inner_tol,
                    "inner_tol_learned": args.inner_tol_learned,
-                   "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm},
+                   "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm,
+                   "pressure_guess": "2p^n - p^(n-1)" if args.p_guess == "extrapolate" else "p^n"},
         "plain_fp64_value": plain["value"] if plain else None,
         "speedup_vs_plain_fp64": head["value"] / plain["value"] if plain else None,
         "solvers": {k: {kk: vv for kk, vv in v.items()

@@ -134,6 +134,10 @@ typedef struct {
                             /* flux, q_f = (1 - w) q_central + w q_QUICK (Sec. 3:    */
                             /* 0.1 in the paper's runs; 0 = central); explicit in    */
                             /* both schemes (the CN operator keeps central)          */
+    double* p_prev;         /* NULL, or a device array of N doubles holding p^{n-1}: */
+                            /* the pressure solve then starts from 2 p^n - p^{n-1}   */
+                            /* instead of p^n, and p_prev receives p^n (set it to p  */
+                            /* before the first step); distinct from p_dev           */
 } ibm_step_params;
 
 typedef struct {
@@ -222,7 +226,8 @@ int ibm_init_state(ibm_ctx* ctx, void* u_dev[3], double* U_dev[3], double* p_dev
  * predictor in flux form with the axis-projected ghost values of eq. (q_axis)
  * across blocked faces, face velocity U* (Rhie-Chow style compact face velocity),
  * b = div U* / dt made compatible on enclosed components, pressure solve warm
- * started from p, projection of U and u, FP64 divergence check.
+ * started from p (or, with prm->p_prev, from the linear extrapolation 2 p - p_prev of
+ * the two previous pressures), projection of U and u, FP64 divergence check.
  * u_dev, h_dev: in u^n, H^{n-1}; out u^{n+1}, H^n.  U_dev: in U^n, out U^{n+1}.
  * p_dev: in guess, out p^{n+1} (zero mean on enclosed components).
  * wall_dev: n_cut x 3 wall velocities u_IB at the crossing points, or NULL.

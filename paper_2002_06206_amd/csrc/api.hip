@@ -285,6 +285,7 @@ int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const 
     if (!(prm->dt > 0.0) || !(prm->nu >= 0.0) || prm->poisson.max_iter <= 0 || !(prm->poisson.tol > 0.0))
         return bad("ibm_step: need dt > 0, nu >= 0, tol > 0, max_iter > 0");
     if (prm->scheme != IBM_SCHEME_AB2 && prm->scheme != IBM_SCHEME_CN) return bad("ibm_step: unknown scheme");
+    if (prm->p_prev == p) return bad("ibm_step: p_prev must be distinct from p");
     hipStream_t s = (hipStream_t)stream;
     const bool cn = prm->scheme == IBM_SCHEME_CN;
     if (cn && !c->cn_ws)
@@ -299,6 +300,10 @@ int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const 
     }
     rc = step_rhs(c, U, wall, prm->dt, s);
     if (rc) return rc;
+    if (prm->p_prev) {
+        rc = step_extrapolate(c, p, prm->p_prev, s);
+        if (rc) return rc;
+    }
     ibm_stats local;
     std::memset(&local, 0, sizeof(local));
     int prc = poisson_run(c, c->b, p, &prm->poisson, st ? &local : nullptr, s);

@@ -49,7 +49,7 @@ class StepParams(ctypes.Structure):
                 ("c1", ctypes.c_double),
                 ("csm_on", ctypes.c_int32), ("step", ctypes.c_int32), ("body_force", ctypes.c_double * 3),
                 ("poisson", SolverOpts), ("scheme", ctypes.c_int32), ("mom_max_iter", ctypes.c_int32),
-                ("mom_tol", ctypes.c_double), ("quick", ctypes.c_double)]
+                ("mom_tol", ctypes.c_double), ("quick", ctypes.c_double), ("p_prev", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -378,10 +378,15 @@ def solver_opts(tol=1e-10, max_iter=20000, kind=SOLVER_PCG_JACOBI, inner_tol=1e-
 
 
 def step_params(dt, nu, c1=1.0 / 20.0, csm=True, step=0, body=(0.0, 0.0, 0.0), dt_prev=0.0, scheme="ab2",
-                mom_tol=1e-10, mom_max_iter=200, quick=0.0, **solver):
+                mom_tol=1e-10, mom_max_iter=200, quick=0.0, p_prev=None, **solver):
+    """p_prev: None, or a float64 device tensor holding the previous pressure (the solve
+    then starts from 2 p - p_prev, and p_prev receives p)."""
     sc = {"ab2": SCHEME_AB2, "cn": SCHEME_CN}[scheme]
+    if p_prev is not None and p_prev.dtype != torch.float64:
+        raise IBMError("p_prev must be a float64 tensor")
     return StepParams(dt, dt_prev, nu, c1, int(bool(csm)), int(step), (ctypes.c_double * 3)(*body),
-                      solver_opts(**solver), sc, int(mom_max_iter), float(mom_tol), float(quick))
+                      solver_opts(**solver), sc, int(mom_max_iter), float(mom_tol), float(quick),
+                      None if p_prev is None else _ptr(p_prev))
 
 
 class Solver:

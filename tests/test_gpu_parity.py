@@ -211,18 +211,28 @@ def _run_both(case_grid, tri, steps, prm_kw, u0, deadend=False, wall_fn=None, pr
                            body=prm_kw.get("body", (0, 0, 0)), tol=prm_kw["tol"])
     last = None
     dt_prev = 0.0
+    # extrap: the pressure solve starts from 2 p^n - p^{n-1} (the oracle is handed that
+    # guess, the library forms it from p_prev)
+    extrap = prm_kw.get("extrap", False)
+    pp = p.copy()
+    if extrap:
+        gs["p_prev"] = gs["p"].clone()
     for n in range(steps):
         wall = wall_fn(X, (n + 1) * prm_kw["dt"]) if wall_fn else None
         # a varying step exercises the variable-step Adams-Bashforth weights
         dt = prm_kw["dt"] * (1.0 - 0.07 * (n % 3)) if prm_kw.get("vary_dt") else prm_kw["dt"]
         oprm.dt, oprm.dt_prev = dt, dt_prev
-        u, U, p, h, ostats = flow.step(st, u, U, p, h, oprm, n, wall)
+        guess = 2.0 * p - pp if extrap else p
+        pp = p.copy()
+        u, U, p, h, ostats = flow.step(st, u, U, guess, h, oprm, n, wall)
         gp = ibm.step_params(dt, prm_kw["nu"], csm=prm_kw.get("csm", True), step=n, dt_prev=dt_prev,
-                             body=prm_kw.get("body", (0, 0, 0)), tol=prm_kw["tol"], max_iter=20000)
+                             body=prm_kw.get("body", (0, 0, 0)), tol=prm_kw["tol"], max_iter=20000,
+                             p_prev=gs["p_prev"] if extrap else None)
         dt_prev = dt
         rc, gstats = s.step(gs, gp, torch.from_numpy(wall).cuda() if wall is not None else None)
         assert rc == 0
         last = (ostats, gstats)
+    oprm.p_before_last = pp   # the oracle's pressure before the last step
     return s, st, (u, U, p, h), gs, last, oprm
 
 
@@ -260,6 +270,23 @@ def test_step_parity_sphere32():
     Fp, Fv = s.forces(gs, case.nu)
     oFp, oFv = flow.forces(st, o[0], o[2], ostats["nut"], case.nu)
     assert np.allclose(Fp, oFp, rtol=1e-9, atol=1e-12) and np.allclose(Fv, oFv, rtol=1e-9, atol=1e-12)
+
+
+def test_step_parity_extrapolated_pressure_guess():
+    """With p_prev the step's pressure solve starts from 2 p^n - p^{n-1}: the steps equal
+    the oracle's steps handed that guess (sphere32, 8 steps), p_prev ends holding the
+    pressure before the last step, and an aliased p_prev is refused."""
+    case = inputs.case_sphere32()
+    g = _grid(case.n, case.dx, case.origin, case.bc, case.u_in)
+    print("case sphere32 extrapolated guess", flush=True)
+    s, st, o, gs, (ostats, gstats), oprm = _run_both(
+        g, case.tri, 8, dict(dt=case.dt, nu=case.nu, tol=1e-13, vary_dt=True, extrap=True), (1.0, 0.0, 0.0))
+    _compare_state(o, gs)
+    assert gstats["rel_residual"] < 1e-12
+    assert abs(gstats["iters_inner"] - ostats["iters"]) <= 2
+    assert rel_l2(gs["p_prev"].cpu().numpy(), oprm.p_before_last) < 1e-10
+    with pytest.raises(ibm.IBMError):
+        s.step(gs, ibm.step_params(case.dt, case.nu, step=8, tol=1e-8, max_iter=100, p_prev=gs["p"]))
 
 
 def test_step_parity_deadend_and_channels():
