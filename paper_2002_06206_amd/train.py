@@ -28,16 +28,20 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
     p = its solution).  With depths, the i-th kept pair is taken at Krylov depth
     k = depths[i % len(depths)]: x_k = k Jacobi-PCG iterates from zero on L x = b and
     the pair (b - L x_k, p - x_k), which satisfies the same equation and carries the
-    error a Krylov method still has to remove after k iterations.  Returns the solver
-    (it owns the stencil the pairs belong to) and the pairs."""
+    error a Krylov method still has to remove after k iterations.  Depth -1 takes x
+    = 2 p^n - p^{n-1}, the extrapolated initial guess of the step's solve (what is left
+    for the solver when the step starts from that guess).  Returns the solver (it owns
+    the stencil the pairs belong to) and the pairs."""
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
     blocked, _ = s.tag(case.tri, want_theta=False)
     s.build(blocked, None, case.deadend)
     st = s.new_state(case.u_in)
     pairs = []
     umax, dt_prev = max(abs(v) for v in case.u_in), 0.0
+    p_older = st["p"].clone()   # p^{n-1}
     for k in range(steps):
         dt = min(case.dt, 0.3 * case.dx / max(umax, 1e-30))
+        p_old = st["p"].clone()     # p^n
         rc, stats = s.step(st, ibm.step_params(dt, case.nu, csm=case.csm, step=k, dt_prev=dt_prev, tol=tol))
         if rc < 0 or not np.isfinite(stats["umax"]):
             break
@@ -51,7 +55,11 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
                     x = torch.zeros_like(b)
                     s.poisson(b, x, tol=1e-300, max_iter=depth, kind=ibm.SOLVER_PCG_JACOBI)
                     b, p = b - s.laplacian(x), p - x
+                elif depth < 0:
+                    x = 2.0 * p_old - p_older
+                    b, p = b - s.laplacian(x), p - x
                 pairs.append((b, p))
+        p_older = p_old
     return s, pairs
 
 
