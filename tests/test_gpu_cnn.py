@@ -313,8 +313,9 @@ def test_fcg_cnn_solve_reaches_fp64_tolerance():
 
 def test_steps_allocate_nothing():
     """ibm_step allocates nothing after set-up: the library's allocation count stays the
-    same across learned, mixed-Jacobi and Crank-Nicolson steps once the network is
-    attached and the Crank-Nicolson workspace prepared."""
+    same across learned, mixed-Jacobi and Crank-Nicolson steps, with and without the
+    extrapolated pressure guess, once the network is attached and the Crank-Nicolson
+    workspace prepared."""
     case = inputs.case_ellipsoid_window(103, 32)
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.MIXED)
     gb, _ = s.tag(case.tri, want_theta=False)
@@ -323,15 +324,17 @@ def test_steps_allocate_nothing():
     net.attach(s)
     s.prepare_crank_nicolson()
     st = s.new_state(case.u_in)
+    p_prev = st["p"].clone()
     torch.cuda.synchronize()
     a0 = ibm.alloc_count()
     print("case steps allocate nothing", case.n, flush=True)
     kinds = [(ibm.SOLVER_FCG_CNN, "ab2"), (ibm.SOLVER_FCG_CNN, "ab2"), (ibm.SOLVER_FCG_JACOBI, "ab2"),
              (ibm.SOLVER_FCG_CNN, "cn")]
     for k, (kind, scheme) in enumerate(kinds):
+        # the last two steps start their pressure solves from the extrapolated guess
         rc, stats = s.step(st, ibm.step_params(0.2, case.nu, step=k, dt_prev=0.2 if k else 0.0, tol=1e-6,
                                                kind=kind, inner_tol=1e-3, inner_max_iter=500, scheme=scheme,
-                                               mom_tol=1e-6))
+                                               mom_tol=1e-6, p_prev=p_prev if k >= 2 else None))
         assert rc == 0 and stats["fallback_used"] == 0
     torch.cuda.synchronize()
     assert ibm.alloc_count() == a0
