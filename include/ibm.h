@@ -136,8 +136,9 @@ typedef struct {
                             /* both schemes (the CN operator keeps central)          */
     double* p_prev;         /* NULL, or a device array of N doubles holding p^{n-1}: */
                             /* the pressure solve then starts from 2 p^n - p^{n-1}   */
-                            /* instead of p^n, and p_prev receives p^n (set it to p  */
-                            /* before the first step); distinct from p_dev           */
+                            /* when that leaves a smaller residual ||b - L x|| than  */
+                            /* p^n (else from p^n), and p_prev receives p^n (set it  */
+                            /* to p before the first step); distinct from p_dev      */
 } ibm_step_params;
 
 typedef struct {
@@ -227,7 +228,8 @@ int ibm_init_state(ibm_ctx* ctx, void* u_dev[3], double* U_dev[3], double* p_dev
  * across blocked faces, face velocity U* (Rhie-Chow style compact face velocity),
  * b = div U* / dt made compatible on enclosed components, pressure solve warm
  * started from p (or, with prm->p_prev, from the linear extrapolation 2 p - p_prev of
- * the two previous pressures), projection of U and u, FP64 divergence check.
+ * the two previous pressures when its residual is the smaller), projection of U and u,
+ * FP64 divergence check.
  * u_dev, h_dev: in u^n, H^{n-1}; out u^{n+1}, H^n.  U_dev: in U^n, out U^{n+1}.
  * p_dev: in guess, out p^{n+1} (zero mean on enclosed components).
  * wall_dev: n_cut x 3 wall velocities u_IB at the crossing points, or NULL.

@@ -301,7 +301,7 @@ int ibm_step(ibm_ctx* c, void* u[3], double* U[3], double* p, void* h[3], const 
     rc = step_rhs(c, U, wall, prm->dt, s);
     if (rc) return rc;
     if (prm->p_prev) {
-        rc = step_extrapolate(c, p, prm->p_prev, s);
+        rc = step_initial_guess(c, c->b, p, prm->p_prev, s);
         if (rc) return rc;
     }
     ibm_stats local;

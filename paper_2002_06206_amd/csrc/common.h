@@ -340,8 +340,9 @@ int laplacian_run(ibm_ctx* c, const double* x, double* y, hipStream_t s);
 int march_blocks(const Geo& g);
 int init_state_run(ibm_ctx* c, void** u, double** U, double* p, void** h, const double* u0,
                    const double* wall, hipStream_t s);
-// p <- 2 p - p_prev and p_prev <- p (old), one pass
-int step_extrapolate(ibm_ctx* c, double* p, double* p_prev, hipStream_t s);
+// initial guess of a step's solve: p <- 2 p - p_prev where that leaves the smaller
+// residual of L x = b, and p_prev <- p (old)
+int step_initial_guess(ibm_ctx* c, const double* b, double* p, double* p_prev, hipStream_t s);
 int step_predict(ibm_ctx* c, void** u, double** U, void** h, const double* wall, const ibm_step_params* prm,
                  hipStream_t s);
 int step_rhs(ibm_ctx* c, double** U, const double* wall, double dt, hipStream_t s);

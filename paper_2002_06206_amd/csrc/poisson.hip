@@ -1041,6 +1041,67 @@ void timing_collect(ibm_ctx* c) {
     }
 }
 
+// ---------------------------------------------------------- initial guess of a step
+// A step's solve starts from p^n or from g = 2 p^n - p^{n-1}, whichever leaves the
+// smaller residual ||b - L x||: the extrapolation pays once the flow is developed and
+// overshoots while an impulsive start still changes the pressure quickly.  Partials of
+// ||b - L p||^2 go to SLOT_RES0 and of ||b - L g||^2 to SLOT_RES1; every block of the
+// picking kernel sums them in block order, so all blocks take the same decision.
+
+__global__ void __launch_bounds__(NT) k_guess_fill(long long n, const double* __restrict__ p,
+                                                   const double* __restrict__ pp, double* __restrict__ g) {
+    for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += (long long)gridDim.x * NT)
+        g[c] = 2.0 * p[c] - pp[c];
+}
+
+__global__ void __launch_bounds__(NT) k_guess_res(Geo g, const uint8_t* __restrict__ pcode,
+                                                  const double* __restrict__ b, const double* __restrict__ x,
+                                                  double* __restrict__ partials, int slot) {
+    __shared__ double sh[NT];
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    double v[1] = {0.0};
+    march(g, pcode, x, [&](long long c, uint8_t pc, double xc, double xw, double xe, double xs, double xn,
+                           double xb, double xt) {
+        const double res = b[c] - lap_code(pc, xc, xw, xe, xs, xn, xb, xt, idx2);
+        v[0] += res * res;
+    });
+    block_reduce<1>(v, sh);
+    if (threadIdx.x == 0) partials[slot * MAX_BLOCKS + blockIdx.x] = v[0];
+}
+
+// p <- g where g leaves the smaller residual; p_prev <- p (old)
+__global__ void __launch_bounds__(NT) k_guess_pick(long long n, const double* __restrict__ partials, int nparts,
+                                                   double* __restrict__ p, double* __restrict__ pp,
+                                                   const double* __restrict__ g) {
+    __shared__ double sh[2 * NT];
+    double v[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < nparts; q += NT) {
+        v[0] += partials[SLOT_RES0 * MAX_BLOCKS + q];
+        v[1] += partials[SLOT_RES1 * MAX_BLOCKS + q];
+    }
+    block_reduce<2>(v, sh);
+    const bool use = v[1] < v[0];
+    for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += (long long)gridDim.x * NT) {
+        const double t = p[c];
+        if (use) p[c] = g[c];
+        pp[c] = t;
+    }
+}
+
+int step_initial_guess(ibm_ctx* c, const double* b, double* p, double* p_prev, hipStream_t s) {
+    const Geo& g = c->geo;
+    const long long N = c->N;
+    const int nb = march_blocks(g);
+    const int ne = (int)std::min<long long>((N + NT - 1) / NT, 4096);
+    double* gbuf = c->zbuf;   // free before the solve, which initialises it
+    k_guess_fill<<<ne, NT, 0, s>>>(N, p, p_prev, gbuf);
+    k_guess_res<<<nb, NT, 0, s>>>(g, c->pcode, b, p, c->partials, SLOT_RES0);
+    k_guess_res<<<nb, NT, 0, s>>>(g, c->pcode, b, gbuf, c->partials, SLOT_RES1);
+    k_guess_pick<<<ne, NT, 0, s>>>(N, c->partials, nb, p, p_prev, gbuf);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
 int laplacian_run(ibm_ctx* c, const double* x, double* y, hipStream_t s) {
     k_lap<<<march_blocks(c->geo), NT, 0, s>>>(c->geo, c->pcode, x, y);
     IBM_HIP(hipGetLastError());

@@ -1126,22 +1126,6 @@ int init_state_run(ibm_ctx* c, void** u, double** U, double* p, void** h, const 
                                     : init_t<float>(c, u, U, p, h, u0, wall, s);
 }
 
-// initial guess of the pressure solve from the two previous pressures
-__global__ void __launch_bounds__(NT) k_extrapolate(long long n, double* __restrict__ p, double* __restrict__ pp) {
-    for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += (long long)gridDim.x * NT) {
-        const double pn = p[c];
-        p[c] = 2.0 * pn - pp[c];
-        pp[c] = pn;
-    }
-}
-
-int step_extrapolate(ibm_ctx* c, double* p, double* p_prev, hipStream_t s) {
-    const long long nb = std::min<long long>((c->N + NT - 1) / NT, 8192);
-    k_extrapolate<<<(int)nb, NT, 0, s>>>(c->N, p, p_prev);
-    IBM_HIP(hipGetLastError());
-    return IBM_OK;
-}
-
 int step_predict(ibm_ctx* c, void** u, double** U, void** h, const double* wall, const ibm_step_params* prm,
                  hipStream_t s) {
     return c->precision == IBM_FP64 ? predict_t<double>(c, u, U, h, wall, prm, s)
