@@ -208,8 +208,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     st = s.new_state(case.u_in)
-    # pressure history for the solve's initial guess 2 p^n - p^{n-1} (at the first step
-    # p_prev = p, so the guess is p)
+    # pressure history for the solve's initial guess (the better of p^n and
+    # 2 p^n - p^{n-1}; at the first step p_prev = p, so the guess is p)
     p_prev = st["p"].clone() if args.p_guess == "extrapolate" else None
     # device memory in use with the context, the state (and the network) resident: the
     # whole device's figure after torch's cache is released, of which torch_live are
@@ -730,7 +730,8 @@ def main():
     ap.add_argument("--inner-restart", type=int, default=0,
                     help="mixed solve: 1 = start every FP32 segment from a fresh search direction")
     ap.add_argument("--p-guess", default="extrapolate", choices=["extrapolate", "previous"],
-                    help="initial guess of each step's pressure solve: 2 p^n - p^{n-1} or p^n")
+                    help="initial guess of each step's pressure solve: the better of p^n and "
+                         "2 p^n - p^{n-1} (by residual), or p^n")
     ap.add_argument("--solver", default="mixed_learned", choices=["mixed", "mixed_learned", "pcg_fp64"],
                     help="headline solver (the metric names mixed+learned); plain FP64 and mixed always run")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned solver")
@@ -834,7 +835,8 @@ def main():
                    "cuts": head["cuts"], "solver": head["solver"], "tol": args.tol, "inner_tol": args.inner_tol,
                    "inner_tol_learned": args.inner_tol_learned,
                    "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm,
-                   "pressure_guess": "2p^n - p^(n-1)" if args.p_guess == "extrapolate" else "p^n"},
+                   "pressure_guess": ("p^n or 2p^n - p^(n-1), the smaller residual" if args.p_guess == "extrapolate"
+                                      else "p^n")},
         "plain_fp64_value": plain["value"] if plain else None,
         "speedup_vs_plain_fp64": head["value"] / plain["value"] if plain else None,
         "solvers": {k: {kk: vv for kk, vv in v.items()
