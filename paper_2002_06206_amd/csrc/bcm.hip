@@ -445,6 +445,29 @@ int ibm_bcm_create(const int32_t K[3], int32_t n, double dx0, const double origi
         set_error("ibm_bcm_create: need K >= 1, even n in [2, 1024], dx0 > 0");
         return IBM_ERR_ARG;
     }
+    {
+        // sizes first, before any table is built: origins in fine cells are 32-bit, and
+        // the storage and the halo tables hold 32-bit indices (up to 8 sources per halo
+        // cell)
+        const long long side = n + 2 * BCM_H;
+        for (int a = 0; a < 3; ++a)
+            if ((long long)K[a] * 2 * n >= 0x7fffffffLL) {
+                set_error("ibm_bcm_create: the domain exceeds 2^31 fine cells along an axis");
+                return IBM_ERR_ARG;
+            }
+        const long long nc = (long long)K[0] * K[1] * K[2];
+        if (nc >= 0x7fffffffLL / (side * side * side)) {
+            set_error("ibm_bcm_create: cube storage exceeds 2^31 entries");
+            return IBM_ERR_ARG;
+        }
+        long long nref = 0;
+        for (long long cc = 0; cc < nc; ++cc) nref += refine_host[cc] ? 1 : 0;
+        const long long ncubes = nc + 7 * nref;
+        if (ncubes * side * side * side >= 0x7fffffffLL || 8 * ncubes * 6LL * BCM_H * n * n >= 0x7fffffffLL) {
+            set_error("ibm_bcm_create: cube storage or halo tables exceed 2^31 entries");
+            return IBM_ERR_ARG;
+        }
+    }
     ibm_bcm* m = new (std::nothrow) ibm_bcm();
     if (!m) {
         set_error("ibm_bcm_create: host allocation failed");
