@@ -46,17 +46,23 @@ def test_one_level_equals_the_uniform_grid():
         assert np.array_equal(C.interior(L, q), ref[k0:k0 + n, j0:j0 + n, i0:i0 + n])
 
 
-def _two_level():
+def _two_level(seed=None):
+    """The two-level test grid: two refined coarse cubes, or with a seed a random set of
+    them (each coarse cube refined with probability 1/2)."""
     K, n, dx = (3, 2, 2), 4, 1.0
     refine = np.zeros(K[::-1], bool)
-    refine[0, 0, 1] = True
-    refine[1, 1, 2] = True
+    if seed is None:
+        refine[0, 0, 1] = True
+        refine[1, 1, 2] = True
+    else:
+        refine = np.random.default_rng(seed).random(K[::-1]) < 0.5
     return bcm.Cubes(K, n, dx, (0.5, -1.0, 2.0), refine)
 
 
-def test_constant_field_on_two_levels():
-    C = _two_level()
-    assert len(C.cubes) == 3 * 2 * 2 - 2 + 16
+@pytest.mark.parametrize("seed", [None, 11, 12, 13])
+def test_constant_field_on_two_levels(seed):
+    C = _two_level(seed)
+    assert len(C.cubes) == 3 * 2 * 2 + 7 * int(C.refine.sum())
     data = C.exchange(C.fill(lambda x, y, z: np.full_like(x, 3.25)))
     s, n, h = C.side, C.n, bcm.H
     for q in range(len(C.cubes)):
@@ -68,8 +74,9 @@ def test_constant_field_on_two_levels():
     assert np.max(np.abs(C.laplacian(data))) == 0.0
 
 
-def test_linear_field_averages_and_copies():
-    C = _two_level()
+@pytest.mark.parametrize("seed", [None, 11, 12, 13])
+def test_linear_field_averages_and_copies(seed):
+    C = _two_level(seed)
     f = lambda x, y, z: 0.3 + 1.7 * x - 0.9 * y + 0.4 * z  # noqa: E731
     data = C.exchange(C.fill(f))
     n, h = C.n, bcm.H
@@ -97,12 +104,13 @@ def test_linear_field_averages_and_copies():
                         checked["copy"] += 1
                     else:                             # same level: the neighbour's own cell
                         assert abs(v - f(*x)) < 1e-12
-    assert checked["avg"] > 0 and checked["copy"] > 0
+    mixed = 0 < C.refine.sum() < C.refine.size
+    assert (checked["avg"] > 0 and checked["copy"] > 0) or not mixed
     # the operator of a linear field vanishes away from the level interfaces
     L = C.laplacian(data)
-    q0 = 0                                            # coarse cube at the corner (0, 0, 0)
-    assert C.cubes[q0][0] == 0
-    assert np.max(np.abs(C.interior(L, q0)[1:3, 1:3, 1:3])) < 1e-12   # clear of boundary and interface
+    for q, (lvl, o) in enumerate(C.cubes):
+        inner = C.interior(L, q)[1:n - 1, 1:n - 1, 1:n - 1]   # clear of boundary and interface
+        assert np.max(np.abs(inner)) < 1e-12
 
 
 def test_rbsor_half_sweeps_and_convergence():
