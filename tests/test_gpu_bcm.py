@@ -46,6 +46,39 @@ def test_exchange_and_operator_bit_exact(K, n, cells):
     G.close()
 
 
+@pytest.mark.parametrize("seed", [21, 22])
+def test_exchange_operator_and_sor_random_refinement(seed):
+    """Random refinement patterns (each coarse cube refined with probability 1/2):
+    exchange, operator and SOR sweeps bit-exact against the oracle."""
+    K, n = (3, 3, 2), 8
+    refine = np.random.default_rng(seed).random(K[::-1]) < 0.5
+    print("case bcm random refinement", seed, int(refine.sum()), flush=True)
+    C = bcm.Cubes(K, n, 0.7, (0.0, 0.5, -0.5), refine)
+    G = ibm.BCM(K, n, 0.7, (0.0, 0.5, -0.5), refine)
+    assert G.ncubes == len(C.cubes)
+    rng = np.random.default_rng(seed)
+    data = rng.standard_normal(C.size())
+    d = torch.from_numpy(data.copy()).cuda()
+    G.exchange(d)
+    ref = C.exchange(data)
+    assert np.array_equal(d.cpu().numpy(), ref)
+    y = torch.zeros_like(d)
+    G.laplacian(d, y)
+    L = C.laplacian(ref)
+    yg = y.cpu().numpy()
+    for q in range(len(C.cubes)):
+        assert np.array_equal(C.interior(yg, q), C.interior(L, q))
+    b = rng.standard_normal(C.size())
+    x0 = rng.standard_normal(C.size())
+    refx = C.rbsor(b, x0, 1.4, 2)
+    x = torch.from_numpy(x0.copy()).cuda()
+    G.sor(torch.from_numpy(b).cuda(), x, 1.4, 2)
+    got = x.cpu().numpy()
+    for q in range(len(C.cubes)):
+        assert np.array_equal(C.interior(got, q), C.interior(refx, q))
+    G.close()
+
+
 @pytest.mark.parametrize("K,n,cells", [((3, 2, 2), 4, ((0, 0, 1), (1, 1, 2))), ((2, 2, 1), 8, ((0, 1, 1),))])
 def test_sor_sweeps_bit_exact(K, n, cells):
     refine = np.zeros(K[::-1], bool)
