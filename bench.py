@@ -42,6 +42,18 @@ KERNEL_SYMBOL = {"pcg_a": "k_pcg_a_v<double, false>", "pcg_b": "k_pcg_b_v<double
 KERNEL_SYMBOL_F32 = {"pcg_a": "k_pcg_a_f4<false>", "pcg_b": "k_pcg_b_f4", "unused": ""}
 # algorithmic FLOPs of one network application per cell: 2 * 27 * (16 + 256 + 256 + 16)
 CNN_FLOP_PER_CELL = 29376
+# Whole-step model (algorithmic bytes of the kernels a step runs, per cell; the same
+# per-kernel figures as the roofline records): the eddy viscosity, predictor,
+# right-hand side and projection sweeps (FP64 fields: 33 + 129 + 57 + 105 B; FP32
+# fields: 17 + 77 + 45 + 81 B), the FP64 divergence check (U read, 24 B) and the choice
+# of the pressure guess (2 p - p_prev formed 24 B, two residual passes 17 B each, the
+# pick 32 B); per solver iteration the two CG passes (FP64 41 + 33 B, FP32 21 + 17 B; the
+# learned FCG 21 + 13 B plus the network application, 38 + 66 + 45 B and 29,376 FLOP);
+# per FP64 refinement sweep of the mixed paths the residual and the accumulation (45 B).
+STEP_BYTES_FIXED = {"f64": 33 + 129 + 57 + 105 + 24, "f32": 17 + 77 + 45 + 81 + 24}
+GUESS_BYTES = 24 + 17 + 17 + 32
+ITER_BYTES = {"pcg_fp64": 41 + 33, "mixed": 21 + 17, "mixed_learned": 21 + 13 + 38 + 66 + 45}
+REFINE_BYTES = 45
 BF16_PEAK_TFLOPS = 2500.0
 # dominant kernel of the learned preconditioner: the fused forward half y = K x (the
 # gated 1 -> 16 layer recomputed on the halo region in LDS, then the 16 -> 16 layer):
@@ -294,7 +306,23 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     avg_s = tim["ms"][k_dom] / 1e3 / max(real, 1)
     achieved = bytes_tab[name] * N / avg_s / 1e9
     Fp, Fv = forces
-    out = {"solver": solver, "value": N * args.steps / elapsed, "ms_per_step": elapsed / args.steps * 1e3,
+    # whole-step roofline: the step's algorithmic bytes (and the network's FLOPs) per cell
+    # at the measured iterations, against 8 TB/s and 2.5 PFLOP/s
+    it_step = sum(iters) / len(iters)
+    sweeps = sum(outers) / len(outers)
+    step_bytes = (STEP_BYTES_FIXED["f64" if precision == ibm.FP64 else "f32"]
+                  + (GUESS_BYTES if p_prev is not None else 0) + ITER_BYTES[solver] * it_step
+                  + (REFINE_BYTES * sweeps if solver != "pcg_fp64" else 0))
+    step_flop = CNN_FLOP_PER_CELL * it_step if solver == "mixed_learned" else 0.0
+    bound_value = min(HBM_PEAK_GBS * 1e9 / step_bytes,
+                      BF16_PEAK_TFLOPS * 1e12 / step_flop if step_flop > 0 else float("inf"))
+    value = N * args.steps / elapsed
+    step_roofline = {"bytes_per_cell_step": round(step_bytes, 1), "flop_per_cell_step": round(step_flop, 1),
+                     "bound": "hbm" if step_flop == 0 or step_bytes / (HBM_PEAK_GBS * 1e9) >= step_flop /
+                     (BF16_PEAK_TFLOPS * 1e12) else "mfma",
+                     "roofline_value": round(bound_value, 1), "frac": round(value / bound_value, 4)}
+    out = {"solver": solver, "value": value, "ms_per_step": elapsed / args.steps * 1e3,
+           "step_roofline": step_roofline,
            "iters_per_step": sum(iters) / len(iters), "refinement_sweeps_per_step": sum(outers) / len(outers),
            "fallbacks": fallbacks, "fp64_fallback_iters_per_step": sum(fb_iters) / len(fb_iters),
            "max_rel_residual": worst_res, "max_div_linf": worst_div,
@@ -847,6 +875,7 @@ def main():
         "training": train_info,
         "roofline": roofline,
         "roofline_sweeps": roofline_sweeps,
+        "step_roofline": head["step_roofline"],
         "surface_force": head.get("surface_force"),
         "crank_nicolson": plain.get("crank_nicolson") if plain else None,
         "hybrid_quick": plain.get("hybrid_quick") if plain else None,
