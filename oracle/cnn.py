@@ -19,6 +19,13 @@ What is computed:
   the pressure operator A = -L: symmetric positive definite, Jacobi when the
   weights are zero.  (Dividing by s only keeps BF16 activations near unit size;
   in exact arithmetic s * net(r/s) = net(r).)
+* Optionally (omega > 0) that preconditioner inside a symmetric two-level form with
+  one damped Jacobi smoothing step S = omega D^-1 before and after it:
+      z1 = S r,   z2 = z1 + M(r - A z1),   z = z2 + S(r - A z2),
+  i.e. z = (2S - S A S) r + (I - S A) M (I - A S) r, symmetric because S, A and M
+  are, and positive definite for 0 < omega < 1 (the eigenvalues of D^-1 A lie in
+  [0, 2], so 2S - S A S is positive definite).  The smoothing takes the error components a convolution of four cells'
+  reach leaves behind off the network.  The network is trained as M alone.
 * Training loss for one (b, p) pair of the pressure equation L p = b, i.e.
   A p = f with f = -b:  the A-norm distance of p from the best multiple of the
   preconditioned right-hand side p_hat = M(f),
@@ -215,8 +222,15 @@ def rms(r: np.ndarray) -> float:
     return float(np.sqrt(np.sum(r * r) / r.size))
 
 
-def precondition(st: flow.Stencil, r: np.ndarray, ws: list, bf16: bool = False) -> np.ndarray:
-    """z = D^-1 r + s net(r/s), s = RMS(r); z = 0 for r = 0."""
+def precondition(st: flow.Stencil, r: np.ndarray, ws: list, bf16: bool = False, omega: float = 0.0) -> np.ndarray:
+    """z = D^-1 r + s net(r/s), s = RMS(r); z = 0 for r = 0.  omega > 0: that map M
+    between two damped Jacobi steps S = omega D^-1, z1 = S r, z2 = z1 + M(r - A z1),
+    z = z2 + S(r - A z2)."""
+    if omega > 0.0:
+        sm = omega * jacobi_inverse(st)
+        z1 = sm * r
+        z2 = z1 + precondition(st, r - apply_A(st, z1), ws, bf16)
+        return z2 + sm * (r - apply_A(st, z2))
     s = rms(r)
     if s == 0.0:
         return np.zeros_like(r)

@@ -237,6 +237,71 @@ def test_loss_gradient_matches_finite_differences():
             assert abs(fd - dws[l][idx]) < 1e-6 * max(1e-3, abs(fd)), (l, idx, fd, dws[l][idx])
 
 
+def test_two_level_form_matches_its_matrix():
+    """The smoothed preconditioner (three sequential steps) equals the matrix
+    2S - S A S + (I - S A) C (I - A S), S = omega D^-1, assembled from dense A and the
+    dense additive preconditioner C: a dropped term, a wrong sign or the unsmoothed
+    residual fed to the network changes it."""
+    g, st = _plate_stencil()
+    A = _dense_A(st)
+    N = g.ncell
+    ws = cnn.split_weights(inputs.cnn_init_weights(7, scale=3.0).astype(np.float64))
+    C = np.zeros((N, N))
+    e = np.zeros(N)
+    for j in range(N):
+        e[j] = 1.0
+        C[:, j] = cnn.precondition(st, e.reshape(g.shape), ws).ravel()
+        e[j] = 0.0
+    omega = 0.8
+    S = np.diag(omega / flow.jacobi_diag(st).ravel())
+    I_ = np.eye(N)
+    M = 2.0 * S - S @ A @ S + (I_ - S @ A) @ C @ (I_ - A @ S)
+    assert np.allclose(M, M.T, rtol=0, atol=1e-12 * np.abs(M).max())
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0.0
+    rng = np.random.default_rng(13)
+    for _ in range(3):
+        r = rng.standard_normal(g.shape)
+        z = cnn.precondition(st, r, ws, omega=omega)
+        np.testing.assert_allclose(z.ravel(), M @ r.ravel(), rtol=0, atol=1e-12 * np.abs(M @ r.ravel()).max())
+
+
+def test_two_level_form_on_a_fourier_mode():
+    """Zero weights on a periodic box: A has the Fourier modes as eigenvectors with
+    lambda = sum over axes of 2 (1 - cos(2 pi m / n)) / dx^2 and D = 6 / dx^2, so the
+    smoothed preconditioner scales a mode by 2 s - s^2 lambda + (1 - s lambda)^2 / D,
+    s = omega / D."""
+    n = (8, 6, 10)
+    dx = 0.5
+    g = flow.Grid(n, dx, (0.0, 0.0, 0.0), (P,) * 6)
+    st = flow.build_stencils(g, np.zeros(g.shape, np.uint8), np.full(g.shape + (6,), 2.0))
+    ws = [np.zeros((27, ci, co)) for _, ci, co in cnn.LAYERS]
+    kz, ky, kx = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    for m, omega in (((1, 2, 3), 6.0 / 7.0), ((4, 3, 5), 0.5), ((0, 1, 0), 1.0)):
+        r = np.cos(2 * np.pi * (m[0] * kx / n[0] + m[1] * ky / n[1] + m[2] * kz / n[2]))
+        lam = sum(2.0 * (1.0 - np.cos(2 * np.pi * m[a] / n[a])) for a in range(3)) / dx ** 2
+        D = 6.0 / dx ** 2
+        sm = omega / D
+        factor = 2.0 * sm - sm * sm * lam + (1.0 - sm * lam) ** 2 / D
+        z = cnn.precondition(st, r, ws, omega=omega)
+        np.testing.assert_allclose(z, factor * r, rtol=0, atol=1e-13 * D ** -1)
+
+
+def test_two_level_jacobi_needs_fewer_iterations():
+    """With zero weights the smoothed form is a degree-two polynomial in D^-1 A around
+    Jacobi; FCG(1) on it converges to the dense solution in fewer iterations than
+    Jacobi-PCG."""
+    g, st = _plate_stencil()
+    A = _dense_A(st)
+    rng = np.random.default_rng(14)
+    b = rng.standard_normal(g.shape)
+    p = np.linalg.solve(A, -b.ravel()).reshape(g.shape)
+    ws = [np.zeros((27, ci, co)) for _, ci, co in cnn.LAYERS]
+    x, it = cnn.fcg(st, b, np.zeros(g.shape), lambda r: cnn.precondition(st, r, ws, omega=6.0 / 7.0), 1e-10, 500)
+    _, it_j = flow.pcg(st, b, np.zeros(g.shape), 1e-10, 500)
+    assert np.max(np.abs(x - p)) < 1e-7 * np.max(np.abs(p))
+    assert it < it_j, (it, it_j)
+
+
 def test_adam_first_steps_closed_form():
     g = np.array([0.3, -2.0, 1e-3, 0.0])
     w0 = np.array([1.0, 2.0, 3.0, 4.0])
