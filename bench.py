@@ -48,11 +48,14 @@ CNN_FLOP_PER_CELL = 29376
 # fields: 17 + 77 + 45 + 81 B), the FP64 divergence check (U read, 24 B) and the choice
 # of the pressure guess (2 p - p_prev formed 24 B, two residual passes 17 B each, the
 # pick 32 B); per solver iteration the two CG passes (FP64 41 + 33 B, FP32 21 + 17 B; the
-# learned FCG 21 + 13 B plus the network application, 38 + 66 + 45 B and 29,376 FLOP);
+# learned FCG 21 + 13 B plus the network application, 38 + 66 + 45 B and 29,376 FLOP,
+# and with the smoothing steps around it the pre-smoothing pass (r and code read, r1
+# written: 9 B) and the post-smoothing pass (z2, r, r_prev, code read, z written: 17 B));
 # per FP64 refinement sweep of the mixed paths the residual and the accumulation (45 B).
 STEP_BYTES_FIXED = {"f64": 33 + 129 + 57 + 105 + 24, "f32": 17 + 77 + 45 + 81 + 24}
 GUESS_BYTES = 24 + 17 + 17 + 32
 ITER_BYTES = {"pcg_fp64": 41 + 33, "mixed": 21 + 17, "mixed_learned": 21 + 13 + 38 + 66 + 45}
+SMOOTH_BYTES = 9 + 17
 REFINE_BYTES = 45
 BF16_PEAK_TFLOPS = 2500.0
 # dominant kernel of the learned preconditioner: the fused forward half y = K x (the
@@ -240,7 +243,8 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
                             tol=args.tol if tol is None else tol,
                             max_iter=20000, check_every=16, kind=kind,
                             inner_tol=args.inner_tol_learned if solver == "mixed_learned" else args.inner_tol,
-                            inner_max_iter=2000, inner_restart=args.inner_restart, p_prev=p_prev)
+                            inner_max_iter=2000, inner_restart=args.inner_restart, p_prev=p_prev,
+                            omega=args.smooth if solver == "mixed_learned" else 0.0)
         ctl["dt_prev"] = dt
         return p
 
@@ -311,7 +315,9 @@ def run_solver(case, solver, args, ibm, torch, weights=None):
     it_step = sum(iters) / len(iters)
     sweeps = sum(outers) / len(outers)
     step_bytes = (STEP_BYTES_FIXED["f64" if precision == ibm.FP64 else "f32"]
-                  + (GUESS_BYTES if p_prev is not None else 0) + ITER_BYTES[solver] * it_step
+                  + (GUESS_BYTES if p_prev is not None else 0)
+                  + (ITER_BYTES[solver] + (SMOOTH_BYTES if solver == "mixed_learned" and args.smooth > 0 else 0))
+                  * it_step
                   + (REFINE_BYTES * sweeps if solver != "pcg_fp64" else 0))
     step_flop = CNN_FLOP_PER_CELL * it_step if solver == "mixed_learned" else 0.0
     bound_value = min(HBM_PEAK_GBS * 1e9 / step_bytes,
@@ -762,6 +768,9 @@ def main():
                          "2 p^n - p^{n-1} (by residual), or p^n")
     ap.add_argument("--solver", default="mixed_learned", choices=["mixed", "mixed_learned", "pcg_fp64"],
                     help="headline solver (the metric names mixed+learned); plain FP64 and mixed always run")
+    ap.add_argument("--smooth", type=float, default=6.0 / 7.0,
+                    help="damped Jacobi weight of the smoothing steps around the network in the learned solve "
+                         "(0: the network's map alone)")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned solver")
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--train-lr", type=float, default=2e-3)
@@ -862,6 +871,7 @@ def main():
         "config": {"workload": case.name, "cells": list(case.n), "triangles": int(len(case.tri)),
                    "cuts": head["cuts"], "solver": head["solver"], "tol": args.tol, "inner_tol": args.inner_tol,
                    "inner_tol_learned": args.inner_tol_learned,
+                   "preconditioner_smoothing_omega": round(args.smooth, 6),
                    "nu": case.nu, "dt_max": case.dt, "cfl": 0.3, "csm": case.csm,
                    "pressure_guess": ("p^n or 2p^n - p^(n-1), the smaller residual" if args.p_guess == "extrapolate"
                                       else "p^n")},

@@ -93,6 +93,10 @@ typedef struct {
                              /* is tested every check_every sweeps; max_iter counts  */
                              /* sweeps.  Periodic axes need an even cell count       */
                              /* (IBM_ERR_ARG otherwise).                              */
+                             /* IBM_SOLVER_FCG_CNN: in (0, 1], the weight of the two  */
+                             /* damped Jacobi steps around the network (the smoothed  */
+                             /* form of ibm_cnn_precondition; needs nx % 4 == 0);    */
+                             /* <= 0: the network's map alone.                        */
     int32_t inner_restart;   /* IBM_SOLVER_FCG_JACOBI: 0 = keep the search direction */
                              /* across residual replacements, and retry a stalled    */
                              /* segment from a fresh direction (up to 3 times per    */
@@ -346,7 +350,10 @@ int ibm_shepard_force(ibm_ctx* ctx, const double* tri_dev, int64_t ntri, const d
  * adjoint (flipped, transposed convolutions) and "." the per-channel product.  As the
  * preconditioner of IBM_SOLVER_FCG_CNN it maps a residual r to
  *     z = D^-1 r + s * net(r / s),   s = RMS of r over the cells,
- * D the diagonal of A = -L (symmetric positive definite; Jacobi for zero weights).
+ * D the diagonal of A = -L (symmetric positive definite; Jacobi for zero weights),
+ * or, when the solver options' omega lies in (0, 1], that map between two damped
+ * Jacobi steps (the smoothed form of ibm_cnn_precondition).  The network is trained
+ * as the map alone.
  * Weights: IBM_CNN_NWEIGHTS floats: W1[t][0][co] (432 at offset 0), W2[t][ci][co]
  * (6912 at 432), Wg[t][0][co] (432 at 7344), row-major, tap
  * t = (dz+1)*9 + (dy+1)*3 + (dx+1) for offsets in {-1,0,1}.  The FP32 master copy
@@ -388,8 +395,12 @@ int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* 
  * gets the loss before the update.  Synchronises the stream. */
 int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, float lr,
                        double* loss_out, void* stream);
-/* z = D^-1 r + s net(r/s) on the context's grid and geometry (r, z: cells floats). */
-int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, void* stream);
+/* z = D^-1 r + s net(r/s) on the context's grid and geometry (r, z: cells floats,
+ * 16-byte aligned).  omega in (0, 1]: that map M between two damped Jacobi steps
+ * S = omega D^-1,  z1 = S r,  z2 = z1 + M(r - A z1),  z = z2 + S (r - A z2)  (symmetric,
+ * positive definite for omega < 1; needs nx % 4 == 0); omega = 0: M itself.  Other
+ * omega: IBM_ERR_ARG. */
+int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, double omega, void* stream);
 /* Preconditioner used by IBM_SOLVER_FCG_CNN on this context (NULL detaches); the network
  * must cover the grid and outlive its use.  Attaching is set-up: it sizes the network's
  * per-grid partial sums (a device allocation when the grid is larger than any it was

@@ -73,6 +73,7 @@ struct CombineIO {
     double dx2;
     float* z;
     double* cpart;
+    float wr;   // non-zero: z = D^-1 (r + wr rp) + s net (the smoothed form's z2), dots unused
 };
 
 // optional operands of the epilogues
@@ -726,7 +727,8 @@ __global__ void __launch_bounds__(256, 3) k_mconv(int nx, int ny, int nz, int mz
             const float om = g == 0 ? o1[0] : (g == 1 ? t1 : (g == 2 ? t2 : t3));
             if (EPI == EPI_COMBINE) {
                 // outside the grid r = r_prev = 0 and the code is 0: no contribution
-                const float zi = invf[jcnt(S.epc)] * S.er + sc * om;
+                const float rin = cio.wr != 0.0f ? fmaf(cio.wr, S.erp, S.er) : S.er;
+                const float zi = invf[jcnt(S.epc)] * rin + sc * om;
                 held1 = zi;
                 zsum[0] += (double)zi * (double)S.er;
                 zsum[1] += (double)zi * (double)S.erp;
@@ -1596,14 +1598,24 @@ int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s) {
 // the partials in rr_slot; <z,r> -> zr_slot, <z,rp> -> zrp_slot (-1: none).  With check,
 // stops the solve at iteration it (converged = 1) when <r,r> <= sv->tol2.  The gate must be
 // prepared.
+// omega > 0: the symmetric two-level form with S = omega D^-1: r1 = r - A S r (into the
+// network's FP32 output buffer, <r1,r1> partials in r1_slot), the network on r1, then
+// z2 = S r + D^-1 r1 + s K^T K (r1/s) from the combine epilogue (into the 16-channel
+// buffer y, free once the gated adjoint has read it) and z = z2 + S (r - A z2) with the
+// dot products; nx % 4 == 0.
 int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
-                            int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, int check,
-                            hipStream_t s) {
+                            int nparts, int rr_slot, int zr_slot, int zrp_slot, int r1_slot, double omega, Solver* sv,
+                            int it, int check, hipStream_t s) {
     ibm_cnn* n = static_cast<ibm_cnn*>(net);
     const Geo& g = c->geo;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     if ((long long)nx * ny * 32 >= (1LL << 31)) {
         set_error("cnn: x-y plane too large for the marching convolutions");
+        return IBM_ERR_ARG;
+    }
+    const bool smooth = omega > 0.0;
+    if (smooth && (nx % 4 != 0 || (uintptr_t)r % 16 || (uintptr_t)z % 16 || (uintptr_t)rp % 16)) {
+        set_error("cnn: the smoothed preconditioner needs nx % 4 == 0 and 16-byte aligned vectors");
         return IBM_ERR_ARG;
     }
     const int mz = mconv_planes(nx, ny, nz);
@@ -1614,11 +1626,24 @@ int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* 
     }
     const uint16_t* wg = pw(n, PV_WG);
     const double* rpart = partials + (long long)rr_slot * MAX_BLOCKS;
-    // kernels after k_input's stop test of iteration it run only while the solve goes on
-    // past it; without that test (the fused FCG tests in its pass A, after these) they
-    // run up to and including iteration it
+    // kernels after the stop test of iteration it (k_input's, or the pre-smoothing's) run
+    // only while the solve goes on past it; without that test (the fused FCG tests in its
+    // pass A, after these) they run up to and including iteration it
     const int gate = check ? it + 1 : it;
-    if (check) {
+    const float* rin = r;
+    if (smooth) {
+        int rc = smooth_pre(c, r, n->out, omega, partials, nparts, r1_slot, rr_slot, sv, it, check, s);
+        if (rc) return rc;
+        rin = n->out;
+        rpart = partials + (long long)r1_slot * MAX_BLOCKS;
+    }
+    if (smooth && sv) {
+        launch_timed(c, TK_DIR, k_mfwd<true>, mb, s, nx, ny, nz, mz, (const void*)rin, (const uint16_t*)n->xg,
+                     pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart, nparts, n->scal, (const Solver*)sv, gate);
+    } else if (smooth) {
+        k_mfwd<true><<<mb, 256, 0, s>>>(nx, ny, nz, mz, rin, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y, rpart,
+                                        nparts, n->scal, sv, gate);
+    } else if (check) {
         // k_input also stops the solve once <r,r> <= tol^2 |b|^2
         k_input<float><<<nparts, NT, 0, s>>>(c->N, r, rpart, nparts, n->xr, n->scal, sv, it, check);
         k_mfwd<false><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->xr, n->xg, pw(n, PV_W1), wg, pw(n, PV_W2), n->y,
@@ -1632,10 +1657,20 @@ int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* 
     }
     k_mconv<16, EPI_GATE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->y, pw(n, PV_W2T), n->a1, n->xg, wg, sv, gate,
                                                  CombineIO{});
-    const CombineIO cio{r, rp, c->pcode, n->scal, g.dx * g.dx, z, n->cpart};
-    k_mconv<1, EPI_COMBINE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), nullptr, nullptr,
-                                                   nullptr, sv, gate, cio);
-    k_relay<<<1, NT, 0, s>>>(n->cpart, mb, partials, nparts, zr_slot, zrp_slot, sv, gate);
+    if (smooth) {
+        float* z2 = reinterpret_cast<float*>(n->y);
+        const CombineIO cio{rin, r, c->pcode, n->scal, g.dx * g.dx, z2, n->cpart, (float)omega};
+        k_mconv<1, EPI_COMBINE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), nullptr, nullptr,
+                                                       nullptr, sv, gate, cio);
+        IBM_HIP(hipGetLastError());
+        int rc = smooth_post(c, z2, r, rp, z, omega, partials, nparts, zr_slot, zrp_slot, sv, gate, s);
+        if (rc) return rc;
+    } else {
+        const CombineIO cio{r, rp, c->pcode, n->scal, g.dx * g.dx, z, n->cpart};
+        k_mconv<1, EPI_COMBINE><<<mb, 256, 0, s>>>(nx, ny, nz, mz, n->a1, pw(n, PV_W1TY), nullptr, nullptr,
+                                                       nullptr, sv, gate, cio);
+        k_relay<<<1, NT, 0, s>>>(n->cpart, mb, partials, nparts, zr_slot, zrp_slot, sv, gate);
+    }
     IBM_HIP(hipGetLastError());
     n->nx = nx;
     n->ny = ny;
@@ -1873,7 +1908,8 @@ int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const do
     return IBM_OK;
 } IBM_CATCH_ALL
 
-int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, void* stream) try {
+int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* z_dev, double omega,
+                         void* stream) try {
     int rc = net_check(net);
     if (rc) return rc;
     if (!ctx || !ctx->stencil_ready || !r_dev || !z_dev) {
@@ -1887,8 +1923,14 @@ int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* 
     if ((rc = prepare_geometry(net, ctx, s))) return rc;
     k_sumsq<float><<<nred, NT, 0, s>>>(ctx->N, r_dev, net->part);
     IBM_HIP(hipGetLastError());
-    // partial slot 0 of net->part holds <r,r>; <z,r> goes to slot 1
-    return cnn_precondition_solver(net, ctx, r_dev, nullptr, z_dev, net->part, nred, 0, 1, -1, nullptr, 0, 0, s);
+    if (!(omega >= 0.0 && omega <= 1.0)) {
+        set_error("ibm_cnn_precondition: omega must lie in [0, 1]");
+        return IBM_ERR_ARG;
+    }
+    // partial slot 0 of net->part holds <r,r>; <z,r> goes to slot 1, <r1,r1> of the
+    // smoothed form to slot 2
+    return cnn_precondition_solver(net, ctx, r_dev, nullptr, z_dev, net->part, nred, 0, 1, -1, 2, omega, nullptr, 0,
+                                   0, s);
 } IBM_CATCH_ALL
 
 int ibm_ctx_set_preconditioner(ibm_ctx* ctx, ibm_cnn* net) try {

@@ -354,10 +354,16 @@ int true_residual(ibm_ctx* c, const double* b, const double* x, double* rel, hip
 int pcg64(ibm_ctx* c, const double* b, double* x, double tol, int max_iter, int check_every, int* iters,
           hipStream_t s);
 int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts* o, ibm_stats* st, hipStream_t s);
-// z = D^-1 r + s net([r/s, g]) inside a solve (cnn.hip); see cnn_precondition_solver there
+// z = D^-1 r + s net([r/s, g]) inside a solve (cnn.hip), or with omega > 0 that map
+// between two damped Jacobi steps; see cnn_precondition_solver there
 int cnn_precondition_solver(void* net, ibm_ctx* c, const float* r, const float* rp, float* z, double* partials,
-                            int nparts, int rr_slot, int zr_slot, int zrp_slot, Solver* sv, int it, int check,
-                            hipStream_t s);
+                            int nparts, int rr_slot, int zr_slot, int zrp_slot, int r1_slot, double omega, Solver* sv,
+                            int it, int check, hipStream_t s);
+// the smoothing passes of that two-level form (poisson.hip)
+int smooth_pre(ibm_ctx* c, const float* r, float* r1, double omega, double* partials, int nparts, int r1_slot,
+               int rr_slot, Solver* sv, int it, int check, hipStream_t s);
+int smooth_post(ibm_ctx* c, const float* z2, const float* r, const float* rp, float* z, double omega,
+                double* partials, int nparts, int zr_slot, int zrp_slot, const Solver* sv, int gate, hipStream_t s);
 bool cnn_covers(const void* net, long long cells);
 int cnn_prepare_geometry(void* net, ibm_ctx* c, hipStream_t s);
 // timing helpers (poisson.hip)

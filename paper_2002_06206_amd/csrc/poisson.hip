@@ -120,6 +120,7 @@ inline int slot_rr_host(int i) { return (i & 1) ? 1 : 0; }
 inline int slot_rz_host(int i) { return (i & 1) ? 3 : 2; }
 // flexible CG: <r,r> of the generic update kernel, <z,r> ping-pong, <z, r_prev>, <d,q>
 constexpr int FCG_RR = 10, FCG_ZR = 11, FCG_ZRP = 13, FCG_DQ = 14;
+constexpr int FCG_R1 = 15;    // <r1,r1> of the smoothed preconditioner's pre-smoothing
 constexpr int SLOT_B2 = 6;    // <b,b>
 constexpr int SLOT_R2D = 7;   // <r,r> of the double residual before any rounding
 constexpr int SLOT_RES0 = 8, SLOT_RES1 = 9;
@@ -915,6 +916,181 @@ __global__ void __launch_bounds__(NT) k_pcg_b_f4(Geo g, const uint8_t* __restric
     }
 }
 
+// ------------------------------------------- smoothing steps of the learned preconditioner
+//
+// The two-level form of the learned preconditioner puts one damped Jacobi step
+// S = omega D^-1 before and after the network map M:
+//     z1 = S r,  r1 = r - A z1,  z2 = z1 + M(r1),  z = z2 + S (r - A z2).
+// Both smoothing steps are FP32 stencil passes in the layout of pass B (four cells per
+// lane, z-marching slabs, x and y neighbours from plain loads served by the L2).  The
+// pre-smoothing pass applies A to S r, whose neighbour values need the neighbours'
+// codes; the post-smoothing pass applies A to the stored z2.
+
+// omega dx^2 / (Jacobi count) per code count, 0 for cells without open faces
+__device__ inline void fill_sinv(float* sinv, double omega, double dx2) {
+    if (threadIdx.x < 16) sinv[threadIdx.x] = threadIdx.x ? (float)(omega * dx2 / (double)threadIdx.x) : 0.0f;
+    __syncthreads();
+}
+
+// S x for four cells with the codes packed in pc4
+__device__ inline f4 smul4(const float* sinv, unsigned pc4, f4 x) {
+    f4 w;
+    w.x = sinv[jcount((uint8_t)(pc4 & 0xFFu))] * x.x;
+    w.y = sinv[jcount((uint8_t)((pc4 >> 8) & 0xFFu))] * x.y;
+    w.z = sinv[jcount((uint8_t)((pc4 >> 16) & 0xFFu))] * x.z;
+    w.w = sinv[jcount((uint8_t)(pc4 >> 24))] * x.w;
+    return w;
+}
+
+__device__ inline unsigned ldc4(const uint8_t* __restrict__ pcode, long long c) {
+    return *reinterpret_cast<const unsigned*>(pcode + c);
+}
+
+// Pre-smoothing: r1 = r - A (S r), partials <r1,r1> into slot r1_slot.  With check the
+// pass first makes the solve's stop test on the <r,r> partials of slot rr_slot (as the
+// network's input step does without smoothing): the solve stops at iteration it once
+// <r,r> <= tol2, and then no block writes anything.
+__global__ void __launch_bounds__(NT) k_smooth_pre_f4(Geo g, const uint8_t* __restrict__ pcode,
+                                                      const float* __restrict__ r, float* __restrict__ r1,
+                                                      double omega, double* __restrict__ partials, int nparts,
+                                                      int r1_slot, int rr_slot, Solver* sv, int it, int check) {
+    if (sv && stopped_before(sv, it)) return;
+    __shared__ double sh[NT];
+    __shared__ float sinv[16];
+    if (sv && check) {
+        const double rr = sum_slot(partials, rr_slot, nparts, sh);
+        if (!(rr == rr)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sv->nan_seen = 1;
+                sv->converged = 3;
+                sv->iters = it;
+                sv->stop_it = it;
+            }
+            return;
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sv->rr = rr;
+            sv->iters = it;
+        }
+        if (rr <= sv->tol2) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sv->converged = 1;
+                sv->stop_it = it;
+            }
+            return;
+        }
+    }
+    const double dx2 = g.dx * g.dx;
+    const float idx2 = (float)(1.0 / dx2);
+    fill_sinv(sinv, omega, dx2);
+    const int ntx4 = (g.nx + FTX - 1) / FTX;
+    const int nzc = fslab_count(g.nz);
+    const long long items = (long long)ntx4 * g.nty * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
+    double v[1] = {0.0};
+    for (long long w = w0; w < w1; ++w) {
+        const VItem it_ = fitem(g, w, ntx4, nzc);
+        if (!it_.valid) continue;
+        const int i = it_.i, j = it_.j;
+        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i + 4 >= g.nx ? 0 : i + 4;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+        const long long col = (long long)i + (long long)g.nx * j;
+        const long long ow = (long long)iw + (long long)g.nx * j - col;
+        const long long oe = (long long)ie + (long long)g.nx * j - col;
+        const long long os = (long long)i + (long long)g.nx * js - col;
+        const long long on = (long long)i + (long long)g.nx * jn - col;
+        const int zb = it_.z0 == 0 ? g.nz - 1 : it_.z0 - 1;
+        const long long cb0 = col + plane * zb, cc0 = col + plane * it_.z0;
+        f4 wb = smul4(sinv, ldc4(pcode, cb0), ld4(r, cb0));
+        f4 rc = ld4(r, cc0);
+        unsigned pcc = ldc4(pcode, cc0);
+        f4 wc = smul4(sinv, pcc, rc);
+        for (int k = it_.z0; k < it_.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = col + plane * k, ct = col + plane * zt;
+            const f4 rt = ld4(r, ct);
+            const unsigned pct = ldc4(pcode, ct);
+            const f4 wt = smul4(sinv, pct, rt);
+            const f4 ws = smul4(sinv, ldc4(pcode, c + os), ld4(r, c + os));
+            const f4 wn = smul4(sinv, ldc4(pcode, c + on), ld4(r, c + on));
+            const float ww = sinv[jcount(pcode[c + ow])] * r[c + ow];
+            const float we = sinv[jcount(pcode[c + oe])] * r[c + oe];
+            const f4 q = aq4(pcc, wc, ww, we, ws, wn, wb, wt, idx2);
+            const f4 rn = rc - q;
+            st4nt(r1, c, rn);
+            v[0] += (double)dot4(rn, rn);
+            wb = wc;
+            wc = wt;
+            rc = rt;
+            pcc = pct;
+        }
+    }
+    block_reduce<1>(v, sh);
+    if (threadIdx.x == 0) partials[r1_slot * MAX_BLOCKS + blockIdx.x] = v[0];
+}
+
+// Post-smoothing: z = z2 + S (r - A z2), partials <z,r> into slot zr_slot and, when rp
+// is given, <z,rp> into slot zrp_slot.
+__global__ void __launch_bounds__(NT) k_smooth_post_f4(Geo g, const uint8_t* __restrict__ pcode,
+                                                       const float* __restrict__ z2, const float* __restrict__ r,
+                                                       const float* __restrict__ rp, float* __restrict__ z,
+                                                       double omega, double* __restrict__ partials, int nparts,
+                                                       int zr_slot, int zrp_slot, const Solver* sv, int gate) {
+    if (sv && stopped_before(sv, gate)) return;
+    __shared__ double sh[2 * NT];
+    __shared__ float sinv[16];
+    const double dx2 = g.dx * g.dx;
+    const float idx2 = (float)(1.0 / dx2);
+    fill_sinv(sinv, omega, dx2);
+    const int ntx4 = (g.nx + FTX - 1) / FTX;
+    const int nzc = fslab_count(g.nz);
+    const long long items = (long long)ntx4 * g.nty * nzc;
+    const int nb = gridDim.x;
+    const int ch = xcd_chunk(blockIdx.x, nb);
+    const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
+    const long long plane = (long long)g.nx * g.ny;
+    double v[2] = {0.0, 0.0};
+    for (long long w = w0; w < w1; ++w) {
+        const VItem it_ = fitem(g, w, ntx4, nzc);
+        if (!it_.valid) continue;
+        const int i = it_.i, j = it_.j;
+        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i + 4 >= g.nx ? 0 : i + 4;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
+        const long long col = (long long)i + (long long)g.nx * j;
+        const long long ow = (long long)iw + (long long)g.nx * j - col;
+        const long long oe = (long long)ie + (long long)g.nx * j - col;
+        const long long os = (long long)i + (long long)g.nx * js - col;
+        const long long on = (long long)i + (long long)g.nx * jn - col;
+        const int zb = it_.z0 == 0 ? g.nz - 1 : it_.z0 - 1;
+        f4 xb = ld4(z2, col + plane * zb);
+        f4 xc = ld4(z2, col + plane * it_.z0);
+        for (int k = it_.z0; k < it_.z1; ++k) {
+            const int zt = k == g.nz - 1 ? 0 : k + 1;
+            const long long c = col + plane * k;
+            const f4 xt = ld4(z2, col + plane * zt);
+            const f4 xs = ld4(z2, c + os), xn = ld4(z2, c + on);
+            const float xw = z2[c + ow], xe = z2[c + oe];
+            const unsigned pc4 = ldc4(pcode, c);
+            const f4 q = aq4(pc4, xc, xw, xe, xs, xn, xb, xt, idx2);
+            const f4 rc = ld4(r, c);
+            const f4 zn = xc + smul4(sinv, pc4, rc - q);
+            st4nt(z, c, zn);
+            v[0] += (double)dot4(zn, rc);
+            if (rp) v[1] += (double)dot4(zn, ld4(rp, c));
+            xb = xc;
+            xc = xt;
+        }
+    }
+    block_reduce<2>(v, sh);
+    if (threadIdx.x == 0) {
+        partials[zr_slot * MAX_BLOCKS + blockIdx.x] = v[0];
+        if (rp) partials[zrp_slot * MAX_BLOCKS + blockIdx.x] = v[1];
+    }
+}
+
 // One block: totals after a residual replacement (an init sweep with parity it) ->
 // solver state of the next FP32 segment, which stops once its recursive <r,r> falls
 // below max(delta^2 <r,r>, (eta_tol)^2 <b,b>).  The host checks the FP64 residual.
@@ -1002,6 +1178,24 @@ __global__ void __launch_bounds__(NT) k_lap(Geo g, const uint8_t* __restrict__ p
 int march_blocks(const Geo& g) {
     long long items = (long long)g.ntx * g.nty * slab_count(g.nz);
     return (int)(items < MAX_BLOCKS ? items : MAX_BLOCKS);
+}
+
+// The smoothing passes of the two-level learned preconditioner, nparts blocks each (one
+// partial per block).  They need nx % 4 == 0 and 16-byte aligned vectors.
+int smooth_pre(ibm_ctx* c, const float* r, float* r1, double omega, double* partials, int nparts, int r1_slot,
+               int rr_slot, Solver* sv, int it, int check, hipStream_t s) {
+    k_smooth_pre_f4<<<nparts, NT, 0, s>>>(c->geo, c->pcode, r, r1, omega, partials, nparts, r1_slot, rr_slot, sv, it,
+                                          check);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
+}
+
+int smooth_post(ibm_ctx* c, const float* z2, const float* r, const float* rp, float* z, double omega,
+                double* partials, int nparts, int zr_slot, int zrp_slot, const Solver* sv, int gate, hipStream_t s) {
+    k_smooth_post_f4<<<nparts, NT, 0, s>>>(c->geo, c->pcode, z2, r, zrp_slot >= 0 ? rp : nullptr, z, omega, partials,
+                                           nparts, zr_slot, zrp_slot, sv, gate);
+    IBM_HIP(hipGetLastError());
+    return IBM_OK;
 }
 
 static int fmarch_blocks(const Geo& g) {
@@ -1342,7 +1536,7 @@ __global__ void __launch_bounds__(NT) k_fcg_upd(long long n, float* __restrict__
 // pass A (flexible beta) applies the lagging x update, forms d_it and <d, A d>; pass B
 // writes r_{it+1} into the other residual buffer with <r,r>.  Convergence is tested by
 // pass A, as in cg_loop.  Sets *made; returns the device flag.
-static int fcg_segment_fused(ibm_ctx* c, int nred, int it0, int max_iter, int check_every, int* made,
+static int fcg_segment_fused(ibm_ctx* c, int nred, int it0, int max_iter, int check_every, double omega, int* made,
                              hipStream_t s) {
     const Geo& g = c->geo;
     float* rb[2] = {c->r32, c->zprev32};
@@ -1368,8 +1562,8 @@ static int fcg_segment_fused(ibm_ctx* c, int nred, int it0, int max_iter, int ch
             const int it = it0 + k;
             timing_begin(c, TK_SPMV, s);
             int rc = cnn_precondition_solver(c->cnn, c, rb[cur], k ? rb[cur ^ 1] : nullptr, c->z32, c->partials, nred,
-                                             slot_rr_host(it), slot_rz_host(it), k ? FCG_ZRP : -1, c->solver, it, 0,
-                                             s);
+                                             slot_rr_host(it), slot_rz_host(it), k ? FCG_ZRP : -1, FCG_R1, omega,
+                                             c->solver, it, 0, s);
             timing_end(c, TK_SPMV, s);
             if (rc) return rc;
             timing_begin(c, TK_UPDATE, s);
@@ -1403,7 +1597,8 @@ static int fcg_segment_fused(ibm_ctx* c, int nred, int it0, int max_iter, int ch
 // One FCG segment from a residual replacement whose init sweep wrote the RR slot of
 // parity it0 (r in c->r32, e = 0).  Sets *made to the iterations made; returns the
 // device flag as cg_loop does.
-static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_every, int* made, hipStream_t s) {
+static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_every, double omega, int* made,
+                       hipStream_t s) {
     const Geo& g = c->geo;
     float* rb[2] = {c->r32, c->zprev32};
     int cur = 0;
@@ -1418,7 +1613,8 @@ static int fcg_segment(ibm_ctx* c, int nred, int it0, int max_iter, int check_ev
             const int zr = FCG_ZR + (k & 1), zrprev = FCG_ZR + ((k + 1) & 1);
             timing_begin(c, TK_SPMV, s);
             int rc = cnn_precondition_solver(c->cnn, c, rb[cur], k ? rb[cur ^ 1] : nullptr, c->z32, c->partials, nred,
-                                             k ? FCG_RR : slot_rr_host(it0), zr, k ? FCG_ZRP : -1, c->solver, it, 1, s);
+                                             k ? FCG_RR : slot_rr_host(it0), zr, k ? FCG_ZRP : -1, FCG_R1, omega,
+                                             c->solver, it, 1, s);
             timing_end(c, TK_SPMV, s);
             if (rc) return rc;
             timing_begin(c, TK_UPDATE, s);
@@ -1580,13 +1776,19 @@ int cnn_fcg_solve(ibm_ctx* c, const double* b, double* x, const ibm_solver_opts*
                       ((uintptr_t)c->d32 % 16) == 0 && ((uintptr_t)c->q32 % 16) == 0;
     const int nred = quad ? fmarch_blocks(g) : march_blocks(g);
     const int inner_max = o->inner_max_iter > 0 ? o->inner_max_iter : 1000;
+    // damped Jacobi weight of the smoothing steps around the network (0: additive form)
+    const double omega = o->omega > 0.0 ? o->omega : 0.0;
+    if (omega > 1.0 || (omega > 0.0 && !quad)) {
+        set_error("IBM_SOLVER_FCG_CNN: smoothing weight omega must lie in (0, 1] and needs nx % 4 == 0");
+        return IBM_ERR_ARG;
+    }
     int rc = cnn_prepare_geometry(c->cnn, c, s);
     if (rc) return rc;
     return refine_solve(
         c, b, x, o, st, nred, false,
         [&](int it, bool, int* made) {
-            return quad ? fcg_segment_fused(c, nred, it, inner_max, o->check_every, made, s)
-                        : fcg_segment(c, nred, it, inner_max, o->check_every, made, s);
+            return quad ? fcg_segment_fused(c, nred, it, inner_max, o->check_every, omega, made, s)
+                        : fcg_segment(c, nred, it, inner_max, o->check_every, omega, made, s);
         },
         s);
 }

@@ -111,7 +111,7 @@ def _load():
         "ibm_cnn_loss": ([vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp], ctypes.c_int),
         "ibm_cnn_train_step": ([vp, vp, vp, vp, ctypes.c_float, ctypes.POINTER(ctypes.c_double), vp],
                                ctypes.c_int),
-        "ibm_cnn_precondition": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "ibm_cnn_precondition": ([vp, vp, vp, vp, ctypes.c_double, vp], ctypes.c_int),
         "ibm_ctx_set_preconditioner": ([vp, vp], ctypes.c_int),
         "ibm_bcm_create": ([ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_double,
                             ctypes.POINTER(ctypes.c_double), vp, ctypes.POINTER(vp)], ctypes.c_int),
@@ -361,8 +361,9 @@ def ibm_cnn_train_step(net, ctx, b, p, lr):
     return loss.value
 
 
-def ibm_cnn_precondition(net, ctx, r, z):
-    return _check(_lib.ibm_cnn_precondition(net, ctx, _ptr(r), _ptr(z), _stream()), "ibm_cnn_precondition")
+def ibm_cnn_precondition(net, ctx, r, z, omega=0.0):
+    return _check(_lib.ibm_cnn_precondition(net, ctx, _ptr(r), _ptr(z), float(omega), _stream()),
+                  "ibm_cnn_precondition")
 
 
 def ibm_ctx_set_preconditioner(ctx, net):

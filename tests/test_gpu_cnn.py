@@ -270,6 +270,75 @@ def test_preconditioner_matches_oracle_ragged_rows():
     s.close()
 
 
+OMEGA = 6.0 / 7.0   # the damped Jacobi weight of the smoothed form
+
+
+@pytest.mark.parametrize("bc", ["walls", "periodic"])
+def test_smoothed_preconditioner_matches_oracle(bc):
+    """The two-level form z1 = S r, z2 = z1 + M(r - A z1), z = z2 + S(r - A z2),
+    S = omega D^-1: the FP32 pre- and post-smoothing passes around the network's
+    marching kernels against the oracle (the network in BF16 as above, the smoothing in
+    FP64) on a 40 x 37 x 24 grid (ragged row tiles) with an immersed sphere, once with
+    inflow, outflow and slip faces and once periodic in every direction (the passes'
+    wrapped neighbours).  The smoothing passes add FP32 rounding of about 1e-7
+    relative to the network's BF16 flips."""
+    n = (40, 37, 24)
+    rng = np.random.default_rng(33)
+    tri = inputs.icosphere(2, 7.0, (19.6, 18.3, 11.7), inputs.random_rotation(rng))
+    faces = (1, 2, 3, 3, 3, 3) if bc == "walls" else (0,) * 6
+    g = flow.Grid(n, 1.0, (0.0, 0.0, 0.0), faces, (1.0, 0.0, 0.0))
+    ob, ot = tagging.tag(tri, g.n, g.dx, g.origin)
+    st = flow.build_stencils(g, ob, ot)
+    s = ibm.Solver(g.n, g.dx, g.origin, g.bc, g.u_in, ibm.MIXED)
+    s.build(torch.from_numpy(ob).cuda(), torch.from_numpy(ot).cuda())
+    w = inputs.cnn_init_weights(34, scale=3.0)
+    net = ibm.Network(g.ncell, w)
+    r = rng.standard_normal(g.shape).astype(np.float32)
+    z = torch.empty(g.shape, dtype=torch.float32, device="cuda")
+    print("case cnn smoothed precondition", bc, n, flush=True)
+    ibm.ibm_cnn_precondition(net.net, s.ctx, torch.from_numpy(r).cuda(), z, OMEGA)
+    zo = cnn.precondition(st, r.astype(np.float64), _layers(w), bf16=True, omega=OMEGA)
+    zg = z.cpu().numpy()
+    e = rel_l2(zg, zo)
+    e_edge = rel_l2(zg[:, 32:, :], zo[:, 32:, :])
+    print("smoothed preconditioner rel L2 %.2e (rows 32-36: %.2e)" % (e, e_edge), flush=True)
+    assert np.all(np.isfinite(zg))
+    assert e < 1.4e-4 and e_edge < 1.4e-4
+    # the smoothing changes the map: the unsmoothed one is far from it
+    assert rel_l2(cnn.precondition(st, r.astype(np.float64), _layers(w), bf16=True), zo) > 1e-2
+    net.close()
+    s.close()
+
+
+def test_smoothed_preconditioner_argument_errors():
+    """The smoothed form needs nx % 4 == 0 and omega in (0, 1]."""
+    g, st, s, b, p = _geometry_case(3, 32)
+    net = ibm.Network(g.ncell, inputs.cnn_init_weights(1, scale=3.0))
+    r = torch.ones(g.shape, dtype=torch.float32, device="cuda")
+    z = torch.empty_like(r)
+    print("case cnn smoothed argument errors", flush=True)
+    for om in (-0.5, 1.5, float("nan")):
+        with pytest.raises(ibm.IBMError):
+            ibm.ibm_cnn_precondition(net.net, s.ctx, r, z, om)
+    net.attach(s)
+    x = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(ibm.IBMError):
+        s.poisson(torch.from_numpy(b).cuda(), x, tol=1e-6, kind=ibm.SOLVER_FCG_CNN, omega=1.5)
+    net.close()
+    s.close()
+    n = RAGGED
+    gr = flow.Grid(n, 1.0, (0.0, 0.0, 0.0), (1, 2, 3, 3, 3, 3), (1.0, 0.0, 0.0))
+    sr = ibm.Solver(gr.n, gr.dx, gr.origin, gr.bc, gr.u_in, ibm.MIXED)
+    zeros = torch.zeros((n[2], n[1], n[0]), dtype=torch.uint8, device="cuda")
+    sr.build(zeros, torch.full((n[2], n[1], n[0], 6), 2.0, dtype=torch.float64, device="cuda"))
+    netr = ibm.Network(gr.ncell, inputs.cnn_init_weights(1, scale=3.0))
+    rr = torch.ones((n[2], n[1], n[0]), dtype=torch.float32, device="cuda")
+    with pytest.raises(ibm.IBMError):
+        ibm.ibm_cnn_precondition(netr.net, sr.ctx, rr, torch.empty_like(rr), OMEGA)
+    netr.close()
+    sr.close()
+
+
 @pytest.mark.parametrize("how", ["force_stall", "nan_weights"])
 def test_fcg_cnn_falls_back_to_fp64(how):
     """A learned solve that stalls (the test hook) or whose network gives non-finite
@@ -293,16 +362,19 @@ def test_fcg_cnn_falls_back_to_fp64(how):
     s.close()
 
 
-def test_fcg_cnn_solve_reaches_fp64_tolerance():
+@pytest.mark.parametrize("omega", [0.0, OMEGA])
+def test_fcg_cnn_solve_reaches_fp64_tolerance(omega):
+    """The learned solve, without and with the smoothing steps, reaches the FP64
+    tolerance and the dense solution."""
     g, st, s, b, p = _geometry_case(3, 48)
     net = ibm.Network(g.ncell, inputs.cnn_init_weights(1, scale=3.0))
     net.attach(s)
     bt = torch.from_numpy(b).cuda()
-    print("case fcg cnn solve", flush=True)
+    print("case fcg cnn solve omega", omega, flush=True)
     for tol in (1e-6, 1e-10):
         x = torch.zeros(g.shape, dtype=torch.float64, device="cuda")
         rc, stats = s.poisson(bt, x, tol=tol, max_iter=20000, kind=ibm.SOLVER_FCG_CNN, inner_tol=0.1,
-                              inner_max_iter=500)
+                              inner_max_iter=500, omega=omega)
         print("tol %g: %s" % (tol, stats), flush=True)
         assert rc == 0 and stats["rel_residual"] <= tol * 1.0001
         assert stats["fallback_used"] == 0
@@ -391,7 +463,7 @@ def test_trained_preconditioner_gains_over_jacobi():
     l1 = train.mean_loss(net, held)
     print("held-out loss %.4f -> %.4f" % (l0, l1), flush=True)
     s, pairs = held[0]
-    it_j, it_c, t_j, t_c = [], [], 0.0, 0.0
+    it_j, it_c, it_s, t_j, t_c = [], [], [], 0.0, 0.0
     for b, p in pairs:
         st, t = train.solve_iterations(s, b, ibm.SOLVER_FCG_JACOBI, tol=1e-6, inner_tol=0.1, inner_max_iter=2000)
         assert st["status"] == 0 and st["fallback_used"] == 0
@@ -402,10 +474,15 @@ def test_trained_preconditioner_gains_over_jacobi():
         assert st["status"] == 0 and st["fallback_used"] == 0 and st["rel_residual"] <= 1e-6 * 1.0001
         it_c.append(st["iters_inner"])
         t_c += t
-    print("held-out solves to 1e-6: Jacobi CG %s iterations (%.1f ms), trained FCG %s iterations (%.1f ms)"
-          % (it_j, 1e3 * t_j, it_c, 1e3 * t_c), flush=True)
+        st, _ = train.solve_iterations(s, b, ibm.SOLVER_FCG_CNN, tol=1e-6, inner_tol=0.1, inner_max_iter=2000,
+                                       omega=OMEGA)
+        assert st["status"] == 0 and st["fallback_used"] == 0 and st["rel_residual"] <= 1e-6 * 1.0001
+        it_s.append(st["iters_inner"])
+    print("held-out solves to 1e-6: Jacobi CG %s iterations (%.1f ms), trained FCG %s iterations (%.1f ms), "
+          "with the smoothing steps %s" % (it_j, 1e3 * t_j, it_c, 1e3 * t_c, it_s), flush=True)
     assert l1 < 0.8 * l0
     assert np.mean(it_c) < 0.6 * np.mean(it_j)
+    assert np.mean(it_s) < np.mean(it_c)
     net.close()
     for s_, _ in data + held:
         s_.close()

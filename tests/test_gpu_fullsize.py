@@ -347,6 +347,67 @@ def test_benchmark_workload_learned_preconditioner_sampled():
     assert e < 6e-5
 
 
+def test_benchmark_workload_smoothed_preconditioner_sampled():
+    # the smoothed learned preconditioner (the benchmark's form) at 256^3 on sampled
+    # cells: z1 = S r, r1 = r - A z1, z2 = z1 + D^-1 r1 + s1 net(r1 / s1) (s1 = RMS of
+    # r1 over the grid), z = z2 + S (r - A z2), S = omega D^-1.  The oracle forms r1 on
+    # the whole grid with its operator, evaluates the network on the 11^3 window of r1
+    # around each sample (exact at the sample and its six neighbours, the network's
+    # reach being four cells), fills z2 at those seven cells and applies its operator
+    # there.  Bar as for the unsmoothed form (the smoothing adds FP32 rounding only).
+    from oracle import cnn
+    omega = 6.0 / 7.0
+    case, g, ob, ot, st = _oracle("ellipsoids256")
+    s, *_ = _gpu(case, ibm.MIXED)
+    w = inputs.cnn_init_weights(8, scale=3.0)
+    net = ibm.Network(int(np.prod(case.n)), w, inference_only=True)
+    nx, ny, nz = case.n
+    rng = np.random.default_rng(37)
+    r = rng.standard_normal((nz, ny, nx)).astype(np.float32)
+    z = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+    print("case full-size smoothed learned preconditioner ellipsoids256", flush=True)
+    ibm.ibm_cnn_precondition(net.net, s.ctx, torch.from_numpy(r).cuda(), z, omega)
+    zg = z.cpu().numpy().astype(np.float64)
+    net.close()
+    s.close()
+    r64 = r.astype(np.float64)
+    jinv = cnn.jacobi_inverse(st)
+    sm = omega * jinv
+    r1 = r64 - cnn.apply_A(st, sm * r64)
+    s1 = cnn.rms(r1)
+    gch = cnn.geometry_channel(st)
+    ws = cnn.split_weights(np.asarray(w, dtype=np.float64))
+    pts = {(int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(60)}
+    for zz in (0, 85, 86, nz - 1):
+        pts |= {(zz, int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(4)}
+    for xx in (0, 255, nx - 1):
+        pts |= {(int(rng.integers(nz)), int(rng.integers(ny)), xx) for _ in range(4)}
+    cut = np.argwhere(st.blocked != 0)
+    pts |= {tuple(int(v) for v in cut[i]) for i in rng.choice(len(cut), size=20, replace=False)}
+    R = 5
+    z2 = np.zeros_like(r64)
+    offs = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    for (k, j, i) in sorted(pts):
+        lo = [max(0, k - R), max(0, j - R), max(0, i - R)]
+        hi = [min(nz, k + R + 1), min(ny, j + R + 1), min(nx, i + R + 1)]
+        win = (slice(lo[0], hi[0]), slice(lo[1], hi[1]), slice(lo[2], hi[2]))
+        y, _ = cnn.forward(r1[win] / s1, gch[win], ws, bf16=True)
+        for dk, dj, di in offs:
+            kk, jj, ii = (k + dk) % nz, (j + dj) % ny, (i + di) % nx
+            if lo[0] <= kk < hi[0] and lo[1] <= jj < hi[1] and lo[2] <= ii < hi[2]:
+                z2[kk, jj, ii] = (sm[kk, jj, ii] * r64[kk, jj, ii] + jinv[kk, jj, ii] * r1[kk, jj, ii]
+                                  + s1 * y[kk - lo[0], jj - lo[1], ii - lo[2]])
+    Az2 = cnn.apply_A(st, z2)
+    got, ref = [], []
+    for (k, j, i) in sorted(pts):
+        ref.append(z2[k, j, i] + sm[k, j, i] * (r64[k, j, i] - Az2[k, j, i]))
+        got.append(zg[k, j, i])
+    e = rel_l2(got, ref)
+    print("256^3 smoothed learned preconditioner: %d sampled cells, rel L2 %.2e" % (len(ref), e), flush=True)
+    assert np.all(np.isfinite(got))
+    assert e < 6e-5
+
+
 @pytest.mark.parametrize("kind", ["mixed", "learned"])
 def test_benchmark_workload_fp64_residual_and_divergence_identity(kind):
     """Mixed (FP32 fields, FP32 CG in FP64 refinement) and learned (FCG with the network,
