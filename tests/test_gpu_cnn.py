@@ -303,7 +303,7 @@ def test_smoothed_preconditioner_matches_oracle(bc):
     e_edge = rel_l2(zg[:, 32:, :], zo[:, 32:, :])
     print("smoothed preconditioner rel L2 %.2e (rows 32-36: %.2e)" % (e, e_edge), flush=True)
     assert np.all(np.isfinite(zg))
-    assert e < 1.4e-4 and e_edge < 1.4e-4
+    assert e < 1.4e-4 and e_edge < 1.4e-4    # measured 5.2e-5 / 3.3e-5 (walls), 4.4e-5 / 3.1e-5 (periodic)
     # the smoothing changes the map: the unsmoothed one is far from it
     assert rel_l2(cnn.precondition(st, r.astype(np.float64), _layers(w), bf16=True), zo) > 1e-2
     net.close()

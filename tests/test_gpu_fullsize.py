@@ -405,7 +405,7 @@ def test_benchmark_workload_smoothed_preconditioner_sampled():
     e = rel_l2(got, ref)
     print("256^3 smoothed learned preconditioner: %d sampled cells, rel L2 %.2e" % (len(ref), e), flush=True)
     assert np.all(np.isfinite(got))
-    assert e < 6e-5
+    assert e < 6e-5          # measured 2.5e-5
 
 
 @pytest.mark.parametrize("kind", ["mixed", "learned"])
