@@ -949,7 +949,9 @@ __device__ inline unsigned ldc4(const uint8_t* __restrict__ pcode, long long c) 
 // Pre-smoothing: r1 = r - A (S r), partials <r1,r1> into slot r1_slot.  With check the
 // pass first makes the solve's stop test on the <r,r> partials of slot rr_slot (as the
 // network's input step does without smoothing): the solve stops at iteration it once
-// <r,r> <= tol2, and then no block writes anything.
+// <r,r> <= tol2, and then no block writes anything.  S r of the plane is shared through a
+// double-buffered LDS tile, as pass A shares its direction: each lane forms it for its
+// own four cells, the edge lanes and rows for the tile's halo.
 __global__ void __launch_bounds__(NT) k_smooth_pre_f4(Geo g, const uint8_t* __restrict__ pcode,
                                                       const float* __restrict__ r, float* __restrict__ r1,
                                                       double omega, double* __restrict__ partials, int nparts,
@@ -957,6 +959,7 @@ __global__ void __launch_bounds__(NT) k_smooth_pre_f4(Geo g, const uint8_t* __re
     if (sv && stopped_before(sv, it)) return;
     __shared__ double sh[NT];
     __shared__ float sinv[16];
+    __shared__ __attribute__((aligned(16))) float pln[2][(TY + 2) * FW];
     if (sv && check) {
         const double rr = sum_slot(partials, rr_slot, nparts, sh);
         if (!(rr == rr)) {
@@ -983,6 +986,8 @@ __global__ void __launch_bounds__(NT) k_smooth_pre_f4(Geo g, const uint8_t* __re
     const double dx2 = g.dx * g.dx;
     const float idx2 = (float)(1.0 / dx2);
     fill_sinv(sinv, omega, dx2);
+    auto sr4 = [&](long long c) -> f4 { return smul4(sinv, ldc4(pcode, c), ld4(r, c)); };
+    auto sr1 = [&](long long c) -> float { return sinv[jcount(pcode[c])] * r[c]; };
     const int ntx4 = (g.nx + FTX - 1) / FTX;
     const int nzc = fslab_count(g.nz);
     const long long items = (long long)ntx4 * g.nty * nzc;
@@ -990,42 +995,65 @@ __global__ void __launch_bounds__(NT) k_smooth_pre_f4(Geo g, const uint8_t* __re
     const int ch = xcd_chunk(blockIdx.x, nb);
     const long long w0 = items * ch / nb, w1 = items * (ch + 1) / nb;
     const long long plane = (long long)g.nx * g.ny;
+    const int lane = threadIdx.x % 64, lj = threadIdx.x / 64;
+    const int li = 4 * lane;
+    const f4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
     double v[1] = {0.0};
+    int buf = 0;
     for (long long w = w0; w < w1; ++w) {
         const VItem it_ = fitem(g, w, ntx4, nzc);
-        if (!it_.valid) continue;
         const int i = it_.i, j = it_.j;
-        const int iw = i == 0 ? g.nx - 1 : i - 1, ie = i + 4 >= g.nx ? 0 : i + 4;
-        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j == g.ny - 1 ? 0 : j + 1;
-        const long long col = (long long)i + (long long)g.nx * j;
-        const long long ow = (long long)iw + (long long)g.nx * j - col;
-        const long long oe = (long long)ie + (long long)g.nx * j - col;
-        const long long os = (long long)i + (long long)g.nx * js - col;
-        const long long on = (long long)i + (long long)g.nx * jn - col;
+        // last valid lane and row of the tile own the east / north halo
+        const int lane_max = min(63, (g.nx - it_.i0) / 4 - 1);
+        const int row_max = min(TY - 1, g.ny - it_.j0 - 1);
+        const int iw = it_.i0 == 0 ? g.nx - 1 : it_.i0 - 1;
+        const int ie = i + 4 >= g.nx ? 0 : i + 4;
+        const int js = j == 0 ? g.ny - 1 : j - 1, jn = j >= g.ny - 1 ? 0 : j + 1;
+        const long long col = it_.valid ? (long long)i + (long long)g.nx * j : 0;
         const int zb = it_.z0 == 0 ? g.nz - 1 : it_.z0 - 1;
-        const long long cb0 = col + plane * zb, cc0 = col + plane * it_.z0;
-        f4 wb = smul4(sinv, ldc4(pcode, cb0), ld4(r, cb0));
-        f4 rc = ld4(r, cc0);
-        unsigned pcc = ldc4(pcode, cc0);
-        f4 wc = smul4(sinv, pcc, rc);
+        f4 wb = zero4, wc = zero4, rc = zero4;
+        unsigned pcc = 0u;
+        if (it_.valid) {
+            wb = sr4(col + plane * zb);
+            const long long c0 = col + plane * it_.z0;
+            rc = ld4(r, c0);
+            pcc = ldc4(pcode, c0);
+            wc = smul4(sinv, pcc, rc);
+        }
         for (int k = it_.z0; k < it_.z1; ++k) {
             const int zt = k == g.nz - 1 ? 0 : k + 1;
-            const long long c = col + plane * k, ct = col + plane * zt;
-            const f4 rt = ld4(r, ct);
-            const unsigned pct = ldc4(pcode, ct);
-            const f4 wt = smul4(sinv, pct, rt);
-            const f4 ws = smul4(sinv, ldc4(pcode, c + os), ld4(r, c + os));
-            const f4 wn = smul4(sinv, ldc4(pcode, c + on), ld4(r, c + on));
-            const float ww = sinv[jcount(pcode[c + ow])] * r[c + ow];
-            const float we = sinv[jcount(pcode[c + oe])] * r[c + oe];
-            const f4 q = aq4(pcc, wc, ww, we, ws, wn, wb, wt, idx2);
-            const f4 rn = rc - q;
-            st4nt(r1, c, rn);
-            v[0] += (double)dot4(rn, rn);
+            float* P = pln[buf];
+            f4 rt = zero4, wt = zero4;
+            unsigned pct = 0u;
+            if (it_.valid) {
+                const long long ct = col + plane * zt;
+                rt = ld4(r, ct);
+                pct = ldc4(pcode, ct);
+                wt = smul4(sinv, pct, rt);
+                *reinterpret_cast<f4*>(&P[(lj + 1) * FW + 4 + li]) = wc;
+                const long long pk = plane * k;
+                if (lane == 0) P[(lj + 1) * FW + 3] = sr1((long long)iw + (long long)g.nx * j + pk);
+                if (lane == lane_max) P[(lj + 1) * FW + 8 + li] = sr1((long long)ie + (long long)g.nx * j + pk);
+                if (lj == 0) *reinterpret_cast<f4*>(&P[4 + li]) = sr4((long long)i + (long long)g.nx * js + pk);
+                if (lj == row_max)
+                    *reinterpret_cast<f4*>(&P[(lj + 2) * FW + 4 + li]) = sr4((long long)i + (long long)g.nx * jn + pk);
+            }
+            __syncthreads();
+            if (it_.valid) {
+                const long long c = col + plane * k;
+                const float w_ = P[(lj + 1) * FW + 3 + li], e_ = P[(lj + 1) * FW + 8 + li];
+                const f4 s4 = *reinterpret_cast<const f4*>(&P[lj * FW + 4 + li]);
+                const f4 n4 = *reinterpret_cast<const f4*>(&P[(lj + 2) * FW + 4 + li]);
+                const f4 q = aq4(pcc, wc, w_, e_, s4, n4, wb, wt, idx2);
+                const f4 rn = rc - q;
+                st4nt(r1, c, rn);
+                v[0] += (double)dot4(rn, rn);
+            }
             wb = wc;
             wc = wt;
             rc = rt;
             pcc = pct;
+            buf ^= 1;
         }
     }
     block_reduce<1>(v, sh);
