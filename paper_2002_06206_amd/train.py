@@ -30,13 +30,16 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
     the pair (b - L x_k, p - x_k), which satisfies the same equation and carries the
     error a Krylov method still has to remove after k iterations.  Depth -1 takes x
     = 2 p^n - p^{n-1}, the extrapolated initial guess of the step's solve (what is left
-    for the solver when the step starts from that guess).  Returns the solver (it owns
-    the stencil the pairs belong to) and the pairs."""
+    for the solver when the step starts from that guess).  Depth -2 takes one damped
+    Jacobi step from zero, x = (6/7) b / diag(L) (what the network sees inside the
+    smoothed preconditioner: the residual after its pre-smoothing step).  Returns the
+    solver (it owns the stencil the pairs belong to) and the pairs."""
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
     blocked, _ = s.tag(case.tri, want_theta=False)
     s.build(blocked, None, case.deadend)
     st = s.new_state(case.u_in)
     pairs = []
+    diag = laplacian_diagonal(s) if -2 in depths else None
     umax, dt_prev = max(abs(v) for v in case.u_in), 0.0
     p_older = st["p"].clone()   # p^{n-1}
     for k in range(steps):
@@ -55,12 +58,40 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
                     x = torch.zeros_like(b)
                     s.poisson(b, x, tol=1e-300, max_iter=depth, kind=ibm.SOLVER_PCG_JACOBI)
                     b, p = b - s.laplacian(x), p - x
-                elif depth < 0:
+                elif depth == -1:
                     x = 2.0 * p_old - p_older
+                    b, p = b - s.laplacian(x), p - x
+                elif depth == -2:
+                    x = torch.where(diag < 0.0, (6.0 / 7.0) * b / diag, torch.zeros_like(b))
                     b, p = b - s.laplacian(x), p - x
                 pairs.append((b, p))
         p_older = p_old
     return s, pairs
+
+
+def laplacian_diagonal(s: ibm.Solver):
+    """Diagonal of the solver's pressure operator L, read off its applications to the
+    indicator fields of a colouring in which no cell shares its colour with one of its
+    six neighbours, periodic wraps included: per axis the index modulo the smallest
+    m >= 2 with n mod m != 1 (neighbours differ by one in one index, or sit at 0 and
+    n - 1), the colour the tuple of the three residues."""
+    nz, ny, nx = s.shape
+    dev = s.dev
+    mods = []
+    for n in (nx, ny, nz):
+        m = 2 if n > 1 else 1   # one cell: no neighbour along the axis
+        while n > 1 and n % m == 1:
+            m += 1
+        mods.append(m)
+    ci = torch.arange(nx, device=dev).view(1, 1, -1) % mods[0]
+    cj = torch.arange(ny, device=dev).view(1, -1, 1) % mods[1]
+    ck = torch.arange(nz, device=dev).view(-1, 1, 1) % mods[2]
+    col = ci + mods[0] * (cj + mods[1] * ck)
+    diag = torch.zeros((nz, ny, nx), dtype=torch.float64, device=dev)
+    for c in range(mods[0] * mods[1] * mods[2]):
+        e = (col == c).to(torch.float64)
+        diag += s.laplacian(e) * e
+    return diag
 
 
 def build_dataset(seeds, n: int = 64, steps: int = 24, every: int = 3, depths=(0,)):

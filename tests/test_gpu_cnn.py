@@ -432,8 +432,9 @@ def test_training_pairs_at_krylov_depth_solve_the_pressure_equation():
     case = inputs.case_ellipsoid_window(101, 32)
     s0, p0 = train.generate_pairs(case, steps=6, every=1, first=2, depths=(0,))
     s1, p1 = train.generate_pairs(case, steps=6, every=1, first=2, depths=(0, 8))
-    assert len(p0) == len(p1) == 4
-    for s, pairs in ((s0, p0), (s1, p1)):
+    s2, p2 = train.generate_pairs(case, steps=6, every=1, first=2, depths=(0, -2))
+    assert len(p0) == len(p1) == len(p2) == 4
+    for s, pairs in ((s0, p0), (s1, p1), (s2, p2)):
         for b, p in pairs:
             e = float(torch.linalg.vector_norm(s.laplacian(p) - b) / torch.linalg.vector_norm(b))
             assert e < 1e-6, e
@@ -442,8 +443,36 @@ def test_training_pairs_at_krylov_depth_solve_the_pressure_equation():
     r = float(torch.linalg.vector_norm(p1[1][0]) / torch.linalg.vector_norm(p0[1][0]))
     print("depth-8 residual / right-hand side %.3f" % r, flush=True)
     assert 0.0 < r < 1.0
+    # after one damped Jacobi step: b' = b - L x with x = (6/7) b / diag(L)
+    assert torch.equal(p0[0][0], p2[0][0])
+    x = torch.where(train.laplacian_diagonal(s2) < 0.0, (6.0 / 7.0) * p0[1][0] / train.laplacian_diagonal(s2),
+                    torch.zeros_like(p0[1][0]))
+    e = float(torch.linalg.vector_norm(p2[1][0] - (p0[1][0] - s2.laplacian(x))) / torch.linalg.vector_norm(p0[1][0]))
+    print("damped-Jacobi pair: residual mismatch %.1e" % e, flush=True)
+    assert e < 1e-14
     s0.close()
     s1.close()
+    s2.close()
+
+
+@pytest.mark.parametrize("n", [(7, 9, 10), (25, 31, 6)])
+def test_laplacian_diagonal_probe_matches_oracle(n):
+    """The colouring probe of the operator's diagonal (training pairs after a damped
+    Jacobi step) equals -diag(A) of the oracle exactly, with periodic x and y axes
+    whose lengths defeat a fixed colouring (7 and 31 are 1 mod 2 and mod 3, 25 is 1 mod
+    2, 3 and 4), an inflow and an outlet face in z and an immersed sphere."""
+    from paper_2002_06206_amd import train
+    rng = np.random.default_rng(51)
+    tri = inputs.icosphere(2, 2.0, (n[0] / 2 + 0.1, n[1] / 2 + 0.2, n[2] / 2 + 0.3), inputs.random_rotation(rng))
+    g = flow.Grid(n, 1.0, (0.0, 0.0, 0.0), (0, 0, 0, 0, 1, 2), (0.0, 0.0, 1.0))
+    ob, ot = tagging.tag(tri, g.n, g.dx, g.origin)
+    st = flow.build_stencils(g, ob, ot)
+    s = ibm.Solver(g.n, g.dx, g.origin, g.bc, g.u_in, ibm.FP64)
+    s.build(torch.from_numpy(ob).cuda(), torch.from_numpy(ot).cuda())
+    print("case laplacian diagonal probe", n, flush=True)
+    d = train.laplacian_diagonal(s).cpu().numpy()
+    np.testing.assert_array_equal(d, -flow.jacobi_diag(st))
+    s.close()
 
 
 def test_trained_preconditioner_gains_over_jacobi():
