@@ -1917,16 +1917,16 @@ int ibm_cnn_precondition(ibm_cnn* net, ibm_ctx* ctx, const float* r_dev, float* 
         return IBM_ERR_ARG;
     }
     if ((rc = check_grid(net, ctx->N))) return rc;
+    if (!(omega >= 0.0 && omega <= 1.0)) {
+        set_error("ibm_cnn_precondition: omega must lie in [0, 1]");
+        return IBM_ERR_ARG;
+    }
     hipStream_t s = (hipStream_t)stream;
     const int nred = 1024;
     if ((rc = size_partials(net, ctx->geo, s))) return rc;
     if ((rc = prepare_geometry(net, ctx, s))) return rc;
     k_sumsq<float><<<nred, NT, 0, s>>>(ctx->N, r_dev, net->part);
     IBM_HIP(hipGetLastError());
-    if (!(omega >= 0.0 && omega <= 1.0)) {
-        set_error("ibm_cnn_precondition: omega must lie in [0, 1]");
-        return IBM_ERR_ARG;
-    }
     // partial slot 0 of net->part holds <r,r>; <z,r> goes to slot 1, <r1,r1> of the
     // smoothed form to slot 2
     return cnn_precondition_solver(net, ctx, r_dev, nullptr, z_dev, net->part, nred, 0, 1, -1, 2, omega, nullptr, 0,

@@ -921,10 +921,11 @@ __global__ void __launch_bounds__(NT) k_pcg_b_f4(Geo g, const uint8_t* __restric
 // The two-level form of the learned preconditioner puts one damped Jacobi step
 // S = omega D^-1 before and after the network map M:
 //     z1 = S r,  r1 = r - A z1,  z2 = z1 + M(r1),  z = z2 + S (r - A z2).
-// Both smoothing steps are FP32 stencil passes in the layout of pass B (four cells per
-// lane, z-marching slabs, x and y neighbours from plain loads served by the L2).  The
-// pre-smoothing pass applies A to S r, whose neighbour values need the neighbours'
-// codes; the post-smoothing pass applies A to the stored z2.
+// Both smoothing steps are FP32 stencil passes over the (256 x 4 tile, z-slab) items of
+// the CG passes, four cells per lane.  The pre-smoothing pass applies A to S r, formed
+// once per cell from r and the cell's code and shared through an LDS tile (as pass A
+// shares its direction); the post-smoothing pass applies A to the stored z2 with the x
+// and y neighbours from plain loads served by the L2 (as pass B).
 
 // omega dx^2 / (Jacobi count) per code count, 0 for cells without open faces
 __device__ inline void fill_sinv(float* sinv, double omega, double dx2) {
