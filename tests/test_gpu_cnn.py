@@ -385,9 +385,9 @@ def test_fcg_cnn_solve_reaches_fp64_tolerance(omega):
 
 def test_steps_allocate_nothing():
     """ibm_step allocates nothing after set-up: the library's allocation count stays the
-    same across learned, mixed-Jacobi and Crank-Nicolson steps, with and without the
-    extrapolated pressure guess, once the network is attached and the Crank-Nicolson
-    workspace prepared."""
+    same across learned (the network's map alone and between the smoothing steps),
+    mixed-Jacobi and Crank-Nicolson steps, with and without the extrapolated pressure
+    guess, once the network is attached and the Crank-Nicolson workspace prepared."""
     case = inputs.case_ellipsoid_window(103, 32)
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.MIXED)
     gb, _ = s.tag(case.tri, want_theta=False)
@@ -406,7 +406,8 @@ def test_steps_allocate_nothing():
         # the last two steps start their pressure solves from the extrapolated guess
         rc, stats = s.step(st, ibm.step_params(0.2, case.nu, step=k, dt_prev=0.2 if k else 0.0, tol=1e-6,
                                                kind=kind, inner_tol=1e-3, inner_max_iter=500, scheme=scheme,
-                                               mom_tol=1e-6, p_prev=p_prev if k >= 2 else None))
+                                               mom_tol=1e-6, p_prev=p_prev if k >= 2 else None,
+                                               omega=OMEGA if k in (1, 3) else 0.0))
         assert rc == 0 and stats["fallback_used"] == 0
     torch.cuda.synchronize()
     assert ibm.alloc_count() == a0
