@@ -25,7 +25,8 @@ What is computed:
   i.e. z = (2S - S A S) r + (I - S A) M (I - A S) r, symmetric because S, A and M
   are, and positive definite for 0 < omega < 1 (the eigenvalues of D^-1 A lie in
   [0, 2], so 2S - S A S is positive definite).  The smoothing takes the error components a convolution of four cells'
-  reach leaves behind off the network.  The network is trained as M alone.
+  reach leaves behind off the network.  The network can be trained as M alone or
+  through this form (the loss below with the smoothed p_hat).
 * Training loss for one (b, p) pair of the pressure equation L p = b, i.e.
   A p = f with f = -b:  the A-norm distance of p from the best multiple of the
   preconditioned right-hand side p_hat = M(f),
@@ -243,27 +244,43 @@ def apply_A(st: flow.Stencil, v: np.ndarray) -> np.ndarray:
     return -flow.laplacian(st, v)
 
 
-def loss_and_grad(st: flow.Stencil, b: np.ndarray, p: np.ndarray, ws: list, bf16: bool = False):
+def loss_and_grad(st: flow.Stencil, b: np.ndarray, p: np.ndarray, ws: list, bf16: bool = False,
+                  omega: float = 0.0):
     """Scale-invariant A-norm loss of the preconditioned right-hand side for the pair
-    (b, p), L p = b, and its gradient in the weights.  Returns (loss, dws)."""
+    (b, p), L p = b, and its gradient in the weights.  omega > 0: the preconditioner is
+    the smoothed form of `precondition`, so the network sees r1 = f - A S f and its
+    output reaches p_hat through (I - S A).  Returns (loss, dws)."""
     f = -b
-    s = rms(f)
-    y, saved = forward(f / s, geometry_channel(st), ws, bf16)
-    ph = jacobi_inverse(st) * f + s * y
+    jinv = jacobi_inverse(st)
+    if omega > 0.0:
+        sm = omega * jinv
+        t = sm * f
+        r_in = f - apply_A(st, t)
+    else:
+        r_in = f
+    s = rms(r_in)
+    y, saved = forward(r_in / s, geometry_channel(st), ws, bf16)
+    ph = jinv * r_in + s * y
+    if omega > 0.0:
+        z2 = t + ph
+        ph = z2 + sm * (f - apply_A(st, z2))
     q = apply_A(st, ph)
     c = float(np.sum(f * ph))
     Q = float(np.sum(ph * q))
     B = float(np.sum(f * p))
     loss = 1.0 - c * c / (B * Q)
     # d loss / d p_hat = (2c/(BQ)) ((c/Q) A p_hat - f), chained through p_hat = ... + s y
+    # (with the smoothing, p_hat = ... + (I - S A) s y, whose adjoint is I - A S)
     gph = (2.0 * c / (B * Q)) * ((c / Q) * q - f)
+    if omega > 0.0:
+        gph = gph - apply_A(st, sm * gph)
     dws, _, _ = backward(saved, ws, s * gph, bf16)
     return loss, dws
 
 
-def loss_only(st, b, p, ws, bf16=False) -> float:
+def loss_only(st, b, p, ws, bf16=False, omega: float = 0.0) -> float:
     f = -b
-    ph = precondition(st, f, ws, bf16)
+    ph = precondition(st, f, ws, bf16, omega)
     c = float(np.sum(f * ph))
     Q = float(np.sum(ph * apply_A(st, ph)))
     return 1.0 - c * c / (float(np.sum(f * p)) * Q)

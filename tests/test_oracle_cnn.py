@@ -181,9 +181,10 @@ def test_zero_weights_give_jacobi():
     np.testing.assert_allclose(z, r / flow.jacobi_diag(st), rtol=1e-15)
 
 
-def test_loss_is_the_minimum_energy_distance():
+@pytest.mark.parametrize("omega", [0.0, 0.8])
+def test_loss_is_the_minimum_energy_distance(omega):
     """loss = min_a |p - a p_hat|_A^2 / |p|_A^2, checked with a dense solve for p and a
-    scalar minimiser for a."""
+    scalar minimiser for a (p_hat from the additive and the smoothed form)."""
     g, st = _plate_stencil()
     A = _dense_A(st)
     assert np.allclose(A, A.T)
@@ -191,7 +192,7 @@ def test_loss_is_the_minimum_energy_distance():
     b = rng.standard_normal(g.shape)
     p = np.linalg.solve(A, -b.ravel()).reshape(g.shape)        # L p = b  <=>  A p = -b
     ws = cnn.split_weights(inputs.cnn_init_weights(3, scale=3.0).astype(np.float64))
-    ph = cnn.precondition(st, -b, ws)
+    ph = cnn.precondition(st, -b, ws, omega=omega)
     pA = p.ravel() @ A @ p.ravel()
 
     def E(a):
@@ -199,9 +200,11 @@ def test_loss_is_the_minimum_energy_distance():
         return e @ A @ e / pA
 
     res = scipy.optimize.minimize_scalar(E, bracket=(0.0, 1.0), tol=1e-12)
-    loss = cnn.loss_only(st, b, p, ws)
+    loss = cnn.loss_only(st, b, p, ws, omega=omega)
     assert 0.0 < loss < 1.0
     assert abs(loss - res.fun) < 1e-10
+    # the training loss evaluates the same p_hat
+    assert abs(cnn.loss_and_grad(st, b, p, ws, omega=omega)[0] - loss) < 1e-13
 
 
 def test_loss_scale_invariance():
@@ -216,15 +219,18 @@ def test_loss_scale_invariance():
     assert abs(l1 - l2) < 1e-12
 
 
-def test_loss_gradient_matches_finite_differences():
+@pytest.mark.parametrize("omega", [0.0, 0.8])
+def test_loss_gradient_matches_finite_differences(omega):
+    """The analytic gradient (through the smoothing steps too) against central
+    differences of the loss, which is evaluated from the preconditioner itself."""
     g, st = _plate_stencil()
     A = _dense_A(st)
     rng = np.random.default_rng(10)
     b = rng.standard_normal(g.shape)
     p = np.linalg.solve(A, -b.ravel()).reshape(g.shape)
     ws = cnn.split_weights(inputs.cnn_init_weights(5, scale=3.0).astype(np.float64))
-    loss, dws = cnn.loss_and_grad(st, b, p, ws)
-    assert abs(loss - cnn.loss_only(st, b, p, ws)) < 1e-14
+    loss, dws = cnn.loss_and_grad(st, b, p, ws, omega=omega)
+    assert abs(loss - cnn.loss_only(st, b, p, ws, omega=omega)) < 1e-13
     h = 1e-6
     for l in range(3):
         for _ in range(6):
@@ -233,7 +239,7 @@ def test_loss_gradient_matches_finite_differences():
             wm = [w.copy() for w in ws]
             wp[l][idx] += h
             wm[l][idx] -= h
-            fd = (cnn.loss_only(st, b, p, wp) - cnn.loss_only(st, b, p, wm)) / (2 * h)
+            fd = (cnn.loss_only(st, b, p, wp, omega=omega) - cnn.loss_only(st, b, p, wm, omega=omega)) / (2 * h)
             assert abs(fd - dws[l][idx]) < 1e-6 * max(1e-3, abs(fd)), (l, idx, fd, dws[l][idx])
 
 
