@@ -693,9 +693,10 @@ def train_network(args, ibm, torch):
     held = train.build_dataset(train.EVAL_SEEDS, 64, steps=24, every=3)
     t1 = time.perf_counter()
     net = ibm.Network(64 ** 3, inputs.cnn_init_weights(0))
-    before = train.mean_loss(net, held)
-    train.train(net, data, args.train_iters, args.train_lr)
-    after = train.mean_loss(net, held)
+    om = getattr(args, "train_smooth", 0.0)
+    before = train.mean_loss(net, held, om)
+    train.train(net, data, args.train_iters, args.train_lr, omega=om)
+    after = train.mean_loss(net, held, om)
     w = net.weights
     net.close()
     for s_, _ in data + held:
@@ -703,7 +704,7 @@ def train_network(args, ibm, torch):
     torch.cuda.synchronize()
     info = {"pairs": sum(len(p) for _, p in data), "data_s": round(t1 - t0, 2),
             "train_s": round(time.perf_counter() - t1, 2), "iters": args.train_iters,
-            "depths": args.train_depths,
+            "depths": args.train_depths, "loss_smoothing_omega": round(om, 6),
             "heldout_loss_before": round(before, 4), "heldout_loss_after": round(after, 4)}
     return w, info
 
@@ -771,6 +772,9 @@ def main():
     ap.add_argument("--smooth", type=float, default=6.0 / 7.0,
                     help="damped Jacobi weight of the smoothing steps around the network in the learned solve "
                          "(0: the network's map alone)")
+    ap.add_argument("--train-smooth", type=float, default=0.0,
+                    help="train the network through the smoothed preconditioner with this weight "
+                         "(0: as the network's map alone)")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned solver")
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--train-lr", type=float, default=2e-3)

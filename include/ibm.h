@@ -387,14 +387,16 @@ int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx
 /* Training loss of one pair (b, p) with L p = b on the context's stencil: with
  * f = -b and h = the preconditioned f,  loss = 1 - (f.h)^2 / ((f.p)(h.A h)), the
  * A-norm distance of p from the best multiple of h relative to |p|_A^2 (in [0,1],
- * invariant to the scale of h).  loss_out (host) and, when dw_dev != NULL, the
- * gradient in the weights.  Synchronises the stream. */
-int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, double* loss_out,
-                 float* dw_dev, void* stream);
+ * invariant to the scale of h).  h is ibm_cnn_precondition's z for the same omega
+ * (0: the network's map alone; in (0, 1]: the smoothed form, so the network is trained
+ * as the part of it that it is); other omega: IBM_ERR_ARG.  loss_out (host) and, when
+ * dw_dev != NULL, the gradient in the weights.  Synchronises the stream. */
+int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, double omega,
+                 double* loss_out, float* dw_dev, void* stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, FP32 moments) on that loss; loss_out
  * gets the loss before the update.  Synchronises the stream. */
 int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, float lr,
-                       double* loss_out, void* stream);
+                       double omega, double* loss_out, void* stream);
 /* z = D^-1 r + s net(r/s) on the context's grid and geometry (r, z: cells floats,
  * 16-byte aligned).  omega in (0, 1]: that map M between two damped Jacobi steps
  * S = omega D^-1,  z1 = S r,  z2 = z1 + M(r - A z1),  z = z2 + S (r - A z2)  (symmetric,

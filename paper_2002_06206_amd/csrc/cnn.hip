@@ -1261,6 +1261,70 @@ __global__ void k_dy(long long n, const double* __restrict__ q, const double* __
         dy[i] = f2bf((float)(k1 * (k2 * q[i] - f[i])));
 }
 
+// --- the training loss through the smoothed preconditioner (S = omega D^-1) ---
+
+// y = A x = -L x (double), one cell per thread
+__global__ void __launch_bounds__(NT) k_amul(Geo g, const uint8_t* __restrict__ pcode, const double* __restrict__ x,
+                                             double* __restrict__ y) {
+    const double idx2 = 1.0 / (g.dx * g.dx);
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    for (long long c = (long long)blockIdx.x * NT + threadIdx.x; c < n; c += (long long)gridDim.x * NT) {
+        const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), k = (int)(c / ((long long)g.nx * g.ny));
+        const uint8_t pc = pcode[c];
+        double acc = (double)jcnt(pc) * x[c];
+        for (int d = 0; d < 6; ++d) {
+            if (pc & (1 << d)) {
+                bool bnd;
+                acc -= x[nb_index(g, i, j, k, d, bnd)];
+            }
+        }
+        y[c] = acc * idx2;
+    }
+}
+
+// elementwise steps; out may be a, b or c (no restrict):
+// SM_S: out = S a;  SM_SUB: out = a - b;  SM_POST: out = a + S (b - c)
+enum { SM_S = 0, SM_SUB = 1, SM_POST = 2 };
+__global__ void k_sm_step(long long n, int mode, double omega, double dx2, const uint8_t* __restrict__ pcode,
+                          const double* a, const double* b, const double* c, double* out) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int cnt = jcnt(pcode[i]);
+        const double sw = cnt ? omega * dx2 / (double)cnt : 0.0;
+        if (mode == SM_S)
+            out[i] = sw * a[i];
+        else if (mode == SM_SUB)
+            out[i] = a[i] - b[i];
+        else
+            out[i] = a[i] + sw * (b[i] - c[i]);
+    }
+}
+
+// z2 = t + D^-1 r1 + s y (out may be r1)
+__global__ void k_z2(long long n, double dx2, const uint8_t* __restrict__ pcode, const double* t, const double* r1,
+                     const float* __restrict__ y, const double* __restrict__ s_in, double* out) {
+    const double s = *s_in;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int cnt = jcnt(pcode[i]);
+        const double dinv = cnt ? dx2 / (double)cnt : 0.0;
+        out[i] = t[i] + dinv * r1[i] + s * (double)y[i];
+    }
+}
+
+// G = s (2c/(BQ)) ((c/Q) q - f): the signal k_dy rounds, kept in double
+__global__ void k_gph(long long n, const double* __restrict__ q, const double* __restrict__ f,
+                      const double* __restrict__ scal, double* __restrict__ out) {
+    const double k1 = scal[1], k2 = scal[2];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        out[i] = k1 * (k2 * q[i] - f[i]);
+}
+
+// dy = BF16(a - b)
+__global__ void k_dy_diff(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                          uint16_t* __restrict__ dy) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dy[i] = f2bf((float)(a[i] - b[i]));
+}
+
 __global__ void k_neg(long long n, const double* __restrict__ a, double* __restrict__ b) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         b[i] = -a[i];
@@ -1567,22 +1631,48 @@ int need_training(const ibm_cnn* n, const char* what) {
 // Loss of one pair (b, p), L p = b, on the context's stencil, and the gradient signal
 // d loss / d out in dy1 (BF16): f = -b, s = RMS(f), h = D^-1 f + s K^T K (f/s),
 // loss = 1 - (f.h)^2 / ((f.p)(h.A h)).  scal[3] = loss.
-int loss_forward(ibm_cnn* n, ibm_ctx* c, const double* b, const double* p, hipStream_t s) {
+// omega > 0: h is the smoothed form (S = omega D^-1): t = S f, r1 = f - A t, s = RMS(r1),
+// z2 = t + D^-1 r1 + s K^T K (r1/s), h = z2 + S (f - A z2), and the signal reaching the
+// network's output is (I - A S) applied to the unsmoothed one.  Buffers: f; q holds t,
+// then A z2, A h, S G; h holds A t, r1, z2, h, then G; f finally holds A S G.
+int loss_forward(ibm_cnn* n, ibm_ctx* c, const double* b, const double* p, double omega, hipStream_t s) {
     const Geo& g = c->geo;
     const long long N = c->N;
     const int nred = 1024;
+    const double dx2 = g.dx * g.dx;
     int rc = size_partials(n, g, s);
     if (!rc) rc = prepare_geometry(n, c, s);
     if (rc) return rc;
+    const bool smooth = omega > 0.0;
     k_neg<<<2048, 256, 0, s>>>(N, b, n->f);
-    k_sumsq<double><<<nred, NT, 0, s>>>(N, n->f, n->part);
-    k_input<double><<<nred, NT, 0, s>>>(N, n->f, n->part, nred, n->xr, n->scal, nullptr, 0, 0);
+    const double* rin = n->f;
+    if (smooth) {
+        k_sm_step<<<2048, 256, 0, s>>>(N, SM_S, omega, dx2, c->pcode, n->f, nullptr, nullptr, n->q);
+        k_amul<<<nred, NT, 0, s>>>(g, c->pcode, n->q, n->h);
+        k_sm_step<<<2048, 256, 0, s>>>(N, SM_SUB, omega, dx2, c->pcode, n->f, n->h, nullptr, n->h);
+        rin = n->h;
+    }
+    k_sumsq<double><<<nred, NT, 0, s>>>(N, rin, n->part);
+    k_input<double><<<nred, NT, 0, s>>>(N, rin, n->part, nred, n->xr, n->scal, nullptr, 0, 0);
     IBM_HIP(hipGetLastError());
     if ((rc = net_forward(n, g.nx, g.ny, g.nz, true, s))) return rc;
-    k_phat<<<2048, 256, 0, s>>>(N, g.dx * g.dx, n->f, c->pcode, n->out, n->scal, n->h);
+    if (smooth) {
+        k_z2<<<2048, 256, 0, s>>>(N, dx2, c->pcode, n->q, n->h, n->out, n->scal, n->h);
+        k_amul<<<nred, NT, 0, s>>>(g, c->pcode, n->h, n->q);
+        k_sm_step<<<2048, 256, 0, s>>>(N, SM_POST, omega, dx2, c->pcode, n->h, n->f, n->q, n->h);
+    } else {
+        k_phat<<<2048, 256, 0, s>>>(N, dx2, n->f, c->pcode, n->out, n->scal, n->h);
+    }
     k_loss_dots<<<nred, NT, 0, s>>>(g, c->pcode, n->f, p, n->h, n->q, n->part);
     k_loss_final<<<1, NT, 0, s>>>(n->part, nred, n->scal);
-    k_dy<<<2048, 256, 0, s>>>(N, n->q, n->f, n->scal, n->dy1);
+    if (smooth) {
+        k_gph<<<2048, 256, 0, s>>>(N, n->q, n->f, n->scal, n->h);
+        k_sm_step<<<2048, 256, 0, s>>>(N, SM_S, omega, dx2, c->pcode, n->h, nullptr, nullptr, n->q);
+        k_amul<<<nred, NT, 0, s>>>(g, c->pcode, n->q, n->f);
+        k_dy_diff<<<2048, 256, 0, s>>>(N, n->h, n->f, n->dy1);
+    } else {
+        k_dy<<<2048, 256, 0, s>>>(N, n->q, n->f, n->scal, n->dy1);
+    }
     IBM_HIP(hipGetLastError());
     return IBM_OK;
 }
@@ -1863,18 +1953,18 @@ int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx
     return IBM_OK;
 } IBM_CATCH_ALL
 
-int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, double* loss_out,
-                 float* dw_dev, void* stream) try {
+int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, double omega,
+                 double* loss_out, float* dw_dev, void* stream) try {
     int rc = net_check(net);
     if (rc) return rc;
     if ((rc = need_training(net, "ibm_cnn_loss"))) return rc;
-    if (!ctx || !ctx->stencil_ready || !b_dev || !p_dev) {
-        set_error("ibm_cnn_loss: bad arguments (context needs a stencil)");
+    if (!ctx || !ctx->stencil_ready || !b_dev || !p_dev || !(omega >= 0.0 && omega <= 1.0)) {
+        set_error("ibm_cnn_loss: bad arguments (context needs a stencil, omega in [0, 1])");
         return IBM_ERR_ARG;
     }
     if ((rc = check_grid(net, ctx->N))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = loss_forward(net, ctx, b_dev, p_dev, s))) return rc;
+    if ((rc = loss_forward(net, ctx, b_dev, p_dev, omega, s))) return rc;
     if (dw_dev) {
         if ((rc = net_backward(net, nullptr, s))) return rc;
         IBM_HIP(hipMemcpyAsync(dw_dev, net->dw, NWTS * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -1886,17 +1976,17 @@ int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* 
 } IBM_CATCH_ALL
 
 int ibm_cnn_train_step(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, float lr,
-                       double* loss_out, void* stream) try {
+                       double omega, double* loss_out, void* stream) try {
     int rc = net_check(net);
     if (rc) return rc;
     if ((rc = need_training(net, "ibm_cnn_train_step"))) return rc;
-    if (!ctx || !ctx->stencil_ready || !b_dev || !p_dev || !(lr > 0.0f)) {
-        set_error("ibm_cnn_train_step: bad arguments (context needs a stencil, lr > 0)");
+    if (!ctx || !ctx->stencil_ready || !b_dev || !p_dev || !(lr > 0.0f) || !(omega >= 0.0 && omega <= 1.0)) {
+        set_error("ibm_cnn_train_step: bad arguments (context needs a stencil, lr > 0, omega in [0, 1])");
         return IBM_ERR_ARG;
     }
     if ((rc = check_grid(net, ctx->N))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    if ((rc = loss_forward(net, ctx, b_dev, p_dev, s))) return rc;
+    if ((rc = loss_forward(net, ctx, b_dev, p_dev, omega, s))) return rc;
     if ((rc = net_backward(net, nullptr, s))) return rc;
     net->adam_t += 1;
     k_adam<<<(NWTS + 255) / 256, 256, 0, s>>>(NWTS, net->w, net->dw, net->m, net->v, net->adam_t, lr);

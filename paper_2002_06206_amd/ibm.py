@@ -108,8 +108,9 @@ def _load():
         "ibm_cnn_get_weights": ([vp, vp, ctypes.c_int64], ctypes.c_int),
         "ibm_cnn_forward": ([vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp], ctypes.c_int),
         "ibm_cnn_backward": ([vp, vp, vp, vp, vp], ctypes.c_int),
-        "ibm_cnn_loss": ([vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp], ctypes.c_int),
-        "ibm_cnn_train_step": ([vp, vp, vp, vp, ctypes.c_float, ctypes.POINTER(ctypes.c_double), vp],
+        "ibm_cnn_loss": ([vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp, vp], ctypes.c_int),
+        "ibm_cnn_train_step": ([vp, vp, vp, vp, ctypes.c_float, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                vp],
                                ctypes.c_int),
         "ibm_cnn_precondition": ([vp, vp, vp, vp, ctypes.c_double, vp], ctypes.c_int),
         "ibm_ctx_set_preconditioner": ([vp, vp], ctypes.c_int),
@@ -348,16 +349,17 @@ def ibm_cnn_backward(net, dy, dw, dx=None):
     return _check(_lib.ibm_cnn_backward(net, _ptr(dy), _ptr(dw), _ptr(dx), _stream()), "ibm_cnn_backward")
 
 
-def ibm_cnn_loss(net, ctx, b, p, dw=None):
+def ibm_cnn_loss(net, ctx, b, p, dw=None, omega=0.0):
     loss = ctypes.c_double()
-    _check(_lib.ibm_cnn_loss(net, ctx, _ptr(b), _ptr(p), ctypes.byref(loss), _ptr(dw), _stream()), "ibm_cnn_loss")
+    _check(_lib.ibm_cnn_loss(net, ctx, _ptr(b), _ptr(p), float(omega), ctypes.byref(loss), _ptr(dw), _stream()),
+           "ibm_cnn_loss")
     return loss.value
 
 
-def ibm_cnn_train_step(net, ctx, b, p, lr):
+def ibm_cnn_train_step(net, ctx, b, p, lr, omega=0.0):
     loss = ctypes.c_double()
-    _check(_lib.ibm_cnn_train_step(net, ctx, _ptr(b), _ptr(p), float(lr), ctypes.byref(loss), _stream()),
-           "ibm_cnn_train_step")
+    _check(_lib.ibm_cnn_train_step(net, ctx, _ptr(b), _ptr(p), float(lr), float(omega), ctypes.byref(loss),
+                                   _stream()), "ibm_cnn_train_step")
     return loss.value
 
 
@@ -511,11 +513,11 @@ class Network:
     def weights(self, w):
         ibm_cnn_set_weights(self.net, w)
 
-    def train_step(self, solver: "Solver", b, p, lr):
-        return ibm_cnn_train_step(self.net, solver.ctx, b, p, lr)
+    def train_step(self, solver: "Solver", b, p, lr, omega=0.0):
+        return ibm_cnn_train_step(self.net, solver.ctx, b, p, lr, omega)
 
-    def loss(self, solver: "Solver", b, p, dw=None):
-        return ibm_cnn_loss(self.net, solver.ctx, b, p, dw)
+    def loss(self, solver: "Solver", b, p, dw=None, omega=0.0):
+        return ibm_cnn_loss(self.net, solver.ctx, b, p, dw, omega)
 
     def attach(self, solver: "Solver"):
         ibm_ctx_set_preconditioner(solver.ctx, self.net)

@@ -104,15 +104,16 @@ def build_dataset(seeds, n: int = 64, steps: int = 24, every: int = 3, depths=(0
     return data
 
 
-def mean_loss(net: ibm.Network, data) -> float:
-    ls = [net.loss(s, b, p) for s, pairs in data for b, p in pairs]
+def mean_loss(net: ibm.Network, data, omega: float = 0.0) -> float:
+    ls = [net.loss(s, b, p, omega=omega) for s, pairs in data for b, p in pairs]
     return float(np.mean(ls)) if ls else float("nan")
 
 
 def train(net: ibm.Network, data, iters: int = 600, lr: float = 1e-3, seed: int = 0, log_every: int = 0,
-          lr_final: float | None = None):
+          lr_final: float | None = None, omega: float = 0.0):
     """Adam on single pairs drawn uniformly at random; the learning rate decays
-    geometrically to lr_final (default lr / 10).  Returns the per-step losses."""
+    geometrically to lr_final (default lr / 10).  omega > 0 trains the network through
+    the smoothed form of the preconditioner.  Returns the per-step losses."""
     rng = np.random.default_rng(seed)
     index = [(i, j) for i, (_, pairs) in enumerate(data) for j in range(len(pairs))]
     lr_final = lr / 10.0 if lr_final is None else lr_final
@@ -122,7 +123,7 @@ def train(net: ibm.Network, data, iters: int = 600, lr: float = 1e-3, seed: int 
         s, pairs = data[i]
         b, p = pairs[j]
         a = lr * (lr_final / lr) ** (k / max(iters - 1, 1))
-        losses.append(net.train_step(s, b, p, a))
+        losses.append(net.train_step(s, b, p, a, omega))
         if log_every and (k + 1) % log_every == 0:
             print("train step %d loss %.4f (mean of last %d %.4f)" % (k + 1, losses[-1], log_every,
                                                                      np.mean(losses[-log_every:])), flush=True)

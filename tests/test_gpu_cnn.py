@@ -187,14 +187,17 @@ def _geometry_case(seed=5, n=40):
     return g, st, s, b, p
 
 
-def test_loss_and_gradient_match_oracle():
+@pytest.mark.parametrize("omega", [0.0, 6.0 / 7.0])
+def test_loss_and_gradient_match_oracle(omega):
+    """The training loss and its weight gradient, for the network's map alone and
+    through the smoothed form (the FP64 smoothing steps of the loss on both sides)."""
     g, st, s, b, p = _geometry_case()
     w = inputs.cnn_init_weights(2, scale=3.0)
     net = ibm.Network(g.ncell, w)
     dw = torch.empty(ibm.CNN_NWEIGHTS, dtype=torch.float32, device="cuda")
-    print("case cnn loss", g.n, flush=True)
-    loss = net.loss(s, torch.from_numpy(b).cuda(), torch.from_numpy(p).cuda(), dw)
-    lo, dws = cnn.loss_and_grad(st, b, p, _layers(w), bf16=True)
+    print("case cnn loss", g.n, "omega", omega, flush=True)
+    loss = net.loss(s, torch.from_numpy(b).cuda(), torch.from_numpy(p).cuda(), dw, omega=omega)
+    lo, dws = cnn.loss_and_grad(st, b, p, _layers(w), bf16=True, omega=omega)
     print("loss gpu %.6f oracle %.6f" % (loss, lo), flush=True)
     assert 0.0 < loss < 1.0
     assert abs(loss - lo) < 1e-4
@@ -202,7 +205,10 @@ def test_loss_and_gradient_match_oracle():
     for l in range(3):
         e = rel_l2(gw[l], dws[l])
         print("%s loss-gradient rel L2 %.2e" % (cnn.LAYERS[l][0], e), flush=True)
-        assert e < 8e-5      # measured 2.0e-5 (W1), 1.6e-5 (W2), 2.6e-5 (Wg)
+        assert e < 8e-5      # measured 2.0e-5 (W1), 1.6e-5 (W2), 2.6e-5 (Wg) for omega = 0
+    # the smoothed loss is a different function of the weights
+    if omega > 0.0:
+        assert abs(lo - cnn.loss_only(st, b, p, _layers(w), bf16=True)) > 1e-3
     net.close()
     s.close()
 
