@@ -337,16 +337,17 @@ def test_fcg_with_jacobi_equals_pcg():
     assert np.max(np.abs(x1 - x2)) < 1e-7 * np.max(np.abs(x2))
 
 
-def test_fcg_with_learned_preconditioner_solves():
-    """The learned operator is symmetric positive definite (Jacobi plus K^T K): FCG(1)
-    converges to the dense solution."""
+@pytest.mark.parametrize("omega", [0.0, 6.0 / 7.0])
+def test_fcg_with_learned_preconditioner_solves(omega):
+    """The learned operator is symmetric positive definite (Jacobi plus K^T K, alone or
+    between the two damped Jacobi steps): FCG(1) converges to the dense solution."""
     g, st = _plate_stencil()
     A = _dense_A(st)
     rng = np.random.default_rng(12)
     b = rng.standard_normal(g.shape)
     p = np.linalg.solve(A, -b.ravel()).reshape(g.shape)
     ws = cnn.split_weights(inputs.cnn_init_weights(6, scale=4.0).astype(np.float64))
-    x, it = cnn.fcg(st, b, np.zeros(g.shape), lambda r: cnn.precondition(st, r, ws), 1e-10, 500)
+    x, it = cnn.fcg(st, b, np.zeros(g.shape), lambda r: cnn.precondition(st, r, ws, omega=omega), 1e-10, 500)
     assert it > 3
     assert np.max(np.abs(x - p)) < 1e-7 * np.max(np.abs(p))
 
