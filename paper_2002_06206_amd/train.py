@@ -3,7 +3,8 @@
 (b, p) pairs come from the plain FP64 solver (ibm_step, Jacobi PCG) run on seeded
 windows of the ellipsoid field; every Adam step goes through ibm_cnn_train_step, i.e.
 the library's own BF16 MFMA forward and backward kernels.  This module only drives
-those entry points (argument marshalling and the host loop).
+those entry points (argument marshalling and the host loop) and forms the training
+pairs from the solver's fields with a few torch vector operations.
 
     python -m paper_2002_06206_amd.train --out weights.npy [--seeds 1 2 3 4] [--n 64]
 """
@@ -34,6 +35,8 @@ def generate_pairs(case: inputs.Case, steps: int = 24, every: int = 3, tol: floa
     Jacobi step from zero, x = (6/7) b / diag(L) (what the network sees inside the
     smoothed preconditioner: the residual after its pre-smoothing step).  Returns the
     solver (it owns the stencil the pairs belong to) and the pairs."""
+    if any(d < -2 for d in depths):
+        raise ValueError("training-pair depths are >= 0, -1 (extrapolated guess) or -2 (damped Jacobi step)")
     s = ibm.Solver(case.n, case.dx, case.origin, case.bc, case.u_in, ibm.FP64)
     blocked, _ = s.tag(case.tri, want_theta=False)
     s.build(blocked, None, case.deadend)
