@@ -388,8 +388,9 @@ int ibm_cnn_backward(ibm_cnn* net, const float* dy_dev, float* dw_dev, float* dx
  * f = -b and h = the preconditioned f,  loss = 1 - (f.h)^2 / ((f.p)(h.A h)), the
  * A-norm distance of p from the best multiple of h relative to |p|_A^2 (in [0,1],
  * invariant to the scale of h).  h is ibm_cnn_precondition's z for the same omega
- * (0: the network's map alone; in (0, 1]: the smoothed form, so the network is trained
- * as the part of it that it is); other omega: IBM_ERR_ARG.  loss_out (host) and, when
+ * (0: the network's map alone; in (0, 1]: the smoothed form, with the network trained
+ * as its inner map M; the smoothing steps of the loss are FP64); other omega:
+ * IBM_ERR_ARG.  loss_out (host) and, when
  * dw_dev != NULL, the gradient in the weights.  Synchronises the stream. */
 int ibm_cnn_loss(ibm_cnn* net, ibm_ctx* ctx, const double* b_dev, const double* p_dev, double omega,
                  double* loss_out, float* dw_dev, void* stream);
